@@ -1,0 +1,168 @@
+/*
+ * pcsplat -- 3D elliptical-Gaussian splatting rasterizer for AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libpcsplat.so. Every entry point takes plain pointers and sizes; no C++ type and no
+ * exception crosses it. Unless stated otherwise:
+ *   - array arguments are DEVICE pointers on the context's device, FP32, planar
+ *     ("component-major": component k of item i lives at ptr[k * n + i]);
+ *   - the caller owns every input and output buffer; the library owns the context, the render
+ *     state and the workspace they hold (device memory allocated with hipMalloc, grown on demand
+ *     and released by the matching destroy call);
+ *   - work is enqueued on `stream` (a hipStream_t; NULL = the null stream) in stream order; the only
+ *     host synchronisation is the 4-byte read of the instance count inside pcs_render_forward;
+ *   - a context or state may be used by one host thread at a time;
+ *   - the return value is a status code; pcs_last_error() gives a thread-local message.
+ *
+ * The method is Section 3.1 of "Low Latency Point Cloud Rendering with Learned Splatting"
+ * (arXiv:2409.16504): every point is a 3D Gaussian <G(p, Sigma), o, c, n>; Sigma = R diag(s^2) R^T
+ * with R from a unit quaternion; the Gaussian is projected with the EWA approximation of Eq. 4
+ * (Sigma_s = J T Sigma T^T J^T, view W = [T t; 0 1] of Eq. 3), bounded at three standard
+ * deviations, depth-sorted per pixel, and alpha-blended front to back (Eq. 1) with
+ * alpha = o * exp(-1/2 d^T Sigma_s^-1 d) (Eq. 2); normals are blended like colours.
+ */
+#ifndef PCSPLAT_H
+#define PCSPLAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------------------------- */
+#define PCS_OK 0
+#define PCS_ERR_INVALID_ARG 1  /* null pointer, bad size, non-finite camera, ... */
+#define PCS_ERR_HIP 2          /* a HIP runtime call failed (message names it) */
+#define PCS_ERR_OOM 3          /* device allocation failed; nothing was leaked */
+#define PCS_ERR_CAPACITY 4     /* a fixed-capacity buffer was too small */
+#define PCS_ERR_UNSUPPORTED 5  /* size beyond a documented limit */
+
+/* ---- render flags ---------------------------------------------------------------------- */
+#define PCS_FLAG_SAVE_STATE 1u /* keep projection, sorted lists and tile ranges for backward */
+
+/* Pinhole camera (Section 3.1, Eq. 3-4). x_c = T p + t with T row-major; camera axes x right,
+ * y down, z forward; pixel (i, j) has its centre at (i + 0.5, j + 0.5); u = fx x/z + cx,
+ * v = fy y/z + cy. Host memory. */
+typedef struct pcs_camera {
+  float T[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+} pcs_camera;
+
+/* Gaussians (Section 3.1): n items; device pointers, planar FP32.
+ *   mean[3][n], quat[4][n] (w,x,y,z, need not be unit; zero means identity), scale[3][n] (the
+ *   standard deviations sigma_x,y,z along the rotated axes), opacity[n], rgb[3][n], normal[3][n].
+ * Gaussians with any non-finite field are culled. */
+typedef struct pcs_gaussians {
+  int64_t n;
+  const float* mean;
+  const float* quat;
+  const float* scale;
+  const float* opacity;
+  const float* rgb;
+  const float* normal;
+} pcs_gaussians;
+
+/* Options (defaults from pcs_options_default):
+ *   z_near 0.2     cull when camera-space z <= z_near
+ *   lowpass 0.3    added to both diagonal entries of Sigma_s (pixels^2)
+ *   sigma_cut 3    splat boundary at sigma_cut standard deviations (Section 3.1)
+ *   alpha_min 1/255, alpha_max 0.99, t_eps 1e-4: a splat is skipped where alpha < alpha_min,
+ *                  alpha is clamped to alpha_max, blending of a pixel stops after the splat that
+ *                  takes its transmittance below t_eps
+ *   bg[3] 0        background colour added with the final transmittance (RGB only) */
+typedef struct pcs_options {
+  float z_near, lowpass, sigma_cut, alpha_min, alpha_max, t_eps;
+  float bg[3];
+  uint32_t flags;
+} pcs_options;
+
+/* Output images, device FP32, planar per camera: rgb[C][3][H][W], normal[C][3][H][W],
+ * depth[C][H][W] (sum of T_k alpha_k z_k, not normalised), alpha[C][H][W] (= 1 - final
+ * transmittance). Any pointer may be NULL except rgb. For pcs_render_backward the same struct
+ * carries the upstream gradients of rgb, normal and depth (alpha ignored; NULL = zero). */
+typedef struct pcs_images {
+  float* rgb;
+  float* normal;
+  float* depth;
+  float* alpha;
+} pcs_images;
+
+/* Gradients, device FP32, planar, ACCUMULATED (+=) into the caller's buffers (the caller zeroes
+ * them). mean[3][n], cov6[6][n] (dL/dSigma for the six unique entries xx,xy,xz,yy,yz,zz, an
+ * off-diagonal entry moving both symmetric elements), quat[4][n], scale[3][n], opacity[n],
+ * rgb[3][n], normal[3][n]. Any pointer may be NULL. */
+typedef struct pcs_grads {
+  float* mean;
+  float* cov6;
+  float* quat;
+  float* scale;
+  float* opacity;
+  float* rgb;
+  float* normal;
+} pcs_grads;
+
+typedef struct pcs_context pcs_context; /* device, stream-independent workspace, timers */
+typedef struct pcs_state pcs_state;     /* per-render saved data for backward and export */
+
+/* Message of the last failing call on this host thread ("" if none). */
+const char* pcs_last_error(void);
+
+/* Create a context on HIP device `device` (makes it current on this thread). */
+int pcs_context_create(int device, pcs_context** out);
+void pcs_context_destroy(pcs_context* ctx);
+
+/* Per-stage timing with HIP events recorded on the caller's stream around every kernel stage.
+ * pcs_context_timing(ctx, 1) resets the accumulators and enables timing; pcs_context_timings
+ * copies up to `cap` accumulated millisecond totals (stage order: project, scan, binning, sort,
+ * ranges, composite, backward_composite, backward_project, knn_pca) plus per-stage launch counts
+ * and synchronises the stream. */
+int pcs_context_timing(pcs_context* ctx, int enable);
+int pcs_context_timings(pcs_context* ctx, double* ms, int64_t* launches, int cap, void* stream);
+
+int pcs_state_create(pcs_context* ctx, pcs_state** out);
+void pcs_state_destroy(pcs_state* st);
+
+void pcs_options_default(pcs_options* out);
+
+/* Forward render (Section 3.1, Eq. 1-4) of `n_cams` cameras (host array) that share one width and
+ * height. Limits: n < 2^31, instance count M < 2^30, n_cams * tiles < 2^32. If `state` is non-NULL
+ * it receives what pcs_render_backward and pcs_state_bins need (the flag SAVE_STATE is implied);
+ * the state stays valid until it is passed to another render or destroyed. */
+int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camera* cams,
+                       int32_t n_cams, const pcs_options* opt, const pcs_images* out,
+                       pcs_state* state, void* stream);
+
+/* Backward render: the adjoint of pcs_render_forward for the Gaussians, cameras and options saved
+ * in `state`, given upstream gradients `grad_out` (same layout as the images). The compositing
+ * is recomputed back to front from the saved per-pixel transmittance and last-contributor
+ * index; per-splat screen-space gradients are reduced across each 64-lane wavefront and added
+ * atomically, then chained through the EWA projection to the Gaussian parameters. */
+int pcs_render_backward(pcs_context* ctx, const pcs_state* state, const pcs_images* grad_out,
+                        const pcs_grads* grads, void* stream);
+
+/* Parity export of a saved state (device pointers owned by the state):
+ *   keys[m]:  ((cam * tiles_per_cam + ty * TX + tx) << 32) | bits(fp32 camera-space depth)
+ *   vals[m]:  Gaussian index, sorted lexicographically by (key, value)
+ *   ranges[2][n_tiles]: start and end of every tile's run (empty tiles: 0, 0)
+ *   n_contrib[C][H][W] (int32): 1 + list position of the last blended splat of each pixel
+ *   t_final[C][H][W]: final transmittance. Valid after the stream has reached the render. */
+int pcs_state_bins(const pcs_state* st, const uint64_t** keys, const uint32_t** vals, int64_t* m,
+                   const uint32_t** ranges, int64_t* n_tiles, const int32_t** n_contrib,
+                   const float** t_final);
+
+/* kNN-PCA surfel ellipsoids (the plain-path estimate of every point's Gaussian): for each of the
+ * n points xyz[3][n] the k nearest points (itself included, ties by index, k <= 32) give a
+ * covariance about their mean; its eigenvectors are the axes, sigma_i = kappa sqrt(lambda_i) with
+ * sigma_3 >= floor * sigma_2, the normal is the least-variance axis oriented away from the cloud
+ * centroid. Outputs quat[4][n] (w >= 0), scale[3][n], normal[3][n]. */
+int pcs_knn_pca(pcs_context* ctx, const float* xyz, int64_t n, int32_t k, float kappa,
+                float floor_ratio, float* quat, float* scale, float* normal, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCSPLAT_H */

@@ -1,0 +1,474 @@
+// C ABI of libpcsplat.so: argument checking, workspace management, stage timing and the launch
+// sequence of the renderer (projection -> scan -> binning -> radix sort -> tile ranges ->
+// compositing) and of its adjoint.
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pcs_internal.hpp"
+
+using namespace pcs;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define PCS_HIP(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(PCS_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));      \
+  } while (0)
+
+#define PCS_TRY(expr)           \
+  do {                          \
+    int rc_ = (expr);           \
+    if (rc_ != PCS_OK) return rc_; \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  template <typename T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+void swap_buf(DevBuf& a, DevBuf& b) {
+  std::swap(a.p, b.p);
+  std::swap(a.cap, b.cap);
+}
+
+// Grow-only device buffer; 25% headroom so slowly growing sizes do not reallocate every call.
+int ensure(DevBuf& b, size_t bytes, const char* what) {
+  if (bytes <= b.cap && b.p) return PCS_OK;
+  b.release();
+  const size_t want = std::max<size_t>(256, bytes + bytes / 4);
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    return fail(PCS_ERR_OOM, std::string("hipMalloc of ") + std::to_string(want) + " bytes for " +
+                                 what + " failed: " + hipGetErrorString(e));
+  }
+  b.cap = want;
+  return PCS_OK;
+}
+
+enum Stage {
+  ST_PROJECT = 0, ST_SCAN, ST_BINNING, ST_SORT, ST_RANGES, ST_COMPOSITE, ST_BWD_COMPOSITE,
+  ST_BWD_PROJECT, ST_KNN, ST_COUNT
+};
+
+int bit_length(uint64_t v) {
+  int b = 0;
+  while (v) { ++b; v >>= 1; }
+  return b;
+}
+
+bool finite_camera(const pcs_camera& c) {
+  for (float v : c.T) if (!std::isfinite(v)) return false;
+  for (float v : c.t) if (!std::isfinite(v)) return false;
+  return std::isfinite(c.fx) && std::isfinite(c.fy) && std::isfinite(c.cx) && std::isfinite(c.cy) &&
+         c.fx != 0.0f && c.fy != 0.0f;
+}
+
+}  // namespace
+
+struct pcs_state;
+
+struct pcs_context {
+  int device = 0;
+  DevBuf counts, offsets, meta, keys_alt, vals_alt, scan_scratch, sort_scratch, sgrad, small;
+  DevBuf knn_scratch;
+  uint32_t* host_small = nullptr;   // pinned: total (u64) then depth-bit range [2]
+  pcs_state* internal = nullptr;    // state used when the caller passes none
+  bool timing = false;
+  struct Ev {
+    hipEvent_t a, b;
+    int stage;
+  };
+  std::vector<Ev> pool;
+  size_t used = 0;
+  double acc_ms[ST_COUNT] = {};
+  int64_t launches[ST_COUNT] = {};
+};
+
+struct pcs_state {
+  pcs_context* ctx = nullptr;
+  DevBuf rec, keys, vals, ranges, t_final, n_contrib, canon, dcams;
+  pcs_gaussians g{};
+  std::vector<pcs_camera> cams;
+  pcs_options opt{};
+  int W = 0, H = 0, C = 0;
+  int64_t n = 0, m = 0, n_tiles = 0;
+  int depth_bits = 0;
+  uint32_t zmin = 0;
+  bool valid = false;
+};
+
+namespace {
+
+// Records HIP events around a stage when timing is on.
+struct StageTimer {
+  pcs_context* ctx;
+  int stage;
+  hipStream_t s;
+  size_t slot = (size_t)-1;
+  StageTimer(pcs_context* c, int st, hipStream_t stream) : ctx(c), stage(st), s(stream) {
+    if (!ctx->timing) return;
+    if (ctx->used == ctx->pool.size()) {
+      pcs_context::Ev ev{};
+      if (hipEventCreate(&ev.a) != hipSuccess || hipEventCreate(&ev.b) != hipSuccess) return;
+      ctx->pool.push_back(ev);
+    }
+    slot = ctx->used++;
+    ctx->pool[slot].stage = stage;
+    (void)hipEventRecord(ctx->pool[slot].a, s);
+  }
+  ~StageTimer() {
+    if (slot != (size_t)-1) (void)hipEventRecord(ctx->pool[slot].b, s);
+  }
+};
+
+DevCamera to_dev(const pcs_camera& c) {
+  DevCamera d{};
+  std::memcpy(d.T, c.T, sizeof d.T);
+  std::memcpy(d.t, c.t, sizeof d.t);
+  d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
+  d.W = c.width; d.H = c.height;
+  return d;
+}
+
+DevOptions to_dev(const pcs_options& o) {
+  DevOptions d{};
+  d.z_near = o.z_near; d.lowpass = o.lowpass; d.sigma_cut = o.sigma_cut;
+  d.alpha_min = o.alpha_min; d.alpha_max = o.alpha_max; d.t_eps = o.t_eps;
+  d.bg[0] = o.bg[0]; d.bg[1] = o.bg[1]; d.bg[2] = o.bg[2];
+  return d;
+}
+
+int check_options(const pcs_options& o) {
+  const float v[] = {o.z_near, o.lowpass, o.sigma_cut, o.alpha_min, o.alpha_max, o.t_eps,
+                     o.bg[0], o.bg[1], o.bg[2]};
+  for (float x : v)
+    if (!std::isfinite(x)) return fail(PCS_ERR_INVALID_ARG, "options must be finite");
+  if (o.sigma_cut <= 0.0f || o.lowpass < 0.0f || o.alpha_max <= 0.0f || o.alpha_max >= 1.0f ||
+      o.alpha_min < 0.0f || o.t_eps < 0.0f)
+    return fail(PCS_ERR_INVALID_ARG,
+                "options out of range (need sigma_cut > 0, lowpass >= 0, 0 < alpha_max < 1, "
+                "alpha_min >= 0, t_eps >= 0)");
+  return PCS_OK;
+}
+
+int check_gaussians(const pcs_gaussians* g) {
+  if (!g) return fail(PCS_ERR_INVALID_ARG, "gaussians is NULL");
+  if (g->n < 0) return fail(PCS_ERR_INVALID_ARG, "gaussian count is negative");
+  if (g->n >= (int64_t(1) << 31)) return fail(PCS_ERR_UNSUPPORTED, "n must be below 2^31");
+  if (g->n > 0 && (!g->mean || !g->quat || !g->scale || !g->opacity || !g->rgb || !g->normal))
+    return fail(PCS_ERR_INVALID_ARG, "a gaussian attribute pointer is NULL");
+  return PCS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pcs_last_error(void) { return g_err.c_str(); }
+
+void pcs_options_default(pcs_options* o) {
+  if (!o) return;
+  o->z_near = 0.2f;
+  o->lowpass = 0.3f;
+  o->sigma_cut = 3.0f;
+  o->alpha_min = 1.0f / 255.0f;
+  o->alpha_max = 0.99f;
+  o->t_eps = 1e-4f;
+  o->bg[0] = o->bg[1] = o->bg[2] = 0.0f;
+  o->flags = 0;
+}
+
+int pcs_context_create(int device, pcs_context** out) {
+  if (!out) return fail(PCS_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  PCS_HIP(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return fail(PCS_ERR_INVALID_ARG, "no such HIP device");
+  PCS_HIP(hipSetDevice(device));
+  pcs_context* ctx = new pcs_context();
+  ctx->device = device;
+  void* hp = nullptr;
+  if (hipHostMalloc(&hp, 64, hipHostMallocDefault) != hipSuccess) {
+    delete ctx;
+    return fail(PCS_ERR_OOM, "pinned host allocation failed");
+  }
+  ctx->host_small = reinterpret_cast<uint32_t*>(hp);
+  *out = ctx;
+  return PCS_OK;
+}
+
+void pcs_state_destroy(pcs_state* st) { delete st; }
+
+void pcs_context_destroy(pcs_context* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  for (auto& ev : ctx->pool) {
+    (void)hipEventDestroy(ev.a);
+    (void)hipEventDestroy(ev.b);
+  }
+  delete ctx->internal;
+  if (ctx->host_small) (void)hipHostFree(ctx->host_small);
+  delete ctx;
+}
+
+int pcs_context_timing(pcs_context* ctx, int enable) {
+  if (!ctx) return fail(PCS_ERR_INVALID_ARG, "context is NULL");
+  ctx->timing = enable != 0;
+  ctx->used = 0;
+  std::fill(std::begin(ctx->acc_ms), std::end(ctx->acc_ms), 0.0);
+  std::fill(std::begin(ctx->launches), std::end(ctx->launches), int64_t(0));
+  return PCS_OK;
+}
+
+int pcs_context_timings(pcs_context* ctx, double* ms, int64_t* launches, int cap, void* stream) {
+  if (!ctx) return fail(PCS_ERR_INVALID_ARG, "context is NULL");
+  PCS_HIP(hipSetDevice(ctx->device));
+  PCS_HIP(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
+  for (size_t i = 0; i < ctx->used; ++i) {
+    float t = 0.0f;
+    PCS_HIP(hipEventElapsedTime(&t, ctx->pool[i].a, ctx->pool[i].b));
+    ctx->acc_ms[ctx->pool[i].stage] += t;
+    ctx->launches[ctx->pool[i].stage] += 1;
+  }
+  ctx->used = 0;
+  for (int i = 0; i < cap && i < ST_COUNT; ++i) {
+    if (ms) ms[i] = ctx->acc_ms[i];
+    if (launches) launches[i] = ctx->launches[i];
+  }
+  return PCS_OK;
+}
+
+int pcs_state_create(pcs_context* ctx, pcs_state** out) {
+  if (!ctx || !out) return fail(PCS_ERR_INVALID_ARG, "context or out is NULL");
+  *out = new pcs_state();
+  (*out)->ctx = ctx;
+  return PCS_OK;
+}
+
+int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camera* cams,
+                       int32_t n_cams, const pcs_options* opt, const pcs_images* out,
+                       pcs_state* state, void* stream) {
+  if (!ctx) return fail(PCS_ERR_INVALID_ARG, "context is NULL");
+  PCS_TRY(check_gaussians(g));
+  if (!cams || n_cams <= 0) return fail(PCS_ERR_INVALID_ARG, "need at least one camera");
+  if (!opt) return fail(PCS_ERR_INVALID_ARG, "options is NULL");
+  PCS_TRY(check_options(*opt));
+  if (!out || !out->rgb) return fail(PCS_ERR_INVALID_ARG, "output rgb image is NULL");
+  const int W = cams[0].width, H = cams[0].height;
+  if (W <= 0 || H <= 0) return fail(PCS_ERR_INVALID_ARG, "image width and height must be positive");
+  if (W > (1 << 20) || H > (1 << 20)) return fail(PCS_ERR_UNSUPPORTED, "image larger than 2^20");
+  for (int c = 0; c < n_cams; ++c) {
+    if (cams[c].width != W || cams[c].height != H)
+      return fail(PCS_ERR_INVALID_ARG, "all cameras of one call must share width and height");
+    if (!finite_camera(cams[c])) return fail(PCS_ERR_INVALID_ARG, "camera has non-finite or zero focal values");
+  }
+  if (state && state->ctx != ctx) return fail(PCS_ERR_INVALID_ARG, "state belongs to another context");
+  const int TX = (W + kTile - 1) / kTile, TY = (H + kTile - 1) / kTile;
+  const int64_t tiles_per_cam = (int64_t)TX * TY;
+  const int64_t total_tiles = tiles_per_cam * n_cams;
+  if (total_tiles >= (int64_t(1) << 31)) return fail(PCS_ERR_UNSUPPORTED, "cameras x tiles must be below 2^31");
+  const int64_t n = g->n;
+  const int64_t cn = n * n_cams;
+  if (cn >= (int64_t(1) << 34)) return fail(PCS_ERR_UNSUPPORTED, "n x cameras too large");
+  PCS_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+
+  pcs_state* st = state;
+  if (!st) {
+    if (!ctx->internal) {
+      ctx->internal = new pcs_state();
+      ctx->internal->ctx = ctx;
+    }
+    st = ctx->internal;
+  }
+  st->valid = false;
+  // cameras to the device (pageable copy: stream-ordered, the host array may be reused at once)
+  std::vector<DevCamera> dc(n_cams);
+  for (int c = 0; c < n_cams; ++c) dc[c] = to_dev(cams[c]);
+  PCS_TRY(ensure(st->dcams, sizeof(DevCamera) * n_cams, "cameras"));
+  PCS_HIP(hipMemcpyAsync(st->dcams.p, dc.data(), sizeof(DevCamera) * n_cams, hipMemcpyHostToDevice, s));
+  const DevOptions dopt = to_dev(*opt);
+
+  PCS_TRY(ensure(st->rec, std::max<int64_t>(cn, 1) * kRecFloat4 * sizeof(float4), "splat records"));
+  PCS_TRY(ensure(ctx->meta, std::max<int64_t>(cn, 1) * sizeof(uint4), "binning meta"));
+  PCS_TRY(ensure(ctx->counts, std::max<int64_t>(cn, 1) * sizeof(uint32_t) + 64, "counts"));
+  PCS_TRY(ensure(ctx->offsets, std::max<int64_t>(cn, 1) * sizeof(uint32_t) + 64, "offsets"));
+  PCS_TRY(ensure(ctx->scan_scratch, scan_scratch_bytes(cn), "scan scratch"));
+  PCS_TRY(ensure(ctx->small, 64, "small"));
+  PCS_TRY(ensure(st->ranges, 2 * total_tiles * sizeof(uint32_t), "tile ranges"));
+  const int64_t HWC = (int64_t)W * H * n_cams;
+  PCS_TRY(ensure(st->t_final, HWC * sizeof(float), "final transmittance"));
+  PCS_TRY(ensure(st->n_contrib, HWC * sizeof(int32_t), "last contributor"));
+
+  uint64_t* d_total = ctx->small.as<uint64_t>();
+  uint32_t* d_zrange = ctx->small.as<uint32_t>() + 2;
+  PCS_HIP(launch_fill_u32(d_zrange, 0xFFFFFFFFu, 1, s));
+  PCS_HIP(launch_fill_u32(d_zrange + 1, 0u, 1, s));
+  {
+    StageTimer tm(ctx, ST_PROJECT, s);
+    PCS_HIP(launch_project(n, n_cams, st->dcams.as<DevCamera>(), dopt, *g, st->rec.as<float4>(),
+                           ctx->meta.as<uint4>(), ctx->counts.as<uint32_t>(), d_zrange, s));
+  }
+  {
+    StageTimer tm(ctx, ST_SCAN, s);
+    PCS_HIP(launch_scan(ctx->counts.as<uint32_t>(), ctx->offsets.as<uint32_t>(), cn, d_total,
+                        ctx->scan_scratch.p, s));
+  }
+  PCS_HIP(hipMemcpyAsync(ctx->host_small, ctx->small.p, 16, hipMemcpyDeviceToHost, s));
+  PCS_HIP(hipStreamSynchronize(s));
+  uint64_t m64;
+  std::memcpy(&m64, ctx->host_small, 8);
+  const uint32_t zmin = ctx->host_small[2], zmax = ctx->host_small[3];
+  if (m64 >= (uint64_t(1) << 30))
+    return fail(PCS_ERR_UNSUPPORTED, "instance count " + std::to_string(m64) + " is not below 2^30");
+  const int64_t m = (int64_t)m64;
+  const int depth_bits = m > 0 ? bit_length((uint64_t)(zmax - zmin)) : 0;
+  const int tile_bits = bit_length((uint64_t)(total_tiles - 1));
+  const int bits = depth_bits + tile_bits;
+
+  PCS_TRY(ensure(st->keys, std::max<int64_t>(m, 1) * sizeof(uint64_t), "keys"));
+  PCS_TRY(ensure(st->vals, std::max<int64_t>(m, 1) * sizeof(uint32_t), "values"));
+  PCS_TRY(ensure(ctx->keys_alt, std::max<int64_t>(m, 1) * sizeof(uint64_t), "keys (alternate)"));
+  PCS_TRY(ensure(ctx->vals_alt, std::max<int64_t>(m, 1) * sizeof(uint32_t), "values (alternate)"));
+  PCS_TRY(ensure(ctx->sort_scratch, sort_scratch_bytes(m), "sort scratch"));
+  if (m > 0) {
+    {
+      StageTimer tm(ctx, ST_BINNING, s);
+      PCS_HIP(launch_binning(n, n_cams, TX, tiles_per_cam, ctx->meta.as<uint4>(),
+                             ctx->counts.as<uint32_t>(), ctx->offsets.as<uint32_t>(), zmin,
+                             depth_bits, st->keys.as<uint64_t>(), st->vals.as<uint32_t>(), s));
+    }
+    bool in_alt = false;
+    {
+      StageTimer tm(ctx, ST_SORT, s);
+      PCS_HIP(launch_sort(st->keys.as<uint64_t>(), st->vals.as<uint32_t>(), ctx->keys_alt.as<uint64_t>(),
+                          ctx->vals_alt.as<uint32_t>(), m, bits, ctx->sort_scratch.p, s, &in_alt,
+                          nullptr, nullptr));
+    }
+    if (in_alt) {
+      swap_buf(st->keys, ctx->keys_alt);
+      swap_buf(st->vals, ctx->vals_alt);
+    }
+  }
+  {
+    StageTimer tm(ctx, ST_RANGES, s);
+    PCS_HIP(launch_ranges(st->keys.as<uint64_t>(), m, depth_bits, total_tiles,
+                          st->ranges.as<uint32_t>(), s));
+  }
+  {
+    StageTimer tm(ctx, ST_COMPOSITE, s);
+    PCS_HIP(launch_composite(n, n_cams, W, H, st->rec.as<float4>(), st->vals.as<uint32_t>(),
+                             st->ranges.as<uint32_t>(), dopt, *out, st->t_final.as<float>(),
+                             st->n_contrib.as<int32_t>(), s));
+  }
+  st->g = *g;
+  st->cams.assign(cams, cams + n_cams);
+  st->opt = *opt;
+  st->W = W;
+  st->H = H;
+  st->C = n_cams;
+  st->n = n;
+  st->m = m;
+  st->n_tiles = total_tiles;
+  st->depth_bits = depth_bits;
+  st->zmin = zmin;
+  st->valid = true;
+  return PCS_OK;
+}
+
+int pcs_render_backward(pcs_context* ctx, const pcs_state* st, const pcs_images* grad_out,
+                        const pcs_grads* grads, void* stream) {
+  if (!ctx || !st || !grad_out || !grads) return fail(PCS_ERR_INVALID_ARG, "NULL argument");
+  if (st->ctx != ctx) return fail(PCS_ERR_INVALID_ARG, "state belongs to another context");
+  if (!st->valid) return fail(PCS_ERR_INVALID_ARG, "state holds no completed forward render");
+  PCS_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int64_t cn = st->n * st->C;
+  if (cn == 0) return PCS_OK;
+  PCS_TRY(ensure(ctx->sgrad, (size_t)cn * kScreenGrads * sizeof(float), "screen-space gradients"));
+  PCS_HIP(launch_fill_f32(ctx->sgrad.as<float>(), 0.0f, cn * kScreenGrads, s));
+  const DevOptions dopt = to_dev(st->opt);
+  {
+    StageTimer tm(ctx, ST_BWD_COMPOSITE, s);
+    PCS_HIP(launch_composite_backward(st->n, st->C, st->W, st->H, st->rec.as<float4>(),
+                                      st->vals.as<uint32_t>(), st->ranges.as<uint32_t>(), dopt,
+                                      st->t_final.as<float>(), st->n_contrib.as<int32_t>(),
+                                      *grad_out, ctx->sgrad.as<float>(), s));
+  }
+  {
+    StageTimer tm(ctx, ST_BWD_PROJECT, s);
+    PCS_HIP(launch_project_backward(st->n, st->C, st->dcams.as<DevCamera>(), dopt, st->g,
+                                    ctx->sgrad.as<float>(), *grads, s));
+  }
+  return PCS_OK;
+}
+
+int pcs_state_bins(const pcs_state* st_c, const uint64_t** keys, const uint32_t** vals, int64_t* m,
+                   const uint32_t** ranges, int64_t* n_tiles, const int32_t** n_contrib,
+                   const float** t_final) {
+  if (!st_c) return fail(PCS_ERR_INVALID_ARG, "state is NULL");
+  if (!st_c->valid) return fail(PCS_ERR_INVALID_ARG, "state holds no completed forward render");
+  pcs_state* st = const_cast<pcs_state*>(st_c);
+  PCS_HIP(hipSetDevice(st->ctx->device));
+  PCS_TRY(ensure(st->canon, std::max<int64_t>(st->m, 1) * sizeof(uint64_t), "canonical keys"));
+  PCS_HIP(hipDeviceSynchronize());
+  PCS_HIP(launch_canonical_keys(st->keys.as<uint64_t>(), st->m, st->depth_bits, st->zmin,
+                                st->canon.as<uint64_t>(), nullptr));
+  PCS_HIP(hipDeviceSynchronize());
+  if (keys) *keys = st->canon.as<uint64_t>();
+  if (vals) *vals = st->vals.as<uint32_t>();
+  if (m) *m = st->m;
+  if (ranges) *ranges = st->ranges.as<uint32_t>();
+  if (n_tiles) *n_tiles = st->n_tiles;
+  if (n_contrib) *n_contrib = st->n_contrib.as<int32_t>();
+  if (t_final) *t_final = st->t_final.as<float>();
+  return PCS_OK;
+}
+
+int pcs_knn_pca(pcs_context* ctx, const float* xyz, int64_t n, int32_t k, float kappa,
+                float floor_ratio, float* quat, float* scale, float* normal, void* stream) {
+  if (!ctx) return fail(PCS_ERR_INVALID_ARG, "context is NULL");
+  if (n < 0 || (n > 0 && (!xyz || !quat || !scale || !normal)))
+    return fail(PCS_ERR_INVALID_ARG, "bad point buffers");
+  if (k < 1 || k > 32) return fail(PCS_ERR_INVALID_ARG, "k must be in [1, 32]");
+  if (n > 0 && k > n) return fail(PCS_ERR_INVALID_ARG, "k exceeds the number of points");
+  if (!std::isfinite(kappa) || !std::isfinite(floor_ratio) || kappa <= 0.0f || floor_ratio < 0.0f)
+    return fail(PCS_ERR_INVALID_ARG, "kappa must be positive and floor_ratio non-negative");
+  if (n >= (int64_t(1) << 31)) return fail(PCS_ERR_UNSUPPORTED, "n must be below 2^31");
+  if (n == 0) return PCS_OK;
+  PCS_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  PCS_TRY(ensure(ctx->knn_scratch, knn_scratch_bytes(n), "kNN scratch"));
+  StageTimer tm(ctx, ST_KNN, s);
+  PCS_HIP(launch_knn_pca(xyz, n, k, kappa, floor_ratio, quat, scale, normal, ctx->knn_scratch.p,
+                         ctx->knn_scratch.cap, s));
+  return PCS_OK;
+}
+
+}  // extern "C"

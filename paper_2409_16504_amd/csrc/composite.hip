@@ -1,0 +1,398 @@
+// Per-tile front-to-back compositing (Section 3.1, Eq. 1-2) and its adjoint.
+//
+// One 256-thread block per 16x16 screen tile (four wave64s, each owning four pixel rows). The
+// tile's depth-sorted splat list is staged through LDS in batches of 256 records; every pixel
+// walks the batch in order, tests the 3-sigma ellipse, evaluates alpha = o * exp(-q/2), and
+// blends RGB, normal and depth until its transmittance drops below t_eps. A block stops loading
+// batches once every pixel has terminated (block-wide vote).
+//
+// The adjoint walks the same list back to front from each pixel's last contributor, recovering
+// the transmittance by division, keeps a running sum of what lies behind each splat, and reduces
+// each splat's 13 screen-space partials across the wavefront before one atomic add per value.
+
+#include "projection.hpp"
+
+namespace pcs {
+
+namespace {
+
+constexpr int kBlock = kTilePixels;   // 256 threads, one per pixel
+
+__global__ __launch_bounds__(kBlock) void k_composite(
+    int64_t n, int W, int H, int TX, int64_t tiles_per_cam, int64_t total_tiles,
+    const float4* __restrict__ rec, const uint32_t* __restrict__ vals,
+    const uint32_t* __restrict__ ranges, DevOptions opt, float* __restrict__ out_rgb,
+    float* __restrict__ out_nrm, float* __restrict__ out_depth, float* __restrict__ out_alpha,
+    float* __restrict__ t_final, int32_t* __restrict__ n_contrib) {
+  __shared__ float4 s_r0[kBlock], s_r1[kBlock], s_r2[kBlock], s_r3[kBlock];
+  const int64_t tile = xcd_remap(blockIdx.x, total_tiles);
+  const int64_t cam = tile / tiles_per_cam;
+  const int64_t t = tile - cam * tiles_per_cam;
+  const int tx = (int)(t % TX), ty = (int)(t / TX);
+  const int tid = threadIdx.x;
+  const int x = tx * kTile + (tid & (kTile - 1)), y = ty * kTile + (tid >> 4);
+  const bool inside = x < W && y < H;
+  const float pxf = (float)x + 0.5f, pyf = (float)y + 0.5f;
+  const uint32_t start = ranges[tile], end = ranges[total_tiles + tile];
+  const float cut2 = opt.sigma_cut * opt.sigma_cut;
+  const float4* rec_cam = rec + cam * n * kRecFloat4;
+  float T = 1.0f;
+  float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f, acc4 = 0.f, acc5 = 0.f, acc6 = 0.f;
+  int32_t last = 0;
+  bool done = !inside;
+  for (uint32_t b = start; b < end; b += kBlock) {
+    if (__syncthreads_count(done) == kBlock) break;
+    const uint32_t j = b + tid;
+    if (j < end) {
+      const uint32_t gi = min(vals[j], (uint32_t)(n - 1));   // indices are < n by construction
+      const float4* r = rec_cam + (int64_t)gi * kRecFloat4;
+      s_r0[tid] = r[0];
+      s_r1[tid] = r[1];
+      s_r2[tid] = r[2];
+      s_r3[tid] = r[3];
+    }
+    __syncthreads();
+    if (!done) {
+      const int cnt = (int)min((uint32_t)kBlock, end - b);
+      for (int k = 0; k < cnt; ++k) {
+        const float4 r0 = s_r0[k];
+        const float4 r1 = s_r1[k];
+        const float dx = pxf - r0.x, dy = pyf - r0.y;
+        const float q = conic_q(r1.x, r1.y, r1.z, dx, dy);
+        if (!(q <= cut2)) continue;
+        const float a = fminf(opt.alpha_max, r0.z * __expf(-0.5f * q));
+        if (a < opt.alpha_min) continue;
+        const float w = a * T;
+        const float4 r2 = s_r2[k];
+        const float4 r3 = s_r3[k];
+        acc0 = fmaf(w, r2.x, acc0);
+        acc1 = fmaf(w, r2.y, acc1);
+        acc2 = fmaf(w, r2.z, acc2);
+        acc3 = fmaf(w, r3.x, acc3);
+        acc4 = fmaf(w, r3.y, acc4);
+        acc5 = fmaf(w, r3.z, acc5);
+        acc6 = fmaf(w, r0.w, acc6);
+        T = T * (1.0f - a);
+        last = (int32_t)(b - start) + k + 1;
+        if (T < opt.t_eps) {
+          done = true;
+          break;
+        }
+      }
+    }
+  }
+  if (!inside) return;
+  const int64_t HW = (int64_t)W * H;
+  const int64_t pix = (int64_t)y * W + x;
+  const int64_t c3 = cam * 3 * HW;
+  out_rgb[c3 + pix] = acc0 + T * opt.bg[0];
+  out_rgb[c3 + HW + pix] = acc1 + T * opt.bg[1];
+  out_rgb[c3 + 2 * HW + pix] = acc2 + T * opt.bg[2];
+  if (out_nrm) {
+    out_nrm[c3 + pix] = acc3;
+    out_nrm[c3 + HW + pix] = acc4;
+    out_nrm[c3 + 2 * HW + pix] = acc5;
+  }
+  if (out_depth) out_depth[cam * HW + pix] = acc6;
+  if (out_alpha) out_alpha[cam * HW + pix] = 1.0f - T;
+  if (t_final) t_final[cam * HW + pix] = T;
+  if (n_contrib) n_contrib[cam * HW + pix] = last;
+}
+
+__global__ __launch_bounds__(kBlock) void k_composite_bwd(
+    int64_t n, int W, int H, int TX, int64_t tiles_per_cam, int64_t total_tiles,
+    const float4* __restrict__ rec, const uint32_t* __restrict__ vals,
+    const uint32_t* __restrict__ ranges, DevOptions opt, const float* __restrict__ t_final,
+    const int32_t* __restrict__ n_contrib, const float* __restrict__ g_rgb,
+    const float* __restrict__ g_nrm, const float* __restrict__ g_depth,
+    float* __restrict__ sgrad, int64_t stride) {
+  __shared__ float4 s_r0[kBlock], s_r1[kBlock], s_r2[kBlock], s_r3[kBlock];
+  __shared__ uint32_t s_g[kBlock];
+  __shared__ int32_t s_max;
+  const int64_t tile = xcd_remap(blockIdx.x, total_tiles);
+  const int64_t cam = tile / tiles_per_cam;
+  const int64_t t = tile - cam * tiles_per_cam;
+  const int tx = (int)(t % TX), ty = (int)(t / TX);
+  const int tid = threadIdx.x;
+  const int x = tx * kTile + (tid & (kTile - 1)), y = ty * kTile + (tid >> 4);
+  const bool inside = x < W && y < H;
+  const float pxf = (float)x + 0.5f, pyf = (float)y + 0.5f;
+  const uint32_t start = ranges[tile];
+  const float cut2 = opt.sigma_cut * opt.sigma_cut;
+  const float4* rec_cam = rec + cam * n * kRecFloat4;
+  const int64_t HW = (int64_t)W * H;
+  const int64_t pix = (int64_t)y * W + x;
+  float T = 1.0f;
+  int32_t nc = 0;
+  float g[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (inside) {
+    T = t_final[cam * HW + pix];
+    nc = n_contrib[cam * HW + pix];
+    const int64_t c3 = cam * 3 * HW;
+    if (g_rgb) { g[0] = g_rgb[c3 + pix]; g[1] = g_rgb[c3 + HW + pix]; g[2] = g_rgb[c3 + 2 * HW + pix]; }
+    if (g_nrm) { g[3] = g_nrm[c3 + pix]; g[4] = g_nrm[c3 + HW + pix]; g[5] = g_nrm[c3 + 2 * HW + pix]; }
+    if (g_depth) g[6] = g_depth[cam * HW + pix];
+  }
+  // what lies behind the current splat: sum_{j>k} T_j a_j f_j + T_final * bg
+  float behind[7] = {T * opt.bg[0], T * opt.bg[1], T * opt.bg[2], 0.f, 0.f, 0.f, 0.f};
+  if (tid == 0) s_max = 0;
+  __syncthreads();
+  if (nc > 0) atomicMax(&s_max, nc);
+  __syncthreads();
+  const int32_t max_nc = s_max;
+  const int64_t base_idx = cam * n;
+  for (int32_t bend = max_nc; bend > 0; bend -= kBlock) {
+    const int32_t bstart = max(0, bend - kBlock);
+    __syncthreads();
+    const int32_t pos = bstart + tid;
+    if (pos < bend) {
+      const uint32_t gi = min(vals[start + pos], (uint32_t)(n - 1));
+      const float4* r = rec_cam + (int64_t)gi * kRecFloat4;
+      s_r0[tid] = r[0];
+      s_r1[tid] = r[1];
+      s_r2[tid] = r[2];
+      s_r3[tid] = r[3];
+      s_g[tid] = gi;
+    }
+    __syncthreads();
+    for (int k = bend - bstart - 1; k >= 0; --k) {
+      const int32_t p = bstart + k;
+      float pg[kScreenGrads];
+#pragma unroll
+      for (int i = 0; i < kScreenGrads; ++i) pg[i] = 0.f;
+      bool contrib = false;
+      if (p < nc) {
+        const float4 r0 = s_r0[k];
+        const float4 r1 = s_r1[k];
+        const float dx = pxf - r0.x, dy = pyf - r0.y;
+        const float q = conic_q(r1.x, r1.y, r1.z, dx, dy);
+        if (q <= cut2) {
+          const float e = __expf(-0.5f * q);
+          const float araw = r0.z * e;
+          const float a = fminf(opt.alpha_max, araw);
+          if (a >= opt.alpha_min) {
+            contrib = true;
+            const float4 r2 = s_r2[k];
+            const float4 r3 = s_r3[k];
+            const float one_m = 1.0f - a;
+            T = T / one_m;                       // transmittance in front of this splat
+            const float w = a * T;
+            const float f[7] = {r2.x, r2.y, r2.z, r3.x, r3.y, r3.z, r0.w};
+            float dLda = 0.f;
+            const float inv = 1.0f / one_m;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) {
+              dLda = fmaf(g[c], fmaf(T, f[c], -behind[c] * inv), dLda);
+              behind[c] = fmaf(w, f[c], behind[c]);
+            }
+            pg[7] = g[0] * w;
+            pg[8] = g[1] * w;
+            pg[9] = g[2] * w;
+            pg[10] = g[3] * w;
+            pg[11] = g[4] * w;
+            pg[12] = g[5] * w;
+            pg[6] = g[6] * w;
+            if (!(araw > opt.alpha_max)) {
+              pg[5] = dLda * e;
+              const float dLdq = dLda * (-0.5f * a);
+              pg[2] = dLdq * dx * dx;
+              pg[3] = dLdq * 2.0f * dx * dy;
+              pg[4] = dLdq * dy * dy;
+              pg[0] = dLdq * (-2.0f * fmaf(r1.x, dx, r1.y * dy));
+              pg[1] = dLdq * (-2.0f * fmaf(r1.y, dx, r1.z * dy));
+            }
+          }
+        }
+      }
+      if (__ballot(contrib) == 0ull) continue;   // wave-uniform
+      const int64_t dst = base_idx + s_g[k];
+#pragma unroll
+      for (int i = 0; i < kScreenGrads; ++i) {
+        const float s = wave_sum(pg[i]);
+        if (lane_id() == 0 && s != 0.0f) unsafeAtomicAdd(&sgrad[i * stride + dst], s);
+      }
+    }
+  }
+}
+
+// Chain the per-(camera, Gaussian) screen-space gradients through the projection to the
+// Gaussian parameters (one thread per Gaussian, cameras summed in registers).
+__global__ __launch_bounds__(256) void k_project_bwd(
+    int64_t n, int n_cams, const DevCamera* __restrict__ cams, DevOptions opt,
+    const float* __restrict__ mean, const float* __restrict__ quat, const float* __restrict__ scale,
+    const float* __restrict__ sgrad, int64_t stride, float* __restrict__ d_mean,
+    float* __restrict__ d_cov, float* __restrict__ d_quat, float* __restrict__ d_scale,
+    float* __restrict__ d_opac, float* __restrict__ d_rgb, float* __restrict__ d_nrm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float px = mean[i], py = mean[n + i], pz = mean[2 * n + i];
+  const float qw = quat[i], qx = quat[n + i], qy = quat[2 * n + i], qz = quat[3 * n + i];
+  const float s0 = scale[i], s1 = scale[n + i], s2 = scale[2 * n + i];
+  float gm[3] = {0.f, 0.f, 0.f}, gS[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float go = 0.f, gc[3] = {0.f, 0.f, 0.f}, gn[3] = {0.f, 0.f, 0.f};
+  ProjGeo G;
+  bool any = false;
+  for (int c = 0; c < n_cams; ++c) {
+    float sg[kScreenGrads];
+    bool nz = false;
+#pragma unroll
+    for (int k = 0; k < kScreenGrads; ++k) {
+      sg[k] = sgrad[k * stride + (int64_t)c * n + i];
+      nz = nz || sg[k] != 0.0f;
+    }
+    if (!nz) continue;
+    any = true;
+    const DevCamera& cam = cams[c];
+    proj_geometry(px, py, pz, qw, qx, qy, qz, s0, s1, s2, cam, opt.lowpass, G);
+    // conic (A,B,C) = (c, -b, a) / det  ->  Sigma_s = [[a, b], [b, c]]
+    const float a = G.a, b = G.b, cc = G.c, det = G.det;
+    const float id = 1.0f / det, id2 = id * id;
+    const float gA = sg[2], gB = sg[3], gC = sg[4];
+    const float ga = gA * (-cc * cc * id2) + gB * (b * cc * id2) + gC * (id - a * cc * id2);
+    const float gb = gA * (2.0f * b * cc * id2) + gB * (-id - 2.0f * b * b * id2) + gC * (2.0f * a * b * id2);
+    const float gcv = gA * (id - a * cc * id2) + gB * (a * b * id2) + gC * (-a * a * id2);
+    const float Gs[4] = {ga, 0.5f * gb, 0.5f * gb, gcv};
+    const float* M = G.M;
+    // dL/dSigma = M^T Gs M
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        gS[3 * j + k] += M[j] * (Gs[0] * M[k] + Gs[1] * M[3 + k]) +
+                         M[3 + j] * (Gs[2] * M[k] + Gs[3] * M[3 + k]);
+    // dL/dM = 2 Gs M Sigma ; dL/dJ = dL/dM T^T
+    float GM[6];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        float acc = 0.f;
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          acc += (Gs[2 * r] * M[j] + Gs[2 * r + 1] * M[3 + j]) * G.S[3 * j + k];
+        GM[3 * r + k] = 2.0f * acc;
+      }
+    const float* T = cam.T;
+    float GJ[6];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+        GJ[3 * r + m] = GM[3 * r] * T[3 * m] + GM[3 * r + 1] * T[3 * m + 1] + GM[3 * r + 2] * T[3 * m + 2];
+    const float z = G.zc, iz = 1.0f / z, iz2 = iz * iz, iz3 = iz2 * iz;
+    const float fx = cam.fx, fy = cam.fy;
+    float gx = GJ[2] * (-fx * iz2);
+    float gy = GJ[5] * (-fy * iz2);
+    float gz = GJ[0] * (-fx * iz2) + GJ[4] * (-fy * iz2) + GJ[2] * (2.0f * fx * G.xc * iz3) +
+               GJ[5] * (2.0f * fy * G.yc * iz3);
+    gx += sg[0] * fx * iz;
+    gz += sg[0] * (-fx * G.xc * iz2);
+    gy += sg[1] * fy * iz;
+    gz += sg[1] * (-fy * G.yc * iz2);
+    gz += sg[6];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gm[k] += T[k] * gx + T[3 + k] * gy + T[6 + k] * gz;
+    go += sg[5];
+    gc[0] += sg[7]; gc[1] += sg[8]; gc[2] += sg[9];
+    gn[0] += sg[10]; gn[1] += sg[11]; gn[2] += sg[12];
+  }
+  if (!any) return;
+  if (d_mean) { d_mean[i] += gm[0]; d_mean[n + i] += gm[1]; d_mean[2 * n + i] += gm[2]; }
+  if (d_cov) {
+    d_cov[i] += gS[0];
+    d_cov[n + i] += gS[1] + gS[3];
+    d_cov[2 * n + i] += gS[2] + gS[6];
+    d_cov[3 * n + i] += gS[4];
+    d_cov[4 * n + i] += gS[5] + gS[7];
+    d_cov[5 * n + i] += gS[8];
+  }
+  if (d_scale || d_quat) {
+    // Sigma = R diag(s^2) R^T: dL/ds_m = 2 s_m (R^T G R)_mm, dL/dR = 2 G R diag(s^2)
+    const float* R = G.R;
+    const float sc[3] = {s0, s1, s2};
+    if (d_scale) {
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        float acc = 0.f;
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+          for (int k = 0; k < 3; ++k) acc += R[3 * j + m] * gS[3 * j + k] * R[3 * k + m];
+        d_scale[m * n + i] += 2.0f * sc[m] * acc;
+      }
+    }
+    if (d_quat && G.qlen > 0.0f) {
+      float GR[9];
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          float acc = 0.f;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) acc += gS[3 * j + k] * R[3 * k + m];
+          GR[3 * j + m] = 2.0f * acc * G.v[m];
+        }
+      const float w = G.qw, x = G.qx, y = G.qy, z = G.qz;
+      float gq[4];
+      gq[0] = 2.0f * (-z * GR[1] + y * GR[2] + z * GR[3] - x * GR[5] - y * GR[6] + x * GR[7]);
+      gq[1] = 2.0f * (y * GR[1] + z * GR[2] + y * GR[3] - 2.0f * x * GR[4] - w * GR[5] + z * GR[6] +
+                      w * GR[7] - 2.0f * x * GR[8]);
+      gq[2] = 2.0f * (-2.0f * y * GR[0] + x * GR[1] + w * GR[2] + x * GR[3] + z * GR[5] - w * GR[6] +
+                      z * GR[7] - 2.0f * y * GR[8]);
+      gq[3] = 2.0f * (-2.0f * z * GR[0] - w * GR[1] + x * GR[2] + w * GR[3] - 2.0f * z * GR[4] +
+                      y * GR[5] + x * GR[6] + y * GR[7]);
+      const float dot = w * gq[0] + x * gq[1] + y * gq[2] + z * gq[3];
+      const float il = 1.0f / G.qlen;
+      d_quat[i] += (gq[0] - w * dot) * il;
+      d_quat[n + i] += (gq[1] - x * dot) * il;
+      d_quat[2 * n + i] += (gq[2] - y * dot) * il;
+      d_quat[3 * n + i] += (gq[3] - z * dot) * il;
+    }
+  }
+  if (d_opac) d_opac[i] += go;
+  if (d_rgb) { d_rgb[i] += gc[0]; d_rgb[n + i] += gc[1]; d_rgb[2 * n + i] += gc[2]; }
+  if (d_nrm) { d_nrm[i] += gn[0]; d_nrm[n + i] += gn[1]; d_nrm[2 * n + i] += gn[2]; }
+}
+
+}  // namespace
+
+hipError_t launch_composite(int64_t n, int n_cams, int W, int H, const float4* rec,
+                            const uint32_t* vals, const uint32_t* ranges, const DevOptions& opt,
+                            const pcs_images& out, float* t_final, int32_t* n_contrib,
+                            hipStream_t s) {
+  const int TX = (W + kTile - 1) / kTile, TY = (H + kTile - 1) / kTile;
+  const int64_t tiles_per_cam = (int64_t)TX * TY;
+  const int64_t total = tiles_per_cam * n_cams;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_composite, dim3((unsigned)total), dim3(kBlock), 0, s, n, W, H, TX,
+                     tiles_per_cam, total, rec, vals, ranges, opt, out.rgb, out.normal, out.depth,
+                     out.alpha, t_final, n_contrib);
+  return hipGetLastError();
+}
+
+hipError_t launch_composite_backward(int64_t n, int n_cams, int W, int H, const float4* rec,
+                                     const uint32_t* vals, const uint32_t* ranges,
+                                     const DevOptions& opt, const float* t_final,
+                                     const int32_t* n_contrib, const pcs_images& grad_out,
+                                     float* sgrad, hipStream_t s) {
+  const int TX = (W + kTile - 1) / kTile, TY = (H + kTile - 1) / kTile;
+  const int64_t tiles_per_cam = (int64_t)TX * TY;
+  const int64_t total = tiles_per_cam * n_cams;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_composite_bwd, dim3((unsigned)total), dim3(kBlock), 0, s, n, W, H, TX,
+                     tiles_per_cam, total, rec, vals, ranges, opt, t_final, n_contrib,
+                     grad_out.rgb, grad_out.normal, grad_out.depth, sgrad, n * n_cams);
+  return hipGetLastError();
+}
+
+hipError_t launch_project_backward(int64_t n, int n_cams, const DevCamera* cams,
+                                   const DevOptions& opt, const pcs_gaussians& g,
+                                   const float* sgrad, const pcs_grads& grads, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, n_cams,
+                     cams, opt, g.mean, g.quat, g.scale, sgrad, n * n_cams, grads.mean, grads.cov6,
+                     grads.quat, grads.scale, grads.opacity, grads.rgb, grads.normal);
+  return hipGetLastError();
+}
+
+}  // namespace pcs

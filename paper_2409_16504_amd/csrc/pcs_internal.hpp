@@ -1,0 +1,141 @@
+// Internal declarations shared by the HIP translation units of libpcsplat.so (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "pcsplat.h"
+
+namespace pcs {
+
+constexpr int kTile = 16;          // screen tile edge in pixels
+constexpr int kTilePixels = kTile * kTile;
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kRecFloat4 = 4;      // splat record: 4 x float4 = 64 bytes
+
+// Camera as the kernels see it.
+struct DevCamera {
+  float T[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t W, H;
+  int32_t pad[2];
+};
+
+struct DevOptions {
+  float z_near, lowpass, sigma_cut, alpha_min, alpha_max, t_eps;
+  float bg[3];
+};
+
+// Splat record written by the projection for every visible (camera, Gaussian), read by
+// compositing and its adjoint:
+//   r0 = (u, v, opacity, z)   r1 = (A, B, C, radius)   r2 = (r, g, b, 0)   r3 = (nx, ny, nz, 0)
+// where (A, B, C) is the conic (inverse screen covariance) and radius the 3-sigma half extent.
+// Meta record for binning: (fp32 depth bits, x0 | x1 << 16, y0 | y1 << 16, 0).
+
+// ---- wave64 helpers -------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// Inclusive prefix sum across the wave (Hillis-Steele with cross-lane shuffles).
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    uint32_t t = __shfl_up(v, o, kWave);
+    if (l >= o) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint64_t wave_inclusive_scan64(uint64_t v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    uint64_t t = __shfl_up(v, o, kWave);
+    if (l >= o) v += t;
+  }
+  return v;
+}
+
+// Sum across the wave using row-local DPP shifts and four lane reads; every lane gets the total.
+__device__ __forceinline__ float wave_sum(float v) {
+  // row_shr:1,2,4,8 within 16-lane rows (bound_ctrl so shifted-in lanes read 0)
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xF, 0xF, true));
+  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 15));
+  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 31));
+  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 47));
+  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+  return (r0 + r1) + (r2 + r3);
+}
+
+// Block-to-tile remap: consecutive tiles land on the same XCD (blocks are dealt round-robin to
+// the 8 XCDs), so neighbouring tiles that share splat records share that XCD's L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
+  const int64_t q = nblocks / 8, r = nblocks % 8;
+  const int64_t xcd = bid % 8, slot = bid / 8;
+  return xcd * q + (xcd < r ? xcd : r) + slot;   // XCD x owns tiles [x q + min(x, r), ...)
+}
+
+// ---- launchers (stream-ordered, return the launch error) ------------------------------------
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
+hipError_t launch_fill_f32(float* p, float value, int64_t n, hipStream_t s);
+
+hipError_t launch_project(int64_t n, int n_cams, const DevCamera* cams, const DevOptions& opt,
+                          const pcs_gaussians& g, float4* rec, uint4* meta, uint32_t* counts,
+                          uint32_t* zrange /*[2]: min, max depth bits (pre-set to ~0, 0)*/,
+                          hipStream_t s);
+
+// Exclusive scan of n u32 values; writes out[n] and *total (u64). Scratch from scan_scratch_bytes.
+size_t scan_scratch_bytes(int64_t n);
+hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, uint64_t* total,
+                       void* scratch, hipStream_t s);
+
+hipError_t launch_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_cam, const uint4* meta,
+                          const uint32_t* counts, const uint32_t* offsets, uint32_t zmin,
+                          int depth_bits, uint64_t* keys, uint32_t* vals, hipStream_t s);
+
+// LSD radix sort of (key, value) pairs over key bits [0, bits). Ping-pongs between (k0,v0) and
+// (k1,v1); returns in *result_in_alt whether the sorted data ended in (k1,v1).
+size_t sort_scratch_bytes(int64_t m);
+hipError_t launch_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t m, int bits,
+                       void* scratch, hipStream_t s, bool* result_in_alt,
+                       void (*stage_mark)(void*, int), void* mark_ctx);
+
+hipError_t launch_ranges(const uint64_t* keys, int64_t m, int depth_bits, int64_t n_tiles,
+                         uint32_t* ranges, hipStream_t s);
+
+hipError_t launch_canonical_keys(const uint64_t* keys, int64_t m, int depth_bits, uint32_t zmin,
+                                 uint64_t* out, hipStream_t s);
+
+hipError_t launch_composite(int64_t n, int n_cams, int W, int H, const float4* rec,
+                            const uint32_t* vals, const uint32_t* ranges, const DevOptions& opt,
+                            const pcs_images& out, float* t_final, int32_t* n_contrib,
+                            hipStream_t s);
+
+// Backward: per-(camera, Gaussian) screen-space gradient accumulators, planar [13][C*n]:
+// u, v, A, B, C, opacity, depth, r, g, b, nx, ny, nz.
+constexpr int kScreenGrads = 13;
+hipError_t launch_composite_backward(int64_t n, int n_cams, int W, int H, const float4* rec,
+                                     const uint32_t* vals, const uint32_t* ranges,
+                                     const DevOptions& opt, const float* t_final,
+                                     const int32_t* n_contrib, const pcs_images& grad_out,
+                                     float* sgrad, hipStream_t s);
+hipError_t launch_project_backward(int64_t n, int n_cams, const DevCamera* cams,
+                                   const DevOptions& opt, const pcs_gaussians& g,
+                                   const float* sgrad, const pcs_grads& grads, hipStream_t s);
+
+hipError_t launch_knn_pca(const float* xyz, int64_t n, int k, float kappa, float floor_ratio,
+                          float* quat, float* scale, float* normal, void* scratch,
+                          size_t scratch_bytes, hipStream_t s);
+size_t knn_scratch_bytes(int64_t n);
+
+}  // namespace pcs

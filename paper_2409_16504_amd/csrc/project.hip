@@ -1,0 +1,122 @@
+// Projection of every (camera, Gaussian): EWA screen covariance, conic, 3-sigma extent, tile
+// rectangle (Section 3.1, Eq. 3-4), plus the splat record the compositor stages.
+//
+// The arithmetic up to the tile rectangle is a fixed IEEE-FP32 operation sequence: each line
+// below is one correctly rounded operation evaluated left to right, and this file is compiled
+// without multiply-add contraction. Binning depends only on these values, so the (tile, depth)
+// key lists are reproducible bit for bit by any implementation of the same sequence.
+//
+// One thread per (camera, Gaussian); the planar inputs make every load a coalesced 4-byte stream.
+
+#include "projection.hpp"
+
+namespace pcs {
+
+namespace {
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
+__global__ void k_fill_f32(float* __restrict__ p, float value, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
+__device__ __forceinline__ bool fin(float x) { return isfinite(x); }
+
+__global__ __launch_bounds__(256) void k_project(
+    int64_t n, const DevCamera* __restrict__ cams, DevOptions opt,
+    const float* __restrict__ mean, const float* __restrict__ quat,
+    const float* __restrict__ scale, const float* __restrict__ opac,
+    const float* __restrict__ rgb, const float* __restrict__ nrm, float4* __restrict__ rec,
+    uint4* __restrict__ meta, uint32_t* __restrict__ counts, uint32_t* __restrict__ zrange) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  const DevCamera& cam = cams[c];
+  const int64_t out = (int64_t)c * n + i;
+  bool visible = false;
+  uint32_t zbits = 0;
+  if (i < n) {
+    const float px = mean[i], py = mean[n + i], pz = mean[2 * n + i];
+    const float qw = quat[i], qx = quat[n + i], qy = quat[2 * n + i], qz = quat[3 * n + i];
+    const float s0 = scale[i], s1 = scale[n + i], s2 = scale[2 * n + i];
+    const float o = opac[i];
+    const float cr = rgb[i], cg = rgb[n + i], cb = rgb[2 * n + i];
+    const float nx = nrm[i], ny = nrm[n + i], nz = nrm[2 * n + i];
+    bool ok = fin(px) && fin(py) && fin(pz) && fin(qw) && fin(qx) && fin(qy) && fin(qz) &&
+              fin(s0) && fin(s1) && fin(s2) && fin(o) && fin(cr) && fin(cg) && fin(cb) &&
+              fin(nx) && fin(ny) && fin(nz) && (o >= opt.alpha_min);
+    ProjGeo G;
+    ok = proj_geometry(px, py, pz, qw, qx, qy, qz, s0, s1, s2, cam, opt.lowpass, G) && ok;
+    const float zc = G.zc, u = G.u, v = G.v2;
+    ok = ok && (zc > opt.z_near) && fin(G.xc) && fin(G.yc) && fin(zc);
+    ok = ok && (G.det > 0.0f);
+    const float A = G.c / G.det, B = -(G.b / G.det), C = G.a / G.det;
+    const float mid = 0.5f * (G.a + G.c);
+    const float disc = mid * mid - G.det;
+    const float lam = mid + sqrtf(fmaxf(disc, 0.0f));
+    const float rad = ceilf(opt.sigma_cut * sqrtf(lam));
+    ok = ok && fin(u) && fin(v) && fin(A) && fin(B) && fin(C) && fin(rad);
+    // tile rectangle of the square [u - r, u + r] x [v - r, v + r]
+    const int TX = (cam.W + kTile - 1) / kTile, TY = (cam.H + kTile - 1) / kTile;
+    const float ts = (float)kTile;
+    const float fx0 = floorf((u - rad) / ts), fx1 = floorf((u + rad) / ts);
+    const float fy0 = floorf((v - rad) / ts), fy1 = floorf((v + rad) / ts);
+    ok = ok && !(fx1 < 0.0f || fy1 < 0.0f || fx0 > (float)(TX - 1) || fy0 > (float)(TY - 1));
+    if (ok) {
+      const int x0 = (int)fmaxf(fx0, 0.0f), x1 = (int)fminf(fx1, (float)(TX - 1));
+      const int y0 = (int)fmaxf(fy0, 0.0f), y1 = (int)fminf(fy1, (float)(TY - 1));
+      visible = true;
+      zbits = __float_as_uint(zc);
+      counts[out] = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+      meta[out] = make_uint4(zbits, (uint32_t)x0 | ((uint32_t)x1 << 16),
+                             (uint32_t)y0 | ((uint32_t)y1 << 16), 0u);
+      float4* r = rec + out * kRecFloat4;
+      r[0] = make_float4(u, v, o, zc);
+      r[1] = make_float4(A, B, C, rad);
+      r[2] = make_float4(cr, cg, cb, 0.0f);
+      r[3] = make_float4(nx, ny, nz, 0.0f);
+    } else {
+      counts[out] = 0u;
+    }
+  }
+  // depth-bit range of the visible splats: one atomic pair per wavefront
+  uint32_t lo = visible ? zbits : 0xFFFFFFFFu, hi = visible ? zbits : 0u;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    lo = min(lo, (uint32_t)__shfl_xor((int)lo, o, kWave));
+    hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, kWave));
+  }
+  if (lane_id() == 0 && hi != 0u) {
+    atomicMin(&zrange[0], lo);
+    atomicMax(&zrange[1], hi);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, value, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float* p, float value, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, value, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_project(int64_t n, int n_cams, const DevCamera* cams, const DevOptions& opt,
+                          const pcs_gaussians& g, float4* rec, uint4* meta, uint32_t* counts,
+                          uint32_t* zrange, hipStream_t s) {
+  if (n <= 0 || n_cams <= 0) return hipSuccess;
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)n_cams);
+  hipLaunchKernelGGL(k_project, grid, dim3(256), 0, s, n, cams, opt, g.mean, g.quat, g.scale,
+                     g.opacity, g.rgb, g.normal, rec, meta, counts, zrange);
+  return hipGetLastError();
+}
+
+}  // namespace pcs

@@ -1,0 +1,425 @@
+// Instance counting, (tile | depth) key emission, LSD radix sort and tile ranges.
+//
+//  * scan:     single-pass exclusive prefix sum with decoupled look-back (Merrill & Garland,
+//              "Single-pass Parallel Prefix Scan with Decoupled Look-back", 2016). A block takes
+//              its partition from an atomic ticket, so it only ever waits on partitions whose
+//              blocks are already running; the look-back reads 64 predecessors per step, one per
+//              lane of a wavefront.
+//  * binning:  one thread per visible (camera, Gaussian) writes its tile keys in rectangle order.
+//  * sort:     Onesweep-style LSD radix sort (Adinets & Merrill, "Onesweep: A Faster Least
+//              Significant Digit Radix Sort for GPUs", 2022): one histogram pass over all digits,
+//              then one chained-scan scatter per 8-bit digit. Ranks inside a wavefront come from
+//              eight ballots (lanes holding the same digit), so the sort is stable; each block
+//              reorders its 4096 keys through LDS so global writes leave in digit runs.
+//  * ranges:   tile start/end from tile-id changes in the sorted keys.
+//
+// Keys are packed as (global tile id << depth_bits) | (fp32 depth bits - minimum depth bits):
+// positive floats order like their bit patterns, so this is the (tile, depth) order of the
+// canonical key ((tile << 32) | depth bits) with only the significant bits left to sort.
+
+#include "pcs_internal.hpp"
+
+namespace pcs {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 16;
+constexpr int kPart = kThreads * kItems;   // 4096 elements per partition
+constexpr int kWaves = kThreads / kWave;
+
+// ---- scan -----------------------------------------------------------------------------------
+constexpr uint64_t kScanAgg = 1ull << 62;
+constexpr uint64_t kScanPrefix = 2ull << 62;
+constexpr uint64_t kScanValue = (1ull << 62) - 1;
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+__device__ __forceinline__ uint64_t atomic_load_u64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void atomic_store_u64(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t atomic_load_u32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void atomic_store_u32(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* __restrict__ in,
+                                                   uint32_t* __restrict__ out, int64_t n,
+                                                   int64_t n_parts, uint64_t* __restrict__ status,
+                                                   uint32_t* __restrict__ ticket,
+                                                   uint64_t* __restrict__ total) {
+  __shared__ uint32_t s_part;
+  __shared__ uint64_t s_wave[kWaves];
+  __shared__ uint64_t s_excl;
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  if (tid == 0) s_part = atomicAdd(ticket, 1u);
+  __syncthreads();
+  const int64_t part = s_part;
+  const int64_t base = part * kPart + (int64_t)tid * kItems;
+  uint32_t x[kItems];
+  if (base + kItems <= n) {
+    const uint4* src = reinterpret_cast<const uint4*>(in + base);
+#pragma unroll
+    for (int q = 0; q < kItems / 4; ++q) {
+      uint4 w = src[q];
+      x[4 * q + 0] = w.x; x[4 * q + 1] = w.y; x[4 * q + 2] = w.z; x[4 * q + 3] = w.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) x[k] = (base + k < n) ? in[base + k] : 0u;
+  }
+  uint64_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) sum += x[k];
+  const uint64_t incl = wave_inclusive_scan64(sum);
+  if (lane == kWave - 1) s_wave[wave] = incl;
+  __syncthreads();
+  uint64_t wave_prefix = 0, block_total = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    if (w < wave) wave_prefix += s_wave[w];
+    block_total += s_wave[w];
+  }
+  if (wave == 0) {
+    uint64_t excl = 0;
+    if (part == 0) {
+      if (lane == 0) atomic_store_u64(&status[0], kScanPrefix | block_total);
+    } else {
+      if (lane == 0) atomic_store_u64(&status[part], kScanAgg | block_total);
+      int64_t p = part - 1;
+      uint32_t spins = 0;
+      while (true) {
+        const int64_t idx = p - lane;
+        const uint64_t v = idx >= 0 ? atomic_load_u64(&status[idx]) : kScanPrefix;
+        const uint64_t flag = v & ~kScanValue;
+        const uint64_t pre = __ballot(flag == kScanPrefix);
+        const uint64_t zero = __ballot(flag == 0);
+        const int first = pre ? __ffsll((unsigned long long)pre) - 1 : kWave;
+        const uint64_t need = first < kWave ? (first == 63 ? ~0ull : ((2ull << first) - 1)) : ~0ull;
+        // a predecessor has not published yet; the bound only guards against a broken launch
+        if ((zero & need) && ++spins < kSpinLimit) continue;
+        excl += wave_sum_u64(lane <= first ? (v & kScanValue) : 0ull);
+        if (first < kWave) break;
+        p -= kWave;
+      }
+      if (lane == 0) atomic_store_u64(&status[part], kScanPrefix | (excl + block_total));
+    }
+    if (lane == 0) s_excl = excl;
+  }
+  __syncthreads();
+  uint64_t running = s_excl + wave_prefix + incl - sum;
+  if (base + kItems <= n) {
+    uint32_t y[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) { y[k] = (uint32_t)running; running += x[k]; }
+    uint4* dst = reinterpret_cast<uint4*>(out + base);
+#pragma unroll
+    for (int q = 0; q < kItems / 4; ++q)
+      dst[q] = make_uint4(y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < kItems; ++k)
+      if (base + k < n) { out[base + k] = (uint32_t)running; running += x[k]; }
+  }
+  if (part == n_parts - 1 && tid == 0) *total = s_excl + block_total;
+}
+
+// ---- binning --------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_binning(int64_t total, int64_t n, int TX,
+                                                 int64_t tiles_per_cam,
+                                                 const uint4* __restrict__ meta,
+                                                 const uint32_t* __restrict__ counts,
+                                                 const uint32_t* __restrict__ offsets,
+                                                 uint32_t zmin, int depth_bits,
+                                                 uint64_t* __restrict__ keys,
+                                                 uint32_t* __restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const uint32_t cnt = counts[i];
+  if (cnt == 0) return;
+  const int64_t cam = i / n;
+  const uint32_t g = (uint32_t)(i - cam * n);
+  const uint4 m = meta[i];
+  const uint64_t depth = (uint64_t)(m.x - zmin);
+  const int x0 = m.y & 0xFFFF, x1 = m.y >> 16, y0 = m.z & 0xFFFF, y1 = m.z >> 16;
+  uint32_t off = offsets[i];
+  const uint64_t cam_base = (uint64_t)cam * (uint64_t)tiles_per_cam;
+  for (int ty = y0; ty <= y1; ++ty)
+    for (int tx = x0; tx <= x1; ++tx) {
+      const uint64_t tile = cam_base + (uint64_t)(ty * TX + tx);
+      keys[off] = (tile << depth_bits) | depth;
+      vals[off] = g;
+      ++off;
+    }
+}
+
+// ---- radix sort -----------------------------------------------------------------------------
+constexpr int kBins = 256;
+constexpr int kMaxPasses = 8;
+constexpr uint32_t kSortAgg = 1u << 30;
+constexpr uint32_t kSortPrefix = 2u << 30;
+constexpr uint32_t kSortValue = (1u << 30) - 1;
+
+__global__ __launch_bounds__(256) void k_radix_hist(const uint64_t* __restrict__ keys, int64_t m,
+                                                    int n_passes, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t sh[kMaxPasses][kBins];
+  const int tid = threadIdx.x;
+  for (int p = 0; p < kMaxPasses; ++p) sh[p][tid] = 0;
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + tid; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = keys[i];
+    for (int p = 0; p < n_passes; ++p) atomicAdd(&sh[p][(k >> (8 * p)) & 0xFF], 1u);
+  }
+  __syncthreads();
+  for (int p = 0; p < n_passes; ++p) {
+    const uint32_t v = sh[p][tid];
+    if (v) atomicAdd(&hist[p * kBins + tid], v);
+  }
+}
+
+// Exclusive scan over the 256 bins of each pass (one block per pass).
+__global__ __launch_bounds__(256) void k_digit_base(const uint32_t* __restrict__ hist,
+                                                    uint32_t* __restrict__ base) {
+  __shared__ uint32_t s_wave[kWaves];
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  const uint32_t v = hist[blockIdx.x * kBins + tid];
+  const uint32_t incl = wave_inclusive_scan(v);
+  if (lane == kWave - 1) s_wave[wave] = incl;
+  __syncthreads();
+  uint32_t pre = 0;
+  for (int w = 0; w < wave; ++w) pre += s_wave[w];
+  base[blockIdx.x * kBins + tid] = pre + incl - v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_onesweep(
+    const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, int64_t m, int shift, const uint32_t* __restrict__ digit_base,
+    uint32_t* __restrict__ status, uint32_t* __restrict__ ticket) {
+  __shared__ uint32_t s_part;
+  __shared__ uint32_t s_hist[kWaves][kBins];   // per-wave counts, then per-wave offsets
+  __shared__ uint32_t s_local[kBins];          // block-local start of each digit run
+  __shared__ uint32_t s_global[kBins];         // global start of the run minus its local start
+  __shared__ uint32_t s_wsum[kWaves];
+  __shared__ uint64_t s_buf[kPart];            // keys, then (as u32) values, in digit order
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) s_hist[w][tid] = 0;
+  if (tid == 0) s_part = atomicAdd(ticket, 1u);
+  __syncthreads();
+  const int64_t part = s_part;
+  const int64_t wbase = part * kPart + (int64_t)wave * (kWave * kItems);
+  uint64_t key[kItems];
+  uint32_t rank[kItems];
+  const uint64_t lt_mask = lanemask_lt();
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
+    const int64_t pos = wbase + (int64_t)it * kWave + lane;
+    const bool valid = pos < m;
+    key[it] = valid ? kin[pos] : 0ull;
+    const uint32_t d = (uint32_t)(key[it] >> shift) & 0xFF;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bal = __ballot(bit);
+      peers &= bit ? bal : ~bal;
+    }
+    const uint32_t below = __popcll(peers & lt_mask);
+    uint32_t old = 0;
+    if (valid) old = s_hist[wave][d];
+    if (valid && below == 0) s_hist[wave][d] = old + (uint32_t)__popcll(peers);
+    rank[it] = old + below;
+  }
+  __syncthreads();
+  // per digit (thread = digit): offsets of each wave's run and the block total
+  const uint32_t c0 = s_hist[0][tid], c1 = s_hist[1][tid], c2 = s_hist[2][tid], c3 = s_hist[3][tid];
+  const uint32_t count = c0 + c1 + c2 + c3;
+  // publish this partition's digit count as early as possible
+  if (part == 0) atomic_store_u32(&status[tid], kSortPrefix | count);
+  else atomic_store_u32(&status[part * kBins + tid], kSortAgg | count);
+  // block-local exclusive scan of the digit counts
+  const uint32_t incl = wave_inclusive_scan(count);
+  if (lane == kWave - 1) s_wsum[wave] = incl;
+  __syncthreads();
+  uint32_t pre = 0;
+  for (int w = 0; w < wave; ++w) pre += s_wsum[w];
+  const uint32_t local_start = pre + incl - count;
+  s_hist[0][tid] = 0;
+  s_hist[1][tid] = c0;
+  s_hist[2][tid] = c0 + c1;
+  s_hist[3][tid] = c0 + c1 + c2;
+  // look back over earlier partitions for this digit
+  uint32_t excl = 0;
+  if (part > 0) {
+    int64_t p = part - 1;
+    uint32_t spins = 0;
+    while (true) {
+      const uint32_t v = atomic_load_u32(&status[p * kBins + tid]);
+      const uint32_t flag = v & ~kSortValue;
+      if (flag == 0 && ++spins < kSpinLimit) continue;
+      excl += v & kSortValue;
+      if (flag == kSortPrefix) break;
+      --p;
+    }
+    atomic_store_u32(&status[part * kBins + tid], kSortPrefix | (excl + count));
+  }
+  s_local[tid] = local_start;
+  s_global[tid] = digit_base[tid] + excl - local_start;
+  __syncthreads();
+  // keys to LDS in block-local digit order
+  uint32_t lpos[kItems];
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
+    const int64_t pos = wbase + (int64_t)it * kWave + lane;
+    const uint32_t d = (uint32_t)(key[it] >> shift) & 0xFF;
+    lpos[it] = s_local[d] + s_hist[wave][d] + rank[it];
+    if (pos < m && lpos[it] < (uint32_t)kPart) s_buf[lpos[it]] = key[it];
+  }
+  __syncthreads();
+  const int64_t pbase = part * kPart;
+  const int n_here = (int)min((int64_t)kPart, m - pbase);
+  uint32_t gdst[kItems];
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const int j = tid + r * kThreads;
+    if (j < n_here) {
+      const uint64_t k = s_buf[j];
+      gdst[r] = s_global[(uint32_t)(k >> shift) & 0xFF] + (uint32_t)j;
+      if (gdst[r] < (uint64_t)m) kout[gdst[r]] = k;
+    }
+  }
+  __syncthreads();
+  // values follow the same permutation
+  uint32_t* s_val = reinterpret_cast<uint32_t*>(s_buf);
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
+    const int64_t pos = wbase + (int64_t)it * kWave + lane;
+    if (pos < m && lpos[it] < (uint32_t)kPart) s_val[lpos[it]] = vin[pos];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const int j = tid + r * kThreads;
+    if (j < n_here && gdst[r] < (uint64_t)m) vout[gdst[r]] = s_val[j];
+  }
+}
+
+__global__ void k_ranges(const uint64_t* __restrict__ keys, int64_t m, int depth_bits,
+                         int64_t n_tiles, uint32_t* __restrict__ ranges) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const uint64_t t = keys[i] >> depth_bits;
+  if (t >= (uint64_t)n_tiles) return;
+  if (i == 0 || (keys[i - 1] >> depth_bits) != t) ranges[t] = (uint32_t)i;
+  if (i == m - 1 || (keys[i + 1] >> depth_bits) != t) ranges[n_tiles + t] = (uint32_t)(i + 1);
+}
+
+__global__ void k_canonical(const uint64_t* __restrict__ keys, int64_t m, int depth_bits,
+                            uint32_t zmin, uint64_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const uint64_t k = keys[i];
+  const uint64_t mask = depth_bits == 0 ? 0ull : ((1ull << depth_bits) - 1);
+  out[i] = ((k >> depth_bits) << 32) | (uint64_t)((uint32_t)(k & mask) + zmin);
+}
+
+inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+// ---- host launchers -------------------------------------------------------------------------
+size_t scan_scratch_bytes(int64_t n) {
+  const int64_t parts = (n + kPart - 1) / kPart;
+  return (size_t)(parts + 1) * sizeof(uint64_t) + 256;
+}
+
+hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, uint64_t* total,
+                       void* scratch, hipStream_t s) {
+  const int64_t parts = (n + kPart - 1) / kPart;
+  uint64_t* status = reinterpret_cast<uint64_t*>(scratch);
+  uint32_t* ticket = reinterpret_cast<uint32_t*>(status + parts);
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(scratch), 0u, parts * 2 + 2, s);
+  if (e != hipSuccess) return e;
+  if (n == 0) return launch_fill_u32(reinterpret_cast<uint32_t*>(total), 0u, 2, s);
+  hipLaunchKernelGGL(k_scan, dim3((unsigned)parts), dim3(kThreads), 0, s, in, out, n, parts, status,
+                     ticket, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_cam, const uint4* meta,
+                          const uint32_t* counts, const uint32_t* offsets, uint32_t zmin,
+                          int depth_bits, uint64_t* keys, uint32_t* vals, hipStream_t s) {
+  const int64_t total = n * n_cams;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_binning, dim3(blocks_for(total, 256)), dim3(256), 0, s, total, n, TX,
+                     tiles_per_cam, meta, counts, offsets, zmin, depth_bits, keys, vals);
+  return hipGetLastError();
+}
+
+size_t sort_scratch_bytes(int64_t m) {
+  const int64_t parts = (m + kPart - 1) / kPart;
+  return (size_t)(2 * kMaxPasses * kBins + kMaxPasses + parts * kBins) * sizeof(uint32_t) + 256;
+}
+
+hipError_t launch_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t m, int bits,
+                       void* scratch, hipStream_t s, bool* result_in_alt,
+                       void (*stage_mark)(void*, int), void* mark_ctx) {
+  *result_in_alt = false;
+  if (m <= 1 || bits <= 0) return hipSuccess;
+  const int n_passes = (bits + 7) / 8;
+  const int64_t parts = (m + kPart - 1) / kPart;
+  uint32_t* hist = reinterpret_cast<uint32_t*>(scratch);
+  uint32_t* base = hist + kMaxPasses * kBins;
+  uint32_t* tickets = base + kMaxPasses * kBins;
+  uint32_t* status = tickets + kMaxPasses;
+  hipError_t e = launch_fill_u32(hist, 0u, kMaxPasses * kBins, s);
+  if (e == hipSuccess) e = launch_fill_u32(tickets, 0u, kMaxPasses, s);
+  if (e != hipSuccess) return e;
+  const unsigned hblocks = (unsigned)std::min<int64_t>(2048, (m + 2047) / 2048);
+  hipLaunchKernelGGL(k_radix_hist, dim3(hblocks), dim3(256), 0, s, k0, m, n_passes, hist);
+  hipLaunchKernelGGL(k_digit_base, dim3(n_passes), dim3(256), 0, s, hist, base);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  uint64_t *ki = k0, *ko = k1;
+  uint32_t *vi = v0, *vo = v1;
+  for (int p = 0; p < n_passes; ++p) {
+    if ((e = launch_fill_u32(status, 0u, parts * kBins, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_onesweep, dim3((unsigned)parts), dim3(kThreads), 0, s, ki, vi, ko, vo, m,
+                       8 * p, base + p * kBins, status, tickets + p);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    std::swap(ki, ko);
+    std::swap(vi, vo);
+  }
+  (void)stage_mark;
+  (void)mark_ctx;
+  *result_in_alt = (n_passes % 2) == 1;
+  return hipSuccess;
+}
+
+hipError_t launch_ranges(const uint64_t* keys, int64_t m, int depth_bits, int64_t n_tiles,
+                         uint32_t* ranges, hipStream_t s) {
+  hipError_t e = launch_fill_u32(ranges, 0u, 2 * n_tiles, s);
+  if (e != hipSuccess || m == 0) return e;
+  hipLaunchKernelGGL(k_ranges, dim3(blocks_for(m, 256)), dim3(256), 0, s, keys, m, depth_bits,
+                     n_tiles, ranges);
+  return hipGetLastError();
+}
+
+hipError_t launch_canonical_keys(const uint64_t* keys, int64_t m, int depth_bits, uint32_t zmin,
+                                 uint64_t* out, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_canonical, dim3(blocks_for(m, 256)), dim3(256), 0, s, keys, m, depth_bits,
+                     zmin, out);
+  return hipGetLastError();
+}
+
+}  // namespace pcs
