@@ -1,0 +1,178 @@
+"""Benchmark of the splatting renderer on one MI355X.
+
+Workload (default): 1,000,000 surfel Gaussians at 1920x1080, RGB + normal + depth + alpha. The
+cloud is a procedural union of 6 spheres and 4 tori (radii U(0.2, 0.6)) normalised into [-1,1]^3,
+sampled area-uniformly, quantised to the 10-bit lattice, coloured with 3-octave value noise; its
+ellipsoids come from kNN-PCA (k = 16, kappa = 1) computed on the GPU; opacity 0.9; one pinhole
+camera at (0, 0, 3) looking at the origin with a 60 degree vertical field of view.
+
+A step is one frame of the renderer: projection, instance scan, binning, radix sort, tile ranges
+and compositing (all inputs resident in HBM). `value` is Gaussians per second = N / frame time.
+Per-stage times come from HIP events the library records on the launch stream; the roofline
+entry is computed for the stage that dominates the frame. The CPU oracle renders the same
+workload once on the host cores for the `cpu_baseline` entry.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ms/frame @1M Gaussians 1080p; Gaussians/s; learned-vs-kNN-PCA PSNR gap"
+HBM_PEAK_GBS = 8000.0
+FP32_VALU_PEAK_TFLOPS = 78.6     # 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, no packed FP32
+
+# Algorithmic bytes per unit (stated in the design doc):
+PROJECT_READ_B = 68      # mean 12 + quat 16 + scale 12 + opacity 4 + rgb 12 + normal 12
+PROJECT_WRITE_VIS_B = 84  # 64 B splat record + 16 B binning meta + 4 B count
+PROJECT_WRITE_CULL_B = 4
+SORT_PASS_B = 24         # read + write of an 8 B key and a 4 B value
+# Compositing FLOP per (pixel, list entry) visit and per blended splat.
+COMPOSITE_VISIT_FLOP = 9     # offset (2), conic quadratic form (7)
+COMPOSITE_BLEND_FLOP = 21    # -q/2, exp, o*e, w = a*T, 7 fused multiply-adds (14), 1 - a, T update
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--width", type=int, default=1920)
+    ap.add_argument("--height", type=int, default=1080)
+    ap.add_argument("--seed", type=int, default=1006)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (this renderer "
+              "runs on a single MI355X; multi-GPU sharding is design only)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2409_16504_amd as P
+    from synthetic import look_at_camera, make_surface
+
+    t0 = time.time()
+    _, xyz, rgb = make_surface(args.n, args.seed, quantize=True)
+    cams = [look_at_camera([0, 0, 3], width=args.width, height=args.height)]
+    print(f"[bench] inputs ready in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+
+    R = P.Renderer(0)
+    dev = torch.device("cuda", 0)
+    txyz = torch.from_numpy(xyz).to(dev)
+    est = R.knn_pca(txyz, k=16, kappa=1.0, floor=0.1)
+    g = dict(mean=txyz, quat=est["quat"], scale=est["scale"],
+             opacity=torch.full((args.n,), 0.9, device=dev), rgb=torch.from_numpy(rgb).to(dev),
+             normal=est["normal"])
+    torch.cuda.synchronize()
+    # kNN-PCA time (ellipsoid estimation, reported separately from the frame)
+    R.timing(True)
+    for _ in range(3):
+        R.knn_pca(txyz, k=16, kappa=1.0, floor=0.1, out=est)
+    knn_ms = R.timings()["knn_pca"][0] / 3.0
+
+    opts = P.default_options()
+    out = R.render(g, cams, opts)
+    for _ in range(args.warmup):
+        R.render(g, cams, opts, out=out)
+    torch.cuda.synchronize()
+    R.timing(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        R.render(g, cams, opts, out=out)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    stages = R.timings()
+    ms_per_step = (t2 - t1) * 1e3 / args.steps
+    print(f"[bench] {args.steps} frames: {ms_per_step:.3f} ms/frame", file=sys.stderr, flush=True)
+
+    # instance count and visible splats of this frame (from a state export)
+    st = P.RenderState(R)
+    R.render(g, cams, opts, state=st)
+    bins = R.bins(st)
+    m = int(bins["keys"].size)
+    per_stage = {k: v[0] / max(1, v[1]) for k, v in stages.items() if v[1] > 0}
+
+    cpu = None
+    visits = blends = None
+    if not args.no_cpu_baseline:
+        cpu, visits, blends = cpu_baseline(xyz, rgb, cams)
+
+    roof = roofline(per_stage, args.n, m, bins, visits, blends)
+    line = dict(
+        metric=METRIC, value=args.n / (ms_per_step * 1e-3), unit="Gaussians/s", n_gpus=1,
+        steps=args.steps, warmup=args.warmup, ms_per_step=ms_per_step, higher_is_better=True,
+        scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
+        config=dict(workload=f"{args.n} surfel Gaussians (procedural sphere/torus surface, kNN-PCA "
+                             f"ellipsoids), {args.width}x{args.height}, RGB+normal+depth",
+                    n_gaussians=args.n, width=args.width, height=args.height, cameras=1),
+        ms_per_frame=ms_per_step, instances=m, knn_pca_ms=knn_ms,
+        stage_ms={k: round(v, 5) for k, v in per_stage.items()},
+        roofline=roof, cpu_baseline=cpu, psnr_gap_db=None,
+    )
+    print(json.dumps(line), flush=True)
+
+
+def roofline(per_stage, n, m, bins, visits, blends):
+    """Roofline entry of the stage that dominates the frame, from algorithmic work per launch."""
+    frame = {k: v for k, v in per_stage.items() if k in ("project", "scan", "binning", "sort", "ranges", "composite")}
+    dom = max(frame, key=frame.get)
+    ms = frame[dom]
+    if dom == "composite" and visits is not None:
+        flop = COMPOSITE_VISIT_FLOP * visits + COMPOSITE_BLEND_FLOP * blends
+        ach = flop / (ms * 1e-3) / 1e12
+        return dict(kernel=dom, bound="alu", achieved=ach, peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=ach / FP32_VALU_PEAK_TFLOPS, traffic=None, avg_ms=ms)
+    if dom == "sort":
+        z = (bins["keys"] & np.uint64(0xFFFFFFFF)).astype(np.int64)
+        depth_bits = int(z.max() - z.min()).bit_length() if m else 0
+        tile_bits = int(bins["ranges"].shape[1] - 1).bit_length()
+        n_pass = (depth_bits + tile_bits + 7) // 8
+        byts = m * (8 + SORT_PASS_B * n_pass)     # one histogram read of the keys, then the passes
+    elif dom == "project":
+        vis = int(np.unique(bins["vals"]).size)
+        byts = n * PROJECT_READ_B + vis * PROJECT_WRITE_VIS_B + (n - vis) * PROJECT_WRITE_CULL_B
+    elif dom == "binning":
+        byts = m * 12
+    else:
+        byts = m * 8
+    ach = byts / (ms * 1e-3) / 1e9
+    return dict(kernel=dom, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                traffic=None, avg_ms=ms)
+
+
+def cpu_baseline(xyz, rgb, cams):
+    """The oracle (exact-FP32 projection, FP64 compositing, OpenMP over pixels) renders one full
+    frame of the same workload on the host cores; its own kNN-PCA supplies the ellipsoids."""
+    import oracle
+    from oracle import knn_pca as kp
+    t0 = time.time()
+    est = kp.knn_pca(xyz, k=16, kappa=1.0)
+    g = dict(mean=xyz, quat=est["quat"].astype(np.float32), scale=est["scale"].astype(np.float32),
+             opacity=np.full(xyz.shape[1], 0.9, np.float32), rgb=rgb, normal=est["normal"].astype(np.float32))
+    print(f"[bench] oracle kNN-PCA {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    t1 = time.perf_counter()
+    img = oracle.render(g, cams, mode="ref")
+    t2 = time.perf_counter()
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    print(f"[bench] oracle frame {t2 - t1:.1f}s on {cores} threads", file=sys.stderr, flush=True)
+    n = xyz.shape[1]
+    return (dict(value=n / (t2 - t1), unit="Gaussians/s", cores=cores, kind="oracle",
+                 sample="one full 1920x1080 frame of the 1M-Gaussian workload (FP32-exact projection, "
+                        "FP64 compositing)", seconds=t2 - t1),
+            int(img["visits"]), int(img["blends"]))
+
+
+if __name__ == "__main__":
+    main()

@@ -55,7 +55,7 @@ def _setup(L):
     L.orc_bin.argtypes = [i64, i32, i32, i32, vp, vp, vp, vp, vp]
     L.orc_bin.restype = i64
     L.orc_composite.argtypes = ([i64] + [vp] * 9 + [i64, vp, vp, ctypes.c_uint64, i32, i32, i32, vp,
-                                vp, i64] + [vp] * 7)
+                                vp, i64] + [vp] * 8)
     L.orc_composite.restype = i64
     L.orc_backward.argtypes = ([i64] + [vp] * 7 + [i32, vp, i32, i32, i32, vp, vp, vp, vp, i64, vp, vp,
                                vp])
@@ -182,7 +182,7 @@ def render(g: dict, cams: list, opts=None, mode="ref", tile=16, pixels=None, cov
     HW = W * H
     res = dict(rgb=np.zeros((C, 3, H, W)), normal=np.zeros((C, 3, H, W)), depth=np.zeros((C, H, W)),
                alpha=np.zeros((C, H, W)), T=np.zeros((C, H, W)), n_contrib=np.zeros((C, H, W), np.int32),
-               flags=np.zeros((C, H, W), np.uint8), keys=keys, vals=vals, proj=projs, visits=0)
+               flags=np.zeros((C, H, W), np.uint8), keys=keys, vals=vals, proj=projs, visits=0, blends=0)
     opac = np.ascontiguousarray(g["opacity"], dtype=np.float64)
     rgb = np.ascontiguousarray(g["rgb"], dtype=np.float64)
     nrm = np.ascontiguousarray(g["normal"], dtype=np.float64)
@@ -202,11 +202,12 @@ def render(g: dict, cams: list, opts=None, mode="ref", tile=16, pixels=None, cov
         o_T = np.ones(HW)
         o_nc = np.zeros(HW, np.int32)
         o_f = np.zeros(HW, np.uint8)
+        o_b = np.zeros(1, np.int64)
         visits = lib().orc_composite(n, _p(sp["u"]), _p(sp["v"]), _p(sp["A"]), _p(sp["B"]), _p(sp["C"]),
                                      _p(sp["z"]), _p(opac), _p(rgb), _p(nrm), int(hi - lo), _p(k_c),
                                      _p(v_c), ci * ntiles, W, H, tile, _p(ov), _p(pix),
                                      0 if pix is None else pix.size, _p(o_rgb), _p(o_nrm), _p(o_d),
-                                     _p(o_a), _p(o_T), _p(o_nc), _p(o_f))
+                                     _p(o_a), _p(o_T), _p(o_nc), _p(o_f), _p(o_b))
         res["rgb"][ci] = o_rgb.reshape(3, H, W)
         res["normal"][ci] = o_nrm.reshape(3, H, W)
         res["depth"][ci] = o_d.reshape(H, W)
@@ -215,6 +216,7 @@ def render(g: dict, cams: list, opts=None, mode="ref", tile=16, pixels=None, cov
         res["n_contrib"][ci] = o_nc.reshape(H, W)
         res["flags"][ci] = o_f.reshape(H, W)
         res["visits"] += int(visits)
+        res["blends"] += int(o_b[0])
     return res
 
 

@@ -349,7 +349,7 @@ int64_t orc_composite(int64_t n, const double* u, const double* v, const double*
                       const uint32_t* vals, uint64_t cam_tile_base, int W, int H, int tile,
                       const float* opt, const int64_t* pix, int64_t npix, double* out_rgb,
                       double* out_nrm, double* out_depth, double* out_alpha, double* out_T,
-                      int32_t* out_ncontrib, uint8_t* out_flags) {
+                      int32_t* out_ncontrib, uint8_t* out_flags, int64_t* out_blends) {
   const int TX = (W + tile - 1) / tile, TY = (H + tile - 1) / tile;
   const int64_t ntiles = (int64_t)TX * TY;
   std::vector<int64_t> start(ntiles, 0), end(ntiles, 0);
@@ -365,8 +365,8 @@ int64_t orc_composite(int64_t n, const double* u, const double* v, const double*
   const double eps = 1e-5;  // relative rounding margin of a decision
   const int64_t npx = pix ? npix : (int64_t)W * H;
   const int64_t HW = (int64_t)W * H;
-  int64_t visits = 0;
-#pragma omp parallel for schedule(dynamic, 64) reduction(+ : visits)
+  int64_t visits = 0, blends = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : visits, blends)
   for (int64_t p = 0; p < npx; ++p) {
     const int64_t pid = pix ? pix[p] : p;
     const int x = (int)(pid % W), y = (int)(pid / W);
@@ -396,6 +396,7 @@ int64_t orc_composite(int64_t n, const double* u, const double* v, const double*
       for (int ch = 0; ch < 3; ++ch) acc[3 + ch] += w * (double)nrm[(int64_t)ch * n + g];
       acc[6] += w * zdepth[g];
       T = T * (1.0 - alpha);
+      ++blends;
       relT += da / (1.0 - alpha) + eps * 1e-2;
       ncontrib = (int32_t)(k - start[t] + 1);
       if (std::fabs(T - teps) <= relT * T) flag |= 4;
@@ -411,6 +412,7 @@ int64_t orc_composite(int64_t n, const double* u, const double* v, const double*
     out_ncontrib[pid] = ncontrib;
     out_flags[pid] = flag;
   }
+  if (out_blends) *out_blends = blends;
   return visits;
 }
 

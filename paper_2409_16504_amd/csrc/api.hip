@@ -467,7 +467,7 @@ int pcs_knn_pca(pcs_context* ctx, const float* xyz, int64_t n, int32_t k, float 
   PCS_TRY(ensure(ctx->knn_scratch, knn_scratch_bytes(n), "kNN scratch"));
   StageTimer tm(ctx, ST_KNN, s);
   PCS_HIP(launch_knn_pca(xyz, n, k, kappa, floor_ratio, quat, scale, normal, ctx->knn_scratch.p,
-                         ctx->knn_scratch.cap, s));
+                         ctx->knn_scratch.cap, ctx->host_small + 8, s));
   return PCS_OK;
 }
 

@@ -133,9 +133,10 @@ hipError_t launch_project_backward(int64_t n, int n_cams, const DevCamera* cams,
                                    const DevOptions& opt, const pcs_gaussians& g,
                                    const float* sgrad, const pcs_grads& grads, hipStream_t s);
 
+// Synchronises the stream once (bounding box readback through host_pinned, >= 24 bytes).
 hipError_t launch_knn_pca(const float* xyz, int64_t n, int k, float kappa, float floor_ratio,
                           float* quat, float* scale, float* normal, void* scratch,
-                          size_t scratch_bytes, hipStream_t s);
+                          size_t scratch_bytes, uint32_t* host_pinned, hipStream_t s);
 size_t knn_scratch_bytes(int64_t n);
 
 }  // namespace pcs

@@ -1,0 +1,100 @@
+"""GPU parity of the kNN-PCA surfel estimate against the oracle (FP64, exact kNN).
+
+What is unique is compared: the ellipsoid covariance R diag(s^2) R^T (not the quaternion, whose
+in-plane axes are arbitrary when two eigenvalues coincide) and the normal where the smallest
+eigenvalue is well separated. Points whose 16th and 17th neighbour distances nearly tie are
+excluded (exact ties on the 10-bit lattice are compared: there FP32 distances are exact).
+"""
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+from oracle import knn_pca as kp
+from synthetic import ProceduralSurface, deformed_surface, make_surface
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    import paper_2409_16504_amd as P
+    return P.Renderer(0)
+
+
+def gpu_knn(R, p, k=16, kappa=1.0, floor=0.1):
+    import torch
+    out = R.knn_pca(torch.from_numpy(np.ascontiguousarray(p, np.float32)).cuda(), k=k, kappa=kappa, floor=floor)
+    return {kk: v.cpu().numpy().astype(np.float64) for kk, v in out.items()}
+
+
+def cov_of(q, s):
+    Rm = Rotation.from_quat(np.stack([q[1], q[2], q[3], q[0]], 1)).as_matrix()
+    return np.einsum("nij,nj,nkj->nik", Rm, s.T ** 2, Rm)
+
+
+def compare(p, gpu, ref, gap, check_normals=True):
+    n = p.shape[1]
+    cg = cov_of(gpu["quat"], gpu["scale"])
+    scale = np.abs(ref["cov"]).reshape(n, -1).max(axis=1)
+    tie = gap <= 1e-9          # squared-distance gap of the k-th and (k+1)-th neighbour
+    ok = ~tie
+    err = np.abs(cg - ref["cov"]).reshape(n, -1).max(axis=1)
+    bad = ok & (err > 1e-4 * scale + 1e-12)
+    assert bad.sum() == 0, (bad.sum(), np.flatnonzero(bad)[:5], err[bad][:5], scale[bad][:5])
+    assert np.allclose(np.linalg.norm(gpu["quat"], axis=0), 1.0, atol=1e-5)
+    assert np.all(gpu["quat"][0] >= 0)
+    if check_normals:
+        lam = ref["eig"]
+        sep = ok & (lam[:, 1] - lam[:, 2] > 1e-2 * lam[:, 1])
+        dots = np.einsum("kn,kn->n", gpu["normal"], ref["normal"])
+        assert np.all(dots[sep] > 1 - 1e-4), np.sort(dots[sep])[:5]
+    return int(tie.sum())
+
+
+def test_lattice_surface_cloud(R):
+    _, p, _ = make_surface(30000, 31, quantize=True)
+    nb, gap = kp.knn(p, 16)
+    ref = kp.knn_pca(p, 16, neighbours=nb)
+    gpu = gpu_knn(R, p)
+    ties = compare(p, gpu, ref, np.full(p.shape[1], np.inf))
+    assert ties == 0
+
+
+def test_noisy_deforming_cloud_and_kappa(R):
+    rng = np.random.default_rng(1005)
+    surf = ProceduralSurface(rng, margin_scale=1.2)
+    p, _ = deformed_surface(surf, 7, 20000, rng)
+    nb, gap = kp.knn(p, 16)
+    ref = kp.knn_pca(p, 16, kappa=1.2, floor=0.2, neighbours=nb)
+    gpu = gpu_knn(R, p, kappa=1.2, floor=0.2)
+    ties = compare(p, gpu, ref, gap)
+    assert ties < 20
+
+
+@pytest.mark.parametrize("k", [1, 5, 24, 32])
+def test_other_k(R, k):
+    rng = np.random.default_rng(40 + k)
+    p = rng.uniform(-1, 1, (3, 3000)).astype(np.float32)
+    nb, gap = kp.knn(p, k)
+    ref = kp.knn_pca(p, k, neighbours=nb)
+    gpu = gpu_knn(R, p, k=k)
+    compare(p, gpu, ref, gap, check_normals=k > 2)
+
+
+def test_rejects_bad_arguments(R):
+    import torch
+    from paper_2409_16504_amd import PcsError
+    p = torch.zeros((3, 10), device="cuda")
+    with pytest.raises(PcsError):
+        R.knn_pca(p, k=11)
+    with pytest.raises(PcsError):
+        R.knn_pca(p, k=33)
+
+
+def test_full_size_cloud(R):
+    """800k lattice points (the 1080p workload's cloud): all points compared."""
+    _, p, _ = make_surface(800_000, 1002, quantize=True)
+    nb, gap = kp.knn(p, 16)
+    ref = kp.knn_pca(p, 16, neighbours=nb)
+    gpu = gpu_knn(R, p)
+    compare(p, gpu, ref, np.full(p.shape[1], np.inf))
