@@ -205,7 +205,7 @@ class ProceduralSurface:
                 local = np.stack([ring * np.cos(phi), ring * np.sin(phi), rr * np.sin(theta)])
             pts.append(self.center[i][:, None] + self.rot[i] @ local)
         p = np.concatenate(pts, axis=1)
-        p = p[:, rng.permutation(p.shape[1])]
+        p = np.ascontiguousarray(p[:, rng.permutation(p.shape[1])])
         return (p - self.norm_center[:, None]) * self.norm_scale
 
     def color(self, p: np.ndarray) -> np.ndarray:
@@ -221,7 +221,7 @@ def make_surface(n: int, seed: int, quantize=True, margin_scale=1.0):
     if quantize:
         p = quantize_10bit(p)
     rgb = surf.color(p)
-    return surf, p.astype(np.float32), rgb.astype(np.float32)
+    return surf, np.ascontiguousarray(p, np.float32), np.ascontiguousarray(rgb, np.float32)
 
 
 def deformed_surface(surf: ProceduralSurface, frame: int, n: int, rng: np.random.Generator,
@@ -232,4 +232,4 @@ def deformed_surface(surf: ProceduralSurface, frame: int, n: int, rng: np.random
     p = surf.sample(n, rng, radius_scale=scale)
     p = p + rng.normal(0.0, noise_std, size=p.shape)
     rgb = surf.color(p)
-    return p.astype(np.float32), rgb.astype(np.float32)
+    return np.ascontiguousarray(p, np.float32), np.ascontiguousarray(rgb, np.float32)
