@@ -96,7 +96,7 @@ struct pcs_context {
   int device = 0;
   DevBuf counts, offsets, meta, keys_alt, vals_alt, scan_scratch, sort_scratch, sgrad, small;
   DevBuf knn_scratch;
-  uint32_t* host_small = nullptr;   // pinned: total (u64) then depth-bit range [2]
+  uint32_t* host_small = nullptr;   // pinned 1 KiB: readback of the small device words
   pcs_state* internal = nullptr;    // state used when the caller passes none
   bool timing = false;
   struct Ev {
@@ -213,7 +213,7 @@ int pcs_context_create(int device, pcs_context** out) {
   pcs_context* ctx = new pcs_context();
   ctx->device = device;
   void* hp = nullptr;
-  if (hipHostMalloc(&hp, 64, hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc(&hp, 1024, hipHostMallocDefault) != hipSuccess) {
     delete ctx;
     return fail(PCS_ERR_OOM, "pinned host allocation failed");
   }
@@ -320,7 +320,7 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   PCS_TRY(ensure(ctx->counts, std::max<int64_t>(cn, 1) * sizeof(uint32_t) + 64, "counts"));
   PCS_TRY(ensure(ctx->offsets, std::max<int64_t>(cn, 1) * sizeof(uint32_t) + 64, "offsets"));
   PCS_TRY(ensure(ctx->scan_scratch, scan_scratch_bytes(cn), "scan scratch"));
-  PCS_TRY(ensure(ctx->small, 64, "small"));
+  PCS_TRY(ensure(ctx->small, kSmallWords * 4, "small"));
   PCS_TRY(ensure(st->ranges, 2 * total_tiles * sizeof(uint32_t), "tile ranges"));
   const int64_t HWC = (int64_t)W * H * n_cams;
   PCS_TRY(ensure(st->t_final, HWC * sizeof(float), "final transmittance"));
@@ -328,8 +328,7 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
 
   uint64_t* d_total = ctx->small.as<uint64_t>();
   uint32_t* d_zrange = ctx->small.as<uint32_t>() + 2;
-  PCS_HIP(launch_fill_u32(d_zrange, 0xFFFFFFFFu, 1, s));
-  PCS_HIP(launch_fill_u32(d_zrange + 1, 0u, 1, s));
+  PCS_HIP(launch_init_small(ctx->small.as<uint32_t>(), s));
   {
     StageTimer tm(ctx, ST_PROJECT, s);
     PCS_HIP(launch_project(n, n_cams, st->dcams.as<DevCamera>(), dopt, *g, st->rec.as<float4>(),
@@ -340,11 +339,15 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
     PCS_HIP(launch_scan(ctx->counts.as<uint32_t>(), ctx->offsets.as<uint32_t>(), cn, d_total,
                         ctx->scan_scratch.p, s));
   }
-  PCS_HIP(hipMemcpyAsync(ctx->host_small, ctx->small.p, 16, hipMemcpyDeviceToHost, s));
+  PCS_HIP(hipMemcpyAsync(ctx->host_small, ctx->small.p, kSmallWords * 4, hipMemcpyDeviceToHost, s));
   PCS_HIP(hipStreamSynchronize(s));
   uint64_t m64;
   std::memcpy(&m64, ctx->host_small, 8);
-  const uint32_t zmin = ctx->host_small[2], zmax = ctx->host_small[3];
+  uint32_t zmin = 0xFFFFFFFFu, zmax = 0u;
+  for (int i = 0; i < kZSlots; ++i) {
+    zmin = std::min(zmin, ctx->host_small[2 + i]);
+    zmax = std::max(zmax, ctx->host_small[2 + kZSlots + i]);
+  }
   if (m64 >= (uint64_t(1) << 30))
     return fail(PCS_ERR_UNSUPPORTED, "instance count " + std::to_string(m64) + " is not below 2^30");
   const int64_t m = (int64_t)m64;
@@ -467,7 +470,7 @@ int pcs_knn_pca(pcs_context* ctx, const float* xyz, int64_t n, int32_t k, float 
   PCS_TRY(ensure(ctx->knn_scratch, knn_scratch_bytes(n), "kNN scratch"));
   StageTimer tm(ctx, ST_KNN, s);
   PCS_HIP(launch_knn_pca(xyz, n, k, kappa, floor_ratio, quat, scale, normal, ctx->knn_scratch.p,
-                         ctx->knn_scratch.cap, ctx->host_small + 8, s));
+                         ctx->knn_scratch.cap, ctx->host_small + 192, s));
   return PCS_OK;
 }
 

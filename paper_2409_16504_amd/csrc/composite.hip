@@ -1,10 +1,13 @@
 // Per-tile front-to-back compositing (Section 3.1, Eq. 1-2) and its adjoint.
 //
-// One 256-thread block per 16x16 screen tile (four wave64s, each owning four pixel rows). The
-// tile's depth-sorted splat list is staged through LDS in batches of 256 records; every pixel
-// walks the batch in order, tests the 3-sigma ellipse, evaluates alpha = o * exp(-q/2), and
-// blends RGB, normal and depth until its transmittance drops below t_eps. A block stops loading
-// batches once every pixel has terminated (block-wide vote).
+// One 256-thread block per 16x16 screen tile (four wave64s, each owning an 8x8 quadrant). The
+// tile's depth-sorted splat list is staged through LDS in batches of 256 records (the next batch
+// is fetched into registers while the current one is composited). Each wavefront first tests the
+// batch against its quadrant with the splats' ellipse bounding boxes (one lane per splat, one
+// ballot per 64 splats) and then walks only the splats that reach it, in list order: every pixel
+// tests the 3-sigma ellipse, evaluates alpha = o * exp(-q/2), and blends RGB, normal and depth
+// until its transmittance drops below t_eps. A block stops loading batches once every pixel has
+// terminated (block-wide vote).
 //
 // The adjoint walks the same list back to front from each pixel's last contributor, recovering
 // the transmittance by division, keeps a running sum of what lies behind each splat, and reduces
@@ -18,6 +21,31 @@ namespace {
 
 constexpr int kBlock = kTilePixels;   // 256 threads, one per pixel
 
+// Pixel of a thread: wavefront w owns the 8x8 quadrant (w & 1, w >> 1) of the 16x16 tile.
+struct TilePixel {
+  int x, y;             // pixel
+  float qx0, qy0;       // centre of the quadrant's first pixel
+};
+
+__device__ __forceinline__ TilePixel tile_pixel(int tx, int ty, int tid) {
+  const int wave = tid / kWave, lane = tid % kWave;
+  TilePixel p;
+  const int bx = tx * kTile + (wave & 1) * 8, by = ty * kTile + (wave >> 1) * 8;
+  p.x = bx + (lane & 7);
+  p.y = by + (lane >> 3);
+  p.qx0 = (float)bx + 0.5f;
+  p.qy0 = (float)by + 0.5f;
+  return p;
+}
+
+// Does the splat's padded ellipse bounding box reach a pixel centre of the 8x8 quadrant?
+__device__ __forceinline__ bool touches_quadrant(float u, float v, float ex, float ey, float qx0,
+                                                 float qy0) {
+  const float gx = fmaxf(fmaxf(qx0 - u, u - (qx0 + 7.0f)), 0.0f);
+  const float gy = fmaxf(fmaxf(qy0 - v, v - (qy0 + 7.0f)), 0.0f);
+  return gx <= ex && gy <= ey;
+}
+
 __global__ __launch_bounds__(kBlock) void k_composite(
     int64_t n, int W, int H, int TX, int64_t tiles_per_cam, int64_t total_tiles,
     const float4* __restrict__ rec, const uint32_t* __restrict__ vals,
@@ -29,10 +57,10 @@ __global__ __launch_bounds__(kBlock) void k_composite(
   const int64_t cam = tile / tiles_per_cam;
   const int64_t t = tile - cam * tiles_per_cam;
   const int tx = (int)(t % TX), ty = (int)(t / TX);
-  const int tid = threadIdx.x;
-  const int x = tx * kTile + (tid & (kTile - 1)), y = ty * kTile + (tid >> 4);
-  const bool inside = x < W && y < H;
-  const float pxf = (float)x + 0.5f, pyf = (float)y + 0.5f;
+  const int tid = threadIdx.x, lane = lane_id();
+  const TilePixel P = tile_pixel(tx, ty, tid);
+  const bool inside = P.x < W && P.y < H;
+  const float pxf = (float)P.x + 0.5f, pyf = (float)P.y + 0.5f;
   const uint32_t start = ranges[tile], end = ranges[total_tiles + tile];
   const float cut2 = opt.sigma_cut * opt.sigma_cut;
   const float4* rec_cam = rec + cam * n * kRecFloat4;
@@ -40,21 +68,37 @@ __global__ __launch_bounds__(kBlock) void k_composite(
   float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f, acc4 = 0.f, acc5 = 0.f, acc6 = 0.f;
   int32_t last = 0;
   bool done = !inside;
+  // records of the next batch travel in registers while the current batch is composited
+  float4 p0, p1, p2, p3;
+  if (start + tid < end) {
+    const float4* r = rec_cam + (int64_t)min(vals[start + tid], (uint32_t)(n - 1)) * kRecFloat4;
+    p0 = r[0]; p1 = r[1]; p2 = r[2]; p3 = r[3];
+  }
   for (uint32_t b = start; b < end; b += kBlock) {
     if (__syncthreads_count(done) == kBlock) break;
-    const uint32_t j = b + tid;
-    if (j < end) {
-      const uint32_t gi = min(vals[j], (uint32_t)(n - 1));   // indices are < n by construction
-      const float4* r = rec_cam + (int64_t)gi * kRecFloat4;
-      s_r0[tid] = r[0];
-      s_r1[tid] = r[1];
-      s_r2[tid] = r[2];
-      s_r3[tid] = r[3];
+    if (b + tid < end) {
+      s_r0[tid] = p0; s_r1[tid] = p1; s_r2[tid] = p2; s_r3[tid] = p3;
     }
     __syncthreads();
-    if (!done) {
-      const int cnt = (int)min((uint32_t)kBlock, end - b);
-      for (int k = 0; k < cnt; ++k) {
+    const uint32_t nb = b + kBlock + tid;
+    if (nb < end) {
+      const float4* r = rec_cam + (int64_t)min(vals[nb], (uint32_t)(n - 1)) * kRecFloat4;
+      p0 = r[0]; p1 = r[1]; p2 = r[2]; p3 = r[3];
+    }
+    const int cnt = (int)min((uint32_t)kBlock, end - b);
+    for (int c = 0; c < cnt; c += kWave) {
+      if (__ballot(!done) == 0ull) break;               // every pixel of this wavefront is done
+      const int e = c + lane;
+      bool rel = false;
+      if (e < cnt) {
+        const float4 a0 = s_r0[e];
+        rel = touches_quadrant(a0.x, a0.y, s_r1[e].w, s_r2[e].w, P.qx0, P.qy0);
+      }
+      uint64_t mask = __ballot(rel);
+      while (mask) {
+        const int k = c + (int)__builtin_ctzll(mask);
+        mask &= mask - 1;
+        if (done) continue;
         const float4 r0 = s_r0[k];
         const float4 r1 = s_r1[k];
         const float dx = pxf - r0.x, dy = pyf - r0.y;
@@ -74,16 +118,13 @@ __global__ __launch_bounds__(kBlock) void k_composite(
         acc6 = fmaf(w, r0.w, acc6);
         T = T * (1.0f - a);
         last = (int32_t)(b - start) + k + 1;
-        if (T < opt.t_eps) {
-          done = true;
-          break;
-        }
+        if (T < opt.t_eps) done = true;
       }
     }
   }
   if (!inside) return;
   const int64_t HW = (int64_t)W * H;
-  const int64_t pix = (int64_t)y * W + x;
+  const int64_t pix = (int64_t)P.y * W + P.x;
   const int64_t c3 = cam * 3 * HW;
   out_rgb[c3 + pix] = acc0 + T * opt.bg[0];
   out_rgb[c3 + HW + pix] = acc1 + T * opt.bg[1];
@@ -113,15 +154,15 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(
   const int64_t cam = tile / tiles_per_cam;
   const int64_t t = tile - cam * tiles_per_cam;
   const int tx = (int)(t % TX), ty = (int)(t / TX);
-  const int tid = threadIdx.x;
-  const int x = tx * kTile + (tid & (kTile - 1)), y = ty * kTile + (tid >> 4);
-  const bool inside = x < W && y < H;
-  const float pxf = (float)x + 0.5f, pyf = (float)y + 0.5f;
+  const int tid = threadIdx.x, lane = lane_id();
+  const TilePixel P = tile_pixel(tx, ty, tid);
+  const bool inside = P.x < W && P.y < H;
+  const float pxf = (float)P.x + 0.5f, pyf = (float)P.y + 0.5f;
   const uint32_t start = ranges[tile];
   const float cut2 = opt.sigma_cut * opt.sigma_cut;
   const float4* rec_cam = rec + cam * n * kRecFloat4;
   const int64_t HW = (int64_t)W * H;
-  const int64_t pix = (int64_t)y * W + x;
+  const int64_t pix = (int64_t)P.y * W + P.x;
   float T = 1.0f;
   int32_t nc = 0;
   float g[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -155,61 +196,74 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(
       s_g[tid] = gi;
     }
     __syncthreads();
-    for (int k = bend - bstart - 1; k >= 0; --k) {
-      const int32_t p = bstart + k;
-      float pg[kScreenGrads];
+    const int cnt = bend - bstart;
+    for (int c = ((cnt - 1) / kWave) * kWave; c >= 0; c -= kWave) {
+      const int e = c + lane;
+      bool rel = false;
+      if (e < cnt) {
+        const float4 a0 = s_r0[e];
+        rel = touches_quadrant(a0.x, a0.y, s_r1[e].w, s_r2[e].w, P.qx0, P.qy0);
+      }
+      uint64_t mask = __ballot(rel);
+      while (mask) {
+        const int hb = 63 - (int)__builtin_clzll(mask);
+        mask &= ~(1ull << hb);
+        const int k = c + hb;
+        const int32_t p = bstart + k;
+        float pg[kScreenGrads];
 #pragma unroll
-      for (int i = 0; i < kScreenGrads; ++i) pg[i] = 0.f;
-      bool contrib = false;
-      if (p < nc) {
-        const float4 r0 = s_r0[k];
-        const float4 r1 = s_r1[k];
-        const float dx = pxf - r0.x, dy = pyf - r0.y;
-        const float q = conic_q(r1.x, r1.y, r1.z, dx, dy);
-        if (q <= cut2) {
-          const float e = __expf(-0.5f * q);
-          const float araw = r0.z * e;
-          const float a = fminf(opt.alpha_max, araw);
-          if (a >= opt.alpha_min) {
-            contrib = true;
-            const float4 r2 = s_r2[k];
-            const float4 r3 = s_r3[k];
-            const float one_m = 1.0f - a;
-            T = T / one_m;                       // transmittance in front of this splat
-            const float w = a * T;
-            const float f[7] = {r2.x, r2.y, r2.z, r3.x, r3.y, r3.z, r0.w};
-            float dLda = 0.f;
-            const float inv = 1.0f / one_m;
+        for (int i = 0; i < kScreenGrads; ++i) pg[i] = 0.f;
+        bool contrib = false;
+        if (p < nc) {
+          const float4 r0 = s_r0[k];
+          const float4 r1 = s_r1[k];
+          const float dx = pxf - r0.x, dy = pyf - r0.y;
+          const float q = conic_q(r1.x, r1.y, r1.z, dx, dy);
+          if (q <= cut2) {
+            const float e = __expf(-0.5f * q);
+            const float araw = r0.z * e;
+            const float a = fminf(opt.alpha_max, araw);
+            if (a >= opt.alpha_min) {
+              contrib = true;
+              const float4 r2 = s_r2[k];
+              const float4 r3 = s_r3[k];
+              const float one_m = 1.0f - a;
+              T = T / one_m;                       // transmittance in front of this splat
+              const float w = a * T;
+              const float f[7] = {r2.x, r2.y, r2.z, r3.x, r3.y, r3.z, r0.w};
+              float dLda = 0.f;
+              const float inv = 1.0f / one_m;
 #pragma unroll
-            for (int c = 0; c < 7; ++c) {
-              dLda = fmaf(g[c], fmaf(T, f[c], -behind[c] * inv), dLda);
-              behind[c] = fmaf(w, f[c], behind[c]);
-            }
-            pg[7] = g[0] * w;
-            pg[8] = g[1] * w;
-            pg[9] = g[2] * w;
-            pg[10] = g[3] * w;
-            pg[11] = g[4] * w;
-            pg[12] = g[5] * w;
-            pg[6] = g[6] * w;
-            if (!(araw > opt.alpha_max)) {
-              pg[5] = dLda * e;
-              const float dLdq = dLda * (-0.5f * a);
-              pg[2] = dLdq * dx * dx;
-              pg[3] = dLdq * 2.0f * dx * dy;
-              pg[4] = dLdq * dy * dy;
-              pg[0] = dLdq * (-2.0f * fmaf(r1.x, dx, r1.y * dy));
-              pg[1] = dLdq * (-2.0f * fmaf(r1.y, dx, r1.z * dy));
+              for (int ch = 0; ch < 7; ++ch) {
+                dLda = fmaf(g[ch], fmaf(T, f[ch], -behind[ch] * inv), dLda);
+                behind[ch] = fmaf(w, f[ch], behind[ch]);
+              }
+              pg[7] = g[0] * w;
+              pg[8] = g[1] * w;
+              pg[9] = g[2] * w;
+              pg[10] = g[3] * w;
+              pg[11] = g[4] * w;
+              pg[12] = g[5] * w;
+              pg[6] = g[6] * w;
+              if (!(araw > opt.alpha_max)) {
+                pg[5] = dLda * e;
+                const float dLdq = dLda * (-0.5f * a);
+                pg[2] = dLdq * dx * dx;
+                pg[3] = dLdq * 2.0f * dx * dy;
+                pg[4] = dLdq * dy * dy;
+                pg[0] = dLdq * (-2.0f * fmaf(r1.x, dx, r1.y * dy));
+                pg[1] = dLdq * (-2.0f * fmaf(r1.y, dx, r1.z * dy));
+              }
             }
           }
         }
-      }
-      if (__ballot(contrib) == 0ull) continue;   // wave-uniform
-      const int64_t dst = base_idx + s_g[k];
+        if (__ballot(contrib) == 0ull) continue;   // wave-uniform
+        const int64_t dst = base_idx + s_g[k];
 #pragma unroll
-      for (int i = 0; i < kScreenGrads; ++i) {
-        const float s = wave_sum(pg[i]);
-        if (lane_id() == 0 && s != 0.0f) unsafeAtomicAdd(&sgrad[i * stride + dst], s);
+        for (int i = 0; i < kScreenGrads; ++i) {
+          const float sv = wave_sum(pg[i]);
+          if (lane == 0 && sv != 0.0f) unsafeAtomicAdd(&sgrad[i * stride + dst], sv);
+        }
       }
     }
   }

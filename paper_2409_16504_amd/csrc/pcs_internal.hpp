@@ -30,8 +30,9 @@ struct DevOptions {
 
 // Splat record written by the projection for every visible (camera, Gaussian), read by
 // compositing and its adjoint:
-//   r0 = (u, v, opacity, z)   r1 = (A, B, C, radius)   r2 = (r, g, b, 0)   r3 = (nx, ny, nz, 0)
-// where (A, B, C) is the conic (inverse screen covariance) and radius the 3-sigma half extent.
+//   r0 = (u, v, opacity, z)   r1 = (A, B, C, ex)   r2 = (r, g, b, ey)   r3 = (nx, ny, nz, 0)
+// where (A, B, C) is the conic (inverse screen covariance) and (ex, ey) the padded half extents
+// of the bounding box of the sigma_cut ellipse.
 // Meta record for binning: (fp32 depth bits, x0 | x1 << 16, y0 | y1 << 16, 0).
 
 // ---- wave64 helpers -------------------------------------------------------------------------
@@ -89,10 +90,14 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, float value, int64_t n, hipStream_t s);
 
+// Depth-bit range slots: zrange[0..kZSlots) minima, zrange[kZSlots..2 kZSlots) maxima.
+constexpr int kZSlots = 64;
+// small[0..1] instance total (u64), small[2..] depth-bit range slots; reset by launch_init_small.
+constexpr int kSmallWords = 2 + 2 * kZSlots;
+hipError_t launch_init_small(uint32_t* small, hipStream_t s);
 hipError_t launch_project(int64_t n, int n_cams, const DevCamera* cams, const DevOptions& opt,
                           const pcs_gaussians& g, float4* rec, uint4* meta, uint32_t* counts,
-                          uint32_t* zrange /*[2]: min, max depth bits (pre-set to ~0, 0)*/,
-                          hipStream_t s);
+                          uint32_t* zrange, hipStream_t s);
 
 // Exclusive scan of n u32 values; writes out[n] and *total (u64). Scratch from scan_scratch_bytes.
 size_t scan_scratch_bytes(int64_t n);

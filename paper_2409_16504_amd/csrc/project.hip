@@ -75,23 +75,46 @@ __global__ __launch_bounds__(256) void k_project(
                              (uint32_t)y0 | ((uint32_t)y1 << 16), 0u);
       float4* r = rec + out * kRecFloat4;
       r[0] = make_float4(u, v, o, zc);
-      r[1] = make_float4(A, B, C, rad);
-      r[2] = make_float4(cr, cg, cb, 0.0f);
+      // half extents of the sigma_cut ellipse's bounding box, padded so that pixels outside it
+      // fail the sigma_cut test by a wide margin whatever the rounding of the quadratic form
+      const float ex = fmaf(opt.sigma_cut * sqrtf(G.a), 1.001f, 0.01f);
+      const float ey = fmaf(opt.sigma_cut * sqrtf(G.c), 1.001f, 0.01f);
+      r[1] = make_float4(A, B, C, ex);
+      r[2] = make_float4(cr, cg, cb, ey);
       r[3] = make_float4(nx, ny, nz, 0.0f);
     } else {
       counts[out] = 0u;
     }
   }
-  // depth-bit range of the visible splats: one atomic pair per wavefront
+  // depth-bit range of the visible splats: block reduction, then one atomic pair per block into
+  // one of kZSlots slot pairs (spreading the atomics; the host folds the slots)
+  __shared__ uint32_t s_lo[4], s_hi[4];
   uint32_t lo = visible ? zbits : 0xFFFFFFFFu, hi = visible ? zbits : 0u;
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
     lo = min(lo, (uint32_t)__shfl_xor((int)lo, o, kWave));
     hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, kWave));
   }
-  if (lane_id() == 0 && hi != 0u) {
-    atomicMin(&zrange[0], lo);
-    atomicMax(&zrange[1], hi);
+  const int wave = threadIdx.x / kWave;
+  if (lane_id() == 0) { s_lo[wave] = lo; s_hi[wave] = hi; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    lo = min(min(s_lo[0], s_lo[1]), min(s_lo[2], s_lo[3]));
+    hi = max(max(s_hi[0], s_hi[1]), max(s_hi[2], s_hi[3]));
+    if (hi != 0u) {
+      const int slot = (blockIdx.x + blockIdx.y * 7) % kZSlots;
+      atomicMin(&zrange[slot], lo);
+      atomicMax(&zrange[kZSlots + slot], hi);
+    }
+  }
+}
+
+__global__ void k_init_small(uint32_t* __restrict__ small) {
+  const int i = threadIdx.x;
+  if (i < 2) small[i] = 0u;                                   // instance total (u64)
+  if (i < kZSlots) {
+    small[2 + i] = 0xFFFFFFFFu;                               // depth-bit minima
+    small[2 + kZSlots + i] = 0u;                              // depth-bit maxima
   }
 }
 
@@ -106,6 +129,11 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s
 hipError_t launch_fill_f32(float* p, float value, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, value, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_small(uint32_t* small, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_small, dim3(1), dim3(64), 0, s, small);
   return hipGetLastError();
 }
 
