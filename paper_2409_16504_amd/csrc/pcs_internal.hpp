@@ -78,12 +78,17 @@ __device__ __forceinline__ float wave_sum(float v) {
   return (r0 + r1) + (r2 + r3);
 }
 
-// Block-to-tile remap: consecutive tiles land on the same XCD (blocks are dealt round-robin to
-// the 8 XCDs), so neighbouring tiles that share splat records share that XCD's L2.
+// Block-to-tile map. Blocks are dealt round-robin to the 8 XCDs (block b runs on XCD b % 8);
+// this map hands each XCD groups of kTileGroup consecutive tiles (a strip of one tile row), so a
+// splat record shared by neighbouring tiles is mostly fetched into one XCD's L2, while the groups
+// of every XCD stay interleaved over the whole screen and the busy screen region is spread over
+// all XCDs. Blocks past the last full round of groups map one to one.
+constexpr int64_t kTileGroup = 4;
 __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
-  const int64_t q = nblocks / 8, r = nblocks % 8;
+  const int64_t full = nblocks - nblocks % (8 * kTileGroup);
+  if (bid >= full) return bid;
   const int64_t xcd = bid % 8, slot = bid / 8;
-  return xcd * q + (xcd < r ? xcd : r) + slot;   // XCD x owns tiles [x q + min(x, r), ...)
+  return ((slot / kTileGroup) * 8 + xcd) * kTileGroup + slot % kTileGroup;
 }
 
 // ---- launchers (stream-ordered, return the launch error) ------------------------------------

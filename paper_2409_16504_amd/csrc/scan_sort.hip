@@ -169,16 +169,35 @@ constexpr int kMaxPasses = 8;
 constexpr uint32_t kSortAgg = 1u << 30;
 constexpr uint32_t kSortPrefix = 2u << 30;
 constexpr uint32_t kSortValue = (1u << 30) - 1;
+constexpr int kLookWindow = 8;
 
+// Digit histograms of every pass in one read of the keys. Lanes of a wavefront holding the same
+// digit are matched with eight ballots and their count is added once, so the long runs of equal
+// digits (all instances of one Gaussian share its depth bits) cost one LDS atomic per run.
 __global__ __launch_bounds__(256) void k_radix_hist(const uint64_t* __restrict__ keys, int64_t m,
                                                     int n_passes, uint32_t* __restrict__ hist) {
   __shared__ uint32_t sh[kMaxPasses][kBins];
   const int tid = threadIdx.x;
   for (int p = 0; p < kMaxPasses; ++p) sh[p][tid] = 0;
   __syncthreads();
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + tid; i < m; i += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t k = keys[i];
-    for (int p = 0; p < n_passes; ++p) atomicAdd(&sh[p][(k >> (8 * p)) & 0xFF], 1u);
+  const uint64_t lt_mask = lanemask_lt();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m; base += stride) {
+    const int64_t i = base + tid;
+    const bool valid = i < m;
+    const uint64_t k = valid ? keys[i] : 0ull;
+    const uint64_t vmask = __ballot(valid);
+    for (int p = 0; p < n_passes; ++p) {
+      const uint32_t d = (uint32_t)(k >> (8 * p)) & 0xFF;
+      uint64_t peers = vmask;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        peers &= bit ? bal : ~bal;
+      }
+      if (valid && (peers & lt_mask) == 0) atomicAdd(&sh[p][d], (uint32_t)__popcll(peers));
+    }
   }
   __syncthreads();
   for (int p = 0; p < n_passes; ++p) {
@@ -204,7 +223,8 @@ __global__ __launch_bounds__(256) void k_digit_base(const uint32_t* __restrict__
 __global__ __launch_bounds__(kThreads) void k_onesweep(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
     uint32_t* __restrict__ vout, int64_t m, int shift, const uint32_t* __restrict__ digit_base,
-    uint32_t* __restrict__ status, uint32_t* __restrict__ ticket) {
+    uint32_t* __restrict__ status, uint32_t* __restrict__ status_next,
+    uint32_t* __restrict__ ticket) {
   __shared__ uint32_t s_part;
   __shared__ uint32_t s_hist[kWaves][kBins];   // per-wave counts, then per-wave offsets
   __shared__ uint32_t s_local[kBins];          // block-local start of each digit run
@@ -219,6 +239,7 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
   const int64_t part = s_part;
   const int64_t wbase = part * kPart + (int64_t)wave * (kWave * kItems);
   uint64_t key[kItems];
+  uint32_t val[kItems];
   uint32_t rank[kItems];
   const uint64_t lt_mask = lanemask_lt();
 #pragma unroll
@@ -226,6 +247,7 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
     const int64_t pos = wbase + (int64_t)it * kWave + lane;
     const bool valid = pos < m;
     key[it] = valid ? kin[pos] : 0ull;
+    val[it] = valid ? vin[pos] : 0u;
     const uint32_t d = (uint32_t)(key[it] >> shift) & 0xFF;
     uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -258,21 +280,40 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
   s_hist[1][tid] = c0;
   s_hist[2][tid] = c0 + c1;
   s_hist[3][tid] = c0 + c1 + c2;
-  // look back over earlier partitions for this digit
+  // look back over earlier partitions for this digit, kLookWindow predecessors per step
   uint32_t excl = 0;
   if (part > 0) {
     int64_t p = part - 1;
     uint32_t spins = 0;
     while (true) {
-      const uint32_t v = atomic_load_u32(&status[p * kBins + tid]);
-      const uint32_t flag = v & ~kSortValue;
-      if (flag == 0 && ++spins < kSpinLimit) continue;
-      excl += v & kSortValue;
-      if (flag == kSortPrefix) break;
-      --p;
+      uint32_t v[kLookWindow];
+#pragma unroll
+      for (int w = 0; w < kLookWindow; ++w)
+        v[w] = (p - w >= 0) ? atomic_load_u32(&status[(p - w) * kBins + tid]) : kSortPrefix;
+      // accept the window up to (and including) its nearest inclusive prefix, if nothing before
+      // it is still unpublished
+      uint32_t acc = 0;
+      int state = 0;                       // 0: all aggregates, 1: reached a prefix, 2: not ready
+#pragma unroll
+      for (int w = 0; w < kLookWindow; ++w) {
+        if (state != 0) continue;
+        const uint32_t flag = v[w] & ~kSortValue;
+        if (flag == 0) { state = 2; continue; }
+        acc += v[w] & kSortValue;
+        if (flag == kSortPrefix) state = 1;
+      }
+      if (state == 2) {
+        if (++spins < kSpinLimit) continue;
+        break;                             // guards a broken launch only
+      }
+      excl += acc;
+      if (state == 1) break;
+      p -= kLookWindow;
     }
     atomic_store_u32(&status[part * kBins + tid], kSortPrefix | (excl + count));
   }
+  // clear this partition's slice of the other status buffer for the next pass
+  status_next[part * kBins + tid] = 0u;
   s_local[tid] = local_start;
   s_global[tid] = digit_base[tid] + excl - local_start;
   __syncthreads();
@@ -304,7 +345,7 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
 #pragma unroll
   for (int it = 0; it < kItems; ++it) {
     const int64_t pos = wbase + (int64_t)it * kWave + lane;
-    if (pos < m && lpos[it] < (uint32_t)kPart) s_val[lpos[it]] = vin[pos];
+    if (pos < m && lpos[it] < (uint32_t)kPart) s_val[lpos[it]] = val[it];
   }
   __syncthreads();
 #pragma unroll
@@ -368,7 +409,7 @@ hipError_t launch_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_cam, 
 
 size_t sort_scratch_bytes(int64_t m) {
   const int64_t parts = (m + kPart - 1) / kPart;
-  return (size_t)(2 * kMaxPasses * kBins + kMaxPasses + parts * kBins) * sizeof(uint32_t) + 256;
+  return (size_t)(2 * kMaxPasses * kBins + kMaxPasses + 2 * parts * kBins) * sizeof(uint32_t) + 256;
 }
 
 hipError_t launch_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t m, int bits,
@@ -378,23 +419,28 @@ hipError_t launch_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, i
   if (m <= 1 || bits <= 0) return hipSuccess;
   const int n_passes = (bits + 7) / 8;
   const int64_t parts = (m + kPart - 1) / kPart;
+  // scratch: hist[8][256] | base[8][256] | tickets[8] | status[2][parts][256] (contiguous, so one
+  // fill clears histograms, tickets and both status buffers)
   uint32_t* hist = reinterpret_cast<uint32_t*>(scratch);
   uint32_t* base = hist + kMaxPasses * kBins;
   uint32_t* tickets = base + kMaxPasses * kBins;
-  uint32_t* status = tickets + kMaxPasses;
+  uint32_t* status0 = tickets + kMaxPasses;
+  uint32_t* status1 = status0 + parts * kBins;
   hipError_t e = launch_fill_u32(hist, 0u, kMaxPasses * kBins, s);
-  if (e == hipSuccess) e = launch_fill_u32(tickets, 0u, kMaxPasses, s);
+  if (e == hipSuccess) e = launch_fill_u32(tickets, 0u, kMaxPasses + 2 * parts * kBins, s);
   if (e != hipSuccess) return e;
-  const unsigned hblocks = (unsigned)std::min<int64_t>(2048, (m + 2047) / 2048);
+  // few blocks: each block adds its 256 x n_passes partial counts to the same global bins
+  const unsigned hblocks = (unsigned)std::min<int64_t>(256, (m + 4095) / 4096);
   hipLaunchKernelGGL(k_radix_hist, dim3(hblocks), dim3(256), 0, s, k0, m, n_passes, hist);
   hipLaunchKernelGGL(k_digit_base, dim3(n_passes), dim3(256), 0, s, hist, base);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   uint64_t *ki = k0, *ko = k1;
   uint32_t *vi = v0, *vo = v1;
   for (int p = 0; p < n_passes; ++p) {
-    if ((e = launch_fill_u32(status, 0u, parts * kBins, s)) != hipSuccess) return e;
+    uint32_t* st = (p & 1) ? status1 : status0;
+    uint32_t* st_next = (p & 1) ? status0 : status1;
     hipLaunchKernelGGL(k_onesweep, dim3((unsigned)parts), dim3(kThreads), 0, s, ki, vi, ko, vo, m,
-                       8 * p, base + p * kBins, status, tickets + p);
+                       8 * p, base + p * kBins, st, st_next, tickets + p);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     std::swap(ki, ko);
     std::swap(vi, vo);
