@@ -8,8 +8,10 @@
  *   - the caller owns every input and output buffer; the library owns the context, the render
  *     state and the workspace they hold (device memory allocated with hipMalloc, grown on demand
  *     and released by the matching destroy call);
- *   - work is enqueued on `stream` (a hipStream_t; NULL = the null stream) in stream order; the only
- *     host synchronisation is the 4-byte read of the instance count inside pcs_render_forward;
+ *   - work is enqueued on `stream` (a hipStream_t; NULL = the null stream) in stream order; the
+ *     host synchronises only where a size must be known: pcs_render_forward reads back the
+ *     instance count and depth range, pcs_knn_pca the cloud's bounding box, pcs_voxelize the
+ *     voxel count;
  *   - a context or state may be used by one host thread at a time;
  *   - the return value is a status code; pcs_last_error() gives a thread-local message.
  *
@@ -117,7 +119,8 @@ void pcs_context_destroy(pcs_context* ctx);
 /* Per-stage timing with HIP events recorded on the caller's stream around every kernel stage.
  * pcs_context_timing(ctx, 1) resets the accumulators and enables timing; pcs_context_timings
  * copies up to `cap` accumulated millisecond totals (stage order: project, scan, binning, sort,
- * ranges, composite, backward_composite, backward_project, knn_pca) plus per-stage launch counts
+ * ranges, composite, backward_composite, backward_project, knn_pca, voxelize, conv, conv_backward,
+ * head, head_backward) plus per-stage launch counts
  * and synchronises the stream. */
 int pcs_context_timing(pcs_context* ctx, int enable);
 int pcs_context_timings(pcs_context* ctx, double* ms, int64_t* launches, int cap, void* stream);
@@ -160,6 +163,60 @@ int pcs_state_bins(const pcs_state* st, const uint64_t** keys, const uint32_t** 
  * centroid. Outputs quat[4][n] (w >= 0), scale[3][n], normal[3][n]. */
 int pcs_knn_pca(pcs_context* ctx, const float* xyz, int64_t n, int32_t k, float kappa,
                 float floor_ratio, float* quat, float* scale, float* normal, void* stream);
+
+/* ---- sparse point-to-ellipsoid estimator (Section 3.2) -------------------------------------
+ * Voxels of a point cloud on the 1024^3 grid over [-1,1]^3 (the 10-bit quantisation of
+ * Section 3.3): coordinate c = clamp(floor((p + 1) * 512), 0, 1023), voxels numbered in ascending
+ * linear key (x << 20 | y << 10 | z). Features are BF16 (bit patterns in uint16_t), row-major
+ * [V][channels]; 32 input channels: mean colour (3), mean residual (p + 1) * 512 - (c + 0.5) (3)
+ * (Section 3.2's colour and coordinate residual), zeros. Owned by the voxels object. */
+typedef struct pcs_voxels pcs_voxels;
+int pcs_voxels_create(pcs_context* ctx, pcs_voxels** out);
+void pcs_voxels_destroy(pcs_voxels* vox);
+
+/* Voxelise n points xyz[3][n], rgb[3][n] (device, FP32) and build the kernel map (for every voxel
+ * and offset k = 9 (dx+1) + 3 (dy+1) + (dz+1), the neighbour's index or -1). Synchronises the
+ * stream once to size the voxel arrays; *n_voxels receives V. n < 2^30. */
+int pcs_voxelize(pcs_context* ctx, const float* xyz, const float* rgb, int64_t n, pcs_voxels* vox,
+                 int64_t* n_voxels, void* stream);
+
+/* Device pointers owned by vox: coords[3][V] (int32), nbr[27][V] (int32), point_voxel[n] (int32),
+ * features[V][32] (BF16). */
+int pcs_voxels_get(const pcs_voxels* vox, const int32_t** coords, const int32_t** nbr,
+                   const int32_t** point_voxel, const uint16_t** features, int64_t* n_voxels);
+
+/* Submanifold 3x3x3 convolution (Section 3.2's sparse convolutions at the active voxels only):
+ * y[v][o] = relu?(bias[o] + sum_k sum_c w[k][o][c] x[nbr_k(v)][c]), absent neighbours contribute
+ * nothing. x[V][cin], y[V][cout], w[27][cout][cin] BF16; bias[cout] FP32 or NULL. Products on
+ * BF16 matrix cores (MFMA) with FP32 accumulation; the output is rounded to BF16.
+ * cin, cout in {32, 64} (UNSUPPORTED otherwise). */
+int pcs_subm_conv_forward(pcs_context* ctx, const pcs_voxels* vox, const uint16_t* x, int32_t cin,
+                          const uint16_t* w, const float* bias, int32_t cout, int32_t relu, uint16_t* y,
+                          void* stream);
+
+/* Adjoint of pcs_subm_conv_forward. If y (the forward output) is given, dy is first multiplied by
+ * the ReLU derivative (y > 0). dx[V][cin] (BF16, overwritten) or NULL; dw[27][cout][cin] and
+ * dbias[cout] FP32, ACCUMULATED (+=), or NULL. */
+int pcs_subm_conv_backward(pcs_context* ctx, const pcs_voxels* vox, const uint16_t* x, int32_t cin,
+                           const uint16_t* w, int32_t cout, const uint16_t* y, const uint16_t* dy,
+                           uint16_t* dx, float* dw, float* dbias, void* stream);
+
+/* Estimator head (Section 3.2's shared per-point head, with the outputs of configuration 4): per
+ * voxel raw = wh f + bh (wh[11][32], bh[11] FP32; f = features[V][32] BF16); per point of the voxel:
+ * scale = (2/1024) exp(raw[0:3]), quat = normalise(raw[3:7] + (1,0,0,0)), opacity =
+ * sigmoid(raw[7]), rgb = point colour + raw[8:11], normal = rotated axis of the smallest scale
+ * oriented away from the cloud centroid. xyz, rgb are the voxelised points; outputs planar. */
+int pcs_estimator_head_forward(pcs_context* ctx, const pcs_voxels* vox, const uint16_t* feat,
+                               const float* wh, const float* bh, const float* xyz, const float* rgb,
+                               float* quat, float* scale, float* opacity, float* out_rgb,
+                               float* normal, void* stream);
+
+/* Adjoint of the head for per-point gradients of quat, scale, opacity and rgb (the normal is not
+ * differentiated): d_feat[V][32] BF16 (overwritten), d_wh[11][32] and d_bh[11] FP32 accumulated. */
+int pcs_estimator_head_backward(pcs_context* ctx, const pcs_voxels* vox, const uint16_t* feat,
+                                const float* wh, const float* bh, const float* d_quat,
+                                const float* d_scale, const float* d_opacity, const float* d_rgb,
+                                uint16_t* d_feat, float* d_wh, float* d_bh, void* stream);
 
 #ifdef __cplusplus
 }

@@ -16,11 +16,14 @@ c_f, c_i32, c_i64, c_u32, c_vp = ctypes.c_float, ctypes.c_int32, ctypes.c_int64,
 PCS_OK, PCS_ERR_INVALID_ARG, PCS_ERR_HIP, PCS_ERR_OOM, PCS_ERR_CAPACITY, PCS_ERR_UNSUPPORTED = range(6)
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "HIP_ERROR", 3: "OUT_OF_MEMORY", 4: "CAPACITY", 5: "UNSUPPORTED"}
 STAGES = ("project", "scan", "binning", "sort", "ranges", "composite", "backward_composite",
-          "backward_project", "knn_pca")
+          "backward_project", "knn_pca", "voxelize", "conv", "conv_backward", "head", "head_backward")
 
 EXPORTED = ("pcs_last_error", "pcs_context_create", "pcs_context_destroy", "pcs_context_timing",
             "pcs_context_timings", "pcs_state_create", "pcs_state_destroy", "pcs_options_default",
-            "pcs_render_forward", "pcs_render_backward", "pcs_state_bins", "pcs_knn_pca")
+            "pcs_render_forward", "pcs_render_backward", "pcs_state_bins", "pcs_knn_pca",
+            "pcs_voxels_create", "pcs_voxels_destroy", "pcs_voxelize", "pcs_voxels_get",
+            "pcs_subm_conv_forward", "pcs_subm_conv_backward", "pcs_estimator_head_forward",
+            "pcs_estimator_head_backward")
 
 
 class Camera(ctypes.Structure):
@@ -89,7 +92,10 @@ def load():
                                  ctypes.POINTER(c_vp)]
     L.pcs_knn_pca.argtypes = [c_vp, c_vp, c_i64, c_i32, c_f, c_f, c_vp, c_vp, c_vp, c_vp]
     for name in ("pcs_context_create", "pcs_context_timing", "pcs_context_timings", "pcs_state_create",
-                 "pcs_render_forward", "pcs_render_backward", "pcs_state_bins", "pcs_knn_pca"):
+                 "pcs_render_forward", "pcs_render_backward", "pcs_state_bins", "pcs_knn_pca",
+            "pcs_voxels_create", "pcs_voxels_destroy", "pcs_voxelize", "pcs_voxels_get",
+            "pcs_subm_conv_forward", "pcs_subm_conv_backward", "pcs_estimator_head_forward",
+            "pcs_estimator_head_backward"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

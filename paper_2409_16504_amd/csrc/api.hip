@@ -72,7 +72,7 @@ int ensure(DevBuf& b, size_t bytes, const char* what) {
 
 enum Stage {
   ST_PROJECT = 0, ST_SCAN, ST_BINNING, ST_SORT, ST_RANGES, ST_COMPOSITE, ST_BWD_COMPOSITE,
-  ST_BWD_PROJECT, ST_KNN, ST_COUNT
+  ST_BWD_PROJECT, ST_KNN, ST_VOXELIZE, ST_CONV, ST_CONV_BWD, ST_HEAD, ST_HEAD_BWD, ST_COUNT
 };
 
 int bit_length(uint64_t v) {
@@ -95,7 +95,7 @@ struct pcs_state;
 struct pcs_context {
   int device = 0;
   DevBuf counts, offsets, meta, keys_alt, vals_alt, scan_scratch, sort_scratch, sgrad, small;
-  DevBuf knn_scratch;
+  DevBuf knn_scratch, conv_tmp, wt_tmp;
   uint32_t* host_small = nullptr;   // pinned 1 KiB: readback of the small device words
   pcs_state* internal = nullptr;    // state used when the caller passes none
   bool timing = false;
@@ -119,6 +119,14 @@ struct pcs_state {
   int64_t n = 0, m = 0, n_tiles = 0;
   int depth_bits = 0;
   uint32_t zmin = 0;
+  bool valid = false;
+};
+
+struct pcs_voxels {
+  pcs_context* ctx = nullptr;
+  int64_t n = 0, V = 0;
+  int log2cap = 0;
+  DevBuf keys, order, flag, excl, start, coords, feat, point_voxel, hkeys, hvals, nbr, centroid;
   bool valid = false;
 };
 
@@ -471,6 +479,152 @@ int pcs_knn_pca(pcs_context* ctx, const float* xyz, int64_t n, int32_t k, float 
   StageTimer tm(ctx, ST_KNN, s);
   PCS_HIP(launch_knn_pca(xyz, n, k, kappa, floor_ratio, quat, scale, normal, ctx->knn_scratch.p,
                          ctx->knn_scratch.cap, ctx->host_small + 192, s));
+  return PCS_OK;
+}
+
+int pcs_voxels_create(pcs_context* ctx, pcs_voxels** out) {
+  if (!ctx || !out) return fail(PCS_ERR_INVALID_ARG, "context or out is NULL");
+  *out = new pcs_voxels();
+  (*out)->ctx = ctx;
+  return PCS_OK;
+}
+
+void pcs_voxels_destroy(pcs_voxels* v) { delete v; }
+
+int pcs_voxelize(pcs_context* ctx, const float* xyz, const float* rgb, int64_t n, pcs_voxels* vox,
+                 int64_t* n_voxels, void* stream) {
+  if (!ctx || !vox || !n_voxels) return fail(PCS_ERR_INVALID_ARG, "NULL argument");
+  if (vox->ctx != ctx) return fail(PCS_ERR_INVALID_ARG, "voxels belong to another context");
+  if (n <= 0 || !xyz || !rgb) return fail(PCS_ERR_INVALID_ARG, "need at least one point");
+  if (n >= (int64_t(1) << 30)) return fail(PCS_ERR_UNSUPPORTED, "n must be below 2^30");
+  PCS_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  vox->valid = false;
+  PCS_TRY(ensure(vox->keys, n * sizeof(uint64_t), "voxel keys"));
+  PCS_TRY(ensure(vox->order, n * sizeof(uint32_t), "voxel point order"));
+  PCS_TRY(ensure(ctx->keys_alt, n * sizeof(uint64_t), "keys (alternate)"));
+  PCS_TRY(ensure(ctx->vals_alt, n * sizeof(uint32_t), "values (alternate)"));
+  PCS_TRY(ensure(ctx->sort_scratch, sort_scratch_bytes(n), "sort scratch"));
+  PCS_TRY(ensure(vox->flag, n * sizeof(uint32_t), "voxel flags"));
+  PCS_TRY(ensure(vox->excl, n * sizeof(uint32_t) + 64, "voxel numbering"));
+  PCS_TRY(ensure(ctx->scan_scratch, scan_scratch_bytes(n), "scan scratch"));
+  PCS_TRY(ensure(ctx->small, kSmallWords * 4, "small"));
+  PCS_TRY(ensure(vox->point_voxel, n * sizeof(int32_t), "point to voxel map"));
+  PCS_TRY(ensure(vox->centroid, 64, "centroid"));
+  StageTimer tm(ctx, ST_VOXELIZE, s);
+  PCS_HIP(launch_vox_keys(xyz, n, vox->keys.as<uint64_t>(), vox->order.as<uint32_t>(), s));
+  bool in_alt = false;
+  PCS_HIP(launch_sort(vox->keys.as<uint64_t>(), vox->order.as<uint32_t>(), ctx->keys_alt.as<uint64_t>(),
+                      ctx->vals_alt.as<uint32_t>(), n, 30, ctx->sort_scratch.p, s, &in_alt, nullptr, nullptr));
+  if (in_alt) {
+    swap_buf(vox->keys, ctx->keys_alt);
+    swap_buf(vox->order, ctx->vals_alt);
+  }
+  PCS_HIP(launch_vox_flags(vox->keys.as<uint64_t>(), n, vox->flag.as<uint32_t>(), s));
+  uint64_t* d_total = ctx->small.as<uint64_t>();
+  PCS_HIP(launch_scan(vox->flag.as<uint32_t>(), vox->excl.as<uint32_t>(), n, d_total, ctx->scan_scratch.p, s));
+  PCS_HIP(hipMemcpyAsync(ctx->host_small, d_total, 8, hipMemcpyDeviceToHost, s));
+  PCS_HIP(hipStreamSynchronize(s));
+  uint64_t V;
+  std::memcpy(&V, ctx->host_small, 8);
+  int log2cap = 6;
+  while ((int64_t(1) << log2cap) < (int64_t)(2 * V)) ++log2cap;
+  PCS_TRY(ensure(vox->start, V * sizeof(uint32_t) + 64, "voxel starts"));
+  PCS_TRY(ensure(vox->coords, 3 * V * sizeof(int32_t), "voxel coordinates"));
+  PCS_TRY(ensure(vox->feat, V * 32 * sizeof(uint16_t), "voxel features"));
+  PCS_TRY(ensure(vox->hkeys, (size_t(1) << log2cap) * sizeof(uint32_t), "voxel hash keys"));
+  PCS_TRY(ensure(vox->hvals, (size_t(1) << log2cap) * sizeof(int32_t), "voxel hash values"));
+  PCS_TRY(ensure(vox->nbr, 27 * V * sizeof(int32_t), "kernel map"));
+  PCS_HIP(launch_vox_build(vox->keys.as<uint64_t>(), vox->order.as<uint32_t>(), vox->flag.as<uint32_t>(),
+                           vox->excl.as<uint32_t>(), n, (int64_t)V, xyz, rgb, vox->start.as<uint32_t>(),
+                           vox->coords.as<int32_t>(), vox->feat.as<uint16_t>(),
+                           vox->point_voxel.as<int32_t>(), vox->hkeys.as<uint32_t>(),
+                           vox->hvals.as<int32_t>(), log2cap, vox->nbr.as<int32_t>(), s));
+  PCS_HIP(launch_centroid(xyz, n, vox->centroid.as<double>(), vox->centroid.as<float>() + 8, s));
+  vox->n = n;
+  vox->V = (int64_t)V;
+  vox->log2cap = log2cap;
+  vox->valid = true;
+  *n_voxels = (int64_t)V;
+  return PCS_OK;
+}
+
+int pcs_voxels_get(const pcs_voxels* vox, const int32_t** coords, const int32_t** nbr,
+                   const int32_t** point_voxel, const uint16_t** features, int64_t* n_voxels) {
+  if (!vox || !vox->valid) return fail(PCS_ERR_INVALID_ARG, "voxels hold no completed voxelisation");
+  if (coords) *coords = vox->coords.as<int32_t>();
+  if (nbr) *nbr = vox->nbr.as<int32_t>();
+  if (point_voxel) *point_voxel = vox->point_voxel.as<int32_t>();
+  if (features) *features = vox->feat.as<uint16_t>();
+  if (n_voxels) *n_voxels = vox->V;
+  return PCS_OK;
+}
+
+int pcs_subm_conv_forward(pcs_context* ctx, const pcs_voxels* vox, const uint16_t* x, int32_t cin,
+                          const uint16_t* w, const float* bias, int32_t cout, int32_t relu, uint16_t* y,
+                          void* stream) {
+  if (!ctx || !vox || !vox->valid || !x || !w || !y) return fail(PCS_ERR_INVALID_ARG, "NULL argument or empty voxels");
+  if (!conv_shape_supported(cin, cout)) return fail(PCS_ERR_UNSUPPORTED, "channels must be 32 or 64");
+  PCS_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  StageTimer tm(ctx, ST_CONV, s);
+  PCS_HIP(launch_subm_conv(x, cin, w, bias, cout, vox->nbr.as<int32_t>(), vox->V, relu ? 1 : 0, y, s));
+  return PCS_OK;
+}
+
+int pcs_subm_conv_backward(pcs_context* ctx, const pcs_voxels* vox, const uint16_t* x, int32_t cin,
+                           const uint16_t* w, int32_t cout, const uint16_t* y, const uint16_t* dy,
+                           uint16_t* dx, float* dw, float* dbias, void* stream) {
+  if (!ctx || !vox || !vox->valid || !x || !w || !dy) return fail(PCS_ERR_INVALID_ARG, "NULL argument or empty voxels");
+  if (!conv_shape_supported(cin, cout)) return fail(PCS_ERR_UNSUPPORTED, "channels must be 32 or 64");
+  PCS_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  StageTimer tm(ctx, ST_CONV_BWD, s);
+  const uint16_t* g = dy;
+  if (y) {
+    PCS_TRY(ensure(ctx->conv_tmp, (size_t)vox->V * cout * sizeof(uint16_t), "masked output gradient"));
+    PCS_HIP(launch_relu_mask(y, dy, vox->V * cout, ctx->conv_tmp.as<uint16_t>(), s));
+    g = ctx->conv_tmp.as<uint16_t>();
+  }
+  if (dbias) PCS_HIP(launch_bias_grad(g, vox->V, cout, dbias, s));
+  if (dw) PCS_HIP(launch_subm_conv_dw(x, cin, g, cout, vox->nbr.as<int32_t>(), vox->V, dw, s));
+  if (dx) {
+    PCS_TRY(ensure(ctx->wt_tmp, (size_t)27 * cin * cout * sizeof(uint16_t), "transposed weights"));
+    PCS_HIP(launch_weight_flip_t(w, cin, cout, ctx->wt_tmp.as<uint16_t>(), s));
+    PCS_HIP(launch_subm_conv(g, cout, ctx->wt_tmp.as<uint16_t>(), nullptr, cin, vox->nbr.as<int32_t>(),
+                             vox->V, 0, dx, s));
+  }
+  return PCS_OK;
+}
+
+int pcs_estimator_head_forward(pcs_context* ctx, const pcs_voxels* vox, const uint16_t* feat,
+                               const float* wh, const float* bh, const float* xyz, const float* rgb,
+                               float* quat, float* scale, float* opacity, float* out_rgb,
+                               float* normal, void* stream) {
+  if (!ctx || !vox || !vox->valid || !feat || !wh || !bh || !xyz || !rgb || !quat || !scale ||
+      !opacity || !out_rgb || !normal)
+    return fail(PCS_ERR_INVALID_ARG, "NULL argument or empty voxels");
+  PCS_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  StageTimer tm(ctx, ST_HEAD, s);
+  PCS_HIP(launch_head_forward(feat, wh, bh, vox->point_voxel.as<int32_t>(), xyz, rgb,
+                              vox->centroid.as<float>() + 8, vox->n, quat, scale, opacity, out_rgb,
+                              normal, s));
+  return PCS_OK;
+}
+
+int pcs_estimator_head_backward(pcs_context* ctx, const pcs_voxels* vox, const uint16_t* feat,
+                                const float* wh, const float* bh, const float* d_quat,
+                                const float* d_scale, const float* d_opacity, const float* d_rgb,
+                                uint16_t* d_feat, float* d_wh, float* d_bh, void* stream) {
+  if (!ctx || !vox || !vox->valid || !feat || !wh || !bh || !d_quat || !d_scale || !d_opacity ||
+      !d_rgb || !d_feat || !d_wh || !d_bh)
+    return fail(PCS_ERR_INVALID_ARG, "NULL argument or empty voxels");
+  PCS_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  StageTimer tm(ctx, ST_HEAD_BWD, s);
+  PCS_HIP(launch_head_backward(feat, wh, bh, vox->order.as<uint32_t>(), vox->start.as<uint32_t>(),
+                               vox->V, vox->n, d_quat, d_scale, d_opacity, d_rgb, d_feat, d_wh, d_bh, s));
   return PCS_OK;
 }
 

@@ -149,4 +149,32 @@ hipError_t launch_knn_pca(const float* xyz, int64_t n, int k, float kappa, float
                           size_t scratch_bytes, uint32_t* host_pinned, hipStream_t s);
 size_t knn_scratch_bytes(int64_t n);
 
+// ---- sparse estimator ---------------------------------------------------------------------------
+hipError_t launch_vox_keys(const float* xyz, int64_t n, uint64_t* keys, uint32_t* vals, hipStream_t s);
+hipError_t launch_vox_flags(const uint64_t* keys, int64_t n, uint32_t* flag, hipStream_t s);
+hipError_t launch_vox_build(const uint64_t* keys, const uint32_t* order, const uint32_t* flag,
+                            const uint32_t* excl, int64_t n, int64_t V, const float* xyz,
+                            const float* rgb, uint32_t* start, int32_t* coords, uint16_t* feat,
+                            int32_t* point_voxel, uint32_t* hkeys, int32_t* hvals, int log2cap,
+                            int32_t* nbr, hipStream_t s);
+bool conv_shape_supported(int cin, int cout);
+hipError_t launch_subm_conv(const uint16_t* x, int cin, const uint16_t* wt, const float* bias, int cout,
+                            const int32_t* nbr, int64_t V, int relu, uint16_t* y, hipStream_t s);
+hipError_t launch_weight_flip_t(const uint16_t* wt, int cin, int cout, uint16_t* out, hipStream_t s);
+hipError_t launch_relu_mask(const uint16_t* y, const uint16_t* dy, int64_t count, uint16_t* out,
+                            hipStream_t s);
+hipError_t launch_bias_grad(const uint16_t* dy, int64_t V, int cout, float* db, hipStream_t s);
+hipError_t launch_subm_conv_dw(const uint16_t* x, int cin, const uint16_t* dy, int cout,
+                               const int32_t* nbr, int64_t V, float* dw, hipStream_t s);
+hipError_t launch_centroid(const float* xyz, int64_t n, double* sum, float* c, hipStream_t s);
+hipError_t launch_head_forward(const uint16_t* feat, const float* wh, const float* bh,
+                               const int32_t* point_voxel, const float* xyz, const float* rgb,
+                               const float* centroid, int64_t n, float* quat, float* scale,
+                               float* opac, float* out_rgb, float* normal, hipStream_t s);
+hipError_t launch_head_backward(const uint16_t* feat, const float* wh, const float* bh,
+                                const uint32_t* order, const uint32_t* start, int64_t V, int64_t n,
+                                const float* d_quat, const float* d_scale, const float* d_opac,
+                                const float* d_rgb, uint16_t* d_feat, float* d_wh, float* d_bh,
+                                hipStream_t s);
+
 }  // namespace pcs

@@ -1,0 +1,610 @@
+// Sparse point-to-ellipsoid estimator (Section 3.2; the configuration-4 network): voxelisation,
+// kernel map, submanifold 3x3x3 convolution on BF16 MFMA with FP32 accumulation (forward, data
+// gradient, weight gradient) and the per-voxel head with its activations.
+//
+//  * voxelise: the 10-bit grid coordinate of every point is a 30-bit key; a radix sort of
+//    (key, point) groups the points of a voxel, a scan of key changes numbers the voxels in key
+//    order, one thread per voxel averages colour and coordinate residual; an open-addressing hash
+//    of the keys answers the 27 neighbour queries of every voxel (the kernel map).
+//  * convolution: output-stationary gather-GEMM. A block owns 256 output voxels (64 per
+//    wavefront, four 16-row MFMA tiles); for each of the 27 offsets the offset's weights are
+//    staged in LDS, each lane gathers 8 BF16 input channels of its row's neighbour (zeros where
+//    the neighbour is absent) and v_mfma_f32_16x16x32_bf16 accumulates in FP32. Bias and ReLU are
+//    fused into the epilogue, which rounds to BF16.
+//  * data gradient: the same kernel with weights W'_k = W_{26-k}^T (submanifold maps are
+//    symmetric: j = nbr_k(i) <=> i = nbr_{26-k}(j), so dx_j = sum_k W_{26-k} dy_{nbr_k(j)}).
+//  * weight gradient: dW_k = sum_i x_{nbr_k(i)} dy_i^T as an MFMA reduction over voxels; each
+//    block stages 64 voxels of dy and of the gathered inputs transposed in LDS, accumulates its
+//    voxel range in registers and adds its partial matrix once with float atomics.
+
+#include "pcs_internal.hpp"
+
+namespace pcs {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return 0x7FC0;   // NaN
+  u += 0x7FFFu + ((u >> 16) & 1u);                                           // nearest even
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) {
+  bf16x8 r;
+  __builtin_memcpy(&r, &v, sizeof r);
+  return r;
+}
+
+__device__ __forceinline__ uint32_t hash_slot(uint32_t key, int log2cap) {
+  return (key * 0x9E3779B1u) >> (32 - log2cap);
+}
+
+// ---- voxelisation -----------------------------------------------------------------------------
+__global__ void k_vox_key(const float* __restrict__ xyz, int64_t n, uint64_t* __restrict__ keys,
+                          uint32_t* __restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t c[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float g = floorf((xyz[a * n + i] + 1.0f) * 512.0f);
+    c[a] = (uint32_t)fminf(fmaxf(g, 0.0f), 1023.0f);
+  }
+  keys[i] = ((uint64_t)c[0] << 20) | ((uint64_t)c[1] << 10) | c[2];
+  vals[i] = (uint32_t)i;
+}
+
+__global__ void k_vox_flag(const uint64_t* __restrict__ keys, int64_t n, uint32_t* __restrict__ flag) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  flag[j] = (j == 0 || keys[j] != keys[j - 1]) ? 1u : 0u;
+}
+
+__global__ void k_vox_start(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ excl,
+                            int64_t n, uint32_t* __restrict__ start) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  if (flag[j]) start[excl[j]] = (uint32_t)j;
+}
+
+// One thread per voxel: coordinates, mean colour and residual (features, BF16, 32 channels:
+// rgb, residual, zero padding), point -> voxel map and hash insertion.
+__global__ void k_vox_reduce(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ order,
+                             const uint32_t* __restrict__ start, int64_t V, int64_t n,
+                             const float* __restrict__ xyz, const float* __restrict__ rgb,
+                             int32_t* __restrict__ coords, uint16_t* __restrict__ feat,
+                             int32_t* __restrict__ point_voxel, uint32_t* __restrict__ hkeys,
+                             int32_t* __restrict__ hvals, int log2cap) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  const uint32_t b = start[v], e = (v + 1 < V) ? start[v + 1] : (uint32_t)n;
+  const uint64_t key = keys[b];
+  const int cx = (int)(key >> 20) & 1023, cy = (int)(key >> 10) & 1023, cz = (int)key & 1023;
+  float s[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (uint32_t j = b; j < e; ++j) {
+    const uint32_t i = order[j];
+    point_voxel[i] = (int32_t)v;
+    s[0] += rgb[i];
+    s[1] += rgb[n + i];
+    s[2] += rgb[2 * n + i];
+    s[3] += (xyz[i] + 1.0f) * 512.0f - ((float)cx + 0.5f);
+    s[4] += (xyz[n + i] + 1.0f) * 512.0f - ((float)cy + 0.5f);
+    s[5] += (xyz[2 * n + i] + 1.0f) * 512.0f - ((float)cz + 0.5f);
+  }
+  const float inv = 1.0f / (float)(e - b);
+  coords[v] = cx;
+  coords[V + v] = cy;
+  coords[2 * V + v] = cz;
+  uint16_t f[32];
+#pragma unroll
+  for (int c = 0; c < 32; ++c) f[c] = c < 6 ? f32_to_bf16(s[c] * inv) : (uint16_t)0;
+  uint4* dst = reinterpret_cast<uint4*>(feat + v * 32);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    uint4 w;
+    w.x = f[8 * q + 0] | ((uint32_t)f[8 * q + 1] << 16);
+    w.y = f[8 * q + 2] | ((uint32_t)f[8 * q + 3] << 16);
+    w.z = f[8 * q + 4] | ((uint32_t)f[8 * q + 5] << 16);
+    w.w = f[8 * q + 6] | ((uint32_t)f[8 * q + 7] << 16);
+    dst[q] = w;
+  }
+  // insert into the hash table (keys are unique; linear probing always finds a free slot because
+  // the table holds at most half its capacity)
+  const uint32_t k32 = (uint32_t)key;
+  const uint32_t mask = (1u << log2cap) - 1u;
+  uint32_t slot = hash_slot(k32, log2cap);
+  for (uint32_t probe = 0; probe <= mask; ++probe) {
+    const uint32_t prev = atomicCAS(&hkeys[slot], kEmptyKey, k32);
+    if (prev == kEmptyKey) {
+      hvals[slot] = (int32_t)v;
+      break;
+    }
+    slot = (slot + 1) & mask;
+  }
+}
+
+__global__ void k_kernel_map(const int32_t* __restrict__ coords, int64_t V,
+                             const uint32_t* __restrict__ hkeys, const int32_t* __restrict__ hvals,
+                             int log2cap, int32_t* __restrict__ nbr) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  const int cx = coords[v], cy = coords[V + v], cz = coords[2 * V + v];
+  const uint32_t mask = (1u << log2cap) - 1u;
+  for (int k = 0; k < 27; ++k) {
+    const int x = cx + (k / 9) - 1, y = cy + ((k / 3) % 3) - 1, z = cz + (k % 3) - 1;
+    int32_t found = -1;
+    if (x >= 0 && x < 1024 && y >= 0 && y < 1024 && z >= 0 && z < 1024) {
+      const uint32_t key = ((uint32_t)x << 20) | ((uint32_t)y << 10) | (uint32_t)z;
+      uint32_t slot = hash_slot(key, log2cap);
+      for (uint32_t probe = 0; probe <= mask; ++probe) {
+        const uint32_t hk = hkeys[slot];
+        if (hk == key) { found = hvals[slot]; break; }
+        if (hk == kEmptyKey) break;
+        slot = (slot + 1) & mask;
+      }
+    }
+    nbr[(int64_t)k * V + v] = found;
+  }
+}
+
+// ---- convolution ------------------------------------------------------------------------------
+// y[v][o] = relu?(bias[o] + sum_k sum_c W[k][o][c] x[nbr_k(v)][c]); wt is [27][COUT][CIN] BF16.
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_subm_conv(const uint16_t* __restrict__ x,
+                                                   const uint16_t* __restrict__ wt,
+                                                   const float* __restrict__ bias,
+                                                   const int32_t* __restrict__ nbr, int64_t V,
+                                                   int relu, uint16_t* __restrict__ y) {
+  constexpr int KC = CIN / 32;       // K chunks of 32 channels
+  constexpr int NB = COUT / 16;      // 16-column output blocks
+  constexpr int LDW = CIN + 8;       // padded LDS row (avoids bank conflicts)
+  __shared__ uint16_t s_w[COUT * LDW];
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  const int64_t vbase = (int64_t)blockIdx.x * 256 + wave * 64;
+  const int row = lane % 16, grp = lane / 16;
+  f32x4 acc[4][NB];
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k = 0; k < 27; ++k) {
+    __syncthreads();
+    // stage W_k into LDS: COUT x CIN BF16, 16 bytes per thread per pass
+    const uint4* wsrc = reinterpret_cast<const uint4*>(wt + (int64_t)k * COUT * CIN);
+    for (int q = tid; q < COUT * CIN / 8; q += 256) {
+      const int o = (q * 8) / CIN, c = (q * 8) % CIN;
+      *reinterpret_cast<uint4*>(&s_w[o * LDW + c]) = wsrc[q];
+    }
+    __syncthreads();
+    bf16x8 bfr[KC][NB];
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        bfr[kc][nb] = as_bf16x8(*reinterpret_cast<const uint4*>(&s_w[(nb * 16 + row) * LDW + kc * 32 + grp * 8]));
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+      const int64_t v = vbase + mb * 16 + row;
+      const int32_t j = v < V ? nbr[(int64_t)k * V + v] : -1;
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        uint4 a = make_uint4(0u, 0u, 0u, 0u);
+        if (j >= 0) a = *reinterpret_cast<const uint4*>(x + (int64_t)j * CIN + kc * 32 + grp * 8);
+        const bf16x8 af = as_bf16x8(a);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr[kc][nb], acc[mb][nb], 0, 0, 0);
+      }
+    }
+  }
+  // epilogue: lane holds rows 4*grp + r of column row of each 16x16 block
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int o = nb * 16 + row;
+      const float bo = bias ? bias[o] : 0.0f;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t v = vbase + mb * 16 + grp * 4 + r;
+        if (v < V) {
+          float val = acc[mb][nb][r] + bo;
+          if (relu) val = fmaxf(val, 0.0f);
+          y[v * COUT + o] = f32_to_bf16(val);
+        }
+      }
+    }
+}
+
+// wt_t[s][c][o] = wt[26 - s][o][c]: weights of the data-gradient convolution.
+__global__ void k_weight_flip_t(const uint16_t* __restrict__ wt, int cin, int cout,
+                                uint16_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)27 * cin * cout;
+  if (i >= total) return;
+  const int s = (int)(i / ((int64_t)cin * cout));
+  const int rem = (int)(i % ((int64_t)cin * cout));
+  const int c = rem / cout, o = rem % cout;
+  out[i] = wt[((int64_t)(26 - s) * cout + o) * cin + c];
+}
+
+// dy_masked = dy * (y > 0) (ReLU derivative), BF16.
+__global__ void k_relu_mask(const uint16_t* __restrict__ y, const uint16_t* __restrict__ dy,
+                            int64_t count, uint16_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  out[i] = bf16_to_f32(y[i]) > 0.0f ? dy[i] : (uint16_t)0;
+}
+
+// Bias gradient: db[o] += sum_v dy[v][o] (block partial sums, one atomic per block and channel).
+__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ dy, int64_t V,
+                                                   int cout, float* __restrict__ db) {
+  __shared__ float s[256];
+  const int tid = threadIdx.x;
+  const int o = tid % cout, lane_set = tid / cout, sets = 256 / cout;
+  float acc = 0.f;
+  for (int64_t v = (int64_t)blockIdx.x * sets + lane_set; v < V; v += (int64_t)gridDim.x * sets)
+    acc += bf16_to_f32(dy[v * cout + o]);
+  s[tid] = acc;
+  __syncthreads();
+  if (tid < cout) {
+    float t = 0.f;
+    for (int q = 0; q < sets; ++q) t += s[q * cout + tid];
+    atomicAdd(&db[tid], t);
+  }
+}
+
+// dW[k][o][c] += sum_v dy[v][o] x[nbr_k(v)][c]; blockIdx.y = k. D (COUT x CIN) = dY^T X_k with
+// the voxel dimension as the MFMA reduction axis, staged transposed through LDS 64 voxels at a time.
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_subm_conv_dw(const uint16_t* __restrict__ x,
+                                                      const uint16_t* __restrict__ dy,
+                                                      const int32_t* __restrict__ nbr, int64_t V,
+                                                      int64_t chunk, float* __restrict__ dw) {
+  constexpr int MB = COUT / 16, NB = CIN / 16, TILES = MB * NB, PER_WAVE = (TILES + 3) / 4;
+  constexpr int LDT = 64 + 8;        // padded rows of the transposed chunks
+  __shared__ uint16_t s_dyT[COUT * LDT];
+  __shared__ uint16_t s_xT[CIN * LDT];
+  const int k = blockIdx.y;
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  const int row = lane % 16, grp = lane / 16;
+  f32x4 acc[PER_WAVE];
+#pragma unroll
+  for (int t = 0; t < PER_WAVE; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int64_t v0 = (int64_t)blockIdx.x * chunk;
+  const int64_t v1 = min(V, v0 + chunk);
+  for (int64_t vb = v0; vb < v1; vb += 64) {
+    __syncthreads();
+    // stage: thread -> (voxel slot, 8-channel group)
+    for (int q = tid; q < 64 * (COUT / 8); q += 256) {
+      const int slot = q / (COUT / 8), cg = (q % (COUT / 8)) * 8;
+      const int64_t v = vb + slot;
+      uint4 w = make_uint4(0u, 0u, 0u, 0u);
+      if (v < v1) w = *reinterpret_cast<const uint4*>(dy + v * COUT + cg);
+      const uint16_t* h = reinterpret_cast<const uint16_t*>(&w);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) s_dyT[(cg + e) * LDT + slot] = h[e];
+    }
+    for (int q = tid; q < 64 * (CIN / 8); q += 256) {
+      const int slot = q / (CIN / 8), cg = (q % (CIN / 8)) * 8;
+      const int64_t v = vb + slot;
+      uint4 w = make_uint4(0u, 0u, 0u, 0u);
+      if (v < v1) {
+        const int32_t j = nbr[(int64_t)k * V + v];
+        if (j >= 0) w = *reinterpret_cast<const uint4*>(x + (int64_t)j * CIN + cg);
+      }
+      const uint16_t* h = reinterpret_cast<const uint16_t*>(&w);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) s_xT[(cg + e) * LDT + slot] = h[e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < PER_WAVE; ++t) {
+      const int tile = wave * PER_WAVE + t;
+      if (tile < TILES) {
+        const int mb = tile / NB, nb = tile % NB;
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+          const bf16x8 af = as_bf16x8(*reinterpret_cast<const uint4*>(&s_dyT[(mb * 16 + row) * LDT + ks * 32 + grp * 8]));
+          const bf16x8 bf = as_bf16x8(*reinterpret_cast<const uint4*>(&s_xT[(nb * 16 + row) * LDT + ks * 32 + grp * 8]));
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, acc[t], 0, 0, 0);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < PER_WAVE; ++t) {
+    const int tile = wave * PER_WAVE + t;
+    if (tile < TILES) {
+      const int mb = tile / NB, nb = tile % NB;
+      const int c = nb * 16 + row;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int o = mb * 16 + grp * 4 + r;
+        const float val = acc[t][r];
+        if (val != 0.0f) unsafeAtomicAdd(&dw[((int64_t)k * COUT + o) * CIN + c], val);
+      }
+    }
+  }
+}
+
+// ---- head -------------------------------------------------------------------------------------
+constexpr int kHeadIn = 32, kHeadOut = 11;
+constexpr float kVoxelSize = 2.0f / 1024.0f;
+
+struct HeadOut {
+  float scale[3], q[4], qn, opacity, drgb[3];
+};
+
+__device__ __forceinline__ void head_voxel(const uint16_t* __restrict__ f, const float* s_wh,
+                                           const float* s_bh, float raw[kHeadOut], HeadOut& h) {
+  float fv[kHeadIn];
+  const uint4* src = reinterpret_cast<const uint4*>(f);
+#pragma unroll
+  for (int q = 0; q < kHeadIn / 8; ++q) {
+    const uint4 w = src[q];
+    const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      fv[8 * q + 2 * e] = bf16_to_f32((uint16_t)(ws[e] & 0xFFFF));
+      fv[8 * q + 2 * e + 1] = bf16_to_f32((uint16_t)(ws[e] >> 16));
+    }
+  }
+#pragma unroll
+  for (int o = 0; o < kHeadOut; ++o) {
+    float a = s_bh[o];
+#pragma unroll
+    for (int c = 0; c < kHeadIn; ++c) a = fmaf(s_wh[o * kHeadIn + c], fv[c], a);
+    raw[o] = a;
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) h.scale[a] = kVoxelSize * __expf(raw[a]);
+  const float q0 = raw[3] + 1.0f, q1 = raw[4], q2 = raw[5], q3 = raw[6];
+  h.qn = sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+  const float iq = h.qn > 0.0f ? 1.0f / h.qn : 0.0f;
+  h.q[0] = h.qn > 0.0f ? q0 * iq : 1.0f;
+  h.q[1] = q1 * iq; h.q[2] = q2 * iq; h.q[3] = q3 * iq;
+  h.opacity = 1.0f / (1.0f + __expf(-raw[7]));
+  h.drgb[0] = raw[8]; h.drgb[1] = raw[9]; h.drgb[2] = raw[10];
+}
+
+// Per point: its voxel's scale, rotation and opacity, colour = point colour + residual, and the
+// normal = rotated axis of the smallest scale oriented away from the centroid.
+__global__ __launch_bounds__(256) void k_head_forward(
+    const uint16_t* __restrict__ feat, const float* __restrict__ wh, const float* __restrict__ bh,
+    const int32_t* __restrict__ point_voxel, const float* __restrict__ xyz,
+    const float* __restrict__ rgb, const float* __restrict__ centroid, int64_t n,
+    float* __restrict__ quat, float* __restrict__ scale, float* __restrict__ opac,
+    float* __restrict__ out_rgb, float* __restrict__ normal) {
+  __shared__ float s_wh[kHeadOut * kHeadIn], s_bh[kHeadOut];
+  for (int i = threadIdx.x; i < kHeadOut * kHeadIn; i += blockDim.x) s_wh[i] = wh[i];
+  if (threadIdx.x < kHeadOut) s_bh[threadIdx.x] = bh[threadIdx.x];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t v = point_voxel[i];
+  float raw[kHeadOut];
+  HeadOut h;
+  head_voxel(feat + (int64_t)v * kHeadIn, s_wh, s_bh, raw, h);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) quat[a * n + i] = h.q[a];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    scale[a * n + i] = h.scale[a];
+    out_rgb[a * n + i] = rgb[a * n + i] + h.drgb[a];
+  }
+  opac[i] = h.opacity;
+  // rotation column of the smallest scale
+  const int m = (h.scale[0] <= h.scale[1] && h.scale[0] <= h.scale[2]) ? 0 : (h.scale[1] <= h.scale[2] ? 1 : 2);
+  const float w = h.q[0], x = h.q[1], y = h.q[2], z = h.q[3];
+  float nx, ny, nz;
+  if (m == 0) { nx = 1 - 2 * (y * y + z * z); ny = 2 * (x * y + w * z); nz = 2 * (x * z - w * y); }
+  else if (m == 1) { nx = 2 * (x * y - w * z); ny = 1 - 2 * (x * x + z * z); nz = 2 * (y * z + w * x); }
+  else { nx = 2 * (x * z + w * y); ny = 2 * (y * z - w * x); nz = 1 - 2 * (x * x + y * y); }
+  const float dx = xyz[i] - centroid[0], dy = xyz[n + i] - centroid[1], dz = xyz[2 * n + i] - centroid[2];
+  if (nx * dx + ny * dy + nz * dz < 0.0f) { nx = -nx; ny = -ny; nz = -nz; }
+  normal[i] = nx; normal[n + i] = ny; normal[2 * n + i] = nz;
+}
+
+// Per voxel: gradients of its points' (quat, scale, opacity, rgb) summed (points are contiguous in
+// voxel order), chained through the activations to raw, then to the features and head weights.
+// The normal is not differentiated (the training loss supervises colour only).
+__global__ __launch_bounds__(256) void k_head_backward(
+    const uint16_t* __restrict__ feat, const float* __restrict__ wh, const float* __restrict__ bh,
+    const uint32_t* __restrict__ order, const uint32_t* __restrict__ start, int64_t V, int64_t n,
+    const float* __restrict__ d_quat, const float* __restrict__ d_scale,
+    const float* __restrict__ d_opac, const float* __restrict__ d_rgb, uint16_t* __restrict__ d_feat,
+    float* __restrict__ d_wh, float* __restrict__ d_bh) {
+  __shared__ float s_wh[kHeadOut * kHeadIn], s_bh[kHeadOut];
+  __shared__ float s_dwh[kHeadOut * kHeadIn], s_dbh[kHeadOut];
+  for (int i = threadIdx.x; i < kHeadOut * kHeadIn; i += blockDim.x) { s_wh[i] = wh[i]; s_dwh[i] = 0.f; }
+  if (threadIdx.x < kHeadOut) { s_bh[threadIdx.x] = bh[threadIdx.x]; s_dbh[threadIdx.x] = 0.f; }
+  __syncthreads();
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < V) {
+    float raw[kHeadOut];
+    HeadOut h;
+    head_voxel(feat + v * kHeadIn, s_wh, s_bh, raw, h);
+    float gq[4] = {0.f, 0.f, 0.f, 0.f}, gs[3] = {0.f, 0.f, 0.f}, go = 0.f, gc[3] = {0.f, 0.f, 0.f};
+    const uint32_t b = start[v], e = (v + 1 < V) ? start[v + 1] : (uint32_t)n;
+    for (uint32_t j = b; j < e; ++j) {
+      const uint32_t i = order[j];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) gq[a] += d_quat[a * n + i];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) { gs[a] += d_scale[a * n + i]; gc[a] += d_rgb[a * n + i]; }
+      go += d_opac[i];
+    }
+    float graw[kHeadOut];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) graw[a] = gs[a] * h.scale[a];
+    const float dot = h.q[0] * gq[0] + h.q[1] * gq[1] + h.q[2] * gq[2] + h.q[3] * gq[3];
+    const float iq = h.qn > 0.0f ? 1.0f / h.qn : 0.0f;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) graw[3 + a] = (gq[a] - h.q[a] * dot) * iq;
+    graw[7] = go * h.opacity * (1.0f - h.opacity);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) graw[8 + a] = gc[a];
+    float fv[kHeadIn];
+    const uint16_t* fr = feat + v * kHeadIn;
+#pragma unroll
+    for (int c = 0; c < kHeadIn; ++c) fv[c] = bf16_to_f32(fr[c]);
+#pragma unroll
+    for (int c = 0; c < kHeadIn; ++c) {
+      float a = 0.f;
+#pragma unroll
+      for (int o = 0; o < kHeadOut; ++o) a = fmaf(s_wh[o * kHeadIn + c], graw[o], a);
+      d_feat[v * kHeadIn + c] = f32_to_bf16(a);
+    }
+#pragma unroll
+    for (int o = 0; o < kHeadOut; ++o) {
+      if (graw[o] == 0.0f) continue;
+      atomicAdd(&s_dbh[o], graw[o]);
+#pragma unroll
+      for (int c = 0; c < kHeadIn; ++c) atomicAdd(&s_dwh[o * kHeadIn + c], graw[o] * fv[c]);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kHeadOut * kHeadIn; i += blockDim.x)
+    if (s_dwh[i] != 0.0f) unsafeAtomicAdd(&d_wh[i], s_dwh[i]);
+  if (threadIdx.x < kHeadOut && s_dbh[threadIdx.x] != 0.0f) unsafeAtomicAdd(&d_bh[threadIdx.x], s_dbh[threadIdx.x]);
+}
+
+__global__ __launch_bounds__(256) void k_centroid(const float* __restrict__ xyz, int64_t n,
+                                                  double* __restrict__ sum) {
+  __shared__ double s[3][256];
+  double a[3] = {0.0, 0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    for (int c = 0; c < 3; ++c) a[c] += xyz[c * n + i];
+  for (int c = 0; c < 3; ++c) s[c][threadIdx.x] = a[c];
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int c = 0; c < 3; ++c) s[c][threadIdx.x] += s[c][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) unsafeAtomicAdd(&sum[threadIdx.x], s[threadIdx.x][0]);
+}
+
+__global__ void k_centroid_finish(const double* __restrict__ sum, int64_t n, float* __restrict__ c) {
+  if (threadIdx.x < 3) c[threadIdx.x] = (float)(sum[threadIdx.x] / (double)n);
+}
+
+inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+// ---- host launchers -----------------------------------------------------------------------------
+hipError_t launch_vox_keys(const float* xyz, int64_t n, uint64_t* keys, uint32_t* vals, hipStream_t s) {
+  hipLaunchKernelGGL(k_vox_key, dim3(blocks_for(n, 256)), dim3(256), 0, s, xyz, n, keys, vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_vox_flags(const uint64_t* keys, int64_t n, uint32_t* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_vox_flag, dim3(blocks_for(n, 256)), dim3(256), 0, s, keys, n, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_vox_build(const uint64_t* keys, const uint32_t* order, const uint32_t* flag,
+                            const uint32_t* excl, int64_t n, int64_t V, const float* xyz,
+                            const float* rgb, uint32_t* start, int32_t* coords, uint16_t* feat,
+                            int32_t* point_voxel, uint32_t* hkeys, int32_t* hvals, int log2cap,
+                            int32_t* nbr, hipStream_t s) {
+  hipError_t e = launch_fill_u32(hkeys, kEmptyKey, int64_t(1) << log2cap, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_vox_start, dim3(blocks_for(n, 256)), dim3(256), 0, s, flag, excl, n, start);
+  hipLaunchKernelGGL(k_vox_reduce, dim3(blocks_for(V, 256)), dim3(256), 0, s, keys, order, start, V, n,
+                     xyz, rgb, coords, feat, point_voxel, hkeys, hvals, log2cap);
+  hipLaunchKernelGGL(k_kernel_map, dim3(blocks_for(V, 256)), dim3(256), 0, s, coords, V, hkeys, hvals,
+                     log2cap, nbr);
+  return hipGetLastError();
+}
+
+bool conv_shape_supported(int cin, int cout) {
+  return (cin == 32 || cin == 64) && (cout == 32 || cout == 64);
+}
+
+hipError_t launch_subm_conv(const uint16_t* x, int cin, const uint16_t* wt, const float* bias, int cout,
+                            const int32_t* nbr, int64_t V, int relu, uint16_t* y, hipStream_t s) {
+  if (V == 0) return hipSuccess;
+  const dim3 grid(blocks_for(V, 256)), block(256);
+  if (cin == 32 && cout == 32) hipLaunchKernelGGL((k_subm_conv<32, 32>), grid, block, 0, s, x, wt, bias, nbr, V, relu, y);
+  else if (cin == 32 && cout == 64) hipLaunchKernelGGL((k_subm_conv<32, 64>), grid, block, 0, s, x, wt, bias, nbr, V, relu, y);
+  else if (cin == 64 && cout == 32) hipLaunchKernelGGL((k_subm_conv<64, 32>), grid, block, 0, s, x, wt, bias, nbr, V, relu, y);
+  else if (cin == 64 && cout == 64) hipLaunchKernelGGL((k_subm_conv<64, 64>), grid, block, 0, s, x, wt, bias, nbr, V, relu, y);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_weight_flip_t(const uint16_t* wt, int cin, int cout, uint16_t* out, hipStream_t s) {
+  const int64_t total = (int64_t)27 * cin * cout;
+  hipLaunchKernelGGL(k_weight_flip_t, dim3(blocks_for(total, 256)), dim3(256), 0, s, wt, cin, cout, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_relu_mask(const uint16_t* y, const uint16_t* dy, int64_t count, uint16_t* out, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_relu_mask, dim3(blocks_for(count, 256)), dim3(256), 0, s, y, dy, count, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_bias_grad(const uint16_t* dy, int64_t V, int cout, float* db, hipStream_t s) {
+  if (V == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<int64_t>(512, (V + 255) / 256);
+  hipLaunchKernelGGL(k_bias_grad, dim3(blocks), dim3(256), 0, s, dy, V, cout, db);
+  return hipGetLastError();
+}
+
+hipError_t launch_subm_conv_dw(const uint16_t* x, int cin, const uint16_t* dy, int cout,
+                               const int32_t* nbr, int64_t V, float* dw, hipStream_t s) {
+  if (V == 0) return hipSuccess;
+  // ~32 voxel ranges per offset: enough blocks to fill the GPU, few atomics per weight
+  const int64_t ranges = std::min<int64_t>(32, (V + 63) / 64);
+  const int64_t chunk = ((V + ranges - 1) / ranges + 63) / 64 * 64;
+  const dim3 grid((unsigned)((V + chunk - 1) / chunk), 27), block(256);
+  if (cin == 32 && cout == 32) hipLaunchKernelGGL((k_subm_conv_dw<32, 32>), grid, block, 0, s, x, dy, nbr, V, chunk, dw);
+  else if (cin == 32 && cout == 64) hipLaunchKernelGGL((k_subm_conv_dw<32, 64>), grid, block, 0, s, x, dy, nbr, V, chunk, dw);
+  else if (cin == 64 && cout == 32) hipLaunchKernelGGL((k_subm_conv_dw<64, 32>), grid, block, 0, s, x, dy, nbr, V, chunk, dw);
+  else if (cin == 64 && cout == 64) hipLaunchKernelGGL((k_subm_conv_dw<64, 64>), grid, block, 0, s, x, dy, nbr, V, chunk, dw);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_centroid(const float* xyz, int64_t n, double* sum, float* c, hipStream_t s) {
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(sum), 0u, 6, s);
+  if (e != hipSuccess) return e;
+  const unsigned blocks = (unsigned)std::min<int64_t>(256, (n + 255) / 256);
+  if (n > 0) hipLaunchKernelGGL(k_centroid, dim3(blocks), dim3(256), 0, s, xyz, n, sum);
+  hipLaunchKernelGGL(k_centroid_finish, dim3(1), dim3(64), 0, s, sum, std::max<int64_t>(n, 1), c);
+  return hipGetLastError();
+}
+
+hipError_t launch_head_forward(const uint16_t* feat, const float* wh, const float* bh,
+                               const int32_t* point_voxel, const float* xyz, const float* rgb,
+                               const float* centroid, int64_t n, float* quat, float* scale,
+                               float* opac, float* out_rgb, float* normal, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_head_forward, dim3(blocks_for(n, 256)), dim3(256), 0, s, feat, wh, bh, point_voxel,
+                     xyz, rgb, centroid, n, quat, scale, opac, out_rgb, normal);
+  return hipGetLastError();
+}
+
+hipError_t launch_head_backward(const uint16_t* feat, const float* wh, const float* bh,
+                                const uint32_t* order, const uint32_t* start, int64_t V, int64_t n,
+                                const float* d_quat, const float* d_scale, const float* d_opac,
+                                const float* d_rgb, uint16_t* d_feat, float* d_wh, float* d_bh,
+                                hipStream_t s) {
+  if (V == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_head_backward, dim3(blocks_for(V, 256)), dim3(256), 0, s, feat, wh, bh, order, start,
+                     V, n, d_quat, d_scale, d_opac, d_rgb, d_feat, d_wh, d_bh);
+  return hipGetLastError();
+}
+
+}  // namespace pcs

@@ -1,0 +1,231 @@
+"""Sparse point-to-ellipsoid estimator (Section 3.2) on the HIP kernels of libpcsplat.
+
+Network (the configuration-4 stand-in for the paper's UNet): eight submanifold 3x3x3 convolutions
+32(6 used) -> 32 -> 32 -> 64 -> 64 -> 64 -> 64 -> 32 -> 32 with ReLU, BF16 activations and weights
+on MFMA with FP32 accumulation, then a per-voxel linear head 32 -> 11 (scale 3, quaternion 4,
+opacity 1, colour residual 3). Inputs per voxel: mean colour and mean coordinate residual
+(Section 3.2). PyTorch holds the weights, the activations and the Adam state; every
+convolution, the voxelisation, the head and the renderer run in the library's kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import torch
+
+from . import _lib
+from ._lib import check
+from .render import Renderer, RenderState, default_options
+
+LAYERS = [(32, 32), (32, 32), (32, 64), (64, 64), (64, 64), (64, 64), (64, 32), (32, 32)]
+IN_CHANNELS = 6          # mean rgb + mean residual (the first layer's input is padded to 32)
+HEAD_OUT = 11
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _s():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class _DevArray:
+    """Zero-copy view of a library-owned device array (``__cuda_array_interface__``)."""
+
+    def __init__(self, ptr: int, shape, typestr: str):
+        self.__cuda_array_interface__ = dict(shape=tuple(shape), typestr=typestr, data=(ptr, True),
+                                             version=2, strides=None)
+
+
+class Voxels:
+    """Voxelised cloud and kernel map (owned by the library)."""
+
+    def __init__(self, renderer: Renderer):
+        self.renderer = renderer
+        self.handle = ctypes.c_void_p()
+        check(_lib.load().pcs_voxels_create(renderer.ctx, ctypes.byref(self.handle)))
+        self.V = 0
+        self.n = 0
+
+    def build(self, xyz: torch.Tensor, rgb: torch.Tensor) -> "Voxels":
+        n = xyz.shape[1]
+        V = ctypes.c_int64()
+        check(_lib.load().pcs_voxelize(self.renderer.ctx, _p(xyz), _p(rgb), n, self.handle, ctypes.byref(V), _s()))
+        self.V, self.n = int(V.value), n
+        self.xyz, self.rgb = xyz, rgb
+        return self
+
+    def arrays(self) -> dict:
+        """Zero-copy tensors: coords (3,V) int32, nbr (27,V) int32, point_voxel (n,) int32,
+        features (V,32) bf16."""
+        c, nb, pv, f = (ctypes.c_void_p() for _ in range(4))
+        V = ctypes.c_int64()
+        check(_lib.load().pcs_voxels_get(self.handle, ctypes.byref(c), ctypes.byref(nb), ctypes.byref(pv),
+                                         ctypes.byref(f), ctypes.byref(V)))
+        dev = torch.device("cuda", self.renderer.device)
+        coords = torch.as_tensor(_DevArray(c.value, (3, self.V), "<i4"), device=dev)
+        nbr = torch.as_tensor(_DevArray(nb.value, (27, self.V), "<i4"), device=dev)
+        pvox = torch.as_tensor(_DevArray(pv.value, (self.n,), "<i4"), device=dev)
+        feat = torch.as_tensor(_DevArray(f.value, (self.V, 32), "<i2"), device=dev).view(torch.bfloat16)
+        return dict(coords=coords, nbr=nbr, point_voxel=pvox, features=feat)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            _lib.load().pcs_voxels_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+
+def conv_forward(R: Renderer, vox: Voxels, x: torch.Tensor, w_bf16: torch.Tensor, bias, relu: bool,
+                 out: torch.Tensor | None = None) -> torch.Tensor:
+    cin, cout = x.shape[1], w_bf16.shape[1]
+    y = out if out is not None else torch.empty((vox.V, cout), device=x.device, dtype=torch.bfloat16)
+    check(_lib.load().pcs_subm_conv_forward(R.ctx, vox.handle, _p(x), cin, _p(w_bf16), _p(bias), cout,
+                                            int(relu), _p(y), _s()))
+    return y
+
+
+def conv_backward(R: Renderer, vox: Voxels, x, w_bf16, y, dy, want_dx=True, dw=None, db=None):
+    cin, cout = x.shape[1], w_bf16.shape[1]
+    dx = torch.empty((vox.V, cin), device=x.device, dtype=torch.bfloat16) if want_dx else None
+    check(_lib.load().pcs_subm_conv_backward(R.ctx, vox.handle, _p(x), cin, _p(w_bf16), cout, _p(y), _p(dy),
+                                             _p(dx), _p(dw), _p(db), _s()))
+    return dx
+
+
+def head_forward(R: Renderer, vox: Voxels, f, wh, bh, xyz, rgb) -> dict:
+    n = xyz.shape[1]
+    dev = xyz.device
+    g = dict(mean=xyz, quat=torch.empty((4, n), device=dev), scale=torch.empty((3, n), device=dev),
+             opacity=torch.empty((n,), device=dev), rgb=torch.empty((3, n), device=dev),
+             normal=torch.empty((3, n), device=dev))
+    check(_lib.load().pcs_estimator_head_forward(R.ctx, vox.handle, _p(f), _p(wh), _p(bh), _p(xyz), _p(rgb),
+                                                 _p(g["quat"]), _p(g["scale"]), _p(g["opacity"]), _p(g["rgb"]),
+                                                 _p(g["normal"]), _s()))
+    return g
+
+
+def head_backward(R: Renderer, vox: Voxels, f, wh, bh, grads: dict, dwh, dbh) -> torch.Tensor:
+    df = torch.empty((vox.V, 32), device=f.device, dtype=torch.bfloat16)
+    check(_lib.load().pcs_estimator_head_backward(R.ctx, vox.handle, _p(f), _p(wh), _p(bh),
+                                                  _p(grads["quat"].contiguous()), _p(grads["scale"].contiguous()),
+                                                  _p(grads["opacity"].contiguous()), _p(grads["rgb"].contiguous()),
+                                                  _p(df), _p(dwh), _p(dbh), _s()))
+    return df
+
+
+class SparseEstimator:
+    """Weights (FP32 masters, BF16 copies for the kernels) and the forward/backward passes."""
+
+    def __init__(self, renderer: Renderer, seed: int = 0, opacity_init: float = 0.9):
+        self.R = renderer
+        dev = torch.device("cuda", renderer.device)
+        gen = torch.Generator(device="cpu").manual_seed(seed)
+        self.w, self.b = [], []
+        for li, (cin, cout) in enumerate(LAYERS):
+            fan_in = 27 * (IN_CHANNELS if li == 0 else cin)
+            w = torch.randn((27, cout, cin), generator=gen) * math.sqrt(2.0 / fan_in)
+            if li == 0:
+                w[:, :, IN_CHANNELS:] = 0.0
+            self.w.append(w.to(dev))
+            self.b.append(torch.zeros(cout, device=dev))
+        self.wh = (torch.randn((HEAD_OUT, 32), generator=gen) * 1e-3).to(dev)
+        self.bh = torch.zeros(HEAD_OUT, device=dev)
+        self.bh[7] = math.log(opacity_init / (1.0 - opacity_init))
+        self.bh[0:3] = math.log(2.3)            # initial scale ~2.3 voxels
+        self.params = self.w + self.b + [self.wh, self.bh]
+
+    def bf16_weights(self):
+        return [w.to(torch.bfloat16).contiguous() for w in self.w]
+
+    def forward(self, vox: Voxels, save=False):
+        """Per-point Gaussians of the voxelised cloud (mean = the points)."""
+        arr = vox.arrays()
+        wb = self.bf16_weights()
+        acts = [arr["features"]]
+        x = arr["features"]
+        for li in range(len(LAYERS)):
+            x = conv_forward(self.R, vox, x, wb[li], self.b[li], relu=True)
+            acts.append(x)
+        g = head_forward(self.R, vox, x, self.wh, self.bh, vox.xyz, vox.rgb)
+        if save:
+            return g, dict(acts=acts, wb=wb)
+        return g
+
+    def backward(self, vox: Voxels, saved: dict, grads: dict):
+        """Weight gradients (FP32, same order as ``params``) from per-point Gaussian gradients."""
+        dws = [torch.zeros_like(w) for w in self.w]
+        dbs = [torch.zeros_like(b) for b in self.b]
+        dwh = torch.zeros_like(self.wh)
+        dbh = torch.zeros_like(self.bh)
+        acts, wb = saved["acts"], saved["wb"]
+        dy = head_backward(self.R, vox, acts[-1], self.wh, self.bh, grads, dwh, dbh)
+        for li in reversed(range(len(LAYERS))):
+            dy = conv_backward(self.R, vox, acts[li], wb[li], acts[li + 1], dy, want_dx=li > 0,
+                               dw=dws[li], db=dbs[li])
+        return dws + dbs + [dwh, dbh]
+
+
+def ssim(a: torch.Tensor, b: torch.Tensor, window=11, sigma=1.5, c1=0.01 ** 2, c2=0.03 ** 2):
+    """Mean SSIM (Wang et al. 2004) of image batches (N,3,H,W) with a Gaussian window."""
+    x = torch.arange(window, device=a.device, dtype=a.dtype) - window // 2
+    g = torch.exp(-(x ** 2) / (2 * sigma ** 2))
+    g = g / g.sum()
+    k = (g[:, None] * g[None, :]).expand(a.shape[1], 1, window, window).contiguous()
+    f = lambda t: torch.nn.functional.conv2d(t, k, groups=a.shape[1])  # noqa: E731
+    mu_a, mu_b = f(a), f(b)
+    saa = f(a * a) - mu_a ** 2
+    sbb = f(b * b) - mu_b ** 2
+    sab = f(a * b) - mu_a * mu_b
+    s = ((2 * mu_a * mu_b + c1) * (2 * sab + c2)) / ((mu_a ** 2 + mu_b ** 2 + c1) * (saa + sbb + c2))
+    return s.mean()
+
+
+def psnr(a: torch.Tensor, b: torch.Tensor) -> float:
+    mse = torch.mean((a.clamp(0, 1) - b.clamp(0, 1)) ** 2).item()
+    return 10.0 * math.log10(1.0 / max(mse, 1e-12))
+
+
+class Adam:
+    def __init__(self, params, lr=1e-3, betas=(0.9, 0.999), eps=1e-8):
+        self.params, self.lr, self.b1, self.b2, self.eps = params, lr, betas[0], betas[1], eps
+        self.m = [torch.zeros_like(p) for p in params]
+        self.v = [torch.zeros_like(p) for p in params]
+        self.t = 0
+
+    def step(self, grads):
+        self.t += 1
+        c1, c2 = 1 - self.b1 ** self.t, 1 - self.b2 ** self.t
+        for p, g, m, v in zip(self.params, grads, self.m, self.v):
+            m.mul_(self.b1).add_(g, alpha=1 - self.b1)
+            v.mul_(self.b2).addcmul_(g, g, value=1 - self.b2)
+            p.addcdiv_(m / c1, (v / c2).sqrt_().add_(self.eps), value=-self.lr)
+
+
+def render_views(R: Renderer, g: dict, cams: list, state: RenderState | None = None):
+    return R.render(g, cams, default_options(), state=state, want=("rgb",))["rgb"]
+
+
+def train_step(est: SparseEstimator, opt: Adam, clouds: list, view_fn, w_l1=0.8, w_ssim=0.2) -> float:
+    """One optimisation step over a batch of clouds. ``clouds`` holds dicts with a built ``vox``;
+    ``view_fn(cloud)`` returns (cameras, ground-truth images (C,3,H,W))."""
+    R = est.R
+    total = [torch.zeros_like(p) for p in est.params]
+    loss_sum = 0.0
+    for c in clouds:
+        cams, gt = view_fn(c)
+        g, saved = est.forward(c["vox"], save=True)
+        st = c.get("state")
+        if st is None:                       # one render state per cloud, its buffers reused
+            st = c["state"] = RenderState(R)
+        img = render_views(R, g, cams, st).requires_grad_(True)
+        loss = w_l1 * (img - gt).abs().mean() + w_ssim * (1.0 - ssim(img, gt))
+        loss.backward()
+        gg = R.render_backward(st, dict(rgb=img.grad))
+        grads = est.backward(c["vox"], saved, gg)
+        for t, gr in zip(total, grads):
+            t.add_(gr, alpha=1.0 / len(clouds))
+        loss_sum += float(loss.item())
+    opt.step(total)
+    return loss_sum / len(clouds)

@@ -1,0 +1,118 @@
+"""Dynamic point-cloud sequence: per frame, estimate every point's ellipsoid (the learned sparse
+estimator in BF16, or the kNN-PCA plain path) and render two views, reporting p50/p99 latency
+per frame and PSNR against a dense ground-truth render (Section 4.3's video setting, at 30 frames
+of a deforming procedural surface).
+
+    python -m paper_2409_16504_amd.sequence --weights gpurun_out/estimator.pt
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from synthetic import look_at_camera  # noqa: E402
+from synthetic.scenes import ProceduralSurface  # noqa: E402
+
+from . import Renderer, default_options  # noqa: E402
+from .estimator import SparseEstimator, Voxels, psnr  # noqa: E402
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--frames", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--points", type=int, default=1_000_000)
+    ap.add_argument("--width", type=int, default=1440)
+    ap.add_argument("--height", type=int, default=1600)
+    ap.add_argument("--weights", default=None)
+    ap.add_argument("--kappa", type=float, default=1.0)
+    ap.add_argument("--psnr-frames", type=int, default=3)
+    args = ap.parse_args(argv)
+
+    R = Renderer(0)
+    dev = torch.device("cuda", 0)
+    rng = np.random.default_rng(1005)
+    surf = ProceduralSurface(rng, margin_scale=1.2)
+    frames = []
+    t0 = time.time()
+    for t in range(args.frames + args.warmup):
+        scale = 1.0 + 0.2 * np.sin(2.0 * math.pi * t / 30 + surf.phase)
+        p = surf.sample(args.points, rng, radius_scale=scale)
+        clean = p.copy()
+        p = p + rng.normal(0.0, 0.002, size=p.shape)
+        rgb = surf.color(p)
+        frames.append(dict(xyz=torch.from_numpy(np.ascontiguousarray(p, np.float32)).to(dev),
+                           rgb=torch.from_numpy(np.ascontiguousarray(rgb, np.float32)).to(dev),
+                           scale=scale, clean=clean))
+    print(f"[sequence] {len(frames)} frames ready in {time.time() - t0:.1f}s", flush=True)
+    cams = [look_at_camera([3.0 * math.sin(a), 0.3, 3.0 * math.cos(a)], width=args.width, height=args.height)
+            for a in (0.0, math.pi / 2)]
+    est = SparseEstimator(R, seed=0)
+    if args.weights:
+        ck = torch.load(args.weights, weights_only=True)
+        for p_, v in zip(est.params, ck["params"]):
+            p_.copy_(v.to(dev))
+    opts = default_options()
+    vox = Voxels(R)
+    out = R.render(dict(mean=frames[0]["xyz"], quat=torch.zeros((4, args.points), device=dev),
+                        scale=torch.full((3, args.points), 0.002, device=dev),
+                        opacity=torch.full((args.points,), 0.9, device=dev), rgb=frames[0]["rgb"],
+                        normal=torch.zeros((3, args.points), device=dev)), cams, opts)
+
+    def learned(f):
+        vox.build(f["xyz"], f["rgb"])
+        return est.forward(vox)
+
+    def plain(f):
+        e = R.knn_pca(f["xyz"], k=16, kappa=args.kappa, floor=0.1)
+        return dict(mean=f["xyz"], quat=e["quat"], scale=e["scale"],
+                    opacity=torch.full((f["xyz"].shape[1],), 0.9, device=dev), rgb=f["rgb"], normal=e["normal"])
+
+    report = {}
+    for name, fn in (("learned_bf16", learned), ("knn_pca", plain)):
+        times = []
+        for i, f in enumerate(frames):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            g = fn(f)
+            R.render(g, cams, opts, out=out)
+            torch.cuda.synchronize()
+            if i >= args.warmup:
+                times.append((time.perf_counter() - t1) * 1e3)
+        report[name] = dict(p50_ms=float(np.percentile(times, 50)), p99_ms=float(np.percentile(times, 99)),
+                            max_ms=float(np.max(times)), frames=len(times))
+        print(f"[sequence] {name}: {report[name]}", flush=True)
+
+    # PSNR on a few frames against the plain render of an 8x dense sample of the clean surface
+    ps = {"learned_bf16": [], "knn_pca": []}
+    for f in frames[args.warmup:args.warmup + args.psnr_frames]:
+        pd = surf.sample(8 * args.points, np.random.default_rng(5), radius_scale=f["scale"])
+        xd = torch.from_numpy(np.ascontiguousarray(pd, np.float32)).to(dev)
+        e = R.knn_pca(xd, k=16, kappa=1.0, floor=0.1)
+        dense = dict(mean=xd, quat=e["quat"], scale=e["scale"], opacity=torch.full((xd.shape[1],), 0.9, device=dev),
+                     rgb=torch.from_numpy(np.ascontiguousarray(surf.color(pd), np.float32)).to(dev), normal=e["normal"])
+        gt = R.render(dense, cams, opts, want=("rgb",))["rgb"].clone()
+        for name, fn in (("learned_bf16", learned), ("knn_pca", plain)):
+            img = R.render(fn(f), cams, opts, want=("rgb",))["rgb"]
+            ps[name].append(psnr(img, gt))
+    for name in ps:
+        report[name]["psnr_db"] = float(np.mean(ps[name]))
+    report["config"] = dict(frames=args.frames, points=args.points, views=2, width=args.width, height=args.height,
+                            weights=args.weights)
+    print(json.dumps(report), flush=True)
+    return report
+
+
+if __name__ == "__main__":
+    main()
