@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--height", type=int, default=1080)
     ap.add_argument("--seed", type=int, default=1006)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
     return ap.parse_args()
 
 
@@ -110,6 +111,7 @@ def main():
         cpu, visits, blends = cpu_baseline(xyz, rgb, cams)
 
     roof = roofline(per_stage, args.n, m, bins, visits, blends)
+    extras = None if args.no_extras else extra_workloads(R)
     line = dict(
         metric=METRIC, value=args.n / (ms_per_step * 1e-3), unit="Gaussians/s", n_gpus=1,
         steps=args.steps, warmup=args.warmup, ms_per_step=ms_per_step, higher_is_better=True,
@@ -119,9 +121,68 @@ def main():
                     n_gaussians=args.n, width=args.width, height=args.height, cameras=1),
         ms_per_frame=ms_per_step, instances=m, knn_pca_ms=knn_ms,
         stage_ms={k: round(v, 5) for k, v in per_stage.items()},
-        roofline=roof, cpu_baseline=cpu, psnr_gap_db=None,
+        roofline=roof, cpu_baseline=cpu, psnr_gap_db=None, extras=extras,
     )
     print(json.dumps(line), flush=True)
+
+
+def extra_workloads(R):
+    """Secondary measurements (not the headline value): the 64-camera 1024^2 forward + backward of
+    the 800k-point surface in one launch, and the sparse estimator on that cloud."""
+    import torch
+    import paper_2409_16504_amd as P
+    from paper_2409_16504_amd.estimator import SparseEstimator, Voxels
+    from synthetic import make_surface, orbit_cameras
+    dev = torch.device("cuda", 0)
+    _, xyz, rgb = make_surface(800_000, 1002, quantize=True)
+    txyz, trgb = torch.from_numpy(xyz).to(dev), torch.from_numpy(rgb).to(dev)
+    est = R.knn_pca(txyz, k=16, kappa=1.0, floor=0.1)
+    g = dict(mean=txyz, quat=est["quat"], scale=est["scale"], opacity=torch.full((xyz.shape[1],), 0.9, device=dev),
+             rgb=trgb, normal=est["normal"])
+    cams = orbit_cameras(64, np.random.default_rng(1003), width=1024, height=1024)
+    st = P.RenderState(R)
+    opts = P.default_options()
+    out = R.render(g, cams, opts, state=st)
+    gen = torch.Generator(device=dev).manual_seed(0)
+    go = dict(rgb=torch.randn(out["rgb"].shape, device=dev, generator=gen),
+              normal=torch.randn(out["normal"].shape, device=dev, generator=gen),
+              depth=torch.randn(out["depth"].shape, device=dev, generator=gen))
+    R.render_backward(st, go)
+    torch.cuda.synchronize()
+    reps = 3
+    R.timing(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        R.render(g, cams, opts, state=st, out=out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        R.render_backward(st, go)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    stages = {k: round(v[0] / reps, 4) for k, v in R.timings().items() if v[1] > 0}
+    many = dict(workload="800k surfel Gaussians x 64 orbit cameras at 1024x1024, one launch",
+                forward_ms=(t1 - t0) * 1e3 / reps, backward_ms=(t2 - t1) * 1e3 / reps, stage_ms=stages)
+    del st, out, go
+    # sparse estimator (BF16 MFMA) on the same cloud: voxelise + 8 convolutions + head
+    E = SparseEstimator(R, seed=0)
+    vox = Voxels(R).build(txyz, trgb)
+    E.forward(vox)
+    torch.cuda.synchronize()
+    R.timing(True)
+    t3 = time.perf_counter()
+    for _ in range(reps):
+        E.forward(Voxels(R).build(txyz, trgb))
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    est_stages = {k: round(v[0] / reps, 4) for k, v in R.timings().items() if v[1] > 0}
+    conv_flop = 2 * 27 * sum(ci * co for ci, co in [(32, 32), (32, 32), (32, 64), (64, 64), (64, 64), (64, 64),
+                                                  (64, 32), (32, 32)]) * vox.V
+    conv_ms = est_stages.get("conv", float("nan"))
+    estimator = dict(workload=f"sparse estimator on {xyz.shape[1]} points ({vox.V} voxels)",
+                     ms_per_cloud=(t4 - t3) * 1e3 / reps, stage_ms=est_stages,
+                     conv_mfma_tflops=conv_flop / (conv_ms * 1e-3) / 1e12 if conv_ms == conv_ms else None)
+    return dict(many_cameras=many, estimator=estimator)
 
 
 def roofline(per_stage, n, m, bins, visits, blends):
