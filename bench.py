@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=1006)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (for scaling HBM byte counters)")
     return ap.parse_args()
 
 
@@ -82,6 +84,15 @@ def main():
         R.knn_pca(txyz, k=16, kappa=1.0, floor=0.1, out=est)
     knn_ms = R.timings()["knn_pca"][0] / 3.0
 
+    if args.copy_calibration_mib:
+        src = torch.empty(args.copy_calibration_mib << 20, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: {args.copy_calibration_mib} MiB read + written", file=sys.stderr,
+              flush=True)
+        del src, dst
     opts = P.default_options()
     out = R.render(g, cams, opts)
     for _ in range(args.warmup):
@@ -131,7 +142,7 @@ def extra_workloads(R):
     the 800k-point surface in one launch, and the sparse estimator on that cloud."""
     import torch
     import paper_2409_16504_amd as P
-    from paper_2409_16504_amd.estimator import SparseEstimator, Voxels
+    from paper_2409_16504_amd.estimator import SparseEstimator, adaptive_grid
     from synthetic import make_surface, orbit_cameras
     dev = torch.device("cuda", 0)
     _, xyz, rgb = make_surface(800_000, 1002, quantize=True)
@@ -166,20 +177,21 @@ def extra_workloads(R):
     del st, out, go
     # sparse estimator (BF16 MFMA) on the same cloud: voxelise + 8 convolutions + head
     E = SparseEstimator(R, seed=0)
-    vox = Voxels(R).build(txyz, trgb)
+    vox = adaptive_grid(R, txyz, trgb)
     E.forward(vox)
     torch.cuda.synchronize()
     R.timing(True)
     t3 = time.perf_counter()
     for _ in range(reps):
-        E.forward(Voxels(R).build(txyz, trgb))
+        E.forward(vox.build(txyz, trgb, vox.grid))
     torch.cuda.synchronize()
     t4 = time.perf_counter()
     est_stages = {k: round(v[0] / reps, 4) for k, v in R.timings().items() if v[1] > 0}
     conv_flop = 2 * 27 * sum(ci * co for ci, co in [(32, 32), (32, 32), (32, 64), (64, 64), (64, 64), (64, 64),
                                                   (64, 32), (32, 32)]) * vox.V
     conv_ms = est_stages.get("conv", float("nan"))
-    estimator = dict(workload=f"sparse estimator on {xyz.shape[1]} points ({vox.V} voxels)",
+    estimator = dict(workload=f"sparse estimator on {xyz.shape[1]} points ({vox.V} voxels, grid {vox.grid}^3, "
+                              f"{vox.mean_neighbours():.1f} occupied neighbours per voxel)",
                      ms_per_cloud=(t4 - t3) * 1e3 / reps, stage_ms=est_stages,
                      conv_mfma_tflops=conv_flop / (conv_ms * 1e-3) / 1e12 if conv_ms == conv_ms else None)
     return dict(many_cameras=many, estimator=estimator)

@@ -165,10 +165,11 @@ int pcs_knn_pca(pcs_context* ctx, const float* xyz, int64_t n, int32_t k, float 
                 float floor_ratio, float* quat, float* scale, float* normal, void* stream);
 
 /* ---- sparse point-to-ellipsoid estimator (Section 3.2) -------------------------------------
- * Voxels of a point cloud on the 1024^3 grid over [-1,1]^3 (the 10-bit quantisation of
- * Section 3.3): coordinate c = clamp(floor((p + 1) * 512), 0, 1023), voxels numbered in ascending
+ * Voxels of a point cloud on a grid of G^3 voxels over [-1,1]^3 (G a power of two <= 1024; G = 1024
+ * is the 10-bit quantisation of Section 3.3; a coarser G is the density-adaptive voxel size of
+ * Section 3.2): coordinate c = clamp(floor((p + 1) * G/2), 0, G-1), voxels numbered in ascending
  * linear key (x << 20 | y << 10 | z). Features are BF16 (bit patterns in uint16_t), row-major
- * [V][channels]; 32 input channels: mean colour (3), mean residual (p + 1) * 512 - (c + 0.5) (3)
+ * [V][channels]; 32 input channels: mean colour (3), mean residual (p + 1) * G/2 - (c + 0.5) (3)
  * (Section 3.2's colour and coordinate residual), zeros. Owned by the voxels object. */
 typedef struct pcs_voxels pcs_voxels;
 int pcs_voxels_create(pcs_context* ctx, pcs_voxels** out);
@@ -177,8 +178,8 @@ void pcs_voxels_destroy(pcs_voxels* vox);
 /* Voxelise n points xyz[3][n], rgb[3][n] (device, FP32) and build the kernel map (for every voxel
  * and offset k = 9 (dx+1) + 3 (dy+1) + (dz+1), the neighbour's index or -1). Synchronises the
  * stream once to size the voxel arrays; *n_voxels receives V. n < 2^30. */
-int pcs_voxelize(pcs_context* ctx, const float* xyz, const float* rgb, int64_t n, pcs_voxels* vox,
-                 int64_t* n_voxels, void* stream);
+int pcs_voxelize(pcs_context* ctx, const float* xyz, const float* rgb, int64_t n, int32_t grid,
+                 pcs_voxels* vox, int64_t* n_voxels, void* stream);
 
 /* Device pointers owned by vox: coords[3][V] (int32), nbr[27][V] (int32), point_voxel[n] (int32),
  * features[V][32] (BF16). */
@@ -203,7 +204,7 @@ int pcs_subm_conv_backward(pcs_context* ctx, const pcs_voxels* vox, const uint16
 
 /* Estimator head (Section 3.2's shared per-point head, with the outputs of configuration 4): per
  * voxel raw = wh f + bh (wh[11][32], bh[11] FP32; f = features[V][32] BF16); per point of the voxel:
- * scale = (2/1024) exp(raw[0:3]), quat = normalise(raw[3:7] + (1,0,0,0)), opacity =
+ * scale = (2/G) exp(raw[0:3]) (the voxel edge times exp), quat = normalise(raw[3:7] + (1,0,0,0)), opacity =
  * sigmoid(raw[7]), rgb = point colour + raw[8:11], normal = rotated axis of the smallest scale
  * oriented away from the cloud centroid. xyz, rgb are the voxelised points; outputs planar. */
 int pcs_estimator_head_forward(pcs_context* ctx, const pcs_voxels* vox, const uint16_t* feat,

@@ -5,15 +5,17 @@ convolutional network and predicts per-point Gaussian parameters with a shared h
 estimator built here is the configuration-4 stand-in for it: eight submanifold 3x3x3 convolutions
 with ReLU and a per-voxel linear head. This module defines each step plainly:
 
-* ``voxelize``: voxel coordinate c = clamp(floor((p + 1) * 512), 0, 1023) on the 1024^3 grid
-  (the 10-bit quantisation of Section 3.3); unique voxels in ascending linear key
-  (x << 20 | y << 10 | z); per voxel the mean colour and the mean residual
-  (p + 1) * 512 - (c + 0.5) of its points (the coordinate residual of Section 3.2).
+* ``voxelize``: voxel coordinate c = clamp(floor((p + 1) * G/2), 0, G-1) on a G^3 grid over
+  [-1,1]^3 (G = 1024 is the 10-bit quantisation of Section 3.3); unique voxels in ascending linear
+  key (x << 20 | y << 10 | z); per voxel the mean colour and the mean residual
+  (p + 1) * G/2 - (c + 0.5) of its points (the coordinate residual of Section 3.2). The cloud's
+  coordinates are FP32, so the voxel decision floor is taken on the FP32 sum p + 1 (times the
+  power of two G/2, exact); the residual is FP64.
 * ``kernel_map``: for voxel i and offset k = 9 (dx + 1) + 3 (dy + 1) + (dz + 1) the index of the
   voxel at c_i + (dx, dy, dz), or -1.
 * ``subm_conv``: y_i = b + sum_k W_k^T x_{nbr_k(i)} over present neighbours (submanifold: outputs
   only at active sites), optional ReLU.
-* ``head``: raw = W_h^T f + b_h per voxel; scale = (1/512) exp(raw[0:3]); q = normalise(raw[3:7] +
+* ``head``: raw = W_h^T f + b_h per voxel; scale = (2/G) exp(raw[0:3]) (voxel edge times exp); q = normalise(raw[3:7] +
   (1, 0, 0, 0)); opacity = sigmoid(raw[7]); rgb = colour + raw[8:11]; normal = the rotated axis of
   the smallest scale, oriented away from the cloud centroid.
 """
@@ -32,22 +34,25 @@ def voxel_key(c: np.ndarray) -> np.ndarray:
     return (c[:, 0] << 20) | (c[:, 1] << 10) | c[:, 2]
 
 
-def voxelize(xyz: np.ndarray, rgb: np.ndarray) -> dict:
-    p = np.asarray(xyz, np.float64).T                       # (n, 3)
-    c = np.clip(np.floor((p + 1.0) * (GRID / 2)), 0, GRID - 1).astype(np.int64)
+def voxelize(xyz: np.ndarray, rgb: np.ndarray, grid: int = GRID) -> dict:
+    if grid < 2 or grid > GRID or grid & (grid - 1):
+        raise ValueError("grid must be a power of two in [2, 1024]")
+    p32 = np.asarray(xyz, np.float32).T                     # (n, 3)
+    p = p32.astype(np.float64)
+    c = np.clip(np.floor((p32 + np.float32(1.0)).astype(np.float64) * (grid / 2)), 0, grid - 1).astype(np.int64)
     keys = voxel_key(c)
     ukeys, inv = np.unique(keys, return_inverse=True)
     V = ukeys.size
     coords = np.stack([(ukeys >> 20) & 1023, (ukeys >> 10) & 1023, ukeys & 1023], axis=1)
     count = np.bincount(inv, minlength=V).astype(np.float64)
     col = np.stack([np.bincount(inv, weights=np.asarray(rgb, np.float64)[a], minlength=V) for a in range(3)], 1)
-    res_p = (p + 1.0) * (GRID / 2) - (c + 0.5)
+    res_p = (p + 1.0) * (grid / 2) - (c + 0.5)
     res = np.stack([np.bincount(inv, weights=res_p[:, a], minlength=V) for a in range(3)], 1)
     return dict(coords=coords, keys=ukeys, point_voxel=inv.astype(np.int64),
                 color=col / count[:, None], residual=res / count[:, None], count=count)
 
 
-def kernel_map(coords: np.ndarray) -> np.ndarray:
+def kernel_map(coords: np.ndarray, grid: int = GRID) -> np.ndarray:
     """nbr (27, V) int64: index of the neighbour at each offset or -1."""
     keys = voxel_key(coords)
     order = np.argsort(keys)
@@ -56,8 +61,8 @@ def kernel_map(coords: np.ndarray) -> np.ndarray:
     nbr = np.full((27, V), -1, np.int64)
     for k, off in enumerate(OFFSETS):
         q = coords + off
-        ok = np.all((q >= 0) & (q < GRID), axis=1)
-        qk = voxel_key(np.clip(q, 0, GRID - 1))
+        ok = np.all((q >= 0) & (q < grid), axis=1)
+        qk = voxel_key(np.clip(q, 0, grid - 1))
         pos = np.searchsorted(sk, qk)
         pos = np.minimum(pos, V - 1)
         hit = ok & (sk[pos] == qk)
@@ -77,10 +82,10 @@ def subm_conv(x: np.ndarray, W: np.ndarray, b: np.ndarray, nbr: np.ndarray, relu
 
 
 def head(f: np.ndarray, Wh: np.ndarray, bh: np.ndarray, color: np.ndarray, points: np.ndarray,
-         point_voxel: np.ndarray) -> dict:
+         point_voxel: np.ndarray, grid: int = GRID) -> dict:
     """Per-point Gaussian parameters from voxel features f (V, C); planar outputs like the renderer."""
     raw = np.asarray(f, np.float64) @ np.asarray(Wh, np.float64) + np.asarray(bh, np.float64)
-    scale = VOXEL * np.exp(raw[:, 0:3])
+    scale = (2.0 / grid) * np.exp(raw[:, 0:3])
     q = raw[:, 3:7] + np.array([1.0, 0, 0, 0])
     q = q / np.linalg.norm(q, axis=1, keepdims=True)
     opac = 1.0 / (1.0 + np.exp(-raw[:, 7]))
@@ -118,12 +123,12 @@ def subm_conv_backward(x: np.ndarray, W: np.ndarray, nbr: np.ndarray, dy: np.nda
     return dx, dW, dy.sum(axis=0)
 
 
-def head_torch(f, Wh, bh, color, point_voxel):
+def head_torch(f, Wh, bh, color, point_voxel, grid: int = GRID):
     """The head of ``head`` (without the normal) in FP64 torch ops, so that autograd gives its
     adjoint: returns per-point quat (4,n), scale (3,n), opacity (n,), rgb (3,n)."""
     import torch
     raw = f @ Wh + bh
-    scale = VOXEL * torch.exp(raw[:, 0:3])
+    scale = (2.0 / grid) * torch.exp(raw[:, 0:3])
     q = raw[:, 3:7] + torch.tensor([1.0, 0.0, 0.0, 0.0], dtype=raw.dtype)
     q = q / torch.linalg.norm(q, dim=1, keepdim=True)
     opac = torch.sigmoid(raw[:, 7])

@@ -126,6 +126,7 @@ struct pcs_voxels {
   pcs_context* ctx = nullptr;
   int64_t n = 0, V = 0;
   int log2cap = 0;
+  int grid = 1024;
   DevBuf keys, order, flag, excl, start, coords, feat, point_voxel, hkeys, hvals, nbr, centroid;
   bool valid = false;
 };
@@ -491,9 +492,11 @@ int pcs_voxels_create(pcs_context* ctx, pcs_voxels** out) {
 
 void pcs_voxels_destroy(pcs_voxels* v) { delete v; }
 
-int pcs_voxelize(pcs_context* ctx, const float* xyz, const float* rgb, int64_t n, pcs_voxels* vox,
-                 int64_t* n_voxels, void* stream) {
+int pcs_voxelize(pcs_context* ctx, const float* xyz, const float* rgb, int64_t n, int32_t grid,
+                 pcs_voxels* vox, int64_t* n_voxels, void* stream) {
   if (!ctx || !vox || !n_voxels) return fail(PCS_ERR_INVALID_ARG, "NULL argument");
+  if (grid < 2 || grid > 1024 || (grid & (grid - 1)) != 0)
+    return fail(PCS_ERR_INVALID_ARG, "grid must be a power of two in [2, 1024]");
   if (vox->ctx != ctx) return fail(PCS_ERR_INVALID_ARG, "voxels belong to another context");
   if (n <= 0 || !xyz || !rgb) return fail(PCS_ERR_INVALID_ARG, "need at least one point");
   if (n >= (int64_t(1) << 30)) return fail(PCS_ERR_UNSUPPORTED, "n must be below 2^30");
@@ -512,7 +515,7 @@ int pcs_voxelize(pcs_context* ctx, const float* xyz, const float* rgb, int64_t n
   PCS_TRY(ensure(vox->point_voxel, n * sizeof(int32_t), "point to voxel map"));
   PCS_TRY(ensure(vox->centroid, 64, "centroid"));
   StageTimer tm(ctx, ST_VOXELIZE, s);
-  PCS_HIP(launch_vox_keys(xyz, n, vox->keys.as<uint64_t>(), vox->order.as<uint32_t>(), s));
+  PCS_HIP(launch_vox_keys(xyz, n, grid, vox->keys.as<uint64_t>(), vox->order.as<uint32_t>(), s));
   bool in_alt = false;
   PCS_HIP(launch_sort(vox->keys.as<uint64_t>(), vox->order.as<uint32_t>(), ctx->keys_alt.as<uint64_t>(),
                       ctx->vals_alt.as<uint32_t>(), n, 30, ctx->sort_scratch.p, s, &in_alt, nullptr, nullptr));
@@ -536,7 +539,7 @@ int pcs_voxelize(pcs_context* ctx, const float* xyz, const float* rgb, int64_t n
   PCS_TRY(ensure(vox->hvals, (size_t(1) << log2cap) * sizeof(int32_t), "voxel hash values"));
   PCS_TRY(ensure(vox->nbr, 27 * V * sizeof(int32_t), "kernel map"));
   PCS_HIP(launch_vox_build(vox->keys.as<uint64_t>(), vox->order.as<uint32_t>(), vox->flag.as<uint32_t>(),
-                           vox->excl.as<uint32_t>(), n, (int64_t)V, xyz, rgb, vox->start.as<uint32_t>(),
+                           vox->excl.as<uint32_t>(), n, (int64_t)V, xyz, rgb, grid, vox->start.as<uint32_t>(),
                            vox->coords.as<int32_t>(), vox->feat.as<uint16_t>(),
                            vox->point_voxel.as<int32_t>(), vox->hkeys.as<uint32_t>(),
                            vox->hvals.as<int32_t>(), log2cap, vox->nbr.as<int32_t>(), s));
@@ -544,6 +547,7 @@ int pcs_voxelize(pcs_context* ctx, const float* xyz, const float* rgb, int64_t n
   vox->n = n;
   vox->V = (int64_t)V;
   vox->log2cap = log2cap;
+  vox->grid = grid;
   vox->valid = true;
   *n_voxels = (int64_t)V;
   return PCS_OK;
@@ -608,8 +612,8 @@ int pcs_estimator_head_forward(pcs_context* ctx, const pcs_voxels* vox, const ui
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   StageTimer tm(ctx, ST_HEAD, s);
   PCS_HIP(launch_head_forward(feat, wh, bh, vox->point_voxel.as<int32_t>(), xyz, rgb,
-                              vox->centroid.as<float>() + 8, vox->n, quat, scale, opacity, out_rgb,
-                              normal, s));
+                              vox->centroid.as<float>() + 8, vox->n, 2.0f / (float)vox->grid, quat,
+                              scale, opacity, out_rgb, normal, s));
   return PCS_OK;
 }
 
@@ -624,7 +628,8 @@ int pcs_estimator_head_backward(pcs_context* ctx, const pcs_voxels* vox, const u
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   StageTimer tm(ctx, ST_HEAD_BWD, s);
   PCS_HIP(launch_head_backward(feat, wh, bh, vox->order.as<uint32_t>(), vox->start.as<uint32_t>(),
-                               vox->V, vox->n, d_quat, d_scale, d_opacity, d_rgb, d_feat, d_wh, d_bh, s));
+                               vox->V, vox->n, 2.0f / (float)vox->grid, d_quat, d_scale, d_opacity, d_rgb,
+                               d_feat, d_wh, d_bh, s));
   return PCS_OK;
 }
 

@@ -38,11 +38,6 @@ __device__ __forceinline__ TilePixel tile_pixel(int tx, int ty, int tid) {
   return p;
 }
 
-// Value of lane l (wave-uniform l) in every lane.
-__device__ __forceinline__ float bcast(float x, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
-}
-
 // Does the splat's padded ellipse bounding box reach a pixel centre of the 8x8 quadrant?
 __device__ __forceinline__ bool touches_quadrant(float u, float v, float ex, float ey, float qx0,
                                                  float qy0) {
@@ -79,8 +74,7 @@ __global__ __launch_bounds__(kBlock) void k_composite(
     const float4* r = rec_cam + (int64_t)min(vals[start + tid], (uint32_t)(n - 1)) * kRecFloat4;
     p0 = r[0]; p1 = r[1]; p2 = r[2]; p3 = r[3];
   }
-  uint32_t b = start;
-  for (; b < end; b += kBlock) {
+  for (uint32_t b = start; b < end; b += kBlock) {
     if (__syncthreads_count(done) == kBlock) break;
     if (b + tid < end) {
       s_r0[tid] = p0; s_r1[tid] = p1; s_r2[tid] = p2; s_r3[tid] = p3;
@@ -94,40 +88,37 @@ __global__ __launch_bounds__(kBlock) void k_composite(
     const int cnt = (int)min((uint32_t)kBlock, end - b);
     for (int c = 0; c < cnt; c += kWave) {
       if (__ballot(!done) == 0ull) break;               // every pixel of this wavefront is done
-      // wavefront-cooperative walk: lane l holds record c + l in registers; the records that reach
-      // this quadrant are then broadcast lane by lane (v_readlane), so the blend loop reads no LDS
       const int e = c + lane;
-      float4 m0 = make_float4(0.f, 0.f, 0.f, 0.f), m1 = m0, m2 = m0, m3 = m0;
       bool rel = false;
       if (e < cnt) {
-        m0 = s_r0[e]; m1 = s_r1[e]; m2 = s_r2[e]; m3 = s_r3[e];
-        rel = touches_quadrant(m0.x, m0.y, m1.w, m2.w, P.qx0, P.qy0);
+        const float4 a0 = s_r0[e];
+        rel = touches_quadrant(a0.x, a0.y, s_r1[e].w, s_r2[e].w, P.qx0, P.qy0);
       }
       uint64_t mask = __ballot(rel);
       while (mask) {
-        const int l = (int)__builtin_ctzll(mask);
+        const int k = c + (int)__builtin_ctzll(mask);
         mask &= mask - 1;
-        const float u = bcast(m0.x, l), v = bcast(m0.y, l), o = bcast(m0.z, l), z = bcast(m0.w, l);
-        const float A = bcast(m1.x, l), B = bcast(m1.y, l), C = bcast(m1.z, l);
-        const float cr = bcast(m2.x, l), cg = bcast(m2.y, l), cb = bcast(m2.z, l);
-        const float nx = bcast(m3.x, l), ny = bcast(m3.y, l), nz = bcast(m3.z, l);
         if (done) continue;
-        const float dx = pxf - u, dy = pyf - v;
-        const float q = conic_q(A, B, C, dx, dy);
-        const float a = fminf(opt.alpha_max, o * __expf(-0.5f * q));
-        if ((q <= cut2) && !(a < opt.alpha_min)) {
-          const float w = a * T;
-          acc0 = fmaf(w, cr, acc0);
-          acc1 = fmaf(w, cg, acc1);
-          acc2 = fmaf(w, cb, acc2);
-          acc3 = fmaf(w, nx, acc3);
-          acc4 = fmaf(w, ny, acc4);
-          acc5 = fmaf(w, nz, acc5);
-          acc6 = fmaf(w, z, acc6);
-          T = T * (1.0f - a);
-          last = (int32_t)(b - start) + c + l + 1;
-          if (T < opt.t_eps) done = true;
-        }
+        const float4 r0 = s_r0[k];
+        const float4 r1 = s_r1[k];
+        const float dx = pxf - r0.x, dy = pyf - r0.y;
+        const float q = conic_q(r1.x, r1.y, r1.z, dx, dy);
+        if (!(q <= cut2)) continue;
+        const float a = fminf(opt.alpha_max, r0.z * __expf(-0.5f * q));
+        if (a < opt.alpha_min) continue;
+        const float w = a * T;
+        const float4 r2 = s_r2[k];
+        const float4 r3 = s_r3[k];
+        acc0 = fmaf(w, r2.x, acc0);
+        acc1 = fmaf(w, r2.y, acc1);
+        acc2 = fmaf(w, r2.z, acc2);
+        acc3 = fmaf(w, r3.x, acc3);
+        acc4 = fmaf(w, r3.y, acc4);
+        acc5 = fmaf(w, r3.z, acc5);
+        acc6 = fmaf(w, r0.w, acc6);
+        T = T * (1.0f - a);
+        last = (int32_t)(b - start) + k + 1;
+        if (T < opt.t_eps) done = true;
       }
     }
   }
@@ -207,69 +198,74 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(
     __syncthreads();
     const int cnt = bend - bstart;
     for (int c = ((cnt - 1) / kWave) * kWave; c >= 0; c -= kWave) {
-      // lane l holds record c + l; relevant records are broadcast lane by lane, back to front
       const int e = c + lane;
-      float4 m0 = make_float4(0.f, 0.f, 0.f, 0.f), m1 = m0, m2 = m0, m3 = m0;
       bool rel = false;
       if (e < cnt) {
-        m0 = s_r0[e]; m1 = s_r1[e]; m2 = s_r2[e]; m3 = s_r3[e];
-        rel = touches_quadrant(m0.x, m0.y, m1.w, m2.w, P.qx0, P.qy0);
+        const float4 a0 = s_r0[e];
+        rel = touches_quadrant(a0.x, a0.y, s_r1[e].w, s_r2[e].w, P.qx0, P.qy0);
       }
       uint64_t mask = __ballot(rel);
       while (mask) {
         const int hb = 63 - (int)__builtin_clzll(mask);
         mask &= ~(1ull << hb);
-        const int32_t p = bstart + c + hb;
-        const float u = bcast(m0.x, hb), v = bcast(m0.y, hb), o = bcast(m0.z, hb), z = bcast(m0.w, hb);
-        const float A = bcast(m1.x, hb), B = bcast(m1.y, hb), C = bcast(m1.z, hb);
-        const float f[7] = {bcast(m2.x, hb), bcast(m2.y, hb), bcast(m2.z, hb), bcast(m3.x, hb),
-                            bcast(m3.y, hb), bcast(m3.z, hb), z};
+        const int k = c + hb;
+        const int32_t p = bstart + k;
         float pg[kScreenGrads];
 #pragma unroll
         for (int i = 0; i < kScreenGrads; ++i) pg[i] = 0.f;
         bool contrib = false;
         if (p < nc) {
-          const float dx = pxf - u, dy = pyf - v;
-          const float q = conic_q(A, B, C, dx, dy);
-          const float ex = __expf(-0.5f * q);
-          const float araw = o * ex;
-          const float a = fminf(opt.alpha_max, araw);
-          if ((q <= cut2) && !(a < opt.alpha_min)) {
-            contrib = true;
-            const float one_m = 1.0f - a;
-            T = T / one_m;                       // transmittance in front of this splat
-            const float w = a * T;
-            float dLda = 0.f;
-            const float inv = 1.0f / one_m;
+          const float4 r0 = s_r0[k];
+          const float4 r1 = s_r1[k];
+          const float dx = pxf - r0.x, dy = pyf - r0.y;
+          const float q = conic_q(r1.x, r1.y, r1.z, dx, dy);
+          if (q <= cut2) {
+            const float e = __expf(-0.5f * q);
+            const float araw = r0.z * e;
+            const float a = fminf(opt.alpha_max, araw);
+            if (a >= opt.alpha_min) {
+              contrib = true;
+              const float4 r2 = s_r2[k];
+              const float4 r3 = s_r3[k];
+              const float one_m = 1.0f - a;
+              T = T / one_m;                       // transmittance in front of this splat
+              const float w = a * T;
+              const float f[7] = {r2.x, r2.y, r2.z, r3.x, r3.y, r3.z, r0.w};
+              float dLda = 0.f;
+              const float inv = 1.0f / one_m;
 #pragma unroll
-            for (int ch = 0; ch < 7; ++ch) {
-              dLda = fmaf(g[ch], fmaf(T, f[ch], -behind[ch] * inv), dLda);
-              behind[ch] = fmaf(w, f[ch], behind[ch]);
-            }
-            pg[7] = g[0] * w;
-            pg[8] = g[1] * w;
-            pg[9] = g[2] * w;
-            pg[10] = g[3] * w;
-            pg[11] = g[4] * w;
-            pg[12] = g[5] * w;
-            pg[6] = g[6] * w;
-            if (!(araw > opt.alpha_max)) {
-              pg[5] = dLda * ex;
-              const float dLdq = dLda * (-0.5f * a);
-              pg[2] = dLdq * dx * dx;
-              pg[3] = dLdq * 2.0f * dx * dy;
-              pg[4] = dLdq * dy * dy;
-              pg[0] = dLdq * (-2.0f * fmaf(A, dx, B * dy));
-              pg[1] = dLdq * (-2.0f * fmaf(B, dx, C * dy));
+              for (int ch = 0; ch < 7; ++ch) {
+                dLda = fmaf(g[ch], fmaf(T, f[ch], -behind[ch] * inv), dLda);
+                behind[ch] = fmaf(w, f[ch], behind[ch]);
+              }
+              pg[7] = g[0] * w;
+              pg[8] = g[1] * w;
+              pg[9] = g[2] * w;
+              pg[10] = g[3] * w;
+              pg[11] = g[4] * w;
+              pg[12] = g[5] * w;
+              pg[6] = g[6] * w;
+              if (!(araw > opt.alpha_max)) {
+                pg[5] = dLda * e;
+                const float dLdq = dLda * (-0.5f * a);
+                pg[2] = dLdq * dx * dx;
+                pg[3] = dLdq * 2.0f * dx * dy;
+                pg[4] = dLdq * dy * dy;
+                pg[0] = dLdq * (-2.0f * fmaf(r1.x, dx, r1.y * dy));
+                pg[1] = dLdq * (-2.0f * fmaf(r1.y, dx, r1.z * dy));
+              }
             }
           }
         }
         if (__ballot(contrib) == 0ull) continue;   // wave-uniform
-        const int64_t dst = base_idx + s_g[c + hb];
+        const int64_t dst = base_idx + s_g[k];
+        float sv[kScreenGrads];
 #pragma unroll
-        for (int i = 0; i < kScreenGrads; ++i) {
-          const float sv = wave_sum(pg[i]);
-          if (lane == 0 && sv != 0.0f) unsafeAtomicAdd(&sgrad[i * stride + dst], sv);
+        for (int i = 0; i < kScreenGrads; ++i) sv[i] = wave_sum_to_last(pg[i]);
+        if (lane == kWave - 1) {
+#pragma unroll
+          for (int i = 0; i < kScreenGrads; ++i)
+            if (sv[i] != 0.0f) unsafeAtomicAdd(&sgrad[i * stride + dst], sv[i]);
         }
       }
     }

@@ -78,6 +78,18 @@ __device__ __forceinline__ float wave_sum(float v) {
   return (r0 + r1) + (r2 + r3);
 }
 
+// Sum across the wave left in lane 63 only (other lanes hold partial sums): row prefix sums by
+// row_shr, then row_bcast:15 and row_bcast:31 carry the row totals into the upper rows.
+__device__ __forceinline__ float wave_sum_to_last(float v) {
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xC, 0xF, false));
+  return v;
+}
+
 // Block-to-tile map. Blocks are dealt round-robin to the 8 XCDs (block b runs on XCD b % 8);
 // this map hands each XCD groups of kTileGroup consecutive tiles (a strip of one tile row), so a
 // splat record shared by neighbouring tiles is mostly fetched into one XCD's L2, while the groups
@@ -150,13 +162,14 @@ hipError_t launch_knn_pca(const float* xyz, int64_t n, int k, float kappa, float
 size_t knn_scratch_bytes(int64_t n);
 
 // ---- sparse estimator ---------------------------------------------------------------------------
-hipError_t launch_vox_keys(const float* xyz, int64_t n, uint64_t* keys, uint32_t* vals, hipStream_t s);
+hipError_t launch_vox_keys(const float* xyz, int64_t n, int grid, uint64_t* keys, uint32_t* vals,
+                           hipStream_t s);
 hipError_t launch_vox_flags(const uint64_t* keys, int64_t n, uint32_t* flag, hipStream_t s);
 hipError_t launch_vox_build(const uint64_t* keys, const uint32_t* order, const uint32_t* flag,
                             const uint32_t* excl, int64_t n, int64_t V, const float* xyz,
-                            const float* rgb, uint32_t* start, int32_t* coords, uint16_t* feat,
-                            int32_t* point_voxel, uint32_t* hkeys, int32_t* hvals, int log2cap,
-                            int32_t* nbr, hipStream_t s);
+                            const float* rgb, int grid, uint32_t* start, int32_t* coords,
+                            uint16_t* feat, int32_t* point_voxel, uint32_t* hkeys, int32_t* hvals,
+                            int log2cap, int32_t* nbr, hipStream_t s);
 bool conv_shape_supported(int cin, int cout);
 hipError_t launch_subm_conv(const uint16_t* x, int cin, const uint16_t* wt, const float* bias, int cout,
                             const int32_t* nbr, int64_t V, int relu, uint16_t* y, hipStream_t s);
@@ -169,12 +182,12 @@ hipError_t launch_subm_conv_dw(const uint16_t* x, int cin, const uint16_t* dy, i
 hipError_t launch_centroid(const float* xyz, int64_t n, double* sum, float* c, hipStream_t s);
 hipError_t launch_head_forward(const uint16_t* feat, const float* wh, const float* bh,
                                const int32_t* point_voxel, const float* xyz, const float* rgb,
-                               const float* centroid, int64_t n, float* quat, float* scale,
-                               float* opac, float* out_rgb, float* normal, hipStream_t s);
+                               const float* centroid, int64_t n, float voxel, float* quat,
+                               float* scale, float* opac, float* out_rgb, float* normal, hipStream_t s);
 hipError_t launch_head_backward(const uint16_t* feat, const float* wh, const float* bh,
                                 const uint32_t* order, const uint32_t* start, int64_t V, int64_t n,
-                                const float* d_quat, const float* d_scale, const float* d_opac,
-                                const float* d_rgb, uint16_t* d_feat, float* d_wh, float* d_bh,
-                                hipStream_t s);
+                                float voxel, const float* d_quat, const float* d_scale,
+                                const float* d_opac, const float* d_rgb, uint16_t* d_feat, float* d_wh,
+                                float* d_bh, hipStream_t s);
 
 }  // namespace pcs

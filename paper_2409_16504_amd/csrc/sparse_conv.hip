@@ -2,7 +2,8 @@
 // kernel map, submanifold 3x3x3 convolution on BF16 MFMA with FP32 accumulation (forward, data
 // gradient, weight gradient) and the per-voxel head with its activations.
 //
-//  * voxelise: the 10-bit grid coordinate of every point is a 30-bit key; a radix sort of
+//  * voxelise: the grid coordinate of every point (a grid of up to 1024^3 voxels over [-1,1]^3) is
+//    a 30-bit key; a radix sort of
 //    (key, point) groups the points of a voxel, a scan of key changes numbers the voxels in key
 //    order, one thread per voxel averages colour and coordinate residual; an open-addressing hash
 //    of the keys answers the 27 neighbour queries of every voxel (the kernel map).
@@ -47,15 +48,15 @@ __device__ __forceinline__ uint32_t hash_slot(uint32_t key, int log2cap) {
 }
 
 // ---- voxelisation -----------------------------------------------------------------------------
-__global__ void k_vox_key(const float* __restrict__ xyz, int64_t n, uint64_t* __restrict__ keys,
-                          uint32_t* __restrict__ vals) {
+__global__ void k_vox_key(const float* __restrict__ xyz, int64_t n, int grid,
+                          uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   uint32_t c[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const float g = floorf((xyz[a * n + i] + 1.0f) * 512.0f);
-    c[a] = (uint32_t)fminf(fmaxf(g, 0.0f), 1023.0f);
+    const float g = floorf((xyz[a * n + i] + 1.0f) * (0.5f * (float)grid));
+    c[a] = (uint32_t)fminf(fmaxf(g, 0.0f), (float)(grid - 1));
   }
   keys[i] = ((uint64_t)c[0] << 20) | ((uint64_t)c[1] << 10) | c[2];
   vals[i] = (uint32_t)i;
@@ -78,7 +79,7 @@ __global__ void k_vox_start(const uint32_t* __restrict__ flag, const uint32_t* _
 // rgb, residual, zero padding), point -> voxel map and hash insertion.
 __global__ void k_vox_reduce(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ order,
                              const uint32_t* __restrict__ start, int64_t V, int64_t n,
-                             const float* __restrict__ xyz, const float* __restrict__ rgb,
+                             const float* __restrict__ xyz, const float* __restrict__ rgb, int grid,
                              int32_t* __restrict__ coords, uint16_t* __restrict__ feat,
                              int32_t* __restrict__ point_voxel, uint32_t* __restrict__ hkeys,
                              int32_t* __restrict__ hvals, int log2cap) {
@@ -94,9 +95,10 @@ __global__ void k_vox_reduce(const uint64_t* __restrict__ keys, const uint32_t* 
     s[0] += rgb[i];
     s[1] += rgb[n + i];
     s[2] += rgb[2 * n + i];
-    s[3] += (xyz[i] + 1.0f) * 512.0f - ((float)cx + 0.5f);
-    s[4] += (xyz[n + i] + 1.0f) * 512.0f - ((float)cy + 0.5f);
-    s[5] += (xyz[2 * n + i] + 1.0f) * 512.0f - ((float)cz + 0.5f);
+    const float half = 0.5f * (float)grid;
+    s[3] += (xyz[i] + 1.0f) * half - ((float)cx + 0.5f);
+    s[4] += (xyz[n + i] + 1.0f) * half - ((float)cy + 0.5f);
+    s[5] += (xyz[2 * n + i] + 1.0f) * half - ((float)cz + 0.5f);
   }
   const float inv = 1.0f / (float)(e - b);
   coords[v] = cx;
@@ -130,7 +132,7 @@ __global__ void k_vox_reduce(const uint64_t* __restrict__ keys, const uint32_t* 
   }
 }
 
-__global__ void k_kernel_map(const int32_t* __restrict__ coords, int64_t V,
+__global__ void k_kernel_map(const int32_t* __restrict__ coords, int64_t V, int grid,
                              const uint32_t* __restrict__ hkeys, const int32_t* __restrict__ hvals,
                              int log2cap, int32_t* __restrict__ nbr) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -140,7 +142,7 @@ __global__ void k_kernel_map(const int32_t* __restrict__ coords, int64_t V,
   for (int k = 0; k < 27; ++k) {
     const int x = cx + (k / 9) - 1, y = cy + ((k / 3) % 3) - 1, z = cz + (k % 3) - 1;
     int32_t found = -1;
-    if (x >= 0 && x < 1024 && y >= 0 && y < 1024 && z >= 0 && z < 1024) {
+    if (x >= 0 && x < grid && y >= 0 && y < grid && z >= 0 && z < grid) {
       const uint32_t key = ((uint32_t)x << 20) | ((uint32_t)y << 10) | (uint32_t)z;
       uint32_t slot = hash_slot(key, log2cap);
       for (uint32_t probe = 0; probe <= mask; ++probe) {
@@ -337,14 +339,14 @@ __global__ __launch_bounds__(256) void k_subm_conv_dw(const uint16_t* __restrict
 
 // ---- head -------------------------------------------------------------------------------------
 constexpr int kHeadIn = 32, kHeadOut = 11;
-constexpr float kVoxelSize = 2.0f / 1024.0f;
 
 struct HeadOut {
   float scale[3], q[4], qn, opacity, drgb[3];
 };
 
 __device__ __forceinline__ void head_voxel(const uint16_t* __restrict__ f, const float* s_wh,
-                                           const float* s_bh, float raw[kHeadOut], HeadOut& h) {
+                                           const float* s_bh, float voxel, float raw[kHeadOut],
+                                           HeadOut& h) {
   float fv[kHeadIn];
   const uint4* src = reinterpret_cast<const uint4*>(f);
 #pragma unroll
@@ -365,7 +367,7 @@ __device__ __forceinline__ void head_voxel(const uint16_t* __restrict__ f, const
     raw[o] = a;
   }
 #pragma unroll
-  for (int a = 0; a < 3; ++a) h.scale[a] = kVoxelSize * __expf(raw[a]);
+  for (int a = 0; a < 3; ++a) h.scale[a] = voxel * __expf(raw[a]);
   const float q0 = raw[3] + 1.0f, q1 = raw[4], q2 = raw[5], q3 = raw[6];
   h.qn = sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
   const float iq = h.qn > 0.0f ? 1.0f / h.qn : 0.0f;
@@ -380,7 +382,7 @@ __device__ __forceinline__ void head_voxel(const uint16_t* __restrict__ f, const
 __global__ __launch_bounds__(256) void k_head_forward(
     const uint16_t* __restrict__ feat, const float* __restrict__ wh, const float* __restrict__ bh,
     const int32_t* __restrict__ point_voxel, const float* __restrict__ xyz,
-    const float* __restrict__ rgb, const float* __restrict__ centroid, int64_t n,
+    const float* __restrict__ rgb, const float* __restrict__ centroid, int64_t n, float voxel,
     float* __restrict__ quat, float* __restrict__ scale, float* __restrict__ opac,
     float* __restrict__ out_rgb, float* __restrict__ normal) {
   __shared__ float s_wh[kHeadOut * kHeadIn], s_bh[kHeadOut];
@@ -392,7 +394,7 @@ __global__ __launch_bounds__(256) void k_head_forward(
   const int32_t v = point_voxel[i];
   float raw[kHeadOut];
   HeadOut h;
-  head_voxel(feat + (int64_t)v * kHeadIn, s_wh, s_bh, raw, h);
+  head_voxel(feat + (int64_t)v * kHeadIn, s_wh, s_bh, voxel, raw, h);
 #pragma unroll
   for (int a = 0; a < 4; ++a) quat[a * n + i] = h.q[a];
 #pragma unroll
@@ -419,7 +421,7 @@ __global__ __launch_bounds__(256) void k_head_forward(
 __global__ __launch_bounds__(256) void k_head_backward(
     const uint16_t* __restrict__ feat, const float* __restrict__ wh, const float* __restrict__ bh,
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ start, int64_t V, int64_t n,
-    const float* __restrict__ d_quat, const float* __restrict__ d_scale,
+    float voxel, const float* __restrict__ d_quat, const float* __restrict__ d_scale,
     const float* __restrict__ d_opac, const float* __restrict__ d_rgb, uint16_t* __restrict__ d_feat,
     float* __restrict__ d_wh, float* __restrict__ d_bh) {
   __shared__ float s_wh[kHeadOut * kHeadIn], s_bh[kHeadOut];
@@ -431,7 +433,7 @@ __global__ __launch_bounds__(256) void k_head_backward(
   if (v < V) {
     float raw[kHeadOut];
     HeadOut h;
-    head_voxel(feat + v * kHeadIn, s_wh, s_bh, raw, h);
+    head_voxel(feat + v * kHeadIn, s_wh, s_bh, voxel, raw, h);
     float gq[4] = {0.f, 0.f, 0.f, 0.f}, gs[3] = {0.f, 0.f, 0.f}, go = 0.f, gc[3] = {0.f, 0.f, 0.f};
     const uint32_t b = start[v], e = (v + 1 < V) ? start[v + 1] : (uint32_t)n;
     for (uint32_t j = b; j < e; ++j) {
@@ -502,8 +504,9 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
 }  // namespace
 
 // ---- host launchers -----------------------------------------------------------------------------
-hipError_t launch_vox_keys(const float* xyz, int64_t n, uint64_t* keys, uint32_t* vals, hipStream_t s) {
-  hipLaunchKernelGGL(k_vox_key, dim3(blocks_for(n, 256)), dim3(256), 0, s, xyz, n, keys, vals);
+hipError_t launch_vox_keys(const float* xyz, int64_t n, int grid, uint64_t* keys, uint32_t* vals,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_vox_key, dim3(blocks_for(n, 256)), dim3(256), 0, s, xyz, n, grid, keys, vals);
   return hipGetLastError();
 }
 
@@ -514,16 +517,16 @@ hipError_t launch_vox_flags(const uint64_t* keys, int64_t n, uint32_t* flag, hip
 
 hipError_t launch_vox_build(const uint64_t* keys, const uint32_t* order, const uint32_t* flag,
                             const uint32_t* excl, int64_t n, int64_t V, const float* xyz,
-                            const float* rgb, uint32_t* start, int32_t* coords, uint16_t* feat,
-                            int32_t* point_voxel, uint32_t* hkeys, int32_t* hvals, int log2cap,
-                            int32_t* nbr, hipStream_t s) {
+                            const float* rgb, int grid, uint32_t* start, int32_t* coords,
+                            uint16_t* feat, int32_t* point_voxel, uint32_t* hkeys, int32_t* hvals,
+                            int log2cap, int32_t* nbr, hipStream_t s) {
   hipError_t e = launch_fill_u32(hkeys, kEmptyKey, int64_t(1) << log2cap, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_vox_start, dim3(blocks_for(n, 256)), dim3(256), 0, s, flag, excl, n, start);
   hipLaunchKernelGGL(k_vox_reduce, dim3(blocks_for(V, 256)), dim3(256), 0, s, keys, order, start, V, n,
-                     xyz, rgb, coords, feat, point_voxel, hkeys, hvals, log2cap);
-  hipLaunchKernelGGL(k_kernel_map, dim3(blocks_for(V, 256)), dim3(256), 0, s, coords, V, hkeys, hvals,
-                     log2cap, nbr);
+                     xyz, rgb, grid, coords, feat, point_voxel, hkeys, hvals, log2cap);
+  hipLaunchKernelGGL(k_kernel_map, dim3(blocks_for(V, 256)), dim3(256), 0, s, coords, V, grid, hkeys,
+                     hvals, log2cap, nbr);
   return hipGetLastError();
 }
 
@@ -588,22 +591,22 @@ hipError_t launch_centroid(const float* xyz, int64_t n, double* sum, float* c, h
 
 hipError_t launch_head_forward(const uint16_t* feat, const float* wh, const float* bh,
                                const int32_t* point_voxel, const float* xyz, const float* rgb,
-                               const float* centroid, int64_t n, float* quat, float* scale,
+                               const float* centroid, int64_t n, float voxel, float* quat, float* scale,
                                float* opac, float* out_rgb, float* normal, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_head_forward, dim3(blocks_for(n, 256)), dim3(256), 0, s, feat, wh, bh, point_voxel,
-                     xyz, rgb, centroid, n, quat, scale, opac, out_rgb, normal);
+                     xyz, rgb, centroid, n, voxel, quat, scale, opac, out_rgb, normal);
   return hipGetLastError();
 }
 
 hipError_t launch_head_backward(const uint16_t* feat, const float* wh, const float* bh,
                                 const uint32_t* order, const uint32_t* start, int64_t V, int64_t n,
-                                const float* d_quat, const float* d_scale, const float* d_opac,
-                                const float* d_rgb, uint16_t* d_feat, float* d_wh, float* d_bh,
-                                hipStream_t s) {
+                                float voxel, const float* d_quat, const float* d_scale,
+                                const float* d_opac, const float* d_rgb, uint16_t* d_feat, float* d_wh,
+                                float* d_bh, hipStream_t s) {
   if (V == 0) return hipSuccess;
   hipLaunchKernelGGL(k_head_backward, dim3(blocks_for(V, 256)), dim3(256), 0, s, feat, wh, bh, order, start,
-                     V, n, d_quat, d_scale, d_opac, d_rgb, d_feat, d_wh, d_bh);
+                     V, n, voxel, d_quat, d_scale, d_opac, d_rgb, d_feat, d_wh, d_bh);
   return hipGetLastError();
 }
 

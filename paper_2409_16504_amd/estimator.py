@@ -35,7 +35,7 @@ class _DevArray:
     """Zero-copy view of a library-owned device array (``__cuda_array_interface__``)."""
 
     def __init__(self, ptr: int, shape, typestr: str):
-        self.__cuda_array_interface__ = dict(shape=tuple(shape), typestr=typestr, data=(ptr, True),
+        self.__cuda_array_interface__ = dict(shape=tuple(shape), typestr=typestr, data=(ptr, False),
                                              version=2, strides=None)
 
 
@@ -49,13 +49,31 @@ class Voxels:
         self.V = 0
         self.n = 0
 
-    def build(self, xyz: torch.Tensor, rgb: torch.Tensor) -> "Voxels":
+    def build(self, xyz: torch.Tensor, rgb: torch.Tensor, grid: int = 1024) -> "Voxels":
         n = xyz.shape[1]
         V = ctypes.c_int64()
-        check(_lib.load().pcs_voxelize(self.renderer.ctx, _p(xyz), _p(rgb), n, self.handle, ctypes.byref(V), _s()))
-        self.V, self.n = int(V.value), n
+        check(_lib.load().pcs_voxelize(self.renderer.ctx, _p(xyz), _p(rgb), n, int(grid), self.handle,
+                                       ctypes.byref(V), _s()))
+        self.V, self.n, self.grid = int(V.value), n, int(grid)
         self.xyz, self.rgb = xyz, rgb
         return self
+
+    def mean_neighbours(self) -> float:
+        """Mean number of occupied voxels among the 26 around each voxel."""
+        nbr = self.arrays()["nbr"]
+        return float((nbr >= 0).sum(dim=0).float().mean().item()) - 1.0
+
+
+def adaptive_grid(R: Renderer, xyz: torch.Tensor, rgb: torch.Tensor, target: float = 6.0) -> Voxels:
+    """Density-adaptive voxel size (Section 3.2 scales the cloud to about one point per voxel so
+    that voxelisation keeps neighbouring points in neighbouring voxels): the finest power-of-two
+    grid, at most 1024^3, whose voxels have on average at least ``target`` occupied neighbours."""
+    vox = None
+    for grid in (1024, 512, 256, 128, 64):
+        vox = Voxels(R).build(xyz, rgb, grid)
+        if vox.mean_neighbours() >= target:
+            return vox
+    return vox
 
     def arrays(self) -> dict:
         """Zero-copy tensors: coords (3,V) int32, nbr (27,V) int32, point_voxel (n,) int32,

@@ -25,7 +25,7 @@ from synthetic import look_at_camera  # noqa: E402
 from synthetic.scenes import ProceduralSurface  # noqa: E402
 
 from . import Renderer, default_options  # noqa: E402
-from .estimator import SparseEstimator, Voxels, psnr  # noqa: E402
+from .estimator import SparseEstimator, Voxels, adaptive_grid, psnr  # noqa: E402
 
 
 def main(argv=None):
@@ -64,6 +64,7 @@ def main(argv=None):
         for p_, v in zip(est.params, ck["params"]):
             p_.copy_(v.to(dev))
     opts = default_options()
+    grid = adaptive_grid(R, frames[0]["xyz"], frames[0]["rgb"]).grid   # the density is the sequence's
     vox = Voxels(R)
     out = R.render(dict(mean=frames[0]["xyz"], quat=torch.zeros((4, args.points), device=dev),
                         scale=torch.full((3, args.points), 0.002, device=dev),
@@ -71,7 +72,7 @@ def main(argv=None):
                         normal=torch.zeros((3, args.points), device=dev)), cams, opts)
 
     def learned(f):
-        vox.build(f["xyz"], f["rgb"])
+        vox.build(f["xyz"], f["rgb"], grid)
         return est.forward(vox)
 
     def plain(f):

@@ -31,7 +31,7 @@ from synthetic import orbit_cameras  # noqa: E402
 from synthetic.scenes import ProceduralSurface, quantize_10bit  # noqa: E402
 
 from . import Renderer, default_options  # noqa: E402
-from .estimator import Adam, SparseEstimator, Voxels, psnr, train_step  # noqa: E402
+from .estimator import Adam, SparseEstimator, adaptive_grid, psnr, train_step  # noqa: E402
 
 
 def make_cloud(R: Renderer, seed: int, n: int, dense_factor: int = 8, gt_kappa: float = 1.0) -> dict:
@@ -50,7 +50,7 @@ def make_cloud(R: Renderer, seed: int, n: int, dense_factor: int = 8, gt_kappa: 
     dense = dict(mean=xd, quat=est["quat"], scale=est["scale"],
                  opacity=torch.full((xd.shape[1],), 0.9, device=dev),
                  rgb=torch.from_numpy(np.ascontiguousarray(rgbd, np.float32)).to(dev), normal=est["normal"])
-    return dict(seed=seed, xyz=xyz, rgb=col, dense=dense, vox=Voxels(R).build(xyz, col))
+    return dict(seed=seed, xyz=xyz, rgb=col, dense=dense, vox=adaptive_grid(R, xyz, col))
 
 
 def knn_gaussians(R: Renderer, c: dict, kappa: float) -> dict:
@@ -93,7 +93,7 @@ def main(argv=None):
     train = [make_cloud(R, 10040 + i, args.points) for i in range(args.train_clouds)]
     held = [make_cloud(R, 2000 + i, args.points) for i in range(args.eval_clouds)]
     print(f"[train] clouds ready in {time.time() - t0:.1f}s; voxels per cloud "
-          f"{[c['vox'].V for c in train]}", flush=True)
+          f"{[c['vox'].V for c in train]} on grids {[c['vox'].grid for c in train]}", flush=True)
 
     # kappa of the plain path, chosen by PSNR on the training clouds
     sel_cams = orbit_cameras(args.views, np.random.default_rng(7), width=args.res, height=args.res)
@@ -150,18 +150,19 @@ def main(argv=None):
 
     # estimator inference time per cloud (voxelise + 8 convolutions + head)
     c = held[0]
+    vox = c["vox"]
     for _ in range(2):
-        est.forward(Voxels(R).build(c["xyz"], c["rgb"]))
+        est.forward(vox.build(c["xyz"], c["rgb"], vox.grid))
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     reps = 10
     for _ in range(reps):
-        est.forward(Voxels(R).build(c["xyz"], c["rgb"]))
+        est.forward(vox.build(c["xyz"], c["rgb"], vox.grid))
     torch.cuda.synchronize()
     infer_ms = (time.perf_counter() - t2) * 1e3 / reps
     report = dict(steps=args.steps, train_seconds=train_s, ms_per_step=train_s * 1e3 / max(1, args.steps),
                   clouds_per_step=len(train), views=args.views, res=args.res, points=args.points,
-                  voxels=[c["vox"].V for c in train], kappa=kappa, kappa_scores=scores, before=before,
+                  voxels=[c["vox"].V for c in train], grids=[c["vox"].grid for c in train], kappa=kappa, kappa_scores=scores, before=before,
                   after=after, loss_first=losses[0] if losses else None, loss_last=losses[-1] if losses else None,
                   inference_ms_per_cloud=infer_ms)
     print(json.dumps(report), flush=True)

@@ -14,6 +14,7 @@ from oracle import estimator as E
 from synthetic import make_surface
 
 pytestmark = pytest.mark.gpu
+GRID = 128
 
 
 @pytest.fixture(scope="module")
@@ -35,8 +36,9 @@ def cloud(R):
     _, p, rgb = make_surface(40000, 21, quantize=False)
     p = p + rng.normal(0, 0.001, p.shape).astype(np.float32)
     p = np.clip(p, -0.999, 0.999).astype(np.float32)
-    vox = Voxels(R).build(torch.from_numpy(p).cuda(), torch.from_numpy(rgb).cuda())
-    ref = E.voxelize(p, rgb)
+    # 40k surface points: the 128^3 grid keeps neighbouring samples in neighbouring voxels
+    vox = Voxels(R).build(torch.from_numpy(p).cuda(), torch.from_numpy(rgb).cuda(), GRID)
+    ref = E.voxelize(p, rgb, GRID)
     return p, rgb, vox, ref
 
 
@@ -46,20 +48,47 @@ def test_voxelize_and_kernel_map(cloud):
     assert vox.V == ref["coords"].shape[0]
     assert np.array_equal(arr["coords"].cpu().numpy().T, ref["coords"])
     assert np.array_equal(arr["point_voxel"].cpu().numpy(), ref["point_voxel"])
-    nbr_ref = E.kernel_map(ref["coords"])
+    nbr_ref = E.kernel_map(ref["coords"], GRID)
     assert np.array_equal(arr["nbr"].cpu().numpy(), nbr_ref)
     f = arr["features"].to(torch.float64).cpu().numpy()
     want = np.concatenate([ref["color"], ref["residual"]], axis=1)
-    assert np.all(np.abs(f[:, :6] - want) <= 2.0 ** -8 * np.abs(want) + 1e-6)
+    # BF16 rounding of the mean (2^-9 relative) plus, for the residual (p + 1) * G/2 - (c + 0.5),
+    # the FP32 rounding of p + 1 amplified by G/2 (at most 2^-23 * 512 = 6.1e-5 per point)
+    absolute = np.array([1e-6] * 3 + [1.5e-4] * 3)
+    assert np.all(np.abs(f[:, :6] - want) <= 2.0 ** -8 * np.abs(want) + absolute)
     assert np.all(f[:, 6:] == 0)
     assert (nbr_ref >= 0).sum(axis=0).mean() > 3          # neighbours exist (surface connectivity)
+
+
+def test_voxelize_grids_and_adaptive_choice(R):
+    """Every power-of-two grid voxelises bit-exactly; the adaptive choice is the finest grid whose
+    voxels have at least six occupied neighbours on average."""
+    from paper_2409_16504_amd.estimator import Voxels, adaptive_grid
+    _, p, rgb = make_surface(20000, 33, quantize=True)
+    tp, tr = torch.from_numpy(p).cuda(), torch.from_numpy(rgb).cuda()
+    means = {}
+    for g in (1024, 512, 256, 128, 64, 2):
+        vox = Voxels(R).build(tp, tr, g)
+        ref = E.voxelize(p, rgb, g)
+        arr = vox.arrays()
+        assert np.array_equal(arr["coords"].cpu().numpy().T, ref["coords"]), g
+        assert np.array_equal(arr["point_voxel"].cpu().numpy(), ref["point_voxel"]), g
+        nb = E.kernel_map(ref["coords"], g)
+        assert np.array_equal(arr["nbr"].cpu().numpy(), nb), g
+        means[g] = (nb >= 0).sum(axis=0).mean() - 1
+        assert abs(vox.mean_neighbours() - means[g]) < 1e-6
+    chosen = adaptive_grid(R, tp, tr)
+    want = next((g for g in (1024, 512, 256, 128, 64) if means[g] >= 6.0), 64)
+    assert chosen.grid == want
+    with pytest.raises(RuntimeError):
+        Voxels(R).build(tp, tr, 100)
 
 
 @pytest.mark.parametrize("cin,cout", [(32, 32), (32, 64), (64, 64), (64, 32)])
 def test_conv_forward_and_adjoint(R, cloud, cin, cout):
     from paper_2409_16504_amd.estimator import conv_backward, conv_forward
     _, _, vox, ref = cloud
-    nbr = E.kernel_map(ref["coords"])
+    nbr = E.kernel_map(ref["coords"], GRID)
     rng = np.random.default_rng(cin * 100 + cout)
     V = vox.V
     x64, xt = bf16_round(rng.normal(size=(V, cin)))
@@ -105,7 +134,7 @@ def test_head_forward_and_adjoint(R, cloud):
     bh = (rng.normal(size=11) * 0.1).astype(np.float32)
     tp, tr = torch.from_numpy(p).cuda(), torch.from_numpy(rgb).cuda()
     g = head_forward(R, vox, ft.cuda(), torch.from_numpy(wh).cuda(), torch.from_numpy(bh).cuda(), tp, tr)
-    out = E.head(f64, wh.T.astype(np.float64), bh.astype(np.float64), rgb, p, ref["point_voxel"])
+    out = E.head(f64, wh.T.astype(np.float64), bh.astype(np.float64), rgb, p, ref["point_voxel"], GRID)
     for k in ("quat", "scale", "opacity", "rgb"):
         a = g[k].cpu().numpy()
         assert np.allclose(a, out[k], rtol=1e-5, atol=1e-5), k
@@ -122,7 +151,7 @@ def test_head_forward_and_adjoint(R, cloud):
     F = torch.from_numpy(f64).requires_grad_(True)
     Wh = torch.from_numpy(wh.T.astype(np.float64)).requires_grad_(True)
     Bh = torch.from_numpy(bh.astype(np.float64)).requires_grad_(True)
-    q, sc, o, c = E.head_torch(F, Wh, Bh, torch.from_numpy(rgb.astype(np.float64)), ref["point_voxel"])
+    q, sc, o, c = E.head_torch(F, Wh, Bh, torch.from_numpy(rgb.astype(np.float64)), ref["point_voxel"], GRID)
     L = (q * up["quat"].double()).sum() + (sc * up["scale"].double()).sum() + (o * up["opacity"].double()).sum() + \
         (c * up["rgb"].double()).sum()
     L.backward()
@@ -139,13 +168,13 @@ def test_estimator_forward_error_vs_fp64(R, cloud):
     p, rgb, vox, ref = cloud
     est = SparseEstimator(R, seed=3)
     g = est.forward(vox)
-    nbr = E.kernel_map(ref["coords"])
+    nbr = E.kernel_map(ref["coords"], GRID)
     x = vox.arrays()["features"].to(torch.float64).cpu().numpy()
     for li in range(len(LAYERS)):
         W = est.w[li].to(torch.bfloat16).to(torch.float64).cpu().numpy().transpose(0, 2, 1)
         x = E.subm_conv(x, W, est.b[li].cpu().numpy().astype(np.float64), nbr, relu=True)
     out = E.head(x, est.wh.cpu().numpy().T.astype(np.float64), est.bh.cpu().numpy().astype(np.float64), rgb, p,
-                 ref["point_voxel"])
+                 ref["point_voxel"], GRID)
     rel_s = np.abs(g["scale"].cpu().numpy() / out["scale"] - 1)
     ang = 2 * np.degrees(np.arccos(np.clip(np.abs(np.einsum("kn,kn->n", g["quat"].cpu().numpy(), out["quat"])), 0, 1)))
     do = np.abs(g["opacity"].cpu().numpy() - out["opacity"])

@@ -1,6 +1,7 @@
 """Pins of the oracle's estimator steps: voxelisation, kernel map, submanifold convolution (equal to
 a dense masked conv3d, a library routine) and the head's activations."""
 import numpy as np
+import pytest
 import torch
 
 from oracle import estimator as E
@@ -23,7 +24,7 @@ def test_voxelize_lattice_points():
 
 def test_voxelize_residuals_unquantized():
     rng = np.random.default_rng(0)
-    p = rng.uniform(-0.99, 0.99, (3, 500))
+    p = rng.uniform(-0.99, 0.99, (3, 500)).astype(np.float32).astype(np.float64)
     v = E.voxelize(p, rng.uniform(0, 1, (3, 500)))
     c = v["coords"][v["point_voxel"]]
     r = (p.T + 1) * 512 - (c + 0.5)
@@ -136,3 +137,32 @@ def test_head_torch_matches_head():
                               torch.from_numpy(col), pv)
     assert np.allclose(q.numpy(), ref["quat"]) and np.allclose(s.numpy(), ref["scale"])
     assert np.allclose(o.numpy(), ref["opacity"]) and np.allclose(c.numpy(), ref["rgb"])
+
+
+def test_voxelize_coarse_grid_lattice():
+    """On a G^3 grid the centres (c + 0.5) * 2/G - 1 voxelise to c with zero residual; every
+    power of two G works and other sizes are refused."""
+    rng = np.random.default_rng(5)
+    for g in (2, 64, 256):
+        c = np.unique(rng.integers(0, g, (400, 3)), axis=0)
+        p = ((c + 0.5) * (2.0 / g) - 1.0).T.astype(np.float32)
+        v = E.voxelize(p, rng.uniform(0, 1, p.shape), g)
+        assert np.array_equal(v["coords"], c)                  # unique keys ascend like np.unique rows
+        assert np.all(np.abs(v["residual"]) < 1e-6)
+        nb = E.kernel_map(v["coords"], g)
+        lo = np.all(c == 0, axis=1)
+        assert np.all(nb[0, lo] == -1)                          # offset (-1,-1,-1) leaves the grid
+    for bad in (0, 100, 2048):
+        with pytest.raises(ValueError):
+            E.voxelize(np.zeros((3, 1), np.float32), np.zeros((3, 1)), bad)
+
+
+def test_voxel_decision_on_fp32_sum():
+    """The floor is taken on the FP32 value of p + 1: a coordinate whose FP64 sum lies just below a
+    voxel boundary but rounds onto it in FP32 belongs to the upper voxel."""
+    b = np.float32(0.25)                                        # boundary k/512 - 1 for k = 640
+    below = np.nextafter(b, np.float32(-1))                     # FP32 just below the boundary
+    # below + 1 in FP64 is 1.25 - 2^-26, which rounds to 1.25 in FP32 (ulp 2^-23 at 1.25)
+    assert np.float64(below) + 1.0 < 1.25 and np.float32(below) + np.float32(1) == np.float32(1.25)
+    v = E.voxelize(np.array([[below], [0.0], [0.0]], np.float32), np.zeros((3, 1)), 1024)
+    assert v["coords"][0, 0] == 640
