@@ -33,7 +33,7 @@ FP32_VALU_PEAK_TFLOPS = 78.6     # 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 G
 PROJECT_READ_B = 68      # mean 12 + quat 16 + scale 12 + opacity 4 + rgb 12 + normal 12
 PROJECT_WRITE_VIS_B = 84  # 64 B splat record + 16 B binning meta + 4 B count
 PROJECT_WRITE_CULL_B = 4
-SORT_PASS_B = 24         # read + write of an 8 B key and a 4 B value
+SORT_PASS_B = 16         # read + write of a 4 B key and a 4 B value
 # Compositing FLOP per (pixel, list entry) visit and per blended splat.
 COMPOSITE_VISIT_FLOP = 9     # offset (2), conic quadratic form (7)
 COMPOSITE_BLEND_FLOP = 21    # -q/2, exp, o*e, w = a*T, 7 fused multiply-adds (14), 1 - a, T update
@@ -85,10 +85,11 @@ def main():
     knn_ms = R.timings()["knn_pca"][0] / 3.0
 
     if args.copy_calibration_mib:
-        src = torch.empty(args.copy_calibration_mib << 20, dtype=torch.uint8, device=dev).fill_(1)
+        # a plain elementwise kernel (negation) that reads and writes the stated size once
+        src = torch.ones((args.copy_calibration_mib << 20) // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        torch.neg(src, out=dst)
         torch.cuda.synchronize()
         print(f"[bench] copy calibration: {args.copy_calibration_mib} MiB read + written", file=sys.stderr,
               flush=True)
@@ -114,7 +115,8 @@ def main():
     R.render(g, cams, opts, state=st)
     bins = R.bins(st)
     m = int(bins["keys"].size)
-    per_stage = {k: v[0] / max(1, v[1]) for k, v in stages.items() if v[1] > 0}
+    # per frame: a stage may run as several timed sections (the sort runs twice per frame)
+    per_stage = {k: v[0] / args.steps for k, v in stages.items() if v[1] > 0}
 
     cpu = None
     visits = blends = None
@@ -197,6 +199,32 @@ def extra_workloads(R):
     return dict(many_cameras=many, estimator=estimator)
 
 
+# Kernel source each stage's dominant kernel is built from (a counter summary applies only while
+# this file is unchanged).
+STAGE_SOURCE = {"composite": "composite.hip", "project": "project.hip", "scan": "scan_sort.hip",
+                "binning": "scan_sort.hip", "sort": "scan_sort.hip", "ranges": "scan_sort.hip"}
+
+
+def measured_traffic(stage):
+    """HBM bytes per launch of the stage's kernel from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE scaled by a plain copy kernel's counters), or None when there is no
+    summary or the kernel source has changed since it was taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"{stage}_1M_1080p_hbm_traffic.md")
+    src = os.path.join(ROOT, "paper_2409_16504_amd", "csrc", STAGE_SOURCE.get(stage, ""))
+    if not os.path.exists(path) or not os.path.isfile(src):
+        return None
+    text = open(path).read()
+    h = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not h or not b:
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != h.group(1):
+        return None
+    return float(b.group(1))
+
+
 def roofline(per_stage, n, m, bins, visits, blends):
     """Roofline entry of the stage that dominates the frame, from algorithmic work per launch."""
     frame = {k: v for k, v in per_stage.items() if k in ("project", "scan", "binning", "sort", "ranges", "composite")}
@@ -206,13 +234,14 @@ def roofline(per_stage, n, m, bins, visits, blends):
         flop = COMPOSITE_VISIT_FLOP * visits + COMPOSITE_BLEND_FLOP * blends
         ach = flop / (ms * 1e-3) / 1e12
         return dict(kernel=dom, bound="alu", achieved=ach, peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=ach / FP32_VALU_PEAK_TFLOPS, traffic=None, avg_ms=ms)
+                    frac=ach / FP32_VALU_PEAK_TFLOPS, traffic=measured_traffic(dom), avg_ms=ms)
     if dom == "sort":
+        # depth sort of the n splats (u32 keys) then tile sort of the m instances (u32 keys): one
+        # histogram read of the keys, then per pass a read and a write of key and value
         z = (bins["keys"] & np.uint64(0xFFFFFFFF)).astype(np.int64)
         depth_bits = int(z.max() - z.min()).bit_length() if m else 0
         tile_bits = int(bins["ranges"].shape[1] - 1).bit_length()
-        n_pass = (depth_bits + tile_bits + 7) // 8
-        byts = m * (8 + SORT_PASS_B * n_pass)     # one histogram read of the keys, then the passes
+        byts = n * (4 + SORT_PASS_B * ((depth_bits + 7) // 8)) + m * (4 + SORT_PASS_B * ((tile_bits + 7) // 8))
     elif dom == "project":
         vis = int(np.unique(bins["vals"]).size)
         byts = n * PROJECT_READ_B + vis * PROJECT_WRITE_VIS_B + (n - vis) * PROJECT_WRITE_CULL_B
@@ -222,7 +251,7 @@ def roofline(per_stage, n, m, bins, visits, blends):
         byts = m * 8
     ach = byts / (ms * 1e-3) / 1e9
     return dict(kernel=dom, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
-                traffic=None, avg_ms=ms)
+                traffic=measured_traffic(dom), avg_ms=ms)
 
 
 def cpu_baseline(xyz, rgb, cams):

@@ -95,8 +95,9 @@ struct pcs_state;
 struct pcs_context {
   int device = 0;
   DevBuf counts, offsets, meta, keys_alt, vals_alt, scan_scratch, sort_scratch, sgrad, small;
+  DevBuf dkeys, dkeys_alt, dvals, dvals_alt;   // depth sort of the (camera, Gaussian) splats
   DevBuf knn_scratch, conv_tmp, wt_tmp;
-  uint32_t* host_small = nullptr;   // pinned 1 KiB: readback of the small device words
+  uint32_t* host_small = nullptr;   // pinned 4 KiB: readback of the small device words
   pcs_state* internal = nullptr;    // state used when the caller passes none
   bool timing = false;
   struct Ev {
@@ -111,7 +112,7 @@ struct pcs_context {
 
 struct pcs_state {
   pcs_context* ctx = nullptr;
-  DevBuf rec, keys, vals, ranges, t_final, n_contrib, canon, dcams;
+  DevBuf rec, keys, vals, ranges, t_final, n_contrib, canon, dcams;   // keys: u32 global tile ids
   pcs_gaussians g{};
   std::vector<pcs_camera> cams;
   pcs_options opt{};
@@ -222,7 +223,7 @@ int pcs_context_create(int device, pcs_context** out) {
   pcs_context* ctx = new pcs_context();
   ctx->device = device;
   void* hp = nullptr;
-  if (hipHostMalloc(&hp, 1024, hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc(&hp, 4096, hipHostMallocDefault) != hipSuccess) {
     delete ctx;
     return fail(PCS_ERR_OOM, "pinned host allocation failed");
   }
@@ -304,7 +305,7 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   if (total_tiles >= (int64_t(1) << 31)) return fail(PCS_ERR_UNSUPPORTED, "cameras x tiles must be below 2^31");
   const int64_t n = g->n;
   const int64_t cn = n * n_cams;
-  if (cn >= (int64_t(1) << 34)) return fail(PCS_ERR_UNSUPPORTED, "n x cameras too large");
+  if (cn >= (int64_t(1) << 32)) return fail(PCS_ERR_UNSUPPORTED, "n x cameras must be below 2^32");
   PCS_HIP(hipSetDevice(ctx->device));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 
@@ -324,10 +325,11 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   PCS_HIP(hipMemcpyAsync(st->dcams.p, dc.data(), sizeof(DevCamera) * n_cams, hipMemcpyHostToDevice, s));
   const DevOptions dopt = to_dev(*opt);
 
-  PCS_TRY(ensure(st->rec, std::max<int64_t>(cn, 1) * kRecFloat4 * sizeof(float4), "splat records"));
-  PCS_TRY(ensure(ctx->meta, std::max<int64_t>(cn, 1) * sizeof(uint4), "binning meta"));
-  PCS_TRY(ensure(ctx->counts, std::max<int64_t>(cn, 1) * sizeof(uint32_t) + 64, "counts"));
-  PCS_TRY(ensure(ctx->offsets, std::max<int64_t>(cn, 1) * sizeof(uint32_t) + 64, "offsets"));
+  const int64_t cn1 = std::max<int64_t>(cn, 1);
+  PCS_TRY(ensure(st->rec, cn1 * kRecFloat4 * sizeof(float4), "splat records"));
+  PCS_TRY(ensure(ctx->meta, cn1 * sizeof(uint4), "binning meta"));
+  PCS_TRY(ensure(ctx->counts, cn1 * sizeof(uint32_t) + 64, "counts"));
+  PCS_TRY(ensure(ctx->offsets, cn1 * sizeof(uint32_t) + 64, "offsets"));
   PCS_TRY(ensure(ctx->scan_scratch, scan_scratch_bytes(cn), "scan scratch"));
   PCS_TRY(ensure(ctx->small, kSmallWords * 4, "small"));
   PCS_TRY(ensure(st->ranges, 2 * total_tiles * sizeof(uint32_t), "tile ranges"));
@@ -337,51 +339,79 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
 
   uint64_t* d_total = ctx->small.as<uint64_t>();
   uint32_t* d_zrange = ctx->small.as<uint32_t>() + 2;
+  auto* d_counts = reinterpret_cast<unsigned long long*>(ctx->small.as<uint32_t>() + kCountWord);
   PCS_HIP(launch_init_small(ctx->small.as<uint32_t>(), s));
   {
     StageTimer tm(ctx, ST_PROJECT, s);
     PCS_HIP(launch_project(n, n_cams, st->dcams.as<DevCamera>(), dopt, *g, st->rec.as<float4>(),
-                           ctx->meta.as<uint4>(), ctx->counts.as<uint32_t>(), d_zrange, s));
-  }
-  {
-    StageTimer tm(ctx, ST_SCAN, s);
-    PCS_HIP(launch_scan(ctx->counts.as<uint32_t>(), ctx->offsets.as<uint32_t>(), cn, d_total,
-                        ctx->scan_scratch.p, s));
+                           ctx->meta.as<uint4>(), ctx->counts.as<uint32_t>(), d_zrange, d_counts, s));
   }
   PCS_HIP(hipMemcpyAsync(ctx->host_small, ctx->small.p, kSmallWords * 4, hipMemcpyDeviceToHost, s));
   PCS_HIP(hipStreamSynchronize(s));
-  uint64_t m64;
-  std::memcpy(&m64, ctx->host_small, 8);
   uint32_t zmin = 0xFFFFFFFFu, zmax = 0u;
+  uint64_t m64 = 0;
   for (int i = 0; i < kZSlots; ++i) {
     zmin = std::min(zmin, ctx->host_small[2 + i]);
     zmax = std::max(zmax, ctx->host_small[2 + kZSlots + i]);
+    uint64_t c;
+    std::memcpy(&c, ctx->host_small + kCountWord + 2 * i, 8);
+    m64 += c;
   }
   if (m64 >= (uint64_t(1) << 30))
     return fail(PCS_ERR_UNSUPPORTED, "instance count " + std::to_string(m64) + " is not below 2^30");
   const int64_t m = (int64_t)m64;
   const int depth_bits = m > 0 ? bit_length((uint64_t)(zmax - zmin)) : 0;
+  const int cam_bits = bit_length((uint64_t)(n_cams - 1));
+  const int dsort_bits = depth_bits + cam_bits;
   const int tile_bits = bit_length((uint64_t)(total_tiles - 1));
-  const int bits = depth_bits + tile_bits;
 
-  PCS_TRY(ensure(st->keys, std::max<int64_t>(m, 1) * sizeof(uint64_t), "keys"));
+  PCS_TRY(ensure(st->keys, std::max<int64_t>(m, 1) * sizeof(uint32_t), "keys"));
   PCS_TRY(ensure(st->vals, std::max<int64_t>(m, 1) * sizeof(uint32_t), "values"));
-  PCS_TRY(ensure(ctx->keys_alt, std::max<int64_t>(m, 1) * sizeof(uint64_t), "keys (alternate)"));
+  PCS_TRY(ensure(ctx->keys_alt, std::max<int64_t>(m, 1) * sizeof(uint32_t), "keys (alternate)"));
   PCS_TRY(ensure(ctx->vals_alt, std::max<int64_t>(m, 1) * sizeof(uint32_t), "values (alternate)"));
-  PCS_TRY(ensure(ctx->sort_scratch, sort_scratch_bytes(m), "sort scratch"));
+  PCS_TRY(ensure(ctx->sort_scratch, sort_scratch_bytes(std::max(m, cn)), "sort scratch"));
+  const size_t dkey_bytes = dsort_bits > 32 ? sizeof(uint64_t) : sizeof(uint32_t);
+  PCS_TRY(ensure(ctx->dkeys, cn1 * dkey_bytes, "depth keys"));
+  PCS_TRY(ensure(ctx->dkeys_alt, cn1 * dkey_bytes, "depth keys (alternate)"));
+  PCS_TRY(ensure(ctx->dvals, cn1 * sizeof(uint32_t), "depth order"));
+  PCS_TRY(ensure(ctx->dvals_alt, cn1 * sizeof(uint32_t), "depth order (alternate)"));
   if (m > 0) {
+    // (camera, depth) order of the splats
+    const uint32_t* order = nullptr;
+    {
+      StageTimer tm(ctx, ST_SORT, s);
+      bool in_alt = false;
+      if (dsort_bits > 32) {
+        PCS_HIP(launch_depth_keys(n, n_cams, ctx->meta.as<uint4>(), ctx->counts.as<uint32_t>(), zmin,
+                                  depth_bits, ctx->dkeys.as<uint64_t>(), ctx->dvals.as<uint32_t>(), s));
+        PCS_HIP(launch_sort(ctx->dkeys.as<uint64_t>(), ctx->dvals.as<uint32_t>(),
+                            ctx->dkeys_alt.as<uint64_t>(), ctx->dvals_alt.as<uint32_t>(), cn, dsort_bits,
+                            ctx->sort_scratch.p, s, &in_alt));
+      } else {
+        PCS_HIP(launch_depth_keys(n, n_cams, ctx->meta.as<uint4>(), ctx->counts.as<uint32_t>(), zmin,
+                                  depth_bits, ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(), s));
+        PCS_HIP(launch_sort(ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(),
+                            ctx->dkeys_alt.as<uint32_t>(), ctx->dvals_alt.as<uint32_t>(), cn, dsort_bits,
+                            ctx->sort_scratch.p, s, &in_alt));
+      }
+      order = in_alt ? ctx->dvals_alt.as<uint32_t>() : ctx->dvals.as<uint32_t>();
+    }
+    {
+      StageTimer tm(ctx, ST_SCAN, s);
+      PCS_HIP(launch_scan(ctx->counts.as<uint32_t>(), order, ctx->offsets.as<uint32_t>(), cn, d_total,
+                          ctx->scan_scratch.p, s));
+    }
     {
       StageTimer tm(ctx, ST_BINNING, s);
-      PCS_HIP(launch_binning(n, n_cams, TX, tiles_per_cam, ctx->meta.as<uint4>(),
-                             ctx->counts.as<uint32_t>(), ctx->offsets.as<uint32_t>(), zmin,
-                             depth_bits, st->keys.as<uint64_t>(), st->vals.as<uint32_t>(), s));
+      PCS_HIP(launch_binning(n, n_cams, TX, tiles_per_cam, order, ctx->meta.as<uint4>(),
+                             ctx->counts.as<uint32_t>(), ctx->offsets.as<uint32_t>(),
+                             st->keys.as<uint32_t>(), st->vals.as<uint32_t>(), s));
     }
     bool in_alt = false;
     {
       StageTimer tm(ctx, ST_SORT, s);
-      PCS_HIP(launch_sort(st->keys.as<uint64_t>(), st->vals.as<uint32_t>(), ctx->keys_alt.as<uint64_t>(),
-                          ctx->vals_alt.as<uint32_t>(), m, bits, ctx->sort_scratch.p, s, &in_alt,
-                          nullptr, nullptr));
+      PCS_HIP(launch_sort(st->keys.as<uint32_t>(), st->vals.as<uint32_t>(), ctx->keys_alt.as<uint32_t>(),
+                          ctx->vals_alt.as<uint32_t>(), m, tile_bits, ctx->sort_scratch.p, s, &in_alt));
     }
     if (in_alt) {
       swap_buf(st->keys, ctx->keys_alt);
@@ -390,8 +420,7 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   }
   {
     StageTimer tm(ctx, ST_RANGES, s);
-    PCS_HIP(launch_ranges(st->keys.as<uint64_t>(), m, depth_bits, total_tiles,
-                          st->ranges.as<uint32_t>(), s));
+    PCS_HIP(launch_ranges(st->keys.as<uint32_t>(), m, total_tiles, st->ranges.as<uint32_t>(), s));
   }
   {
     StageTimer tm(ctx, ST_COMPOSITE, s);
@@ -450,7 +479,8 @@ int pcs_state_bins(const pcs_state* st_c, const uint64_t** keys, const uint32_t*
   PCS_HIP(hipSetDevice(st->ctx->device));
   PCS_TRY(ensure(st->canon, std::max<int64_t>(st->m, 1) * sizeof(uint64_t), "canonical keys"));
   PCS_HIP(hipDeviceSynchronize());
-  PCS_HIP(launch_canonical_keys(st->keys.as<uint64_t>(), st->m, st->depth_bits, st->zmin,
+  PCS_HIP(launch_canonical_keys(st->keys.as<uint32_t>(), st->vals.as<uint32_t>(), st->m, st->n,
+                                st->n_tiles / std::max(st->C, 1), st->rec.as<float4>(),
                                 st->canon.as<uint64_t>(), nullptr));
   PCS_HIP(hipDeviceSynchronize());
   if (keys) *keys = st->canon.as<uint64_t>();
@@ -518,14 +548,15 @@ int pcs_voxelize(pcs_context* ctx, const float* xyz, const float* rgb, int64_t n
   PCS_HIP(launch_vox_keys(xyz, n, grid, vox->keys.as<uint64_t>(), vox->order.as<uint32_t>(), s));
   bool in_alt = false;
   PCS_HIP(launch_sort(vox->keys.as<uint64_t>(), vox->order.as<uint32_t>(), ctx->keys_alt.as<uint64_t>(),
-                      ctx->vals_alt.as<uint32_t>(), n, 30, ctx->sort_scratch.p, s, &in_alt, nullptr, nullptr));
+                      ctx->vals_alt.as<uint32_t>(), n, 30, ctx->sort_scratch.p, s, &in_alt));
   if (in_alt) {
     swap_buf(vox->keys, ctx->keys_alt);
     swap_buf(vox->order, ctx->vals_alt);
   }
   PCS_HIP(launch_vox_flags(vox->keys.as<uint64_t>(), n, vox->flag.as<uint32_t>(), s));
   uint64_t* d_total = ctx->small.as<uint64_t>();
-  PCS_HIP(launch_scan(vox->flag.as<uint32_t>(), vox->excl.as<uint32_t>(), n, d_total, ctx->scan_scratch.p, s));
+  PCS_HIP(launch_scan(vox->flag.as<uint32_t>(), nullptr, vox->excl.as<uint32_t>(), n, d_total,
+                      ctx->scan_scratch.p, s));
   PCS_HIP(hipMemcpyAsync(ctx->host_small, d_total, 8, hipMemcpyDeviceToHost, s));
   PCS_HIP(hipStreamSynchronize(s));
   uint64_t V;

@@ -11,7 +11,8 @@
 //
 // The adjoint walks the same list back to front from each pixel's last contributor, recovering
 // the transmittance by division, keeps a running sum of what lies behind each splat, and reduces
-// each splat's 13 screen-space partials across the wavefront before one atomic add per value.
+// each splat's 13 screen-space partials across the wavefront (lane-half exchanges leave them in
+// four lanes) before one atomic add per value.
 
 #include "projection.hpp"
 
@@ -20,6 +21,7 @@ namespace pcs {
 namespace {
 
 constexpr int kBlock = kTilePixels;   // 256 threads, one per pixel
+constexpr int kGroup = 4;             // reaching splats whose quadratic forms are evaluated together
 
 // Pixel of a thread: wavefront w owns the 8x8 quadrant (w & 1, w >> 1) of the 16x16 tile.
 struct TilePixel {
@@ -96,29 +98,45 @@ __global__ __launch_bounds__(kBlock) void k_composite(
       }
       uint64_t mask = __ballot(rel);
       while (mask) {
-        const int k = c + (int)__builtin_ctzll(mask);
-        mask &= mask - 1;
-        if (done) continue;
-        const float4 r0 = s_r0[k];
-        const float4 r1 = s_r1[k];
-        const float dx = pxf - r0.x, dy = pyf - r0.y;
-        const float q = conic_q(r1.x, r1.y, r1.z, dx, dy);
-        if (!(q <= cut2)) continue;
-        const float a = fminf(opt.alpha_max, r0.z * __expf(-0.5f * q));
-        if (a < opt.alpha_min) continue;
-        const float w = a * T;
-        const float4 r2 = s_r2[k];
-        const float4 r3 = s_r3[k];
-        acc0 = fmaf(w, r2.x, acc0);
-        acc1 = fmaf(w, r2.y, acc1);
-        acc2 = fmaf(w, r2.z, acc2);
-        acc3 = fmaf(w, r3.x, acc3);
-        acc4 = fmaf(w, r3.y, acc4);
-        acc5 = fmaf(w, r3.z, acc5);
-        acc6 = fmaf(w, r0.w, acc6);
-        T = T * (1.0f - a);
-        last = (int32_t)(b - start) + k + 1;
-        if (T < opt.t_eps) done = true;
+        // quadratic forms of up to kGroup reaching splats first (independent of T, so their LDS
+        // reads overlap), then the alpha tests and blends in list order
+        int kk[kGroup];
+        float qq[kGroup];
+#pragma unroll
+        for (int j = 0; j < kGroup; ++j) {
+          kk[j] = mask ? c + (int)__builtin_ctzll(mask) : -1;
+          mask &= mask - 1;
+        }
+#pragma unroll
+        for (int j = 0; j < kGroup; ++j) {
+          qq[j] = cut2 + 1.0f;                            // above the cut: no blend
+          if (kk[j] >= 0) {
+            const float4 r0 = s_r0[kk[j]];
+            const float4 r1 = s_r1[kk[j]];
+            qq[j] = conic_q(r1.x, r1.y, r1.z, pxf - r0.x, pyf - r0.y);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < kGroup; ++j) {
+          if (done || !(qq[j] <= cut2)) continue;
+          const int k = kk[j];
+          const float4 r0 = s_r0[k];
+          const float a = fminf(opt.alpha_max, r0.z * __expf(-0.5f * qq[j]));
+          if (a < opt.alpha_min) continue;
+          const float w = a * T;
+          const float4 r2 = s_r2[k];
+          const float4 r3 = s_r3[k];
+          acc0 = fmaf(w, r2.x, acc0);
+          acc1 = fmaf(w, r2.y, acc1);
+          acc2 = fmaf(w, r2.z, acc2);
+          acc3 = fmaf(w, r3.x, acc3);
+          acc4 = fmaf(w, r3.y, acc4);
+          acc5 = fmaf(w, r3.z, acc5);
+          acc6 = fmaf(w, r0.w, acc6);
+          T = T * (1.0f - a);
+          last = (int32_t)(b - start) + k + 1;
+          if (T < opt.t_eps) done = true;
+        }
       }
     }
   }
@@ -259,13 +277,17 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(
         }
         if (__ballot(contrib) == 0ull) continue;   // wave-uniform
         const int64_t dst = base_idx + s_g[k];
-        float sv[kScreenGrads];
+        float v16[16], sv[4];
 #pragma unroll
-        for (int i = 0; i < kScreenGrads; ++i) sv[i] = wave_sum_to_last(pg[i]);
-        if (lane == kWave - 1) {
+        for (int i = 0; i < 16; ++i) v16[i] = i < kScreenGrads ? pg[i] : 0.0f;
+        wave_sum16_rows(v16, sv);
+        if ((lane & 15) == 15) {                     // one lane per row, four values each
+          const int row = lane >> 4;
 #pragma unroll
-          for (int i = 0; i < kScreenGrads; ++i)
-            if (sv[i] != 0.0f) unsafeAtomicAdd(&sgrad[i * stride + dst], sv[i]);
+          for (int j = 0; j < 4; ++j) {
+            const int i = 4 * row + j;
+            if (i < kScreenGrads && sv[j] != 0.0f) unsafeAtomicAdd(&sgrad[i * stride + dst], sv[j]);
+          }
         }
       }
     }

@@ -78,16 +78,30 @@ __device__ __forceinline__ float wave_sum(float v) {
   return (r0 + r1) + (r2 + r3);
 }
 
-// Sum across the wave left in lane 63 only (other lanes hold partial sums): row prefix sums by
-// row_shr, then row_bcast:15 and row_bcast:31 carry the row totals into the upper rows.
-__device__ __forceinline__ float wave_sum_to_last(float v) {
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, true));
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xF, 0xF, true));
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xF, 0xF, true));
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xF, 0xF, true));
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false));
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xC, 0xF, false));
-  return v;
+// Wave-wide sums of 16 per-lane values v[0..15] (padding with zeros is free), left in four lanes:
+// lane 16 R + 15 holds in out[j] the sum of v[4 R + j] (R = 0..3). Two lane-half exchanges
+// (v_permlane32_swap: the upper 32 lanes of the first operand trade places with the lower 32 of
+// the second; v_permlane16_swap: the same for odd and even 16-lane rows) each fold half of the
+// values into the other half of the lanes, then row_shr prefix sums finish every row.
+__device__ __forceinline__ void wave_sum16_rows(const float (&v)[16], float (&out)[4]) {
+  float q[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 8]),
+                                                    false, false);
+    q[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);   // lanes 0-31: v[i], 32-63: v[i + 8]
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(q[i]), __float_as_uint(q[i + 4]),
+                                                    false, false);
+    float x = __uint_as_float(r[0]) + __uint_as_float(r[1]);  // row R: v[4 R + i]
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x111, 0xF, 0xF, true));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x112, 0xF, 0xF, true));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x114, 0xF, 0xF, true));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x118, 0xF, 0xF, true));
+    out[i] = x;
+  }
 }
 
 // Block-to-tile map. Blocks are dealt round-robin to the 8 XCDs (block b runs on XCD b % 8);
@@ -109,34 +123,45 @@ hipError_t launch_fill_f32(float* p, float value, int64_t n, hipStream_t s);
 
 // Depth-bit range slots: zrange[0..kZSlots) minima, zrange[kZSlots..2 kZSlots) maxima.
 constexpr int kZSlots = 64;
-// small[0..1] instance total (u64), small[2..] depth-bit range slots; reset by launch_init_small.
-constexpr int kSmallWords = 2 + 2 * kZSlots;
+// small[0..1] a u64 total written by the scan, small[2..2+2 kZSlots) depth-bit range slots,
+// small[kCountWord..) kZSlots u64 partial instance counts; reset by launch_init_small.
+constexpr int kCountWord = 2 + 2 * kZSlots;
+constexpr int kSmallWords = kCountWord + 2 * kZSlots;
 hipError_t launch_init_small(uint32_t* small, hipStream_t s);
 hipError_t launch_project(int64_t n, int n_cams, const DevCamera* cams, const DevOptions& opt,
                           const pcs_gaussians& g, float4* rec, uint4* meta, uint32_t* counts,
-                          uint32_t* zrange, hipStream_t s);
+                          uint32_t* zrange, unsigned long long* count_slots, hipStream_t s);
 
-// Exclusive scan of n u32 values; writes out[n] and *total (u64). Scratch from scan_scratch_bytes.
+// Exclusive scan of n u32 values in[gather[j]] (gather may be null: in[j]); writes out[n] and
+// *total (u64). Scratch from scan_scratch_bytes.
 size_t scan_scratch_bytes(int64_t n);
-hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, uint64_t* total,
-                       void* scratch, hipStream_t s);
+hipError_t launch_scan(const uint32_t* in, const uint32_t* gather, uint32_t* out, int64_t n,
+                       uint64_t* total, void* scratch, hipStream_t s);
 
-hipError_t launch_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_cam, const uint4* meta,
-                          const uint32_t* counts, const uint32_t* offsets, uint32_t zmin,
-                          int depth_bits, uint64_t* keys, uint32_t* vals, hipStream_t s);
+// Depth key per (camera, Gaussian) and its combined index as the value.
+template <typename K>
+hipError_t launch_depth_keys(int64_t n, int n_cams, const uint4* meta, const uint32_t* counts,
+                             uint32_t zmin, int depth_bits, K* keys, uint32_t* vals, hipStream_t s);
 
-// LSD radix sort of (key, value) pairs over key bits [0, bits). Ping-pongs between (k0,v0) and
-// (k1,v1); returns in *result_in_alt whether the sorted data ended in (k1,v1).
+// Tile keys of every visible splat, written in the depth order `order` at `offsets`.
+hipError_t launch_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_cam, const uint32_t* order,
+                          const uint4* meta, const uint32_t* counts, const uint32_t* offsets,
+                          uint32_t* keys, uint32_t* vals, hipStream_t s);
+
+// Stable LSD radix sort of (key, value) pairs over key bits [0, bits), K = uint32_t or uint64_t.
+// Ping-pongs between (k0,v0) and (k1,v1); returns in *result_in_alt whether the sorted data ended
+// in (k1,v1).
 size_t sort_scratch_bytes(int64_t m);
-hipError_t launch_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t m, int bits,
-                       void* scratch, hipStream_t s, bool* result_in_alt,
-                       void (*stage_mark)(void*, int), void* mark_ctx);
+template <typename K>
+hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int bits, void* scratch,
+                       hipStream_t s, bool* result_in_alt);
 
-hipError_t launch_ranges(const uint64_t* keys, int64_t m, int depth_bits, int64_t n_tiles,
-                         uint32_t* ranges, hipStream_t s);
+hipError_t launch_ranges(const uint32_t* keys, int64_t m, int64_t n_tiles, uint32_t* ranges,
+                         hipStream_t s);
 
-hipError_t launch_canonical_keys(const uint64_t* keys, int64_t m, int depth_bits, uint32_t zmin,
-                                 uint64_t* out, hipStream_t s);
+hipError_t launch_canonical_keys(const uint32_t* keys, const uint32_t* vals, int64_t m, int64_t n,
+                                 int64_t tiles_per_cam, const float4* rec, uint64_t* out,
+                                 hipStream_t s);
 
 hipError_t launch_composite(int64_t n, int n_cams, int W, int H, const float4* rec,
                             const uint32_t* vals, const uint32_t* ranges, const DevOptions& opt,

@@ -31,13 +31,14 @@ __global__ __launch_bounds__(256) void k_project(
     const float* __restrict__ mean, const float* __restrict__ quat,
     const float* __restrict__ scale, const float* __restrict__ opac,
     const float* __restrict__ rgb, const float* __restrict__ nrm, float4* __restrict__ rec,
-    uint4* __restrict__ meta, uint32_t* __restrict__ counts, uint32_t* __restrict__ zrange) {
+    uint4* __restrict__ meta, uint32_t* __restrict__ counts, uint32_t* __restrict__ zrange,
+    unsigned long long* __restrict__ count_slots) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int c = blockIdx.y;
   const DevCamera& cam = cams[c];
   const int64_t out = (int64_t)c * n + i;
   bool visible = false;
-  uint32_t zbits = 0;
+  uint32_t zbits = 0, my_count = 0;
   if (i < n) {
     const float px = mean[i], py = mean[n + i], pz = mean[2 * n + i];
     const float qw = quat[i], qx = quat[n + i], qy = quat[2 * n + i], qz = quat[3 * n + i];
@@ -70,7 +71,8 @@ __global__ __launch_bounds__(256) void k_project(
       const int y0 = (int)fmaxf(fy0, 0.0f), y1 = (int)fminf(fy1, (float)(TY - 1));
       visible = true;
       zbits = __float_as_uint(zc);
-      counts[out] = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+      my_count = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+      counts[out] = my_count;
       meta[out] = make_uint4(zbits, (uint32_t)x0 | ((uint32_t)x1 << 16),
                              (uint32_t)y0 | ((uint32_t)y1 << 16), 0u);
       float4* r = rec + out * kRecFloat4;
@@ -86,25 +88,30 @@ __global__ __launch_bounds__(256) void k_project(
       counts[out] = 0u;
     }
   }
-  // depth-bit range of the visible splats: block reduction, then one atomic pair per block into
-  // one of kZSlots slot pairs (spreading the atomics; the host folds the slots)
+  // depth-bit range and instance total of the block: block reduction, then one atomic each into
+  // one of kZSlots slots (spreading the atomics; the host folds the slots)
   __shared__ uint32_t s_lo[4], s_hi[4];
+  __shared__ unsigned long long s_cnt[4];
   uint32_t lo = visible ? zbits : 0xFFFFFFFFu, hi = visible ? zbits : 0u;
+  unsigned long long cnt = my_count;
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
     lo = min(lo, (uint32_t)__shfl_xor((int)lo, o, kWave));
     hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, kWave));
+    cnt += __shfl_xor(cnt, o, kWave);
   }
   const int wave = threadIdx.x / kWave;
-  if (lane_id() == 0) { s_lo[wave] = lo; s_hi[wave] = hi; }
+  if (lane_id() == 0) { s_lo[wave] = lo; s_hi[wave] = hi; s_cnt[wave] = cnt; }
   __syncthreads();
   if (threadIdx.x == 0) {
     lo = min(min(s_lo[0], s_lo[1]), min(s_lo[2], s_lo[3]));
     hi = max(max(s_hi[0], s_hi[1]), max(s_hi[2], s_hi[3]));
+    cnt = (s_cnt[0] + s_cnt[1]) + (s_cnt[2] + s_cnt[3]);
     if (hi != 0u) {
       const int slot = (blockIdx.x + blockIdx.y * 7) % kZSlots;
       atomicMin(&zrange[slot], lo);
       atomicMax(&zrange[kZSlots + slot], hi);
+      atomicAdd(&count_slots[slot], cnt);
     }
   }
 }
@@ -116,6 +123,7 @@ __global__ void k_init_small(uint32_t* __restrict__ small) {
     small[2 + i] = 0xFFFFFFFFu;                               // depth-bit minima
     small[2 + kZSlots + i] = 0u;                              // depth-bit maxima
   }
+  if (i < 2 * kZSlots) small[kCountWord + i] = 0u;           // partial instance counts (u64)
 }
 
 }  // namespace
@@ -133,17 +141,17 @@ hipError_t launch_fill_f32(float* p, float value, int64_t n, hipStream_t s) {
 }
 
 hipError_t launch_init_small(uint32_t* small, hipStream_t s) {
-  hipLaunchKernelGGL(k_init_small, dim3(1), dim3(64), 0, s, small);
+  hipLaunchKernelGGL(k_init_small, dim3(1), dim3(2 * kZSlots), 0, s, small);
   return hipGetLastError();
 }
 
 hipError_t launch_project(int64_t n, int n_cams, const DevCamera* cams, const DevOptions& opt,
                           const pcs_gaussians& g, float4* rec, uint4* meta, uint32_t* counts,
-                          uint32_t* zrange, hipStream_t s) {
+                          uint32_t* zrange, unsigned long long* count_slots, hipStream_t s) {
   if (n <= 0 || n_cams <= 0) return hipSuccess;
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)n_cams);
   hipLaunchKernelGGL(k_project, grid, dim3(256), 0, s, n, cams, opt, g.mean, g.quat, g.scale,
-                     g.opacity, g.rgb, g.normal, rec, meta, counts, zrange);
+                     g.opacity, g.rgb, g.normal, rec, meta, counts, zrange, count_slots);
   return hipGetLastError();
 }
 

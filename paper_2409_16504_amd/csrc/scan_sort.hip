@@ -1,21 +1,27 @@
-// Instance counting, (tile | depth) key emission, LSD radix sort and tile ranges.
+// Instance ordering: depth sort of the projected splats, prefix sum of their tile counts in that
+// order, tile-key emission, stable tile sort and tile ranges.
 //
 //  * scan:     single-pass exclusive prefix sum with decoupled look-back (Merrill & Garland,
-//              "Single-pass Parallel Prefix Scan with Decoupled Look-back", 2016). A block takes
-//              its partition from an atomic ticket, so it only ever waits on partitions whose
-//              blocks are already running; the look-back reads 64 predecessors per step, one per
-//              lane of a wavefront.
-//  * binning:  one thread per visible (camera, Gaussian) writes its tile keys in rectangle order.
+//              "Single-pass Parallel Prefix Scan with Decoupled Look-back", 2016), optionally
+//              reading its input through a permutation. Block b scans partition b: blocks are
+//              dispatched in index order on each XCD, so every partition a block waits on
+//              belongs to a block that is already running or done. The look-back reads 64
+//              predecessors per step, one per lane of a wavefront; its spin is bounded.
+//  * depth keys / binning: the (camera, depth) order of the splats is found by sorting one key per
+//              (camera, Gaussian); each visible splat then writes its tile keys, in rectangle order,
+//              at its offset in that order. A stable sort by tile afterwards leaves every tile's
+//              run in (depth, Gaussian index) order: the (tile, depth, index) order of Section 3.1
+//              with the deep key sort done over splats rather than over their tile instances.
 //  * sort:     Onesweep-style LSD radix sort (Adinets & Merrill, "Onesweep: A Faster Least
-//              Significant Digit Radix Sort for GPUs", 2022): one histogram pass over all digits,
-//              then one chained-scan scatter per 8-bit digit. Ranks inside a wavefront come from
-//              eight ballots (lanes holding the same digit), so the sort is stable; each block
-//              reorders its 4096 keys through LDS so global writes leave in digit runs.
+//              Significant Digit Radix Sort for GPUs", 2022) on 32- or 64-bit keys: one histogram
+//              pass over all digits, then one chained-scan scatter per 8-bit digit. Ranks inside a
+//              wavefront come from eight ballots (lanes holding the same digit), so the sort is
+//              stable; each block reorders its 4096 keys through LDS so global writes leave in
+//              digit runs.
 //  * ranges:   tile start/end from tile-id changes in the sorted keys.
 //
-// Keys are packed as (global tile id << depth_bits) | (fp32 depth bits - minimum depth bits):
-// positive floats order like their bit patterns, so this is the (tile, depth) order of the
-// canonical key ((tile << 32) | depth bits) with only the significant bits left to sort.
+// Depth keys are (camera << depth_bits) | (fp32 depth bits - minimum depth bits): positive floats
+// order like their bit patterns, so only the significant bits are sorted.
 
 #include "pcs_internal.hpp"
 
@@ -54,20 +60,20 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
 }
 
 __global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* __restrict__ in,
+                                                   const uint32_t* __restrict__ gather,
                                                    uint32_t* __restrict__ out, int64_t n,
                                                    int64_t n_parts, uint64_t* __restrict__ status,
-                                                   uint32_t* __restrict__ ticket,
                                                    uint64_t* __restrict__ total) {
-  __shared__ uint32_t s_part;
   __shared__ uint64_t s_wave[kWaves];
   __shared__ uint64_t s_excl;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-  if (tid == 0) s_part = atomicAdd(ticket, 1u);
-  __syncthreads();
-  const int64_t part = s_part;
+  const int64_t part = blockIdx.x;    // in-order dispatch: predecessors are running or done
   const int64_t base = part * kPart + (int64_t)tid * kItems;
   uint32_t x[kItems];
-  if (base + kItems <= n) {
+  if (gather) {
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) x[k] = (base + k < n) ? in[gather[base + k]] : 0u;
+  } else if (base + kItems <= n) {
     const uint4* src = reinterpret_cast<const uint4*>(in + base);
 #pragma unroll
     for (int q = 0; q < kItems / 4; ++q) {
@@ -134,30 +140,49 @@ __global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* __restrict__ 
   if (part == n_parts - 1 && tid == 0) *total = s_excl + block_total;
 }
 
-// ---- binning --------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_binning(int64_t total, int64_t n, int TX,
-                                                 int64_t tiles_per_cam,
+// ---- depth keys and binning ----------------------------------------------------------------
+// One key per (camera, Gaussian); culled splats get all bits set (they have no tile instances,
+// so where they land in the order does not matter).
+template <typename K>
+__global__ __launch_bounds__(256) void k_depth_keys(int64_t n, const uint4* __restrict__ meta,
+                                                    const uint32_t* __restrict__ counts,
+                                                    uint32_t zmin, int depth_bits,
+                                                    K* __restrict__ keys,
+                                                    uint32_t* __restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t j = (int64_t)blockIdx.y * n + i;
+  const uint32_t zb = meta[j].x;
+  // a camera field exists only with several cameras, and then depth_bits < the key width
+  const K cam = blockIdx.y ? ((K)blockIdx.y << depth_bits) : (K)0;
+  keys[j] = counts[j] ? (cam | (K)(zb - zmin)) : ~(K)0;
+  vals[j] = (uint32_t)j;
+}
+
+// Thread per position of the depth order: the splat there writes its tile keys (global tile id)
+// and Gaussian index at its offset in that order.
+__global__ __launch_bounds__(256) void k_binning(int64_t total, uint32_t n, int TX,
+                                                 uint32_t tiles_per_cam,
+                                                 const uint32_t* __restrict__ order,
                                                  const uint4* __restrict__ meta,
                                                  const uint32_t* __restrict__ counts,
                                                  const uint32_t* __restrict__ offsets,
-                                                 uint32_t zmin, int depth_bits,
-                                                 uint64_t* __restrict__ keys,
+                                                 uint32_t* __restrict__ keys,
                                                  uint32_t* __restrict__ vals) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= total) return;
+  const uint32_t i = order[j];
   const uint32_t cnt = counts[i];
   if (cnt == 0) return;
-  const int64_t cam = i / n;
-  const uint32_t g = (uint32_t)(i - cam * n);
+  const uint32_t cam = i / n;
+  const uint32_t g = i - cam * n;
   const uint4 m = meta[i];
-  const uint64_t depth = (uint64_t)(m.x - zmin);
   const int x0 = m.y & 0xFFFF, x1 = m.y >> 16, y0 = m.z & 0xFFFF, y1 = m.z >> 16;
-  uint32_t off = offsets[i];
-  const uint64_t cam_base = (uint64_t)cam * (uint64_t)tiles_per_cam;
+  uint32_t off = offsets[j];
+  const uint32_t cam_base = cam * tiles_per_cam;
   for (int ty = y0; ty <= y1; ++ty)
     for (int tx = x0; tx <= x1; ++tx) {
-      const uint64_t tile = cam_base + (uint64_t)(ty * TX + tx);
-      keys[off] = (tile << depth_bits) | depth;
+      keys[off] = cam_base + (uint32_t)(ty * TX + tx);
       vals[off] = g;
       ++off;
     }
@@ -169,49 +194,60 @@ constexpr int kMaxPasses = 8;
 constexpr uint32_t kSortAgg = 1u << 30;
 constexpr uint32_t kSortPrefix = 2u << 30;
 constexpr uint32_t kSortValue = (1u << 30) - 1;
-constexpr int kLookWindow = 8;
+constexpr int kLookWindow = 32;
 
-// Digit histograms of every pass in one read of the keys. Lanes of a wavefront holding the same
-// digit are matched with eight ballots and their count is added once, so the long runs of equal
-// digits (all instances of one Gaussian share its depth bits) cost one LDS atomic per run.
-__global__ __launch_bounds__(256) void k_radix_hist(const uint64_t* __restrict__ keys, int64_t m,
-                                                    int n_passes, uint32_t* __restrict__ hist) {
+// Digit histograms of every pass in one read of the keys, one partial histogram per block. Each
+// block takes partitions of 4096 keys
+// (16 per thread, all loads issued before any is used). Lanes of a wavefront holding the same digit
+// are matched with eight ballots and their count is added once, so the long runs of equal digits
+// cost one LDS atomic per run.
+template <typename K>
+__global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, int64_t m,
+                                                    int n_passes, uint32_t* __restrict__ partial) {
   __shared__ uint32_t sh[kMaxPasses][kBins];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   for (int p = 0; p < kMaxPasses; ++p) sh[p][tid] = 0;
   __syncthreads();
   const uint64_t lt_mask = lanemask_lt();
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m; base += stride) {
-    const int64_t i = base + tid;
-    const bool valid = i < m;
-    const uint64_t k = valid ? keys[i] : 0ull;
-    const uint64_t vmask = __ballot(valid);
-    for (int p = 0; p < n_passes; ++p) {
-      const uint32_t d = (uint32_t)(k >> (8 * p)) & 0xFF;
-      uint64_t peers = vmask;
+  for (int64_t part = blockIdx.x; part * kPart < m; part += gridDim.x) {
+    const int64_t wbase = part * kPart + (int64_t)wave * (kWave * kItems);
+    K k[kItems];
 #pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t bal = __ballot(bit);
-        peers &= bit ? bal : ~bal;
+    for (int it = 0; it < kItems; ++it) {
+      const int64_t pos = wbase + (int64_t)it * kWave + lane;
+      k[it] = pos < m ? keys[pos] : (K)0;
+    }
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+      const bool valid = wbase + (int64_t)it * kWave + lane < m;
+      const uint64_t vmask = __ballot(valid);
+      if (vmask == 0) break;
+      for (int p = 0; p < n_passes; ++p) {
+        const uint32_t d = (uint32_t)(k[it] >> (8 * p)) & 0xFF;
+        uint64_t peers = vmask;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          const bool bit = (d >> b) & 1u;
+          const uint64_t bal = __ballot(bit);
+          peers &= bit ? bal : ~bal;
+        }
+        if (valid && (peers & lt_mask) == 0) atomicAdd(&sh[p][d], (uint32_t)__popcll(peers));
       }
-      if (valid && (peers & lt_mask) == 0) atomicAdd(&sh[p][d], (uint32_t)__popcll(peers));
     }
   }
   __syncthreads();
-  for (int p = 0; p < n_passes; ++p) {
-    const uint32_t v = sh[p][tid];
-    if (v) atomicAdd(&hist[p * kBins + tid], v);
-  }
+  // this block's counts, summed over blocks by k_digit_base (plain stores: no shared counters)
+  for (int p = 0; p < n_passes; ++p) partial[((int64_t)blockIdx.x * kMaxPasses + p) * kBins + tid] = sh[p][tid];
 }
 
-// Exclusive scan over the 256 bins of each pass (one block per pass).
-__global__ __launch_bounds__(256) void k_digit_base(const uint32_t* __restrict__ hist,
-                                                    uint32_t* __restrict__ base) {
+// Sum of the blocks' partial histograms and exclusive scan over the 256 bins of each pass (one
+// block per pass).
+__global__ __launch_bounds__(256) void k_digit_base(const uint32_t* __restrict__ partial,
+                                                    int n_blocks, uint32_t* __restrict__ base) {
   __shared__ uint32_t s_wave[kWaves];
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-  const uint32_t v = hist[blockIdx.x * kBins + tid];
+  uint32_t v = 0;
+  for (int b = 0; b < n_blocks; ++b) v += partial[((int64_t)b * kMaxPasses + blockIdx.x) * kBins + tid];
   const uint32_t incl = wave_inclusive_scan(v);
   if (lane == kWave - 1) s_wave[wave] = incl;
   __syncthreads();
@@ -220,25 +256,23 @@ __global__ __launch_bounds__(256) void k_digit_base(const uint32_t* __restrict__
   base[blockIdx.x * kBins + tid] = pre + incl - v;
 }
 
+template <typename K>
 __global__ __launch_bounds__(kThreads) void k_onesweep(
-    const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
+    const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
     uint32_t* __restrict__ vout, int64_t m, int shift, const uint32_t* __restrict__ digit_base,
-    uint32_t* __restrict__ status, uint32_t* __restrict__ status_next,
-    uint32_t* __restrict__ ticket) {
-  __shared__ uint32_t s_part;
+    uint32_t* __restrict__ status, uint32_t* __restrict__ status_next) {
   __shared__ uint32_t s_hist[kWaves][kBins];   // per-wave counts, then per-wave offsets
   __shared__ uint32_t s_local[kBins];          // block-local start of each digit run
   __shared__ uint32_t s_global[kBins];         // global start of the run minus its local start
   __shared__ uint32_t s_wsum[kWaves];
-  __shared__ uint64_t s_buf[kPart];            // keys, then (as u32) values, in digit order
+  __shared__ K s_buf[kPart];                   // keys, then (as u32) values, in digit order
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
 #pragma unroll
   for (int w = 0; w < kWaves; ++w) s_hist[w][tid] = 0;
-  if (tid == 0) s_part = atomicAdd(ticket, 1u);
   __syncthreads();
-  const int64_t part = s_part;
+  const int64_t part = blockIdx.x;    // in-order dispatch: predecessors are running or done
   const int64_t wbase = part * kPart + (int64_t)wave * (kWave * kItems);
-  uint64_t key[kItems];
+  K key[kItems];
   uint32_t val[kItems];
   uint32_t rank[kItems];
   const uint64_t lt_mask = lanemask_lt();
@@ -246,7 +280,7 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
   for (int it = 0; it < kItems; ++it) {
     const int64_t pos = wbase + (int64_t)it * kWave + lane;
     const bool valid = pos < m;
-    key[it] = valid ? kin[pos] : 0ull;
+    key[it] = valid ? kin[pos] : (K)0;
     val[it] = valid ? vin[pos] : 0u;
     const uint32_t d = (uint32_t)(key[it] >> shift) & 0xFF;
     uint64_t peers = __ballot(valid);
@@ -334,7 +368,7 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
   for (int r = 0; r < kItems; ++r) {
     const int j = tid + r * kThreads;
     if (j < n_here) {
-      const uint64_t k = s_buf[j];
+      const K k = s_buf[j];
       gdst[r] = s_global[(uint32_t)(k >> shift) & 0xFF] + (uint32_t)j;
       if (gdst[r] < (uint64_t)m) kout[gdst[r]] = k;
     }
@@ -355,23 +389,26 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
   }
 }
 
-__global__ void k_ranges(const uint64_t* __restrict__ keys, int64_t m, int depth_bits,
-                         int64_t n_tiles, uint32_t* __restrict__ ranges) {
+__global__ void k_ranges(const uint32_t* __restrict__ keys, int64_t m, int64_t n_tiles,
+                         uint32_t* __restrict__ ranges) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
-  const uint64_t t = keys[i] >> depth_bits;
+  const uint32_t t = keys[i];
   if (t >= (uint64_t)n_tiles) return;
-  if (i == 0 || (keys[i - 1] >> depth_bits) != t) ranges[t] = (uint32_t)i;
-  if (i == m - 1 || (keys[i + 1] >> depth_bits) != t) ranges[n_tiles + t] = (uint32_t)(i + 1);
+  if (i == 0 || keys[i - 1] != t) ranges[t] = (uint32_t)i;
+  if (i == m - 1 || keys[i + 1] != t) ranges[n_tiles + t] = (uint32_t)(i + 1);
 }
 
-__global__ void k_canonical(const uint64_t* __restrict__ keys, int64_t m, int depth_bits,
-                            uint32_t zmin, uint64_t* __restrict__ out) {
+// Canonical key (tile << 32) | fp32 depth bits, the depth read back from the splat record.
+__global__ void k_canonical(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                            int64_t m, int64_t n, int64_t tiles_per_cam,
+                            const float4* __restrict__ rec, uint64_t* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
-  const uint64_t k = keys[i];
-  const uint64_t mask = depth_bits == 0 ? 0ull : ((1ull << depth_bits) - 1);
-  out[i] = ((k >> depth_bits) << 32) | (uint64_t)((uint32_t)(k & mask) + zmin);
+  const uint32_t t = keys[i];
+  const int64_t cam = (int64_t)t / tiles_per_cam;
+  const float z = rec[(cam * n + vals[i]) * kRecFloat4].w;
+  out[i] = ((uint64_t)t << 32) | (uint64_t)__float_as_uint(z);
 }
 
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
@@ -384,87 +421,102 @@ size_t scan_scratch_bytes(int64_t n) {
   return (size_t)(parts + 1) * sizeof(uint64_t) + 256;
 }
 
-hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, uint64_t* total,
-                       void* scratch, hipStream_t s) {
+hipError_t launch_scan(const uint32_t* in, const uint32_t* gather, uint32_t* out, int64_t n,
+                       uint64_t* total, void* scratch, hipStream_t s) {
   const int64_t parts = (n + kPart - 1) / kPart;
   uint64_t* status = reinterpret_cast<uint64_t*>(scratch);
-  uint32_t* ticket = reinterpret_cast<uint32_t*>(status + parts);
-  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(scratch), 0u, parts * 2 + 2, s);
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(scratch), 0u, parts * 2, s);
   if (e != hipSuccess) return e;
   if (n == 0) return launch_fill_u32(reinterpret_cast<uint32_t*>(total), 0u, 2, s);
-  hipLaunchKernelGGL(k_scan, dim3((unsigned)parts), dim3(kThreads), 0, s, in, out, n, parts, status,
-                     ticket, total);
+  hipLaunchKernelGGL(k_scan, dim3((unsigned)parts), dim3(kThreads), 0, s, in, gather, out, n, parts,
+                     status, total);
   return hipGetLastError();
 }
 
-hipError_t launch_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_cam, const uint4* meta,
-                          const uint32_t* counts, const uint32_t* offsets, uint32_t zmin,
-                          int depth_bits, uint64_t* keys, uint32_t* vals, hipStream_t s) {
-  const int64_t total = n * n_cams;
-  if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_binning, dim3(blocks_for(total, 256)), dim3(256), 0, s, total, n, TX,
-                     tiles_per_cam, meta, counts, offsets, zmin, depth_bits, keys, vals);
+template <typename K>
+hipError_t launch_depth_keys(int64_t n, int n_cams, const uint4* meta, const uint32_t* counts,
+                             uint32_t zmin, int depth_bits, K* keys, uint32_t* vals, hipStream_t s) {
+  if (n == 0 || n_cams == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_depth_keys<K>, dim3(blocks_for(n, 256), (unsigned)n_cams), dim3(256), 0, s, n,
+                     meta, counts, zmin, depth_bits, keys, vals);
   return hipGetLastError();
 }
+template hipError_t launch_depth_keys<uint32_t>(int64_t, int, const uint4*, const uint32_t*, uint32_t,
+                                                int, uint32_t*, uint32_t*, hipStream_t);
+template hipError_t launch_depth_keys<uint64_t>(int64_t, int, const uint4*, const uint32_t*, uint32_t,
+                                                int, uint64_t*, uint32_t*, hipStream_t);
+
+hipError_t launch_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_cam, const uint32_t* order,
+                          const uint4* meta, const uint32_t* counts, const uint32_t* offsets,
+                          uint32_t* keys, uint32_t* vals, hipStream_t s) {
+  const int64_t total = n * n_cams;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_binning, dim3(blocks_for(total, 256)), dim3(256), 0, s, total, (uint32_t)n, TX,
+                     (uint32_t)tiles_per_cam, order, meta, counts, offsets, keys, vals);
+  return hipGetLastError();
+}
+
+constexpr int kHistBlocks = 256;
 
 size_t sort_scratch_bytes(int64_t m) {
   const int64_t parts = (m + kPart - 1) / kPart;
-  return (size_t)(2 * kMaxPasses * kBins + kMaxPasses + 2 * parts * kBins) * sizeof(uint32_t) + 256;
+  return (size_t)((int64_t)kHistBlocks * kMaxPasses * kBins + kMaxPasses * kBins + 2 * parts * kBins) *
+             sizeof(uint32_t) + 256;
 }
 
-hipError_t launch_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t m, int bits,
-                       void* scratch, hipStream_t s, bool* result_in_alt,
-                       void (*stage_mark)(void*, int), void* mark_ctx) {
+template <typename K>
+hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int bits, void* scratch,
+                       hipStream_t s, bool* result_in_alt) {
   *result_in_alt = false;
   if (m <= 1 || bits <= 0) return hipSuccess;
   const int n_passes = (bits + 7) / 8;
   const int64_t parts = (m + kPart - 1) / kPart;
-  // scratch: hist[8][256] | base[8][256] | tickets[8] | status[2][parts][256] (contiguous, so one
-  // fill clears histograms, tickets and both status buffers)
-  uint32_t* hist = reinterpret_cast<uint32_t*>(scratch);
-  uint32_t* base = hist + kMaxPasses * kBins;
-  uint32_t* tickets = base + kMaxPasses * kBins;
-  uint32_t* status0 = tickets + kMaxPasses;
+  // scratch: partial[kHistBlocks][8][256] | base[8][256] | status[2][parts][256]. Pass p reads
+  // status[p & 1] and clears its partitions' slice of the other buffer for pass p + 1, so only
+  // status[0] is cleared here.
+  uint32_t* partial = reinterpret_cast<uint32_t*>(scratch);
+  uint32_t* base = partial + (int64_t)kHistBlocks * kMaxPasses * kBins;
+  uint32_t* status0 = base + kMaxPasses * kBins;
   uint32_t* status1 = status0 + parts * kBins;
-  hipError_t e = launch_fill_u32(hist, 0u, kMaxPasses * kBins, s);
-  if (e == hipSuccess) e = launch_fill_u32(tickets, 0u, kMaxPasses + 2 * parts * kBins, s);
+  hipError_t e = launch_fill_u32(status0, 0u, parts * kBins, s);
   if (e != hipSuccess) return e;
-  // few blocks: each block adds its 256 x n_passes partial counts to the same global bins
-  const unsigned hblocks = (unsigned)std::min<int64_t>(256, (m + 4095) / 4096);
-  hipLaunchKernelGGL(k_radix_hist, dim3(hblocks), dim3(256), 0, s, k0, m, n_passes, hist);
-  hipLaunchKernelGGL(k_digit_base, dim3(n_passes), dim3(256), 0, s, hist, base);
+  const int hblocks = (int)std::min<int64_t>(kHistBlocks, parts);
+  hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)hblocks), dim3(256), 0, s, k0, m, n_passes, partial);
+  hipLaunchKernelGGL(k_digit_base, dim3(n_passes), dim3(256), 0, s, partial, hblocks, base);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  uint64_t *ki = k0, *ko = k1;
+  K *ki = k0, *ko = k1;
   uint32_t *vi = v0, *vo = v1;
   for (int p = 0; p < n_passes; ++p) {
     uint32_t* st = (p & 1) ? status1 : status0;
     uint32_t* st_next = (p & 1) ? status0 : status1;
-    hipLaunchKernelGGL(k_onesweep, dim3((unsigned)parts), dim3(kThreads), 0, s, ki, vi, ko, vo, m,
-                       8 * p, base + p * kBins, st, st_next, tickets + p);
+    hipLaunchKernelGGL(k_onesweep<K>, dim3((unsigned)parts), dim3(kThreads), 0, s, ki, vi, ko, vo, m,
+                       8 * p, base + p * kBins, st, st_next);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     std::swap(ki, ko);
     std::swap(vi, vo);
   }
-  (void)stage_mark;
-  (void)mark_ctx;
   *result_in_alt = (n_passes % 2) == 1;
   return hipSuccess;
 }
+template hipError_t launch_sort<uint32_t>(uint32_t*, uint32_t*, uint32_t*, uint32_t*, int64_t, int,
+                                          void*, hipStream_t, bool*);
+template hipError_t launch_sort<uint64_t>(uint64_t*, uint32_t*, uint64_t*, uint32_t*, int64_t, int,
+                                          void*, hipStream_t, bool*);
 
-hipError_t launch_ranges(const uint64_t* keys, int64_t m, int depth_bits, int64_t n_tiles,
-                         uint32_t* ranges, hipStream_t s) {
+hipError_t launch_ranges(const uint32_t* keys, int64_t m, int64_t n_tiles, uint32_t* ranges,
+                         hipStream_t s) {
   hipError_t e = launch_fill_u32(ranges, 0u, 2 * n_tiles, s);
   if (e != hipSuccess || m == 0) return e;
-  hipLaunchKernelGGL(k_ranges, dim3(blocks_for(m, 256)), dim3(256), 0, s, keys, m, depth_bits,
-                     n_tiles, ranges);
+  hipLaunchKernelGGL(k_ranges, dim3(blocks_for(m, 256)), dim3(256), 0, s, keys, m, n_tiles, ranges);
   return hipGetLastError();
 }
 
-hipError_t launch_canonical_keys(const uint64_t* keys, int64_t m, int depth_bits, uint32_t zmin,
-                                 uint64_t* out, hipStream_t s) {
+hipError_t launch_canonical_keys(const uint32_t* keys, const uint32_t* vals, int64_t m, int64_t n,
+                                 int64_t tiles_per_cam, const float4* rec, uint64_t* out,
+                                 hipStream_t s) {
   if (m == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_canonical, dim3(blocks_for(m, 256)), dim3(256), 0, s, keys, m, depth_bits,
-                     zmin, out);
+  hipLaunchKernelGGL(k_canonical, dim3(blocks_for(m, 256)), dim3(256), 0, s, keys, vals, m, n,
+                     tiles_per_cam, rec, out);
   return hipGetLastError();
 }
 

@@ -64,17 +64,6 @@ class Voxels:
         return float((nbr >= 0).sum(dim=0).float().mean().item()) - 1.0
 
 
-def adaptive_grid(R: Renderer, xyz: torch.Tensor, rgb: torch.Tensor, target: float = 6.0) -> Voxels:
-    """Density-adaptive voxel size (Section 3.2 scales the cloud to about one point per voxel so
-    that voxelisation keeps neighbouring points in neighbouring voxels): the finest power-of-two
-    grid, at most 1024^3, whose voxels have on average at least ``target`` occupied neighbours."""
-    vox = None
-    for grid in (1024, 512, 256, 128, 64):
-        vox = Voxels(R).build(xyz, rgb, grid)
-        if vox.mean_neighbours() >= target:
-            return vox
-    return vox
-
     def arrays(self) -> dict:
         """Zero-copy tensors: coords (3,V) int32, nbr (27,V) int32, point_voxel (n,) int32,
         features (V,32) bf16."""
@@ -93,6 +82,18 @@ def adaptive_grid(R: Renderer, xyz: torch.Tensor, rgb: torch.Tensor, target: flo
         if getattr(self, "handle", None) and self.handle.value:
             _lib.load().pcs_voxels_destroy(self.handle)
             self.handle = ctypes.c_void_p()
+
+
+def adaptive_grid(R: Renderer, xyz: torch.Tensor, rgb: torch.Tensor, target: float = 6.0) -> Voxels:
+    """Density-adaptive voxel size (Section 3.2 scales the cloud to about one point per voxel so
+    that voxelisation keeps neighbouring points in neighbouring voxels): the finest power-of-two
+    grid, at most 1024^3, whose voxels have on average at least ``target`` occupied neighbours."""
+    vox = None
+    for grid in (1024, 512, 256, 128, 64):
+        vox = Voxels(R).build(xyz, rgb, grid)
+        if vox.mean_neighbours() >= target:
+            return vox
+    return vox
 
 
 def conv_forward(R: Renderer, vox: Voxels, x: torch.Tensor, w_bf16: torch.Tensor, bias, relu: bool,

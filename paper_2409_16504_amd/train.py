@@ -31,10 +31,10 @@ from synthetic import orbit_cameras  # noqa: E402
 from synthetic.scenes import ProceduralSurface, quantize_10bit  # noqa: E402
 
 from . import Renderer, default_options  # noqa: E402
-from .estimator import Adam, SparseEstimator, adaptive_grid, psnr, train_step  # noqa: E402
+from .estimator import Adam, SparseEstimator, Voxels, adaptive_grid, psnr, train_step  # noqa: E402
 
 
-def make_cloud(R: Renderer, seed: int, n: int, dense_factor: int = 8, gt_kappa: float = 1.0) -> dict:
+def make_cloud(R: Renderer, seed: int, n: int, grid: int = 0, dense_factor: int = 8, gt_kappa: float = 1.0) -> dict:
     """Sparse quantised cloud plus the Gaussians of its dense unquantised ground-truth sample."""
     rng = np.random.default_rng(seed)
     surf = ProceduralSurface(rng)
@@ -50,7 +50,8 @@ def make_cloud(R: Renderer, seed: int, n: int, dense_factor: int = 8, gt_kappa: 
     dense = dict(mean=xd, quat=est["quat"], scale=est["scale"],
                  opacity=torch.full((xd.shape[1],), 0.9, device=dev),
                  rgb=torch.from_numpy(np.ascontiguousarray(rgbd, np.float32)).to(dev), normal=est["normal"])
-    return dict(seed=seed, xyz=xyz, rgb=col, dense=dense, vox=adaptive_grid(R, xyz, col))
+    vox = Voxels(R).build(xyz, col, grid) if grid else adaptive_grid(R, xyz, col)
+    return dict(seed=seed, xyz=xyz, rgb=col, dense=dense, vox=vox)
 
 
 def knn_gaussians(R: Renderer, c: dict, kappa: float) -> dict:
@@ -84,14 +85,15 @@ def main(argv=None):
     ap.add_argument("--views", type=int, default=8)
     ap.add_argument("--res", type=int, default=512)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--grid", type=int, default=0, help="voxel grid edge (power of two); 0 = density-adaptive")
     ap.add_argument("--out", default=None)
     ap.add_argument("--resume", default=None)
     args = ap.parse_args(argv)
 
     R = Renderer(0)
     t0 = time.time()
-    train = [make_cloud(R, 10040 + i, args.points) for i in range(args.train_clouds)]
-    held = [make_cloud(R, 2000 + i, args.points) for i in range(args.eval_clouds)]
+    train = [make_cloud(R, 10040 + i, args.points, args.grid) for i in range(args.train_clouds)]
+    held = [make_cloud(R, 2000 + i, args.points, args.grid) for i in range(args.eval_clouds)]
     print(f"[train] clouds ready in {time.time() - t0:.1f}s; voxels per cloud "
           f"{[c['vox'].V for c in train]} on grids {[c['vox'].grid for c in train]}", flush=True)
 

@@ -78,3 +78,15 @@ def test_renderer_requires_gpu_and_library():
         pytest.skip("a GPU is present")
     with pytest.raises(RuntimeError):
         P.Renderer(0)
+
+
+def test_python_binding_surface():
+    """The binding modules import without a GPU and expose the documented names."""
+    from paper_2409_16504_amd import estimator, render
+    for name in ("build", "mean_neighbours", "arrays"):
+        assert callable(getattr(estimator.Voxels, name)), name
+    for name in ("adaptive_grid", "conv_forward", "conv_backward", "head_forward", "head_backward",
+                 "train_step", "ssim", "psnr"):
+        assert callable(getattr(estimator, name)), name
+    for name in ("render", "render_backward", "bins", "knn_pca", "timing", "timings"):
+        assert callable(getattr(render.Renderer, name)), name
