@@ -98,30 +98,28 @@ __global__ __launch_bounds__(kBlock) void k_composite(
       }
       uint64_t mask = __ballot(rel);
       while (mask) {
-        // quadratic forms of up to kGroup reaching splats first (independent of T, so their LDS
-        // reads overlap), then the alpha tests and blends in list order
+        // quadratic forms of up to kGroup reaching splats first (independent of T; the reads
+        // are unconditional, an empty slot re-reads entry c and is pushed above the cut, so all
+        // LDS reads issue before the first wait), then the alpha tests and blends in list order
         int kk[kGroup];
-        float qq[kGroup];
+        float qq[kGroup], oo[kGroup], zz[kGroup];
 #pragma unroll
         for (int j = 0; j < kGroup; ++j) {
-          kk[j] = mask ? c + (int)__builtin_ctzll(mask) : -1;
+          const bool ok = mask != 0;
+          kk[j] = ok ? c + (int)__builtin_ctzll(mask) : c;
           mask &= mask - 1;
-        }
-#pragma unroll
-        for (int j = 0; j < kGroup; ++j) {
-          qq[j] = cut2 + 1.0f;                            // above the cut: no blend
-          if (kk[j] >= 0) {
-            const float4 r0 = s_r0[kk[j]];
-            const float4 r1 = s_r1[kk[j]];
-            qq[j] = conic_q(r1.x, r1.y, r1.z, pxf - r0.x, pyf - r0.y);
-          }
+          const float4 r0 = s_r0[kk[j]];
+          const float4 r1 = s_r1[kk[j]];
+          const float q = conic_q(r1.x, r1.y, r1.z, pxf - r0.x, pyf - r0.y);
+          qq[j] = ok ? q : cut2 + 1.0f;
+          oo[j] = r0.z;
+          zz[j] = r0.w;
         }
 #pragma unroll
         for (int j = 0; j < kGroup; ++j) {
           if (done || !(qq[j] <= cut2)) continue;
           const int k = kk[j];
-          const float4 r0 = s_r0[k];
-          const float a = fminf(opt.alpha_max, r0.z * __expf(-0.5f * qq[j]));
+          const float a = fminf(opt.alpha_max, oo[j] * __expf(-0.5f * qq[j]));
           if (a < opt.alpha_min) continue;
           const float w = a * T;
           const float4 r2 = s_r2[k];
@@ -132,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void k_composite(
           acc3 = fmaf(w, r3.x, acc3);
           acc4 = fmaf(w, r3.y, acc4);
           acc5 = fmaf(w, r3.z, acc5);
-          acc6 = fmaf(w, r0.w, acc6);
+          acc6 = fmaf(w, zz[j], acc6);
           T = T * (1.0f - a);
           last = (int32_t)(b - start) + k + 1;
           if (T < opt.t_eps) done = true;

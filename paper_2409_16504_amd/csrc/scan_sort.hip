@@ -196,14 +196,13 @@ constexpr uint32_t kSortPrefix = 2u << 30;
 constexpr uint32_t kSortValue = (1u << 30) - 1;
 constexpr int kLookWindow = 32;
 
-// Digit histograms of every pass in one read of the keys, one partial histogram per block. Each
-// block takes partitions of 4096 keys
+// Digit histograms of every pass in one read of the keys. Each block takes partitions of 4096 keys
 // (16 per thread, all loads issued before any is used). Lanes of a wavefront holding the same digit
 // are matched with eight ballots and their count is added once, so the long runs of equal digits
 // cost one LDS atomic per run.
 template <typename K>
 __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, int64_t m,
-                                                    int n_passes, uint32_t* __restrict__ partial) {
+                                                    int n_passes, uint32_t* __restrict__ hist) {
   __shared__ uint32_t sh[kMaxPasses][kBins];
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   for (int p = 0; p < kMaxPasses; ++p) sh[p][tid] = 0;
@@ -236,18 +235,18 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, 
     }
   }
   __syncthreads();
-  // this block's counts, summed over blocks by k_digit_base (plain stores: no shared counters)
-  for (int p = 0; p < n_passes; ++p) partial[((int64_t)blockIdx.x * kMaxPasses + p) * kBins + tid] = sh[p][tid];
+  for (int p = 0; p < n_passes; ++p) {
+    const uint32_t v = sh[p][tid];
+    if (v) atomicAdd(&hist[p * kBins + tid], v);
+  }
 }
 
-// Sum of the blocks' partial histograms and exclusive scan over the 256 bins of each pass (one
-// block per pass).
-__global__ __launch_bounds__(256) void k_digit_base(const uint32_t* __restrict__ partial,
-                                                    int n_blocks, uint32_t* __restrict__ base) {
+// Exclusive scan over the 256 bins of each pass (one block per pass).
+__global__ __launch_bounds__(256) void k_digit_base(const uint32_t* __restrict__ hist,
+                                                    uint32_t* __restrict__ base) {
   __shared__ uint32_t s_wave[kWaves];
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-  uint32_t v = 0;
-  for (int b = 0; b < n_blocks; ++b) v += partial[((int64_t)b * kMaxPasses + blockIdx.x) * kBins + tid];
+  const uint32_t v = hist[blockIdx.x * kBins + tid];
   const uint32_t incl = wave_inclusive_scan(v);
   if (lane == kWave - 1) s_wave[wave] = incl;
   __syncthreads();
@@ -460,8 +459,7 @@ constexpr int kHistBlocks = 256;
 
 size_t sort_scratch_bytes(int64_t m) {
   const int64_t parts = (m + kPart - 1) / kPart;
-  return (size_t)((int64_t)kHistBlocks * kMaxPasses * kBins + kMaxPasses * kBins + 2 * parts * kBins) *
-             sizeof(uint32_t) + 256;
+  return (size_t)(2 * kMaxPasses * kBins + 2 * parts * kBins) * sizeof(uint32_t) + 256;
 }
 
 template <typename K>
@@ -471,18 +469,18 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
   if (m <= 1 || bits <= 0) return hipSuccess;
   const int n_passes = (bits + 7) / 8;
   const int64_t parts = (m + kPart - 1) / kPart;
-  // scratch: partial[kHistBlocks][8][256] | base[8][256] | status[2][parts][256]. Pass p reads
-  // status[p & 1] and clears its partitions' slice of the other buffer for pass p + 1, so only
-  // status[0] is cleared here.
-  uint32_t* partial = reinterpret_cast<uint32_t*>(scratch);
-  uint32_t* base = partial + (int64_t)kHistBlocks * kMaxPasses * kBins;
-  uint32_t* status0 = base + kMaxPasses * kBins;
-  uint32_t* status1 = status0 + parts * kBins;
-  hipError_t e = launch_fill_u32(status0, 0u, parts * kBins, s);
+  // scratch: hist[8][256] | status0[parts][256] | base[8][256] | status1[parts][256]. One fill
+  // clears the histograms and status0; pass p reads status[p & 1] and clears its partitions'
+  // slice of the other buffer for pass p + 1.
+  uint32_t* hist = reinterpret_cast<uint32_t*>(scratch);
+  uint32_t* status0 = hist + kMaxPasses * kBins;
+  uint32_t* base = status0 + parts * kBins;
+  uint32_t* status1 = base + kMaxPasses * kBins;
+  hipError_t e = launch_fill_u32(hist, 0u, kMaxPasses * kBins + parts * kBins, s);
   if (e != hipSuccess) return e;
   const int hblocks = (int)std::min<int64_t>(kHistBlocks, parts);
-  hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)hblocks), dim3(256), 0, s, k0, m, n_passes, partial);
-  hipLaunchKernelGGL(k_digit_base, dim3(n_passes), dim3(256), 0, s, partial, hblocks, base);
+  hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)hblocks), dim3(256), 0, s, k0, m, n_passes, hist);
+  hipLaunchKernelGGL(k_digit_base, dim3(n_passes), dim3(256), 0, s, hist, base);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   K *ki = k0, *ko = k1;
   uint32_t *vi = v0, *vo = v1;

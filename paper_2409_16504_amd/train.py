@@ -86,6 +86,8 @@ def main(argv=None):
     ap.add_argument("--res", type=int, default=512)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--grid", type=int, default=0, help="voxel grid edge (power of two); 0 = density-adaptive")
+    ap.add_argument("--cosine", action="store_true", help="cosine decay of the learning rate to 0.1x")
+    ap.add_argument("--params-out", default=None, help="also save the network parameters alone")
     ap.add_argument("--out", default=None)
     ap.add_argument("--resume", default=None)
     args = ap.parse_args(argv)
@@ -141,6 +143,8 @@ def main(argv=None):
     torch.cuda.synchronize()
     t1 = time.time()
     for step in range(args.steps):
+        if args.cosine:
+            opt.lr = args.lr * (0.1 + 0.45 * (1.0 + math.cos(math.pi * step / max(1, args.steps))))
         loss = train_step(est, opt, train, views)
         losses.append(loss)
         if step % 25 == 0 or step == args.steps - 1:
@@ -168,6 +172,8 @@ def main(argv=None):
                   after=after, loss_first=losses[0] if losses else None, loss_last=losses[-1] if losses else None,
                   inference_ms_per_cloud=infer_ms)
     print(json.dumps(report), flush=True)
+    if args.params_out:
+        torch.save(dict(params=[p.detach().cpu() for p in est.params], report=report), args.params_out)
     if args.out:
         torch.save(dict(params=[p.detach().cpu() for p in est.params], adam_m=[m.cpu() for m in opt.m],
                         adam_v=[v.cpu() for v in opt.v], adam_t=opt.t, losses=losses, report=report), args.out)
