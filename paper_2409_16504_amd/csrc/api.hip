@@ -112,7 +112,7 @@ struct pcs_context {
 
 struct pcs_state {
   pcs_context* ctx = nullptr;
-  DevBuf rec, keys, vals, ranges, t_final, n_contrib, canon, dcams;   // keys: u32 global tile ids
+  DevBuf rec, keys, vals, ranges, order, t_final, n_contrib, canon, dcams;   // keys: u32 tile ids
   pcs_gaussians g{};
   std::vector<pcs_camera> cams;
   pcs_options opt{};
@@ -333,6 +333,7 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   PCS_TRY(ensure(ctx->scan_scratch, scan_scratch_bytes(cn), "scan scratch"));
   PCS_TRY(ensure(ctx->small, kSmallWords * 4, "small"));
   PCS_TRY(ensure(st->ranges, 2 * total_tiles * sizeof(uint32_t), "tile ranges"));
+  PCS_TRY(ensure(st->order, total_tiles * sizeof(uint32_t), "tile order"));
   const int64_t HWC = (int64_t)W * H * n_cams;
   PCS_TRY(ensure(st->t_final, HWC * sizeof(float), "final transmittance"));
   PCS_TRY(ensure(st->n_contrib, HWC * sizeof(int32_t), "last contributor"));
@@ -421,11 +422,12 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   {
     StageTimer tm(ctx, ST_RANGES, s);
     PCS_HIP(launch_ranges(st->keys.as<uint32_t>(), m, total_tiles, st->ranges.as<uint32_t>(), s));
+    PCS_HIP(launch_tile_order(st->ranges.as<uint32_t>(), total_tiles, st->order.as<uint32_t>(), s));
   }
   {
     StageTimer tm(ctx, ST_COMPOSITE, s);
     PCS_HIP(launch_composite(n, n_cams, W, H, st->rec.as<float4>(), st->vals.as<uint32_t>(),
-                             st->ranges.as<uint32_t>(), dopt, *out, st->t_final.as<float>(),
+                             st->ranges.as<uint32_t>(), st->order.as<uint32_t>(), dopt, *out, st->t_final.as<float>(),
                              st->n_contrib.as<int32_t>(), s));
   }
   st->g = *g;
@@ -458,7 +460,8 @@ int pcs_render_backward(pcs_context* ctx, const pcs_state* st, const pcs_images*
   {
     StageTimer tm(ctx, ST_BWD_COMPOSITE, s);
     PCS_HIP(launch_composite_backward(st->n, st->C, st->W, st->H, st->rec.as<float4>(),
-                                      st->vals.as<uint32_t>(), st->ranges.as<uint32_t>(), dopt,
+                                      st->vals.as<uint32_t>(), st->ranges.as<uint32_t>(),
+                                      st->order.as<uint32_t>(), dopt,
                                       st->t_final.as<float>(), st->n_contrib.as<int32_t>(),
                                       *grad_out, ctx->sgrad.as<float>(), s));
   }

@@ -1,13 +1,12 @@
 // Per-tile front-to-back compositing (Section 3.1, Eq. 1-2) and its adjoint.
 //
-// One 256-thread block per 16x16 screen tile (four wave64s, each owning an 8x8 quadrant). The
-// tile's depth-sorted splat list is staged through LDS in batches of 256 records (the next batch
-// is fetched into registers while the current one is composited). Each wavefront first tests the
-// batch against its quadrant with the splats' ellipse bounding boxes (one lane per splat, one
-// ballot per 64 splats) and then walks only the splats that reach it, in list order: every pixel
-// tests the 3-sigma ellipse, evaluates alpha = o * exp(-q/2), and blends RGB, normal and depth
-// until its transmittance drops below t_eps. A block stops loading batches once every pixel has
-// terminated (block-wide vote).
+// Forward: one single-wavefront block per 8x8 quadrant of a 16x16 screen tile, tiles taken longest
+// list first. The wavefront streams the tile's depth-sorted list in batches of 64 records (one per
+// lane, the next batch fetched into registers while the current one is composited), keeps the
+// records whose ellipse bounding box reaches its quadrant, compacted into LDS in list order, and
+// walks them: every pixel tests the 3-sigma ellipse, evaluates alpha = o * exp(-q/2), and blends
+// RGB, normal and depth until its transmittance drops below t_eps. The quadrants of a tile run
+// independently, so none waits for another and each stops as soon as its own pixels are done.
 //
 // The adjoint walks the same list back to front from each pixel's last contributor, recovering
 // the transmittance by division, keeps a running sum of what lies behind each splat, and reduces
@@ -48,95 +47,105 @@ __device__ __forceinline__ bool touches_quadrant(float u, float v, float ex, flo
   return gx <= ex && gy <= ey;
 }
 
-__global__ __launch_bounds__(kBlock) void k_composite(
+// Block b of the forward pass composites quadrant (b / 8) % 4 of the tile at position
+// (b / 32) * 8 + b % 8 of the order: the four quadrants of a tile are blocks b, b + 8, b + 16,
+// b + 24, which the dispatcher deals to the same XCD (blocks go round-robin over the 8 XCDs), so
+// they share the tile's records in one L2. Returns false for positions past the last tile.
+__device__ __forceinline__ bool quadrant_of_block(int64_t b, int64_t total_tiles, int64_t& pos,
+                                                  int& quad) {
+  pos = (b / 32) * 8 + b % 8;
+  quad = (int)((b / 8) % 4);
+  return pos < total_tiles;
+}
+
+__global__ __launch_bounds__(kWave) void k_composite(
     int64_t n, int W, int H, int TX, int64_t tiles_per_cam, int64_t total_tiles,
     const float4* __restrict__ rec, const uint32_t* __restrict__ vals,
-    const uint32_t* __restrict__ ranges, DevOptions opt, float* __restrict__ out_rgb,
+    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, DevOptions opt,
+    float* __restrict__ out_rgb,
     float* __restrict__ out_nrm, float* __restrict__ out_depth, float* __restrict__ out_alpha,
     float* __restrict__ t_final, int32_t* __restrict__ n_contrib) {
-  __shared__ float4 s_r0[kBlock], s_r1[kBlock], s_r2[kBlock], s_r3[kBlock];
-  const int64_t tile = xcd_remap(blockIdx.x, total_tiles);
+  __shared__ float4 s_r0[kWave], s_r1[kWave], s_r2[kWave], s_r3[kWave];
+  __shared__ int32_t s_pos[kWave];
+  int64_t opos;
+  int quad;
+  if (!quadrant_of_block(blockIdx.x, total_tiles, opos, quad)) return;
+  const int64_t tile = order[opos];         // longest lists first
   const int64_t cam = tile / tiles_per_cam;
   const int64_t t = tile - cam * tiles_per_cam;
   const int tx = (int)(t % TX), ty = (int)(t / TX);
-  const int tid = threadIdx.x, lane = lane_id();
-  const TilePixel P = tile_pixel(tx, ty, tid);
+  const int lane = threadIdx.x;
+  const TilePixel P = tile_pixel(tx, ty, quad * kWave + lane);
   const bool inside = P.x < W && P.y < H;
   const float pxf = (float)P.x + 0.5f, pyf = (float)P.y + 0.5f;
   const uint32_t start = ranges[tile], end = ranges[total_tiles + tile];
   const float cut2 = opt.sigma_cut * opt.sigma_cut;
   const float4* rec_cam = rec + cam * n * kRecFloat4;
+  const uint64_t lt = lanemask_lt();
   float T = 1.0f;
   float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f, acc4 = 0.f, acc5 = 0.f, acc6 = 0.f;
   int32_t last = 0;
   bool done = !inside;
-  // records of the next batch travel in registers while the current batch is composited
+  // one record per lane; the next batch travels in registers while the current one is composited
   float4 p0, p1, p2, p3;
-  if (start + tid < end) {
-    const float4* r = rec_cam + (int64_t)min(vals[start + tid], (uint32_t)(n - 1)) * kRecFloat4;
+  if (start + lane < end) {
+    const float4* r = rec_cam + (int64_t)min(vals[start + lane], (uint32_t)(n - 1)) * kRecFloat4;
     p0 = r[0]; p1 = r[1]; p2 = r[2]; p3 = r[3];
   }
-  for (uint32_t b = start; b < end; b += kBlock) {
-    if (__syncthreads_count(done) == kBlock) break;
-    if (b + tid < end) {
-      s_r0[tid] = p0; s_r1[tid] = p1; s_r2[tid] = p2; s_r3[tid] = p3;
+  for (uint32_t b = start; b < end; b += kWave) {
+    if (__ballot(!done) == 0ull) break;              // every pixel of the quadrant is done
+    // keep the records whose padded ellipse box reaches the quadrant, compacted in list order
+    const bool rel = b + lane < end && touches_quadrant(p0.x, p0.y, p1.w, p2.w, P.qx0, P.qy0);
+    const uint64_t relmask = __ballot(rel);
+    if (rel) {
+      const int slot = __popcll(relmask & lt);
+      s_r0[slot] = p0; s_r1[slot] = p1; s_r2[slot] = p2; s_r3[slot] = p3;
+      s_pos[slot] = (int32_t)(b - start) + lane;
     }
-    __syncthreads();
-    const uint32_t nb = b + kBlock + tid;
+    const uint32_t nb = b + kWave + lane;
     if (nb < end) {
       const float4* r = rec_cam + (int64_t)min(vals[nb], (uint32_t)(n - 1)) * kRecFloat4;
       p0 = r[0]; p1 = r[1]; p2 = r[2]; p3 = r[3];
     }
-    const int cnt = (int)min((uint32_t)kBlock, end - b);
-    for (int c = 0; c < cnt; c += kWave) {
-      if (__ballot(!done) == 0ull) break;               // every pixel of this wavefront is done
-      const int e = c + lane;
-      bool rel = false;
-      if (e < cnt) {
-        const float4 a0 = s_r0[e];
-        rel = touches_quadrant(a0.x, a0.y, s_r1[e].w, s_r2[e].w, P.qx0, P.qy0);
+    __syncthreads();                                  // one wavefront: orders the LDS writes
+    const int nrel = __popcll(relmask);
+    for (int k0 = 0; k0 < nrel; k0 += kGroup) {
+      // quadratic forms of up to kGroup splats first (independent of T; unconditional reads,
+      // slots past the end re-read the last entry and are pushed above the cut), then the alpha
+      // tests and blends in list order
+      float qq[kGroup], oo[kGroup], zz[kGroup];
+#pragma unroll
+      for (int j = 0; j < kGroup; ++j) {
+        const int k = min(k0 + j, nrel - 1);
+        const float4 r0 = s_r0[k];
+        const float4 r1 = s_r1[k];
+        const float q = conic_q(r1.x, r1.y, r1.z, pxf - r0.x, pyf - r0.y);
+        qq[j] = k0 + j < nrel ? q : cut2 + 1.0f;
+        oo[j] = r0.z;
+        zz[j] = r0.w;
       }
-      uint64_t mask = __ballot(rel);
-      while (mask) {
-        // quadratic forms of up to kGroup reaching splats first (independent of T; the reads
-        // are unconditional, an empty slot re-reads entry c and is pushed above the cut, so all
-        // LDS reads issue before the first wait), then the alpha tests and blends in list order
-        int kk[kGroup];
-        float qq[kGroup], oo[kGroup], zz[kGroup];
 #pragma unroll
-        for (int j = 0; j < kGroup; ++j) {
-          const bool ok = mask != 0;
-          kk[j] = ok ? c + (int)__builtin_ctzll(mask) : c;
-          mask &= mask - 1;
-          const float4 r0 = s_r0[kk[j]];
-          const float4 r1 = s_r1[kk[j]];
-          const float q = conic_q(r1.x, r1.y, r1.z, pxf - r0.x, pyf - r0.y);
-          qq[j] = ok ? q : cut2 + 1.0f;
-          oo[j] = r0.z;
-          zz[j] = r0.w;
-        }
-#pragma unroll
-        for (int j = 0; j < kGroup; ++j) {
-          if (done || !(qq[j] <= cut2)) continue;
-          const int k = kk[j];
-          const float a = fminf(opt.alpha_max, oo[j] * __expf(-0.5f * qq[j]));
-          if (a < opt.alpha_min) continue;
-          const float w = a * T;
-          const float4 r2 = s_r2[k];
-          const float4 r3 = s_r3[k];
-          acc0 = fmaf(w, r2.x, acc0);
-          acc1 = fmaf(w, r2.y, acc1);
-          acc2 = fmaf(w, r2.z, acc2);
-          acc3 = fmaf(w, r3.x, acc3);
-          acc4 = fmaf(w, r3.y, acc4);
-          acc5 = fmaf(w, r3.z, acc5);
-          acc6 = fmaf(w, zz[j], acc6);
-          T = T * (1.0f - a);
-          last = (int32_t)(b - start) + k + 1;
-          if (T < opt.t_eps) done = true;
-        }
+      for (int j = 0; j < kGroup; ++j) {
+        if (done || !(qq[j] <= cut2)) continue;
+        const int k = k0 + j;
+        const float a = fminf(opt.alpha_max, oo[j] * __expf(-0.5f * qq[j]));
+        if (a < opt.alpha_min) continue;
+        const float w = a * T;
+        const float4 r2 = s_r2[k];
+        const float4 r3 = s_r3[k];
+        acc0 = fmaf(w, r2.x, acc0);
+        acc1 = fmaf(w, r2.y, acc1);
+        acc2 = fmaf(w, r2.z, acc2);
+        acc3 = fmaf(w, r3.x, acc3);
+        acc4 = fmaf(w, r3.y, acc4);
+        acc5 = fmaf(w, r3.z, acc5);
+        acc6 = fmaf(w, zz[j], acc6);
+        T = T * (1.0f - a);
+        last = s_pos[k] + 1;
+        if (T < opt.t_eps) done = true;
       }
     }
+    __syncthreads();                                  // reads done before the next batch lands
   }
   if (!inside) return;
   const int64_t HW = (int64_t)W * H;
@@ -159,14 +168,15 @@ __global__ __launch_bounds__(kBlock) void k_composite(
 __global__ __launch_bounds__(kBlock) void k_composite_bwd(
     int64_t n, int W, int H, int TX, int64_t tiles_per_cam, int64_t total_tiles,
     const float4* __restrict__ rec, const uint32_t* __restrict__ vals,
-    const uint32_t* __restrict__ ranges, DevOptions opt, const float* __restrict__ t_final,
+    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, DevOptions opt,
+    const float* __restrict__ t_final,
     const int32_t* __restrict__ n_contrib, const float* __restrict__ g_rgb,
     const float* __restrict__ g_nrm, const float* __restrict__ g_depth,
     float* __restrict__ sgrad, int64_t stride) {
   __shared__ float4 s_r0[kBlock], s_r1[kBlock], s_r2[kBlock], s_r3[kBlock];
   __shared__ uint32_t s_g[kBlock];
   __shared__ int32_t s_max;
-  const int64_t tile = xcd_remap(blockIdx.x, total_tiles);
+  const int64_t tile = order[blockIdx.x];   // longest lists first
   const int64_t cam = tile / tiles_per_cam;
   const int64_t t = tile - cam * tiles_per_cam;
   const int tx = (int)(t % TX), ty = (int)(t / TX);
@@ -434,22 +444,24 @@ __global__ __launch_bounds__(256) void k_project_bwd(
 }  // namespace
 
 hipError_t launch_composite(int64_t n, int n_cams, int W, int H, const float4* rec,
-                            const uint32_t* vals, const uint32_t* ranges, const DevOptions& opt,
-                            const pcs_images& out, float* t_final, int32_t* n_contrib,
-                            hipStream_t s) {
+                            const uint32_t* vals, const uint32_t* ranges, const uint32_t* order,
+                            const DevOptions& opt, const pcs_images& out, float* t_final,
+                            int32_t* n_contrib, hipStream_t s) {
   const int TX = (W + kTile - 1) / kTile, TY = (H + kTile - 1) / kTile;
   const int64_t tiles_per_cam = (int64_t)TX * TY;
   const int64_t total = tiles_per_cam * n_cams;
   if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_composite, dim3((unsigned)total), dim3(kBlock), 0, s, n, W, H, TX,
-                     tiles_per_cam, total, rec, vals, ranges, opt, out.rgb, out.normal, out.depth,
+  // four single-wavefront blocks per tile, in groups of 8 tiles (see quadrant_of_block)
+  const int64_t blocks = (total + 7) / 8 * 32;
+  hipLaunchKernelGGL(k_composite, dim3((unsigned)blocks), dim3(kWave), 0, s, n, W, H, TX,
+                     tiles_per_cam, total, rec, vals, ranges, order, opt, out.rgb, out.normal, out.depth,
                      out.alpha, t_final, n_contrib);
   return hipGetLastError();
 }
 
 hipError_t launch_composite_backward(int64_t n, int n_cams, int W, int H, const float4* rec,
                                      const uint32_t* vals, const uint32_t* ranges,
-                                     const DevOptions& opt, const float* t_final,
+                                     const uint32_t* order, const DevOptions& opt, const float* t_final,
                                      const int32_t* n_contrib, const pcs_images& grad_out,
                                      float* sgrad, hipStream_t s) {
   const int TX = (W + kTile - 1) / kTile, TY = (H + kTile - 1) / kTile;
@@ -457,7 +469,7 @@ hipError_t launch_composite_backward(int64_t n, int n_cams, int W, int H, const 
   const int64_t total = tiles_per_cam * n_cams;
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_composite_bwd, dim3((unsigned)total), dim3(kBlock), 0, s, n, W, H, TX,
-                     tiles_per_cam, total, rec, vals, ranges, opt, t_final, n_contrib,
+                     tiles_per_cam, total, rec, vals, ranges, order, opt, t_final, n_contrib,
                      grad_out.rgb, grad_out.normal, grad_out.depth, sgrad, n * n_cams);
   return hipGetLastError();
 }

@@ -104,19 +104,6 @@ __device__ __forceinline__ void wave_sum16_rows(const float (&v)[16], float (&ou
   }
 }
 
-// Block-to-tile map. Blocks are dealt round-robin to the 8 XCDs (block b runs on XCD b % 8);
-// this map hands each XCD groups of kTileGroup consecutive tiles (a strip of one tile row), so a
-// splat record shared by neighbouring tiles is mostly fetched into one XCD's L2, while the groups
-// of every XCD stay interleaved over the whole screen and the busy screen region is spread over
-// all XCDs. Blocks past the last full round of groups map one to one.
-constexpr int64_t kTileGroup = 4;
-__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
-  const int64_t full = nblocks - nblocks % (8 * kTileGroup);
-  if (bid >= full) return bid;
-  const int64_t xcd = bid % 8, slot = bid / 8;
-  return ((slot / kTileGroup) * 8 + xcd) * kTileGroup + slot % kTileGroup;
-}
-
 // ---- launchers (stream-ordered, return the launch error) ------------------------------------
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, float value, int64_t n, hipStream_t s);
@@ -159,21 +146,24 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
 hipError_t launch_ranges(const uint32_t* keys, int64_t m, int64_t n_tiles, uint32_t* ranges,
                          hipStream_t s);
 
+// Permutation of the tiles for compositing: longest lists first, empty tiles last.
+hipError_t launch_tile_order(const uint32_t* ranges, int64_t n_tiles, uint32_t* order, hipStream_t s);
+
 hipError_t launch_canonical_keys(const uint32_t* keys, const uint32_t* vals, int64_t m, int64_t n,
                                  int64_t tiles_per_cam, const float4* rec, uint64_t* out,
                                  hipStream_t s);
 
 hipError_t launch_composite(int64_t n, int n_cams, int W, int H, const float4* rec,
-                            const uint32_t* vals, const uint32_t* ranges, const DevOptions& opt,
-                            const pcs_images& out, float* t_final, int32_t* n_contrib,
-                            hipStream_t s);
+                            const uint32_t* vals, const uint32_t* ranges, const uint32_t* order,
+                            const DevOptions& opt, const pcs_images& out, float* t_final,
+                            int32_t* n_contrib, hipStream_t s);
 
 // Backward: per-(camera, Gaussian) screen-space gradient accumulators, planar [13][C*n]:
 // u, v, A, B, C, opacity, depth, r, g, b, nx, ny, nz.
 constexpr int kScreenGrads = 13;
 hipError_t launch_composite_backward(int64_t n, int n_cams, int W, int H, const float4* rec,
                                      const uint32_t* vals, const uint32_t* ranges,
-                                     const DevOptions& opt, const float* t_final,
+                                     const uint32_t* order, const DevOptions& opt, const float* t_final,
                                      const int32_t* n_contrib, const pcs_images& grad_out,
                                      float* sgrad, hipStream_t s);
 hipError_t launch_project_backward(int64_t n, int n_cams, const DevCamera* cams,

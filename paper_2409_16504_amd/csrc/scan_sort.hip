@@ -398,6 +398,42 @@ __global__ void k_ranges(const uint32_t* __restrict__ keys, int64_t m, int64_t n
   if (i == m - 1 || keys[i + 1] != t) ranges[n_tiles + t] = (uint32_t)(i + 1);
 }
 
+// Compositing order of the tiles, longest list first (a list-scheduling heuristic for blocks of
+// very unequal work): lengths are bucketed by 64 entries, buckets taken in descending order, empty
+// tiles last; the order inside a bucket is arbitrary. One block; it writes a permutation of all
+// tiles.
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderBuckets = 257;              // 256 length buckets + empty tiles
+__device__ __forceinline__ int order_bucket(uint32_t len) {
+  return len == 0 ? kOrderBuckets - 1 : 255 - (int)min(len >> 6, 255u);
+}
+
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint32_t* __restrict__ ranges,
+                                                              int64_t n_tiles,
+                                                              uint32_t* __restrict__ order) {
+  __shared__ uint32_t s_cnt[kOrderBuckets + 1];
+  const int tid = threadIdx.x;
+  for (int b = tid; b <= kOrderBuckets; b += kOrderThreads) s_cnt[b] = 0;
+  __syncthreads();
+  for (int64_t t = tid; t < n_tiles; t += kOrderThreads)
+    atomicAdd(&s_cnt[order_bucket(ranges[n_tiles + t] - ranges[t])], 1u);
+  __syncthreads();
+  if (tid < kWave) {                                // exclusive scan of the bucket counts
+    uint32_t carry = 0;
+    for (int b0 = 0; b0 < kOrderBuckets; b0 += kWave) {
+      const uint32_t v = b0 + tid < kOrderBuckets ? s_cnt[b0 + tid] : 0u;
+      const uint32_t incl = wave_inclusive_scan(v);
+      if (b0 + tid < kOrderBuckets) s_cnt[b0 + tid] = carry + incl - v;
+      carry += __shfl(incl, kWave - 1, kWave);
+    }
+  }
+  __syncthreads();
+  for (int64_t t = tid; t < n_tiles; t += kOrderThreads) {
+    const uint32_t pos = atomicAdd(&s_cnt[order_bucket(ranges[n_tiles + t] - ranges[t])], 1u);
+    if (pos < (uint64_t)n_tiles) order[pos] = (uint32_t)t;
+  }
+}
+
 // Canonical key (tile << 32) | fp32 depth bits, the depth read back from the splat record.
 __global__ void k_canonical(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
                             int64_t m, int64_t n, int64_t tiles_per_cam,
@@ -506,6 +542,12 @@ hipError_t launch_ranges(const uint32_t* keys, int64_t m, int64_t n_tiles, uint3
   hipError_t e = launch_fill_u32(ranges, 0u, 2 * n_tiles, s);
   if (e != hipSuccess || m == 0) return e;
   hipLaunchKernelGGL(k_ranges, dim3(blocks_for(m, 256)), dim3(256), 0, s, keys, m, n_tiles, ranges);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_order(const uint32_t* ranges, int64_t n_tiles, uint32_t* order, hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, s, ranges, n_tiles, order);
   return hipGetLastError();
 }
 
