@@ -454,8 +454,8 @@ int pcs_render_backward(pcs_context* ctx, const pcs_state* st, const pcs_images*
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int64_t cn = st->n * st->C;
   if (cn == 0) return PCS_OK;
-  PCS_TRY(ensure(ctx->sgrad, (size_t)cn * kScreenGrads * sizeof(float), "screen-space gradients"));
-  PCS_HIP(launch_fill_f32(ctx->sgrad.as<float>(), 0.0f, cn * kScreenGrads, s));
+  PCS_TRY(ensure(ctx->sgrad, (size_t)cn * kScreenStride * sizeof(float), "screen-space gradients"));
+  PCS_HIP(launch_fill_f32(ctx->sgrad.as<float>(), 0.0f, cn * kScreenStride, s));
   const DevOptions dopt = to_dev(st->opt);
   {
     StageTimer tm(ctx, ST_BWD_COMPOSITE, s);

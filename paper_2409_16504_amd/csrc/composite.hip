@@ -8,10 +8,11 @@
 // RGB, normal and depth until its transmittance drops below t_eps. The quadrants of a tile run
 // independently, so none waits for another and each stops as soon as its own pixels are done.
 //
-// The adjoint walks the same list back to front from each pixel's last contributor, recovering
-// the transmittance by division, keeps a running sum of what lies behind each splat, and reduces
-// each splat's 13 screen-space partials across the wavefront (lane-half exchanges leave them in
-// four lanes) before one atomic add per value.
+// The adjoint uses the same quadrant wavefronts and walks the list back to front from the
+// quadrant's furthest last contributor, recovering each pixel's transmittance by division, keeps a
+// running sum of what lies behind each splat, and reduces each splat's 13 screen-space partials
+// across the wavefront (lane-half exchanges leave them in four lanes) before one atomic add per
+// value.
 
 #include "projection.hpp"
 
@@ -19,7 +20,6 @@ namespace pcs {
 
 namespace {
 
-constexpr int kBlock = kTilePixels;   // 256 threads, one per pixel
 constexpr int kGroup = 4;             // reaching splats whose quadratic forms are evaluated together
 
 // Pixel of a thread: wavefront w owns the 8x8 quadrant (w & 1, w >> 1) of the 16x16 tile.
@@ -165,23 +165,26 @@ __global__ __launch_bounds__(kWave) void k_composite(
   if (n_contrib) n_contrib[cam * HW + pix] = last;
 }
 
-__global__ __launch_bounds__(kBlock) void k_composite_bwd(
+__global__ __launch_bounds__(kWave) void k_composite_bwd(
     int64_t n, int W, int H, int TX, int64_t tiles_per_cam, int64_t total_tiles,
     const float4* __restrict__ rec, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, DevOptions opt,
     const float* __restrict__ t_final,
     const int32_t* __restrict__ n_contrib, const float* __restrict__ g_rgb,
     const float* __restrict__ g_nrm, const float* __restrict__ g_depth,
-    float* __restrict__ sgrad, int64_t stride) {
-  __shared__ float4 s_r0[kBlock], s_r1[kBlock], s_r2[kBlock], s_r3[kBlock];
-  __shared__ uint32_t s_g[kBlock];
-  __shared__ int32_t s_max;
-  const int64_t tile = order[blockIdx.x];   // longest lists first
+    float* __restrict__ sgrad) {
+  __shared__ float4 s_r0[kWave], s_r1[kWave], s_r2[kWave], s_r3[kWave];
+  __shared__ uint32_t s_g[kWave];
+  __shared__ int32_t s_pos[kWave];
+  int64_t opos;
+  int quad;
+  if (!quadrant_of_block(blockIdx.x, total_tiles, opos, quad)) return;
+  const int64_t tile = order[opos];         // longest lists first
   const int64_t cam = tile / tiles_per_cam;
   const int64_t t = tile - cam * tiles_per_cam;
   const int tx = (int)(t % TX), ty = (int)(t / TX);
-  const int tid = threadIdx.x, lane = lane_id();
-  const TilePixel P = tile_pixel(tx, ty, tid);
+  const int lane = threadIdx.x;
+  const TilePixel P = tile_pixel(tx, ty, quad * kWave + lane);
   const bool inside = P.x < W && P.y < H;
   const float pxf = (float)P.x + 0.5f, pyf = (float)P.y + 0.5f;
   const uint32_t start = ranges[tile];
@@ -189,6 +192,7 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(
   const float4* rec_cam = rec + cam * n * kRecFloat4;
   const int64_t HW = (int64_t)W * H;
   const int64_t pix = (int64_t)P.y * W + P.x;
+  const uint64_t lt = lanemask_lt();
   float T = 1.0f;
   int32_t nc = 0;
   float g[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -200,105 +204,99 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(
     if (g_nrm) { g[3] = g_nrm[c3 + pix]; g[4] = g_nrm[c3 + HW + pix]; g[5] = g_nrm[c3 + 2 * HW + pix]; }
     if (g_depth) g[6] = g_depth[cam * HW + pix];
   }
-  // what lies behind the current splat: sum_{j>k} T_j a_j f_j + T_final * bg
-  float behind[7] = {T * opt.bg[0], T * opt.bg[1], T * opt.bg[2], 0.f, 0.f, 0.f, 0.f};
-  if (tid == 0) s_max = 0;
-  __syncthreads();
-  if (nc > 0) atomicMax(&s_max, nc);
-  __syncthreads();
-  const int32_t max_nc = s_max;
+  // g . (what lies behind the current splat), with behind = sum_{j>k} T_j a_j f_j + T_final * bg:
+  // g is fixed along the walk, so the seven-channel sum enters only through this dot product
+  float gb = T * fmaf(g[0], opt.bg[0], fmaf(g[1], opt.bg[1], g[2] * opt.bg[2]));
+  // the quadrant's furthest last contributor bounds the walk
+  int32_t max_nc = nc;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) max_nc = max(max_nc, __shfl_xor(max_nc, o, kWave));
   const int64_t base_idx = cam * n;
-  for (int32_t bend = max_nc; bend > 0; bend -= kBlock) {
-    const int32_t bstart = max(0, bend - kBlock);
-    __syncthreads();
-    const int32_t pos = bstart + tid;
+  // batches of 64 list positions, back to front; the batch below is fetched into registers while
+  // the current one is walked
+  float4 p0, p1, p2, p3;
+  uint32_t pg_idx = 0;
+  auto fetch = [&](int32_t bstart, int32_t bend) {
+    const int32_t pos = bstart + lane;
     if (pos < bend) {
-      const uint32_t gi = min(vals[start + pos], (uint32_t)(n - 1));
-      const float4* r = rec_cam + (int64_t)gi * kRecFloat4;
-      s_r0[tid] = r[0];
-      s_r1[tid] = r[1];
-      s_r2[tid] = r[2];
-      s_r3[tid] = r[3];
-      s_g[tid] = gi;
+      pg_idx = min(vals[start + pos], (uint32_t)(n - 1));
+      const float4* r = rec_cam + (int64_t)pg_idx * kRecFloat4;
+      p0 = r[0]; p1 = r[1]; p2 = r[2]; p3 = r[3];
     }
-    __syncthreads();
-    const int cnt = bend - bstart;
-    for (int c = ((cnt - 1) / kWave) * kWave; c >= 0; c -= kWave) {
-      const int e = c + lane;
-      bool rel = false;
-      if (e < cnt) {
-        const float4 a0 = s_r0[e];
-        rel = touches_quadrant(a0.x, a0.y, s_r1[e].w, s_r2[e].w, P.qx0, P.qy0);
-      }
-      uint64_t mask = __ballot(rel);
-      while (mask) {
-        const int hb = 63 - (int)__builtin_clzll(mask);
-        mask &= ~(1ull << hb);
-        const int k = c + hb;
-        const int32_t p = bstart + k;
-        float pg[kScreenGrads];
+  };
+  if (max_nc > 0) fetch(max(0, max_nc - kWave), max_nc);
+  for (int32_t bend = max_nc; bend > 0; bend -= kWave) {
+    const int32_t bstart = max(0, bend - kWave);
+    const bool rel = bstart + lane < bend && touches_quadrant(p0.x, p0.y, p1.w, p2.w, P.qx0, P.qy0);
+    const uint64_t relmask = __ballot(rel);
+    if (rel) {
+      const int slot = __popcll(relmask & lt);
+      s_r0[slot] = p0; s_r1[slot] = p1; s_r2[slot] = p2; s_r3[slot] = p3;
+      s_g[slot] = pg_idx;
+      s_pos[slot] = bstart + lane;
+    }
+    if (bstart > 0) fetch(max(0, bstart - kWave), bstart);
+    __syncthreads();                                  // one wavefront: orders the LDS writes
+    for (int k = __popcll(relmask) - 1; k >= 0; --k) {
+      float pg[kScreenGrads];
 #pragma unroll
-        for (int i = 0; i < kScreenGrads; ++i) pg[i] = 0.f;
-        bool contrib = false;
-        if (p < nc) {
-          const float4 r0 = s_r0[k];
-          const float4 r1 = s_r1[k];
-          const float dx = pxf - r0.x, dy = pyf - r0.y;
-          const float q = conic_q(r1.x, r1.y, r1.z, dx, dy);
-          if (q <= cut2) {
-            const float e = __expf(-0.5f * q);
-            const float araw = r0.z * e;
-            const float a = fminf(opt.alpha_max, araw);
-            if (a >= opt.alpha_min) {
-              contrib = true;
-              const float4 r2 = s_r2[k];
-              const float4 r3 = s_r3[k];
-              const float one_m = 1.0f - a;
-              T = T / one_m;                       // transmittance in front of this splat
-              const float w = a * T;
-              const float f[7] = {r2.x, r2.y, r2.z, r3.x, r3.y, r3.z, r0.w};
-              float dLda = 0.f;
-              const float inv = 1.0f / one_m;
-#pragma unroll
-              for (int ch = 0; ch < 7; ++ch) {
-                dLda = fmaf(g[ch], fmaf(T, f[ch], -behind[ch] * inv), dLda);
-                behind[ch] = fmaf(w, f[ch], behind[ch]);
-              }
-              pg[7] = g[0] * w;
-              pg[8] = g[1] * w;
-              pg[9] = g[2] * w;
-              pg[10] = g[3] * w;
-              pg[11] = g[4] * w;
-              pg[12] = g[5] * w;
-              pg[6] = g[6] * w;
-              if (!(araw > opt.alpha_max)) {
-                pg[5] = dLda * e;
-                const float dLdq = dLda * (-0.5f * a);
-                pg[2] = dLdq * dx * dx;
-                pg[3] = dLdq * 2.0f * dx * dy;
-                pg[4] = dLdq * dy * dy;
-                pg[0] = dLdq * (-2.0f * fmaf(r1.x, dx, r1.y * dy));
-                pg[1] = dLdq * (-2.0f * fmaf(r1.y, dx, r1.z * dy));
-              }
+      for (int i = 0; i < kScreenGrads; ++i) pg[i] = 0.f;
+      bool contrib = false;
+      if (s_pos[k] < nc) {
+        const float4 r0 = s_r0[k];
+        const float4 r1 = s_r1[k];
+        const float dx = pxf - r0.x, dy = pyf - r0.y;
+        const float q = conic_q(r1.x, r1.y, r1.z, dx, dy);
+        if (q <= cut2) {
+          const float e = __expf(-0.5f * q);
+          const float araw = r0.z * e;
+          const float a = fminf(opt.alpha_max, araw);
+          if (a >= opt.alpha_min) {
+            contrib = true;
+            const float4 r2 = s_r2[k];
+            const float4 r3 = s_r3[k];
+            const float inv = __builtin_amdgcn_rcpf(1.0f - a);
+            T = T * inv;                         // transmittance in front of this splat
+            const float w = a * T;
+            const float gf = fmaf(g[0], r2.x, fmaf(g[1], r2.y, fmaf(g[2], r2.z, fmaf(g[3], r3.x,
+                             fmaf(g[4], r3.y, fmaf(g[5], r3.z, g[6] * r0.w))))));
+            const float dLda = fmaf(T, gf, -gb * inv);
+            gb = fmaf(w, gf, gb);
+            pg[7] = g[0] * w;
+            pg[8] = g[1] * w;
+            pg[9] = g[2] * w;
+            pg[10] = g[3] * w;
+            pg[11] = g[4] * w;
+            pg[12] = g[5] * w;
+            pg[6] = g[6] * w;
+            if (!(araw > opt.alpha_max)) {
+              pg[5] = dLda * e;
+              const float dLdq = dLda * (-0.5f * a);
+              pg[2] = dLdq * dx * dx;
+              pg[3] = dLdq * 2.0f * dx * dy;
+              pg[4] = dLdq * dy * dy;
+              pg[0] = dLdq * (-2.0f * fmaf(r1.x, dx, r1.y * dy));
+              pg[1] = dLdq * (-2.0f * fmaf(r1.y, dx, r1.z * dy));
             }
           }
         }
-        if (__ballot(contrib) == 0ull) continue;   // wave-uniform
-        const int64_t dst = base_idx + s_g[k];
-        float v16[16], sv[4];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) v16[i] = i < kScreenGrads ? pg[i] : 0.0f;
-        wave_sum16_rows(v16, sv);
-        if ((lane & 15) == 15) {                     // one lane per row, four values each
-          const int row = lane >> 4;
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int i = 4 * row + j;
-            if (i < kScreenGrads && sv[j] != 0.0f) unsafeAtomicAdd(&sgrad[i * stride + dst], sv[j]);
-          }
-        }
       }
+      if (__ballot(contrib) == 0ull) continue;   // wave-uniform
+      const int64_t dst = base_idx + s_g[k];
+      float v16[16], sv[4];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v16[i] = i < kScreenGrads ? pg[i] : 0.0f;
+      wave_sum16_rows(v16, sv);
+      // sum i sits in lane 16 (i / 4) + 15, slot i % 4: bring it to lane i, then one atomic
+      // instruction adds all thirteen into the splat's 64-byte line
+      const int src = 16 * ((lane & 15) >> 2) + 15;
+      const float t0 = __shfl(sv[0], src, kWave), t1 = __shfl(sv[1], src, kWave);
+      const float t2 = __shfl(sv[2], src, kWave), t3 = __shfl(sv[3], src, kWave);
+      const int j = lane & 3;
+      const float val = j == 0 ? t0 : (j == 1 ? t1 : (j == 2 ? t2 : t3));
+      if (lane < kScreenGrads && val != 0.0f) unsafeAtomicAdd(&sgrad[dst * kScreenStride + lane], val);
     }
+    __syncthreads();                                  // reads done before the next batch lands
   }
 }
 
@@ -307,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(
 __global__ __launch_bounds__(256) void k_project_bwd(
     int64_t n, int n_cams, const DevCamera* __restrict__ cams, DevOptions opt,
     const float* __restrict__ mean, const float* __restrict__ quat, const float* __restrict__ scale,
-    const float* __restrict__ sgrad, int64_t stride, float* __restrict__ d_mean,
+    const float* __restrict__ sgrad, float* __restrict__ d_mean,
     float* __restrict__ d_cov, float* __restrict__ d_quat, float* __restrict__ d_scale,
     float* __restrict__ d_opac, float* __restrict__ d_rgb, float* __restrict__ d_nrm) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -320,13 +318,16 @@ __global__ __launch_bounds__(256) void k_project_bwd(
   ProjGeo G;
   bool any = false;
   for (int c = 0; c < n_cams; ++c) {
-    float sg[kScreenGrads];
+    float sg[16];
+    const float4* line = reinterpret_cast<const float4*>(sgrad + ((int64_t)c * n + i) * kScreenStride);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 v = line[q];
+      sg[4 * q] = v.x; sg[4 * q + 1] = v.y; sg[4 * q + 2] = v.z; sg[4 * q + 3] = v.w;
+    }
     bool nz = false;
 #pragma unroll
-    for (int k = 0; k < kScreenGrads; ++k) {
-      sg[k] = sgrad[k * stride + (int64_t)c * n + i];
-      nz = nz || sg[k] != 0.0f;
-    }
+    for (int k = 0; k < kScreenGrads; ++k) nz = nz || sg[k] != 0.0f;
     if (!nz) continue;
     any = true;
     const DevCamera& cam = cams[c];
@@ -468,9 +469,10 @@ hipError_t launch_composite_backward(int64_t n, int n_cams, int W, int H, const 
   const int64_t tiles_per_cam = (int64_t)TX * TY;
   const int64_t total = tiles_per_cam * n_cams;
   if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_composite_bwd, dim3((unsigned)total), dim3(kBlock), 0, s, n, W, H, TX,
+  const int64_t blocks = (total + 7) / 8 * 32;      // four single-wavefront blocks per tile
+  hipLaunchKernelGGL(k_composite_bwd, dim3((unsigned)blocks), dim3(kWave), 0, s, n, W, H, TX,
                      tiles_per_cam, total, rec, vals, ranges, order, opt, t_final, n_contrib,
-                     grad_out.rgb, grad_out.normal, grad_out.depth, sgrad, n * n_cams);
+                     grad_out.rgb, grad_out.normal, grad_out.depth, sgrad);
   return hipGetLastError();
 }
 
@@ -479,7 +481,7 @@ hipError_t launch_project_backward(int64_t n, int n_cams, const DevCamera* cams,
                                    const float* sgrad, const pcs_grads& grads, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, n_cams,
-                     cams, opt, g.mean, g.quat, g.scale, sgrad, n * n_cams, grads.mean, grads.cov6,
+                     cams, opt, g.mean, g.quat, g.scale, sgrad, grads.mean, grads.cov6,
                      grads.quat, grads.scale, grads.opacity, grads.rgb, grads.normal);
   return hipGetLastError();
 }

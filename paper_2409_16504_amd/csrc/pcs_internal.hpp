@@ -158,9 +158,11 @@ hipError_t launch_composite(int64_t n, int n_cams, int W, int H, const float4* r
                             const DevOptions& opt, const pcs_images& out, float* t_final,
                             int32_t* n_contrib, hipStream_t s);
 
-// Backward: per-(camera, Gaussian) screen-space gradient accumulators, planar [13][C*n]:
-// u, v, A, B, C, opacity, depth, r, g, b, nx, ny, nz.
+// Backward: per-(camera, Gaussian) screen-space gradient accumulators, [C*n][16] (one 64-byte
+// line per splat, so a splat's partials from one wavefront go out as one atomic request):
+// u, v, A, B, C, opacity, depth, r, g, b, nx, ny, nz, three unused.
 constexpr int kScreenGrads = 13;
+constexpr int kScreenStride = 16;
 hipError_t launch_composite_backward(int64_t n, int n_cams, int W, int H, const float4* rec,
                                      const uint32_t* vals, const uint32_t* ranges,
                                      const uint32_t* order, const DevOptions& opt, const float* t_final,
