@@ -275,12 +275,25 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
   uint32_t val[kItems];
   uint32_t rank[kItems];
   const uint64_t lt_mask = lanemask_lt();
+  // every load issued before the first is used
 #pragma unroll
   for (int it = 0; it < kItems; ++it) {
     const int64_t pos = wbase + (int64_t)it * kWave + lane;
-    const bool valid = pos < m;
-    key[it] = valid ? kin[pos] : (K)0;
-    val[it] = valid ? vin[pos] : 0u;
+    key[it] = pos < m ? kin[pos] : (K)0;
+  }
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
+    const int64_t pos = wbase + (int64_t)it * kWave + lane;
+    val[it] = pos < m ? vin[pos] : 0u;
+  }
+  // rank within the wave: lanes holding the same digit are matched with eight ballots; the lowest
+  // of them adds the run to the wave's digit counter (an LDS atomic returning the old count, so
+  // the items' updates pipeline instead of waiting on each other) and its peers read the old count
+  // from it
+  int leader[kItems];
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
+    const bool valid = wbase + (int64_t)it * kWave + lane < m;
     const uint32_t d = (uint32_t)(key[it] >> shift) & 0xFF;
     uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -291,9 +304,14 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
     }
     const uint32_t below = __popcll(peers & lt_mask);
     uint32_t old = 0;
-    if (valid) old = s_hist[wave][d];
-    if (valid && below == 0) s_hist[wave][d] = old + (uint32_t)__popcll(peers);
-    rank[it] = old + below;
+    if (valid && below == 0) old = atomicAdd(&s_hist[wave][d], (uint32_t)__popcll(peers));
+    leader[it] = valid ? (int)__builtin_ctzll(peers) : lane;
+    rank[it] = old + below;                     // the leader's old count arrives below
+  }
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
+    const uint32_t lead_old = __shfl(rank[it], leader[it], kWave);   // the leader holds its old count
+    rank[it] = lane == leader[it] ? lead_old : lead_old + rank[it];
   }
   __syncthreads();
   // per digit (thread = digit): offsets of each wave's run and the block total
@@ -412,11 +430,29 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint32_t* __
                                                               int64_t n_tiles,
                                                               uint32_t* __restrict__ order) {
   __shared__ uint32_t s_cnt[kOrderBuckets + 1];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = lane_id();
+  const uint64_t lt = lanemask_lt();
+  constexpr int kPer = 8;                          // tiles per thread per step, loads issued first
+  constexpr int64_t kStep = (int64_t)kOrderThreads * kPer;
   for (int b = tid; b <= kOrderBuckets; b += kOrderThreads) s_cnt[b] = 0;
   __syncthreads();
-  for (int64_t t = tid; t < n_tiles; t += kOrderThreads)
-    atomicAdd(&s_cnt[order_bucket(ranges[n_tiles + t] - ranges[t])], 1u);
+  for (int64_t t0 = 0; t0 < n_tiles; t0 += kStep) {
+    uint32_t len[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int64_t t = t0 + (int64_t)j * kOrderThreads + tid;
+      len[j] = t < n_tiles ? ranges[n_tiles + t] - ranges[t] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int64_t t = t0 + (int64_t)j * kOrderThreads + tid;
+      const bool valid = t < n_tiles;
+      // empty tiles, most of a frame, are counted once per wavefront
+      const uint64_t em = __ballot(valid && len[j] == 0);
+      if (em && lane == (int)__builtin_ctzll(em)) atomicAdd(&s_cnt[kOrderBuckets - 1], (uint32_t)__popcll(em));
+      if (valid && len[j] != 0) atomicAdd(&s_cnt[order_bucket(len[j])], 1u);
+    }
+  }
   __syncthreads();
   if (tid < kWave) {                                // exclusive scan of the bucket counts
     uint32_t carry = 0;
@@ -428,9 +464,26 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint32_t* __
     }
   }
   __syncthreads();
-  for (int64_t t = tid; t < n_tiles; t += kOrderThreads) {
-    const uint32_t pos = atomicAdd(&s_cnt[order_bucket(ranges[n_tiles + t] - ranges[t])], 1u);
-    if (pos < (uint64_t)n_tiles) order[pos] = (uint32_t)t;
+  for (int64_t t0 = 0; t0 < n_tiles; t0 += kStep) {
+    uint32_t len[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int64_t t = t0 + (int64_t)j * kOrderThreads + tid;
+      len[j] = t < n_tiles ? ranges[n_tiles + t] - ranges[t] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int64_t t = t0 + (int64_t)j * kOrderThreads + tid;
+      const bool valid = t < n_tiles;
+      const uint64_t em = __ballot(valid && len[j] == 0);
+      uint32_t base = 0;
+      if (em && lane == (int)__builtin_ctzll(em)) base = atomicAdd(&s_cnt[kOrderBuckets - 1], (uint32_t)__popcll(em));
+      if (em) base = __shfl(base, (int)__builtin_ctzll(em), kWave);
+      uint32_t pos;
+      if (len[j] == 0) pos = base + (uint32_t)__popcll(em & lt);
+      else pos = valid ? atomicAdd(&s_cnt[order_bucket(len[j])], 1u) : 0u;
+      if (valid && pos < (uint64_t)n_tiles) order[pos] = (uint32_t)t;
+    }
   }
 }
 
