@@ -98,17 +98,24 @@ def main():
     out = R.render(g, cams, opts)
     for _ in range(args.warmup):
         R.render(g, cams, opts, out=out)
+    # timed frames: HIP events only around the compositing kernel (the roofline's kernel), so the
+    # frame time carries no per-stage instrumentation
     torch.cuda.synchronize()
-    R.timing(True)
+    R.timing(True, stages=["composite"])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for _ in range(args.steps):
         R.render(g, cams, opts, out=out)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    stages = R.timings()
+    composite_ms = R.timings()["composite"][0] / args.steps
     ms_per_step = (t2 - t1) * 1e3 / args.steps
     print(f"[bench] {args.steps} frames: {ms_per_step:.3f} ms/frame", file=sys.stderr, flush=True)
+    # per-stage breakdown from a separate run of the same frames with events around every stage
+    R.timing(True)
+    for _ in range(args.steps):
+        R.render(g, cams, opts, out=out)
+    stages = R.timings()
 
     # instance count and visible splats of this frame (from a state export)
     st = P.RenderState(R)
@@ -123,7 +130,8 @@ def main():
     if not args.no_cpu_baseline:
         cpu, visits, blends = cpu_baseline(xyz, rgb, cams)
 
-    roof = roofline(per_stage, args.n, m, bins, visits, blends)
+    roof = roofline(dict(per_stage, composite=composite_ms), args.n, m, bins, visits, blends)
+    stage_roof = stage_rooflines(per_stage, args.n, m, bins, args.width, args.height)
     extras = None if args.no_extras else extra_workloads(R)
     gap = None if args.no_extras else psnr_gap(R)
     if extras is not None:
@@ -137,7 +145,7 @@ def main():
                     n_gaussians=args.n, width=args.width, height=args.height, cameras=1),
         ms_per_frame=ms_per_step, instances=m, knn_pca_ms=knn_ms,
         stage_ms={k: round(v, 5) for k, v in per_stage.items()},
-        roofline=roof, cpu_baseline=cpu, psnr_gap_db=None if gap is None else gap["gap_db"], extras=extras,
+        roofline=roof, stage_roofline=stage_roof, cpu_baseline=cpu, psnr_gap_db=None if gap is None else gap["gap_db"], extras=extras,
     )
     print(json.dumps(line), flush=True)
 
@@ -256,6 +264,30 @@ def psnr_gap(R):
                 workload=f"2 held-out procedural clouds ({rep['points']} points, seeds 2000-2001) x "
                          f"{rep['views']} orbit views at {rep['res']}x{rep['res']}; ground truth = plain render "
                          "of the 8x denser unquantised sample; kNN-PCA kappa chosen on the training clouds")
+
+
+def stage_rooflines(per_stage, n, m, bins, W, H):
+    """Algorithmic HBM bytes of every ordering stage (per frame) over its measured time, against the
+    8 TB/s peak. Bytes per unit as stated in the design doc."""
+    vis = int(np.unique(bins["vals"]).size) if m else 0
+    z = (bins["keys"] & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    depth_bits = int(z.max() - z.min()).bit_length() if m else 0
+    tiles = int(bins["ranges"].shape[1])
+    tile_bits = int(tiles - 1).bit_length()
+    byts = {
+        "project": n * PROJECT_READ_B + vis * PROJECT_WRITE_VIS_B + (n - vis) * PROJECT_WRITE_CULL_B,
+        "scan": n * 12,                                            # order, gathered count, offset
+        "binning": vis * 28 + m * 8,                               # order/count/meta/offset; key+value
+        "sort": n * (28 + 4 + SORT_PASS_B * ((depth_bits + 7) // 8)) +   # depth keys, hist, passes
+                m * (4 + SORT_PASS_B * ((tile_bits + 7) // 8)),
+        "ranges": m * 4 + tiles * 16,                              # keys; ranges fill + order
+    }
+    out = {}
+    for k, b in byts.items():
+        if k in per_stage and per_stage[k] > 0:
+            gbs = b / (per_stage[k] * 1e-3) / 1e9
+            out[k] = dict(ms=round(per_stage[k], 5), bytes=int(b), gbs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4))
+    return out
 
 
 def roofline(per_stage, n, m, bins, visits, blends):

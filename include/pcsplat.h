@@ -123,6 +123,9 @@ void pcs_context_destroy(pcs_context* ctx);
  * head, head_backward) plus per-stage launch counts
  * and synchronises the stream. */
 int pcs_context_timing(pcs_context* ctx, int enable);
+/* As pcs_context_timing(ctx, 1), but events are recorded only around the stages whose bit
+ * (1 << stage index, order above) is set in stage_mask; 0 disables timing. */
+int pcs_context_timing_stages(pcs_context* ctx, uint32_t stage_mask);
 int pcs_context_timings(pcs_context* ctx, double* ms, int64_t* launches, int cap, void* stream);
 
 int pcs_state_create(pcs_context* ctx, pcs_state** out);

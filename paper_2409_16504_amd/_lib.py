@@ -19,6 +19,7 @@ STAGES = ("project", "scan", "binning", "sort", "ranges", "composite", "backward
           "backward_project", "knn_pca", "voxelize", "conv", "conv_backward", "head", "head_backward")
 
 EXPORTED = ("pcs_last_error", "pcs_context_create", "pcs_context_destroy", "pcs_context_timing",
+            "pcs_context_timing_stages",
             "pcs_context_timings", "pcs_state_create", "pcs_state_destroy", "pcs_options_default",
             "pcs_render_forward", "pcs_render_backward", "pcs_state_bins", "pcs_knn_pca",
             "pcs_voxels_create", "pcs_voxels_destroy", "pcs_voxelize", "pcs_voxels_get",
@@ -77,6 +78,7 @@ def load():
     L.pcs_context_destroy.argtypes = [c_vp]
     L.pcs_context_destroy.restype = None
     L.pcs_context_timing.argtypes = [c_vp, ctypes.c_int]
+    L.pcs_context_timing_stages.argtypes = [c_vp, ctypes.c_uint32]
     L.pcs_context_timings.argtypes = [c_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_i64),
                                       ctypes.c_int, c_vp]
     L.pcs_state_create.argtypes = [c_vp, ctypes.POINTER(c_vp)]
@@ -91,7 +93,8 @@ def load():
                                  ctypes.POINTER(c_vp), ctypes.POINTER(c_i64), ctypes.POINTER(c_vp),
                                  ctypes.POINTER(c_vp)]
     L.pcs_knn_pca.argtypes = [c_vp, c_vp, c_i64, c_i32, c_f, c_f, c_vp, c_vp, c_vp, c_vp]
-    for name in ("pcs_context_create", "pcs_context_timing", "pcs_context_timings", "pcs_state_create",
+    for name in ("pcs_context_create", "pcs_context_timing", "pcs_context_timing_stages",
+                 "pcs_context_timings", "pcs_state_create",
                  "pcs_render_forward", "pcs_render_backward", "pcs_state_bins", "pcs_knn_pca",
             "pcs_voxels_create", "pcs_voxels_destroy", "pcs_voxelize", "pcs_voxels_get",
             "pcs_subm_conv_forward", "pcs_subm_conv_backward", "pcs_estimator_head_forward",

@@ -95,11 +95,13 @@ struct pcs_state;
 struct pcs_context {
   int device = 0;
   DevBuf counts, offsets, meta, keys_alt, vals_alt, scan_scratch, sort_scratch, sgrad, small;
-  DevBuf dkeys, dkeys_alt, dvals, dvals_alt;   // depth sort of the (camera, Gaussian) splats
+  DevBuf dkeys, dkeys_alt, dvals, dvals_alt, dsort_scratch;   // depth sort of the splats
   DevBuf knn_scratch, conv_tmp, wt_tmp;
   uint32_t* host_small = nullptr;   // pinned 4 KiB: readback of the small device words
+  hipEvent_t counts_ready = nullptr;  // recorded after the instance-count read-back
   pcs_state* internal = nullptr;    // state used when the caller passes none
   bool timing = false;
+  uint32_t stage_mask = ~0u;        // stages whose launches are timed
   struct Ev {
     hipEvent_t a, b;
     int stage;
@@ -118,8 +120,6 @@ struct pcs_state {
   pcs_options opt{};
   int W = 0, H = 0, C = 0;
   int64_t n = 0, m = 0, n_tiles = 0;
-  int depth_bits = 0;
-  uint32_t zmin = 0;
   bool valid = false;
 };
 
@@ -141,7 +141,7 @@ struct StageTimer {
   hipStream_t s;
   size_t slot = (size_t)-1;
   StageTimer(pcs_context* c, int st, hipStream_t stream) : ctx(c), stage(st), s(stream) {
-    if (!ctx->timing) return;
+    if (!ctx->timing || !((ctx->stage_mask >> stage) & 1u)) return;
     if (ctx->used == ctx->pool.size()) {
       pcs_context::Ev ev{};
       if (hipEventCreate(&ev.a) != hipSuccess || hipEventCreate(&ev.b) != hipSuccess) return;
@@ -244,12 +244,21 @@ void pcs_context_destroy(pcs_context* ctx) {
   }
   delete ctx->internal;
   if (ctx->host_small) (void)hipHostFree(ctx->host_small);
+  if (ctx->counts_ready) (void)hipEventDestroy(ctx->counts_ready);
   delete ctx;
+}
+
+int pcs_context_timing_stages(pcs_context* ctx, uint32_t stage_mask) {
+  if (!ctx) return fail(PCS_ERR_INVALID_ARG, "context is NULL");
+  PCS_TRY(pcs_context_timing(ctx, stage_mask != 0u));
+  ctx->stage_mask = stage_mask;
+  return PCS_OK;
 }
 
 int pcs_context_timing(pcs_context* ctx, int enable) {
   if (!ctx) return fail(PCS_ERR_INVALID_ARG, "context is NULL");
   ctx->timing = enable != 0;
+  ctx->stage_mask = ~0u;
   ctx->used = 0;
   std::fill(std::begin(ctx->acc_ms), std::end(ctx->acc_ms), 0.0);
   std::fill(std::begin(ctx->launches), std::end(ctx->launches), int64_t(0));
@@ -341,19 +350,55 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   uint64_t* d_total = ctx->small.as<uint64_t>();
   uint32_t* d_zrange = ctx->small.as<uint32_t>() + 2;
   auto* d_counts = reinterpret_cast<unsigned long long*>(ctx->small.as<uint32_t>() + kCountWord);
+  uint32_t* d_depth = ctx->small.as<uint32_t>() + kDepthWord;   // passes, depth bits, min depth bits
   PCS_HIP(launch_init_small(ctx->small.as<uint32_t>(), s));
   {
     StageTimer tm(ctx, ST_PROJECT, s);
     PCS_HIP(launch_project(n, n_cams, st->dcams.as<DevCamera>(), dopt, *g, st->rec.as<float4>(),
                            ctx->meta.as<uint4>(), ctx->counts.as<uint32_t>(), d_zrange, d_counts, s));
   }
+  // The instance total goes to the host right after the projection; the (camera, depth) order
+  // and the prefix sum of the tile counts in that order need nothing from the host (the depth
+  // range is read from the projection's slots on the device, and sort passes beyond the bits that
+  // range needs return at once), so they are queued behind the read-back and the host waits only
+  // for the read-back: it sizes the tile sort while the GPU sorts by depth.
+  if (!ctx->counts_ready) PCS_HIP(hipEventCreateWithFlags(&ctx->counts_ready, hipEventDisableTiming));
   PCS_HIP(hipMemcpyAsync(ctx->host_small, ctx->small.p, kSmallWords * 4, hipMemcpyDeviceToHost, s));
-  PCS_HIP(hipStreamSynchronize(s));
-  uint32_t zmin = 0xFFFFFFFFu, zmax = 0u;
+  PCS_HIP(hipEventRecord(ctx->counts_ready, s));
+  const int cam_bits = bit_length((uint64_t)(n_cams - 1));
+  const bool wide = n_cams > 1;                       // camera field + up to 31 depth bits
+  const int dsort_max_bits = cam_bits + 31;
+  const size_t dkey_bytes = wide ? sizeof(uint64_t) : sizeof(uint32_t);
+  PCS_TRY(ensure(ctx->dkeys, cn1 * dkey_bytes, "depth keys"));
+  PCS_TRY(ensure(ctx->dkeys_alt, cn1 * dkey_bytes, "depth keys (alternate)"));
+  PCS_TRY(ensure(ctx->dvals, cn1 * sizeof(uint32_t), "depth order"));
+  PCS_TRY(ensure(ctx->dvals_alt, cn1 * sizeof(uint32_t), "depth order (alternate)"));
+  PCS_TRY(ensure(ctx->dsort_scratch, sort_scratch_bytes(cn), "depth sort scratch"));
+  if (cn > 0) {
+    StageTimer tm(ctx, ST_SORT, s);
+    bool unused = false;
+    if (wide) {
+      PCS_HIP(launch_depth_keys(n, n_cams, ctx->meta.as<uint4>(), ctx->counts.as<uint32_t>(), d_zrange,
+                                cam_bits, d_depth, ctx->dkeys.as<uint64_t>(), ctx->dvals.as<uint32_t>(), s));
+      PCS_HIP(launch_sort(ctx->dkeys.as<uint64_t>(), ctx->dvals.as<uint32_t>(), ctx->dkeys_alt.as<uint64_t>(),
+                          ctx->dvals_alt.as<uint32_t>(), cn, dsort_max_bits, ctx->dsort_scratch.p, s,
+                          &unused, d_depth));
+    } else {
+      PCS_HIP(launch_depth_keys(n, n_cams, ctx->meta.as<uint4>(), ctx->counts.as<uint32_t>(), d_zrange,
+                                cam_bits, d_depth, ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(), s));
+      PCS_HIP(launch_sort(ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(), ctx->dkeys_alt.as<uint32_t>(),
+                          ctx->dvals_alt.as<uint32_t>(), cn, dsort_max_bits, ctx->dsort_scratch.p, s,
+                          &unused, d_depth));
+    }
+  }
+  if (cn > 0) {
+    StageTimer tm(ctx, ST_SCAN, s);
+    PCS_HIP(launch_scan(ctx->counts.as<uint32_t>(), ctx->dvals.as<uint32_t>(), ctx->dvals_alt.as<uint32_t>(),
+                        d_depth, ctx->offsets.as<uint32_t>(), cn, d_total, ctx->scan_scratch.p, s));
+  }
+  PCS_HIP(hipEventSynchronize(ctx->counts_ready));
   uint64_t m64 = 0;
   for (int i = 0; i < kZSlots; ++i) {
-    zmin = std::min(zmin, ctx->host_small[2 + i]);
-    zmax = std::max(zmax, ctx->host_small[2 + kZSlots + i]);
     uint64_t c;
     std::memcpy(&c, ctx->host_small + kCountWord + 2 * i, 8);
     m64 += c;
@@ -361,50 +406,18 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   if (m64 >= (uint64_t(1) << 30))
     return fail(PCS_ERR_UNSUPPORTED, "instance count " + std::to_string(m64) + " is not below 2^30");
   const int64_t m = (int64_t)m64;
-  const int depth_bits = m > 0 ? bit_length((uint64_t)(zmax - zmin)) : 0;
-  const int cam_bits = bit_length((uint64_t)(n_cams - 1));
-  const int dsort_bits = depth_bits + cam_bits;
   const int tile_bits = bit_length((uint64_t)(total_tiles - 1));
 
   PCS_TRY(ensure(st->keys, std::max<int64_t>(m, 1) * sizeof(uint32_t), "keys"));
   PCS_TRY(ensure(st->vals, std::max<int64_t>(m, 1) * sizeof(uint32_t), "values"));
   PCS_TRY(ensure(ctx->keys_alt, std::max<int64_t>(m, 1) * sizeof(uint32_t), "keys (alternate)"));
   PCS_TRY(ensure(ctx->vals_alt, std::max<int64_t>(m, 1) * sizeof(uint32_t), "values (alternate)"));
-  PCS_TRY(ensure(ctx->sort_scratch, sort_scratch_bytes(std::max(m, cn)), "sort scratch"));
-  const size_t dkey_bytes = dsort_bits > 32 ? sizeof(uint64_t) : sizeof(uint32_t);
-  PCS_TRY(ensure(ctx->dkeys, cn1 * dkey_bytes, "depth keys"));
-  PCS_TRY(ensure(ctx->dkeys_alt, cn1 * dkey_bytes, "depth keys (alternate)"));
-  PCS_TRY(ensure(ctx->dvals, cn1 * sizeof(uint32_t), "depth order"));
-  PCS_TRY(ensure(ctx->dvals_alt, cn1 * sizeof(uint32_t), "depth order (alternate)"));
+  PCS_TRY(ensure(ctx->sort_scratch, sort_scratch_bytes(m), "sort scratch"));
   if (m > 0) {
-    // (camera, depth) order of the splats
-    const uint32_t* order = nullptr;
-    {
-      StageTimer tm(ctx, ST_SORT, s);
-      bool in_alt = false;
-      if (dsort_bits > 32) {
-        PCS_HIP(launch_depth_keys(n, n_cams, ctx->meta.as<uint4>(), ctx->counts.as<uint32_t>(), zmin,
-                                  depth_bits, ctx->dkeys.as<uint64_t>(), ctx->dvals.as<uint32_t>(), s));
-        PCS_HIP(launch_sort(ctx->dkeys.as<uint64_t>(), ctx->dvals.as<uint32_t>(),
-                            ctx->dkeys_alt.as<uint64_t>(), ctx->dvals_alt.as<uint32_t>(), cn, dsort_bits,
-                            ctx->sort_scratch.p, s, &in_alt));
-      } else {
-        PCS_HIP(launch_depth_keys(n, n_cams, ctx->meta.as<uint4>(), ctx->counts.as<uint32_t>(), zmin,
-                                  depth_bits, ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(), s));
-        PCS_HIP(launch_sort(ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(),
-                            ctx->dkeys_alt.as<uint32_t>(), ctx->dvals_alt.as<uint32_t>(), cn, dsort_bits,
-                            ctx->sort_scratch.p, s, &in_alt));
-      }
-      order = in_alt ? ctx->dvals_alt.as<uint32_t>() : ctx->dvals.as<uint32_t>();
-    }
-    {
-      StageTimer tm(ctx, ST_SCAN, s);
-      PCS_HIP(launch_scan(ctx->counts.as<uint32_t>(), order, ctx->offsets.as<uint32_t>(), cn, d_total,
-                          ctx->scan_scratch.p, s));
-    }
     {
       StageTimer tm(ctx, ST_BINNING, s);
-      PCS_HIP(launch_binning(n, n_cams, TX, tiles_per_cam, order, ctx->meta.as<uint4>(),
+      PCS_HIP(launch_binning(n, n_cams, TX, tiles_per_cam, ctx->dvals.as<uint32_t>(),
+                             ctx->dvals_alt.as<uint32_t>(), d_depth, ctx->meta.as<uint4>(),
                              ctx->counts.as<uint32_t>(), ctx->offsets.as<uint32_t>(),
                              st->keys.as<uint32_t>(), st->vals.as<uint32_t>(), s));
     }
@@ -439,8 +452,6 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   st->n = n;
   st->m = m;
   st->n_tiles = total_tiles;
-  st->depth_bits = depth_bits;
-  st->zmin = zmin;
   st->valid = true;
   return PCS_OK;
 }
@@ -558,7 +569,7 @@ int pcs_voxelize(pcs_context* ctx, const float* xyz, const float* rgb, int64_t n
   }
   PCS_HIP(launch_vox_flags(vox->keys.as<uint64_t>(), n, vox->flag.as<uint32_t>(), s));
   uint64_t* d_total = ctx->small.as<uint64_t>();
-  PCS_HIP(launch_scan(vox->flag.as<uint32_t>(), nullptr, vox->excl.as<uint32_t>(), n, d_total,
+  PCS_HIP(launch_scan(vox->flag.as<uint32_t>(), nullptr, nullptr, nullptr, vox->excl.as<uint32_t>(), n, d_total,
                       ctx->scan_scratch.p, s));
   PCS_HIP(hipMemcpyAsync(ctx->host_small, d_total, 8, hipMemcpyDeviceToHost, s));
   PCS_HIP(hipStreamSynchronize(s));

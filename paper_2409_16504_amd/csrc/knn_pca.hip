@@ -388,7 +388,7 @@ hipError_t launch_knn_pca(const float* xyz, int64_t n, int k, float kappa, float
   hipLaunchKernelGGL(k_cell_count, dim3(blocks_for(n, 256)), dim3(256), 0, s, xyz, n, G, cell_id, counts);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   uint64_t* total = reinterpret_cast<uint64_t*>(base + 64);
-  if ((e = launch_scan(counts, nullptr, cell_start, G.ncells + 1, total, scan_scr, s)) != hipSuccess) return e;
+  if ((e = launch_scan(counts, nullptr, nullptr, nullptr, cell_start, G.ncells + 1, total, scan_scr, s)) != hipSuccess) return e;
   if ((e = launch_fill_u32(counts, 0u, G.ncells + 1, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_cell_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s, xyz, n, cell_id,
                      cell_start, counts, sorted);

@@ -111,37 +111,48 @@ hipError_t launch_fill_f32(float* p, float value, int64_t n, hipStream_t s);
 // Depth-bit range slots: zrange[0..kZSlots) minima, zrange[kZSlots..2 kZSlots) maxima.
 constexpr int kZSlots = 64;
 // small[0..1] a u64 total written by the scan, small[2..2+2 kZSlots) depth-bit range slots,
-// small[kCountWord..) kZSlots u64 partial instance counts; reset by launch_init_small.
+// small[kCountWord..) kZSlots u64 partial instance counts, small[kDepthWord..+3) the depth sort's
+// pass count, depth bits and minimum depth bits (written on the device); slots reset by
+// launch_init_small.
 constexpr int kCountWord = 2 + 2 * kZSlots;
-constexpr int kSmallWords = kCountWord + 2 * kZSlots;
+constexpr int kDepthWord = kCountWord + 2 * kZSlots;
+constexpr int kSmallWords = kDepthWord + 4;
 hipError_t launch_init_small(uint32_t* small, hipStream_t s);
 hipError_t launch_project(int64_t n, int n_cams, const DevCamera* cams, const DevOptions& opt,
                           const pcs_gaussians& g, float4* rec, uint4* meta, uint32_t* counts,
                           uint32_t* zrange, unsigned long long* count_slots, hipStream_t s);
 
-// Exclusive scan of n u32 values in[gather[j]] (gather may be null: in[j]); writes out[n] and
-// *total (u64). Scratch from scan_scratch_bytes.
+// Exclusive scan of n u32 values in[gather[j]] (no gather: in[j]); writes out[n] and *total (u64).
+// gather is gather1 when sel is set and *sel is odd, else gather0. Scratch from scan_scratch_bytes.
 size_t scan_scratch_bytes(int64_t n);
-hipError_t launch_scan(const uint32_t* in, const uint32_t* gather, uint32_t* out, int64_t n,
-                       uint64_t* total, void* scratch, hipStream_t s);
+hipError_t launch_scan(const uint32_t* in, const uint32_t* gather0, const uint32_t* gather1,
+                       const uint32_t* sel, uint32_t* out, int64_t n, uint64_t* total, void* scratch,
+                       hipStream_t s);
 
-// Depth key per (camera, Gaussian) and its combined index as the value.
+// Depth key per (camera, Gaussian) and its combined index as the value. The depth-bit range comes
+// from the projection's slots on the device; info[0..3) receives the pass count, depth bits and
+// minimum depth bits.
 template <typename K>
 hipError_t launch_depth_keys(int64_t n, int n_cams, const uint4* meta, const uint32_t* counts,
-                             uint32_t zmin, int depth_bits, K* keys, uint32_t* vals, hipStream_t s);
+                             const uint32_t* zrange, int cam_bits, uint32_t* info, K* keys,
+                             uint32_t* vals, hipStream_t s);
 
-// Tile keys of every visible splat, written in the depth order `order` at `offsets`.
-hipError_t launch_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_cam, const uint32_t* order,
-                          const uint4* meta, const uint32_t* counts, const uint32_t* offsets,
-                          uint32_t* keys, uint32_t* vals, hipStream_t s);
+// Tile keys of every visible splat, written in the depth order at `offsets`; the order is order1
+// when *passes is odd (where the depth sort ended), else order0.
+hipError_t launch_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_cam, const uint32_t* order0,
+                          const uint32_t* order1, const uint32_t* passes, const uint4* meta,
+                          const uint32_t* counts, const uint32_t* offsets, uint32_t* keys,
+                          uint32_t* vals, hipStream_t s);
 
 // Stable LSD radix sort of (key, value) pairs over key bits [0, bits), K = uint32_t or uint64_t.
 // Ping-pongs between (k0,v0) and (k1,v1); returns in *result_in_alt whether the sorted data ended
 // in (k1,v1).
 size_t sort_scratch_bytes(int64_t m);
+// live_passes (device, may be null): passes at or beyond *live_passes return at once, so the data
+// ends in (k1,v1) when *live_passes is odd; *result_in_alt then describes the host's pass count.
 template <typename K>
 hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int bits, void* scratch,
-                       hipStream_t s, bool* result_in_alt);
+                       hipStream_t s, bool* result_in_alt, const uint32_t* live_passes = nullptr);
 
 hipError_t launch_ranges(const uint32_t* keys, int64_t m, int64_t n_tiles, uint32_t* ranges,
                          hipStream_t s);

@@ -60,7 +60,9 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
 }
 
 __global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* __restrict__ in,
-                                                   const uint32_t* __restrict__ gather,
+                                                   const uint32_t* __restrict__ gather0,
+                                                   const uint32_t* __restrict__ gather1,
+                                                   const uint32_t* __restrict__ sel,
                                                    uint32_t* __restrict__ out, int64_t n,
                                                    int64_t n_parts, uint64_t* __restrict__ status,
                                                    uint64_t* __restrict__ total) {
@@ -69,6 +71,7 @@ __global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* __restrict__ 
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   const int64_t part = blockIdx.x;    // in-order dispatch: predecessors are running or done
   const int64_t base = part * kPart + (int64_t)tid * kItems;
+  const uint32_t* gather = (sel && (*sel & 1u)) ? gather1 : gather0;
   uint32_t x[kItems];
   if (gather) {
 #pragma unroll
@@ -146,14 +149,34 @@ __global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* __restrict__ 
 template <typename K>
 __global__ __launch_bounds__(256) void k_depth_keys(int64_t n, const uint4* __restrict__ meta,
                                                     const uint32_t* __restrict__ counts,
-                                                    uint32_t zmin, int depth_bits,
+                                                    const uint32_t* __restrict__ zrange, int cam_bits,
+                                                    uint32_t* __restrict__ info,
                                                     K* __restrict__ keys,
                                                     uint32_t* __restrict__ vals) {
+  // depth-bit range of the frame from the projection's kZSlots slot pairs
+  __shared__ uint32_t s_z[2];
+  if (threadIdx.x < kWave) {
+    uint32_t lo = zrange[threadIdx.x], hi = zrange[kZSlots + threadIdx.x];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      lo = min(lo, (uint32_t)__shfl_xor((int)lo, o, kWave));
+      hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, kWave));
+    }
+    if (threadIdx.x == 0) { s_z[0] = lo; s_z[1] = hi; }
+  }
+  __syncthreads();
+  const uint32_t zmin = s_z[0], zmax = s_z[1];
+  const int depth_bits = zmax > zmin ? 32 - __clz(zmax - zmin) : 0;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    info[0] = (uint32_t)((cam_bits + depth_bits + 7) / 8);   // passes the depth sort needs
+    info[1] = (uint32_t)depth_bits;
+    info[2] = zmin;
+  }
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int64_t j = (int64_t)blockIdx.y * n + i;
   const uint32_t zb = meta[j].x;
-  // a camera field exists only with several cameras, and then depth_bits < the key width
+  // a camera field exists only with several cameras, and then the keys are 64-bit
   const K cam = blockIdx.y ? ((K)blockIdx.y << depth_bits) : (K)0;
   keys[j] = counts[j] ? (cam | (K)(zb - zmin)) : ~(K)0;
   vals[j] = (uint32_t)j;
@@ -163,7 +186,9 @@ __global__ __launch_bounds__(256) void k_depth_keys(int64_t n, const uint4* __re
 // and Gaussian index at its offset in that order.
 __global__ __launch_bounds__(256) void k_binning(int64_t total, uint32_t n, int TX,
                                                  uint32_t tiles_per_cam,
-                                                 const uint32_t* __restrict__ order,
+                                                 const uint32_t* __restrict__ order0,
+                                                 const uint32_t* __restrict__ order1,
+                                                 const uint32_t* __restrict__ passes,
                                                  const uint4* __restrict__ meta,
                                                  const uint32_t* __restrict__ counts,
                                                  const uint32_t* __restrict__ offsets,
@@ -171,6 +196,7 @@ __global__ __launch_bounds__(256) void k_binning(int64_t total, uint32_t n, int 
                                                  uint32_t* __restrict__ vals) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= total) return;
+  const uint32_t* order = (*passes & 1u) ? order1 : order0;   // where the depth sort ended
   const uint32_t i = order[j];
   const uint32_t cnt = counts[i];
   if (cnt == 0) return;
@@ -259,7 +285,9 @@ template <typename K>
 __global__ __launch_bounds__(kThreads) void k_onesweep(
     const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
     uint32_t* __restrict__ vout, int64_t m, int shift, const uint32_t* __restrict__ digit_base,
-    uint32_t* __restrict__ status, uint32_t* __restrict__ status_next) {
+    uint32_t* __restrict__ status, uint32_t* __restrict__ status_next,
+    const uint32_t* __restrict__ live_passes, int pass) {
+  if (live_passes && pass >= (int)*live_passes) return;    // digit beyond the data's bits
   __shared__ uint32_t s_hist[kWaves][kBins];   // per-wave counts, then per-wave offsets
   __shared__ uint32_t s_local[kBins];          // block-local start of each digit run
   __shared__ uint32_t s_global[kBins];         // global start of the run minus its local start
@@ -509,38 +537,43 @@ size_t scan_scratch_bytes(int64_t n) {
   return (size_t)(parts + 1) * sizeof(uint64_t) + 256;
 }
 
-hipError_t launch_scan(const uint32_t* in, const uint32_t* gather, uint32_t* out, int64_t n,
-                       uint64_t* total, void* scratch, hipStream_t s) {
+hipError_t launch_scan(const uint32_t* in, const uint32_t* gather0, const uint32_t* gather1,
+                       const uint32_t* sel, uint32_t* out, int64_t n, uint64_t* total, void* scratch,
+                       hipStream_t s) {
   const int64_t parts = (n + kPart - 1) / kPart;
   uint64_t* status = reinterpret_cast<uint64_t*>(scratch);
   hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(scratch), 0u, parts * 2, s);
   if (e != hipSuccess) return e;
   if (n == 0) return launch_fill_u32(reinterpret_cast<uint32_t*>(total), 0u, 2, s);
-  hipLaunchKernelGGL(k_scan, dim3((unsigned)parts), dim3(kThreads), 0, s, in, gather, out, n, parts,
-                     status, total);
+  hipLaunchKernelGGL(k_scan, dim3((unsigned)parts), dim3(kThreads), 0, s, in, gather0, gather1, sel, out,
+                     n, parts, status, total);
   return hipGetLastError();
 }
 
 template <typename K>
 hipError_t launch_depth_keys(int64_t n, int n_cams, const uint4* meta, const uint32_t* counts,
-                             uint32_t zmin, int depth_bits, K* keys, uint32_t* vals, hipStream_t s) {
+                             const uint32_t* zrange, int cam_bits, uint32_t* info, K* keys,
+                             uint32_t* vals, hipStream_t s) {
   if (n == 0 || n_cams == 0) return hipSuccess;
   hipLaunchKernelGGL(k_depth_keys<K>, dim3(blocks_for(n, 256), (unsigned)n_cams), dim3(256), 0, s, n,
-                     meta, counts, zmin, depth_bits, keys, vals);
+                     meta, counts, zrange, cam_bits, info, keys, vals);
   return hipGetLastError();
 }
-template hipError_t launch_depth_keys<uint32_t>(int64_t, int, const uint4*, const uint32_t*, uint32_t,
-                                                int, uint32_t*, uint32_t*, hipStream_t);
-template hipError_t launch_depth_keys<uint64_t>(int64_t, int, const uint4*, const uint32_t*, uint32_t,
-                                                int, uint64_t*, uint32_t*, hipStream_t);
+template hipError_t launch_depth_keys<uint32_t>(int64_t, int, const uint4*, const uint32_t*,
+                                                const uint32_t*, int, uint32_t*, uint32_t*, uint32_t*,
+                                                hipStream_t);
+template hipError_t launch_depth_keys<uint64_t>(int64_t, int, const uint4*, const uint32_t*,
+                                                const uint32_t*, int, uint32_t*, uint64_t*, uint32_t*,
+                                                hipStream_t);
 
-hipError_t launch_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_cam, const uint32_t* order,
-                          const uint4* meta, const uint32_t* counts, const uint32_t* offsets,
-                          uint32_t* keys, uint32_t* vals, hipStream_t s) {
+hipError_t launch_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_cam, const uint32_t* order0,
+                          const uint32_t* order1, const uint32_t* passes, const uint4* meta,
+                          const uint32_t* counts, const uint32_t* offsets, uint32_t* keys,
+                          uint32_t* vals, hipStream_t s) {
   const int64_t total = n * n_cams;
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_binning, dim3(blocks_for(total, 256)), dim3(256), 0, s, total, (uint32_t)n, TX,
-                     (uint32_t)tiles_per_cam, order, meta, counts, offsets, keys, vals);
+                     (uint32_t)tiles_per_cam, order0, order1, passes, meta, counts, offsets, keys, vals);
   return hipGetLastError();
 }
 
@@ -553,7 +586,7 @@ size_t sort_scratch_bytes(int64_t m) {
 
 template <typename K>
 hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int bits, void* scratch,
-                       hipStream_t s, bool* result_in_alt) {
+                       hipStream_t s, bool* result_in_alt, const uint32_t* live_passes) {
   *result_in_alt = false;
   if (m <= 1 || bits <= 0) return hipSuccess;
   const int n_passes = (bits + 7) / 8;
@@ -577,7 +610,7 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
     uint32_t* st = (p & 1) ? status1 : status0;
     uint32_t* st_next = (p & 1) ? status0 : status1;
     hipLaunchKernelGGL(k_onesweep<K>, dim3((unsigned)parts), dim3(kThreads), 0, s, ki, vi, ko, vo, m,
-                       8 * p, base + p * kBins, st, st_next);
+                       8 * p, base + p * kBins, st, st_next, live_passes, p);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     std::swap(ki, ko);
     std::swap(vi, vo);
@@ -586,9 +619,9 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
   return hipSuccess;
 }
 template hipError_t launch_sort<uint32_t>(uint32_t*, uint32_t*, uint32_t*, uint32_t*, int64_t, int,
-                                          void*, hipStream_t, bool*);
+                                          void*, hipStream_t, bool*, const uint32_t*);
 template hipError_t launch_sort<uint64_t>(uint64_t*, uint32_t*, uint64_t*, uint32_t*, int64_t, int,
-                                          void*, hipStream_t, bool*);
+                                          void*, hipStream_t, bool*, const uint32_t*);
 
 hipError_t launch_ranges(const uint32_t* keys, int64_t m, int64_t n_tiles, uint32_t* ranges,
                          hipStream_t s) {

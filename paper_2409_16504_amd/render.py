@@ -191,8 +191,16 @@ class Renderer:
         return out
 
     # -- timing -------------------------------------------------------------------------------
-    def timing(self, enable=True):
-        check(_lib.load().pcs_context_timing(self.ctx, int(enable)))
+    def timing(self, enable=True, stages=None):
+        """Enable per-stage HIP-event timing (resetting the totals); ``stages`` limits the events to
+        the named stages."""
+        if stages is None or not enable:
+            check(_lib.load().pcs_context_timing(self.ctx, int(enable)))
+        else:
+            mask = 0
+            for st in stages:
+                mask |= 1 << _lib.STAGES.index(st)
+            check(_lib.load().pcs_context_timing_stages(self.ctx, mask))
 
     def timings(self) -> dict:
         n = len(_lib.STAGES)
