@@ -5,8 +5,10 @@
 // lane, the next batch fetched into registers while the current one is composited), keeps the
 // records whose ellipse bounding box reaches its quadrant, compacted into LDS in list order, and
 // walks them: every pixel tests the 3-sigma ellipse, evaluates alpha = o * exp(-q/2), and blends
-// RGB, normal and depth until its transmittance drops below t_eps. The quadrants of a tile run
-// independently, so none waits for another and each stops as soon as its own pixels are done.
+// RGB, normal and depth until its transmittance drops below t_eps. Records are kept only if their
+// box reaches the rectangle of the quadrant's pixels that are still blending, which shrinks as
+// pixels finish. The quadrants of a tile run independently, so none waits for another and each
+// stops as soon as its own pixels are done.
 //
 // The adjoint uses the same quadrant wavefronts and walks the list back to front from the
 // quadrant's furthest last contributor, recovering each pixel's transmittance by division, keeps a
@@ -21,6 +23,7 @@ namespace pcs {
 namespace {
 
 constexpr int kGroup = 4;             // reaching splats whose quadratic forms are evaluated together
+constexpr float kNegHalfLog2e = -0.72134752044448170f;   // -log2(e) / 2
 
 // Pixel of a thread: wavefront w owns the 8x8 quadrant (w & 1, w >> 1) of the 16x16 tile.
 struct TilePixel {
@@ -58,6 +61,35 @@ __device__ __forceinline__ bool quadrant_of_block(int64_t b, int64_t total_tiles
   return pos < total_tiles;
 }
 
+// Bounding rectangle (pixel centres) of the lanes set in an 8x8 quadrant's lane mask.
+struct ActiveRect {
+  float x0, x1, y0, y1;
+};
+
+__device__ __forceinline__ ActiveRect active_rect(uint64_t live, float qx0, float qy0) {
+  uint64_t cols = live | (live >> 32);
+  cols |= cols >> 16;
+  cols |= cols >> 8;
+  const uint32_t colmask = (uint32_t)cols & 0xFFu;
+  uint64_t rows = live | (live >> 4);
+  rows |= rows >> 2;
+  rows |= rows >> 1;
+  rows &= 0x0101010101010101ull;                      // bit 8 r set: row r has a live lane
+  ActiveRect r;
+  r.x0 = qx0 + (float)__builtin_ctz(colmask);
+  r.x1 = qx0 + (float)(31 - __builtin_clz(colmask));
+  r.y0 = qy0 + (float)(__builtin_ctzll(rows) >> 3);
+  r.y1 = qy0 + (float)((63 - __builtin_clzll(rows)) >> 3);
+  return r;
+}
+
+// Does the splat's padded ellipse bounding box reach a pixel centre of the rectangle?
+__device__ __forceinline__ bool touches_rect(float u, float v, float ex, float ey, const ActiveRect& r) {
+  const float gx = fmaxf(fmaxf(r.x0 - u, u - r.x1), 0.0f);
+  const float gy = fmaxf(fmaxf(r.y0 - v, v - r.y1), 0.0f);
+  return gx <= ex && gy <= ey;
+}
+
 __global__ __launch_bounds__(kWave) void k_composite(
     int64_t n, int W, int H, int TX, int64_t tiles_per_cam, int64_t total_tiles,
     const float4* __restrict__ rec, const uint32_t* __restrict__ vals,
@@ -86,62 +118,74 @@ __global__ __launch_bounds__(kWave) void k_composite(
   float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f, acc4 = 0.f, acc5 = 0.f, acc6 = 0.f;
   int32_t last = 0;
   bool done = !inside;
-  // one record per lane; the next batch travels in registers while the current one is composited
-  float4 p0, p1, p2, p3;
-  if (start + lane < end) {
-    const float4* r = rec_cam + (int64_t)min(vals[start + lane], (uint32_t)(n - 1)) * kRecFloat4;
+  // one record per lane; the next batch's records and the batch after's splat indices travel in
+  // registers while the current batch is composited, so each batch waits on one round trip. The
+  // loads are unconditional (positions past the list re-read its last entry; the position test
+  // below drops them), which keeps the prefetched values in registers.
+  const uint32_t lastpos = end > start ? end - 1 : start;
+  float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0, p2 = p0, p3 = p0;
+  uint32_t vnext = 0;
+  if (end > start) {
+    const float4* r = rec_cam + (int64_t)min(vals[min(start + lane, lastpos)], (uint32_t)(n - 1)) * kRecFloat4;
     p0 = r[0]; p1 = r[1]; p2 = r[2]; p3 = r[3];
+    vnext = vals[min(start + kWave + lane, lastpos)];
   }
   for (uint32_t b = start; b < end; b += kWave) {
-    if (__ballot(!done) == 0ull) break;              // every pixel of the quadrant is done
-    // keep the records whose padded ellipse box reaches the quadrant, compacted in list order
-    const bool rel = b + lane < end && touches_quadrant(p0.x, p0.y, p1.w, p2.w, P.qx0, P.qy0);
+    const uint64_t live = __ballot(!done);
+    if (live == 0ull) break;                          // every pixel of the quadrant is done
+    // keep the records whose padded ellipse box reaches a pixel that is still blending, compacted
+    // in list order; the live pixels' bounding rectangle comes from the ballot (lane = 8 y + x):
+    // rows are its non-zero bytes, columns the OR of its bytes
+    const ActiveRect ar = active_rect(live, P.qx0, P.qy0);
+    const bool rel = b + lane < end && touches_rect(p0.x, p0.y, p1.w, p2.w, ar);
     const uint64_t relmask = __ballot(rel);
     if (rel) {
       const int slot = __popcll(relmask & lt);
       s_r0[slot] = p0; s_r1[slot] = p1; s_r2[slot] = p2; s_r3[slot] = p3;
       s_pos[slot] = (int32_t)(b - start) + lane;
     }
-    const uint32_t nb = b + kWave + lane;
-    if (nb < end) {
-      const float4* r = rec_cam + (int64_t)min(vals[nb], (uint32_t)(n - 1)) * kRecFloat4;
+    {
+      const float4* r = rec_cam + (int64_t)min(vnext, (uint32_t)(n - 1)) * kRecFloat4;
       p0 = r[0]; p1 = r[1]; p2 = r[2]; p3 = r[3];
+      vnext = vals[min(b + 2 * kWave + lane, lastpos)];
     }
     __syncthreads();                                  // one wavefront: orders the LDS writes
     const int nrel = __popcll(relmask);
     for (int k0 = 0; k0 < nrel; k0 += kGroup) {
-      // quadratic forms of up to kGroup splats first (independent of T; unconditional reads,
-      // slots past the end re-read the last entry and are pushed above the cut), then the alpha
-      // tests and blends in list order
-      float qq[kGroup], oo[kGroup], zz[kGroup];
+      // everything the group's blends need first: records, quadratic forms and alphas are
+      // independent of T (slots past the end re-read the last entry and are marked invalid),
+      // so the in-order blends below run from registers
+      float aa[kGroup], zz[kGroup];
+      float4 c2[kGroup], c3[kGroup];
+      int32_t pp[kGroup];
 #pragma unroll
       for (int j = 0; j < kGroup; ++j) {
         const int k = min(k0 + j, nrel - 1);
         const float4 r0 = s_r0[k];
         const float4 r1 = s_r1[k];
+        c2[j] = s_r2[k];
+        c3[j] = s_r3[k];
+        pp[j] = s_pos[k];
         const float q = conic_q(r1.x, r1.y, r1.z, pxf - r0.x, pyf - r0.y);
-        qq[j] = k0 + j < nrel ? q : cut2 + 1.0f;
-        oo[j] = r0.z;
+        // o * e^(-q/2) as o * 2^(q * (-log2(e) / 2)), one hardware exp2
+        const float a = fminf(opt.alpha_max, r0.z * __builtin_amdgcn_exp2f(q * kNegHalfLog2e));
+        aa[j] = (k0 + j < nrel && q <= cut2 && !(a < opt.alpha_min)) ? a : -1.0f;
         zz[j] = r0.w;
       }
 #pragma unroll
       for (int j = 0; j < kGroup; ++j) {
-        if (done || !(qq[j] <= cut2)) continue;
-        const int k = k0 + j;
-        const float a = fminf(opt.alpha_max, oo[j] * __expf(-0.5f * qq[j]));
-        if (a < opt.alpha_min) continue;
+        if (done || !(aa[j] >= 0.0f)) continue;
+        const float a = aa[j];
         const float w = a * T;
-        const float4 r2 = s_r2[k];
-        const float4 r3 = s_r3[k];
-        acc0 = fmaf(w, r2.x, acc0);
-        acc1 = fmaf(w, r2.y, acc1);
-        acc2 = fmaf(w, r2.z, acc2);
-        acc3 = fmaf(w, r3.x, acc3);
-        acc4 = fmaf(w, r3.y, acc4);
-        acc5 = fmaf(w, r3.z, acc5);
+        acc0 = fmaf(w, c2[j].x, acc0);
+        acc1 = fmaf(w, c2[j].y, acc1);
+        acc2 = fmaf(w, c2[j].z, acc2);
+        acc3 = fmaf(w, c3[j].x, acc3);
+        acc4 = fmaf(w, c3[j].y, acc4);
+        acc5 = fmaf(w, c3[j].z, acc5);
         acc6 = fmaf(w, zz[j], acc6);
         T = T * (1.0f - a);
-        last = s_pos[k] + 1;
+        last = pp[j] + 1;
         if (T < opt.t_eps) done = true;
       }
     }
@@ -214,15 +258,15 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(
   const int64_t base_idx = cam * n;
   // batches of 64 list positions, back to front; the batch below is fetched into registers while
   // the current one is walked
-  float4 p0, p1, p2, p3;
+  // unconditional loads (positions past the batch re-read its last entry; the position test drops
+  // them), which keeps the prefetched values in registers
+  float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0, p2 = p0, p3 = p0;
   uint32_t pg_idx = 0;
   auto fetch = [&](int32_t bstart, int32_t bend) {
-    const int32_t pos = bstart + lane;
-    if (pos < bend) {
-      pg_idx = min(vals[start + pos], (uint32_t)(n - 1));
-      const float4* r = rec_cam + (int64_t)pg_idx * kRecFloat4;
-      p0 = r[0]; p1 = r[1]; p2 = r[2]; p3 = r[3];
-    }
+    const int32_t pos = min(bstart + lane, bend - 1);
+    pg_idx = min(vals[start + pos], (uint32_t)(n - 1));
+    const float4* r = rec_cam + (int64_t)pg_idx * kRecFloat4;
+    p0 = r[0]; p1 = r[1]; p2 = r[2]; p3 = r[3];
   };
   if (max_nc > 0) fetch(max(0, max_nc - kWave), max_nc);
   for (int32_t bend = max_nc; bend > 0; bend -= kWave) {
