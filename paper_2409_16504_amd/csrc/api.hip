@@ -365,31 +365,18 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   if (!ctx->counts_ready) PCS_HIP(hipEventCreateWithFlags(&ctx->counts_ready, hipEventDisableTiming));
   PCS_HIP(hipMemcpyAsync(ctx->host_small, ctx->small.p, kSmallWords * 4, hipMemcpyDeviceToHost, s));
   PCS_HIP(hipEventRecord(ctx->counts_ready, s));
-  const int cam_bits = bit_length((uint64_t)(n_cams - 1));
-  const bool wide = n_cams > 1;                       // camera field + up to 31 depth bits
-  const int dsort_max_bits = cam_bits + 31;
-  const size_t dkey_bytes = wide ? sizeof(uint64_t) : sizeof(uint32_t);
-  PCS_TRY(ensure(ctx->dkeys, cn1 * dkey_bytes, "depth keys"));
-  PCS_TRY(ensure(ctx->dkeys_alt, cn1 * dkey_bytes, "depth keys (alternate)"));
+  PCS_TRY(ensure(ctx->dkeys, cn1 * sizeof(uint32_t), "depth keys"));
+  PCS_TRY(ensure(ctx->dkeys_alt, cn1 * sizeof(uint32_t), "depth keys (alternate)"));
   PCS_TRY(ensure(ctx->dvals, cn1 * sizeof(uint32_t), "depth order"));
   PCS_TRY(ensure(ctx->dvals_alt, cn1 * sizeof(uint32_t), "depth order (alternate)"));
   PCS_TRY(ensure(ctx->dsort_scratch, sort_scratch_bytes(cn), "depth sort scratch"));
   if (cn > 0) {
     StageTimer tm(ctx, ST_SORT, s);
     bool unused = false;
-    if (wide) {
-      PCS_HIP(launch_depth_keys(n, n_cams, ctx->meta.as<uint4>(), ctx->counts.as<uint32_t>(), d_zrange,
-                                cam_bits, d_depth, ctx->dkeys.as<uint64_t>(), ctx->dvals.as<uint32_t>(), s));
-      PCS_HIP(launch_sort(ctx->dkeys.as<uint64_t>(), ctx->dvals.as<uint32_t>(), ctx->dkeys_alt.as<uint64_t>(),
-                          ctx->dvals_alt.as<uint32_t>(), cn, dsort_max_bits, ctx->dsort_scratch.p, s,
-                          &unused, d_depth));
-    } else {
-      PCS_HIP(launch_depth_keys(n, n_cams, ctx->meta.as<uint4>(), ctx->counts.as<uint32_t>(), d_zrange,
-                                cam_bits, d_depth, ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(), s));
-      PCS_HIP(launch_sort(ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(), ctx->dkeys_alt.as<uint32_t>(),
-                          ctx->dvals_alt.as<uint32_t>(), cn, dsort_max_bits, ctx->dsort_scratch.p, s,
-                          &unused, d_depth));
-    }
+    PCS_HIP(launch_depth_keys(n, n_cams, ctx->meta.as<uint4>(), ctx->counts.as<uint32_t>(), d_zrange, d_depth,
+                              ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(), s));
+    PCS_HIP(launch_sort(ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(), ctx->dkeys_alt.as<uint32_t>(),
+                        ctx->dvals_alt.as<uint32_t>(), cn, 31, ctx->dsort_scratch.p, s, &unused, d_depth));
   }
   if (cn > 0) {
     StageTimer tm(ctx, ST_SCAN, s);

@@ -132,10 +132,9 @@ hipError_t launch_scan(const uint32_t* in, const uint32_t* gather0, const uint32
 // Depth key per (camera, Gaussian) and its combined index as the value. The depth-bit range comes
 // from the projection's slots on the device; info[0..3) receives the pass count, depth bits and
 // minimum depth bits.
-template <typename K>
 hipError_t launch_depth_keys(int64_t n, int n_cams, const uint4* meta, const uint32_t* counts,
-                             const uint32_t* zrange, int cam_bits, uint32_t* info, K* keys,
-                             uint32_t* vals, hipStream_t s);
+                             const uint32_t* zrange, uint32_t* info, uint32_t* keys, uint32_t* vals,
+                             hipStream_t s);
 
 // Tile keys of every visible splat, written in the depth order at `offsets`; the order is order1
 // when *passes is odd (where the depth sort ended), else order0.

@@ -20,8 +20,8 @@
 //              digit runs.
 //  * ranges:   tile start/end from tile-id changes in the sorted keys.
 //
-// Depth keys are (camera << depth_bits) | (fp32 depth bits - minimum depth bits): positive floats
-// order like their bit patterns, so only the significant bits are sorted.
+// Depth keys are fp32 depth bits - minimum depth bits over all cameras: positive floats order
+// like their bit patterns, so only the significant bits are sorted.
 
 #include "pcs_internal.hpp"
 
@@ -146,12 +146,15 @@ __global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* __restrict__ 
 // ---- depth keys and binning ----------------------------------------------------------------
 // One key per (camera, Gaussian); culled splats get all bits set (they have no tile instances,
 // so where they land in the order does not matter).
-template <typename K>
+// One depth key per (camera, Gaussian): the bits of its depth above the frame's minimum (positive
+// floats order like their bit patterns). No camera field is needed: the tile keys carry the
+// camera, and the stable tile sort keeps each (camera, tile) run in depth order with ties by the
+// combined index, i.e. by Gaussian index within a camera.
 __global__ __launch_bounds__(256) void k_depth_keys(int64_t n, const uint4* __restrict__ meta,
                                                     const uint32_t* __restrict__ counts,
-                                                    const uint32_t* __restrict__ zrange, int cam_bits,
+                                                    const uint32_t* __restrict__ zrange,
                                                     uint32_t* __restrict__ info,
-                                                    K* __restrict__ keys,
+                                                    uint32_t* __restrict__ keys,
                                                     uint32_t* __restrict__ vals) {
   // depth-bit range of the frame from the projection's kZSlots slot pairs
   __shared__ uint32_t s_z[2];
@@ -168,17 +171,14 @@ __global__ __launch_bounds__(256) void k_depth_keys(int64_t n, const uint4* __re
   const uint32_t zmin = s_z[0], zmax = s_z[1];
   const int depth_bits = zmax > zmin ? 32 - __clz(zmax - zmin) : 0;
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
-    info[0] = (uint32_t)((cam_bits + depth_bits + 7) / 8);   // passes the depth sort needs
+    info[0] = (uint32_t)((depth_bits + 7) / 8);          // passes the depth sort needs
     info[1] = (uint32_t)depth_bits;
     info[2] = zmin;
   }
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int64_t j = (int64_t)blockIdx.y * n + i;
-  const uint32_t zb = meta[j].x;
-  // a camera field exists only with several cameras, and then the keys are 64-bit
-  const K cam = blockIdx.y ? ((K)blockIdx.y << depth_bits) : (K)0;
-  keys[j] = counts[j] ? (cam | (K)(zb - zmin)) : ~(K)0;
+  keys[j] = counts[j] ? meta[j].x - zmin : ~0u;
   vals[j] = (uint32_t)j;
 }
 
@@ -550,21 +550,14 @@ hipError_t launch_scan(const uint32_t* in, const uint32_t* gather0, const uint32
   return hipGetLastError();
 }
 
-template <typename K>
 hipError_t launch_depth_keys(int64_t n, int n_cams, const uint4* meta, const uint32_t* counts,
-                             const uint32_t* zrange, int cam_bits, uint32_t* info, K* keys,
-                             uint32_t* vals, hipStream_t s) {
+                             const uint32_t* zrange, uint32_t* info, uint32_t* keys, uint32_t* vals,
+                             hipStream_t s) {
   if (n == 0 || n_cams == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_depth_keys<K>, dim3(blocks_for(n, 256), (unsigned)n_cams), dim3(256), 0, s, n,
-                     meta, counts, zrange, cam_bits, info, keys, vals);
+  hipLaunchKernelGGL(k_depth_keys, dim3(blocks_for(n, 256), (unsigned)n_cams), dim3(256), 0, s, n, meta,
+                     counts, zrange, info, keys, vals);
   return hipGetLastError();
 }
-template hipError_t launch_depth_keys<uint32_t>(int64_t, int, const uint4*, const uint32_t*,
-                                                const uint32_t*, int, uint32_t*, uint32_t*, uint32_t*,
-                                                hipStream_t);
-template hipError_t launch_depth_keys<uint64_t>(int64_t, int, const uint4*, const uint32_t*,
-                                                const uint32_t*, int, uint32_t*, uint64_t*, uint32_t*,
-                                                hipStream_t);
 
 hipError_t launch_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_cam, const uint32_t* order0,
                           const uint32_t* order1, const uint32_t* passes, const uint4* meta,
