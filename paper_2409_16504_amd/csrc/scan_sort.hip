@@ -249,6 +249,12 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, 
       if (vmask == 0) break;
       for (int p = 0; p < n_passes; ++p) {
         const uint32_t d = (uint32_t)(k[it] >> (8 * p)) & 0xFF;
+        if (p < n_passes - 1) {                       // lower digits: spread, one atomic per key
+          if (valid) atomicAdd(&sh[p][d], 1u);
+          continue;
+        }
+        // top digit: few distinct values in a wavefront (sorted runs), so equal digits are
+        // matched with eight ballots and counted once
         uint64_t peers = vmask;
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
