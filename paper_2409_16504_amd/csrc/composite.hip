@@ -97,8 +97,9 @@ __global__ __launch_bounds__(kWave) void k_composite(
     float* __restrict__ out_rgb,
     float* __restrict__ out_nrm, float* __restrict__ out_depth, float* __restrict__ out_alpha,
     float* __restrict__ t_final, int32_t* __restrict__ n_contrib) {
-  __shared__ float4 s_r0[kWave], s_r1[kWave], s_r2[kWave], s_r3[kWave];
-  __shared__ int32_t s_pos[kWave];
+  // compacted records of a batch, plus kGroup slots past the last one whose conic is NaN
+  __shared__ float4 s_r0[kWave + kGroup], s_r1[kWave + kGroup], s_r2[kWave + kGroup], s_r3[kWave + kGroup];
+  __shared__ int32_t s_pos[kWave + kGroup];     // list position + 1
   int64_t opos;
   int quad;
   if (!quadrant_of_block(blockIdx.x, total_tiles, opos, quad)) return;
@@ -122,6 +123,15 @@ __global__ __launch_bounds__(kWave) void k_composite(
   // registers while the current batch is composited, so each batch waits on one round trip. The
   // loads are unconditional (positions past the list re-read its last entry; the position test
   // below drops them), which keeps the prefetched values in registers.
+  // every slot starts finite (zeros), so a slot after the last kept record, read with zero
+  // weight, leaves the sums exact
+  {
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    s_r0[lane] = z4; s_r2[lane] = z4; s_r3[lane] = z4; s_pos[lane] = 0;
+    if (lane < kGroup) {
+      s_r0[kWave + lane] = z4; s_r2[kWave + lane] = z4; s_r3[kWave + lane] = z4; s_pos[kWave + lane] = 0;
+    }
+  }
   const uint32_t lastpos = end > start ? end - 1 : start;
   float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0, p2 = p0, p3 = p0;
   uint32_t vnext = 0;
@@ -142,8 +152,11 @@ __global__ __launch_bounds__(kWave) void k_composite(
     if (rel) {
       const int slot = __popcll(relmask & lt);
       s_r0[slot] = p0; s_r1[slot] = p1; s_r2[slot] = p2; s_r3[slot] = p3;
-      s_pos[slot] = (int32_t)(b - start) + lane;
+      s_pos[slot] = (int32_t)(b - start) + lane + 1;
     }
+    // the kGroup slots after the last kept record can never blend (NaN conic: q <= cut fails);
+    // their other fields are finite (earlier records or the initial zeros)
+    if (lane < kGroup) s_r1[__popcll(relmask) + lane] = make_float4(__int_as_float(0x7fc00000), 0.f, 0.f, 0.f);
     {
       const float4* r = rec_cam + (int64_t)min(vnext, (uint32_t)(n - 1)) * kRecFloat4;
       p0 = r[0]; p1 = r[1]; p2 = r[2]; p3 = r[3];
@@ -153,14 +166,13 @@ __global__ __launch_bounds__(kWave) void k_composite(
     const int nrel = __popcll(relmask);
     for (int k0 = 0; k0 < nrel; k0 += kGroup) {
       // everything the group's blends need first: records, quadratic forms and alphas are
-      // independent of T (slots past the end re-read the last entry and are marked invalid),
-      // so the in-order blends below run from registers
+      // independent of T, so the in-order blends below run from registers
       float aa[kGroup], zz[kGroup];
       float4 c2[kGroup], c3[kGroup];
       int32_t pp[kGroup];
 #pragma unroll
       for (int j = 0; j < kGroup; ++j) {
-        const int k = min(k0 + j, nrel - 1);
+        const int k = k0 + j;
         const float4 r0 = s_r0[k];
         const float4 r1 = s_r1[k];
         c2[j] = s_r2[k];
@@ -169,13 +181,15 @@ __global__ __launch_bounds__(kWave) void k_composite(
         const float q = conic_q(r1.x, r1.y, r1.z, pxf - r0.x, pyf - r0.y);
         // o * e^(-q/2) as o * 2^(q * (-log2(e) / 2)), one hardware exp2
         const float a = fminf(opt.alpha_max, r0.z * __builtin_amdgcn_exp2f(q * kNegHalfLog2e));
-        aa[j] = (k0 + j < nrel && q <= cut2 && !(a < opt.alpha_min)) ? a : -1.0f;
+        aa[j] = (q <= cut2 && !(a < opt.alpha_min)) ? a : -1.0f;  // negative: no blend
         zz[j] = r0.w;
       }
+      // blends in list order without branches: a lane that is done or has no blend uses a = 0,
+      // which leaves T and the sums exactly as they are
 #pragma unroll
       for (int j = 0; j < kGroup; ++j) {
-        if (done || !(aa[j] >= 0.0f)) continue;
-        const float a = aa[j];
+        const bool v = !done && aa[j] >= 0.0f;
+        const float a = v ? aa[j] : 0.0f;
         const float w = a * T;
         acc0 = fmaf(w, c2[j].x, acc0);
         acc1 = fmaf(w, c2[j].y, acc1);
@@ -185,8 +199,8 @@ __global__ __launch_bounds__(kWave) void k_composite(
         acc5 = fmaf(w, c3[j].z, acc5);
         acc6 = fmaf(w, zz[j], acc6);
         T = T * (1.0f - a);
-        last = pp[j] + 1;
-        if (T < opt.t_eps) done = true;
+        last = v ? pp[j] : last;
+        done = done || (v && T < opt.t_eps);
       }
     }
     __syncthreads();                                  // reads done before the next batch lands
