@@ -287,24 +287,29 @@ __global__ __launch_bounds__(256) void k_digit_base(const uint32_t* __restrict__
   base[blockIdx.x * kBins + tid] = pre + incl - v;
 }
 
-template <typename K>
-__global__ __launch_bounds__(kThreads) void k_onesweep(
+// One scatter pass over digit `shift`. THREADS threads take a partition of THREADS * ITEMS keys
+// (4096: 512 threads x 8 keys for 32-bit keys, so each wavefront ranks half as many keys in
+// sequence; 256 x 16 for 64-bit keys).
+template <typename K, int THREADS, int ITEMS>
+__global__ __launch_bounds__(THREADS) void k_onesweep(
     const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
     uint32_t* __restrict__ vout, int64_t m, int shift, const uint32_t* __restrict__ digit_base,
     uint32_t* __restrict__ status, uint32_t* __restrict__ status_next,
     const uint32_t* __restrict__ live_passes, int pass) {
+  constexpr int W = THREADS / kWave;
+  constexpr int PART = THREADS * ITEMS;
+  constexpr int kItems = ITEMS;
   if (live_passes && pass >= (int)*live_passes) return;    // digit beyond the data's bits
-  __shared__ uint32_t s_hist[kWaves][kBins];   // per-wave counts, then per-wave offsets
+  __shared__ uint32_t s_hist[W][kBins];        // per-wave counts, then per-wave offsets
   __shared__ uint32_t s_local[kBins];          // block-local start of each digit run
   __shared__ uint32_t s_global[kBins];         // global start of the run minus its local start
-  __shared__ uint32_t s_wsum[kWaves];
-  __shared__ K s_buf[kPart];                   // keys, then (as u32) values, in digit order
+  __shared__ uint32_t s_wsum[kBins / kWave];
+  __shared__ K s_buf[PART];                    // keys, then (as u32) values, in digit order
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-#pragma unroll
-  for (int w = 0; w < kWaves; ++w) s_hist[w][tid] = 0;
+  for (int i = tid; i < W * kBins; i += THREADS) (&s_hist[0][0])[i] = 0u;
   __syncthreads();
   const int64_t part = blockIdx.x;    // in-order dispatch: predecessors are running or done
-  const int64_t wbase = part * kPart + (int64_t)wave * (kWave * kItems);
+  const int64_t wbase = part * PART + (int64_t)wave * (kWave * kItems);
   K key[kItems];
   uint32_t val[kItems];
   uint32_t rank[kItems];
@@ -348,59 +353,65 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
     rank[it] = lane == leader[it] ? lead_old : lead_old + rank[it];
   }
   __syncthreads();
-  // per digit (thread = digit): offsets of each wave's run and the block total
-  const uint32_t c0 = s_hist[0][tid], c1 = s_hist[1][tid], c2 = s_hist[2][tid], c3 = s_hist[3][tid];
-  const uint32_t count = c0 + c1 + c2 + c3;
-  // publish this partition's digit count as early as possible
-  if (part == 0) atomic_store_u32(&status[tid], kSortPrefix | count);
-  else atomic_store_u32(&status[part * kBins + tid], kSortAgg | count);
-  // block-local exclusive scan of the digit counts
-  const uint32_t incl = wave_inclusive_scan(count);
-  if (lane == kWave - 1) s_wsum[wave] = incl;
-  __syncthreads();
-  uint32_t pre = 0;
-  for (int w = 0; w < wave; ++w) pre += s_wsum[w];
-  const uint32_t local_start = pre + incl - count;
-  s_hist[0][tid] = 0;
-  s_hist[1][tid] = c0;
-  s_hist[2][tid] = c0 + c1;
-  s_hist[3][tid] = c0 + c1 + c2;
-  // look back over earlier partitions for this digit, kLookWindow predecessors per step
-  uint32_t excl = 0;
-  if (part > 0) {
-    int64_t p = part - 1;
-    uint32_t spins = 0;
-    while (true) {
-      uint32_t v[kLookWindow];
+  // per digit (threads 0..255, one digit each): offsets of each wave's run and the block total
+  const bool digit_thread = tid < kBins;
+  uint32_t count = 0, incl = 0;
+  uint32_t cw[W];
+  if (digit_thread) {
 #pragma unroll
-      for (int w = 0; w < kLookWindow; ++w)
-        v[w] = (p - w >= 0) ? atomic_load_u32(&status[(p - w) * kBins + tid]) : kSortPrefix;
-      // accept the window up to (and including) its nearest inclusive prefix, if nothing before
-      // it is still unpublished
-      uint32_t acc = 0;
-      int state = 0;                       // 0: all aggregates, 1: reached a prefix, 2: not ready
-#pragma unroll
-      for (int w = 0; w < kLookWindow; ++w) {
-        if (state != 0) continue;
-        const uint32_t flag = v[w] & ~kSortValue;
-        if (flag == 0) { state = 2; continue; }
-        acc += v[w] & kSortValue;
-        if (flag == kSortPrefix) state = 1;
-      }
-      if (state == 2) {
-        if (++spins < kSpinLimit) continue;
-        break;                             // guards a broken launch only
-      }
-      excl += acc;
-      if (state == 1) break;
-      p -= kLookWindow;
-    }
-    atomic_store_u32(&status[part * kBins + tid], kSortPrefix | (excl + count));
+    for (int w = 0; w < W; ++w) { cw[w] = s_hist[w][tid]; count += cw[w]; }
+    // publish this partition's digit count as early as possible
+    if (part == 0) atomic_store_u32(&status[tid], kSortPrefix | count);
+    else atomic_store_u32(&status[part * kBins + tid], kSortAgg | count);
+    // block-local exclusive scan of the digit counts
+    incl = wave_inclusive_scan(count);
+    if (lane == kWave - 1) s_wsum[wave] = incl;
   }
-  // clear this partition's slice of the other status buffer for the next pass
-  status_next[part * kBins + tid] = 0u;
-  s_local[tid] = local_start;
-  s_global[tid] = digit_base[tid] + excl - local_start;
+  __syncthreads();
+  if (digit_thread) {
+    uint32_t pre = 0;
+    for (int w = 0; w < wave; ++w) pre += s_wsum[w];
+    const uint32_t local_start = pre + incl - count;
+    uint32_t run = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) { s_hist[w][tid] = run; run += cw[w]; }
+    // look back over earlier partitions for this digit, kLookWindow predecessors per step
+    uint32_t excl = 0;
+    if (part > 0) {
+      int64_t p = part - 1;
+      uint32_t spins = 0;
+      while (true) {
+        uint32_t v[kLookWindow];
+#pragma unroll
+        for (int w = 0; w < kLookWindow; ++w)
+          v[w] = (p - w >= 0) ? atomic_load_u32(&status[(p - w) * kBins + tid]) : kSortPrefix;
+        // accept the window up to (and including) its nearest inclusive prefix, if nothing
+        // before it is still unpublished
+        uint32_t acc = 0;
+        int state = 0;                       // 0: all aggregates, 1: reached a prefix, 2: not ready
+#pragma unroll
+        for (int w = 0; w < kLookWindow; ++w) {
+          if (state != 0) continue;
+          const uint32_t flag = v[w] & ~kSortValue;
+          if (flag == 0) { state = 2; continue; }
+          acc += v[w] & kSortValue;
+          if (flag == kSortPrefix) state = 1;
+        }
+        if (state == 2) {
+          if (++spins < kSpinLimit) continue;
+          break;                             // guards a broken launch only
+        }
+        excl += acc;
+        if (state == 1) break;
+        p -= kLookWindow;
+      }
+      atomic_store_u32(&status[part * kBins + tid], kSortPrefix | (excl + count));
+    }
+    // clear this partition's slice of the other status buffer for the next pass
+    status_next[part * kBins + tid] = 0u;
+    s_local[tid] = local_start;
+    s_global[tid] = digit_base[tid] + excl - local_start;
+  }
   __syncthreads();
   // keys to LDS in block-local digit order
   uint32_t lpos[kItems];
@@ -409,15 +420,15 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
     const int64_t pos = wbase + (int64_t)it * kWave + lane;
     const uint32_t d = (uint32_t)(key[it] >> shift) & 0xFF;
     lpos[it] = s_local[d] + s_hist[wave][d] + rank[it];
-    if (pos < m && lpos[it] < (uint32_t)kPart) s_buf[lpos[it]] = key[it];
+    if (pos < m && lpos[it] < (uint32_t)PART) s_buf[lpos[it]] = key[it];
   }
   __syncthreads();
-  const int64_t pbase = part * kPart;
-  const int n_here = (int)min((int64_t)kPart, m - pbase);
+  const int64_t pbase = part * PART;
+  const int n_here = (int)min((int64_t)PART, m - pbase);
   uint32_t gdst[kItems];
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
-    const int j = tid + r * kThreads;
+    const int j = tid + r * THREADS;
     if (j < n_here) {
       const K k = s_buf[j];
       gdst[r] = s_global[(uint32_t)(k >> shift) & 0xFF] + (uint32_t)j;
@@ -430,12 +441,12 @@ __global__ __launch_bounds__(kThreads) void k_onesweep(
 #pragma unroll
   for (int it = 0; it < kItems; ++it) {
     const int64_t pos = wbase + (int64_t)it * kWave + lane;
-    if (pos < m && lpos[it] < (uint32_t)kPart) s_val[lpos[it]] = val[it];
+    if (pos < m && lpos[it] < (uint32_t)PART) s_val[lpos[it]] = val[it];
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
-    const int j = tid + r * kThreads;
+    const int j = tid + r * THREADS;
     if (j < n_here && gdst[r] < (uint64_t)m) vout[gdst[r]] = s_val[j];
   }
 }
@@ -589,7 +600,10 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
   *result_in_alt = false;
   if (m <= 1 || bits <= 0) return hipSuccess;
   const int n_passes = (bits + 7) / 8;
-  const int64_t parts = (m + kPart - 1) / kPart;
+  const int64_t parts = (m + kPart - 1) / kPart;    // partitions of the histogram (and the bound)
+  constexpr int kSweepThreads = sizeof(K) == 4 ? 512 : 256;
+  constexpr int kSweepItems = kPart / kSweepThreads;
+  const int64_t sweep_parts = parts;
   // scratch: hist[8][256] | status0[parts][256] | base[8][256] | status1[parts][256]. One fill
   // clears the histograms and status0; pass p reads status[p & 1] and clears its partitions'
   // slice of the other buffer for pass p + 1.
@@ -608,7 +622,7 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
   for (int p = 0; p < n_passes; ++p) {
     uint32_t* st = (p & 1) ? status1 : status0;
     uint32_t* st_next = (p & 1) ? status0 : status1;
-    hipLaunchKernelGGL(k_onesweep<K>, dim3((unsigned)parts), dim3(kThreads), 0, s, ki, vi, ko, vo, m,
+    hipLaunchKernelGGL((k_onesweep<K, kSweepThreads, kSweepItems>), dim3((unsigned)sweep_parts), dim3(kSweepThreads), 0, s, ki, vi, ko, vo, m,
                        8 * p, base + p * kBins, st, st_next, live_passes, p);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     std::swap(ki, ko);
