@@ -42,14 +42,6 @@ __device__ __forceinline__ TilePixel tile_pixel(int tx, int ty, int tid) {
   return p;
 }
 
-// Does the splat's padded ellipse bounding box reach a pixel centre of the 8x8 quadrant?
-__device__ __forceinline__ bool touches_quadrant(float u, float v, float ex, float ey, float qx0,
-                                                 float qy0) {
-  const float gx = fmaxf(fmaxf(qx0 - u, u - (qx0 + 7.0f)), 0.0f);
-  const float gy = fmaxf(fmaxf(qy0 - v, v - (qy0 + 7.0f)), 0.0f);
-  return gx <= ex && gy <= ey;
-}
-
 // Block b of the forward pass composites quadrant (b / 8) % 4 of the tile at position
 // (b / 32) * 8 + b % 8 of the order: the four quadrants of a tile are blocks b, b + 8, b + 16,
 // b + 24, which the dispatcher deals to the same XCD (blocks go round-robin over the 8 XCDs), so
@@ -285,7 +277,11 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(
   if (max_nc > 0) fetch(max(0, max_nc - kWave), max_nc);
   for (int32_t bend = max_nc; bend > 0; bend -= kWave) {
     const int32_t bstart = max(0, bend - kWave);
-    const bool rel = bstart + lane < bend && touches_quadrant(p0.x, p0.y, p1.w, p2.w, P.qx0, P.qy0);
+    // pixels whose last contributor lies past the batch start are the only ones it can touch;
+    // keep the records whose padded box reaches their rectangle
+    const uint64_t live = __ballot(nc > bstart);
+    const ActiveRect ar = active_rect(live, P.qx0, P.qy0);
+    const bool rel = bstart + lane < bend && touches_rect(p0.x, p0.y, p1.w, p2.w, ar);
     const uint64_t relmask = __ballot(rel);
     if (rel) {
       const int slot = __popcll(relmask & lt);
