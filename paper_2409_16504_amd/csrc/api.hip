@@ -351,11 +351,22 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   uint32_t* d_zrange = ctx->small.as<uint32_t>() + 2;
   auto* d_counts = reinterpret_cast<unsigned long long*>(ctx->small.as<uint32_t>() + kCountWord);
   uint32_t* d_depth = ctx->small.as<uint32_t>() + kDepthWord;   // passes, depth bits, min depth bits
+  PCS_TRY(ensure(ctx->dkeys, cn1 * sizeof(uint32_t), "depth keys"));
+  PCS_TRY(ensure(ctx->dkeys_alt, cn1 * sizeof(uint32_t), "depth keys (alternate)"));
+  PCS_TRY(ensure(ctx->dvals, cn1 * sizeof(uint32_t), "depth order"));
+  PCS_TRY(ensure(ctx->dvals_alt, cn1 * sizeof(uint32_t), "depth order (alternate)"));
+  PCS_TRY(ensure(ctx->dsort_scratch, sort_scratch_bytes(cn), "depth sort scratch"));
   PCS_HIP(launch_init_small(ctx->small.as<uint32_t>(), s));
   {
+    // the projection also clears what the depth sort and the scan need zeroed
+    ClearSpans clear;
+    clear.p[0] = ctx->dsort_scratch.as<uint32_t>();
+    clear.count[0] = sort_clear_words(cn);
+    clear.p[1] = ctx->scan_scratch.as<uint32_t>();
+    clear.count[1] = scan_clear_words(cn);
     StageTimer tm(ctx, ST_PROJECT, s);
     PCS_HIP(launch_project(n, n_cams, st->dcams.as<DevCamera>(), dopt, *g, st->rec.as<float4>(),
-                           ctx->meta.as<uint4>(), ctx->counts.as<uint32_t>(), d_zrange, d_counts, s));
+                           ctx->meta.as<uint4>(), ctx->counts.as<uint32_t>(), d_zrange, d_counts, clear, s));
   }
   // The instance total goes to the host right after the projection; the (camera, depth) order
   // and the prefix sum of the tile counts in that order need nothing from the host (the depth
@@ -365,23 +376,19 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   if (!ctx->counts_ready) PCS_HIP(hipEventCreateWithFlags(&ctx->counts_ready, hipEventDisableTiming));
   PCS_HIP(hipMemcpyAsync(ctx->host_small, ctx->small.p, kSmallWords * 4, hipMemcpyDeviceToHost, s));
   PCS_HIP(hipEventRecord(ctx->counts_ready, s));
-  PCS_TRY(ensure(ctx->dkeys, cn1 * sizeof(uint32_t), "depth keys"));
-  PCS_TRY(ensure(ctx->dkeys_alt, cn1 * sizeof(uint32_t), "depth keys (alternate)"));
-  PCS_TRY(ensure(ctx->dvals, cn1 * sizeof(uint32_t), "depth order"));
-  PCS_TRY(ensure(ctx->dvals_alt, cn1 * sizeof(uint32_t), "depth order (alternate)"));
-  PCS_TRY(ensure(ctx->dsort_scratch, sort_scratch_bytes(cn), "depth sort scratch"));
   if (cn > 0) {
     StageTimer tm(ctx, ST_SORT, s);
     bool unused = false;
     PCS_HIP(launch_depth_keys(n, n_cams, ctx->meta.as<uint4>(), ctx->counts.as<uint32_t>(), d_zrange, d_depth,
                               ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(), s));
     PCS_HIP(launch_sort(ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(), ctx->dkeys_alt.as<uint32_t>(),
-                        ctx->dvals_alt.as<uint32_t>(), cn, 31, ctx->dsort_scratch.p, s, &unused, d_depth));
+                        ctx->dvals_alt.as<uint32_t>(), cn, 31, ctx->dsort_scratch.p, s, &unused, d_depth,
+                        true));
   }
   if (cn > 0) {
     StageTimer tm(ctx, ST_SCAN, s);
     PCS_HIP(launch_scan(ctx->counts.as<uint32_t>(), ctx->dvals.as<uint32_t>(), ctx->dvals_alt.as<uint32_t>(),
-                        d_depth, ctx->offsets.as<uint32_t>(), cn, d_total, ctx->scan_scratch.p, s));
+                        d_depth, ctx->offsets.as<uint32_t>(), cn, d_total, ctx->scan_scratch.p, s, true));
   }
   PCS_HIP(hipEventSynchronize(ctx->counts_ready));
   uint64_t m64 = 0;
@@ -403,22 +410,30 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   if (m > 0) {
     {
       StageTimer tm(ctx, ST_BINNING, s);
+      // binning also clears what the tile sort and the tile ranges need zeroed
+      ClearSpans clear;
+      clear.p[0] = ctx->sort_scratch.as<uint32_t>();
+      clear.count[0] = sort_clear_words(m);
+      clear.p[1] = st->ranges.as<uint32_t>();
+      clear.count[1] = 2 * total_tiles;
       PCS_HIP(launch_binning(n, n_cams, TX, tiles_per_cam, ctx->dvals.as<uint32_t>(),
                              ctx->dvals_alt.as<uint32_t>(), d_depth, ctx->meta.as<uint4>(),
                              ctx->counts.as<uint32_t>(), ctx->offsets.as<uint32_t>(),
-                             st->keys.as<uint32_t>(), st->vals.as<uint32_t>(), s));
+                             st->keys.as<uint32_t>(), st->vals.as<uint32_t>(), clear, s));
     }
     bool in_alt = false;
     {
       StageTimer tm(ctx, ST_SORT, s);
       PCS_HIP(launch_sort(st->keys.as<uint32_t>(), st->vals.as<uint32_t>(), ctx->keys_alt.as<uint32_t>(),
-                          ctx->vals_alt.as<uint32_t>(), m, tile_bits, ctx->sort_scratch.p, s, &in_alt));
+                          ctx->vals_alt.as<uint32_t>(), m, tile_bits, ctx->sort_scratch.p, s, &in_alt,
+                          nullptr, true));
     }
     if (in_alt) {
       swap_buf(st->keys, ctx->keys_alt);
       swap_buf(st->vals, ctx->vals_alt);
     }
   }
+  if (m == 0) PCS_HIP(launch_fill_u32(st->ranges.as<uint32_t>(), 0u, 2 * total_tiles, s));
   {
     StageTimer tm(ctx, ST_RANGES, s);
     PCS_HIP(launch_ranges(st->keys.as<uint32_t>(), m, total_tiles, st->ranges.as<uint32_t>(), s));

@@ -104,6 +104,18 @@ __device__ __forceinline__ void wave_sum16_rows(const float (&v)[16], float (&ou
   }
 }
 
+// Zeroing folded into a kernel that runs anyway: every thread of the grid clears the words
+// i = its global index, + the grid size, ... of each span (a span of count 0 is skipped).
+struct ClearSpans {
+  uint32_t* p[3] = {nullptr, nullptr, nullptr};
+  int64_t count[3] = {0, 0, 0};
+};
+__device__ __forceinline__ void clear_spans(const ClearSpans& c, int64_t gid, int64_t gsize) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    for (int64_t i = gid; i < c.count[k]; i += gsize) c.p[k][i] = 0u;
+}
+
 // ---- launchers (stream-ordered, return the launch error) ------------------------------------
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, float value, int64_t n, hipStream_t s);
@@ -120,14 +132,17 @@ constexpr int kSmallWords = kDepthWord + 4;
 hipError_t launch_init_small(uint32_t* small, hipStream_t s);
 hipError_t launch_project(int64_t n, int n_cams, const DevCamera* cams, const DevOptions& opt,
                           const pcs_gaussians& g, float4* rec, uint4* meta, uint32_t* counts,
-                          uint32_t* zrange, unsigned long long* count_slots, hipStream_t s);
+                          uint32_t* zrange, unsigned long long* count_slots, const ClearSpans& clear,
+                          hipStream_t s);
 
 // Exclusive scan of n u32 values in[gather[j]] (no gather: in[j]); writes out[n] and *total (u64).
 // gather is gather1 when sel is set and *sel is odd, else gather0. Scratch from scan_scratch_bytes.
 size_t scan_scratch_bytes(int64_t n);
 hipError_t launch_scan(const uint32_t* in, const uint32_t* gather0, const uint32_t* gather1,
                        const uint32_t* sel, uint32_t* out, int64_t n, uint64_t* total, void* scratch,
-                       hipStream_t s);
+                       hipStream_t s, bool scratch_cleared = false);
+// Words of scan scratch that must be zero before a scan of n values.
+int64_t scan_clear_words(int64_t n);
 
 // Depth key per (camera, Gaussian) and its combined index as the value. The depth-bit range comes
 // from the projection's slots on the device; info[0..3) receives the pass count, depth bits and
@@ -141,7 +156,7 @@ hipError_t launch_depth_keys(int64_t n, int n_cams, const uint4* meta, const uin
 hipError_t launch_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_cam, const uint32_t* order0,
                           const uint32_t* order1, const uint32_t* passes, const uint4* meta,
                           const uint32_t* counts, const uint32_t* offsets, uint32_t* keys,
-                          uint32_t* vals, hipStream_t s);
+                          uint32_t* vals, const ClearSpans& clear, hipStream_t s);
 
 // Stable LSD radix sort of (key, value) pairs over key bits [0, bits), K = uint32_t or uint64_t.
 // Ping-pongs between (k0,v0) and (k1,v1); returns in *result_in_alt whether the sorted data ended
@@ -151,8 +166,13 @@ size_t sort_scratch_bytes(int64_t m);
 // ends in (k1,v1) when *live_passes is odd; *result_in_alt then describes the host's pass count.
 template <typename K>
 hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int bits, void* scratch,
-                       hipStream_t s, bool* result_in_alt, const uint32_t* live_passes = nullptr);
+                       hipStream_t s, bool* result_in_alt, const uint32_t* live_passes = nullptr,
+                       bool scratch_cleared = false);
+// Words at the start of sort scratch that must be zero before a sort of m pairs (cleared by the
+// sort itself unless the caller has cleared them and says so).
+int64_t sort_clear_words(int64_t m);
 
+// ranges must be zero (cleared by the caller, e.g. folded into binning).
 hipError_t launch_ranges(const uint32_t* keys, int64_t m, int64_t n_tiles, uint32_t* ranges,
                          hipStream_t s);
 

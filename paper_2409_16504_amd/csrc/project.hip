@@ -32,7 +32,9 @@ __global__ __launch_bounds__(256) void k_project(
     const float* __restrict__ scale, const float* __restrict__ opac,
     const float* __restrict__ rgb, const float* __restrict__ nrm, float4* __restrict__ rec,
     uint4* __restrict__ meta, uint32_t* __restrict__ counts, uint32_t* __restrict__ zrange,
-    unsigned long long* __restrict__ count_slots) {
+    unsigned long long* __restrict__ count_slots, ClearSpans clear) {
+  clear_spans(clear, ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x,
+              (int64_t)gridDim.x * gridDim.y * blockDim.x);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int c = blockIdx.y;
   const DevCamera& cam = cams[c];
@@ -147,11 +149,12 @@ hipError_t launch_init_small(uint32_t* small, hipStream_t s) {
 
 hipError_t launch_project(int64_t n, int n_cams, const DevCamera* cams, const DevOptions& opt,
                           const pcs_gaussians& g, float4* rec, uint4* meta, uint32_t* counts,
-                          uint32_t* zrange, unsigned long long* count_slots, hipStream_t s) {
+                          uint32_t* zrange, unsigned long long* count_slots, const ClearSpans& clear,
+                          hipStream_t s) {
   if (n <= 0 || n_cams <= 0) return hipSuccess;
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)n_cams);
   hipLaunchKernelGGL(k_project, grid, dim3(256), 0, s, n, cams, opt, g.mean, g.quat, g.scale,
-                     g.opacity, g.rgb, g.normal, rec, meta, counts, zrange, count_slots);
+                     g.opacity, g.rgb, g.normal, rec, meta, counts, zrange, count_slots, clear);
   return hipGetLastError();
 }
 

@@ -193,8 +193,9 @@ __global__ __launch_bounds__(256) void k_binning(int64_t total, uint32_t n, int 
                                                  const uint32_t* __restrict__ counts,
                                                  const uint32_t* __restrict__ offsets,
                                                  uint32_t* __restrict__ keys,
-                                                 uint32_t* __restrict__ vals) {
+                                                 uint32_t* __restrict__ vals, ClearSpans clear) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  clear_spans(clear, j, (int64_t)gridDim.x * blockDim.x);
   if (j >= total) return;
   const uint32_t* order = (*passes & 1u) ? order1 : order0;   // where the depth sort ended
   const uint32_t i = order[j];
@@ -554,12 +555,15 @@ size_t scan_scratch_bytes(int64_t n) {
   return (size_t)(parts + 1) * sizeof(uint64_t) + 256;
 }
 
+int64_t scan_clear_words(int64_t n) { return (n + kPart - 1) / kPart * 2; }
+
 hipError_t launch_scan(const uint32_t* in, const uint32_t* gather0, const uint32_t* gather1,
                        const uint32_t* sel, uint32_t* out, int64_t n, uint64_t* total, void* scratch,
-                       hipStream_t s) {
+                       hipStream_t s, bool scratch_cleared) {
   const int64_t parts = (n + kPart - 1) / kPart;
   uint64_t* status = reinterpret_cast<uint64_t*>(scratch);
-  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(scratch), 0u, parts * 2, s);
+  hipError_t e = scratch_cleared ? hipSuccess
+                                 : launch_fill_u32(reinterpret_cast<uint32_t*>(scratch), 0u, parts * 2, s);
   if (e != hipSuccess) return e;
   if (n == 0) return launch_fill_u32(reinterpret_cast<uint32_t*>(total), 0u, 2, s);
   hipLaunchKernelGGL(k_scan, dim3((unsigned)parts), dim3(kThreads), 0, s, in, gather0, gather1, sel, out,
@@ -579,11 +583,12 @@ hipError_t launch_depth_keys(int64_t n, int n_cams, const uint4* meta, const uin
 hipError_t launch_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_cam, const uint32_t* order0,
                           const uint32_t* order1, const uint32_t* passes, const uint4* meta,
                           const uint32_t* counts, const uint32_t* offsets, uint32_t* keys,
-                          uint32_t* vals, hipStream_t s) {
+                          uint32_t* vals, const ClearSpans& clear, hipStream_t s) {
   const int64_t total = n * n_cams;
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_binning, dim3(blocks_for(total, 256)), dim3(256), 0, s, total, (uint32_t)n, TX,
-                     (uint32_t)tiles_per_cam, order0, order1, passes, meta, counts, offsets, keys, vals);
+                     (uint32_t)tiles_per_cam, order0, order1, passes, meta, counts, offsets, keys, vals,
+                     clear);
   return hipGetLastError();
 }
 
@@ -594,9 +599,12 @@ size_t sort_scratch_bytes(int64_t m) {
   return (size_t)(2 * kMaxPasses * kBins + 2 * parts * kBins) * sizeof(uint32_t) + 256;
 }
 
+int64_t sort_clear_words(int64_t m) { return kMaxPasses * kBins + (m + kPart - 1) / kPart * kBins; }
+
 template <typename K>
 hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int bits, void* scratch,
-                       hipStream_t s, bool* result_in_alt, const uint32_t* live_passes) {
+                       hipStream_t s, bool* result_in_alt, const uint32_t* live_passes,
+                       bool scratch_cleared) {
   *result_in_alt = false;
   if (m <= 1 || bits <= 0) return hipSuccess;
   const int n_passes = (bits + 7) / 8;
@@ -611,7 +619,7 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
   uint32_t* status0 = hist + kMaxPasses * kBins;
   uint32_t* base = status0 + parts * kBins;
   uint32_t* status1 = base + kMaxPasses * kBins;
-  hipError_t e = launch_fill_u32(hist, 0u, kMaxPasses * kBins + parts * kBins, s);
+  hipError_t e = scratch_cleared ? hipSuccess : launch_fill_u32(hist, 0u, kMaxPasses * kBins + parts * kBins, s);
   if (e != hipSuccess) return e;
   const int hblocks = (int)std::min<int64_t>(kHistBlocks, parts);
   hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)hblocks), dim3(256), 0, s, k0, m, n_passes, hist);
@@ -632,14 +640,13 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
   return hipSuccess;
 }
 template hipError_t launch_sort<uint32_t>(uint32_t*, uint32_t*, uint32_t*, uint32_t*, int64_t, int,
-                                          void*, hipStream_t, bool*, const uint32_t*);
+                                          void*, hipStream_t, bool*, const uint32_t*, bool);
 template hipError_t launch_sort<uint64_t>(uint64_t*, uint32_t*, uint64_t*, uint32_t*, int64_t, int,
-                                          void*, hipStream_t, bool*, const uint32_t*);
+                                          void*, hipStream_t, bool*, const uint32_t*, bool);
 
 hipError_t launch_ranges(const uint32_t* keys, int64_t m, int64_t n_tiles, uint32_t* ranges,
                          hipStream_t s) {
-  hipError_t e = launch_fill_u32(ranges, 0u, 2 * n_tiles, s);
-  if (e != hipSuccess || m == 0) return e;
+  if (m == 0) return hipSuccess;
   hipLaunchKernelGGL(k_ranges, dim3(blocks_for(m, 256)), dim3(256), 0, s, keys, m, n_tiles, ranges);
   return hipGetLastError();
 }
