@@ -379,11 +379,11 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   if (cn > 0) {
     StageTimer tm(ctx, ST_SORT, s);
     bool unused = false;
-    PCS_HIP(launch_depth_keys(n, n_cams, ctx->meta.as<uint4>(), ctx->counts.as<uint32_t>(), d_zrange, d_depth,
-                              ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(), s));
+    PCS_HIP(launch_depth_keys_hist(cn, ctx->meta.as<uint4>(), ctx->counts.as<uint32_t>(), d_zrange, d_depth,
+                                   ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(), ctx->dsort_scratch.p, s));
     PCS_HIP(launch_sort(ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(), ctx->dkeys_alt.as<uint32_t>(),
-                        ctx->dvals_alt.as<uint32_t>(), cn, 31, ctx->dsort_scratch.p, s, &unused, d_depth,
-                        true));
+                        ctx->dvals_alt.as<uint32_t>(), cn, 32, ctx->dsort_scratch.p, s, &unused, d_depth,
+                        true, true));
   }
   if (cn > 0) {
     StageTimer tm(ctx, ST_SCAN, s);

@@ -144,12 +144,13 @@ hipError_t launch_scan(const uint32_t* in, const uint32_t* gather0, const uint32
 // Words of scan scratch that must be zero before a scan of n values.
 int64_t scan_clear_words(int64_t n);
 
-// Depth key per (camera, Gaussian) and its combined index as the value. The depth-bit range comes
-// from the projection's slots on the device; info[0..3) receives the pass count, depth bits and
-// minimum depth bits.
-hipError_t launch_depth_keys(int64_t n, int n_cams, const uint4* meta, const uint32_t* counts,
-                             const uint32_t* zrange, uint32_t* info, uint32_t* keys, uint32_t* vals,
-                             hipStream_t s);
+// Depth key per (camera, Gaussian) entry and its index as the value, and the keys' four digit
+// histograms into the sort scratch's histogram area (zeroed beforehand), for a launch_sort with
+// hist_ready. The depth-bit range comes from the projection's slots on the device; info[0..3)
+// receives the pass count, depth bits and minimum depth bits.
+hipError_t launch_depth_keys_hist(int64_t m, const uint4* meta, const uint32_t* counts,
+                                  const uint32_t* zrange, uint32_t* info, uint32_t* keys, uint32_t* vals,
+                                  void* sort_scratch, hipStream_t s);
 
 // Tile keys of every visible splat, written in the depth order at `offsets`; the order is order1
 // when *passes is odd (where the depth sort ended), else order0.
@@ -167,7 +168,7 @@ size_t sort_scratch_bytes(int64_t m);
 template <typename K>
 hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int bits, void* scratch,
                        hipStream_t s, bool* result_in_alt, const uint32_t* live_passes = nullptr,
-                       bool scratch_cleared = false);
+                       bool scratch_cleared = false, bool hist_ready = false);
 // Words at the start of sort scratch that must be zero before a sort of m pairs (cleared by the
 // sort itself unless the caller has cleared them and says so).
 int64_t sort_clear_words(int64_t m);

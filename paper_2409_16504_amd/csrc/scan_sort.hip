@@ -146,42 +146,6 @@ __global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* __restrict__ 
 // ---- depth keys and binning ----------------------------------------------------------------
 // One key per (camera, Gaussian); culled splats get all bits set (they have no tile instances,
 // so where they land in the order does not matter).
-// One depth key per (camera, Gaussian): the bits of its depth above the frame's minimum (positive
-// floats order like their bit patterns). No camera field is needed: the tile keys carry the
-// camera, and the stable tile sort keeps each (camera, tile) run in depth order with ties by the
-// combined index, i.e. by Gaussian index within a camera.
-__global__ __launch_bounds__(256) void k_depth_keys(int64_t n, const uint4* __restrict__ meta,
-                                                    const uint32_t* __restrict__ counts,
-                                                    const uint32_t* __restrict__ zrange,
-                                                    uint32_t* __restrict__ info,
-                                                    uint32_t* __restrict__ keys,
-                                                    uint32_t* __restrict__ vals) {
-  // depth-bit range of the frame from the projection's kZSlots slot pairs
-  __shared__ uint32_t s_z[2];
-  if (threadIdx.x < kWave) {
-    uint32_t lo = zrange[threadIdx.x], hi = zrange[kZSlots + threadIdx.x];
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      lo = min(lo, (uint32_t)__shfl_xor((int)lo, o, kWave));
-      hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, kWave));
-    }
-    if (threadIdx.x == 0) { s_z[0] = lo; s_z[1] = hi; }
-  }
-  __syncthreads();
-  const uint32_t zmin = s_z[0], zmax = s_z[1];
-  const int depth_bits = zmax > zmin ? 32 - __clz(zmax - zmin) : 0;
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
-    info[0] = (uint32_t)((depth_bits + 7) / 8);          // passes the depth sort needs
-    info[1] = (uint32_t)depth_bits;
-    info[2] = zmin;
-  }
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int64_t j = (int64_t)blockIdx.y * n + i;
-  keys[j] = counts[j] ? meta[j].x - zmin : ~0u;
-  vals[j] = (uint32_t)j;
-}
-
 // Thread per position of the depth order: the splat there writes its tile keys (global tile id)
 // and Gaussian index at its offset in that order.
 __global__ __launch_bounds__(256) void k_binning(int64_t total, uint32_t n, int TX,
@@ -222,6 +186,7 @@ constexpr uint32_t kSortAgg = 1u << 30;
 constexpr uint32_t kSortPrefix = 2u << 30;
 constexpr uint32_t kSortValue = (1u << 30) - 1;
 constexpr int kLookWindow = 32;
+constexpr int kHistBlocks = 256;
 
 // Digit histograms of every pass in one read of the keys. Each block takes partitions of 4096 keys
 // (16 per thread, all loads issued before any is used). Lanes of a wavefront holding the same digit
@@ -269,6 +234,79 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, 
   }
   __syncthreads();
   for (int p = 0; p < n_passes; ++p) {
+    const uint32_t v = sh[p][tid];
+    if (v) atomicAdd(&hist[p * kBins + tid], v);
+  }
+}
+
+// Depth keys and their digit histograms in one pass (the key of entry j, over all cameras, is the
+// bits of its depth above the frame's minimum, or all ones for a culled splat; its value is j).
+// The depth-bit range comes from the projection's slots; block 0 also records the pass count.
+// The histograms of the four 8-bit digits go to hist[4][256] (zeroed beforehand).
+__global__ __launch_bounds__(256) void k_depth_keys_hist(int64_t m, const uint4* __restrict__ meta,
+                                                         const uint32_t* __restrict__ counts,
+                                                         const uint32_t* __restrict__ zrange,
+                                                         uint32_t* __restrict__ info,
+                                                         uint32_t* __restrict__ keys,
+                                                         uint32_t* __restrict__ vals,
+                                                         uint32_t* __restrict__ hist) {
+  constexpr int kDigits = 4;
+  __shared__ uint32_t sh[kDigits][kBins];
+  __shared__ uint32_t s_z[2];
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  for (int p = 0; p < kDigits; ++p) sh[p][tid] = 0;
+  if (tid < kWave) {
+    uint32_t lo = zrange[tid], hi = zrange[kZSlots + tid];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      lo = min(lo, (uint32_t)__shfl_xor((int)lo, o, kWave));
+      hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, kWave));
+    }
+    if (tid == 0) { s_z[0] = lo; s_z[1] = hi; }
+  }
+  __syncthreads();
+  const uint32_t zmin = s_z[0], zmax = s_z[1];
+  if (blockIdx.x == 0 && tid == 0) {
+    const int depth_bits = zmax > zmin ? 32 - __clz(zmax - zmin) : 0;
+    info[0] = (uint32_t)((depth_bits + 7) / 8);          // passes the depth sort needs
+    info[1] = (uint32_t)depth_bits;
+    info[2] = zmin;
+  }
+  const uint64_t lt_mask = lanemask_lt();
+  for (int64_t part = blockIdx.x; part * kPart < m; part += gridDim.x) {
+    const int64_t wbase = part * kPart + (int64_t)wave * (kWave * kItems);
+    uint32_t zb[kItems], c[kItems];
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+      const int64_t pos = wbase + (int64_t)it * kWave + lane;
+      zb[it] = pos < m ? meta[pos].x : 0u;
+      c[it] = pos < m ? counts[pos] : 0u;
+    }
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+      const int64_t pos = wbase + (int64_t)it * kWave + lane;
+      const bool valid = pos < m;
+      const uint64_t vmask = __ballot(valid);
+      if (vmask == 0) break;
+      const uint32_t k = c[it] ? zb[it] - zmin : ~0u;
+      if (valid) { keys[pos] = k; vals[pos] = (uint32_t)pos; }
+#pragma unroll
+      for (int p = 0; p < kDigits - 1; ++p)            // lower digits: one atomic per key
+        if (valid) atomicAdd(&sh[p][(k >> (8 * p)) & 0xFF], 1u);
+      // top digit: few distinct values (0, or all ones for culled splats): count runs once
+      const uint32_t d = k >> 24;
+      uint64_t peers = vmask;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        peers &= bit ? bal : ~bal;
+      }
+      if (valid && (peers & lt_mask) == 0) atomicAdd(&sh[kDigits - 1][d], (uint32_t)__popcll(peers));
+    }
+  }
+  __syncthreads();
+  for (int p = 0; p < kDigits; ++p) {
     const uint32_t v = sh[p][tid];
     if (v) atomicAdd(&hist[p * kBins + tid], v);
   }
@@ -571,12 +609,13 @@ hipError_t launch_scan(const uint32_t* in, const uint32_t* gather0, const uint32
   return hipGetLastError();
 }
 
-hipError_t launch_depth_keys(int64_t n, int n_cams, const uint4* meta, const uint32_t* counts,
-                             const uint32_t* zrange, uint32_t* info, uint32_t* keys, uint32_t* vals,
-                             hipStream_t s) {
-  if (n == 0 || n_cams == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_depth_keys, dim3(blocks_for(n, 256), (unsigned)n_cams), dim3(256), 0, s, n, meta,
-                     counts, zrange, info, keys, vals);
+hipError_t launch_depth_keys_hist(int64_t m, const uint4* meta, const uint32_t* counts,
+                                  const uint32_t* zrange, uint32_t* info, uint32_t* keys, uint32_t* vals,
+                                  void* sort_scratch, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<int64_t>(kHistBlocks, (m + kPart - 1) / kPart);
+  hipLaunchKernelGGL(k_depth_keys_hist, dim3(blocks), dim3(256), 0, s, m, meta, counts, zrange, info, keys,
+                     vals, reinterpret_cast<uint32_t*>(sort_scratch));
   return hipGetLastError();
 }
 
@@ -592,7 +631,6 @@ hipError_t launch_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_cam, 
   return hipGetLastError();
 }
 
-constexpr int kHistBlocks = 256;
 
 size_t sort_scratch_bytes(int64_t m) {
   const int64_t parts = (m + kPart - 1) / kPart;
@@ -604,7 +642,7 @@ int64_t sort_clear_words(int64_t m) { return kMaxPasses * kBins + (m + kPart - 1
 template <typename K>
 hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int bits, void* scratch,
                        hipStream_t s, bool* result_in_alt, const uint32_t* live_passes,
-                       bool scratch_cleared) {
+                       bool scratch_cleared, bool hist_ready) {
   *result_in_alt = false;
   if (m <= 1 || bits <= 0) return hipSuccess;
   const int n_passes = (bits + 7) / 8;
@@ -622,7 +660,8 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
   hipError_t e = scratch_cleared ? hipSuccess : launch_fill_u32(hist, 0u, kMaxPasses * kBins + parts * kBins, s);
   if (e != hipSuccess) return e;
   const int hblocks = (int)std::min<int64_t>(kHistBlocks, parts);
-  hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)hblocks), dim3(256), 0, s, k0, m, n_passes, hist);
+  if (!hist_ready)
+    hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)hblocks), dim3(256), 0, s, k0, m, n_passes, hist);
   hipLaunchKernelGGL(k_digit_base, dim3(n_passes), dim3(256), 0, s, hist, base);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   K *ki = k0, *ko = k1;
@@ -640,9 +679,9 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
   return hipSuccess;
 }
 template hipError_t launch_sort<uint32_t>(uint32_t*, uint32_t*, uint32_t*, uint32_t*, int64_t, int,
-                                          void*, hipStream_t, bool*, const uint32_t*, bool);
+                                          void*, hipStream_t, bool*, const uint32_t*, bool, bool);
 template hipError_t launch_sort<uint64_t>(uint64_t*, uint32_t*, uint64_t*, uint32_t*, int64_t, int,
-                                          void*, hipStream_t, bool*, const uint32_t*, bool);
+                                          void*, hipStream_t, bool*, const uint32_t*, bool, bool);
 
 hipError_t launch_ranges(const uint32_t* keys, int64_t m, int64_t n_tiles, uint32_t* ranges,
                          hipStream_t s) {
