@@ -163,9 +163,13 @@ int pcs_state_bins(const pcs_state* st, const uint64_t** keys, const uint32_t** 
  * n points xyz[3][n] the k nearest points (itself included, ties by index, k <= 32) give a
  * covariance about their mean; its eigenvectors are the axes, sigma_i = kappa sqrt(lambda_i) with
  * sigma_3 >= floor * sigma_2, the normal is the least-variance axis oriented away from the cloud
- * centroid. Outputs quat[4][n] (w >= 0), scale[3][n], normal[3][n]. */
+ * centroid. Outputs quat[4][n] (w >= 0), scale[3][n], normal[3][n], and, if nn_dist is not
+ * NULL, nn_dist[n]: the distance to the nearest other point (the second of the k, self included;
+ * 0 for a duplicated point), from which the average point spacing of Section 4.1's global-sigma
+ * baseline is taken. nn_dist needs k >= 2. */
 int pcs_knn_pca(pcs_context* ctx, const float* xyz, int64_t n, int32_t k, float kappa,
-                float floor_ratio, float* quat, float* scale, float* normal, void* stream);
+                float floor_ratio, float* quat, float* scale, float* normal, float* nn_dist,
+                void* stream);
 
 /* ---- sparse point-to-ellipsoid estimator (Section 3.2) -------------------------------------
  * Voxels of a point cloud on a grid of G^3 voxels over [-1,1]^3 (G a power of two <= 1024; G = 1024

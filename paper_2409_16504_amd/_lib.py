@@ -92,7 +92,7 @@ def load():
     L.pcs_state_bins.argtypes = [c_vp, ctypes.POINTER(c_vp), ctypes.POINTER(c_vp), ctypes.POINTER(c_i64),
                                  ctypes.POINTER(c_vp), ctypes.POINTER(c_i64), ctypes.POINTER(c_vp),
                                  ctypes.POINTER(c_vp)]
-    L.pcs_knn_pca.argtypes = [c_vp, c_vp, c_i64, c_i32, c_f, c_f, c_vp, c_vp, c_vp, c_vp]
+    L.pcs_knn_pca.argtypes = [c_vp, c_vp, c_i64, c_i32, c_f, c_f, c_vp, c_vp, c_vp, c_vp, c_vp]
     for name in ("pcs_context_create", "pcs_context_timing", "pcs_context_timing_stages",
                  "pcs_context_timings", "pcs_state_create",
                  "pcs_render_forward", "pcs_render_backward", "pcs_state_bins", "pcs_knn_pca",

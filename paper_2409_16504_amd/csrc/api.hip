@@ -510,12 +510,14 @@ int pcs_state_bins(const pcs_state* st_c, const uint64_t** keys, const uint32_t*
 }
 
 int pcs_knn_pca(pcs_context* ctx, const float* xyz, int64_t n, int32_t k, float kappa,
-                float floor_ratio, float* quat, float* scale, float* normal, void* stream) {
+                float floor_ratio, float* quat, float* scale, float* normal, float* nn_dist,
+                void* stream) {
   if (!ctx) return fail(PCS_ERR_INVALID_ARG, "context is NULL");
   if (n < 0 || (n > 0 && (!xyz || !quat || !scale || !normal)))
     return fail(PCS_ERR_INVALID_ARG, "bad point buffers");
   if (k < 1 || k > 32) return fail(PCS_ERR_INVALID_ARG, "k must be in [1, 32]");
   if (n > 0 && k > n) return fail(PCS_ERR_INVALID_ARG, "k exceeds the number of points");
+  if (nn_dist && k < 2) return fail(PCS_ERR_INVALID_ARG, "the nearest-neighbour distance needs k >= 2");
   if (!std::isfinite(kappa) || !std::isfinite(floor_ratio) || kappa <= 0.0f || floor_ratio < 0.0f)
     return fail(PCS_ERR_INVALID_ARG, "kappa must be positive and floor_ratio non-negative");
   if (n >= (int64_t(1) << 31)) return fail(PCS_ERR_UNSUPPORTED, "n must be below 2^31");
@@ -524,7 +526,7 @@ int pcs_knn_pca(pcs_context* ctx, const float* xyz, int64_t n, int32_t k, float 
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   PCS_TRY(ensure(ctx->knn_scratch, knn_scratch_bytes(n), "kNN scratch"));
   StageTimer tm(ctx, ST_KNN, s);
-  PCS_HIP(launch_knn_pca(xyz, n, k, kappa, floor_ratio, quat, scale, normal, ctx->knn_scratch.p,
+  PCS_HIP(launch_knn_pca(xyz, n, k, kappa, floor_ratio, quat, scale, normal, nn_dist, ctx->knn_scratch.p,
                          ctx->knn_scratch.cap, ctx->host_small + 192, s));
   return PCS_OK;
 }

@@ -177,7 +177,8 @@ __global__ __launch_bounds__(256) void k_knn_pca(const float4* __restrict__ sort
                                                  const double* __restrict__ sum, float kappa,
                                                  float floor_ratio, float* __restrict__ quat,
                                                  float* __restrict__ scale,
-                                                 float* __restrict__ normal) {
+                                                 float* __restrict__ normal,
+                                                 float* __restrict__ nn_dist) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const float4 P = sorted[s];
@@ -240,6 +241,7 @@ __global__ __launch_bounds__(256) void k_knn_pca(const float4* __restrict__ sort
     bnd = fmaxf(bnd, 0.0f);
     if (thr < bnd * bnd * (1.0f - 1e-5f)) break;
   }
+  if (nn_dist) nn_dist[self] = sqrtf(bd[1]);   // nearest other point (self is one of the first two)
   // neighbourhood mean and covariance (two passes, coordinates relative to P)
   const float inv_k = 1.0f / (float)k;
   float mx = 0.f, my = 0.f, mz = 0.f;
@@ -332,7 +334,7 @@ size_t knn_scratch_bytes(int64_t n) {
 }
 
 hipError_t launch_knn_pca(const float* xyz, int64_t n, int k, float kappa, float floor_ratio,
-                          float* quat, float* scale, float* normal, void* scratch,
+                          float* quat, float* scale, float* normal, float* nn_dist, void* scratch,
                           size_t scratch_bytes, uint32_t* host_pinned, hipStream_t s) {
   if (scratch_bytes < knn_scratch_bytes(n)) return hipErrorInvalidValue;
   char* base = reinterpret_cast<char*>(scratch);
@@ -395,10 +397,10 @@ hipError_t launch_knn_pca(const float* xyz, int64_t n, int k, float kappa, float
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (k <= 16) {
     hipLaunchKernelGGL(k_knn_pca<16>, dim3(blocks_for(n, 256)), dim3(256), 0, s, sorted, xyz, n, k, G,
-                       cell_start, sums, kappa, floor_ratio, quat, scale, normal);
+                       cell_start, sums, kappa, floor_ratio, quat, scale, normal, nn_dist);
   } else {
     hipLaunchKernelGGL(k_knn_pca<32>, dim3(blocks_for(n, 256)), dim3(256), 0, s, sorted, xyz, n, k, G,
-                       cell_start, sums, kappa, floor_ratio, quat, scale, normal);
+                       cell_start, sums, kappa, floor_ratio, quat, scale, normal, nn_dist);
   }
   return hipGetLastError();
 }

@@ -205,7 +205,7 @@ hipError_t launch_project_backward(int64_t n, int n_cams, const DevCamera* cams,
 
 // Synchronises the stream once (bounding box readback through host_pinned, >= 24 bytes).
 hipError_t launch_knn_pca(const float* xyz, int64_t n, int k, float kappa, float floor_ratio,
-                          float* quat, float* scale, float* normal, void* scratch,
+                          float* quat, float* scale, float* normal, float* nn_dist, void* scratch,
                           size_t scratch_bytes, uint32_t* host_pinned, hipStream_t s);
 size_t knn_scratch_bytes(int64_t n);
 

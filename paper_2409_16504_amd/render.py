@@ -176,7 +176,10 @@ class Renderer:
         return dict(keys=keys, vals=vals, ranges=ranges, n_contrib=nc, t_final=tf)
 
     # -- kNN-PCA ------------------------------------------------------------------------------
-    def knn_pca(self, xyz: torch.Tensor, k=16, kappa=1.0, floor=0.1, out: dict | None = None) -> dict:
+    def knn_pca(self, xyz: torch.Tensor, k=16, kappa=1.0, floor=0.1, out: dict | None = None,
+                nn_dist: bool = False) -> dict:
+        """kNN-PCA surfels of the points xyz (3, n); with ``nn_dist`` also each point's distance to
+        its nearest other point (key "nn_dist")."""
         n = xyz.shape[1]
         if xyz.shape != (3, n) or xyz.dtype != torch.float32 or not xyz.is_cuda or not xyz.is_contiguous():
             raise ValueError("xyz must be a contiguous float32 CUDA tensor of shape (3, n)")
@@ -184,10 +187,12 @@ class Renderer:
         if out is None:
             out = dict(quat=torch.empty((4, n), device=dev), scale=torch.empty((3, n), device=dev),
                        normal=torch.empty((3, n), device=dev))
+        if nn_dist and "nn_dist" not in out:
+            out["nn_dist"] = torch.empty((n,), device=dev)
         with torch.cuda.device(self.device):
             check(_lib.load().pcs_knn_pca(self.ctx, _ptr(xyz), n, int(k), float(kappa), float(floor),
                                           _ptr(out["quat"]), _ptr(out["scale"]), _ptr(out["normal"]),
-                                          _stream()))
+                                          _ptr(out["nn_dist"]) if nn_dist else None, _stream()))
         return out
 
     # -- timing -------------------------------------------------------------------------------

@@ -51,7 +51,23 @@ def make_cloud(R: Renderer, seed: int, n: int, grid: int = 0, dense_factor: int 
                  opacity=torch.full((xd.shape[1],), 0.9, device=dev),
                  rgb=torch.from_numpy(np.ascontiguousarray(rgbd, np.float32)).to(dev), normal=est["normal"])
     vox = Voxels(R).build(xyz, col, grid) if grid else adaptive_grid(R, xyz, col)
-    return dict(seed=seed, xyz=xyz, rgb=col, dense=dense, vox=vox)
+    # average point spacing (mean distance to the nearest other point) for the global-sigma baseline
+    dbar = float(R.knn_pca(xyz, k=16, kappa=1.0, floor=0.1, nn_dist=True)["nn_dist"].mean().item())
+    return dict(seed=seed, xyz=xyz, rgb=col, dense=dense, vox=vox, dbar=dbar)
+
+
+SIGMA_FACTORS = (1.2, 1.5, 1.7)
+
+
+def global_sigma_gaussians(c: dict, factor: float) -> dict:
+    """Section 4.1's real-time baseline: every point an isotropic Gaussian of one global standard
+    deviation, factor x the average point spacing (opacity 0.9 as on the kNN-PCA path)."""
+    n = c["xyz"].shape[1]
+    dev = c["xyz"].device
+    quat = torch.zeros((4, n), device=dev)
+    quat[0] = 1.0
+    return dict(mean=c["xyz"], quat=quat, scale=torch.full((3, n), factor * c["dbar"], device=dev),
+                opacity=torch.full((n,), 0.9, device=dev), rgb=c["rgb"], normal=torch.zeros((3, n), device=dev))
 
 
 def knn_gaussians(R: Renderer, c: dict, kappa: float) -> dict:
@@ -65,15 +81,20 @@ def render_rgb(R: Renderer, g: dict, cams: list) -> torch.Tensor:
     return R.render(g, cams, default_options(), want=("rgb",))["rgb"]
 
 
-def evaluate(R, est, clouds, cams, kappa) -> dict:
-    learned, plain = [], []
+def evaluate(R, est, clouds, cams, kappa, sigma_factor=None) -> dict:
+    learned, plain, glob = [], [], []
     with torch.no_grad():
         for c in clouds:
             gt = render_rgb(R, c["dense"], cams)
             learned.append(psnr(render_rgb(R, est.forward(c["vox"]), cams), gt))
             plain.append(psnr(render_rgb(R, knn_gaussians(R, c, kappa), cams), gt))
-    return dict(psnr_learned=float(np.mean(learned)), psnr_knn_pca=float(np.mean(plain)),
-                gap_db=float(np.mean(learned) - np.mean(plain)))
+            if sigma_factor is not None:
+                glob.append(psnr(render_rgb(R, global_sigma_gaussians(c, sigma_factor), cams), gt))
+    out = dict(psnr_learned=float(np.mean(learned)), psnr_knn_pca=float(np.mean(plain)),
+               gap_db=float(np.mean(learned) - np.mean(plain)))
+    if sigma_factor is not None:
+        out.update(psnr_global_sigma=float(np.mean(glob)), gap_vs_global_sigma_db=float(np.mean(learned) - np.mean(glob)))
+    return out
 
 
 def main(argv=None):
@@ -110,6 +131,15 @@ def main(argv=None):
         scores[kappa] = float(np.mean(vals))
     kappa = max(scores, key=scores.get)
     print(f"[train] kNN-PCA kappa scores {scores} -> {kappa}", flush=True)
+    sscores = {}
+    for fac in SIGMA_FACTORS:
+        vals = []
+        for c in train:
+            gt = render_rgb(R, c["dense"], sel_cams)
+            vals.append(psnr(render_rgb(R, global_sigma_gaussians(c, fac), sel_cams), gt))
+        sscores[fac] = float(np.mean(vals))
+    sigma_factor = max(sscores, key=sscores.get)
+    print(f"[train] global-sigma factor scores {sscores} -> {sigma_factor}", flush=True)
 
     est = SparseEstimator(R, seed=0)
     opt = Adam(est.params, lr=args.lr)
@@ -123,7 +153,7 @@ def main(argv=None):
             m.copy_(v)
         opt.t = int(ck["adam_t"])
     eval_cams = orbit_cameras(args.views, np.random.default_rng(2024), width=args.res, height=args.res)
-    before = evaluate(R, est, held, eval_cams, kappa)
+    before = evaluate(R, est, held, eval_cams, kappa, sigma_factor)
     print(f"[train] before: {before}", flush=True)
 
     view_rng = np.random.default_rng(99)
@@ -151,7 +181,7 @@ def main(argv=None):
             print(f"[train] step {step} loss {loss:.5f} ({time.time() - t1:.1f}s)", flush=True)
     torch.cuda.synchronize()
     train_s = time.time() - t1
-    after = evaluate(R, est, held, eval_cams, kappa)
+    after = evaluate(R, est, held, eval_cams, kappa, sigma_factor)
     print(f"[train] after: {after}", flush=True)
 
     # estimator inference time per cloud (voxelise + 8 convolutions + head)
@@ -168,7 +198,8 @@ def main(argv=None):
     infer_ms = (time.perf_counter() - t2) * 1e3 / reps
     report = dict(steps=args.steps, train_seconds=train_s, ms_per_step=train_s * 1e3 / max(1, args.steps),
                   clouds_per_step=len(train), views=args.views, res=args.res, points=args.points,
-                  voxels=[c["vox"].V for c in train], grids=[c["vox"].grid for c in train], kappa=kappa, kappa_scores=scores, before=before,
+                  voxels=[c["vox"].V for c in train], grids=[c["vox"].grid for c in train], kappa=kappa, kappa_scores=scores,
+                  sigma_factor=sigma_factor, sigma_scores=sscores, before=before,
                   after=after, loss_first=losses[0] if losses else None, loss_last=losses[-1] if losses else None,
                   inference_ms_per_cloud=infer_ms)
     print(json.dumps(report), flush=True)

@@ -51,7 +51,7 @@ def test_null_arguments_are_rejected(L):
     assert b"context" in L.pcs_last_error()
     assert L.pcs_render_backward(None, None, None, None, None) == _lib.PCS_ERR_INVALID_ARG
     assert L.pcs_state_bins(None, None, None, None, None, None, None, None) == _lib.PCS_ERR_INVALID_ARG
-    assert L.pcs_knn_pca(None, None, 0, 16, 1.0, 0.1, None, None, None, None) == _lib.PCS_ERR_INVALID_ARG
+    assert L.pcs_knn_pca(None, None, 0, 16, 1.0, 0.1, None, None, None, None, None) == _lib.PCS_ERR_INVALID_ARG
     assert L.pcs_context_create(0, None) == _lib.PCS_ERR_INVALID_ARG
     assert L.pcs_context_timing(None, 1) == _lib.PCS_ERR_INVALID_ARG
     assert L.pcs_state_create(None, None) == _lib.PCS_ERR_INVALID_ARG

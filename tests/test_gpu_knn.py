@@ -98,3 +98,22 @@ def test_full_size_cloud(R):
     ref = kp.knn_pca(p, 16, neighbours=nb)
     gpu = gpu_knn(R, p)
     compare(p, gpu, ref, np.full(p.shape[1], np.inf))
+
+
+def test_nearest_neighbour_distance(R):
+    """The optional nearest-other-point distance: FP32 against the exact FP64 distance to the
+    oracle's second neighbour (self is the first); duplicated points give 0; k < 2 is refused."""
+    import torch
+    _, p, _ = make_surface(20000, 37, quantize=False)
+    p = np.ascontiguousarray(np.concatenate([p, p[:, :50]], axis=1), np.float32)   # 50 duplicates
+    tp = torch.from_numpy(p).cuda()
+    out = R.knn_pca(tp, k=16, nn_dist=True)
+    d = out["nn_dist"].cpu().numpy().astype(np.float64)
+    nb, _ = kp.knn(p, 2)
+    pd = p.astype(np.float64)
+    ref = np.linalg.norm(pd[:, nb[:, 1]] - pd, axis=0)
+    assert np.all(np.abs(d - ref) <= 1e-5 * ref + 1e-7), np.max(np.abs(d - ref))
+    dup = np.r_[np.arange(50), p.shape[1] - 50 + np.arange(50)]
+    assert np.all(d[dup] == 0.0)
+    with pytest.raises(RuntimeError):
+        R.knn_pca(tp, k=1, nn_dist=True)
