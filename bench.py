@@ -136,6 +136,7 @@ def main():
     gap = None if args.no_extras else psnr_gap(R)
     if extras is not None:
         extras["psnr_gap"] = gap
+        extras["late_shading"] = late_shading(R, out, cams)
     line = dict(
         metric=METRIC, value=args.n / (ms_per_step * 1e-3), unit="Gaussians/s", n_gpus=1,
         steps=args.steps, warmup=args.warmup, ms_per_step=ms_per_step, higher_is_better=True,
@@ -208,6 +209,23 @@ def extra_workloads(R):
                      ms_per_cloud=(t4 - t3) * 1e3 / reps, stage_ms=est_stages,
                      conv_mfma_tflops=conv_flop / (conv_ms * 1e-3) / 1e12 if conv_ms == conv_ms else None)
     return dict(many_cameras=many, estimator=estimator)
+
+
+def late_shading(R, out, cams, reps=20):
+    """Blinn-Phong late shading of the headline frame's rgb / normal / alpha (one kernel, 28 B read
+    and 12 B written per pixel)."""
+    import torch
+    light = dict(dir=(0.3, 0.8, 0.5), color=(1.0, 1.0, 1.0), ambient=0.15, diffuse=0.7, specular=0.3, shininess=24.0)
+    shaded = R.shade(out, cams, light)
+    torch.cuda.synchronize()
+    R.timing(True, stages=["shade"])
+    for _ in range(reps):
+        R.shade(out, cams, light, out=shaded)
+    ms = R.timings()["shade"][0] / reps
+    W, H = cams[0].width, cams[0].height
+    byts = W * H * 40
+    return dict(workload=f"Blinn-Phong late shading of the {W}x{H} frame", ms=ms, bytes=byts,
+                gbs=byts / (ms * 1e-3) / 1e9, frac=byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
 
 
 # Kernel source each stage's dominant kernel is built from (a counter summary applies only while

@@ -120,7 +120,7 @@ void pcs_context_destroy(pcs_context* ctx);
  * pcs_context_timing(ctx, 1) resets the accumulators and enables timing; pcs_context_timings
  * copies up to `cap` accumulated millisecond totals (stage order: project, scan, binning, sort,
  * ranges, composite, backward_composite, backward_project, knn_pca, voxelize, conv, conv_backward,
- * head, head_backward) plus per-stage launch counts
+ * head, head_backward, shade) plus per-stage launch counts
  * and synchronises the stream. */
 int pcs_context_timing(pcs_context* ctx, int enable);
 /* As pcs_context_timing(ctx, 1), but events are recorded only around the stages whose bit
@@ -170,6 +170,26 @@ int pcs_state_bins(const pcs_state* st, const uint64_t** keys, const uint32_t** 
 int pcs_knn_pca(pcs_context* ctx, const float* xyz, int64_t n, int32_t k, float kappa,
                 float floor_ratio, float* quat, float* scale, float* normal, float* nn_dist,
                 void* stream);
+
+/* ---- late shading (Section 3.1: the rendered normal map shaded by a pixel shader) -----------
+ * The paper fixes no shading model; this is Blinn-Phong with one directional light. Per pixel of
+ * camera c: fg = rgb - (1 - alpha) bg (the premultiplied albedo), n = normal / |normal| (world
+ * frame; a zero normal keeps only the ambient term), v = the unit direction from the pixel back to
+ * the camera (the pixel ray (x + 0.5 - cx) / fx, (y + 0.5 - cy) / fy, 1 rotated to world by T^T,
+ * negated), l = light.dir normalised, h = (l + v) / |l + v|:
+ *   out = (fg (ambient + diffuse max(0, n.l)) + alpha specular max(0, n.h)^shininess) color
+ *         + (1 - alpha) bg.
+ * in->rgb, in->normal ([C][3][H][W]) and in->alpha ([C][H][W]) are required; out_rgb [C][3][H][W]
+ * may be in->rgb (each pixel is read before it is written). All cameras share width and height.
+ * Errors: NULL buffers, non-positive shininess, a zero light direction -> PCS_ERR_INVALID_ARG. */
+typedef struct {
+  float dir[3];      /* towards the light, world frame (normalised by the library) */
+  float color[3];
+  float ambient, diffuse, specular, shininess;
+} pcs_light;
+
+int pcs_shade(pcs_context* ctx, const pcs_images* in, const pcs_camera* cams, int32_t n_cams,
+              const pcs_light* light, const float bg[3], float* out_rgb, void* stream);
 
 /* ---- sparse point-to-ellipsoid estimator (Section 3.2) -------------------------------------
  * Voxels of a point cloud on a grid of G^3 voxels over [-1,1]^3 (G a power of two <= 1024; G = 1024

@@ -16,10 +16,11 @@ c_f, c_i32, c_i64, c_u32, c_vp = ctypes.c_float, ctypes.c_int32, ctypes.c_int64,
 PCS_OK, PCS_ERR_INVALID_ARG, PCS_ERR_HIP, PCS_ERR_OOM, PCS_ERR_CAPACITY, PCS_ERR_UNSUPPORTED = range(6)
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "HIP_ERROR", 3: "OUT_OF_MEMORY", 4: "CAPACITY", 5: "UNSUPPORTED"}
 STAGES = ("project", "scan", "binning", "sort", "ranges", "composite", "backward_composite",
-          "backward_project", "knn_pca", "voxelize", "conv", "conv_backward", "head", "head_backward")
+          "backward_project", "knn_pca", "voxelize", "conv", "conv_backward", "head", "head_backward",
+          "shade")
 
 EXPORTED = ("pcs_last_error", "pcs_context_create", "pcs_context_destroy", "pcs_context_timing",
-            "pcs_context_timing_stages",
+            "pcs_context_timing_stages", "pcs_shade",
             "pcs_context_timings", "pcs_state_create", "pcs_state_destroy", "pcs_options_default",
             "pcs_render_forward", "pcs_render_backward", "pcs_state_bins", "pcs_knn_pca",
             "pcs_voxels_create", "pcs_voxels_destroy", "pcs_voxelize", "pcs_voxels_get",
@@ -44,6 +45,11 @@ class Options(ctypes.Structure):
 
 class Images(ctypes.Structure):
     _fields_ = [("rgb", c_vp), ("normal", c_vp), ("depth", c_vp), ("alpha", c_vp)]
+
+
+class Light(ctypes.Structure):
+    _fields_ = [("dir", c_f * 3), ("color", c_f * 3), ("ambient", c_f), ("diffuse", c_f),
+                ("specular", c_f), ("shininess", c_f)]
 
 
 class Grads(ctypes.Structure):
@@ -93,7 +99,9 @@ def load():
                                  ctypes.POINTER(c_vp), ctypes.POINTER(c_i64), ctypes.POINTER(c_vp),
                                  ctypes.POINTER(c_vp)]
     L.pcs_knn_pca.argtypes = [c_vp, c_vp, c_i64, c_i32, c_f, c_f, c_vp, c_vp, c_vp, c_vp, c_vp]
-    for name in ("pcs_context_create", "pcs_context_timing", "pcs_context_timing_stages",
+    L.pcs_shade.argtypes = [c_vp, ctypes.POINTER(Images), ctypes.POINTER(Camera), c_i32,
+                            ctypes.POINTER(Light), ctypes.POINTER(c_f * 3), c_vp, c_vp]
+    for name in ("pcs_context_create", "pcs_context_timing", "pcs_context_timing_stages", "pcs_shade",
                  "pcs_context_timings", "pcs_state_create",
                  "pcs_render_forward", "pcs_render_backward", "pcs_state_bins", "pcs_knn_pca",
             "pcs_voxels_create", "pcs_voxels_destroy", "pcs_voxelize", "pcs_voxels_get",

@@ -72,7 +72,7 @@ int ensure(DevBuf& b, size_t bytes, const char* what) {
 
 enum Stage {
   ST_PROJECT = 0, ST_SCAN, ST_BINNING, ST_SORT, ST_RANGES, ST_COMPOSITE, ST_BWD_COMPOSITE,
-  ST_BWD_PROJECT, ST_KNN, ST_VOXELIZE, ST_CONV, ST_CONV_BWD, ST_HEAD, ST_HEAD_BWD, ST_COUNT
+  ST_BWD_PROJECT, ST_KNN, ST_VOXELIZE, ST_CONV, ST_CONV_BWD, ST_HEAD, ST_HEAD_BWD, ST_SHADE, ST_COUNT
 };
 
 int bit_length(uint64_t v) {
@@ -96,7 +96,7 @@ struct pcs_context {
   int device = 0;
   DevBuf counts, offsets, meta, keys_alt, vals_alt, scan_scratch, sort_scratch, sgrad, small;
   DevBuf dkeys, dkeys_alt, dvals, dvals_alt, dsort_scratch;   // depth sort of the splats
-  DevBuf knn_scratch, conv_tmp, wt_tmp;
+  DevBuf knn_scratch, conv_tmp, wt_tmp, shade_cams;
   uint32_t* host_small = nullptr;   // pinned 4 KiB: readback of the small device words
   hipEvent_t counts_ready = nullptr;  // recorded after the instance-count read-back
   pcs_state* internal = nullptr;    // state used when the caller passes none
@@ -528,6 +528,42 @@ int pcs_knn_pca(pcs_context* ctx, const float* xyz, int64_t n, int32_t k, float 
   StageTimer tm(ctx, ST_KNN, s);
   PCS_HIP(launch_knn_pca(xyz, n, k, kappa, floor_ratio, quat, scale, normal, nn_dist, ctx->knn_scratch.p,
                          ctx->knn_scratch.cap, ctx->host_small + 192, s));
+  return PCS_OK;
+}
+
+int pcs_shade(pcs_context* ctx, const pcs_images* in, const pcs_camera* cams, int32_t n_cams,
+              const pcs_light* light, const float bg[3], float* out_rgb, void* stream) {
+  if (!ctx || !in || !cams || !light || !out_rgb) return fail(PCS_ERR_INVALID_ARG, "NULL argument");
+  if (!in->rgb || !in->normal || !in->alpha) return fail(PCS_ERR_INVALID_ARG, "shading needs rgb, normal and alpha");
+  if (n_cams <= 0) return fail(PCS_ERR_INVALID_ARG, "need at least one camera");
+  const int W = cams[0].width, H = cams[0].height;
+  if (W <= 0 || H <= 0) return fail(PCS_ERR_INVALID_ARG, "image width and height must be positive");
+  for (int c = 0; c < n_cams; ++c) {
+    if (cams[c].width != W || cams[c].height != H)
+      return fail(PCS_ERR_INVALID_ARG, "all cameras of one call must share width and height");
+    if (!finite_camera(cams[c])) return fail(PCS_ERR_INVALID_ARG, "camera has non-finite or zero focal values");
+  }
+  const float dl = std::sqrt(light->dir[0] * light->dir[0] + light->dir[1] * light->dir[1] +
+                             light->dir[2] * light->dir[2]);
+  if (!(dl > 0.0f) || !std::isfinite(dl)) return fail(PCS_ERR_INVALID_ARG, "light direction must be non-zero");
+  if (!(light->shininess > 0.0f)) return fail(PCS_ERR_INVALID_ARG, "shininess must be positive");
+  DevLight L{};
+  for (int k = 0; k < 3; ++k) {
+    L.dir[k] = light->dir[k] / dl;
+    L.color[k] = light->color[k];
+    L.bg[k] = bg ? bg[k] : 0.0f;
+  }
+  L.ambient = light->ambient; L.diffuse = light->diffuse; L.specular = light->specular;
+  L.shininess = light->shininess;
+  PCS_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  std::vector<DevCamera> dc(n_cams);
+  for (int c = 0; c < n_cams; ++c) dc[c] = to_dev(cams[c]);
+  PCS_TRY(ensure(ctx->shade_cams, sizeof(DevCamera) * n_cams, "cameras"));
+  PCS_HIP(hipMemcpyAsync(ctx->shade_cams.p, dc.data(), sizeof(DevCamera) * n_cams, hipMemcpyHostToDevice, s));
+  StageTimer tm(ctx, ST_SHADE, s);
+  PCS_HIP(launch_shade(W, H, n_cams, ctx->shade_cams.as<DevCamera>(), in->rgb, in->normal, in->alpha, L,
+                       out_rgb, s));
   return PCS_OK;
 }
 

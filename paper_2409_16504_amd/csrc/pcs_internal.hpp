@@ -116,6 +116,14 @@ __device__ __forceinline__ void clear_spans(const ClearSpans& c, int64_t gid, in
     for (int64_t i = gid; i < c.count[k]; i += gsize) c.p[k][i] = 0u;
 }
 
+// Late-shading parameters on the device: unit direction towards the light, light colour,
+// Blinn-Phong coefficients, background colour.
+struct DevLight {
+  float dir[3], color[3];
+  float ambient, diffuse, specular, shininess;
+  float bg[3];
+};
+
 // ---- launchers (stream-ordered, return the launch error) ------------------------------------
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, float value, int64_t n, hipStream_t s);
@@ -237,5 +245,10 @@ hipError_t launch_head_backward(const uint16_t* feat, const float* wh, const flo
                                 float voxel, const float* d_quat, const float* d_scale,
                                 const float* d_opac, const float* d_rgb, uint16_t* d_feat, float* d_wh,
                                 float* d_bh, hipStream_t s);
+
+// Late shading of rendered frames: out[C][3][H][W] from rgb/normal [C][3][H][W], alpha [C][H][W].
+hipError_t launch_shade(int W, int H, int n_cams, const DevCamera* cams, const float* rgb,
+                        const float* nrm, const float* alpha, const DevLight& L, float* out,
+                        hipStream_t s);
 
 }  // namespace pcs

@@ -13,7 +13,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import Camera, Gaussians, Grads, Images, Options, check
+from ._lib import Camera, Gaussians, Grads, Images, Light, Options, check
 
 GAUSS_SHAPES = dict(mean=3, quat=4, scale=3, opacity=None, rgb=3, normal=3)
 
@@ -193,6 +193,32 @@ class Renderer:
             check(_lib.load().pcs_knn_pca(self.ctx, _ptr(xyz), n, int(k), float(kappa), float(floor),
                                           _ptr(out["quat"]), _ptr(out["scale"]), _ptr(out["normal"]),
                                           _ptr(out["nn_dist"]) if nn_dist else None, _stream()))
+        return out
+
+    # -- late shading ---------------------------------------------------------------------------
+    def shade(self, images: dict, cams: list, light: dict, bg=(0.0, 0.0, 0.0), out: torch.Tensor | None = None):
+        """Blinn-Phong late shading of rendered frames (rgb, normal (C,3,H,W), alpha (C,H,W)) with
+        one directional light: dir (towards the light), color, ambient, diffuse, specular,
+        shininess. Returns the shaded rgb (C,3,H,W); ``out`` may be images["rgb"]."""
+        for k in ("rgb", "normal", "alpha"):
+            t = images[k]
+            if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"{k} must be a contiguous float32 CUDA tensor")
+        cams_c = (Camera * len(cams))(*[camera_struct(c) for c in cams])
+        C, W, H = len(cams), cams_c[0].width, cams_c[0].height
+        if images["rgb"].shape != (C, 3, H, W) or images["normal"].shape != (C, 3, H, W) or \
+                images["alpha"].shape != (C, H, W):
+            raise ValueError("image shapes do not match the cameras")
+        if out is None:
+            out = torch.empty_like(images["rgb"])
+        imgs = Images(_ptr(images["rgb"]), _ptr(images["normal"]), None, _ptr(images["alpha"]))
+        lt = Light((ctypes.c_float * 3)(*light["dir"]), (ctypes.c_float * 3)(*light.get("color", (1.0, 1.0, 1.0))),
+                   float(light.get("ambient", 0.1)), float(light.get("diffuse", 0.7)),
+                   float(light.get("specular", 0.2)), float(light.get("shininess", 16.0)))
+        bgc = (ctypes.c_float * 3)(*bg)
+        with torch.cuda.device(self.device):
+            check(_lib.load().pcs_shade(self.ctx, ctypes.byref(imgs), cams_c, C, ctypes.byref(lt), ctypes.byref(bgc),
+                                        _ptr(out), _stream()))
         return out
 
     # -- timing -------------------------------------------------------------------------------
