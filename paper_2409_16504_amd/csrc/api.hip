@@ -96,7 +96,7 @@ struct pcs_context {
   int device = 0;
   DevBuf counts, offsets, meta, keys_alt, vals_alt, scan_scratch, sort_scratch, sgrad, small;
   DevBuf dkeys, dkeys_alt, dvals, dvals_alt, dsort_scratch;   // depth sort of the splats
-  DevBuf knn_scratch, conv_tmp, wt_tmp, shade_cams;
+  DevBuf knn_scratch, conv_tmp, wt_tmp, shade_cams, tile_hist;
   uint32_t* host_small = nullptr;   // pinned 4 KiB: readback of the small device words
   hipEvent_t counts_ready = nullptr;  // recorded after the instance-count read-back
   pcs_state* internal = nullptr;    // state used when the caller passes none
@@ -356,6 +356,7 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   PCS_TRY(ensure(ctx->dvals, cn1 * sizeof(uint32_t), "depth order"));
   PCS_TRY(ensure(ctx->dvals_alt, cn1 * sizeof(uint32_t), "depth order (alternate)"));
   PCS_TRY(ensure(ctx->dsort_scratch, sort_scratch_bytes(cn), "depth sort scratch"));
+  PCS_TRY(ensure(ctx->tile_hist, kTileHistWords * sizeof(uint32_t), "tile digit histograms"));
   PCS_HIP(launch_init_small(ctx->small.as<uint32_t>(), s));
   {
     // the projection also clears what the depth sort and the scan need zeroed
@@ -364,6 +365,8 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
     clear.count[0] = sort_clear_words(cn);
     clear.p[1] = ctx->scan_scratch.as<uint32_t>();
     clear.count[1] = scan_clear_words(cn);
+    clear.p[2] = ctx->tile_hist.as<uint32_t>();            // binning counts the tile digits here
+    clear.count[2] = kTileHistWords;
     StageTimer tm(ctx, ST_PROJECT, s);
     PCS_HIP(launch_project(n, n_cams, st->dcams.as<DevCamera>(), dopt, *g, st->rec.as<float4>(),
                            ctx->meta.as<uint4>(), ctx->counts.as<uint32_t>(), d_zrange, d_counts, clear, s));
@@ -419,14 +422,15 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
       PCS_HIP(launch_binning(n, n_cams, TX, tiles_per_cam, ctx->dvals.as<uint32_t>(),
                              ctx->dvals_alt.as<uint32_t>(), d_depth, ctx->meta.as<uint4>(),
                              ctx->counts.as<uint32_t>(), ctx->offsets.as<uint32_t>(),
-                             st->keys.as<uint32_t>(), st->vals.as<uint32_t>(), clear, s));
+                             st->keys.as<uint32_t>(), st->vals.as<uint32_t>(), tile_bits,
+                             ctx->tile_hist.as<uint32_t>(), clear, s));
     }
     bool in_alt = false;
     {
       StageTimer tm(ctx, ST_SORT, s);
       PCS_HIP(launch_sort(st->keys.as<uint32_t>(), st->vals.as<uint32_t>(), ctx->keys_alt.as<uint32_t>(),
                           ctx->vals_alt.as<uint32_t>(), m, tile_bits, ctx->sort_scratch.p, s, &in_alt,
-                          nullptr, true));
+                          nullptr, true, false, ctx->tile_hist.as<uint32_t>()));
     }
     if (in_alt) {
       swap_buf(st->keys, ctx->keys_alt);

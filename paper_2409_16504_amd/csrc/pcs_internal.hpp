@@ -162,10 +162,19 @@ hipError_t launch_depth_keys_hist(int64_t m, const uint4* meta, const uint32_t* 
 
 // Tile keys of every visible splat, written in the depth order at `offsets`; the order is order1
 // when *passes is odd (where the depth sort ended), else order0.
+// Tile-digit histograms counted by binning: kTileHistCopies partial copies of
+// [kTileHistPasses][256] counters, summed by the tile sort.
+constexpr int kTileHistCopies = 32;
+constexpr int kTileHistPasses = 4;
+constexpr int64_t kTileHistWords = (int64_t)kTileHistCopies * kTileHistPasses * 256;
+
+// Also counts the tile keys' 8-bit digits into hist (kTileHistWords, zeroed beforehand), the
+// histogram input of the tile sort (launch_sort with ext_hist).
 hipError_t launch_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_cam, const uint32_t* order0,
                           const uint32_t* order1, const uint32_t* passes, const uint4* meta,
                           const uint32_t* counts, const uint32_t* offsets, uint32_t* keys,
-                          uint32_t* vals, const ClearSpans& clear, hipStream_t s);
+                          uint32_t* vals, int tile_bits, uint32_t* hist, const ClearSpans& clear,
+                          hipStream_t s);
 
 // Stable LSD radix sort of (key, value) pairs over key bits [0, bits), K = uint32_t or uint64_t.
 // Ping-pongs between (k0,v0) and (k1,v1); returns in *result_in_alt whether the sorted data ended
@@ -176,7 +185,8 @@ size_t sort_scratch_bytes(int64_t m);
 template <typename K>
 hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int bits, void* scratch,
                        hipStream_t s, bool* result_in_alt, const uint32_t* live_passes = nullptr,
-                       bool scratch_cleared = false, bool hist_ready = false);
+                       bool scratch_cleared = false, bool hist_ready = false,
+                       const uint32_t* ext_hist = nullptr);
 // Words at the start of sort scratch that must be zero before a sort of m pairs (cleared by the
 // sort itself unless the caller has cleared them and says so).
 int64_t sort_clear_words(int64_t m);

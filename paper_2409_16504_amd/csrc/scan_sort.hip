@@ -39,6 +39,7 @@ constexpr uint64_t kScanAgg = 1ull << 62;
 constexpr uint64_t kScanPrefix = 2ull << 62;
 constexpr uint64_t kScanValue = (1ull << 62) - 1;
 constexpr uint32_t kSpinLimit = 1u << 22;
+constexpr int kBins = 256;
 
 __device__ __forceinline__ uint64_t atomic_load_u64(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -146,8 +147,10 @@ __global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* __restrict__ 
 // ---- depth keys and binning ----------------------------------------------------------------
 // One key per (camera, Gaussian); culled splats get all bits set (they have no tile instances,
 // so where they land in the order does not matter).
-// Thread per position of the depth order: the splat there writes its tile keys (global tile id)
-// and Gaussian index at its offset in that order.
+// Positions of the depth order, grid-stride: the splat at each writes its tile keys (global tile
+// id) and Gaussian index at its offset in that order, and counts the keys' digits (n_digits 8-bit
+// digits) into the block's LDS histograms, added once per block to hist (zeroed beforehand,
+// [kTileHistCopies][kTileHistPasses][256]) for the tile sort.
 __global__ __launch_bounds__(256) void k_binning(int64_t total, uint32_t n, int TX,
                                                  uint32_t tiles_per_cam,
                                                  const uint32_t* __restrict__ order0,
@@ -157,30 +160,58 @@ __global__ __launch_bounds__(256) void k_binning(int64_t total, uint32_t n, int 
                                                  const uint32_t* __restrict__ counts,
                                                  const uint32_t* __restrict__ offsets,
                                                  uint32_t* __restrict__ keys,
-                                                 uint32_t* __restrict__ vals, ClearSpans clear) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  clear_spans(clear, j, (int64_t)gridDim.x * blockDim.x);
-  if (j >= total) return;
+                                                 uint32_t* __restrict__ vals, int n_digits,
+                                                 uint32_t* __restrict__ hist, ClearSpans clear) {
+  __shared__ uint32_t sh[kTileHistPasses][kBins];
+  const int tid = threadIdx.x;
+  for (int d = 0; d < kTileHistPasses; ++d) sh[d][tid] = 0u;
+  const int64_t gsize = (int64_t)gridDim.x * blockDim.x;
+  clear_spans(clear, (int64_t)blockIdx.x * blockDim.x + tid, gsize);
+  __syncthreads();
   const uint32_t* order = (*passes & 1u) ? order1 : order0;   // where the depth sort ended
-  const uint32_t i = order[j];
-  const uint32_t cnt = counts[i];
-  if (cnt == 0) return;
-  const uint32_t cam = i / n;
-  const uint32_t g = i - cam * n;
-  const uint4 m = meta[i];
-  const int x0 = m.y & 0xFFFF, x1 = m.y >> 16, y0 = m.z & 0xFFFF, y1 = m.z >> 16;
-  uint32_t off = offsets[j];
-  const uint32_t cam_base = cam * tiles_per_cam;
-  for (int ty = y0; ty <= y1; ++ty)
-    for (int tx = x0; tx <= x1; ++tx) {
-      keys[off] = cam_base + (uint32_t)(ty * TX + tx);
-      vals[off] = g;
-      ++off;
+  // kBinItems positions per thread and step, all of their loads issued before any key is written
+  // (indices clamped so that the loads need no branch)
+  constexpr int kBinItems = 4;
+  for (int64_t j0 = (int64_t)blockIdx.x * blockDim.x + tid; j0 < total; j0 += kBinItems * gsize) {
+    uint32_t idx[kBinItems], cnt[kBinItems], off[kBinItems];
+    uint4 m[kBinItems];
+#pragma unroll
+    for (int k = 0; k < kBinItems; ++k) idx[k] = order[std::min<int64_t>(j0 + k * gsize, total - 1)];
+#pragma unroll
+    for (int k = 0; k < kBinItems; ++k) {
+      cnt[k] = counts[idx[k]];
+      m[k] = meta[idx[k]];
+      off[k] = offsets[std::min<int64_t>(j0 + k * gsize, total - 1)];
     }
+#pragma unroll
+    for (int k = 0; k < kBinItems; ++k) {
+      if (j0 + k * gsize >= total || cnt[k] == 0) continue;
+      const uint32_t cam = idx[k] / n;
+      const uint32_t g = idx[k] - cam * n;
+      const int x0 = m[k].y & 0xFFFF, x1 = m[k].y >> 16, y0 = m[k].z & 0xFFFF, y1 = m[k].z >> 16;
+      uint32_t o = off[k];
+      const uint32_t cam_base = cam * tiles_per_cam;
+      for (int ty = y0; ty <= y1; ++ty)
+        for (int tx = x0; tx <= x1; ++tx) {
+          const uint32_t key = cam_base + (uint32_t)(ty * TX + tx);
+          keys[o] = key;
+          vals[o] = g;
+          ++o;
+          for (int d = 0; d < n_digits; ++d) atomicAdd(&sh[d][(key >> (8 * d)) & 0xFF], 1u);
+        }
+    }
+  }
+  __syncthreads();
+  // blocks spread their sums over kTileHistCopies copies (blocks of a copy share an XCD), which
+  // keeps each counter's chain of atomics short
+  uint32_t* h = hist + (blockIdx.x % kTileHistCopies) * (kTileHistPasses * kBins);
+  for (int d = 0; d < n_digits; ++d) {
+    const uint32_t v = sh[d][tid];
+    if (v) atomicAdd(&h[d * kBins + tid], v);
+  }
 }
 
 // ---- radix sort -----------------------------------------------------------------------------
-constexpr int kBins = 256;
 constexpr int kMaxPasses = 8;
 constexpr uint32_t kSortAgg = 1u << 30;
 constexpr uint32_t kSortPrefix = 2u << 30;
@@ -313,11 +344,12 @@ __global__ __launch_bounds__(256) void k_depth_keys_hist(int64_t m, const uint4*
 }
 
 // Exclusive scan over the 256 bins of each pass (one block per pass).
-__global__ __launch_bounds__(256) void k_digit_base(const uint32_t* __restrict__ hist,
-                                                    uint32_t* __restrict__ base) {
+__global__ __launch_bounds__(256) void k_digit_base(const uint32_t* __restrict__ hist, int copies,
+                                                    int64_t copy_stride, uint32_t* __restrict__ base) {
   __shared__ uint32_t s_wave[kWaves];
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-  const uint32_t v = hist[blockIdx.x * kBins + tid];
+  uint32_t v = 0;
+  for (int c = 0; c < copies; ++c) v += hist[c * copy_stride + blockIdx.x * kBins + tid];
   const uint32_t incl = wave_inclusive_scan(v);
   if (lane == kWave - 1) s_wave[wave] = incl;
   __syncthreads();
@@ -622,12 +654,16 @@ hipError_t launch_depth_keys_hist(int64_t m, const uint4* meta, const uint32_t* 
 hipError_t launch_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_cam, const uint32_t* order0,
                           const uint32_t* order1, const uint32_t* passes, const uint4* meta,
                           const uint32_t* counts, const uint32_t* offsets, uint32_t* keys,
-                          uint32_t* vals, const ClearSpans& clear, hipStream_t s) {
+                          uint32_t* vals, int tile_bits, uint32_t* hist, const ClearSpans& clear,
+                          hipStream_t s) {
   const int64_t total = n * n_cams;
   if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_binning, dim3(blocks_for(total, 256)), dim3(256), 0, s, total, (uint32_t)n, TX,
+  if (tile_bits > 8 * kTileHistPasses) return hipErrorInvalidValue;
+  // a bounded grid keeps the per-block histogram flushes few
+  const unsigned blocks = (unsigned)std::min<int64_t>(1024, blocks_for(total, 256));
+  hipLaunchKernelGGL(k_binning, dim3(blocks), dim3(256), 0, s, total, (uint32_t)n, TX,
                      (uint32_t)tiles_per_cam, order0, order1, passes, meta, counts, offsets, keys, vals,
-                     clear);
+                     (tile_bits + 7) / 8, hist, clear);
   return hipGetLastError();
 }
 
@@ -642,7 +678,7 @@ int64_t sort_clear_words(int64_t m) { return kMaxPasses * kBins + (m + kPart - 1
 template <typename K>
 hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int bits, void* scratch,
                        hipStream_t s, bool* result_in_alt, const uint32_t* live_passes,
-                       bool scratch_cleared, bool hist_ready) {
+                       bool scratch_cleared, bool hist_ready, const uint32_t* ext_hist) {
   *result_in_alt = false;
   if (m <= 1 || bits <= 0) return hipSuccess;
   const int n_passes = (bits + 7) / 8;
@@ -660,9 +696,14 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
   hipError_t e = scratch_cleared ? hipSuccess : launch_fill_u32(hist, 0u, kMaxPasses * kBins + parts * kBins, s);
   if (e != hipSuccess) return e;
   const int hblocks = (int)std::min<int64_t>(kHistBlocks, parts);
-  if (!hist_ready)
+  if (!hist_ready && !ext_hist)
     hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)hblocks), dim3(256), 0, s, k0, m, n_passes, hist);
-  hipLaunchKernelGGL(k_digit_base, dim3(n_passes), dim3(256), 0, s, hist, base);
+  if (ext_hist)
+    hipLaunchKernelGGL(k_digit_base, dim3(n_passes), dim3(256), 0, s, ext_hist, kTileHistCopies,
+                       (int64_t)kTileHistPasses * kBins, base);
+  else
+    hipLaunchKernelGGL(k_digit_base, dim3(n_passes), dim3(256), 0, s, (const uint32_t*)hist, 1,
+                       (int64_t)0, base);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   K *ki = k0, *ko = k1;
   uint32_t *vi = v0, *vo = v1;
@@ -679,9 +720,11 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
   return hipSuccess;
 }
 template hipError_t launch_sort<uint32_t>(uint32_t*, uint32_t*, uint32_t*, uint32_t*, int64_t, int,
-                                          void*, hipStream_t, bool*, const uint32_t*, bool, bool);
+                                          void*, hipStream_t, bool*, const uint32_t*, bool, bool,
+                                          const uint32_t*);
 template hipError_t launch_sort<uint64_t>(uint64_t*, uint32_t*, uint64_t*, uint32_t*, int64_t, int,
-                                          void*, hipStream_t, bool*, const uint32_t*, bool, bool);
+                                          void*, hipStream_t, bool*, const uint32_t*, bool, bool,
+                                          const uint32_t*);
 
 hipError_t launch_ranges(const uint32_t* keys, int64_t m, int64_t n_tiles, uint32_t* ranges,
                          hipStream_t s) {
