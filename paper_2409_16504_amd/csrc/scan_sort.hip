@@ -343,30 +343,15 @@ __global__ __launch_bounds__(256) void k_depth_keys_hist(int64_t m, const uint4*
   }
 }
 
-// Exclusive scan over the 256 bins of each pass (one block per pass).
-__global__ __launch_bounds__(256) void k_digit_base(const uint32_t* __restrict__ hist, int copies,
-                                                    int64_t copy_stride, uint32_t* __restrict__ base) {
-  __shared__ uint32_t s_wave[kWaves];
-  const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-  uint32_t v = 0;
-  for (int c = 0; c < copies; ++c) v += hist[c * copy_stride + blockIdx.x * kBins + tid];
-  const uint32_t incl = wave_inclusive_scan(v);
-  if (lane == kWave - 1) s_wave[wave] = incl;
-  __syncthreads();
-  uint32_t pre = 0;
-  for (int w = 0; w < wave; ++w) pre += s_wave[w];
-  base[blockIdx.x * kBins + tid] = pre + incl - v;
-}
-
 // One scatter pass over digit `shift`. THREADS threads take a partition of THREADS * ITEMS keys
 // (4096: 512 threads x 8 keys for 32-bit keys, so each wavefront ranks half as many keys in
 // sequence; 256 x 16 for 64-bit keys).
 template <typename K, int THREADS, int ITEMS>
 __global__ __launch_bounds__(THREADS) void k_onesweep(
     const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
-    uint32_t* __restrict__ vout, int64_t m, int shift, const uint32_t* __restrict__ digit_base,
-    uint32_t* __restrict__ status, uint32_t* __restrict__ status_next,
-    const uint32_t* __restrict__ live_passes, int pass) {
+    uint32_t* __restrict__ vout, int64_t m, int shift, const uint32_t* __restrict__ hist_row,
+    int copies, int64_t copy_stride, uint32_t* __restrict__ status,
+    uint32_t* __restrict__ status_next, const uint32_t* __restrict__ live_passes, int pass) {
   constexpr int W = THREADS / kWave;
   constexpr int PART = THREADS * ITEMS;
   constexpr int kItems = ITEMS;
@@ -375,6 +360,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   __shared__ uint32_t s_local[kBins];          // block-local start of each digit run
   __shared__ uint32_t s_global[kBins];         // global start of the run minus its local start
   __shared__ uint32_t s_wsum[kBins / kWave];
+  __shared__ uint32_t s_tsum[kBins / kWave];
   __shared__ K s_buf[PART];                    // keys, then (as u32) values, in digit order
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   for (int i = tid; i < W * kBins; i += THREADS) (&s_hist[0][0])[i] = 0u;
@@ -385,6 +371,12 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   uint32_t val[kItems];
   uint32_t rank[kItems];
   const uint64_t lt_mask = lanemask_lt();
+  // partition 0: the pass's digit totals, loaded first so that they arrive during the ranking
+  uint32_t tot = 0;
+  if (part == 0 && tid < kBins) {
+#pragma unroll 8
+    for (int c = 0; c < copies; ++c) tot += hist_row[c * copy_stride + tid];
+  }
   // every load issued before the first is used
 #pragma unroll
   for (int it = 0; it < kItems; ++it) {
@@ -432,11 +424,25 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
 #pragma unroll
     for (int w = 0; w < W; ++w) { cw[w] = s_hist[w][tid]; count += cw[w]; }
     // publish this partition's digit count as early as possible
-    if (part == 0) atomic_store_u32(&status[tid], kSortPrefix | count);
-    else atomic_store_u32(&status[part * kBins + tid], kSortAgg | count);
+    if (part > 0) atomic_store_u32(&status[part * kBins + tid], kSortAgg | count);
     // block-local exclusive scan of the digit counts
     incl = wave_inclusive_scan(count);
     if (lane == kWave - 1) s_wsum[wave] = incl;
+  }
+  // Partition 0 turns the pass's digit totals (the sum of `copies` partial histograms) into the
+  // digit bases and publishes base + count as its inclusive prefix, so every later partition's
+  // look-back already includes the base.
+  uint32_t excl = 0;
+  if (part == 0) {
+    const uint32_t tincl = digit_thread ? wave_inclusive_scan(tot) : 0u;
+    if (digit_thread && lane == kWave - 1) s_tsum[wave] = tincl;
+    __syncthreads();
+    if (digit_thread) {
+      uint32_t pre = 0;
+      for (int w = 0; w < wave; ++w) pre += s_tsum[w];
+      excl = pre + tincl - tot;
+      atomic_store_u32(&status[tid], kSortPrefix | (excl + count));
+    }
   }
   __syncthreads();
   if (digit_thread) {
@@ -447,7 +453,6 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
 #pragma unroll
     for (int w = 0; w < W; ++w) { s_hist[w][tid] = run; run += cw[w]; }
     // look back over earlier partitions for this digit, kLookWindow predecessors per step
-    uint32_t excl = 0;
     if (part > 0) {
       int64_t p = part - 1;
       uint32_t spins = 0;
@@ -481,7 +486,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     // clear this partition's slice of the other status buffer for the next pass
     status_next[part * kBins + tid] = 0u;
     s_local[tid] = local_start;
-    s_global[tid] = digit_base[tid] + excl - local_start;
+    s_global[tid] = excl - local_start;
   }
   __syncthreads();
   // keys to LDS in block-local digit order
@@ -670,7 +675,7 @@ hipError_t launch_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_cam, 
 
 size_t sort_scratch_bytes(int64_t m) {
   const int64_t parts = (m + kPart - 1) / kPart;
-  return (size_t)(2 * kMaxPasses * kBins + 2 * parts * kBins) * sizeof(uint32_t) + 256;
+  return (size_t)(kMaxPasses * kBins + 2 * parts * kBins) * sizeof(uint32_t) + 256;
 }
 
 int64_t sort_clear_words(int64_t m) { return kMaxPasses * kBins + (m + kPart - 1) / kPart * kBins; }
@@ -686,32 +691,29 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
   constexpr int kSweepThreads = sizeof(K) == 4 ? 512 : 256;
   constexpr int kSweepItems = kPart / kSweepThreads;
   const int64_t sweep_parts = parts;
-  // scratch: hist[8][256] | status0[parts][256] | base[8][256] | status1[parts][256]. One fill
-  // clears the histograms and status0; pass p reads status[p & 1] and clears its partitions'
-  // slice of the other buffer for pass p + 1.
+  // scratch: hist[8][256] | status0[parts][256] | status1[parts][256]. One fill clears the
+  // histograms and status0; pass p reads status[p & 1] and clears its partitions' slice of the
+  // other buffer for pass p + 1.
   uint32_t* hist = reinterpret_cast<uint32_t*>(scratch);
   uint32_t* status0 = hist + kMaxPasses * kBins;
-  uint32_t* base = status0 + parts * kBins;
-  uint32_t* status1 = base + kMaxPasses * kBins;
+  uint32_t* status1 = status0 + parts * kBins;
   hipError_t e = scratch_cleared ? hipSuccess : launch_fill_u32(hist, 0u, kMaxPasses * kBins + parts * kBins, s);
   if (e != hipSuccess) return e;
   const int hblocks = (int)std::min<int64_t>(kHistBlocks, parts);
-  if (!hist_ready && !ext_hist)
+  if (!hist_ready && !ext_hist) {
     hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)hblocks), dim3(256), 0, s, k0, m, n_passes, hist);
-  if (ext_hist)
-    hipLaunchKernelGGL(k_digit_base, dim3(n_passes), dim3(256), 0, s, ext_hist, kTileHistCopies,
-                       (int64_t)kTileHistPasses * kBins, base);
-  else
-    hipLaunchKernelGGL(k_digit_base, dim3(n_passes), dim3(256), 0, s, (const uint32_t*)hist, 1,
-                       (int64_t)0, base);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  const uint32_t* rows = ext_hist ? ext_hist : hist;
+  const int copies = ext_hist ? kTileHistCopies : 1;
+  const int64_t copy_stride = ext_hist ? (int64_t)kTileHistPasses * kBins : 0;
   K *ki = k0, *ko = k1;
   uint32_t *vi = v0, *vo = v1;
   for (int p = 0; p < n_passes; ++p) {
     uint32_t* st = (p & 1) ? status1 : status0;
     uint32_t* st_next = (p & 1) ? status0 : status1;
     hipLaunchKernelGGL((k_onesweep<K, kSweepThreads, kSweepItems>), dim3((unsigned)sweep_parts), dim3(kSweepThreads), 0, s, ki, vi, ko, vo, m,
-                       8 * p, base + p * kBins, st, st_next, live_passes, p);
+                       8 * p, rows + p * kBins, copies, copy_stride, st, st_next, live_passes, p);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     std::swap(ki, ko);
     std::swap(vi, vo);
