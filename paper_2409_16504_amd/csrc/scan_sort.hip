@@ -673,12 +673,25 @@ hipError_t launch_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_cam, 
 }
 
 
+// Scatter partitions of 4096 keys: 32-bit keys 512 threads x 8, 64-bit keys 256 x 16. Scratch is
+// sized (and cleared) for kSortPartMin-key partitions.
+constexpr int kSortPartMin = 4096;
+template <typename K> struct SweepShape {
+  static constexpr int threads = sizeof(K) == 4 ? 512 : 256;
+  static constexpr int items = sizeof(K) == 4 ? 8 : 16;
+  static constexpr int part = threads * items;
+};
+static_assert(SweepShape<uint32_t>::part >= kSortPartMin && SweepShape<uint64_t>::part >= kSortPartMin,
+              "scratch sizing assumes partitions of at least kSortPartMin keys");
+
 size_t sort_scratch_bytes(int64_t m) {
-  const int64_t parts = (m + kPart - 1) / kPart;
+  const int64_t parts = (m + kSortPartMin - 1) / kSortPartMin;
   return (size_t)(kMaxPasses * kBins + 2 * parts * kBins) * sizeof(uint32_t) + 256;
 }
 
-int64_t sort_clear_words(int64_t m) { return kMaxPasses * kBins + (m + kPart - 1) / kPart * kBins; }
+int64_t sort_clear_words(int64_t m) {
+  return kMaxPasses * kBins + (m + kSortPartMin - 1) / kSortPartMin * kBins;
+}
 
 template <typename K>
 hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int bits, void* scratch,
@@ -687,17 +700,17 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
   *result_in_alt = false;
   if (m <= 1 || bits <= 0) return hipSuccess;
   const int n_passes = (bits + 7) / 8;
-  const int64_t parts = (m + kPart - 1) / kPart;    // partitions of the histogram (and the bound)
-  constexpr int kSweepThreads = sizeof(K) == 4 ? 512 : 256;
-  constexpr int kSweepItems = kPart / kSweepThreads;
-  const int64_t sweep_parts = parts;
+  const int64_t parts = (m + kPart - 1) / kPart;    // partitions of the histogram
+  constexpr int kSweepThreads = SweepShape<K>::threads;
+  constexpr int kSweepItems = SweepShape<K>::items;
+  const int64_t sweep_parts = (m + SweepShape<K>::part - 1) / SweepShape<K>::part;
   // scratch: hist[8][256] | status0[parts][256] | status1[parts][256]. One fill clears the
   // histograms and status0; pass p reads status[p & 1] and clears its partitions' slice of the
   // other buffer for pass p + 1.
   uint32_t* hist = reinterpret_cast<uint32_t*>(scratch);
   uint32_t* status0 = hist + kMaxPasses * kBins;
-  uint32_t* status1 = status0 + parts * kBins;
-  hipError_t e = scratch_cleared ? hipSuccess : launch_fill_u32(hist, 0u, kMaxPasses * kBins + parts * kBins, s);
+  uint32_t* status1 = status0 + sweep_parts * kBins;
+  hipError_t e = scratch_cleared ? hipSuccess : launch_fill_u32(hist, 0u, kMaxPasses * kBins + sweep_parts * kBins, s);
   if (e != hipSuccess) return e;
   const int hblocks = (int)std::min<int64_t>(kHistBlocks, parts);
   if (!hist_ready && !ext_hist) {
