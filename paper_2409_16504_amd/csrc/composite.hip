@@ -82,6 +82,24 @@ __device__ __forceinline__ bool touches_rect(float u, float v, float ex, float e
   return gx <= ex && gy <= ey;
 }
 
+// Blend-order form of a record, written by the lane that keeps it:
+//   f0 = (u, v, k A, 2 k B)   f1 = (k C, log2 o, thr, z)   f2 = (r, g, b, list position + 1)
+//   f3 = (nx, ny, nz, 0)
+// with k = -log2(e) / 2, so that s = k q comes out of the quadratic form directly and
+// alpha = o e^(-q/2) = 2^(s + log2 o). thr = max(k sigma_cut^2, log2 alpha_min - log2 o): s >= thr
+// is the 3-sigma test (q <= sigma_cut^2) and the alpha cut-off together (alpha_max >= alpha_min).
+// For o = 0 the difference is NaN or +inf and fmaxf leaves the 3-sigma test or never, as the
+// sequential test would (a zero-alpha blend counts only when alpha_min = 0).
+__device__ __forceinline__ void blend_form(const float4& r0, const float4& r1, const float4& r2,
+                                           const float4& r3, int32_t pos, float k_cut2, float l2amin,
+                                           float4& f0, float4& f1, float4& f2, float4& f3) {
+  const float l2o = __log2f(r0.z);
+  f0 = make_float4(r0.x, r0.y, kNegHalfLog2e * r1.x, (2.0f * kNegHalfLog2e) * r1.y);
+  f1 = make_float4(kNegHalfLog2e * r1.z, l2o, fmaxf(k_cut2, l2amin - l2o), r0.w);
+  f2 = make_float4(r2.x, r2.y, r2.z, __int_as_float(pos));
+  f3 = make_float4(r3.x, r3.y, r3.z, 0.0f);
+}
+
 __global__ __launch_bounds__(kWave) void k_composite(
     int64_t n, int W, int H, int TX, int64_t tiles_per_cam, int64_t total_tiles,
     const float4* __restrict__ rec, const uint32_t* __restrict__ vals,
@@ -89,9 +107,9 @@ __global__ __launch_bounds__(kWave) void k_composite(
     float* __restrict__ out_rgb,
     float* __restrict__ out_nrm, float* __restrict__ out_depth, float* __restrict__ out_alpha,
     float* __restrict__ t_final, int32_t* __restrict__ n_contrib) {
-  // compacted records of a batch, plus kGroup slots past the last one whose conic is NaN
-  __shared__ float4 s_r0[kWave + kGroup], s_r1[kWave + kGroup], s_r2[kWave + kGroup], s_r3[kWave + kGroup];
-  __shared__ int32_t s_pos[kWave + kGroup];     // list position + 1
+  // blend forms of a batch's kept records, plus kGroup slots past the last one whose threshold
+  // is NaN
+  __shared__ float4 s_f0[kWave + kGroup], s_f1[kWave + kGroup], s_f2[kWave + kGroup], s_f3[kWave + kGroup];
   int64_t opos;
   int quad;
   if (!quadrant_of_block(blockIdx.x, total_tiles, opos, quad)) return;
@@ -104,13 +122,18 @@ __global__ __launch_bounds__(kWave) void k_composite(
   const bool inside = P.x < W && P.y < H;
   const float pxf = (float)P.x + 0.5f, pyf = (float)P.y + 0.5f;
   const uint32_t start = ranges[tile], end = ranges[total_tiles + tile];
-  const float cut2 = opt.sigma_cut * opt.sigma_cut;
+  const float k_cut2 = kNegHalfLog2e * (opt.sigma_cut * opt.sigma_cut);
+  const float amax = fmaxf(opt.alpha_max, opt.alpha_max);    // canonical once, not per use
+  // alpha_max below alpha_min: no alpha passes the cut-off
+  const float l2amin = opt.alpha_max < opt.alpha_min ? __builtin_inff() : __log2f(opt.alpha_min);
   const float4* rec_cam = rec + cam * n * kRecFloat4;
   const uint64_t lt = lanemask_lt();
-  float T = 1.0f;
+  // T and the sums run until the pixel's stop; a stopped pixel keeps its T and last contributor
+  // in t_stop / last_stop and continues with T = 0, which leaves the sums as they are
+  float T = 1.0f, t_stop = 0.0f;
   float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f, acc4 = 0.f, acc5 = 0.f, acc6 = 0.f;
-  int32_t last = 0;
-  bool done = !inside;
+  int32_t last = 0, last_stop = 0;
+  uint64_t done = __ballot(!inside);                 // stopped pixels (wave-uniform)
   // one record per lane; the next batch's records and the batch after's splat indices travel in
   // registers while the current batch is composited, so each batch waits on one round trip. The
   // loads are unconditional (positions past the list re-read its last entry; the position test
@@ -119,10 +142,8 @@ __global__ __launch_bounds__(kWave) void k_composite(
   // weight, leaves the sums exact
   {
     const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    s_r0[lane] = z4; s_r2[lane] = z4; s_r3[lane] = z4; s_pos[lane] = 0;
-    if (lane < kGroup) {
-      s_r0[kWave + lane] = z4; s_r2[kWave + lane] = z4; s_r3[kWave + lane] = z4; s_pos[kWave + lane] = 0;
-    }
+    s_f0[lane] = z4; s_f2[lane] = z4; s_f3[lane] = z4;
+    if (lane < kGroup) { s_f0[kWave + lane] = z4; s_f2[kWave + lane] = z4; s_f3[kWave + lane] = z4; }
   }
   const uint32_t lastpos = end > start ? end - 1 : start;
   float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0, p2 = p0, p3 = p0;
@@ -133,22 +154,23 @@ __global__ __launch_bounds__(kWave) void k_composite(
     vnext = vals[min(start + kWave + lane, lastpos)];
   }
   for (uint32_t b = start; b < end; b += kWave) {
-    const uint64_t live = __ballot(!done);
+    const uint64_t live = ~done;
     if (live == 0ull) break;                          // every pixel of the quadrant is done
     // keep the records whose padded ellipse box reaches a pixel that is still blending, compacted
-    // in list order; the live pixels' bounding rectangle comes from the ballot (lane = 8 y + x):
+    // in list order; the live pixels' bounding rectangle comes from the stop mask (lane = 8 y + x):
     // rows are its non-zero bytes, columns the OR of its bytes
     const ActiveRect ar = active_rect(live, P.qx0, P.qy0);
     const bool rel = b + lane < end && touches_rect(p0.x, p0.y, p1.w, p2.w, ar);
     const uint64_t relmask = __ballot(rel);
     if (rel) {
       const int slot = __popcll(relmask & lt);
-      s_r0[slot] = p0; s_r1[slot] = p1; s_r2[slot] = p2; s_r3[slot] = p3;
-      s_pos[slot] = (int32_t)(b - start) + lane + 1;
+      float4 f0, f1, f2, f3;
+      blend_form(p0, p1, p2, p3, (int32_t)(b - start) + lane + 1, k_cut2, l2amin, f0, f1, f2, f3);
+      s_f0[slot] = f0; s_f1[slot] = f1; s_f2[slot] = f2; s_f3[slot] = f3;
     }
-    // the kGroup slots after the last kept record can never blend (NaN conic: q <= cut fails);
-    // their other fields are finite (earlier records or the initial zeros)
-    if (lane < kGroup) s_r1[__popcll(relmask) + lane] = make_float4(__int_as_float(0x7fc00000), 0.f, 0.f, 0.f);
+    // the kGroup slots after the last kept record can never blend (NaN threshold: s >= thr
+    // fails); their other fields are finite (earlier records or the initial zeros)
+    if (lane < kGroup) s_f1[__popcll(relmask) + lane] = make_float4(0.f, 0.f, __int_as_float(0x7fc00000), 0.f);
     {
       const float4* r = rec_cam + (int64_t)min(vnext, (uint32_t)(n - 1)) * kRecFloat4;
       p0 = r[0]; p1 = r[1]; p2 = r[2]; p3 = r[3];
@@ -157,31 +179,30 @@ __global__ __launch_bounds__(kWave) void k_composite(
     __syncthreads();                                  // one wavefront: orders the LDS writes
     const int nrel = __popcll(relmask);
     for (int k0 = 0; k0 < nrel; k0 += kGroup) {
-      // everything the group's blends need first: records, quadratic forms and alphas are
-      // independent of T, so the in-order blends below run from registers
-      float aa[kGroup], zz[kGroup];
+      // the group's alphas first: they do not depend on T, so the in-order blends below run
+      // from registers
+      float aa[kGroup];
       float4 c2[kGroup], c3[kGroup];
-      int32_t pp[kGroup];
+      float zz[kGroup];
 #pragma unroll
       for (int j = 0; j < kGroup; ++j) {
         const int k = k0 + j;
-        const float4 r0 = s_r0[k];
-        const float4 r1 = s_r1[k];
-        c2[j] = s_r2[k];
-        c3[j] = s_r3[k];
-        pp[j] = s_pos[k];
-        const float q = conic_q(r1.x, r1.y, r1.z, pxf - r0.x, pyf - r0.y);
-        // o * e^(-q/2) as o * 2^(q * (-log2(e) / 2)), one hardware exp2
-        const float a = fminf(opt.alpha_max, r0.z * __builtin_amdgcn_exp2f(q * kNegHalfLog2e));
-        aa[j] = (q <= cut2 && !(a < opt.alpha_min)) ? a : -1.0f;  // negative: no blend
-        zz[j] = r0.w;
+        const float4 f0 = s_f0[k];
+        const float4 f1 = s_f1[k];
+        c2[j] = s_f2[k];
+        c3[j] = s_f3[k];
+        zz[j] = f1.w;
+        const float dx = pxf - f0.x, dy = pyf - f0.y;
+        const float sq = fmaf(dx, fmaf(f0.z, dx, f0.w * dy), (f1.x * dy) * dy);   // k q
+        const float a = fminf(amax, __builtin_amdgcn_exp2f(sq + f1.y));
+        aa[j] = sq >= f1.z ? a : -0.0f;               // -0: no blend, and w = -0 says so
       }
-      // blends in list order without branches: a lane that is done or has no blend uses a = 0,
-      // which leaves T and the sums exactly as they are
+      // blends in list order without branches: a record that does not blend has a = -0, which
+      // leaves T and the sums as they are; w >= +0 marks a blend (T > 0 while blending, T = 0
+      // after the stop, where last no longer matters)
 #pragma unroll
       for (int j = 0; j < kGroup; ++j) {
-        const bool v = !done && aa[j] >= 0.0f;
-        const float a = v ? aa[j] : 0.0f;
+        const float a = aa[j];
         const float w = a * T;
         acc0 = fmaf(w, c2[j].x, acc0);
         acc1 = fmaf(w, c2[j].y, acc1);
@@ -191,13 +212,20 @@ __global__ __launch_bounds__(kWave) void k_composite(
         acc5 = fmaf(w, c3[j].z, acc5);
         acc6 = fmaf(w, zz[j], acc6);
         T = T * (1.0f - a);
-        last = v ? pp[j] : last;
-        done = done || (v && T < opt.t_eps);
+        const bool blended = __builtin_amdgcn_classf(w, 0x3C0);   // +0, +denormal, +normal, +inf
+        last = blended ? __float_as_int(c2[j].w) : last;
+        // a pixel stops at the blend that takes T below t_eps (rare: checked wave-wide)
+        if (__ballot(T < opt.t_eps) & ~done) {
+          const bool stop = !((done >> lane) & 1ull) && T < opt.t_eps && blended;
+          if (stop) { t_stop = T; last_stop = last; T = 0.0f; }
+          done |= __ballot(stop);
+        }
       }
     }
     __syncthreads();                                  // reads done before the next batch lands
   }
   if (!inside) return;
+  if ((done >> lane) & 1ull) { T = t_stop; last = last_stop; }
   const int64_t HW = (int64_t)W * H;
   const int64_t pix = (int64_t)P.y * W + P.x;
   const int64_t c3 = cam * 3 * HW;
