@@ -100,6 +100,15 @@ __device__ __forceinline__ void blend_form(const float4& r0, const float4& r1, c
   f3 = make_float4(r3.x, r3.y, r3.z, 0.0f);
 }
 
+// k q of a blend form at the pixel centre (px, py), with the offsets it used. Compositing and its
+// adjoint evaluate this same operation sequence, so they take the same blend decisions.
+__device__ __forceinline__ float blend_kq(const float4& f0, const float4& f1, float px, float py,
+                                          float& dx, float& dy) {
+  dx = px - f0.x;
+  dy = py - f0.y;
+  return fmaf(dx, fmaf(f0.z, dx, f0.w * dy), (f1.x * dy) * dy);
+}
+
 __global__ __launch_bounds__(kWave) void k_composite(
     int64_t n, int W, int H, int TX, int64_t tiles_per_cam, int64_t total_tiles,
     const float4* __restrict__ rec, const uint32_t* __restrict__ vals,
@@ -192,8 +201,8 @@ __global__ __launch_bounds__(kWave) void k_composite(
         c2[j] = s_f2[k];
         c3[j] = s_f3[k];
         zz[j] = f1.w;
-        const float dx = pxf - f0.x, dy = pyf - f0.y;
-        const float sq = fmaf(dx, fmaf(f0.z, dx, f0.w * dy), (f1.x * dy) * dy);   // k q
+        float dx, dy;
+        const float sq = blend_kq(f0, f1, pxf, pyf, dx, dy);
         const float a = fminf(amax, __builtin_amdgcn_exp2f(sq + f1.y));
         aa[j] = sq >= f1.z ? a : -0.0f;               // -0: no blend, and w = -0 says so
       }
@@ -251,9 +260,8 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(
     const int32_t* __restrict__ n_contrib, const float* __restrict__ g_rgb,
     const float* __restrict__ g_nrm, const float* __restrict__ g_depth,
     float* __restrict__ sgrad) {
-  __shared__ float4 s_r0[kWave], s_r1[kWave], s_r2[kWave], s_r3[kWave];
+  __shared__ float4 s_f0[kWave], s_f1[kWave], s_f2[kWave], s_f3[kWave];   // blend forms
   __shared__ uint32_t s_g[kWave];
-  __shared__ int32_t s_pos[kWave];
   int64_t opos;
   int quad;
   if (!quadrant_of_block(blockIdx.x, total_tiles, opos, quad)) return;
@@ -266,7 +274,11 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(
   const bool inside = P.x < W && P.y < H;
   const float pxf = (float)P.x + 0.5f, pyf = (float)P.y + 0.5f;
   const uint32_t start = ranges[tile];
-  const float cut2 = opt.sigma_cut * opt.sigma_cut;
+  const float k_cut2 = kNegHalfLog2e * (opt.sigma_cut * opt.sigma_cut);
+  const float amax = fmaxf(opt.alpha_max, opt.alpha_max);
+  const float l2amin = opt.alpha_max < opt.alpha_min ? __builtin_inff() : __log2f(opt.alpha_min);
+  // the conic's gradients from k-scaled entries: d/du of q = -2 (A dx + B dy) = (-2 / k) (k A dx + k B dy)
+  constexpr float kM2OverK = -2.0f / kNegHalfLog2e;
   const float4* rec_cam = rec + cam * n * kRecFloat4;
   const int64_t HW = (int64_t)W * H;
   const int64_t pix = (int64_t)P.y * W + P.x;
@@ -313,9 +325,10 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(
     const uint64_t relmask = __ballot(rel);
     if (rel) {
       const int slot = __popcll(relmask & lt);
-      s_r0[slot] = p0; s_r1[slot] = p1; s_r2[slot] = p2; s_r3[slot] = p3;
+      float4 f0, f1, f2, f3;
+      blend_form(p0, p1, p2, p3, bstart + lane, k_cut2, l2amin, f0, f1, f2, f3);   // position from 0
+      s_f0[slot] = f0; s_f1[slot] = f1; s_f2[slot] = f2; s_f3[slot] = f3;
       s_g[slot] = pg_idx;
-      s_pos[slot] = bstart + lane;
     }
     if (bstart > 0) fetch(max(0, bstart - kWave), bstart);
     __syncthreads();                                  // one wavefront: orders the LDS writes
@@ -324,42 +337,40 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(
 #pragma unroll
       for (int i = 0; i < kScreenGrads; ++i) pg[i] = 0.f;
       bool contrib = false;
-      if (s_pos[k] < nc) {
-        const float4 r0 = s_r0[k];
-        const float4 r1 = s_r1[k];
-        const float dx = pxf - r0.x, dy = pyf - r0.y;
-        const float q = conic_q(r1.x, r1.y, r1.z, dx, dy);
-        if (q <= cut2) {
-          const float e = __expf(-0.5f * q);
-          const float araw = r0.z * e;
-          const float a = fminf(opt.alpha_max, araw);
-          if (a >= opt.alpha_min) {
-            contrib = true;
-            const float4 r2 = s_r2[k];
-            const float4 r3 = s_r3[k];
-            const float inv = __builtin_amdgcn_rcpf(1.0f - a);
-            T = T * inv;                         // transmittance in front of this splat
-            const float w = a * T;
-            const float gf = fmaf(g[0], r2.x, fmaf(g[1], r2.y, fmaf(g[2], r2.z, fmaf(g[3], r3.x,
-                             fmaf(g[4], r3.y, fmaf(g[5], r3.z, g[6] * r0.w))))));
-            const float dLda = fmaf(T, gf, -gb * inv);
-            gb = fmaf(w, gf, gb);
-            pg[7] = g[0] * w;
-            pg[8] = g[1] * w;
-            pg[9] = g[2] * w;
-            pg[10] = g[3] * w;
-            pg[11] = g[4] * w;
-            pg[12] = g[5] * w;
-            pg[6] = g[6] * w;
-            if (!(araw > opt.alpha_max)) {
-              pg[5] = dLda * e;
-              const float dLdq = dLda * (-0.5f * a);
-              pg[2] = dLdq * dx * dx;
-              pg[3] = dLdq * 2.0f * dx * dy;
-              pg[4] = dLdq * dy * dy;
-              pg[0] = dLdq * (-2.0f * fmaf(r1.x, dx, r1.y * dy));
-              pg[1] = dLdq * (-2.0f * fmaf(r1.y, dx, r1.z * dy));
-            }
+      const float4 f2 = s_f2[k];
+      if (__float_as_int(f2.w) < nc) {           // list position (from 0) before the pixel's stop
+        const float4 f0 = s_f0[k];
+        const float4 f1 = s_f1[k];
+        float dx, dy;
+        const float sq = blend_kq(f0, f1, pxf, pyf, dx, dy);
+        if (sq >= f1.z) {                        // the forward pass's blend decision
+          const float araw = __builtin_amdgcn_exp2f(sq + f1.y);
+          const float a = fminf(amax, araw);
+          contrib = true;
+          const float4 f3 = s_f3[k];
+          const float inv = __builtin_amdgcn_rcpf(1.0f - a);
+          T = T * inv;                           // transmittance in front of this splat
+          const float w = a * T;
+          const float gf = fmaf(g[0], f2.x, fmaf(g[1], f2.y, fmaf(g[2], f2.z, fmaf(g[3], f3.x,
+                           fmaf(g[4], f3.y, fmaf(g[5], f3.z, g[6] * f1.w))))));
+          const float dLda = fmaf(T, gf, -gb * inv);
+          gb = fmaf(w, gf, gb);
+          pg[7] = g[0] * w;
+          pg[8] = g[1] * w;
+          pg[9] = g[2] * w;
+          pg[10] = g[3] * w;
+          pg[11] = g[4] * w;
+          pg[12] = g[5] * w;
+          pg[6] = g[6] * w;
+          if (!(araw > opt.alpha_max)) {
+            pg[5] = dLda * __builtin_amdgcn_exp2f(sq);      // d alpha / d o = e^(-q/2)
+            const float dLdq = dLda * (-0.5f * a);
+            pg[2] = dLdq * dx * dx;
+            pg[3] = dLdq * 2.0f * dx * dy;
+            pg[4] = dLdq * dy * dy;
+            const float dLdq2 = dLdq * kM2OverK;
+            pg[0] = dLdq2 * fmaf(f0.z, dx, (0.5f * f0.w) * dy);
+            pg[1] = dLdq2 * fmaf(0.5f * f0.w, dx, f1.x * dy);
           }
         }
       }
