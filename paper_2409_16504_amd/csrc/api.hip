@@ -99,6 +99,8 @@ struct pcs_context {
   DevBuf knn_scratch, conv_tmp, wt_tmp, shade_cams, tile_hist;
   uint32_t* host_small = nullptr;   // pinned 4 KiB: readback of the small device words
   hipEvent_t counts_ready = nullptr;  // recorded after the instance-count read-back
+  hipEvent_t proj_done = nullptr;     // recorded after the projection, for the read-back stream
+  hipStream_t aux = nullptr;          // the read-back's own stream (default priority)
   pcs_state* internal = nullptr;    // state used when the caller passes none
   bool timing = false;
   uint32_t stage_mask = ~0u;        // stages whose launches are timed
@@ -228,6 +230,12 @@ int pcs_context_create(int device, pcs_context** out) {
     return fail(PCS_ERR_OOM, "pinned host allocation failed");
   }
   ctx->host_small = reinterpret_cast<uint32_t*>(hp);
+  if (hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->counts_ready, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->proj_done, hipEventDisableTiming) != hipSuccess) {
+    pcs_context_destroy(ctx);
+    return fail(PCS_ERR_HIP, "stream or event creation failed");
+  }
   *out = ctx;
   return PCS_OK;
 }
@@ -245,6 +253,8 @@ void pcs_context_destroy(pcs_context* ctx) {
   delete ctx->internal;
   if (ctx->host_small) (void)hipHostFree(ctx->host_small);
   if (ctx->counts_ready) (void)hipEventDestroy(ctx->counts_ready);
+  if (ctx->proj_done) (void)hipEventDestroy(ctx->proj_done);
+  if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
   delete ctx;
 }
 
@@ -327,11 +337,10 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
     st = ctx->internal;
   }
   st->valid = false;
-  // cameras to the device (pageable copy: stream-ordered, the host array may be reused at once)
+  // cameras reach the device as kernel arguments of the frame's first launch (no copy to wait on)
   std::vector<DevCamera> dc(n_cams);
   for (int c = 0; c < n_cams; ++c) dc[c] = to_dev(cams[c]);
   PCS_TRY(ensure(st->dcams, sizeof(DevCamera) * n_cams, "cameras"));
-  PCS_HIP(hipMemcpyAsync(st->dcams.p, dc.data(), sizeof(DevCamera) * n_cams, hipMemcpyHostToDevice, s));
   const DevOptions dopt = to_dev(*opt);
 
   const int64_t cn1 = std::max<int64_t>(cn, 1);
@@ -357,7 +366,7 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   PCS_TRY(ensure(ctx->dvals_alt, cn1 * sizeof(uint32_t), "depth order (alternate)"));
   PCS_TRY(ensure(ctx->dsort_scratch, sort_scratch_bytes(cn), "depth sort scratch"));
   PCS_TRY(ensure(ctx->tile_hist, kTileHistWords * sizeof(uint32_t), "tile digit histograms"));
-  PCS_HIP(launch_init_small(ctx->small.as<uint32_t>(), s));
+  PCS_HIP(launch_init_small(ctx->small.as<uint32_t>(), dc.data(), n_cams, st->dcams.as<DevCamera>(), s));
   {
     // the projection also clears what the depth sort and the scan need zeroed
     ClearSpans clear;
@@ -376,9 +385,14 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   // range is read from the projection's slots on the device, and sort passes beyond the bits that
   // range needs return at once), so they are queued behind the read-back and the host waits only
   // for the read-back: it sizes the tile sort while the GPU sorts by depth.
-  if (!ctx->counts_ready) PCS_HIP(hipEventCreateWithFlags(&ctx->counts_ready, hipEventDisableTiming));
-  PCS_HIP(hipMemcpyAsync(ctx->host_small, ctx->small.p, kSmallWords * 4, hipMemcpyDeviceToHost, s));
-  PCS_HIP(hipEventRecord(ctx->counts_ready, s));
+  // The read-back runs on its own stream, so the depth sort does not wait for the copy. It reads
+  // only the count slots, which nothing on the frame's stream writes again before the host has
+  // waited for the copy.
+  PCS_HIP(hipEventRecord(ctx->proj_done, s));
+  PCS_HIP(hipStreamWaitEvent(ctx->aux, ctx->proj_done, 0));
+  PCS_HIP(hipMemcpyAsync(ctx->host_small + kCountWord, ctx->small.as<uint32_t>() + kCountWord,
+                         2 * kZSlots * sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->aux));
+  PCS_HIP(hipEventRecord(ctx->counts_ready, ctx->aux));
   if (cn > 0) {
     StageTimer tm(ctx, ST_SORT, s);
     bool unused = false;

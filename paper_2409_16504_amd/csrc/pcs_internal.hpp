@@ -137,7 +137,14 @@ constexpr int kZSlots = 64;
 constexpr int kCountWord = 2 + 2 * kZSlots;
 constexpr int kDepthWord = kCountWord + 2 * kZSlots;
 constexpr int kSmallWords = kDepthWord + 4;
-hipError_t launch_init_small(uint32_t* small, hipStream_t s);
+// Cameras travel to the device as kernel arguments, kArgCams per launch: the frame's first launch
+// resets the small words and writes the first batch into dst.
+constexpr int kArgCams = 8;
+struct CamBatch {
+  DevCamera c[kArgCams];
+};
+hipError_t launch_init_small(uint32_t* small, const DevCamera* cams, int n_cams, DevCamera* dst,
+                             hipStream_t s);
 hipError_t launch_project(int64_t n, int n_cams, const DevCamera* cams, const DevOptions& opt,
                           const pcs_gaussians& g, float4* rec, uint4* meta, uint32_t* counts,
                           uint32_t* zrange, unsigned long long* count_slots, const ClearSpans& clear,

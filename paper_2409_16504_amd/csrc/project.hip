@@ -8,6 +8,8 @@
 //
 // One thread per (camera, Gaussian); the planar inputs make every load a coalesced 4-byte stream.
 
+#include <algorithm>
+
 #include "projection.hpp"
 
 namespace pcs {
@@ -118,8 +120,14 @@ __global__ __launch_bounds__(256) void k_project(
   }
 }
 
-__global__ void k_init_small(uint32_t* __restrict__ small) {
+// Resets the small words (when small is set) and copies n of the batch's cameras to dst.
+__global__ __launch_bounds__(256) void k_init_small(uint32_t* __restrict__ small, CamBatch cams, int n,
+                                                    DevCamera* __restrict__ dst) {
   const int i = threadIdx.x;
+  constexpr int kWords = (int)(sizeof(DevCamera) / 4);
+  if (i < n * kWords)
+    reinterpret_cast<uint32_t*>(dst)[i] = reinterpret_cast<const uint32_t*>(cams.c)[i];
+  if (!small) return;
   if (i < 2) small[i] = 0u;                                   // instance total (u64)
   if (i < kZSlots) {
     small[2 + i] = 0xFFFFFFFFu;                               // depth-bit minima
@@ -142,9 +150,19 @@ hipError_t launch_fill_f32(float* p, float value, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_init_small(uint32_t* small, hipStream_t s) {
-  hipLaunchKernelGGL(k_init_small, dim3(1), dim3(2 * kZSlots), 0, s, small);
-  return hipGetLastError();
+hipError_t launch_init_small(uint32_t* small, const DevCamera* cams, int n_cams, DevCamera* dst,
+                             hipStream_t s) {
+  static_assert(kArgCams * sizeof(DevCamera) / 4 <= 256 && 2 * kZSlots <= 256, "one 256-thread block");
+  for (int c0 = 0; c0 == 0 || c0 < n_cams; c0 += kArgCams) {
+    CamBatch b{};
+    const int nb = std::min(kArgCams, n_cams - c0);
+    for (int k = 0; k < nb; ++k) b.c[k] = cams[c0 + k];
+    hipLaunchKernelGGL(k_init_small, dim3(1), dim3(256), 0, s, c0 == 0 ? small : nullptr, b,
+                       std::max(nb, 0), dst + c0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_project(int64_t n, int n_cams, const DevCamera* cams, const DevOptions& opt,
