@@ -45,10 +45,11 @@ def _excluded(g, cams):
     return bad
 
 
-def test_backward_matches_fp64_adjoint(R):
+@pytest.mark.parametrize("n_cams", [3, 11])      # 11: cameras reach the device in two launches
+def test_backward_matches_fp64_adjoint(R, n_cams):
     import torch
     import paper_2409_16504_amd as P
-    g, cams, go = _scene()
+    g, cams, go = _scene(n_cams=n_cams)
     st = P.RenderState(R)
     R.render(to_torch(g), cams, P.default_options(), state=st)
     gg = R.render_backward(st, {k: torch.from_numpy(v.astype(np.float32)).cuda() for k, v in go.items()},
@@ -57,7 +58,7 @@ def test_backward_matches_fp64_adjoint(R):
     ref, sabs, _ = oracle.backward({k: v.astype(np.float64) for k, v in g.items()}, cams, go)
     bad = _excluded(g, cams)
     keep = np.array([i not in bad for i in range(g["opacity"].size)])
-    assert keep.sum() > 200
+    assert keep.sum() > 180
     checked = 0
     for name in ("mean", "cov6", "quat", "scale", "opacity", "rgb", "normal"):
         a = gg[name].reshape(-1, keep.size)[:, keep]

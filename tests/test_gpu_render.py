@@ -65,6 +65,18 @@ def test_multi_camera_ragged_tiles(R):
     check_images(imgs, bins, ref, 5.0)
 
 
+def test_many_cameras_in_batches(R):
+    """19 cameras: the camera records reach the device as arguments of three launches (8 + 8 + 3)."""
+    rng = np.random.default_rng(29)
+    g = random_gaussians(2500, rng, scale_range=(0.005, 0.08))
+    cams = orbit_cameras(19, rng, width=70, height=52)         # 5 x 4 tiles, ragged edges
+    imgs, bins, _ = gpu_render(R, g, cams)
+    ref = oracle.render(g, cams, mode="ref")
+    check_bins(bins, ref, 19 * 20)
+    check_images(imgs, bins, ref, 5.0)
+    assert all((ref["n_contrib"][c] > 0).sum() > 100 for c in range(19))
+
+
 def test_options_background_and_thresholds(R):
     g, cams = c1_scene()
     opts = dict(bg=(0.25, 0.5, 1.0), alpha_min=0.02, alpha_max=0.95, t_eps=1e-3, lowpass=0.1, sigma_cut=2.5)
