@@ -31,8 +31,8 @@ FP32_VALU_PEAK_TFLOPS = 78.6     # 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 G
 
 # Algorithmic bytes per unit (stated in the design doc):
 PROJECT_READ_B = 68      # mean 12 + quat 16 + scale 12 + opacity 4 + rgb 12 + normal 12
-PROJECT_WRITE_VIS_B = 84  # 64 B splat record + 16 B binning meta + 4 B count
-PROJECT_WRITE_CULL_B = 4
+PROJECT_WRITE_VIS_B = 76  # 64 B splat record + 4 B depth bits + 8 B tile rectangle
+PROJECT_WRITE_CULL_B = 12  # depth bits and rectangle, zero
 SORT_PASS_B = 16         # read + write of a 4 B key and a 4 B value
 # Compositing FLOP per (pixel, list entry) visit and per blended splat.
 COMPOSITE_VISIT_FLOP = 9     # offset (2), conic quadratic form (7)
@@ -230,7 +230,7 @@ def late_shading(R, out, cams, reps=20):
 
 # Kernel source each stage's dominant kernel is built from (a counter summary applies only while
 # this file is unchanged).
-STAGE_SOURCE = {"composite": "composite.hip", "project": "project.hip", "scan": "scan_sort.hip",
+STAGE_SOURCE = {"composite": "composite.hip", "project": "project.hip",
                 "binning": "scan_sort.hip", "sort": "scan_sort.hip", "ranges": "scan_sort.hip"}
 
 
@@ -304,10 +304,9 @@ def stage_rooflines(per_stage, n, m, bins, W, H):
     tile_bits = int(tiles - 1).bit_length()
     byts = {
         "project": n * PROJECT_READ_B + vis * PROJECT_WRITE_VIS_B + (n - vis) * PROJECT_WRITE_CULL_B,
-        "scan": n * 12,                                            # order, gathered count, offset
-        "binning": vis * 28 + m * 8,                               # order/count/meta/offset; key+value
-        "sort": n * (28 + 4 + SORT_PASS_B * ((depth_bits + 7) // 8)) +   # depth keys, hist, passes
-                m * (4 + SORT_PASS_B * ((tile_bits + 7) // 8)),
+        "binning": n * 12 + m * 8,                                 # order + gathered rectangle; key+value
+        "sort": n * (12 + SORT_PASS_B * ((depth_bits + 7) // 8)) +      # depth keys, passes
+                m * SORT_PASS_B * ((tile_bits + 7) // 8),                 # (histograms come fused)
         "ranges": m * 4 + tiles * 16,                              # keys; ranges fill + order
     }
     out = {}
@@ -322,7 +321,7 @@ def roofline(per_stage, n, m, bins, visits, blends):
     """Roofline entry of the frame's dominant kernel, from algorithmic work per launch. Every stage
     but compositing is a chain of short kernels (the sort alone runs about a dozen), so the longest
     single kernel is the compositing kernel; the other stages are in `stage_roofline`."""
-    frame = {k: v for k, v in per_stage.items() if k in ("project", "scan", "binning", "sort", "ranges", "composite")}
+    frame = {k: v for k, v in per_stage.items() if k in ("project", "binning", "sort", "ranges", "composite")}
     dom = "composite" if "composite" in frame else max(frame, key=frame.get)
     ms = frame[dom]
     if dom == "composite" and visits is not None:
@@ -331,17 +330,18 @@ def roofline(per_stage, n, m, bins, visits, blends):
         return dict(kernel=dom, bound="alu", achieved=ach, peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
                     frac=ach / FP32_VALU_PEAK_TFLOPS, traffic=measured_traffic(dom), avg_ms=ms)
     if dom == "sort":
-        # depth sort of the n splats (u32 keys) then tile sort of the m instances (u32 keys): one
-        # histogram read of the keys, then per pass a read and a write of key and value
+        # depth sort of the n splats (u32 keys) then tile sort of the m instances (u32 keys): per
+        # pass a read and a write of key and value (the histograms are counted by the kernels that
+        # write the keys)
         z = (bins["keys"] & np.uint64(0xFFFFFFFF)).astype(np.int64)
         depth_bits = int(z.max() - z.min()).bit_length() if m else 0
         tile_bits = int(bins["ranges"].shape[1] - 1).bit_length()
-        byts = n * (4 + SORT_PASS_B * ((depth_bits + 7) // 8)) + m * (4 + SORT_PASS_B * ((tile_bits + 7) // 8))
+        byts = n * (12 + SORT_PASS_B * ((depth_bits + 7) // 8)) + m * SORT_PASS_B * ((tile_bits + 7) // 8)
     elif dom == "project":
         vis = int(np.unique(bins["vals"]).size)
         byts = n * PROJECT_READ_B + vis * PROJECT_WRITE_VIS_B + (n - vis) * PROJECT_WRITE_CULL_B
     elif dom == "binning":
-        byts = m * 12
+        byts = n * 12 + m * 8
     else:
         byts = m * 8
     ach = byts / (ms * 1e-3) / 1e9

@@ -68,7 +68,7 @@ typedef struct pcs_gaussians {
 } pcs_gaussians;
 
 /* Options (defaults from pcs_options_default):
- *   z_near 0.2     cull when camera-space z <= z_near
+ *   z_near 0.2     cull when camera-space z <= z_near (must be > 0: depths order as positive floats)
  *   lowpass 0.3    added to both diagonal entries of Sigma_s (pixels^2)
  *   sigma_cut 3    splat boundary at sigma_cut standard deviations (Section 3.1)
  *   alpha_min 1/255, alpha_max 0.99, t_eps 1e-4: a splat is skipped where alpha < alpha_min,

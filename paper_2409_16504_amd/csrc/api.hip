@@ -94,7 +94,7 @@ struct pcs_state;
 
 struct pcs_context {
   int device = 0;
-  DevBuf counts, offsets, meta, keys_alt, vals_alt, scan_scratch, sort_scratch, sgrad, small;
+  DevBuf zbits, rect, keys_alt, vals_alt, scan_scratch, sort_scratch, sgrad, small;
   DevBuf dkeys, dkeys_alt, dvals, dvals_alt, dsort_scratch;   // depth sort of the splats
   DevBuf knn_scratch, conv_tmp, wt_tmp, shade_cams, tile_hist;
   uint32_t* host_small = nullptr;   // pinned 4 KiB: readback of the small device words
@@ -180,11 +180,11 @@ int check_options(const pcs_options& o) {
                      o.bg[0], o.bg[1], o.bg[2]};
   for (float x : v)
     if (!std::isfinite(x)) return fail(PCS_ERR_INVALID_ARG, "options must be finite");
-  if (o.sigma_cut <= 0.0f || o.lowpass < 0.0f || o.alpha_max <= 0.0f || o.alpha_max >= 1.0f ||
-      o.alpha_min < 0.0f || o.t_eps < 0.0f)
+  if (o.z_near <= 0.0f || o.sigma_cut <= 0.0f || o.lowpass < 0.0f || o.alpha_max <= 0.0f ||
+      o.alpha_max >= 1.0f || o.alpha_min < 0.0f || o.t_eps < 0.0f)
     return fail(PCS_ERR_INVALID_ARG,
-                "options out of range (need sigma_cut > 0, lowpass >= 0, 0 < alpha_max < 1, "
-                "alpha_min >= 0, t_eps >= 0)");
+                "options out of range (need z_near > 0, sigma_cut > 0, lowpass >= 0, "
+                "0 < alpha_max < 1, alpha_min >= 0, t_eps >= 0)");
   return PCS_OK;
 }
 
@@ -311,7 +311,8 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   if (!out || !out->rgb) return fail(PCS_ERR_INVALID_ARG, "output rgb image is NULL");
   const int W = cams[0].width, H = cams[0].height;
   if (W <= 0 || H <= 0) return fail(PCS_ERR_INVALID_ARG, "image width and height must be positive");
-  if (W > (1 << 20) || H > (1 << 20)) return fail(PCS_ERR_UNSUPPORTED, "image larger than 2^20");
+  if (W > 65535 * kTile || H > 65535 * kTile)
+    return fail(PCS_ERR_UNSUPPORTED, "image side above 65535 tiles");
   for (int c = 0; c < n_cams; ++c) {
     if (cams[c].width != W || cams[c].height != H)
       return fail(PCS_ERR_INVALID_ARG, "all cameras of one call must share width and height");
@@ -345,9 +346,8 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
 
   const int64_t cn1 = std::max<int64_t>(cn, 1);
   PCS_TRY(ensure(st->rec, cn1 * kRecFloat4 * sizeof(float4), "splat records"));
-  PCS_TRY(ensure(ctx->meta, cn1 * sizeof(uint4), "binning meta"));
-  PCS_TRY(ensure(ctx->counts, cn1 * sizeof(uint32_t) + 64, "counts"));
-  PCS_TRY(ensure(ctx->offsets, cn1 * sizeof(uint32_t) + 64, "offsets"));
+  PCS_TRY(ensure(ctx->zbits, cn1 * sizeof(uint32_t), "depth bits"));
+  PCS_TRY(ensure(ctx->rect, cn1 * sizeof(uint2), "tile rectangles"));
   PCS_TRY(ensure(ctx->scan_scratch, scan_scratch_bytes(cn), "scan scratch"));
   PCS_TRY(ensure(ctx->small, kSmallWords * 4, "small"));
   PCS_TRY(ensure(st->ranges, 2 * total_tiles * sizeof(uint32_t), "tile ranges"));
@@ -378,16 +378,15 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
     clear.count[2] = kTileHistWords;
     StageTimer tm(ctx, ST_PROJECT, s);
     PCS_HIP(launch_project(n, n_cams, st->dcams.as<DevCamera>(), dopt, *g, st->rec.as<float4>(),
-                           ctx->meta.as<uint4>(), ctx->counts.as<uint32_t>(), d_zrange, d_counts, clear, s));
+                           ctx->zbits.as<uint32_t>(), ctx->rect.as<uint2>(), d_zrange, d_counts, clear, s));
   }
   // The instance total goes to the host right after the projection; the (camera, depth) order
-  // and the prefix sum of the tile counts in that order need nothing from the host (the depth
-  // range is read from the projection's slots on the device, and sort passes beyond the bits that
-  // range needs return at once), so they are queued behind the read-back and the host waits only
-  // for the read-back: it sizes the tile sort while the GPU sorts by depth.
-  // The read-back runs on its own stream, so the depth sort does not wait for the copy. It reads
-  // only the count slots, which nothing on the frame's stream writes again before the host has
-  // waited for the copy.
+  // needs nothing from the host (the depth range is read from the projection's slots on the
+  // device, and sort passes beyond the bits that range needs return at once), so it is queued at
+  // once and the host waits only for the read-back: it sizes the tile buffers while the GPU sorts
+  // by depth. The read-back runs on its own stream, so the depth sort does not wait for the copy.
+  // It reads only the count slots, which nothing on the frame's stream writes again before the
+  // host has waited for the copy.
   PCS_HIP(hipEventRecord(ctx->proj_done, s));
   PCS_HIP(hipStreamWaitEvent(ctx->aux, ctx->proj_done, 0));
   PCS_HIP(hipMemcpyAsync(ctx->host_small + kCountWord, ctx->small.as<uint32_t>() + kCountWord,
@@ -396,16 +395,11 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   if (cn > 0) {
     StageTimer tm(ctx, ST_SORT, s);
     bool unused = false;
-    PCS_HIP(launch_depth_keys_hist(cn, ctx->meta.as<uint4>(), ctx->counts.as<uint32_t>(), d_zrange, d_depth,
-                                   ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(), ctx->dsort_scratch.p, s));
+    PCS_HIP(launch_depth_keys_hist(cn, ctx->zbits.as<uint32_t>(), d_zrange, d_depth, ctx->dkeys.as<uint32_t>(),
+                                   ctx->dvals.as<uint32_t>(), ctx->dsort_scratch.p, s));
     PCS_HIP(launch_sort(ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(), ctx->dkeys_alt.as<uint32_t>(),
                         ctx->dvals_alt.as<uint32_t>(), cn, 32, ctx->dsort_scratch.p, s, &unused, d_depth,
                         true, true));
-  }
-  if (cn > 0) {
-    StageTimer tm(ctx, ST_SCAN, s);
-    PCS_HIP(launch_scan(ctx->counts.as<uint32_t>(), ctx->dvals.as<uint32_t>(), ctx->dvals_alt.as<uint32_t>(),
-                        d_depth, ctx->offsets.as<uint32_t>(), cn, d_total, ctx->scan_scratch.p, s, true));
   }
   PCS_HIP(hipEventSynchronize(ctx->counts_ready));
   uint64_t m64 = 0;
@@ -427,17 +421,18 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   if (m > 0) {
     {
       StageTimer tm(ctx, ST_BINNING, s);
-      // binning also clears what the tile sort and the tile ranges need zeroed
+      // binning (with the prefix sum that places its keys) also clears what the tile sort and
+      // the tile ranges need zeroed
       ClearSpans clear;
       clear.p[0] = ctx->sort_scratch.as<uint32_t>();
       clear.count[0] = sort_clear_words(m);
       clear.p[1] = st->ranges.as<uint32_t>();
       clear.count[1] = 2 * total_tiles;
-      PCS_HIP(launch_binning(n, n_cams, TX, tiles_per_cam, ctx->dvals.as<uint32_t>(),
-                             ctx->dvals_alt.as<uint32_t>(), d_depth, ctx->meta.as<uint4>(),
-                             ctx->counts.as<uint32_t>(), ctx->offsets.as<uint32_t>(),
-                             st->keys.as<uint32_t>(), st->vals.as<uint32_t>(), tile_bits,
-                             ctx->tile_hist.as<uint32_t>(), clear, s));
+      PCS_HIP(launch_scan_binning(n, n_cams, TX, tiles_per_cam, ctx->dvals.as<uint32_t>(),
+                                  ctx->dvals_alt.as<uint32_t>(), d_depth, ctx->rect.as<uint2>(),
+                                  ctx->scan_scratch.p, d_total, st->keys.as<uint32_t>(),
+                                  st->vals.as<uint32_t>(), tile_bits, ctx->tile_hist.as<uint32_t>(),
+                                  clear, s));
     }
     bool in_alt = false;
     {

@@ -33,7 +33,8 @@ struct DevOptions {
 //   r0 = (u, v, opacity, z)   r1 = (A, B, C, ex)   r2 = (r, g, b, ey)   r3 = (nx, ny, nz, 0)
 // where (A, B, C) is the conic (inverse screen covariance) and (ex, ey) the padded half extents
 // of the bounding box of the sigma_cut ellipse.
-// Meta record for binning: (fp32 depth bits, x0 | x1 << 16, y0 | y1 << 16, 0).
+// Binning inputs per (camera, Gaussian): the fp32 bits of the depth (0 for a culled splat) and the
+// tile rectangle (x0 | x_end << 16, y0 | y_end << 16), ends exclusive (zero for a culled splat).
 
 // ---- wave64 helpers -------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
@@ -146,7 +147,7 @@ struct CamBatch {
 hipError_t launch_init_small(uint32_t* small, const DevCamera* cams, int n_cams, DevCamera* dst,
                              hipStream_t s);
 hipError_t launch_project(int64_t n, int n_cams, const DevCamera* cams, const DevOptions& opt,
-                          const pcs_gaussians& g, float4* rec, uint4* meta, uint32_t* counts,
+                          const pcs_gaussians& g, float4* rec, uint32_t* zbits, uint2* rect,
                           uint32_t* zrange, unsigned long long* count_slots, const ClearSpans& clear,
                           hipStream_t s);
 
@@ -163,25 +164,28 @@ int64_t scan_clear_words(int64_t n);
 // histograms into the sort scratch's histogram area (zeroed beforehand), for a launch_sort with
 // hist_ready. The depth-bit range comes from the projection's slots on the device; info[0..3)
 // receives the pass count, depth bits and minimum depth bits.
-hipError_t launch_depth_keys_hist(int64_t m, const uint4* meta, const uint32_t* counts,
-                                  const uint32_t* zrange, uint32_t* info, uint32_t* keys, uint32_t* vals,
-                                  void* sort_scratch, hipStream_t s);
+hipError_t launch_depth_keys_hist(int64_t m, const uint32_t* zbits, const uint32_t* zrange,
+                                  uint32_t* info, uint32_t* keys, uint32_t* vals, void* sort_scratch,
+                                  hipStream_t s);
 
-// Tile keys of every visible splat, written in the depth order at `offsets`; the order is order1
-// when *passes is odd (where the depth sort ended), else order0.
 // Tile-digit histograms counted by binning: kTileHistCopies partial copies of
 // [kTileHistPasses][256] counters, summed by the tile sort.
 constexpr int kTileHistCopies = 32;
 constexpr int kTileHistPasses = 4;
 constexpr int64_t kTileHistWords = (int64_t)kTileHistCopies * kTileHistPasses * 256;
 
-// Also counts the tile keys' 8-bit digits into hist (kTileHistWords, zeroed beforehand), the
-// histogram input of the tile sort (launch_sort with ext_hist).
-hipError_t launch_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_cam, const uint32_t* order0,
-                          const uint32_t* order1, const uint32_t* passes, const uint4* meta,
-                          const uint32_t* counts, const uint32_t* offsets, uint32_t* keys,
-                          uint32_t* vals, int tile_bits, uint32_t* hist, const ClearSpans& clear,
-                          hipStream_t s);
+// Binning fused with the prefix sum of the tile counts in depth order: the (camera, Gaussian)
+// entries in the depth order (order1 when *passes is odd, where the depth sort ended, else
+// order0) get their offsets from a decoupled look-back scan, and every block then writes its
+// entries' tile keys (global tile ids, row-major within a rectangle) and Gaussian indices at
+// those offsets, counting the keys' 8-bit digits into hist (kTileHistWords, zeroed beforehand)
+// for the tile sort (launch_sort with ext_hist). scan_scratch must be cleared (scan_clear_words);
+// *total receives the instance count.
+hipError_t launch_scan_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_cam,
+                               const uint32_t* order0, const uint32_t* order1,
+                               const uint32_t* passes, const uint2* rect, void* scan_scratch,
+                               uint64_t* total, uint32_t* keys, uint32_t* vals, int tile_bits,
+                               uint32_t* hist, const ClearSpans& clear, hipStream_t s);
 
 // Stable LSD radix sort of (key, value) pairs over key bits [0, bits), K = uint32_t or uint64_t.
 // Ping-pongs between (k0,v0) and (k1,v1); returns in *result_in_alt whether the sorted data ended

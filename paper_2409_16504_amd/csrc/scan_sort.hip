@@ -147,68 +147,136 @@ __global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* __restrict__ 
 // ---- depth keys and binning ----------------------------------------------------------------
 // One key per (camera, Gaussian); culled splats get all bits set (they have no tile instances,
 // so where they land in the order does not matter).
-// Positions of the depth order, grid-stride: the splat at each writes its tile keys (global tile
-// id) and Gaussian index at its offset in that order, and counts the keys' digits (n_digits 8-bit
-// digits) into the block's LDS histograms, added once per block to hist (zeroed beforehand,
-// [kTileHistCopies][kTileHistPasses][256]) for the tile sort.
-__global__ __launch_bounds__(256) void k_binning(int64_t total, uint32_t n, int TX,
-                                                 uint32_t tiles_per_cam,
-                                                 const uint32_t* __restrict__ order0,
-                                                 const uint32_t* __restrict__ order1,
-                                                 const uint32_t* __restrict__ passes,
-                                                 const uint4* __restrict__ meta,
-                                                 const uint32_t* __restrict__ counts,
-                                                 const uint32_t* __restrict__ offsets,
-                                                 uint32_t* __restrict__ keys,
-                                                 uint32_t* __restrict__ vals, int n_digits,
-                                                 uint32_t* __restrict__ hist, ClearSpans clear) {
+// Tile count of a rectangle (x0 | x_end << 16, y0 | y_end << 16); zero for a culled splat.
+__device__ __forceinline__ uint32_t rect_count(uint2 r) {
+  return ((r.x >> 16) - (r.x & 0xFFFFu)) * ((r.y >> 16) - (r.y & 0xFFFFu));
+}
+
+// Binning fused with the prefix sum that places it. Block b takes positions
+// [kBinPart b, kBinPart (b + 1)) of the depth order (kBinItems per thread): their tile counts, the
+// block's scan and a decoupled look-back (as in k_scan) give each position its offset. The block
+// then writes its keys in output order, kBinSlots slots per thread per step, consecutive threads
+// on consecutive slots (coalesced, and balanced whatever the splat sizes): a binary search over
+// the block's offsets finds the position whose rectangle holds slot p, and the slot's rank inside
+// that rectangle gives the tile (row-major). The keys' digits are counted in LDS and added to one
+// of kTileHistCopies copies.
+constexpr int kBinItems = 4;
+constexpr int kBinPart = kThreads * kBinItems;   // 1024 positions per block
+constexpr int kBinSlots = 4;                      // output slots searched together per thread
+
+__global__ __launch_bounds__(kThreads) void k_scan_bin(
+    int64_t total, uint32_t n, int TX, uint32_t tiles_per_cam, const uint32_t* __restrict__ order0,
+    const uint32_t* __restrict__ order1, const uint32_t* __restrict__ passes,
+    const uint2* __restrict__ rect, int64_t n_parts, uint64_t* __restrict__ status,
+    uint64_t* __restrict__ instances, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+    int n_digits, uint32_t* __restrict__ hist, ClearSpans clear) {
+  __shared__ uint32_t s_off[kBinPart];          // block-relative offset of each position
+  __shared__ uint32_t s_idx[kBinPart];          // its (camera, Gaussian) entry
+  __shared__ uint2 s_rect[kBinPart];
   __shared__ uint32_t sh[kTileHistPasses][kBins];
-  const int tid = threadIdx.x;
+  __shared__ uint64_t s_wave[kWaves];
+  __shared__ uint64_t s_excl;
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  clear_spans(clear, (int64_t)blockIdx.x * kThreads + tid, (int64_t)gridDim.x * kThreads);
   for (int d = 0; d < kTileHistPasses; ++d) sh[d][tid] = 0u;
-  const int64_t gsize = (int64_t)gridDim.x * blockDim.x;
-  clear_spans(clear, (int64_t)blockIdx.x * blockDim.x + tid, gsize);
-  __syncthreads();
+  const int64_t part = blockIdx.x;    // in-order dispatch: predecessors are running or done
+  const int64_t base = part * kBinPart + (int64_t)tid * kBinItems;
   const uint32_t* order = (*passes & 1u) ? order1 : order0;   // where the depth sort ended
-  // kBinItems positions per thread and step, all of their loads issued before any key is written
-  // (indices clamped so that the loads need no branch)
-  constexpr int kBinItems = 4;
-  for (int64_t j0 = (int64_t)blockIdx.x * blockDim.x + tid; j0 < total; j0 += kBinItems * gsize) {
-    uint32_t idx[kBinItems], cnt[kBinItems], off[kBinItems];
-    uint4 m[kBinItems];
+  uint32_t idx[kBinItems], cnt[kBinItems];
+  uint2 r[kBinItems];
 #pragma unroll
-    for (int k = 0; k < kBinItems; ++k) idx[k] = order[std::min<int64_t>(j0 + k * gsize, total - 1)];
+  for (int k = 0; k < kBinItems; ++k) idx[k] = base + k < total ? order[base + k] : 0u;
+#pragma unroll
+  for (int k = 0; k < kBinItems; ++k) {
+    r[k] = base + k < total ? rect[idx[k]] : make_uint2(0u, 0u);
+    cnt[k] = rect_count(r[k]);
+  }
+  uint64_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kBinItems; ++k) sum += cnt[k];
+  const uint64_t incl = wave_inclusive_scan64(sum);
+  if (lane == kWave - 1) s_wave[wave] = incl;
+  __syncthreads();
+  uint64_t wave_prefix = 0, block_total = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    if (w < wave) wave_prefix += s_wave[w];
+    block_total += s_wave[w];
+  }
+  {
+    uint32_t running = (uint32_t)(wave_prefix + incl - sum);
 #pragma unroll
     for (int k = 0; k < kBinItems; ++k) {
-      cnt[k] = counts[idx[k]];
-      m[k] = meta[idx[k]];
-      off[k] = offsets[std::min<int64_t>(j0 + k * gsize, total - 1)];
+      const int j = tid * kBinItems + k;
+      s_off[j] = running;
+      s_idx[j] = idx[k];
+      s_rect[j] = r[k];
+      running += cnt[k];
     }
+  }
+  if (wave == 0) {
+    uint64_t excl = 0;
+    if (part == 0) {
+      if (lane == 0) atomic_store_u64(&status[0], kScanPrefix | block_total);
+    } else {
+      if (lane == 0) atomic_store_u64(&status[part], kScanAgg | block_total);
+      int64_t p = part - 1;
+      uint32_t spins = 0;
+      while (true) {
+        const int64_t q = p - lane;
+        const uint64_t v = q >= 0 ? atomic_load_u64(&status[q]) : kScanPrefix;
+        const uint64_t flag = v & ~kScanValue;
+        const uint64_t pre = __ballot(flag == kScanPrefix);
+        const uint64_t zero = __ballot(flag == 0);
+        const int first = pre ? __ffsll((unsigned long long)pre) - 1 : kWave;
+        const uint64_t need = first < kWave ? (first == 63 ? ~0ull : ((2ull << first) - 1)) : ~0ull;
+        // a predecessor has not published yet; the bound only guards against a broken launch
+        if ((zero & need) && ++spins < kSpinLimit) continue;
+        excl += wave_sum_u64(lane <= first ? (v & kScanValue) : 0ull);
+        if (first < kWave) break;
+        p -= kWave;
+      }
+      if (lane == 0) atomic_store_u64(&status[part], kScanPrefix | (excl + block_total));
+    }
+    if (lane == 0) s_excl = excl;
+  }
+  __syncthreads();
+  const uint64_t out0 = s_excl;
+  const uint32_t bt = (uint32_t)block_total;
+  for (uint32_t p0 = tid; p0 < bt; p0 += kThreads * kBinSlots) {
+    // per slot: the last position whose offset is <= p (offsets never decrease, and that
+    // position's count is > 0); the kBinSlots searches run interleaved
+    int j[kBinSlots];
 #pragma unroll
-    for (int k = 0; k < kBinItems; ++k) {
-      if (j0 + k * gsize >= total || cnt[k] == 0) continue;
-      const uint32_t cam = idx[k] / n;
-      const uint32_t g = idx[k] - cam * n;
-      const int x0 = m[k].y & 0xFFFF, x1 = m[k].y >> 16, y0 = m[k].z & 0xFFFF, y1 = m[k].z >> 16;
-      uint32_t o = off[k];
-      const uint32_t cam_base = cam * tiles_per_cam;
-      for (int ty = y0; ty <= y1; ++ty)
-        for (int tx = x0; tx <= x1; ++tx) {
-          const uint32_t key = cam_base + (uint32_t)(ty * TX + tx);
-          keys[o] = key;
-          vals[o] = g;
-          ++o;
-          for (int d = 0; d < n_digits; ++d) atomicAdd(&sh[d][(key >> (8 * d)) & 0xFF], 1u);
-        }
+    for (int t = 0; t < kBinSlots; ++t) j[t] = 0;
+#pragma unroll
+    for (int step = kBinPart / 2; step >= 1; step >>= 1)
+#pragma unroll
+      for (int t = 0; t < kBinSlots; ++t)
+        if (s_off[j[t] + step] <= p0 + t * kThreads) j[t] += step;
+#pragma unroll
+    for (int t = 0; t < kBinSlots; ++t) {
+      const uint32_t p = p0 + t * kThreads;
+      if (p >= bt) break;
+      const uint32_t local = p - s_off[j[t]];
+      const uint2 rr = s_rect[j[t]];
+      const uint32_t x0 = rr.x & 0xFFFFu, w = (rr.x >> 16) - x0, y0 = rr.y & 0xFFFFu;
+      const uint32_t dy = local / w, dx = local - dy * w;
+      const uint32_t i = s_idx[j[t]];
+      const uint32_t cam = i / n;
+      const uint32_t key = cam * tiles_per_cam + (y0 + dy) * (uint32_t)TX + x0 + dx;
+      keys[out0 + p] = key;
+      vals[out0 + p] = i - cam * n;
+      for (int d = 0; d < n_digits; ++d) atomicAdd(&sh[d][(key >> (8 * d)) & 0xFF], 1u);
     }
   }
   __syncthreads();
-  // blocks spread their sums over kTileHistCopies copies (blocks of a copy share an XCD), which
-  // keeps each counter's chain of atomics short
   uint32_t* h = hist + (blockIdx.x % kTileHistCopies) * (kTileHistPasses * kBins);
   for (int d = 0; d < n_digits; ++d) {
     const uint32_t v = sh[d][tid];
     if (v) atomicAdd(&h[d * kBins + tid], v);
   }
+  if (part == n_parts - 1 && tid == 0) *instances = out0 + block_total;
 }
 
 // ---- radix sort -----------------------------------------------------------------------------
@@ -274,8 +342,7 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, 
 // bits of its depth above the frame's minimum, or all ones for a culled splat; its value is j).
 // The depth-bit range comes from the projection's slots; block 0 also records the pass count.
 // The histograms of the four 8-bit digits go to hist[4][256] (zeroed beforehand).
-__global__ __launch_bounds__(256) void k_depth_keys_hist(int64_t m, const uint4* __restrict__ meta,
-                                                         const uint32_t* __restrict__ counts,
+__global__ __launch_bounds__(256) void k_depth_keys_hist(int64_t m, const uint32_t* __restrict__ zbits,
                                                          const uint32_t* __restrict__ zrange,
                                                          uint32_t* __restrict__ info,
                                                          uint32_t* __restrict__ keys,
@@ -306,12 +373,11 @@ __global__ __launch_bounds__(256) void k_depth_keys_hist(int64_t m, const uint4*
   const uint64_t lt_mask = lanemask_lt();
   for (int64_t part = blockIdx.x; part * kPart < m; part += gridDim.x) {
     const int64_t wbase = part * kPart + (int64_t)wave * (kWave * kItems);
-    uint32_t zb[kItems], c[kItems];
+    uint32_t zb[kItems];
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
       const int64_t pos = wbase + (int64_t)it * kWave + lane;
-      zb[it] = pos < m ? meta[pos].x : 0u;
-      c[it] = pos < m ? counts[pos] : 0u;
+      zb[it] = pos < m ? zbits[pos] : 0u;
     }
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
@@ -319,7 +385,7 @@ __global__ __launch_bounds__(256) void k_depth_keys_hist(int64_t m, const uint4*
       const bool valid = pos < m;
       const uint64_t vmask = __ballot(valid);
       if (vmask == 0) break;
-      const uint32_t k = c[it] ? zb[it] - zmin : ~0u;
+      const uint32_t k = zb[it] ? zb[it] - zmin : ~0u;        // zero bits: culled
       if (valid) { keys[pos] = k; vals[pos] = (uint32_t)pos; }
 #pragma unroll
       for (int p = 0; p < kDigits - 1; ++p)            // lower digits: one atomic per key
@@ -626,11 +692,12 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
 
 // ---- host launchers -------------------------------------------------------------------------
 size_t scan_scratch_bytes(int64_t n) {
-  const int64_t parts = (n + kPart - 1) / kPart;
+  const int64_t parts = (n + kBinPart - 1) / kBinPart;     // kBinPart <= kPart: covers both scans
   return (size_t)(parts + 1) * sizeof(uint64_t) + 256;
 }
 
-int64_t scan_clear_words(int64_t n) { return (n + kPart - 1) / kPart * 2; }
+// (the fused binning scan uses partitions of kBinPart <= kPart positions: counted in those)
+int64_t scan_clear_words(int64_t n) { return (n + kBinPart - 1) / kBinPart * 2; }
 
 hipError_t launch_scan(const uint32_t* in, const uint32_t* gather0, const uint32_t* gather1,
                        const uint32_t* sel, uint32_t* out, int64_t n, uint64_t* total, void* scratch,
@@ -646,29 +713,29 @@ hipError_t launch_scan(const uint32_t* in, const uint32_t* gather0, const uint32
   return hipGetLastError();
 }
 
-hipError_t launch_depth_keys_hist(int64_t m, const uint4* meta, const uint32_t* counts,
-                                  const uint32_t* zrange, uint32_t* info, uint32_t* keys, uint32_t* vals,
-                                  void* sort_scratch, hipStream_t s) {
+hipError_t launch_depth_keys_hist(int64_t m, const uint32_t* zbits, const uint32_t* zrange,
+                                  uint32_t* info, uint32_t* keys, uint32_t* vals, void* sort_scratch,
+                                  hipStream_t s) {
   if (m == 0) return hipSuccess;
   const unsigned blocks = (unsigned)std::min<int64_t>(kHistBlocks, (m + kPart - 1) / kPart);
-  hipLaunchKernelGGL(k_depth_keys_hist, dim3(blocks), dim3(256), 0, s, m, meta, counts, zrange, info, keys,
+  hipLaunchKernelGGL(k_depth_keys_hist, dim3(blocks), dim3(256), 0, s, m, zbits, zrange, info, keys,
                      vals, reinterpret_cast<uint32_t*>(sort_scratch));
   return hipGetLastError();
 }
 
-hipError_t launch_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_cam, const uint32_t* order0,
-                          const uint32_t* order1, const uint32_t* passes, const uint4* meta,
-                          const uint32_t* counts, const uint32_t* offsets, uint32_t* keys,
-                          uint32_t* vals, int tile_bits, uint32_t* hist, const ClearSpans& clear,
-                          hipStream_t s) {
-  const int64_t total = n * n_cams;
-  if (total == 0) return hipSuccess;
+hipError_t launch_scan_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_cam,
+                               const uint32_t* order0, const uint32_t* order1,
+                               const uint32_t* passes, const uint2* rect, void* scan_scratch,
+                               uint64_t* total, uint32_t* keys, uint32_t* vals, int tile_bits,
+                               uint32_t* hist, const ClearSpans& clear, hipStream_t s) {
+  const int64_t cn = n * n_cams;
+  if (cn == 0) return hipSuccess;
   if (tile_bits > 8 * kTileHistPasses) return hipErrorInvalidValue;
-  // a bounded grid keeps the per-block histogram flushes few
-  const unsigned blocks = (unsigned)std::min<int64_t>(1024, blocks_for(total, 256));
-  hipLaunchKernelGGL(k_binning, dim3(blocks), dim3(256), 0, s, total, (uint32_t)n, TX,
-                     (uint32_t)tiles_per_cam, order0, order1, passes, meta, counts, offsets, keys, vals,
-                     (tile_bits + 7) / 8, hist, clear);
+  const int64_t parts = (cn + kBinPart - 1) / kBinPart;
+  hipLaunchKernelGGL(k_scan_bin, dim3((unsigned)parts), dim3(kThreads), 0, s, cn, (uint32_t)n, TX,
+                     (uint32_t)tiles_per_cam, order0, order1, passes, rect, parts,
+                     reinterpret_cast<uint64_t*>(scan_scratch), total, keys, vals, (tile_bits + 7) / 8,
+                     hist, clear);
   return hipGetLastError();
 }
 
