@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <chrono>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -98,9 +99,10 @@ struct pcs_context {
   DevBuf dkeys, dkeys_alt, dvals, dvals_alt, dsort_scratch;   // depth sort of the splats
   DevBuf knn_scratch, conv_tmp, wt_tmp, shade_cams, tile_hist;
   uint32_t* host_small = nullptr;   // pinned 4 KiB: readback of the small device words
-  hipEvent_t counts_ready = nullptr;  // recorded after the instance-count read-back
-  hipEvent_t proj_done = nullptr;     // recorded after the projection, for the read-back stream
-  hipStream_t aux = nullptr;          // the read-back's own stream (default priority)
+  // pinned, coherent host word that the depth-key kernel sets to seq << 32 | instance total
+  unsigned long long* host_word = nullptr;
+  unsigned long long* host_word_dev = nullptr;   // its device address
+  uint32_t seq = 0;                              // frame sequence number (never 0 once used)
   pcs_state* internal = nullptr;    // state used when the caller passes none
   bool timing = false;
   uint32_t stage_mask = ~0u;        // stages whose launches are timed
@@ -188,6 +190,34 @@ int check_options(const pcs_options& o) {
   return PCS_OK;
 }
 
+// Polls the pinned word until it carries this frame's sequence number. After the first
+// millisecond the stream is queried every 100 microseconds (a query is not free: it is kept off
+// the common path), so a failed launch or a stream that drained without the store is an error
+// instead of a hang.
+int wait_instance_total(pcs_context* ctx, hipStream_t s, uint64_t* total) {
+  volatile unsigned long long* w = ctx->host_word;
+  using clock = std::chrono::steady_clock;
+  auto next_query = clock::now() + std::chrono::milliseconds(1);
+  for (uint64_t it = 1;; ++it) {
+    const unsigned long long v = *w;
+    if ((uint32_t)(v >> 32) == ctx->seq) {
+      *total = v & 0xFFFFFFFFull;
+      return PCS_OK;
+    }
+    if ((it & 255) == 0 && clock::now() >= next_query) {
+      next_query = clock::now() + std::chrono::microseconds(100);
+      const hipError_t q = hipStreamQuery(s);
+      if (q == hipSuccess) {
+        const unsigned long long v2 = *w;
+        if ((uint32_t)(v2 >> 32) != ctx->seq) return fail(PCS_ERR_HIP, "instance total not delivered");
+        *total = v2 & 0xFFFFFFFFull;
+        return PCS_OK;
+      }
+      if (q != hipErrorNotReady) return fail(PCS_ERR_HIP, std::string("stream error: ") + hipGetErrorString(q));
+    }
+  }
+}
+
 int check_gaussians(const pcs_gaussians* g) {
   if (!g) return fail(PCS_ERR_INVALID_ARG, "gaussians is NULL");
   if (g->n < 0) return fail(PCS_ERR_INVALID_ARG, "gaussian count is negative");
@@ -230,12 +260,19 @@ int pcs_context_create(int device, pcs_context** out) {
     return fail(PCS_ERR_OOM, "pinned host allocation failed");
   }
   ctx->host_small = reinterpret_cast<uint32_t*>(hp);
-  if (hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&ctx->counts_ready, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&ctx->proj_done, hipEventDisableTiming) != hipSuccess) {
+  void* hw = nullptr;
+  void* hw_dev = nullptr;
+  if (hipHostMalloc(&hw, 64, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
     pcs_context_destroy(ctx);
-    return fail(PCS_ERR_HIP, "stream or event creation failed");
+    return fail(PCS_ERR_OOM, "pinned host allocation failed");
   }
+  ctx->host_word = reinterpret_cast<unsigned long long*>(hw);
+  *ctx->host_word = 0ull;
+  if (hipHostGetDevicePointer(&hw_dev, hw, 0) != hipSuccess) {
+    pcs_context_destroy(ctx);
+    return fail(PCS_ERR_HIP, "no device address for the pinned host word");
+  }
+  ctx->host_word_dev = reinterpret_cast<unsigned long long*>(hw_dev);
   *out = ctx;
   return PCS_OK;
 }
@@ -252,9 +289,7 @@ void pcs_context_destroy(pcs_context* ctx) {
   }
   delete ctx->internal;
   if (ctx->host_small) (void)hipHostFree(ctx->host_small);
-  if (ctx->counts_ready) (void)hipEventDestroy(ctx->counts_ready);
-  if (ctx->proj_done) (void)hipEventDestroy(ctx->proj_done);
-  if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
+  if (ctx->host_word) (void)hipHostFree(ctx->host_word);
   delete ctx;
 }
 
@@ -380,34 +415,24 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
     PCS_HIP(launch_project(n, n_cams, st->dcams.as<DevCamera>(), dopt, *g, st->rec.as<float4>(),
                            ctx->zbits.as<uint32_t>(), ctx->rect.as<uint2>(), d_zrange, d_counts, clear, s));
   }
-  // The instance total goes to the host right after the projection; the (camera, depth) order
-  // needs nothing from the host (the depth range is read from the projection's slots on the
-  // device, and sort passes beyond the bits that range needs return at once), so it is queued at
-  // once and the host waits only for the read-back: it sizes the tile buffers while the GPU sorts
-  // by depth. The read-back runs on its own stream, so the depth sort does not wait for the copy.
-  // It reads only the count slots, which nothing on the frame's stream writes again before the
-  // host has waited for the copy.
-  PCS_HIP(hipEventRecord(ctx->proj_done, s));
-  PCS_HIP(hipStreamWaitEvent(ctx->aux, ctx->proj_done, 0));
-  PCS_HIP(hipMemcpyAsync(ctx->host_small + kCountWord, ctx->small.as<uint32_t>() + kCountWord,
-                         2 * kZSlots * sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->aux));
-  PCS_HIP(hipEventRecord(ctx->counts_ready, ctx->aux));
+  // The instance total reaches the host from the first depth-sort kernel (a store into a pinned
+  // word, which the host polls); the (camera, depth) order needs nothing from the host (the depth
+  // range is read from the projection's slots on the device, and sort passes beyond the bits that
+  // range needs return at once), so it is all queued at once and the host sizes the tile buffers
+  // while the GPU sorts by depth.
+  ctx->seq = ctx->seq + 1 == 0 ? 1 : ctx->seq + 1;
   if (cn > 0) {
     StageTimer tm(ctx, ST_SORT, s);
     bool unused = false;
-    PCS_HIP(launch_depth_keys_hist(cn, ctx->zbits.as<uint32_t>(), d_zrange, d_depth, ctx->dkeys.as<uint32_t>(),
-                                   ctx->dvals.as<uint32_t>(), ctx->dsort_scratch.p, s));
+    PCS_HIP(launch_depth_keys_hist(cn, ctx->zbits.as<uint32_t>(), d_counts, ctx->host_word_dev, ctx->seq,
+                                   d_zrange, d_depth, ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(),
+                                   ctx->dsort_scratch.p, s));
     PCS_HIP(launch_sort(ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(), ctx->dkeys_alt.as<uint32_t>(),
                         ctx->dvals_alt.as<uint32_t>(), cn, 32, ctx->dsort_scratch.p, s, &unused, d_depth,
                         true, true));
   }
-  PCS_HIP(hipEventSynchronize(ctx->counts_ready));
   uint64_t m64 = 0;
-  for (int i = 0; i < kZSlots; ++i) {
-    uint64_t c;
-    std::memcpy(&c, ctx->host_small + kCountWord + 2 * i, 8);
-    m64 += c;
-  }
+  if (cn > 0) PCS_TRY(wait_instance_total(ctx, s, &m64));
   if (m64 >= (uint64_t(1) << 30))
     return fail(PCS_ERR_UNSUPPORTED, "instance count " + std::to_string(m64) + " is not below 2^30");
   const int64_t m = (int64_t)m64;

@@ -163,8 +163,12 @@ int64_t scan_clear_words(int64_t n);
 // Depth key per (camera, Gaussian) entry and its index as the value, and the keys' four digit
 // histograms into the sort scratch's histogram area (zeroed beforehand), for a launch_sort with
 // hist_ready. The depth-bit range comes from the projection's slots on the device; info[0..3)
-// receives the pass count, depth bits and minimum depth bits.
-hipError_t launch_depth_keys_hist(int64_t m, const uint32_t* zbits, const uint32_t* zrange,
+// receives the pass count, depth bits and minimum depth bits. The sum of the projection's
+// kZSlots count slots goes to *host_word (pinned, coherent host memory) as seq << 32 | total,
+// the total capped at 2^32 - 1.
+hipError_t launch_depth_keys_hist(int64_t m, const uint32_t* zbits,
+                                  const unsigned long long* count_slots,
+                                  unsigned long long* host_word, uint32_t seq, const uint32_t* zrange,
                                   uint32_t* info, uint32_t* keys, uint32_t* vals, void* sort_scratch,
                                   hipStream_t s);
 

@@ -343,6 +343,9 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, 
 // The depth-bit range comes from the projection's slots; block 0 also records the pass count.
 // The histograms of the four 8-bit digits go to hist[4][256] (zeroed beforehand).
 __global__ __launch_bounds__(256) void k_depth_keys_hist(int64_t m, const uint32_t* __restrict__ zbits,
+                                                         const unsigned long long* __restrict__ count_slots,
+                                                         unsigned long long* __restrict__ host_word,
+                                                         uint32_t seq,
                                                          const uint32_t* __restrict__ zrange,
                                                          uint32_t* __restrict__ info,
                                                          uint32_t* __restrict__ keys,
@@ -364,6 +367,16 @@ __global__ __launch_bounds__(256) void k_depth_keys_hist(int64_t m, const uint32
   }
   __syncthreads();
   const uint32_t zmin = s_z[0], zmax = s_z[1];
+  // block 0 also sends the instance total (the projection's count slots) to the host's pinned
+  // word with the frame's sequence number: one system-scope store, which the host polls
+  if (blockIdx.x == 0 && wave == 0) {
+    unsigned long long c = count_slots[lane];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, kWave);
+    if (lane == 0)
+      __hip_atomic_store(host_word, ((unsigned long long)seq << 32) | (c < 0xFFFFFFFFull ? c : 0xFFFFFFFFull),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
   if (blockIdx.x == 0 && tid == 0) {
     const int depth_bits = zmax > zmin ? 32 - __clz(zmax - zmin) : 0;
     info[0] = (uint32_t)((depth_bits + 7) / 8);          // passes the depth sort needs
@@ -713,13 +726,16 @@ hipError_t launch_scan(const uint32_t* in, const uint32_t* gather0, const uint32
   return hipGetLastError();
 }
 
-hipError_t launch_depth_keys_hist(int64_t m, const uint32_t* zbits, const uint32_t* zrange,
+hipError_t launch_depth_keys_hist(int64_t m, const uint32_t* zbits,
+                                  const unsigned long long* count_slots,
+                                  unsigned long long* host_word, uint32_t seq, const uint32_t* zrange,
                                   uint32_t* info, uint32_t* keys, uint32_t* vals, void* sort_scratch,
                                   hipStream_t s) {
   if (m == 0) return hipSuccess;
+  static_assert(kZSlots == kWave, "one count slot per lane");
   const unsigned blocks = (unsigned)std::min<int64_t>(kHistBlocks, (m + kPart - 1) / kPart);
-  hipLaunchKernelGGL(k_depth_keys_hist, dim3(blocks), dim3(256), 0, s, m, zbits, zrange, info, keys,
-                     vals, reinterpret_cast<uint32_t*>(sort_scratch));
+  hipLaunchKernelGGL(k_depth_keys_hist, dim3(blocks), dim3(256), 0, s, m, zbits, count_slots, host_word,
+                     seq, zrange, info, keys, vals, reinterpret_cast<uint32_t*>(sort_scratch));
   return hipGetLastError();
 }
 
