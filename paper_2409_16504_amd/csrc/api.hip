@@ -190,30 +190,36 @@ int check_options(const pcs_options& o) {
   return PCS_OK;
 }
 
-// Polls the pinned word until it carries this frame's sequence number. After the first
-// millisecond the stream is queried every 100 microseconds (a query is not free: it is kept off
-// the common path), so a failed launch or a stream that drained without the store is an error
-// instead of a hang.
-int wait_instance_total(pcs_context* ctx, hipStream_t s, uint64_t* total) {
+// Polls the two pinned words until both carry this frame's sequence number (word 0: instance
+// total, word 1: depth bits). After the first millisecond the stream is queried every 100
+// microseconds (a query is not free: it is kept off the common path), so a failed launch or a
+// stream that drained without the stores is an error instead of a hang.
+int wait_frame_words(pcs_context* ctx, hipStream_t s, uint64_t* total, int* depth_bits) {
   volatile unsigned long long* w = ctx->host_word;
   using clock = std::chrono::steady_clock;
   auto next_query = clock::now() + std::chrono::milliseconds(1);
+  auto ready = [&](unsigned long long a, unsigned long long b) {
+    return (uint32_t)(a >> 32) == ctx->seq && (uint32_t)(b >> 32) == ctx->seq;
+  };
   for (uint64_t it = 1;; ++it) {
-    const unsigned long long v = *w;
-    if ((uint32_t)(v >> 32) == ctx->seq) {
-      *total = v & 0xFFFFFFFFull;
-      return PCS_OK;
-    }
-    if ((it & 255) == 0 && clock::now() >= next_query) {
+    unsigned long long a = w[0], b = w[1];
+    bool ok = ready(a, b);
+    if (!ok && (it & 255) == 0 && clock::now() >= next_query) {
       next_query = clock::now() + std::chrono::microseconds(100);
       const hipError_t q = hipStreamQuery(s);
+      if (q != hipSuccess && q != hipErrorNotReady)
+        return fail(PCS_ERR_HIP, std::string("stream error: ") + hipGetErrorString(q));
       if (q == hipSuccess) {
-        const unsigned long long v2 = *w;
-        if ((uint32_t)(v2 >> 32) != ctx->seq) return fail(PCS_ERR_HIP, "instance total not delivered");
-        *total = v2 & 0xFFFFFFFFull;
-        return PCS_OK;
+        a = w[0];
+        b = w[1];
+        if (!ready(a, b)) return fail(PCS_ERR_HIP, "instance total not delivered");
+        ok = true;
       }
-      if (q != hipErrorNotReady) return fail(PCS_ERR_HIP, std::string("stream error: ") + hipGetErrorString(q));
+    }
+    if (ok) {
+      *total = a & 0xFFFFFFFFull;
+      *depth_bits = (int)(b & 0xFFFFFFFFull);
+      return PCS_OK;
     }
   }
 }
@@ -267,7 +273,7 @@ int pcs_context_create(int device, pcs_context** out) {
     return fail(PCS_ERR_OOM, "pinned host allocation failed");
   }
   ctx->host_word = reinterpret_cast<unsigned long long*>(hw);
-  *ctx->host_word = 0ull;
+  ctx->host_word[0] = ctx->host_word[1] = 0ull;
   if (hipHostGetDevicePointer(&hw_dev, hw, 0) != hipSuccess) {
     pcs_context_destroy(ctx);
     return fail(PCS_ERR_HIP, "no device address for the pinned host word");
@@ -427,12 +433,25 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
     PCS_HIP(launch_depth_keys_hist(cn, ctx->zbits.as<uint32_t>(), d_counts, ctx->host_word_dev, ctx->seq,
                                    d_zrange, d_depth, ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(),
                                    ctx->dsort_scratch.p, s));
+    // the first pass now (it returns at once if the depths need none), the others once the host
+    // knows how many the depth range needs
     PCS_HIP(launch_sort(ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(), ctx->dkeys_alt.as<uint32_t>(),
                         ctx->dvals_alt.as<uint32_t>(), cn, 32, ctx->dsort_scratch.p, s, &unused, d_depth,
-                        true, true));
+                        true, true, nullptr, 0, 1));
   }
   uint64_t m64 = 0;
-  if (cn > 0) PCS_TRY(wait_instance_total(ctx, s, &m64));
+  if (cn > 0) {
+    int depth_bits = 0;
+    PCS_TRY(wait_frame_words(ctx, s, &m64, &depth_bits));
+    const int depth_passes = (depth_bits + 7) / 8;
+    if (depth_passes > 1) {
+      StageTimer tm(ctx, ST_SORT, s);
+      bool unused = false;
+      PCS_HIP(launch_sort(ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(), ctx->dkeys_alt.as<uint32_t>(),
+                          ctx->dvals_alt.as<uint32_t>(), cn, 32, ctx->dsort_scratch.p, s, &unused, d_depth,
+                          true, true, nullptr, 1, depth_passes));
+    }
+  }
   if (m64 >= (uint64_t(1) << 30))
     return fail(PCS_ERR_UNSUPPORTED, "instance count " + std::to_string(m64) + " is not below 2^30");
   const int64_t m = (int64_t)m64;

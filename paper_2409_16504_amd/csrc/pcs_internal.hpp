@@ -164,8 +164,8 @@ int64_t scan_clear_words(int64_t n);
 // histograms into the sort scratch's histogram area (zeroed beforehand), for a launch_sort with
 // hist_ready. The depth-bit range comes from the projection's slots on the device; info[0..3)
 // receives the pass count, depth bits and minimum depth bits. The sum of the projection's
-// kZSlots count slots goes to *host_word (pinned, coherent host memory) as seq << 32 | total,
-// the total capped at 2^32 - 1.
+// kZSlots count slots goes to host_word[0] (pinned, coherent host memory) as seq << 32 | total,
+// the total capped at 2^32 - 1, and the depth bits to host_word[1] as seq << 32 | bits.
 hipError_t launch_depth_keys_hist(int64_t m, const uint32_t* zbits,
                                   const unsigned long long* count_slots,
                                   unsigned long long* host_word, uint32_t seq, const uint32_t* zrange,
@@ -197,11 +197,13 @@ hipError_t launch_scan_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_
 size_t sort_scratch_bytes(int64_t m);
 // live_passes (device, may be null): passes at or beyond *live_passes return at once, so the data
 // ends in (k1,v1) when *live_passes is odd; *result_in_alt then describes the host's pass count.
+// [pass_begin, pass_end) launches only those passes (pass_end < 0: all): a sort may be launched in
+// pieces on one stream, the set-up (clear, histogram) going with the piece that starts at pass 0.
 template <typename K>
 hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int bits, void* scratch,
                        hipStream_t s, bool* result_in_alt, const uint32_t* live_passes = nullptr,
                        bool scratch_cleared = false, bool hist_ready = false,
-                       const uint32_t* ext_hist = nullptr);
+                       const uint32_t* ext_hist = nullptr, int pass_begin = 0, int pass_end = -1);
 // Words at the start of sort scratch that must be zero before a sort of m pairs (cleared by the
 // sort itself unless the caller has cleared them and says so).
 int64_t sort_clear_words(int64_t m);

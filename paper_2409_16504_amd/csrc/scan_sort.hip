@@ -382,6 +382,9 @@ __global__ __launch_bounds__(256) void k_depth_keys_hist(int64_t m, const uint32
     info[0] = (uint32_t)((depth_bits + 7) / 8);          // passes the depth sort needs
     info[1] = (uint32_t)depth_bits;
     info[2] = zmin;
+    // the host launches only the passes after the first that the depth range needs
+    __hip_atomic_store(host_word + 1, ((unsigned long long)seq << 32) | (unsigned)depth_bits,
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
   const uint64_t lt_mask = lanemask_lt();
   for (int64_t part = blockIdx.x; part * kPart < m; part += gridDim.x) {
@@ -779,10 +782,12 @@ int64_t sort_clear_words(int64_t m) {
 template <typename K>
 hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int bits, void* scratch,
                        hipStream_t s, bool* result_in_alt, const uint32_t* live_passes,
-                       bool scratch_cleared, bool hist_ready, const uint32_t* ext_hist) {
+                       bool scratch_cleared, bool hist_ready, const uint32_t* ext_hist,
+                       int pass_begin, int pass_end) {
   *result_in_alt = false;
   if (m <= 1 || bits <= 0) return hipSuccess;
   const int n_passes = (bits + 7) / 8;
+  if (pass_end < 0 || pass_end > n_passes) pass_end = n_passes;
   const int64_t parts = (m + kPart - 1) / kPart;    // partitions of the histogram
   constexpr int kSweepThreads = SweepShape<K>::threads;
   constexpr int kSweepItems = SweepShape<K>::items;
@@ -793,10 +798,12 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
   uint32_t* hist = reinterpret_cast<uint32_t*>(scratch);
   uint32_t* status0 = hist + kMaxPasses * kBins;
   uint32_t* status1 = status0 + sweep_parts * kBins;
-  hipError_t e = scratch_cleared ? hipSuccess : launch_fill_u32(hist, 0u, kMaxPasses * kBins + sweep_parts * kBins, s);
+  hipError_t e = (scratch_cleared || pass_begin > 0)
+                     ? hipSuccess
+                     : launch_fill_u32(hist, 0u, kMaxPasses * kBins + sweep_parts * kBins, s);
   if (e != hipSuccess) return e;
   const int hblocks = (int)std::min<int64_t>(kHistBlocks, parts);
-  if (!hist_ready && !ext_hist) {
+  if (!hist_ready && !ext_hist && pass_begin == 0) {
     hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)hblocks), dim3(256), 0, s, k0, m, n_passes, hist);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
@@ -805,7 +812,11 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
   const int64_t copy_stride = ext_hist ? (int64_t)kTileHistPasses * kBins : 0;
   K *ki = k0, *ko = k1;
   uint32_t *vi = v0, *vo = v1;
-  for (int p = 0; p < n_passes; ++p) {
+  if (pass_begin & 1) {
+    std::swap(ki, ko);
+    std::swap(vi, vo);
+  }
+  for (int p = pass_begin; p < pass_end; ++p) {
     uint32_t* st = (p & 1) ? status1 : status0;
     uint32_t* st_next = (p & 1) ? status0 : status1;
     hipLaunchKernelGGL((k_onesweep<K, kSweepThreads, kSweepItems>), dim3((unsigned)sweep_parts), dim3(kSweepThreads), 0, s, ki, vi, ko, vo, m,
@@ -814,15 +825,15 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
     std::swap(ki, ko);
     std::swap(vi, vo);
   }
-  *result_in_alt = (n_passes % 2) == 1;
+  *result_in_alt = (pass_end % 2) == 1;
   return hipSuccess;
 }
 template hipError_t launch_sort<uint32_t>(uint32_t*, uint32_t*, uint32_t*, uint32_t*, int64_t, int,
                                           void*, hipStream_t, bool*, const uint32_t*, bool, bool,
-                                          const uint32_t*);
+                                          const uint32_t*, int, int);
 template hipError_t launch_sort<uint64_t>(uint64_t*, uint32_t*, uint64_t*, uint32_t*, int64_t, int,
                                           void*, hipStream_t, bool*, const uint32_t*, bool, bool,
-                                          const uint32_t*);
+                                          const uint32_t*, int, int);
 
 hipError_t launch_ranges(const uint32_t* keys, int64_t m, int64_t n_tiles, uint32_t* ranges,
                          hipStream_t s) {
