@@ -73,7 +73,7 @@ typedef struct pcs_gaussians {
  *   sigma_cut 3    splat boundary at sigma_cut standard deviations (Section 3.1)
  *   alpha_min 1/255, alpha_max 0.99, t_eps 1e-4: a splat is skipped where alpha < alpha_min,
  *                  alpha is clamped to alpha_max, blending of a pixel stops after the splat that
- *                  takes its transmittance below t_eps
+ *                  takes its transmittance below t_eps (0 <= t_eps <= 1)
  *   bg[3] 0        background colour added with the final transmittance (RGB only) */
 typedef struct pcs_options {
   float z_near, lowpass, sigma_cut, alpha_min, alpha_max, t_eps;

@@ -183,10 +183,10 @@ int check_options(const pcs_options& o) {
   for (float x : v)
     if (!std::isfinite(x)) return fail(PCS_ERR_INVALID_ARG, "options must be finite");
   if (o.z_near <= 0.0f || o.sigma_cut <= 0.0f || o.lowpass < 0.0f || o.alpha_max <= 0.0f ||
-      o.alpha_max >= 1.0f || o.alpha_min < 0.0f || o.t_eps < 0.0f)
+      o.alpha_max >= 1.0f || o.alpha_min < 0.0f || o.t_eps < 0.0f || o.t_eps > 1.0f)
     return fail(PCS_ERR_INVALID_ARG,
                 "options out of range (need z_near > 0, sigma_cut > 0, lowpass >= 0, "
-                "0 < alpha_max < 1, alpha_min >= 0, t_eps >= 0)");
+                "0 < alpha_max < 1, alpha_min >= 0, 0 <= t_eps <= 1)");
   return PCS_OK;
 }
 

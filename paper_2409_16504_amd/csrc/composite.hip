@@ -137,12 +137,12 @@ __global__ __launch_bounds__(kWave) void k_composite(
   const float l2amin = opt.alpha_max < opt.alpha_min ? __builtin_inff() : __log2f(opt.alpha_min);
   const float4* rec_cam = rec + cam * n * kRecFloat4;
   const uint64_t lt = lanemask_lt();
-  // T and the sums run until the pixel's stop; a stopped pixel keeps its T and last contributor
-  // in t_stop / last_stop and continues with T = 0, which leaves the sums as they are
-  float T = 1.0f, t_stop = 0.0f;
+  // A pixel blends while T >= t_eps (t_eps <= 1, so it starts blending): the blend that takes T
+  // below t_eps is its last, and after it T, the sums and the last contributor stay as they are.
+  // Pixels outside the image start at T = 0 and never blend.
+  float T = inside ? 1.0f : 0.0f;
   float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f, acc4 = 0.f, acc5 = 0.f, acc6 = 0.f;
-  int32_t last = 0, last_stop = 0;
-  uint64_t done = __ballot(!inside);                 // stopped pixels (wave-uniform)
+  int32_t last = 0;
   // one record per lane; the next batch's records and the batch after's splat indices travel in
   // registers while the current batch is composited, so each batch waits on one round trip. The
   // loads are unconditional (positions past the list re-read its last entry; the position test
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(kWave) void k_composite(
     vnext = vals[min(start + kWave + lane, lastpos)];
   }
   for (uint32_t b = start; b < end; b += kWave) {
-    const uint64_t live = ~done;
+    const uint64_t live = __ballot(T >= opt.t_eps);
     if (live == 0ull) break;                          // every pixel of the quadrant is done
     // keep the records whose padded ellipse box reaches a pixel that is still blending, compacted
     // in list order; the live pixels' bounding rectangle comes from the stop mask (lane = 8 y + x):
@@ -206,13 +206,13 @@ __global__ __launch_bounds__(kWave) void k_composite(
         const float a = fminf(amax, __builtin_amdgcn_exp2f(sq + f1.y));
         aa[j] = sq >= f1.z ? a : -0.0f;               // -0: no blend, and w = -0 says so
       }
-      // blends in list order without branches: a record that does not blend has a = -0, which
-      // leaves T and the sums as they are; w >= +0 marks a blend (T > 0 while blending, T = 0
-      // after the stop, where last no longer matters)
+      // blends in list order without branches: a record that does not blend, or a pixel that
+      // has stopped, gives w = -0, which leaves T and the sums as they are; w >= +0 marks a blend
 #pragma unroll
       for (int j = 0; j < kGroup; ++j) {
         const float a = aa[j];
-        const float w = a * T;
+        const bool go = T >= opt.t_eps;
+        const float w = go ? a * T : -0.0f;
         acc0 = fmaf(w, c2[j].x, acc0);
         acc1 = fmaf(w, c2[j].y, acc1);
         acc2 = fmaf(w, c2[j].z, acc2);
@@ -220,21 +220,14 @@ __global__ __launch_bounds__(kWave) void k_composite(
         acc4 = fmaf(w, c3[j].y, acc4);
         acc5 = fmaf(w, c3[j].z, acc5);
         acc6 = fmaf(w, zz[j], acc6);
-        T = T * (1.0f - a);
+        T = go ? T * (1.0f - a) : T;
         const bool blended = __builtin_amdgcn_classf(w, 0x3C0);   // +0, +denormal, +normal, +inf
         last = blended ? __float_as_int(c2[j].w) : last;
-        // a pixel stops at the blend that takes T below t_eps (rare: checked wave-wide)
-        if (__ballot(T < opt.t_eps) & ~done) {
-          const bool stop = !((done >> lane) & 1ull) && T < opt.t_eps && blended;
-          if (stop) { t_stop = T; last_stop = last; T = 0.0f; }
-          done |= __ballot(stop);
-        }
       }
     }
     __syncthreads();                                  // reads done before the next batch lands
   }
   if (!inside) return;
-  if ((done >> lane) & 1ull) { T = t_stop; last = last_stop; }
   const int64_t HW = (int64_t)W * H;
   const int64_t pix = (int64_t)P.y * W + P.x;
   const int64_t c3 = cam * 3 * HW;

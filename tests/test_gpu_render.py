@@ -89,6 +89,25 @@ def test_options_background_and_thresholds(R):
     assert np.allclose(imgs["rgb"][0][:, empty], np.array([0.25, 0.5, 1.0])[:, None], atol=0)
 
 
+@pytest.mark.parametrize("t_eps", [0.0, 1.0])
+def test_stop_threshold_extremes(R, t_eps):
+    """t_eps = 0: no pixel ever stops; t_eps = 1: every pixel stops after its first blend with
+    alpha > 0 (the stop test follows the blend)."""
+    g, cams = c1_scene()
+    imgs, bins, _ = gpu_render(R, g, cams, dict(t_eps=t_eps))
+    ref = oracle.render(g, cams, opts=dict(t_eps=t_eps), mode="ref")
+    check_bins(bins, ref, 64)
+    check_images(imgs, bins, ref, 4.0)
+
+
+def test_out_of_range_options_are_rejected(R):
+    import paper_2409_16504_amd as P
+    g, cams = c1_scene()
+    for bad in (dict(t_eps=1.5), dict(t_eps=-1e-3), dict(z_near=0.0), dict(alpha_max=1.0)):
+        with pytest.raises(P.PcsError):
+            gpu_render(R, g, cams, bad)
+
+
 def test_empty_and_culled_scenes(R):
     cams = [look_at_camera([0, 0, 3], width=48, height=40)]
     g0 = {k: v[..., :0] for k, v in c1_scene()[0].items()}
