@@ -191,7 +191,8 @@ hipError_t launch_scan_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_
                                uint64_t* total, uint32_t* keys, uint32_t* vals, int tile_bits,
                                uint32_t* hist, const ClearSpans& clear, hipStream_t s);
 
-// Stable LSD radix sort of (key, value) pairs over key bits [0, bits), K = uint32_t or uint64_t.
+// Stable LSD radix sort of (key, value) pairs over key bits [0, bits), K = uint32_t or uint64_t;
+// keys must have no bit set at or above `bits` (the ranking skips those bits).
 // Ping-pongs between (k0,v0) and (k1,v1); returns in *result_in_alt whether the sorted data ended
 // in (k1,v1).
 size_t sort_scratch_bytes(int64_t m);

@@ -431,7 +431,8 @@ __global__ __launch_bounds__(256) void k_depth_keys_hist(int64_t m, const uint32
 template <typename K, int THREADS, int ITEMS>
 __global__ __launch_bounds__(THREADS) void k_onesweep(
     const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
-    uint32_t* __restrict__ vout, int64_t m, int shift, const uint32_t* __restrict__ hist_row,
+    uint32_t* __restrict__ vout, uint32_t m, int shift, int digit_bits,
+    const uint32_t* __restrict__ hist_row,
     int copies, int64_t copy_stride, uint32_t* __restrict__ status,
     uint32_t* __restrict__ status_next, const uint32_t* __restrict__ live_passes, int pass) {
   constexpr int W = THREADS / kWave;
@@ -447,8 +448,8 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   for (int i = tid; i < W * kBins; i += THREADS) (&s_hist[0][0])[i] = 0u;
   __syncthreads();
-  const int64_t part = blockIdx.x;    // in-order dispatch: predecessors are running or done
-  const int64_t wbase = part * PART + (int64_t)wave * (kWave * kItems);
+  const uint32_t part = blockIdx.x;   // in-order dispatch: predecessors are running or done
+  const uint32_t wbase = part * PART + (uint32_t)wave * (kWave * kItems);   // 32-bit: m < 2^32
   K key[kItems];
   uint32_t val[kItems];
   uint32_t rank[kItems];
@@ -462,12 +463,12 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   // every load issued before the first is used
 #pragma unroll
   for (int it = 0; it < kItems; ++it) {
-    const int64_t pos = wbase + (int64_t)it * kWave + lane;
+    const uint32_t pos = wbase + (uint32_t)(it * kWave + lane);
     key[it] = pos < m ? kin[pos] : (K)0;
   }
 #pragma unroll
   for (int it = 0; it < kItems; ++it) {
-    const int64_t pos = wbase + (int64_t)it * kWave + lane;
+    const uint32_t pos = wbase + (uint32_t)(it * kWave + lane);
     val[it] = pos < m ? vin[pos] : 0u;
   }
   // rank within the wave: lanes holding the same digit are matched with eight ballots; the lowest
@@ -477,11 +478,13 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   int leader[kItems];
 #pragma unroll
   for (int it = 0; it < kItems; ++it) {
-    const bool valid = wbase + (int64_t)it * kWave + lane < m;
+    const bool valid = wbase + (uint32_t)(it * kWave + lane) < m;
     const uint32_t d = (uint32_t)(key[it] >> shift) & 0xFF;
     uint64_t peers = __ballot(valid);
+    // digit bits above digit_bits are zero in every key: they need no ballot
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
+      if (b >= digit_bits) break;
       const bool bit = (d >> b) & 1u;
       const uint64_t bal = __ballot(bit);
       peers &= bit ? bal : ~bal;
@@ -536,7 +539,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     for (int w = 0; w < W; ++w) { s_hist[w][tid] = run; run += cw[w]; }
     // look back over earlier partitions for this digit, kLookWindow predecessors per step
     if (part > 0) {
-      int64_t p = part - 1;
+      int64_t p = (int64_t)part - 1;
       uint32_t spins = 0;
       while (true) {
         uint32_t v[kLookWindow];
@@ -575,14 +578,14 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   uint32_t lpos[kItems];
 #pragma unroll
   for (int it = 0; it < kItems; ++it) {
-    const int64_t pos = wbase + (int64_t)it * kWave + lane;
+    const uint32_t pos = wbase + (uint32_t)(it * kWave + lane);
     const uint32_t d = (uint32_t)(key[it] >> shift) & 0xFF;
     lpos[it] = s_local[d] + s_hist[wave][d] + rank[it];
     if (pos < m && lpos[it] < (uint32_t)PART) s_buf[lpos[it]] = key[it];
   }
   __syncthreads();
-  const int64_t pbase = part * PART;
-  const int n_here = (int)min((int64_t)PART, m - pbase);
+  const uint32_t pbase = part * PART;
+  const int n_here = (int)min((uint32_t)PART, m - pbase);
   uint32_t gdst[kItems];
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
@@ -590,7 +593,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     if (j < n_here) {
       const K k = s_buf[j];
       gdst[r] = s_global[(uint32_t)(k >> shift) & 0xFF] + (uint32_t)j;
-      if (gdst[r] < (uint64_t)m) kout[gdst[r]] = k;
+      if (gdst[r] < m) kout[gdst[r]] = k;
     }
   }
   __syncthreads();
@@ -598,14 +601,14 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   uint32_t* s_val = reinterpret_cast<uint32_t*>(s_buf);
 #pragma unroll
   for (int it = 0; it < kItems; ++it) {
-    const int64_t pos = wbase + (int64_t)it * kWave + lane;
+    const uint32_t pos = wbase + (uint32_t)(it * kWave + lane);
     if (pos < m && lpos[it] < (uint32_t)PART) s_val[lpos[it]] = val[it];
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const int j = tid + r * THREADS;
-    if (j < n_here && gdst[r] < (uint64_t)m) vout[gdst[r]] = s_val[j];
+    if (j < n_here && gdst[r] < m) vout[gdst[r]] = s_val[j];
   }
 }
 
@@ -786,6 +789,7 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
                        int pass_begin, int pass_end) {
   *result_in_alt = false;
   if (m <= 1 || bits <= 0) return hipSuccess;
+  if (m >= (int64_t(1) << 32)) return hipErrorInvalidValue;    // the scatter indexes in 32 bits
   const int n_passes = (bits + 7) / 8;
   if (pass_end < 0 || pass_end > n_passes) pass_end = n_passes;
   const int64_t parts = (m + kPart - 1) / kPart;    // partitions of the histogram
@@ -819,8 +823,8 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
   for (int p = pass_begin; p < pass_end; ++p) {
     uint32_t* st = (p & 1) ? status1 : status0;
     uint32_t* st_next = (p & 1) ? status0 : status1;
-    hipLaunchKernelGGL((k_onesweep<K, kSweepThreads, kSweepItems>), dim3((unsigned)sweep_parts), dim3(kSweepThreads), 0, s, ki, vi, ko, vo, m,
-                       8 * p, rows + p * kBins, copies, copy_stride, st, st_next, live_passes, p);
+    hipLaunchKernelGGL((k_onesweep<K, kSweepThreads, kSweepItems>), dim3((unsigned)sweep_parts), dim3(kSweepThreads), 0, s, ki, vi, ko, vo, (uint32_t)m,
+                       8 * p, std::min(8, bits - 8 * p), rows + p * kBins, copies, copy_stride, st, st_next, live_passes, p);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     std::swap(ki, ko);
     std::swap(vi, vo);
