@@ -406,7 +406,10 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   PCS_TRY(ensure(ctx->dvals, cn1 * sizeof(uint32_t), "depth order"));
   PCS_TRY(ensure(ctx->dvals_alt, cn1 * sizeof(uint32_t), "depth order (alternate)"));
   PCS_TRY(ensure(ctx->dsort_scratch, sort_scratch_bytes(cn), "depth sort scratch"));
-  PCS_TRY(ensure(ctx->tile_hist, kTileHistWords * sizeof(uint32_t), "tile digit histograms"));
+  // digit histograms counted by the kernels that write the keys: the tile sort's, then the depth
+  // sort's
+  PCS_TRY(ensure(ctx->tile_hist, 2 * kTileHistWords * sizeof(uint32_t), "digit histograms"));
+  uint32_t* depth_hist = ctx->tile_hist.as<uint32_t>() + kTileHistWords;
   PCS_HIP(launch_init_small(ctx->small.as<uint32_t>(), dc.data(), n_cams, st->dcams.as<DevCamera>(), s));
   {
     // the projection also clears what the depth sort and the scan need zeroed
@@ -415,8 +418,8 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
     clear.count[0] = sort_clear_words(cn);
     clear.p[1] = ctx->scan_scratch.as<uint32_t>();
     clear.count[1] = scan_clear_words(cn);
-    clear.p[2] = ctx->tile_hist.as<uint32_t>();            // binning counts the tile digits here
-    clear.count[2] = kTileHistWords;
+    clear.p[2] = ctx->tile_hist.as<uint32_t>();            // both sorts' digit histograms
+    clear.count[2] = 2 * kTileHistWords;
     StageTimer tm(ctx, ST_PROJECT, s);
     PCS_HIP(launch_project(n, n_cams, st->dcams.as<DevCamera>(), dopt, *g, st->rec.as<float4>(),
                            ctx->zbits.as<uint32_t>(), ctx->rect.as<uint2>(), d_zrange, d_counts, clear, s));
@@ -432,12 +435,12 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
     bool unused = false;
     PCS_HIP(launch_depth_keys_hist(cn, ctx->zbits.as<uint32_t>(), d_counts, ctx->host_word_dev, ctx->seq,
                                    d_zrange, d_depth, ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(),
-                                   ctx->dsort_scratch.p, s));
+                                   depth_hist, s));
     // the first pass now (it returns at once if the depths need none), the others once the host
     // knows how many the depth range needs
     PCS_HIP(launch_sort(ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(), ctx->dkeys_alt.as<uint32_t>(),
                         ctx->dvals_alt.as<uint32_t>(), cn, 32, ctx->dsort_scratch.p, s, &unused, d_depth,
-                        true, true, nullptr, 0, 1));
+                        true, true, depth_hist, 0, 1));
   }
   uint64_t m64 = 0;
   if (cn > 0) {
@@ -449,7 +452,7 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
       bool unused = false;
       PCS_HIP(launch_sort(ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(), ctx->dkeys_alt.as<uint32_t>(),
                           ctx->dvals_alt.as<uint32_t>(), cn, 32, ctx->dsort_scratch.p, s, &unused, d_depth,
-                          true, true, nullptr, 1, depth_passes));
+                          true, true, depth_hist, 1, depth_passes));
     }
   }
   if (m64 >= (uint64_t(1) << 30))

@@ -161,15 +161,15 @@ hipError_t launch_scan(const uint32_t* in, const uint32_t* gather0, const uint32
 int64_t scan_clear_words(int64_t n);
 
 // Depth key per (camera, Gaussian) entry and its index as the value, and the keys' four digit
-// histograms into the sort scratch's histogram area (zeroed beforehand), for a launch_sort with
-// hist_ready. The depth-bit range comes from the projection's slots on the device; info[0..3)
+// histograms into hist_copies (kTileHistWords, kTileHistCopies partial copies, zeroed beforehand),
+// for a launch_sort with them as ext_hist. The depth-bit range comes from the projection's slots on the device; info[0..3)
 // receives the pass count, depth bits and minimum depth bits. The sum of the projection's
 // kZSlots count slots goes to host_word[0] (pinned, coherent host memory) as seq << 32 | total,
 // the total capped at 2^32 - 1, and the depth bits to host_word[1] as seq << 32 | bits.
 hipError_t launch_depth_keys_hist(int64_t m, const uint32_t* zbits,
                                   const unsigned long long* count_slots,
                                   unsigned long long* host_word, uint32_t seq, const uint32_t* zrange,
-                                  uint32_t* info, uint32_t* keys, uint32_t* vals, void* sort_scratch,
+                                  uint32_t* info, uint32_t* keys, uint32_t* vals, uint32_t* hist_copies,
                                   hipStream_t s);
 
 // Tile-digit histograms counted by binning: kTileHistCopies partial copies of

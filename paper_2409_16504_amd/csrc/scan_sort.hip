@@ -387,16 +387,18 @@ __global__ __launch_bounds__(256) void k_depth_keys_hist(int64_t m, const uint32
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
   const uint64_t lt_mask = lanemask_lt();
-  for (int64_t part = blockIdx.x; part * kPart < m; part += gridDim.x) {
-    const int64_t wbase = part * kPart + (int64_t)wave * (kWave * kItems);
-    uint32_t zb[kItems];
+  constexpr int kDkItems = 4;
+  constexpr int kDkPart = kThreads * kDkItems;
+  for (int64_t part = blockIdx.x; part * kDkPart < m; part += gridDim.x) {
+    const int64_t wbase = part * kDkPart + (int64_t)wave * (kWave * kDkItems);
+    uint32_t zb[kDkItems];
 #pragma unroll
-    for (int it = 0; it < kItems; ++it) {
+    for (int it = 0; it < kDkItems; ++it) {
       const int64_t pos = wbase + (int64_t)it * kWave + lane;
       zb[it] = pos < m ? zbits[pos] : 0u;
     }
 #pragma unroll
-    for (int it = 0; it < kItems; ++it) {
+    for (int it = 0; it < kDkItems; ++it) {
       const int64_t pos = wbase + (int64_t)it * kWave + lane;
       const bool valid = pos < m;
       const uint64_t vmask = __ballot(valid);
@@ -419,9 +421,11 @@ __global__ __launch_bounds__(256) void k_depth_keys_hist(int64_t m, const uint32
     }
   }
   __syncthreads();
+  // blocks spread their sums over kTileHistCopies copies (blocks of a copy share an XCD)
+  uint32_t* h = hist + (blockIdx.x % kTileHistCopies) * (kTileHistPasses * kBins);
   for (int p = 0; p < kDigits; ++p) {
     const uint32_t v = sh[p][tid];
-    if (v) atomicAdd(&hist[p * kBins + tid], v);
+    if (v) atomicAdd(&h[p * kBins + tid], v);
   }
 }
 
@@ -735,13 +739,13 @@ hipError_t launch_scan(const uint32_t* in, const uint32_t* gather0, const uint32
 hipError_t launch_depth_keys_hist(int64_t m, const uint32_t* zbits,
                                   const unsigned long long* count_slots,
                                   unsigned long long* host_word, uint32_t seq, const uint32_t* zrange,
-                                  uint32_t* info, uint32_t* keys, uint32_t* vals, void* sort_scratch,
+                                  uint32_t* info, uint32_t* keys, uint32_t* vals, uint32_t* hist_copies,
                                   hipStream_t s) {
   if (m == 0) return hipSuccess;
   static_assert(kZSlots == kWave, "one count slot per lane");
-  const unsigned blocks = (unsigned)std::min<int64_t>(kHistBlocks, (m + kPart - 1) / kPart);
+  const unsigned blocks = (unsigned)std::min<int64_t>(1024, (m + kThreads * 4 - 1) / (kThreads * 4));
   hipLaunchKernelGGL(k_depth_keys_hist, dim3(blocks), dim3(256), 0, s, m, zbits, count_slots, host_word,
-                     seq, zrange, info, keys, vals, reinterpret_cast<uint32_t*>(sort_scratch));
+                     seq, zrange, info, keys, vals, hist_copies);
   return hipGetLastError();
 }
 
