@@ -448,7 +448,8 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   __shared__ uint32_t s_global[kBins];         // global start of the run minus its local start
   __shared__ uint32_t s_wsum[kBins / kWave];
   __shared__ uint32_t s_tsum[kBins / kWave];
-  __shared__ K s_buf[PART];                    // keys, then (as u32) values, in digit order
+  __shared__ K s_buf[PART];                    // keys in block-local digit order
+  __shared__ uint32_t s_val[PART];             // values in the same order
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   for (int i = tid; i < W * kBins; i += THREADS) (&s_hist[0][0])[i] = 0u;
   __syncthreads();
@@ -534,13 +535,30 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     }
   }
   __syncthreads();
+  uint32_t local_start = 0;
   if (digit_thread) {
     uint32_t pre = 0;
     for (int w = 0; w < wave; ++w) pre += s_wsum[w];
-    const uint32_t local_start = pre + incl - count;
+    local_start = pre + incl - count;
     uint32_t run = 0;
 #pragma unroll
     for (int w = 0; w < W; ++w) { s_hist[w][tid] = run; run += cw[w]; }
+    s_local[tid] = local_start;
+  }
+  __syncthreads();
+  // keys and values to LDS in block-local digit order before the look-back, so that they no
+  // longer hold registers while the digit threads wait on their predecessors
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
+    const uint32_t pos = wbase + (uint32_t)(it * kWave + lane);
+    const uint32_t d = (uint32_t)(key[it] >> shift) & 0xFF;
+    const uint32_t lp = s_local[d] + s_hist[wave][d] + rank[it];
+    if (pos < m && lp < (uint32_t)PART) {
+      s_buf[lp] = key[it];
+      s_val[lp] = val[it];
+    }
+  }
+  if (digit_thread) {
     // look back over earlier partitions for this digit, kLookWindow predecessors per step
     if (part > 0) {
       int64_t p = (int64_t)part - 1;
@@ -574,45 +592,23 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     }
     // clear this partition's slice of the other status buffer for the next pass
     status_next[part * kBins + tid] = 0u;
-    s_local[tid] = local_start;
     s_global[tid] = excl - local_start;
   }
   __syncthreads();
-  // keys to LDS in block-local digit order
-  uint32_t lpos[kItems];
-#pragma unroll
-  for (int it = 0; it < kItems; ++it) {
-    const uint32_t pos = wbase + (uint32_t)(it * kWave + lane);
-    const uint32_t d = (uint32_t)(key[it] >> shift) & 0xFF;
-    lpos[it] = s_local[d] + s_hist[wave][d] + rank[it];
-    if (pos < m && lpos[it] < (uint32_t)PART) s_buf[lpos[it]] = key[it];
-  }
-  __syncthreads();
+  // keys and values leave in digit runs
   const uint32_t pbase = part * PART;
   const int n_here = (int)min((uint32_t)PART, m - pbase);
-  uint32_t gdst[kItems];
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const int j = tid + r * THREADS;
     if (j < n_here) {
       const K k = s_buf[j];
-      gdst[r] = s_global[(uint32_t)(k >> shift) & 0xFF] + (uint32_t)j;
-      if (gdst[r] < m) kout[gdst[r]] = k;
+      const uint32_t g = s_global[(uint32_t)(k >> shift) & 0xFF] + (uint32_t)j;
+      if (g < m) {
+        kout[g] = k;
+        vout[g] = s_val[j];
+      }
     }
-  }
-  __syncthreads();
-  // values follow the same permutation
-  uint32_t* s_val = reinterpret_cast<uint32_t*>(s_buf);
-#pragma unroll
-  for (int it = 0; it < kItems; ++it) {
-    const uint32_t pos = wbase + (uint32_t)(it * kWave + lane);
-    if (pos < m && lpos[it] < (uint32_t)PART) s_val[lpos[it]] = val[it];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < kItems; ++r) {
-    const int j = tid + r * THREADS;
-    if (j < n_here && gdst[r] < m) vout[gdst[r]] = s_val[j];
   }
 }
 
