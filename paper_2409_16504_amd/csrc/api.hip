@@ -484,9 +484,11 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
     bool in_alt = false;
     {
       StageTimer tm(ctx, ST_SORT, s);
+      // its last pass also finds the tiles' runs
       PCS_HIP(launch_sort(st->keys.as<uint32_t>(), st->vals.as<uint32_t>(), ctx->keys_alt.as<uint32_t>(),
                           ctx->vals_alt.as<uint32_t>(), m, tile_bits, ctx->sort_scratch.p, s, &in_alt,
-                          nullptr, true, false, ctx->tile_hist.as<uint32_t>()));
+                          nullptr, true, false, ctx->tile_hist.as<uint32_t>(), 0, -1,
+                          st->ranges.as<uint32_t>(), total_tiles));
     }
     if (in_alt) {
       swap_buf(st->keys, ctx->keys_alt);
@@ -496,7 +498,9 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   if (m == 0) PCS_HIP(launch_fill_u32(st->ranges.as<uint32_t>(), 0u, 2 * total_tiles, s));
   {
     StageTimer tm(ctx, ST_RANGES, s);
-    PCS_HIP(launch_ranges(st->keys.as<uint32_t>(), m, total_tiles, st->ranges.as<uint32_t>(), s));
+    // runs found by the tile sort unless it had no pass to run (one instance or one tile)
+    if (m <= 1 || tile_bits == 0)
+      PCS_HIP(launch_ranges(st->keys.as<uint32_t>(), m, total_tiles, st->ranges.as<uint32_t>(), s));
     PCS_HIP(launch_tile_order(st->ranges.as<uint32_t>(), total_tiles, st->order.as<uint32_t>(), s));
   }
   {

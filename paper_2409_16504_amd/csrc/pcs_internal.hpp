@@ -200,21 +200,27 @@ size_t sort_scratch_bytes(int64_t m);
 // ends in (k1,v1) when *live_passes is odd; *result_in_alt then describes the host's pass count.
 // [pass_begin, pass_end) launches only those passes (pass_end < 0: all): a sort may be launched in
 // pieces on one stream, the set-up (clear, histogram) going with the piece that starts at pass 0.
+// ranges (32-bit keys below n_tiles, zeroed beforehand): the last pass also records every key's
+// run as ranges[key] = ~start, ranges[n_tiles + key] = end (launch_tile_order turns the starts
+// back into plain ones).
 template <typename K>
 hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int bits, void* scratch,
                        hipStream_t s, bool* result_in_alt, const uint32_t* live_passes = nullptr,
                        bool scratch_cleared = false, bool hist_ready = false,
-                       const uint32_t* ext_hist = nullptr, int pass_begin = 0, int pass_end = -1);
+                       const uint32_t* ext_hist = nullptr, int pass_begin = 0, int pass_end = -1,
+                       uint32_t* ranges = nullptr, int64_t n_tiles = 0);
 // Words at the start of sort scratch that must be zero before a sort of m pairs (cleared by the
 // sort itself unless the caller has cleared them and says so).
 int64_t sort_clear_words(int64_t m);
 
-// ranges must be zero (cleared by the caller, e.g. folded into binning).
+// ranges must be zero (cleared by the caller, e.g. folded into binning); starts are written
+// complemented, like the sort's (launch_tile_order turns them back).
 hipError_t launch_ranges(const uint32_t* keys, int64_t m, int64_t n_tiles, uint32_t* ranges,
                          hipStream_t s);
 
-// Permutation of the tiles for compositing: longest lists first, empty tiles last.
-hipError_t launch_tile_order(const uint32_t* ranges, int64_t n_tiles, uint32_t* order, hipStream_t s);
+// Permutation of the tiles for compositing: longest lists first, empty tiles last. Reads the
+// complemented starts and leaves plain ones.
+hipError_t launch_tile_order(uint32_t* ranges, int64_t n_tiles, uint32_t* order, hipStream_t s);
 
 hipError_t launch_canonical_keys(const uint32_t* keys, const uint32_t* vals, int64_t m, int64_t n,
                                  int64_t tiles_per_cam, const float4* rec, uint64_t* out,

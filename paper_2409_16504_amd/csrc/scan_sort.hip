@@ -438,7 +438,8 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     uint32_t* __restrict__ vout, uint32_t m, int shift, int digit_bits,
     const uint32_t* __restrict__ hist_row,
     int copies, int64_t copy_stride, uint32_t* __restrict__ status,
-    uint32_t* __restrict__ status_next, const uint32_t* __restrict__ live_passes, int pass) {
+    uint32_t* __restrict__ status_next, const uint32_t* __restrict__ live_passes, int pass,
+    uint32_t* __restrict__ ranges, uint32_t n_tiles) {
   constexpr int W = THREADS / kWave;
   constexpr int PART = THREADS * ITEMS;
   constexpr int kItems = ITEMS;
@@ -607,6 +608,13 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
       if (g < m) {
         kout[g] = k;
         vout[g] = s_val[j];
+        // last pass of a tile sort: every run boundary in the block proposes its tile's start and
+        // end; the earliest start and the latest end win (starts stored complemented, so that one
+        // atomic maximum serves both and zero still means "no run")
+        if (ranges && (uint64_t)k < n_tiles) {
+          if (j == 0 || s_buf[j - 1] != k) atomicMax(&ranges[(uint32_t)k], ~g);
+          if (j == n_here - 1 || s_buf[j + 1] != k) atomicMax(&ranges[n_tiles + (uint32_t)k], g + 1);
+        }
       }
     }
   }
@@ -618,7 +626,7 @@ __global__ void k_ranges(const uint32_t* __restrict__ keys, int64_t m, int64_t n
   if (i >= m) return;
   const uint32_t t = keys[i];
   if (t >= (uint64_t)n_tiles) return;
-  if (i == 0 || keys[i - 1] != t) ranges[t] = (uint32_t)i;
+  if (i == 0 || keys[i - 1] != t) ranges[t] = ~(uint32_t)i;        // complemented, as the sort writes it
   if (i == m - 1 || keys[i + 1] != t) ranges[n_tiles + t] = (uint32_t)(i + 1);
 }
 
@@ -627,12 +635,16 @@ __global__ void k_ranges(const uint32_t* __restrict__ keys, int64_t m, int64_t n
 // tiles last; the order inside a bucket is arbitrary. One block; it writes a permutation of all
 // tiles.
 constexpr int kOrderThreads = 1024;
+// Length of a run whose start is stored complemented (0: empty tile).
+__device__ __forceinline__ uint32_t run_length(uint32_t start_complemented, uint32_t end) {
+  return start_complemented ? end - ~start_complemented : 0u;
+}
 constexpr int kOrderBuckets = 257;              // 256 length buckets + empty tiles
 __device__ __forceinline__ int order_bucket(uint32_t len) {
   return len == 0 ? kOrderBuckets - 1 : 255 - (int)min(len >> 6, 255u);
 }
 
-__global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint32_t* __restrict__ ranges,
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(uint32_t* __restrict__ ranges,
                                                               int64_t n_tiles,
                                                               uint32_t* __restrict__ order) {
   __shared__ uint32_t s_cnt[kOrderBuckets + 1];
@@ -647,7 +659,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint32_t* __
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
       const int64_t t = t0 + (int64_t)j * kOrderThreads + tid;
-      len[j] = t < n_tiles ? ranges[n_tiles + t] - ranges[t] : 0u;
+      len[j] = t < n_tiles ? run_length(ranges[t], ranges[n_tiles + t]) : 0u;
     }
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
@@ -675,7 +687,12 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint32_t* __
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
       const int64_t t = t0 + (int64_t)j * kOrderThreads + tid;
-      len[j] = t < n_tiles ? ranges[n_tiles + t] - ranges[t] : 0u;
+      len[j] = 0u;
+      if (t < n_tiles) {
+        const uint32_t raw = ranges[t];
+        len[j] = run_length(raw, ranges[n_tiles + t]);
+        ranges[t] = raw ? ~raw : 0u;                  // plain starts for the tiles' readers
+      }
     }
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
@@ -786,7 +803,7 @@ template <typename K>
 hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int bits, void* scratch,
                        hipStream_t s, bool* result_in_alt, const uint32_t* live_passes,
                        bool scratch_cleared, bool hist_ready, const uint32_t* ext_hist,
-                       int pass_begin, int pass_end) {
+                       int pass_begin, int pass_end, uint32_t* ranges, int64_t n_tiles) {
   *result_in_alt = false;
   if (m <= 1 || bits <= 0) return hipSuccess;
   if (m >= (int64_t(1) << 32)) return hipErrorInvalidValue;    // the scatter indexes in 32 bits
@@ -820,11 +837,14 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
     std::swap(ki, ko);
     std::swap(vi, vo);
   }
+  if (ranges && (sizeof(K) != 4 || n_tiles <= 0 || n_tiles > 0xFFFFFFFFll)) return hipErrorInvalidValue;
   for (int p = pass_begin; p < pass_end; ++p) {
     uint32_t* st = (p & 1) ? status1 : status0;
     uint32_t* st_next = (p & 1) ? status0 : status1;
+    uint32_t* rng = p == n_passes - 1 ? ranges : nullptr;
     hipLaunchKernelGGL((k_onesweep<K, kSweepThreads, kSweepItems>), dim3((unsigned)sweep_parts), dim3(kSweepThreads), 0, s, ki, vi, ko, vo, (uint32_t)m,
-                       8 * p, std::min(8, bits - 8 * p), rows + p * kBins, copies, copy_stride, st, st_next, live_passes, p);
+                       8 * p, std::min(8, bits - 8 * p), rows + p * kBins, copies, copy_stride, st, st_next, live_passes, p,
+                       rng, (uint32_t)n_tiles);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     std::swap(ki, ko);
     std::swap(vi, vo);
@@ -834,10 +854,10 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
 }
 template hipError_t launch_sort<uint32_t>(uint32_t*, uint32_t*, uint32_t*, uint32_t*, int64_t, int,
                                           void*, hipStream_t, bool*, const uint32_t*, bool, bool,
-                                          const uint32_t*, int, int);
+                                          const uint32_t*, int, int, uint32_t*, int64_t);
 template hipError_t launch_sort<uint64_t>(uint64_t*, uint32_t*, uint64_t*, uint32_t*, int64_t, int,
                                           void*, hipStream_t, bool*, const uint32_t*, bool, bool,
-                                          const uint32_t*, int, int);
+                                          const uint32_t*, int, int, uint32_t*, int64_t);
 
 hipError_t launch_ranges(const uint32_t* keys, int64_t m, int64_t n_tiles, uint32_t* ranges,
                          hipStream_t s) {
@@ -846,7 +866,7 @@ hipError_t launch_ranges(const uint32_t* keys, int64_t m, int64_t n_tiles, uint3
   return hipGetLastError();
 }
 
-hipError_t launch_tile_order(const uint32_t* ranges, int64_t n_tiles, uint32_t* order, hipStream_t s) {
+hipError_t launch_tile_order(uint32_t* ranges, int64_t n_tiles, uint32_t* order, hipStream_t s) {
   if (n_tiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, s, ranges, n_tiles, order);
   return hipGetLastError();
