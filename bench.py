@@ -307,7 +307,7 @@ def stage_rooflines(per_stage, n, m, bins, W, H):
         "binning": n * 12 + m * 8,                                 # order + gathered rectangle; key+value
         "sort": n * (12 + SORT_PASS_B * ((depth_bits + 7) // 8)) +      # depth keys, passes
                 m * SORT_PASS_B * ((tile_bits + 7) // 8),                 # (histograms come fused)
-        "ranges": m * 4 + tiles * 16,                              # keys; ranges fill + order
+        "ranges": tiles * 24,                                      # tile order: runs read twice, starts + order written
     }
     out = {}
     for k, b in byts.items():
