@@ -8,6 +8,7 @@ world-to-camera rotation), t (3,), fx, fy, cx, cy, width, height (Section 3.1, E
 from __future__ import annotations
 
 import ctypes
+import sys
 
 import numpy as np
 import torch
@@ -96,13 +97,25 @@ class Renderer:
         self.device = torch.cuda.current_device() if device is None else int(device)
         L = _lib.load()
         self.ctx = ctypes.c_void_p()
+        # held by the instance: module globals may already be cleared when __del__ runs
+        self._destroy = L.pcs_context_destroy
+        self._finalizing = sys.is_finalizing
         with torch.cuda.device(self.device):
             check(L.pcs_context_create(self.device, ctypes.byref(self.ctx)))
 
-    def __del__(self):
-        if getattr(self, "ctx", None) and self.ctx.value:
-            _lib.load().pcs_context_destroy(self.ctx)
+    def close(self) -> None:
+        """Release the context's device buffers now (also done when the renderer is collected)."""
+        ctx = getattr(self, "ctx", None)
+        if ctx is not None and ctx.value:
+            self._destroy(ctx)
             self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        # at interpreter exit the HIP runtime may be shutting down; process exit frees the memory
+        finalizing = getattr(self, "_finalizing", None)
+        if finalizing is None or finalizing():
+            return
+        self.close()
 
     # -- forward --------------------------------------------------------------------------
     def render(self, g: dict, cams: list, opts: Options | None = None, state: RenderState | None = None,
