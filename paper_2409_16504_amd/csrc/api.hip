@@ -148,7 +148,11 @@ struct StageTimer {
     if (!ctx->timing || !((ctx->stage_mask >> stage) & 1u)) return;
     if (ctx->used == ctx->pool.size()) {
       pcs_context::Ev ev{};
-      if (hipEventCreate(&ev.a) != hipSuccess || hipEventCreate(&ev.b) != hipSuccess) return;
+      // timing only (read after a stream synchronisation): no system-scope fence, whose cache
+      // writeback would otherwise stall the stream at every record
+      if (hipEventCreateWithFlags(&ev.a, hipEventDisableSystemFence) != hipSuccess ||
+          hipEventCreateWithFlags(&ev.b, hipEventDisableSystemFence) != hipSuccess)
+        return;
       ctx->pool.push_back(ev);
     }
     slot = ctx->used++;
