@@ -285,6 +285,10 @@ constexpr uint32_t kSortAgg = 1u << 30;
 constexpr uint32_t kSortPrefix = 2u << 30;
 constexpr uint32_t kSortValue = (1u << 30) - 1;
 constexpr int kLookWindow = 32;
+// Partitions per look-back group: the group's last partition publishes the group's digit total
+// (or its inclusive prefix) in a second status row, so a look-back walks over groups, not
+// partitions, once it has left its own group.
+constexpr int kGroupParts = kLookWindow;
 constexpr int kHistBlocks = 256;
 
 // Digit histograms of every pass in one read of the keys. Each block takes partitions of 4096 keys
@@ -438,7 +442,8 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     uint32_t* __restrict__ vout, uint32_t m, int shift, int digit_bits,
     const uint32_t* __restrict__ hist_row,
     int copies, int64_t copy_stride, uint32_t* __restrict__ status,
-    uint32_t* __restrict__ status_next, const uint32_t* __restrict__ live_passes, int pass,
+    uint32_t* __restrict__ status_next, uint32_t* __restrict__ gstatus,
+    uint32_t* __restrict__ gstatus_next, const uint32_t* __restrict__ live_passes, int pass,
     uint32_t* __restrict__ ranges, uint32_t n_tiles) {
   constexpr int W = THREADS / kWave;
   constexpr int PART = THREADS * ITEMS;
@@ -559,40 +564,77 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
       s_val[lp] = val[it];
     }
   }
+  // the staged keys and values leave registers before the look-back's loads are issued
+  __builtin_amdgcn_sched_barrier(0);
   if (digit_thread) {
-    // look back over earlier partitions for this digit, kLookWindow predecessors per step
+    // look back for this digit: first over the earlier partitions of this partition's group, then,
+    // if none of them holds an inclusive prefix, over the group rows of the earlier groups
     if (part > 0) {
-      int64_t p = (int64_t)part - 1;
-      uint32_t spins = 0;
+      const uint32_t grp = part / kGroupParts, g_first = grp * kGroupParts;
+      const bool group_last = part - g_first == kGroupParts - 1;
+      const int n_in_group = (int)(part - g_first);   // earlier partitions of the group
+      uint32_t spins = 0, acc = 0;
+      int state = 0;                         // 0: all aggregates, 1: reached a prefix, 2: not ready
+      const uint32_t* win = status + ((int64_t)part - 1) * kBins + tid;
       while (true) {
-        uint32_t v[kLookWindow];
+        // one window of predecessors (loads at fixed offsets from one address, which is re-derived
+        // each round so that 32 addresses do not stay live across the wait); those before the
+        // group are read but count as empty aggregates
+        asm volatile("" : "+v"(win));
+        uint32_t v[kGroupParts];
 #pragma unroll
-        for (int w = 0; w < kLookWindow; ++w)
-          v[w] = (p - w >= 0) ? atomic_load_u32(&status[(p - w) * kBins + tid]) : kSortPrefix;
-        // accept the window up to (and including) its nearest inclusive prefix, if nothing
-        // before it is still unpublished
-        uint32_t acc = 0;
-        int state = 0;                       // 0: all aggregates, 1: reached a prefix, 2: not ready
+        for (int w = 0; w < kGroupParts; ++w)
+          v[w] = ((int64_t)part - 1 - w >= 0) ? atomic_load_u32(win - (int64_t)w * kBins) : kSortAgg;
+        acc = 0;
+        state = 0;
 #pragma unroll
-        for (int w = 0; w < kLookWindow; ++w) {
-          if (state != 0) continue;
+        for (int w = 0; w < kGroupParts; ++w) {
+          if (state != 0 || w >= n_in_group) continue;
           const uint32_t flag = v[w] & ~kSortValue;
           if (flag == 0) { state = 2; continue; }
           acc += v[w] & kSortValue;
           if (flag == kSortPrefix) state = 1;
         }
-        if (state == 2) {
-          if (++spins < kSpinLimit) continue;
-          break;                             // guards a broken launch only
+        if (state == 2 && ++spins < kSpinLimit) continue;
+        break;                               // a spin-out guards a broken launch only
+      }
+      excl += acc;
+      // the group's total is known as soon as its last partition has read the group (group 0 always
+      // meets partition 0's prefix, so only later groups publish a total)
+      if (group_last && state == 0) atomic_store_u32(&gstatus[grp * kBins + tid], kSortAgg | (acc + count));
+      if (state == 0) {
+        int64_t q = (int64_t)grp - 1;       // grp >= 1 here
+        spins = 0;
+        while (true) {
+          uint32_t v[kLookWindow];
+#pragma unroll
+          for (int w = 0; w < kLookWindow; ++w)
+            v[w] = (q - w >= 0) ? atomic_load_u32(&gstatus[(q - w) * kBins + tid]) : kSortPrefix;
+          acc = 0;
+          state = 0;
+#pragma unroll
+          for (int w = 0; w < kLookWindow; ++w) {
+            if (state != 0) continue;
+            const uint32_t flag = v[w] & ~kSortValue;
+            if (flag == 0) { state = 2; continue; }
+            acc += v[w] & kSortValue;
+            if (flag == kSortPrefix) state = 1;
+          }
+          if (state == 2) {
+            if (++spins < kSpinLimit) continue;
+            break;
+          }
+          excl += acc;
+          if (state == 1) break;
+          q -= kLookWindow;
         }
-        excl += acc;
-        if (state == 1) break;
-        p -= kLookWindow;
       }
       atomic_store_u32(&status[part * kBins + tid], kSortPrefix | (excl + count));
+      if (group_last) atomic_store_u32(&gstatus[grp * kBins + tid], kSortPrefix | (excl + count));
     }
-    // clear this partition's slice of the other status buffer for the next pass
+    // clear this partition's slices of the other status buffers for the next pass
     status_next[part * kBins + tid] = 0u;
+    if (part % kGroupParts == kGroupParts - 1) gstatus_next[(part / kGroupParts) * kBins + tid] = 0u;
     s_global[tid] = excl - local_start;
   }
   __syncthreads();
@@ -792,11 +834,13 @@ static_assert(SweepShape<uint32_t>::part >= kSortPartMin && SweepShape<uint64_t>
 
 size_t sort_scratch_bytes(int64_t m) {
   const int64_t parts = (m + kSortPartMin - 1) / kSortPartMin;
-  return (size_t)(kMaxPasses * kBins + 2 * parts * kBins) * sizeof(uint32_t) + 256;
+  const int64_t groups = (parts + kGroupParts - 1) / kGroupParts;
+  return (size_t)(kMaxPasses * kBins + 2 * (parts + groups) * kBins) * sizeof(uint32_t) + 256;
 }
 
 int64_t sort_clear_words(int64_t m) {
-  return kMaxPasses * kBins + (m + kSortPartMin - 1) / kSortPartMin * kBins;
+  const int64_t parts = (m + kSortPartMin - 1) / kSortPartMin;
+  return kMaxPasses * kBins + (parts + (parts + kGroupParts - 1) / kGroupParts) * kBins;
 }
 
 template <typename K>
@@ -813,15 +857,18 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
   constexpr int kSweepThreads = SweepShape<K>::threads;
   constexpr int kSweepItems = SweepShape<K>::items;
   const int64_t sweep_parts = (m + SweepShape<K>::part - 1) / SweepShape<K>::part;
-  // scratch: hist[8][256] | status0[parts][256] | status1[parts][256]. One fill clears the
-  // histograms and status0; pass p reads status[p & 1] and clears its partitions' slice of the
-  // other buffer for pass p + 1.
+  // scratch: hist[8][256] | status0[parts][256] | gstatus0[groups][256] | status1[parts][256] |
+  // gstatus1[groups][256]. One fill clears the histograms, status0 and gstatus0; pass p reads the
+  // buffers of parity p & 1 and clears its slices of the other pair for pass p + 1.
+  const int64_t sweep_groups = (sweep_parts + kGroupParts - 1) / kGroupParts;
   uint32_t* hist = reinterpret_cast<uint32_t*>(scratch);
   uint32_t* status0 = hist + kMaxPasses * kBins;
-  uint32_t* status1 = status0 + sweep_parts * kBins;
+  uint32_t* gstatus0 = status0 + sweep_parts * kBins;
+  uint32_t* status1 = gstatus0 + sweep_groups * kBins;
+  uint32_t* gstatus1 = status1 + sweep_parts * kBins;
   hipError_t e = (scratch_cleared || pass_begin > 0)
                      ? hipSuccess
-                     : launch_fill_u32(hist, 0u, kMaxPasses * kBins + sweep_parts * kBins, s);
+                     : launch_fill_u32(hist, 0u, kMaxPasses * kBins + (sweep_parts + sweep_groups) * kBins, s);
   if (e != hipSuccess) return e;
   const int hblocks = (int)std::min<int64_t>(kHistBlocks, parts);
   if (!hist_ready && !ext_hist && pass_begin == 0) {
@@ -841,9 +888,11 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
   for (int p = pass_begin; p < pass_end; ++p) {
     uint32_t* st = (p & 1) ? status1 : status0;
     uint32_t* st_next = (p & 1) ? status0 : status1;
+    uint32_t* gst = (p & 1) ? gstatus1 : gstatus0;
+    uint32_t* gst_next = (p & 1) ? gstatus0 : gstatus1;
     uint32_t* rng = p == n_passes - 1 ? ranges : nullptr;
     hipLaunchKernelGGL((k_onesweep<K, kSweepThreads, kSweepItems>), dim3((unsigned)sweep_parts), dim3(kSweepThreads), 0, s, ki, vi, ko, vo, (uint32_t)m,
-                       8 * p, std::min(8, bits - 8 * p), rows + p * kBins, copies, copy_stride, st, st_next, live_passes, p,
+                       8 * p, std::min(8, bits - 8 * p), rows + p * kBins, copies, copy_stride, st, st_next, gst, gst_next, live_passes, p,
                        rng, (uint32_t)n_tiles);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     std::swap(ki, ko);
