@@ -17,7 +17,9 @@
 //              pass over all digits, then one chained-scan scatter per 8-bit digit. Ranks inside a
 //              wavefront come from eight ballots (lanes holding the same digit), so the sort is
 //              stable; each block reorders its 4096 keys through LDS so global writes leave in
-//              digit runs.
+//              digit runs. The chained scan looks back in two levels: the last partition of each
+//              group of 32 publishes the group's digit totals as soon as it has read the group, so
+//              a look-back crosses earlier groups one status row per group.
 //  * ranges:   tile start/end from tile-id changes in the sorted keys.
 //
 // Depth keys are fp32 depth bits - minimum depth bits over all cameras: positive floats order
