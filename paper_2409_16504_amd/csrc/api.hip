@@ -138,13 +138,16 @@ struct pcs_voxels {
 
 namespace {
 
-// Records HIP events around a stage when timing is on.
+// Records HIP events around a stage when timing is on. A stage of one kernel can instead hand the
+// pair to its launch (around = false), which stamps the kernel's own start and end into them.
 struct StageTimer {
   pcs_context* ctx;
   int stage;
   hipStream_t s;
+  bool around;
   size_t slot = (size_t)-1;
-  StageTimer(pcs_context* c, int st, hipStream_t stream) : ctx(c), stage(st), s(stream) {
+  StageTimer(pcs_context* c, int st, hipStream_t stream, bool around_stage = true)
+      : ctx(c), stage(st), s(stream), around(around_stage) {
     if (!ctx->timing || !((ctx->stage_mask >> stage) & 1u)) return;
     if (ctx->used == ctx->pool.size()) {
       pcs_context::Ev ev{};
@@ -157,10 +160,12 @@ struct StageTimer {
     }
     slot = ctx->used++;
     ctx->pool[slot].stage = stage;
-    (void)hipEventRecord(ctx->pool[slot].a, s);
+    if (around) (void)hipEventRecord(ctx->pool[slot].a, s);
   }
+  hipEvent_t start() const { return !around && slot != (size_t)-1 ? ctx->pool[slot].a : nullptr; }
+  hipEvent_t stop() const { return !around && slot != (size_t)-1 ? ctx->pool[slot].b : nullptr; }
   ~StageTimer() {
-    if (slot != (size_t)-1) (void)hipEventRecord(ctx->pool[slot].b, s);
+    if (around && slot != (size_t)-1) (void)hipEventRecord(ctx->pool[slot].b, s);
   }
 };
 
@@ -508,10 +513,10 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
     PCS_HIP(launch_tile_order(st->ranges.as<uint32_t>(), total_tiles, st->order.as<uint32_t>(), s));
   }
   {
-    StageTimer tm(ctx, ST_COMPOSITE, s);
+    StageTimer tm(ctx, ST_COMPOSITE, s, false);   // the kernel's own start and end
     PCS_HIP(launch_composite(n, n_cams, W, H, st->rec.as<float4>(), st->vals.as<uint32_t>(),
                              st->ranges.as<uint32_t>(), st->order.as<uint32_t>(), dopt, *out, st->t_final.as<float>(),
-                             st->n_contrib.as<int32_t>(), s));
+                             st->n_contrib.as<int32_t>(), s, tm.start(), tm.stop()));
   }
   st->g = *g;
   st->cams.assign(cams, cams + n_cams);

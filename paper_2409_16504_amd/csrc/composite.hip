@@ -16,6 +16,8 @@
 // across the wavefront (lane-half exchanges leave them in four lanes) before one atomic add per
 // value.
 
+#include <hip/hip_ext.h>
+
 #include "projection.hpp"
 
 namespace pcs {
@@ -533,16 +535,23 @@ __global__ __launch_bounds__(256) void k_project_bwd(
 hipError_t launch_composite(int64_t n, int n_cams, int W, int H, const float4* rec,
                             const uint32_t* vals, const uint32_t* ranges, const uint32_t* order,
                             const DevOptions& opt, const pcs_images& out, float* t_final,
-                            int32_t* n_contrib, hipStream_t s) {
+                            int32_t* n_contrib, hipStream_t s, hipEvent_t ev_start,
+                            hipEvent_t ev_stop) {
   const int TX = (W + kTile - 1) / kTile, TY = (H + kTile - 1) / kTile;
   const int64_t tiles_per_cam = (int64_t)TX * TY;
   const int64_t total = tiles_per_cam * n_cams;
   if (total == 0) return hipSuccess;
   // four single-wavefront blocks per tile, in groups of 8 tiles (see quadrant_of_block)
   const int64_t blocks = (total + 7) / 8 * 32;
-  hipLaunchKernelGGL(k_composite, dim3((unsigned)blocks), dim3(kWave), 0, s, n, W, H, TX,
-                     tiles_per_cam, total, rec, vals, ranges, order, opt, out.rgb, out.normal, out.depth,
-                     out.alpha, t_final, n_contrib);
+  if (ev_start || ev_stop)
+    // the dispatch itself stamps the events: no marker packets in the stream around the kernel
+    hipExtLaunchKernelGGL(k_composite, dim3((unsigned)blocks), dim3(kWave), 0, s, ev_start, ev_stop, 0,
+                          n, W, H, TX, tiles_per_cam, total, rec, vals, ranges, order, opt, out.rgb,
+                          out.normal, out.depth, out.alpha, t_final, n_contrib);
+  else
+    hipLaunchKernelGGL(k_composite, dim3((unsigned)blocks), dim3(kWave), 0, s, n, W, H, TX,
+                       tiles_per_cam, total, rec, vals, ranges, order, opt, out.rgb, out.normal, out.depth,
+                       out.alpha, t_final, n_contrib);
   return hipGetLastError();
 }
 

@@ -226,10 +226,12 @@ hipError_t launch_canonical_keys(const uint32_t* keys, const uint32_t* vals, int
                                  int64_t tiles_per_cam, const float4* rec, uint64_t* out,
                                  hipStream_t s);
 
+// ev_start / ev_stop, when given, receive the compositing kernel's own start and end times.
 hipError_t launch_composite(int64_t n, int n_cams, int W, int H, const float4* rec,
                             const uint32_t* vals, const uint32_t* ranges, const uint32_t* order,
                             const DevOptions& opt, const pcs_images& out, float* t_final,
-                            int32_t* n_contrib, hipStream_t s);
+                            int32_t* n_contrib, hipStream_t s, hipEvent_t ev_start = nullptr,
+                            hipEvent_t ev_stop = nullptr);
 
 // Backward: per-(camera, Gaussian) screen-space gradient accumulators, [C*n][16] (one 64-byte
 // line per splat, so a splat's partials from one wavefront go out as one atomic request):
