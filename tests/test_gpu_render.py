@@ -190,3 +190,29 @@ def test_full_size_surface_frame(R, n, W, H, seed):
     unf = rsub["flags"] == 0
     assert np.array_equal(flat(bins["n_contrib"])[unf], flat(ref["n_contrib"])[unf])
     assert err["flagged"] < 0.01 * pix.size
+
+
+@pytest.mark.parametrize("n", [32 * 4096, 32 * 4096 + 1, 64 * 4096 + 4095])
+def test_sort_partition_group_edges(R, n):
+    """Splat counts at the edges of the sort's look-back groups (groups of 32 scatter partitions
+    of 4096 keys): one full group, one key into a second group, and a third group holding one
+    partial partition. The depth sort runs over the n splats, the tile sort over their instances;
+    the complete key lists are compared bit-exact, images on sampled pixels."""
+    W, H = 640, 480
+    rng = np.random.default_rng(n % 9973)
+    g = random_gaussians(n, rng, scale_range=(0.002, 0.02))
+    cams = [look_at_camera([0, 0, 3], width=W, height=H)]
+    imgs, bins, _ = gpu_render(R, g, cams)
+    assert bins["keys"].size > 32 * 4096                    # the tile sort spans several groups too
+    pix = rng.choice(W * H, 4000, replace=False)
+    ref = oracle.render(g, cams, mode="ref", pixels=pix)
+    check_bins(bins, ref, ((W + 15) // 16) * ((H + 15) // 16))
+    flat = lambda a: a.reshape(a.shape[0], -1)[..., pix] if a.ndim == 3 else a.reshape(a.shape[0], 3, -1)[..., pix]  # noqa: E731
+    sub = {k: flat(imgs[k]) for k in ("rgb", "normal", "depth", "alpha")}
+    rsub = {k: flat(ref[k]) for k in ("rgb", "normal", "depth", "alpha")}
+    rsub["flags"] = flat(ref["flags"])
+    err = image_errors(sub, rsub)
+    assert err["rgb"] <= 1e-4 and err["normal"] <= 1e-4 and err["alpha"] <= 1e-4, err
+    assert err["depth"] <= 1e-4 * 5.0, err
+    unf = rsub["flags"] == 0
+    assert np.array_equal(flat(bins["n_contrib"])[unf], flat(ref["n_contrib"])[unf])
