@@ -98,8 +98,8 @@ def main():
     out = R.render(g, cams, opts)
     for _ in range(args.warmup):
         R.render(g, cams, opts, out=out)
-    # timed frames: HIP events only around the compositing kernel (the roofline's kernel), so the
-    # frame time carries no per-stage instrumentation
+    # timed frames: the compositing kernel's dispatch (the roofline's kernel) stamps its start and
+    # end into HIP events, so the frame time carries no per-stage instrumentation
     torch.cuda.synchronize()
     R.timing(True, stages=["composite"])
     torch.cuda.synchronize()
