@@ -358,9 +358,23 @@ __global__ __launch_bounds__(256) void k_depth_keys_hist(int64_t m, const uint32
                                                          uint32_t* __restrict__ vals,
                                                          uint32_t* __restrict__ hist) {
   constexpr int kDigits = 4;
+  constexpr int kDkItems = 4;
+  constexpr int kDkPart = kThreads * kDkItems;
   __shared__ uint32_t sh[kDigits][kBins];
   __shared__ uint32_t s_z[2];
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  // the first partition's depth bits are requested before the depth range is reduced, so the two
+  // round trips overlap
+  uint32_t zb[kDkItems];
+  auto load_bits = [&](int64_t part) {
+    const int64_t wbase = part * kDkPart + (int64_t)wave * (kWave * kDkItems);
+#pragma unroll
+    for (int it = 0; it < kDkItems; ++it) {
+      const int64_t pos = wbase + (int64_t)it * kWave + lane;
+      zb[it] = pos < m ? zbits[pos] : 0u;
+    }
+  };
+  load_bits(blockIdx.x);
   for (int p = 0; p < kDigits; ++p) sh[p][tid] = 0;
   if (tid < kWave) {
     uint32_t lo = zrange[tid], hi = zrange[kZSlots + tid];
@@ -393,16 +407,9 @@ __global__ __launch_bounds__(256) void k_depth_keys_hist(int64_t m, const uint32
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
   const uint64_t lt_mask = lanemask_lt();
-  constexpr int kDkItems = 4;
-  constexpr int kDkPart = kThreads * kDkItems;
   for (int64_t part = blockIdx.x; part * kDkPart < m; part += gridDim.x) {
     const int64_t wbase = part * kDkPart + (int64_t)wave * (kWave * kDkItems);
-    uint32_t zb[kDkItems];
-#pragma unroll
-    for (int it = 0; it < kDkItems; ++it) {
-      const int64_t pos = wbase + (int64_t)it * kWave + lane;
-      zb[it] = pos < m ? zbits[pos] : 0u;
-    }
+    if (part != (int64_t)blockIdx.x) load_bits(part);
 #pragma unroll
     for (int it = 0; it < kDkItems; ++it) {
       const int64_t pos = wbase + (int64_t)it * kWave + lane;
@@ -698,12 +705,18 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(uint32_t* __restri
   constexpr int64_t kStep = (int64_t)kOrderThreads * kPer;
   for (int b = tid; b <= kOrderBuckets; b += kOrderThreads) s_cnt[b] = 0;
   __syncthreads();
+  // with every tile in one step (a 1080p frame: 8,160 tiles) the second sweep reuses the lengths
+  // and starts held in registers instead of reading the ranges again
+  const bool one_step = n_tiles <= kStep;
+  uint32_t kept_len[kPer], kept_raw[kPer];
   for (int64_t t0 = 0; t0 < n_tiles; t0 += kStep) {
     uint32_t len[kPer];
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
       const int64_t t = t0 + (int64_t)j * kOrderThreads + tid;
-      len[j] = t < n_tiles ? run_length(ranges[t], ranges[n_tiles + t]) : 0u;
+      kept_raw[j] = t < n_tiles ? ranges[t] : 0u;
+      len[j] = t < n_tiles ? run_length(kept_raw[j], ranges[n_tiles + t]) : 0u;
+      kept_len[j] = len[j];
     }
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
@@ -733,8 +746,8 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(uint32_t* __restri
       const int64_t t = t0 + (int64_t)j * kOrderThreads + tid;
       len[j] = 0u;
       if (t < n_tiles) {
-        const uint32_t raw = ranges[t];
-        len[j] = run_length(raw, ranges[n_tiles + t]);
+        const uint32_t raw = one_step ? kept_raw[j] : ranges[t];
+        len[j] = one_step ? kept_len[j] : run_length(raw, ranges[n_tiles + t]);
         ranges[t] = raw ? ~raw : 0u;                  // plain starts for the tiles' readers
       }
     }
