@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--seed", type=int, default=1006)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras-only", action="store_true",
+                    help="run only the secondary workloads (64 views forward + backward, estimator) "
+                         "and print their JSON; for profiling them apart from the headline frame")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for scaling HBM byte counters)")
     return ap.parse_args()
@@ -65,6 +68,9 @@ def main():
     import paper_2409_16504_amd as P
     from synthetic import look_at_camera, make_surface
 
+    if args.extras_only:
+        print(json.dumps({"extras": extra_workloads(P.Renderer(0))}), flush=True)
+        return
     t0 = time.time()
     _, xyz, rgb = make_surface(args.n, args.seed, quantize=True)
     cams = [look_at_camera([0, 0, 3], width=args.width, height=args.height)]
