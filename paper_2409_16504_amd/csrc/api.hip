@@ -371,6 +371,7 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   if (state && state->ctx != ctx) return fail(PCS_ERR_INVALID_ARG, "state belongs to another context");
   const int TX = (W + kTile - 1) / kTile, TY = (H + kTile - 1) / kTile;
   const int64_t tiles_per_cam = (int64_t)TX * TY;
+  const bool narrow_rect = TX <= kNarrowRectTiles && TY <= kNarrowRectTiles;   // 4-byte rectangles
   const int64_t total_tiles = tiles_per_cam * n_cams;
   if (total_tiles >= (int64_t(1) << 31)) return fail(PCS_ERR_UNSUPPORTED, "cameras x tiles must be below 2^31");
   const int64_t n = g->n;
@@ -431,7 +432,8 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
     clear.count[2] = 2 * kTileHistWords;
     StageTimer tm(ctx, ST_PROJECT, s);
     PCS_HIP(launch_project(n, n_cams, st->dcams.as<DevCamera>(), dopt, *g, st->rec.as<float4>(),
-                           ctx->zbits.as<uint32_t>(), ctx->rect.as<uint2>(), d_zrange, d_counts, clear, s));
+                           ctx->zbits.as<uint32_t>(), ctx->rect.as<uint2>(), narrow_rect, d_zrange, d_counts,
+                           clear, s));
   }
   // The instance total reaches the host from the first depth-sort kernel (a store into a pinned
   // word, which the host polls); the (camera, depth) order needs nothing from the host (the depth
@@ -485,7 +487,7 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
       clear.p[1] = st->ranges.as<uint32_t>();
       clear.count[1] = 2 * total_tiles;
       PCS_HIP(launch_scan_binning(n, n_cams, TX, tiles_per_cam, ctx->dvals.as<uint32_t>(),
-                                  ctx->dvals_alt.as<uint32_t>(), d_depth, ctx->rect.as<uint2>(),
+                                  ctx->dvals_alt.as<uint32_t>(), d_depth, ctx->rect.as<uint2>(), narrow_rect,
                                   ctx->scan_scratch.p, d_total, st->keys.as<uint32_t>(),
                                   st->vals.as<uint32_t>(), tile_bits, ctx->tile_hist.as<uint32_t>(),
                                   clear, s));

@@ -35,6 +35,23 @@ struct DevOptions {
 // of the bounding box of the sigma_cut ellipse.
 // Binning inputs per (camera, Gaussian): the fp32 bits of the depth (0 for a culled splat) and the
 // tile rectangle (x0 | x_end << 16, y0 | y_end << 16), ends exclusive (zero for a culled splat).
+// When the frame has at most kNarrowRectTiles tile columns and rows, the rectangle is stored in
+// one word instead (x0 | x_end << 8 | y0 << 16 | y_end << 24): binning reads the rectangles in
+// depth order, one random 4-byte read per splat rather than 8.
+constexpr int kNarrowRectTiles = 255;
+__device__ __forceinline__ void store_rect(uint2* rect, int64_t i, bool narrow, uint32_t x0,
+                                           uint32_t x_end, uint32_t y0, uint32_t y_end) {
+  if (narrow)
+    reinterpret_cast<uint32_t*>(rect)[i] = x0 | (x_end << 8) | (y0 << 16) | (y_end << 24);
+  else
+    rect[i] = make_uint2(x0 | (x_end << 16), y0 | (y_end << 16));
+}
+// The rectangle in its wide form, whichever form it was stored in.
+__device__ __forceinline__ uint2 load_rect(const uint2* rect, int64_t i, bool narrow) {
+  if (!narrow) return rect[i];
+  const uint32_t c = reinterpret_cast<const uint32_t*>(rect)[i];
+  return make_uint2((c & 0xFFu) | (((c >> 8) & 0xFFu) << 16), ((c >> 16) & 0xFFu) | ((c >> 24) << 16));
+}
 
 // ---- wave64 helpers -------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
@@ -148,8 +165,8 @@ hipError_t launch_init_small(uint32_t* small, const DevCamera* cams, int n_cams,
                              hipStream_t s);
 hipError_t launch_project(int64_t n, int n_cams, const DevCamera* cams, const DevOptions& opt,
                           const pcs_gaussians& g, float4* rec, uint32_t* zbits, uint2* rect,
-                          uint32_t* zrange, unsigned long long* count_slots, const ClearSpans& clear,
-                          hipStream_t s);
+                          bool narrow_rect, uint32_t* zrange, unsigned long long* count_slots,
+                          const ClearSpans& clear, hipStream_t s);
 
 // Exclusive scan of n u32 values in[gather[j]] (no gather: in[j]); writes out[n] and *total (u64).
 // gather is gather1 when sel is set and *sel is odd, else gather0. Scratch from scan_scratch_bytes.
@@ -184,11 +201,13 @@ constexpr int64_t kTileHistWords = (int64_t)kTileHistCopies * kTileHistPasses * 
 // entries' tile keys (global tile ids, row-major within a rectangle) and Gaussian indices at
 // those offsets, counting the keys' 8-bit digits into hist (kTileHistWords, zeroed beforehand)
 // for the tile sort (launch_sort with ext_hist). scan_scratch must be cleared (scan_clear_words);
-// *total receives the instance count.
+// *total receives the instance count. rect holds the rectangles in their narrow form when
+// narrow_rect is set (store_rect).
 hipError_t launch_scan_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_cam,
                                const uint32_t* order0, const uint32_t* order1,
-                               const uint32_t* passes, const uint2* rect, void* scan_scratch,
-                               uint64_t* total, uint32_t* keys, uint32_t* vals, int tile_bits,
+                               const uint32_t* passes, const uint2* rect, bool narrow_rect,
+                               void* scan_scratch, uint64_t* total, uint32_t* keys, uint32_t* vals,
+                               int tile_bits,
                                uint32_t* hist, const ClearSpans& clear, hipStream_t s);
 
 // Stable LSD radix sort of (key, value) pairs over key bits [0, bits), K = uint32_t or uint64_t;

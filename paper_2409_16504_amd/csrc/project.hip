@@ -33,7 +33,8 @@ __global__ __launch_bounds__(256) void k_project(
     const float* __restrict__ mean, const float* __restrict__ quat,
     const float* __restrict__ scale, const float* __restrict__ opac,
     const float* __restrict__ rgb, const float* __restrict__ nrm, float4* __restrict__ rec,
-    uint32_t* __restrict__ zbits_out, uint2* __restrict__ rect, uint32_t* __restrict__ zrange,
+    uint32_t* __restrict__ zbits_out, uint2* __restrict__ rect, bool narrow_rect,
+    uint32_t* __restrict__ zrange,
     unsigned long long* __restrict__ count_slots, ClearSpans clear) {
   clear_spans(clear, ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x,
               (int64_t)gridDim.x * gridDim.y * blockDim.x);
@@ -77,8 +78,8 @@ __global__ __launch_bounds__(256) void k_project(
       zbits = __float_as_uint(zc);
       my_count = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
       zbits_out[out] = zbits;
-      rect[out] = make_uint2((uint32_t)x0 | ((uint32_t)(x1 + 1) << 16),
-                             (uint32_t)y0 | ((uint32_t)(y1 + 1) << 16));
+      store_rect(rect, out, narrow_rect, (uint32_t)x0, (uint32_t)(x1 + 1), (uint32_t)y0,
+                 (uint32_t)(y1 + 1));
       float4* r = rec + out * kRecFloat4;
       r[0] = make_float4(u, v, o, zc);
       // half extents of the sigma_cut ellipse's bounding box, padded so that pixels outside it
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(256) void k_project(
       r[3] = make_float4(nx, ny, nz, 0.0f);
     } else {
       zbits_out[out] = 0u;                 // a visible depth is above z_near > 0: never zero bits
-      rect[out] = make_uint2(0u, 0u);
+      store_rect(rect, out, narrow_rect, 0u, 0u, 0u, 0u);
     }
   }
   // depth-bit range and instance total of the block: block reduction, then one atomic each into
@@ -168,12 +169,13 @@ hipError_t launch_init_small(uint32_t* small, const DevCamera* cams, int n_cams,
 
 hipError_t launch_project(int64_t n, int n_cams, const DevCamera* cams, const DevOptions& opt,
                           const pcs_gaussians& g, float4* rec, uint32_t* zbits, uint2* rect,
-                          uint32_t* zrange, unsigned long long* count_slots, const ClearSpans& clear,
-                          hipStream_t s) {
+                          bool narrow_rect, uint32_t* zrange, unsigned long long* count_slots,
+                          const ClearSpans& clear, hipStream_t s) {
   if (n <= 0 || n_cams <= 0) return hipSuccess;
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)n_cams);
   hipLaunchKernelGGL(k_project, grid, dim3(256), 0, s, n, cams, opt, g.mean, g.quat, g.scale,
-                     g.opacity, g.rgb, g.normal, rec, zbits, rect, zrange, count_slots, clear);
+                     g.opacity, g.rgb, g.normal, rec, zbits, rect, narrow_rect, zrange, count_slots,
+                     clear);
   return hipGetLastError();
 }
 

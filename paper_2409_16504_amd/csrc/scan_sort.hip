@@ -169,7 +169,7 @@ constexpr int kBinSlots = 4;                      // output slots searched toget
 __global__ __launch_bounds__(kThreads) void k_scan_bin(
     int64_t total, uint32_t n, int TX, uint32_t tiles_per_cam, const uint32_t* __restrict__ order0,
     const uint32_t* __restrict__ order1, const uint32_t* __restrict__ passes,
-    const uint2* __restrict__ rect, int64_t n_parts, uint64_t* __restrict__ status,
+    const uint2* __restrict__ rect, bool narrow_rect, int64_t n_parts, uint64_t* __restrict__ status,
     uint64_t* __restrict__ instances, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
     int n_digits, uint32_t* __restrict__ hist, ClearSpans clear) {
   __shared__ uint32_t s_off[kBinPart];          // block-relative offset of each position
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_bin(
   for (int k = 0; k < kBinItems; ++k) idx[k] = base + k < total ? order[base + k] : 0u;
 #pragma unroll
   for (int k = 0; k < kBinItems; ++k) {
-    r[k] = base + k < total ? rect[idx[k]] : make_uint2(0u, 0u);
+    r[k] = base + k < total ? load_rect(rect, idx[k], narrow_rect) : make_uint2(0u, 0u);
     cnt[k] = rect_count(r[k]);
   }
   uint64_t sum = 0;
@@ -821,15 +821,15 @@ hipError_t launch_depth_keys_hist(int64_t m, const uint32_t* zbits,
 
 hipError_t launch_scan_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_cam,
                                const uint32_t* order0, const uint32_t* order1,
-                               const uint32_t* passes, const uint2* rect, void* scan_scratch,
-                               uint64_t* total, uint32_t* keys, uint32_t* vals, int tile_bits,
+                               const uint32_t* passes, const uint2* rect, bool narrow_rect,
+                               void* scan_scratch, uint64_t* total, uint32_t* keys, uint32_t* vals, int tile_bits,
                                uint32_t* hist, const ClearSpans& clear, hipStream_t s) {
   const int64_t cn = n * n_cams;
   if (cn == 0) return hipSuccess;
   if (tile_bits > 8 * kTileHistPasses) return hipErrorInvalidValue;
   const int64_t parts = (cn + kBinPart - 1) / kBinPart;
   hipLaunchKernelGGL(k_scan_bin, dim3((unsigned)parts), dim3(kThreads), 0, s, cn, (uint32_t)n, TX,
-                     (uint32_t)tiles_per_cam, order0, order1, passes, rect, parts,
+                     (uint32_t)tiles_per_cam, order0, order1, passes, rect, narrow_rect, parts,
                      reinterpret_cast<uint64_t*>(scan_scratch), total, keys, vals, (tile_bits + 7) / 8,
                      hist, clear);
   return hipGetLastError();

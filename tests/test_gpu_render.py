@@ -77,6 +77,25 @@ def test_many_cameras_in_batches(R):
     assert all((ref["n_contrib"][c] > 0).sum() > 100 for c in range(19))
 
 
+@pytest.mark.parametrize("W,H", [(4080, 64), (4112, 64), (64, 4080), (64, 4112)])
+def test_rectangle_forms_at_the_tile_limit(R, W, H):
+    """255 tile columns (or rows) keep the 4-byte tile rectangles; 257 take the 8-byte form. The
+    focal length along the long side spreads the splats over all of its tiles."""
+    import dataclasses
+    rng = np.random.default_rng(41)
+    g = random_gaussians(1500, rng, scale_range=(0.005, 0.05))
+    cam = dataclasses.replace(look_at_camera([0, 0, 3], width=W, height=H),
+                              fx=float(np.float32(W)), fy=float(np.float32(H)))
+    imgs, bins, _ = gpu_render(R, g, [cam])
+    ref = oracle.render(g, [cam], mode="ref")
+    TX, TY = (W + 15) // 16, (H + 15) // 16
+    tiles = (ref["keys"] >> np.uint64(32)).astype(np.int64)
+    long_side = tiles % TX if W > H else tiles // TX
+    assert long_side.max() >= max(TX, TY) - 2                 # the last tiles are used
+    check_bins(bins, ref, TX * TY)
+    check_images(imgs, bins, ref, 5.0)
+
+
 def test_options_background_and_thresholds(R):
     g, cams = c1_scene()
     opts = dict(bg=(0.25, 0.5, 1.0), alpha_min=0.02, alpha_max=0.95, t_eps=1e-3, lowpass=0.1, sigma_cut=2.5)
