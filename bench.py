@@ -33,6 +33,12 @@ FP32_VALU_PEAK_TFLOPS = 78.6     # 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 G
 PROJECT_READ_B = 68      # mean 12 + quat 16 + scale 12 + opacity 4 + rgb 12 + normal 12
 PROJECT_WRITE_VIS_B = 76  # 64 B splat record + 4 B depth bits + 8 B tile rectangle
 PROJECT_WRITE_CULL_B = 12  # depth bits and rectangle, zero
+NARROW_RECT_TILES = 255    # up to this many tile columns and rows a tile rectangle takes 4 B, not 8
+
+
+def rect_bytes(W, H):
+    """Bytes of one stored tile rectangle for a W x H frame."""
+    return 4 if max((W + 15) // 16, (H + 15) // 16) <= NARROW_RECT_TILES else 8
 SORT_PASS_B = 16         # read + write of a 4 B key and a 4 B value
 # Compositing FLOP per (pixel, list entry) visit and per blended splat.
 COMPOSITE_VISIT_FLOP = 9     # offset (2), conic quadratic form (7)
@@ -308,9 +314,11 @@ def stage_rooflines(per_stage, n, m, bins, W, H):
     depth_bits = int(z.max() - z.min()).bit_length() if m else 0
     tiles = int(bins["ranges"].shape[1])
     tile_bits = int(tiles - 1).bit_length()
+    shrink = 8 - rect_bytes(W, H)                              # rectangle bytes saved per splat
     byts = {
-        "project": n * PROJECT_READ_B + vis * PROJECT_WRITE_VIS_B + (n - vis) * PROJECT_WRITE_CULL_B,
-        "binning": n * 12 + m * 8,                                 # order + gathered rectangle; key+value
+        "project": n * PROJECT_READ_B + vis * (PROJECT_WRITE_VIS_B - shrink) +
+                   (n - vis) * (PROJECT_WRITE_CULL_B - shrink),
+        "binning": n * (4 + 8 - shrink) + m * 8,                   # order + gathered rectangle; key+value
         "sort": n * (12 + SORT_PASS_B * ((depth_bits + 7) // 8)) +      # depth keys, passes
                 m * SORT_PASS_B * ((tile_bits + 7) // 8),                 # (histograms come fused)
         "ranges": tiles * 24,                                      # tile order: runs read twice, starts + order written
@@ -330,7 +338,13 @@ def roofline(per_stage, n, m, bins, visits, blends):
     frame = {k: v for k, v in per_stage.items() if k in ("project", "binning", "sort", "ranges", "composite")}
     dom = "composite" if "composite" in frame else max(frame, key=frame.get)
     ms = frame[dom]
-    if dom == "composite" and visits is not None:
+    if dom == "composite":
+        if visits is None:
+            # the FLOP count needs the oracle's visit and blend counts, which only the CPU
+            # baseline leg computes: no achieved figure without them
+            return dict(kernel=dom, bound="alu", achieved=None, peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
+                        frac=None, traffic=measured_traffic(dom), avg_ms=ms,
+                        note="achieved needs the CPU baseline leg (run without --no-cpu-baseline)")
         flop = COMPOSITE_VISIT_FLOP * visits + COMPOSITE_BLEND_FLOP * blends
         ach = flop / (ms * 1e-3) / 1e12
         return dict(kernel=dom, bound="alu", achieved=ach, peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",

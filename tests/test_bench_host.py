@@ -70,12 +70,18 @@ def test_stage_bytes(bench):
     per_stage = dict(project=1e-6, binning=1e-6, sort=1e-6, ranges=1e-6)    # ms
     out = bench.stage_rooflines(per_stage, n, m, bins, 64, 64)
     vis = 6
-    assert out["project"]["bytes"] == n * 68 + vis * 76 + (n - vis) * 12
-    assert out["binning"]["bytes"] == n * 12 + m * 8
+    # a 64 x 64 frame stores its tile rectangles in 4 bytes
+    assert out["project"]["bytes"] == n * 68 + vis * 72 + (n - vis) * 8
+    assert out["binning"]["bytes"] == n * 8 + m * 8
     assert out["sort"]["bytes"] == n * (12 + 16 * 3) + m * 16 * 2
     assert out["ranges"]["bytes"] == 300 * 24
     # bytes over the stage time as GB/s, and the fraction of the 8 TB/s peak
-    assert out["binning"]["gbs"] == pytest.approx((n * 12 + m * 8) / 1e-9 / 1e9, rel=1e-3)
+    assert out["binning"]["gbs"] == pytest.approx((n * 8 + m * 8) / 1e-9 / 1e9, rel=1e-3)
+    # 257 tile columns: the 8-byte form
+    wide = bench.stage_rooflines(per_stage, n, m, bins, 4112, 64)
+    assert wide["project"]["bytes"] == n * 68 + vis * 76 + (n - vis) * 12
+    assert wide["binning"]["bytes"] == n * 12 + m * 8
+    assert bench.rect_bytes(4080, 4080) == 4 and bench.rect_bytes(64, 4112) == 8
     assert out["binning"]["frac"] == pytest.approx(out["binning"]["gbs"] / 8000.0, rel=1e-3)
 
 
@@ -89,3 +95,13 @@ def test_composite_roofline_is_alu_bound(bench):
     assert r["achieved"] == pytest.approx(flop / 0.5e-3 / 1e12)
     assert r["frac"] == pytest.approx(r["achieved"] / 78.6)
     assert r["avg_ms"] == 0.5
+
+
+def test_composite_roofline_without_visit_counts_reports_no_figure(bench):
+    """Without the CPU baseline leg there are no visit counts: the entry stays ALU-bound and
+    gives no achieved figure rather than a bytes-based one."""
+    bins = _bins(4, [0, 1], [3, 4], [0, 1])
+    per_stage = dict(project=0.01, binning=0.01, sort=0.02, ranges=0.005, composite=0.5)
+    r = bench.roofline(per_stage, 2, 2, bins, None, None)
+    assert r["kernel"] == "composite" and r["bound"] == "alu"
+    assert r["achieved"] is None and r["frac"] is None and r["avg_ms"] == 0.5
