@@ -84,7 +84,7 @@ typedef struct pcs_options {
 /* Output images, device FP32, planar per camera: rgb[C][3][H][W], normal[C][3][H][W],
  * depth[C][H][W] (sum of T_k alpha_k z_k, not normalised), alpha[C][H][W] (= 1 - final
  * transmittance). Any pointer may be NULL except rgb. For pcs_render_backward the same struct
- * carries the upstream gradients of rgb, normal and depth (alpha ignored; NULL = zero). */
+ * carries the upstream gradients of rgb, normal, depth and alpha (NULL = zero). */
 typedef struct pcs_images {
   float* rgb;
   float* normal;
@@ -134,7 +134,8 @@ void pcs_state_destroy(pcs_state* st);
 void pcs_options_default(pcs_options* out);
 
 /* Forward render (Section 3.1, Eq. 1-4) of `n_cams` cameras (host array) that share one width and
- * height. Limits: n < 2^31, instance count M < 2^30, n_cams * tiles < 2^32. If `state` is non-NULL
+ * height. Limits (PCS_ERR_UNSUPPORTED beyond them): n < 2^31, n * n_cams < 2^30, instance count
+ * M < 2^30, n_cams * tiles < 2^31. If `state` is non-NULL
  * it receives what pcs_render_backward and pcs_state_bins need (the flag SAVE_STATE is implied);
  * the state stays valid until it is passed to another render or destroyed. */
 int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camera* cams,
@@ -145,7 +146,9 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
  * in `state`, given upstream gradients `grad_out` (same layout as the images). The compositing
  * is recomputed back to front from the saved per-pixel transmittance and last-contributor
  * index; per-splat screen-space gradients are reduced across each 64-lane wavefront and added
- * atomically, then chained through the EWA projection to the Gaussian parameters. */
+ * atomically, then chained through the EWA projection to the Gaussian parameters.
+ * The saved options must leave the final transmittance recoverable: t_eps * (1 - alpha_max) >= 2^-100
+ * (PCS_ERR_UNSUPPORTED otherwise, e.g. for t_eps = 0). */
 int pcs_render_backward(pcs_context* ctx, const pcs_state* state, const pcs_images* grad_out,
                         const pcs_grads* grads, void* stream);
 

@@ -57,8 +57,8 @@ def _setup(L):
     L.orc_composite.argtypes = ([i64] + [vp] * 9 + [i64, vp, vp, ctypes.c_uint64, i32, i32, i32, vp,
                                 vp, i64] + [vp] * 8)
     L.orc_composite.restype = i64
-    L.orc_backward.argtypes = ([i64] + [vp] * 7 + [i32, vp, i32, i32, i32, vp, vp, vp, vp, i64, vp, vp,
-                               vp])
+    L.orc_backward.argtypes = ([i64] + [vp] * 7 + [i32, vp, i32, i32, i32, vp, vp, vp, vp, vp, i64, vp,
+                               vp, vp])
     L.orc_backward.restype = None
 
 
@@ -226,7 +226,7 @@ GRAD_LAYOUT = dict(mean=(0, 3), cov6=(3, 9), quat=(9, 13), scale=(13, 16), opaci
 
 def backward(g: dict, cams: list, grad_out: dict, opts=None, tile=16, cov6=None, sabs_for=-1):
     """FP64 adjoint of the FP64 render. ``grad_out`` holds rgb [C][3][H][W], normal [C][3][H][W]
-    and depth [C][H][W]. Returns (grads, sabs, signature): dicts keyed like GRAD_LAYOUT with
+    and depth [C][H][W], optionally alpha [C][H][W]. Returns (grads, sabs, signature): dicts keyed like GRAD_LAYOUT with
     planar (k, n) float64 arrays; ``sabs`` is the sum over pixels of each per-pixel term's absolute
     value (``sabs_for``: -1 every Gaussian, i only Gaussian i, -2 none)."""
     n = g["opacity"].shape[-1]
@@ -238,12 +238,14 @@ def backward(g: dict, cams: list, grad_out: dict, opts=None, tile=16, cov6=None,
     gr = np.ascontiguousarray(grad_out["rgb"], dtype=np.float64)
     gn = np.ascontiguousarray(grad_out["normal"], dtype=np.float64)
     gd = np.ascontiguousarray(grad_out["depth"], dtype=np.float64)
+    ga = grad_out.get("alpha")
+    ga = None if ga is None else np.ascontiguousarray(ga, dtype=np.float64)
     grad = np.zeros((23, n))
     sabs = np.zeros((23, n))
     sig = np.zeros(1, np.uint64)
     lib().orc_backward(n, _p(d["mean"]), _p(d["quat"]), _p(d["scale"]), _p(c6), _p(d["opacity"]),
                        _p(d["rgb"]), _p(d["normal"]), len(cams), _p(camv), W, H, tile,
-                       _p(options_vector(opts)), _p(gr), _p(gn), _p(gd), int(sabs_for), _p(grad),
+                       _p(options_vector(opts)), _p(gr), _p(gn), _p(gd), _p(ga), int(sabs_for), _p(grad),
                        _p(sabs), _p(sig))
     split = lambda a: {k: a[lo:hi] for k, (lo, hi) in GRAD_LAYOUT.items()}  # noqa: E731
     return split(grad), split(sabs), int(sig[0])

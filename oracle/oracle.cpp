@@ -579,7 +579,8 @@ void pull_back(const Geo& G, const double* cam, const double* sg, double* pg, do
 extern "C" {
 
 // FP64 adjoint of the FP64 render of n_cams cameras. grad images: grad_rgb [C][3][H][W],
-// grad_nrm [C][3][H][W], grad_depth [C][H][W] (double). Outputs: grad[PG_COUNT][n] (planar, see
+// grad_nrm [C][3][H][W], grad_depth [C][H][W] and, if not NULL, grad_alpha [C][H][W] (double; the
+// alpha output is 1 - the final transmittance, the covered fraction of the pixel). Outputs: grad[PG_COUNT][n] (planar, see
 // layout above) accumulated over cameras, sabs[PG_COUNT][n] the sum over pixels of the absolute
 // per-pixel contribution, and sig: a 64-bit signature of the discrete decisions (which splats each
 // pixel blends and where it stops), used to detect when a finite-difference step changes them.
@@ -589,8 +590,8 @@ void orc_backward(int64_t n, const double* mean, const double* quat, const doubl
                   const double* cov6, const double* opac, const double* rgb, const double* nrm,
                   int n_cams, const double* cams /*[C][16]*/, int W, int H, int tile,
                   const float* opt, const double* grad_rgb, const double* grad_nrm,
-                  const double* grad_depth, int64_t only_gauss, double* grad, double* sabs,
-                  uint64_t* sig) {
+                  const double* grad_depth, const double* grad_alpha, int64_t only_gauss,
+                  double* grad, double* sabs, uint64_t* sig) {
   const int TX = (W + tile - 1) / tile, TY = (H + tile - 1) / tile;
   const int64_t ntiles = (int64_t)TX * TY, HW = (int64_t)W * H;
   const double cut2 = (double)opt[OPT_SIGMA_CUT] * (double)opt[OPT_SIGMA_CUT];
@@ -655,6 +656,7 @@ void orc_backward(int64_t n, const double* mean, const double* quat, const doubl
         gch[3 + ch] = grad_nrm[((int64_t)cam_i * 3 + ch) * HW + pid];
       }
       gch[6] = grad_depth[(int64_t)cam_i * HW + pid];
+      const double g_cover = grad_alpha ? grad_alpha[(int64_t)cam_i * HW + pid] : 0.0;
       double behind[7] = {T * bg[0], T * bg[1], T * bg[2], 0, 0, 0, 0};
       for (int64_t h = (int64_t)hits.size() - 1; h >= 0; --h) {
         const Hit& hit = hits[h];
@@ -668,6 +670,8 @@ void orc_backward(int64_t n, const double* mean, const double* quat, const doubl
           dL_dalpha += gch[ch] * (hit.T * f[ch] - behind[ch] / (1.0 - hit.alpha));
           behind[ch] += wgt * f[ch];
         }
+        // alpha output 1 - prod_j (1 - alpha_j): its derivative in alpha_h is T_final / (1 - alpha_h)
+        dL_dalpha += g_cover * T / (1.0 - hit.alpha);
         for (int ch = 0; ch < 3; ++ch) {
           px_sg[SG_R + ch] = gch[ch] * wgt;
           px_sg[SG_NX + ch] = gch[3 + ch] * wgt;

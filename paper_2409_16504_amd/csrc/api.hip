@@ -82,6 +82,10 @@ int bit_length(uint64_t v) {
   return b;
 }
 
+// Smallest final transmittance the adjoint accepts (2^-100): far above the smallest normal float,
+// so that the per-splat transmittances recovered from it by division keep full precision.
+constexpr double kMinFinalTransmittance = 7.888609052210118e-31;
+
 bool finite_camera(const pcs_camera& c) {
   for (float v : c.T) if (!std::isfinite(v)) return false;
   for (float v : c.t) if (!std::isfinite(v)) return false;
@@ -376,7 +380,8 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   if (total_tiles >= (int64_t(1) << 31)) return fail(PCS_ERR_UNSUPPORTED, "cameras x tiles must be below 2^31");
   const int64_t n = g->n;
   const int64_t cn = n * n_cams;
-  if (cn >= (int64_t(1) << 32)) return fail(PCS_ERR_UNSUPPORTED, "n x cameras must be below 2^32");
+  // the depth sort's chained scan carries counts in 30-bit status words
+  if (cn >= (int64_t(1) << 30)) return fail(PCS_ERR_UNSUPPORTED, "n x cameras must be below 2^30");
   PCS_HIP(hipSetDevice(ctx->device));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 
@@ -538,6 +543,13 @@ int pcs_render_backward(pcs_context* ctx, const pcs_state* st, const pcs_images*
   if (!ctx || !st || !grad_out || !grads) return fail(PCS_ERR_INVALID_ARG, "NULL argument");
   if (st->ctx != ctx) return fail(PCS_ERR_INVALID_ARG, "state belongs to another context");
   if (!st->valid) return fail(PCS_ERR_INVALID_ARG, "state holds no completed forward render");
+  // the adjoint recovers each splat's transmittance from the final one by division; the final
+  // transmittance is at least t_eps (1 - alpha_max), which must stay a normal float with room to
+  // spare, or the recovered values (and every gradient through them) collapse to zero
+  if (!((double)st->opt.t_eps * (1.0 - (double)st->opt.alpha_max) >= kMinFinalTransmittance))
+    return fail(PCS_ERR_UNSUPPORTED,
+                "the backward needs t_eps * (1 - alpha_max) >= 2^-100 (the final transmittance "
+                "must stay recoverable); render with a larger t_eps");
   PCS_HIP(hipSetDevice(ctx->device));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int64_t cn = st->n * st->C;

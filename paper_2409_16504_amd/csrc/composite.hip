@@ -254,7 +254,7 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(
     const float* __restrict__ t_final,
     const int32_t* __restrict__ n_contrib, const float* __restrict__ g_rgb,
     const float* __restrict__ g_nrm, const float* __restrict__ g_depth,
-    float* __restrict__ sgrad) {
+    const float* __restrict__ g_alpha, float* __restrict__ sgrad) {
   __shared__ float4 s_f0[kWave], s_f1[kWave], s_f2[kWave], s_f3[kWave];   // blend forms
   __shared__ uint32_t s_g[kWave];
   int64_t opos;
@@ -281,6 +281,7 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(
   float T = 1.0f;
   int32_t nc = 0;
   float g[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float g_cover = 0.f;                      // upstream gradient of the alpha output 1 - T_final
   if (inside) {
     T = t_final[cam * HW + pix];
     nc = n_contrib[cam * HW + pix];
@@ -288,10 +289,13 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(
     if (g_rgb) { g[0] = g_rgb[c3 + pix]; g[1] = g_rgb[c3 + HW + pix]; g[2] = g_rgb[c3 + 2 * HW + pix]; }
     if (g_nrm) { g[3] = g_nrm[c3 + pix]; g[4] = g_nrm[c3 + HW + pix]; g[5] = g_nrm[c3 + 2 * HW + pix]; }
     if (g_depth) g[6] = g_depth[cam * HW + pix];
+    if (g_alpha) g_cover = g_alpha[cam * HW + pix];
   }
   // g . (what lies behind the current splat), with behind = sum_{j>k} T_j a_j f_j + T_final * bg:
-  // g is fixed along the walk, so the seven-channel sum enters only through this dot product
-  float gb = T * fmaf(g[0], opt.bg[0], fmaf(g[1], opt.bg[1], g[2] * opt.bg[2]));
+  // g is fixed along the walk, so the seven-channel sum enters only through this dot product. The
+  // alpha output 1 - T_final adds -g_alpha T_final to it: like the background term, it scales with
+  // T_final, whose derivative in alpha_k is -T_final / (1 - alpha_k).
+  float gb = T * (fmaf(g[0], opt.bg[0], fmaf(g[1], opt.bg[1], g[2] * opt.bg[2])) - g_cover);
   // the quadrant's furthest last contributor bounds the walk
   int32_t max_nc = nc;
 #pragma unroll
@@ -567,7 +571,7 @@ hipError_t launch_composite_backward(int64_t n, int n_cams, int W, int H, const 
   const int64_t blocks = (total + 7) / 8 * 32;      // four single-wavefront blocks per tile
   hipLaunchKernelGGL(k_composite_bwd, dim3((unsigned)blocks), dim3(kWave), 0, s, n, W, H, TX,
                      tiles_per_cam, total, rec, vals, ranges, order, opt, t_final, n_contrib,
-                     grad_out.rgb, grad_out.normal, grad_out.depth, sgrad);
+                     grad_out.rgb, grad_out.normal, grad_out.depth, grad_out.alpha, sgrad);
   return hipGetLastError();
 }
 

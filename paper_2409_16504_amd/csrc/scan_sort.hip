@@ -865,7 +865,8 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
                        int pass_begin, int pass_end, uint32_t* ranges, int64_t n_tiles) {
   *result_in_alt = false;
   if (m <= 1 || bits <= 0) return hipSuccess;
-  if (m >= (int64_t(1) << 32)) return hipErrorInvalidValue;    // the scatter indexes in 32 bits
+  // the chained scan's status words carry 30-bit counts
+  if (m >= (int64_t(1) << 30)) return hipErrorInvalidValue;
   const int n_passes = (bits + 7) / 8;
   if (pass_end < 0 || pass_end > n_passes) pass_end = n_passes;
   const int64_t parts = (m + kPart - 1) / kPart;    // partitions of the histogram

@@ -153,12 +153,12 @@ class Renderer:
         C, H, W, n = state.shape
         dev = torch.device("cuda", self.device)
         gi = {}
-        for k in ("rgb", "normal", "depth"):
+        for k in ("rgb", "normal", "depth", "alpha"):
             t = grad_out.get(k)
             if t is not None:
                 t = t.to(device=dev, dtype=torch.float32).contiguous()
             gi[k] = t
-        imgs = Images(_ptr(gi["rgb"]), _ptr(gi["normal"]), _ptr(gi["depth"]), None)
+        imgs = Images(_ptr(gi["rgb"]), _ptr(gi["normal"]), _ptr(gi["depth"]), _ptr(gi["alpha"]))
         grads = {k: torch.zeros((r, n) if r else (n,), device=dev, dtype=torch.float32)
                  for k, r in dict(mean=3, quat=4, scale=3, opacity=None, rgb=3, normal=3).items()}
         if want_cov:
@@ -286,7 +286,9 @@ def _hip_memcpy_d2h(dst: int, src: int, nbytes: int):
 
 class RenderFunction(torch.autograd.Function):
     """Differentiable render: images from (mean, quat, scale, opacity, rgb, normal); the backward
-    is the hand-written adjoint kernel of libpcsplat."""
+    is the hand-written adjoint kernel of libpcsplat. All four outputs (rgb, normal, depth, alpha)
+    carry gradients. The adjoint reads the Gaussians the forward rendered: they are saved for
+    backward, so modifying one in place in between makes autograd raise."""
 
     @staticmethod
     def forward(ctx, mean, quat, scale, opacity, rgb, normal, renderer, cams, opts):
@@ -294,13 +296,16 @@ class RenderFunction(torch.autograd.Function):
                  opacity=opacity.contiguous(), rgb=rgb.contiguous(), normal=normal.contiguous())
         state = RenderState(renderer)
         out = renderer.render(g, cams, opts, state=state)
+        ctx.save_for_backward(*(g[k] for k in ("mean", "quat", "scale", "opacity", "rgb", "normal")))
         ctx.renderer = renderer
         ctx.state = state
         return out["rgb"], out["normal"], out["depth"], out["alpha"]
 
     @staticmethod
     def backward(ctx, g_rgb, g_nrm, g_depth, g_alpha):
-        grads = ctx.renderer.render_backward(ctx.state, dict(rgb=g_rgb, normal=g_nrm, depth=g_depth))
+        ctx.saved_tensors          # raises if a saved Gaussian tensor was modified in place
+        grads = ctx.renderer.render_backward(ctx.state, dict(rgb=g_rgb, normal=g_nrm, depth=g_depth,
+                                                             alpha=g_alpha))
         ctx.state = None
         return (grads["mean"], grads["quat"], grads["scale"], grads["opacity"], grads["rgb"],
                 grads["normal"], None, None, None)

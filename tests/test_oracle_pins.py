@@ -405,19 +405,25 @@ def _fd_scene():
     C, H, W = 2, 36, 40
     grng = np.random.default_rng(78)
     go = dict(rgb=grng.normal(size=(C, 3, H, W)), normal=grng.normal(size=(C, 3, H, W)),
-              depth=grng.normal(size=(C, H, W)))
+              depth=grng.normal(size=(C, H, W)), alpha=grng.normal(size=(C, H, W)))
     return g, cams, go
 
 
-def _loss(g, cams, go, cov6=None):
-    img = oracle.render(g, cams, mode="f64", cov6=cov6)
+def _loss(g, cams, go, cov6=None, opts=None):
+    img = oracle.render(g, cams, opts, mode="f64", cov6=cov6)
     return float((img["rgb"] * go["rgb"]).sum() + (img["normal"] * go["normal"]).sum()
-                 + (img["depth"] * go["depth"]).sum())
+                 + (img["depth"] * go["depth"]).sum() + (img["alpha"] * go["alpha"]).sum())
 
 
-def test_adjoint_matches_finite_differences():
+# default options, and a background colour with an alpha clamp that binds (opacities up to 0.95
+# against alpha_max 0.8) and a stop threshold far below the default
+FD_OPTIONS = [None, dict(bg=(0.3, 0.6, 0.2), alpha_max=0.8, t_eps=1e-7)]
+
+
+@pytest.mark.parametrize("opts", FD_OPTIONS)
+def test_adjoint_matches_finite_differences(opts):
     g, cams, go = _fd_scene()
-    grads, sabs, sig0 = oracle.backward(g, cams, go)
+    grads, sabs, sig0 = oracle.backward(g, cams, go, opts)
     params = [("mean", 3), ("quat", 4), ("scale", 3), ("opacity", 1), ("rgb", 3), ("normal", 3)]
     checked = skipped = 0
     for i in range(10):
@@ -430,12 +436,12 @@ def test_adjoint_matches_finite_differences():
                 gm = {kk: vv.copy() for kk, vv in g.items()}
                 (gp[name] if name != "opacity" else gp[name][None, :])[c, i] += h
                 (gm[name] if name != "opacity" else gm[name][None, :])[c, i] -= h
-                _, _, sp = oracle.backward(gp, cams, go, sabs_for=-2)
-                _, _, sm = oracle.backward(gm, cams, go, sabs_for=-2)
+                _, _, sp = oracle.backward(gp, cams, go, opts, sabs_for=-2)
+                _, _, sm = oracle.backward(gm, cams, go, opts, sabs_for=-2)
                 if sp != sig0 or sm != sig0:
                     skipped += 1
                     continue
-                fd = (_loss(gp, cams, go) - _loss(gm, cams, go)) / (2 * h)
+                fd = (_loss(gp, cams, go, opts=opts) - _loss(gm, cams, go, opts=opts)) / (2 * h)
                 an = grads[name][c, i]
                 tol = 1e-6 * sabs[name][c, i] + 1e-7
                 assert abs(fd - an) <= tol, (name, c, i, fd, an, sabs[name][c, i])
