@@ -9,8 +9,11 @@ computes (Section 3.1):
 * the 3-sigma splat boundary, (tile | depth) keys and their lexicographic sort;
 * front-to-back alpha blending of RGB, normal and depth (Eq. 1 with the opacity of Eq. 2);
 * the FP64 adjoint of the render (``backward``);
-* kNN-PCA surfel ellipsoids (``knn_pca``), a tiny-scene brute-force renderer (``brute``) and the
-  sparse-convolution estimator reference (``estimator``), in their own modules.
+* the FP64 pull-back of screen-space gradients to the Gaussian parameters alone (``pull_back``);
+* kNN-PCA surfel ellipsoids (``knn_pca``), a tiny-scene brute-force renderer (``brute``), the
+  sparse-convolution estimator reference (``estimator``), the image metrics PSNR and SSIM
+  (``metrics``) and a second, numpy.float32 emulation of the exact-FP32 projection
+  (``emulate32``), in their own modules.
 
 ``render(..., mode="ref")`` composites in FP64 from the exact-FP32 projection (the image the GPU
 is held to); ``mode="f64"`` runs every step in FP64.
@@ -60,6 +63,8 @@ def _setup(L):
     L.orc_backward.argtypes = ([i64] + [vp] * 7 + [i32, vp, i32, i32, i32, vp, vp, vp, vp, vp, i64, vp,
                                vp, vp])
     L.orc_backward.restype = None
+    L.orc_pull_back.argtypes = [i64] + [vp] * 8
+    L.orc_pull_back.restype = None
 
 
 def options_vector(opts=None) -> np.ndarray:
@@ -249,3 +254,20 @@ def backward(g: dict, cams: list, grad_out: dict, opts=None, tile=16, cov6=None,
                        _p(sabs), _p(sig))
     split = lambda a: {k: a[lo:hi] for k, (lo, hi) in GRAD_LAYOUT.items()}  # noqa: E731
     return split(grad), split(sabs), int(sig[0])
+
+
+SCREEN_GRADS = ("u", "v", "A", "B", "C", "opacity", "depth", "r", "g", "b", "nx", "ny", "nz")
+
+
+def pull_back(g: dict, cam, sgrad: np.ndarray, opts=None, cov6=None) -> dict:
+    """FP64 chain of screen-space gradients ``sgrad`` [13][n] (order SCREEN_GRADS: the splat's pixel
+    position, conic, opacity, depth, colour and normal in camera ``cam``) to the Gaussian
+    parameters; a dict keyed like GRAD_LAYOUT of planar (k, n) arrays."""
+    n = g["opacity"].shape[-1]
+    d = {k: np.ascontiguousarray(g[k], dtype=np.float64) for k in ("mean", "quat", "scale")}
+    c6 = None if cov6 is None else np.ascontiguousarray(cov6, dtype=np.float64)
+    sg = np.ascontiguousarray(sgrad, dtype=np.float64).reshape(len(SCREEN_GRADS), n)
+    grad = np.zeros((23, n))
+    lib().orc_pull_back(n, _p(d["mean"]), _p(d["quat"]), _p(d["scale"]), _p(c6),
+                        _p(camera_vector(cam, np.float64)), _p(options_vector(opts)), _p(sg), _p(grad))
+    return {k: grad[lo:hi] for k, (lo, hi) in GRAD_LAYOUT.items()}

@@ -578,6 +578,24 @@ void pull_back(const Geo& G, const double* cam, const double* sg, double* pg, do
 
 extern "C" {
 
+// Pull-back alone: screen-space gradients sg[SG_COUNT][n] (u, v, A, B, C, opacity, depth, rgb,
+// normal of every Gaussian's splat in one camera) to the Gaussian parameters, grad[PG_COUNT][n]
+// (overwritten). Gaussians at or behind the near plane get zeros.
+void orc_pull_back(int64_t n, const double* mean, const double* quat, const double* scale,
+                   const double* cov6, const double* cam, const float* opt, const double* sg,
+                   double* grad) {
+  std::memset(grad, 0, sizeof(double) * PG_COUNT * n);
+  for (int64_t i = 0; i < n; ++i) {
+    Geo G;
+    geo_f64(n, i, mean, quat, scale, cov6, cam, G);
+    if (!(G.zc > (double)opt[OPT_ZNEAR])) continue;
+    double s[SG_COUNT], pg[PG_COUNT] = {0};
+    for (int k = 0; k < SG_COUNT; ++k) s[k] = sg[(size_t)k * n + i];
+    pull_back(G, cam, s, pg, opt[OPT_LOWPASS]);
+    for (int k = 0; k < PG_COUNT; ++k) grad[(size_t)k * n + i] = pg[k];
+  }
+}
+
 // FP64 adjoint of the FP64 render of n_cams cameras. grad images: grad_rgb [C][3][H][W],
 // grad_nrm [C][3][H][W], grad_depth [C][H][W] and, if not NULL, grad_alpha [C][H][W] (double; the
 // alpha output is 1 - the final transmittance, the covered fraction of the pixel). Outputs: grad[PG_COUNT][n] (planar, see
