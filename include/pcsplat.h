@@ -152,6 +152,21 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
 int pcs_render_backward(pcs_context* ctx, const pcs_state* state, const pcs_images* grad_out,
                         const pcs_grads* grads, void* stream);
 
+/* Allocation-free variant of pcs_render_backward, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving or training loops, hosts that forbid hipMalloc).
+ * Same arguments, kernels and results as pcs_render_backward (up to the order of the float atomic
+ * additions); it calls no hipMalloc, hipFree or other allocating routine. The per-splat
+ * screen-space gradient lines live instead in a fixed device array of the library, 16 MiB per GPU
+ * (held from library load until the process ends), so the state may hold at most
+ * n * n_cams <= 2^18 = 262,144 (camera, Gaussian) splats: PCS_ERR_CAPACITY beyond that, with
+ * nothing launched. The array is cleared by a kernel at the start of every call and keeps the last
+ * call's contents afterwards. All calls on one GPU share that one array: calls that overlap in
+ * time on one GPU (different streams, host threads or contexts without ordering between them)
+ * race and give wrong gradients; order them on one stream or with events. Other errors as for
+ * pcs_render_backward. */
+int pcs_render_backward_noalloc(pcs_context* ctx, const pcs_state* state, const pcs_images* grad_out,
+                                const pcs_grads* grads, void* stream);
+
 /* Parity export of a saved state (device pointers owned by the state):
  *   keys[m]:  ((cam * tiles_per_cam + ty * TX + tx) << 32) | bits(fp32 camera-space depth)
  *   vals[m]:  Gaussian index, sorted lexicographically by (key, value)

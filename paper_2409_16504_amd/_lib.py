@@ -22,8 +22,8 @@ STAGES = ("project", "scan", "binning", "sort", "ranges", "composite", "backward
 EXPORTED = ("pcs_last_error", "pcs_context_create", "pcs_context_destroy", "pcs_context_timing",
             "pcs_context_timing_stages", "pcs_shade",
             "pcs_context_timings", "pcs_state_create", "pcs_state_destroy", "pcs_options_default",
-            "pcs_render_forward", "pcs_render_backward", "pcs_state_bins", "pcs_knn_pca",
-            "pcs_voxels_create", "pcs_voxels_destroy", "pcs_voxelize", "pcs_voxels_get",
+            "pcs_render_forward", "pcs_render_backward", "pcs_render_backward_noalloc", "pcs_state_bins",
+            "pcs_knn_pca", "pcs_voxels_create", "pcs_voxels_destroy", "pcs_voxelize", "pcs_voxels_get",
             "pcs_subm_conv_forward", "pcs_subm_conv_backward", "pcs_estimator_head_forward",
             "pcs_estimator_head_backward")
 
@@ -95,6 +95,7 @@ def load():
     L.pcs_render_forward.argtypes = [c_vp, ctypes.POINTER(Gaussians), ctypes.POINTER(Camera), c_i32,
                                      ctypes.POINTER(Options), ctypes.POINTER(Images), c_vp, c_vp]
     L.pcs_render_backward.argtypes = [c_vp, c_vp, ctypes.POINTER(Images), ctypes.POINTER(Grads), c_vp]
+    L.pcs_render_backward_noalloc.argtypes = [c_vp, c_vp, ctypes.POINTER(Images), ctypes.POINTER(Grads), c_vp]
     L.pcs_state_bins.argtypes = [c_vp, ctypes.POINTER(c_vp), ctypes.POINTER(c_vp), ctypes.POINTER(c_i64),
                                  ctypes.POINTER(c_vp), ctypes.POINTER(c_i64), ctypes.POINTER(c_vp),
                                  ctypes.POINTER(c_vp)]
@@ -103,8 +104,8 @@ def load():
                             ctypes.POINTER(Light), ctypes.POINTER(c_f * 3), c_vp, c_vp]
     for name in ("pcs_context_create", "pcs_context_timing", "pcs_context_timing_stages", "pcs_shade",
                  "pcs_context_timings", "pcs_state_create",
-                 "pcs_render_forward", "pcs_render_backward", "pcs_state_bins", "pcs_knn_pca",
-            "pcs_voxels_create", "pcs_voxels_destroy", "pcs_voxelize", "pcs_voxels_get",
+                 "pcs_render_forward", "pcs_render_backward", "pcs_render_backward_noalloc",
+                 "pcs_state_bins", "pcs_knn_pca", "pcs_voxels_create", "pcs_voxels_destroy", "pcs_voxelize", "pcs_voxels_get",
             "pcs_subm_conv_forward", "pcs_subm_conv_backward", "pcs_estimator_head_forward",
             "pcs_estimator_head_backward"):
         getattr(L, name).restype = ctypes.c_int

@@ -6,12 +6,20 @@
 #include <cmath>
 #include <chrono>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "pcs_internal.hpp"
 
 using namespace pcs;
+
+// Screen-space gradient lines of pcs_render_backward_noalloc: one 64-byte line per
+// (camera, Gaussian) splat, at most kNoAllocSplats splats (16 MiB). Host code never uses the
+// array's name as an address: its device address is taken once per device with
+// hipGetSymbolAddress (noalloc_scratch) and only that pointer reaches kernels and copies.
+constexpr int64_t kNoAllocSplats = int64_t(1) << 18;
+static __device__ __align__(256) float scratch[kNoAllocSplats * kScreenStride];
 
 namespace {
 
@@ -86,6 +94,25 @@ int bit_length(uint64_t v) {
 // so that the per-splat transmittances recovered from it by division keep full precision.
 constexpr double kMinFinalTransmittance = 7.888609052210118e-31;
 
+std::mutex g_scratch_mutex;
+std::vector<float*> g_scratch_ptr;   // per device; null until taken
+
+// Device address of `scratch` on `device` (which must be current), taken on first use per device.
+int noalloc_scratch(int device, float** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize(device + 1, nullptr);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(PCS_ERR_HIP, std::string("hipGetSymbolAddress of the backward scratch: ") +
+                                   hipGetErrorString(e));
+    g_scratch_ptr[device] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[device];
+  return PCS_OK;
+}
+
 bool finite_camera(const pcs_camera& c) {
   for (float v : c.T) if (!std::isfinite(v)) return false;
   for (float v : c.t) if (!std::isfinite(v)) return false;
@@ -107,6 +134,7 @@ struct pcs_context {
   unsigned long long* host_word = nullptr;
   unsigned long long* host_word_dev = nullptr;   // its device address
   uint32_t seq = 0;                              // frame sequence number (never 0 once used)
+  float* noalloc_sgrad = nullptr;   // device address of `scratch` on this context's device
   pcs_state* internal = nullptr;    // state used when the caller passes none
   bool timing = false;
   uint32_t stage_mask = ~0u;        // stages whose launches are timed
@@ -150,9 +178,9 @@ struct StageTimer {
   hipStream_t s;
   bool around;
   size_t slot = (size_t)-1;
-  StageTimer(pcs_context* c, int st, hipStream_t stream, bool around_stage = true)
+  StageTimer(pcs_context* c, int st, hipStream_t stream, bool around_stage = true, bool enabled = true)
       : ctx(c), stage(st), s(stream), around(around_stage) {
-    if (!ctx->timing || !((ctx->stage_mask >> stage) & 1u)) return;
+    if (!enabled || !ctx->timing || !((ctx->stage_mask >> stage) & 1u)) return;
     if (ctx->used == ctx->pool.size()) {
       pcs_context::Ev ev{};
       // timing only (read after a stream synchronisation): no system-scope fence, whose cache
@@ -246,6 +274,45 @@ int check_gaussians(const pcs_gaussians* g) {
   return PCS_OK;
 }
 
+
+int check_backward(pcs_context* ctx, const pcs_state* st, const pcs_images* grad_out,
+                   const pcs_grads* grads) {
+  if (!ctx || !st || !grad_out || !grads) return fail(PCS_ERR_INVALID_ARG, "NULL argument");
+  if (st->ctx != ctx) return fail(PCS_ERR_INVALID_ARG, "state belongs to another context");
+  if (!st->valid) return fail(PCS_ERR_INVALID_ARG, "state holds no completed forward render");
+  // the adjoint recovers each splat's transmittance from the final one by division; the final
+  // transmittance is at least t_eps (1 - alpha_max), which must stay a normal float with room to
+  // spare, or the recovered values (and every gradient through them) collapse to zero
+  if (!((double)st->opt.t_eps * (1.0 - (double)st->opt.alpha_max) >= kMinFinalTransmittance))
+    return fail(PCS_ERR_UNSUPPORTED,
+                "the backward needs t_eps * (1 - alpha_max) >= 2^-100 (the final transmittance "
+                "must stay recoverable); render with a larger t_eps");
+  return PCS_OK;
+}
+
+// The adjoint's launches with the screen-space gradient lines in `sgrad` (cn lines, cleared here
+// by a fill kernel). `timed`: record stage events when timing is on.
+int backward_launch(pcs_context* ctx, const pcs_state* st, const pcs_images* grad_out,
+                    const pcs_grads* grads, float* sgrad, bool timed, hipStream_t s) {
+  const int64_t cn = st->n * st->C;
+  PCS_HIP(launch_fill_f32(sgrad, 0.0f, cn * kScreenStride, s));
+  const DevOptions dopt = to_dev(st->opt);
+  {
+    StageTimer tm(ctx, ST_BWD_COMPOSITE, s, true, timed);
+    PCS_HIP(launch_composite_backward(st->n, st->C, st->W, st->H, st->rec.as<float4>(),
+                                      st->vals.as<uint32_t>(), st->ranges.as<uint32_t>(),
+                                      st->order.as<uint32_t>(), dopt,
+                                      st->t_final.as<float>(), st->n_contrib.as<int32_t>(),
+                                      *grad_out, sgrad, s));
+  }
+  {
+    StageTimer tm(ctx, ST_BWD_PROJECT, s, true, timed);
+    PCS_HIP(launch_project_backward(st->n, st->C, st->dcams.as<DevCamera>(), dopt, st->g, sgrad,
+                                    *grads, s));
+  }
+  return PCS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -292,6 +359,12 @@ int pcs_context_create(int device, pcs_context** out) {
     return fail(PCS_ERR_HIP, "no device address for the pinned host word");
   }
   ctx->host_word_dev = reinterpret_cast<unsigned long long*>(hw_dev);
+  // device address of the allocation-free backward's scratch on this device (taken once)
+  if (noalloc_scratch(device, &ctx->noalloc_sgrad) != PCS_OK) {
+    const std::string msg = g_err;
+    pcs_context_destroy(ctx);
+    return fail(PCS_ERR_HIP, msg);
+  }
   *out = ctx;
   return PCS_OK;
 }
@@ -540,37 +613,27 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
 
 int pcs_render_backward(pcs_context* ctx, const pcs_state* st, const pcs_images* grad_out,
                         const pcs_grads* grads, void* stream) {
-  if (!ctx || !st || !grad_out || !grads) return fail(PCS_ERR_INVALID_ARG, "NULL argument");
-  if (st->ctx != ctx) return fail(PCS_ERR_INVALID_ARG, "state belongs to another context");
-  if (!st->valid) return fail(PCS_ERR_INVALID_ARG, "state holds no completed forward render");
-  // the adjoint recovers each splat's transmittance from the final one by division; the final
-  // transmittance is at least t_eps (1 - alpha_max), which must stay a normal float with room to
-  // spare, or the recovered values (and every gradient through them) collapse to zero
-  if (!((double)st->opt.t_eps * (1.0 - (double)st->opt.alpha_max) >= kMinFinalTransmittance))
-    return fail(PCS_ERR_UNSUPPORTED,
-                "the backward needs t_eps * (1 - alpha_max) >= 2^-100 (the final transmittance "
-                "must stay recoverable); render with a larger t_eps");
+  PCS_TRY(check_backward(ctx, st, grad_out, grads));
   PCS_HIP(hipSetDevice(ctx->device));
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int64_t cn = st->n * st->C;
   if (cn == 0) return PCS_OK;
   PCS_TRY(ensure(ctx->sgrad, (size_t)cn * kScreenStride * sizeof(float), "screen-space gradients"));
-  PCS_HIP(launch_fill_f32(ctx->sgrad.as<float>(), 0.0f, cn * kScreenStride, s));
-  const DevOptions dopt = to_dev(st->opt);
-  {
-    StageTimer tm(ctx, ST_BWD_COMPOSITE, s);
-    PCS_HIP(launch_composite_backward(st->n, st->C, st->W, st->H, st->rec.as<float4>(),
-                                      st->vals.as<uint32_t>(), st->ranges.as<uint32_t>(),
-                                      st->order.as<uint32_t>(), dopt,
-                                      st->t_final.as<float>(), st->n_contrib.as<int32_t>(),
-                                      *grad_out, ctx->sgrad.as<float>(), s));
-  }
-  {
-    StageTimer tm(ctx, ST_BWD_PROJECT, s);
-    PCS_HIP(launch_project_backward(st->n, st->C, st->dcams.as<DevCamera>(), dopt, st->g,
-                                    ctx->sgrad.as<float>(), *grads, s));
-  }
-  return PCS_OK;
+  return backward_launch(ctx, st, grad_out, grads, ctx->sgrad.as<float>(), true,
+                         reinterpret_cast<hipStream_t>(stream));
+}
+
+int pcs_render_backward_noalloc(pcs_context* ctx, const pcs_state* st, const pcs_images* grad_out,
+                                const pcs_grads* grads, void* stream) {
+  PCS_TRY(check_backward(ctx, st, grad_out, grads));
+  const int64_t cn = st->n * st->C;
+  if (cn > kNoAllocSplats)
+    return fail(PCS_ERR_CAPACITY, "the allocation-free backward takes at most " +
+                                      std::to_string(kNoAllocSplats) + " (camera, Gaussian) splats, got " +
+                                      std::to_string(cn));
+  PCS_HIP(hipSetDevice(ctx->device));
+  if (cn == 0) return PCS_OK;
+  return backward_launch(ctx, st, grad_out, grads, ctx->noalloc_sgrad, false,
+                         reinterpret_cast<hipStream_t>(stream));
 }
 
 int pcs_state_bins(const pcs_state* st_c, const uint64_t** keys, const uint32_t** vals, int64_t* m,
