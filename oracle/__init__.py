@@ -51,14 +51,14 @@ def _setup(L):
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
     L.orc_project_f32.argtypes = [i64] + [vp] * 7 + [i32, i32, i32, vp] + [vp] * 10
     L.orc_project_f32.restype = None
-    L.orc_project_f64.argtypes = [i64] + [vp] * 6 + [i32, i32, i32, vp] + [vp] * 11
+    L.orc_project_f64.argtypes = [i64] + [vp] * 6 + [i32, i32, i32, vp] + [vp] * 12
     L.orc_cov3d_f64.argtypes = [i64, vp, vp, vp]
     L.orc_cov3d_f64.restype = None
     L.orc_project_f64.restype = None
     L.orc_bin.argtypes = [i64, i32, i32, i32, vp, vp, vp, vp, vp]
     L.orc_bin.restype = i64
     L.orc_composite.argtypes = ([i64] + [vp] * 9 + [i64, vp, vp, ctypes.c_uint64, i32, i32, i32, vp,
-                                vp, i64] + [vp] * 8)
+                                vp, i64] + [vp] * 9)
     L.orc_composite.restype = i64
     L.orc_backward.argtypes = ([i64] + [vp] * 7 + [i32, vp, i32, i32, i32, vp, vp, vp, vp, vp, i64, vp,
                                vp, vp])
@@ -117,13 +117,14 @@ def project_f64(g: dict, cam, opts=None, tile=16, cov6=None) -> dict:
     out["rect"] = np.zeros((4, n), np.int32)
     out["count"] = np.zeros(n, np.uint32)
     out["cov2d"] = np.zeros((3, n), np.float64)
+    out["zf"] = np.zeros(n, np.float32)      # FP32 depth of the exact projection: the depth order
     d = {k: np.ascontiguousarray(g[k], dtype=np.float64) for k in ("mean", "quat", "scale", "opacity")}
     c6 = None if cov6 is None else np.ascontiguousarray(cov6, dtype=np.float64)
     lib().orc_project_f64(n, _p(d["mean"]), _p(d["quat"]), _p(d["scale"]), _p(c6), _p(d["opacity"]),
                           _p(camera_vector(cam, np.float64)), W, H, tile, _p(options_vector(opts)),
                           _p(out["valid"]), _p(out["u"]), _p(out["v"]), _p(out["z"]), _p(out["A"]),
                           _p(out["B"]), _p(out["C"]), _p(out["radius"]), _p(out["rect"]),
-                          _p(out["count"]), _p(out["cov2d"]))
+                          _p(out["count"]), _p(out["cov2d"]), _p(out["zf"]))
     return out
 
 
@@ -142,7 +143,8 @@ def bin_sorted(projs: list, n: int, W: int, H: int, tile=16):
     TX, TY = (W + tile - 1) // tile, (H + tile - 1) // tile
     C = len(projs)
     valid = np.ascontiguousarray(np.stack([p["valid"] for p in projs]))
-    zf = np.ascontiguousarray(np.stack([np.asarray(p["z"], np.float32) for p in projs]))
+    zf = np.ascontiguousarray(np.stack([np.asarray(p["zf"] if "zf" in p else p["z"], np.float32)
+                                        for p in projs]))
     rect = np.ascontiguousarray(np.stack([p["rect"] for p in projs]))
     m = int(sum(int(p["count"].astype(np.int64).sum()) for p in projs))
     keys = np.zeros(m, np.uint64)
@@ -168,9 +170,13 @@ def tile_ranges(keys: np.ndarray, n_tiles_total: int) -> np.ndarray:
     return rng
 
 
-def render(g: dict, cams: list, opts=None, mode="ref", tile=16, pixels=None, cov6=None) -> dict:
+def render(g: dict, cams: list, opts=None, mode="ref", tile=16, pixels=None, cov6=None,
+           margin_vs=None) -> dict:
     """Render every camera. Returns planar float64 images [C][3][H][W] / [C][H][W], the final
-    transmittance, n_contrib, margin flags, the sorted key/value lists and the visit count."""
+    transmittance, n_contrib, margin flags, the sorted key/value lists and the visit count.
+    ``margin_vs`` ("ref" or "f64"): also flag the pixels where the other projection's quadratic
+    forms could take a decision differently (the margins widen by the difference between the two);
+    the images are unchanged."""
     n = g["opacity"].shape[-1]
     W, H = _cam_wh(cams[0])
     TX, TY = (W + tile - 1) // tile, (H + tile - 1) // tile
@@ -182,6 +188,12 @@ def render(g: dict, cams: list, opts=None, mode="ref", tile=16, pixels=None, cov
         projs = [project_f64(g, c, opts, tile, cov6=cov6) for c in cams]
     else:
         raise ValueError(mode)
+    alts = [None] * len(cams)
+    if margin_vs is not None:
+        other = [project_f32(g, c, opts, tile) if margin_vs == "ref" else project_f64(g, c, opts, tile, cov6=cov6)
+                 for c in cams]
+        alts = [np.ascontiguousarray(np.stack([np.asarray(o[k], np.float64) for k in ("u", "v", "A", "B", "C")]))
+                for o in other]
     keys, vals = bin_sorted(projs, n, W, H, tile)
     C = len(cams)
     HW = W * H
@@ -212,7 +224,7 @@ def render(g: dict, cams: list, opts=None, mode="ref", tile=16, pixels=None, cov
                                      _p(sp["z"]), _p(opac), _p(rgb), _p(nrm), int(hi - lo), _p(k_c),
                                      _p(v_c), ci * ntiles, W, H, tile, _p(ov), _p(pix),
                                      0 if pix is None else pix.size, _p(o_rgb), _p(o_nrm), _p(o_d),
-                                     _p(o_a), _p(o_T), _p(o_nc), _p(o_f), _p(o_b))
+                                     _p(o_a), _p(o_T), _p(o_nc), _p(o_f), _p(o_b), _p(alts[ci]))
         res["rgb"][ci] = o_rgb.reshape(3, H, W)
         res["normal"][ci] = o_nrm.reshape(3, H, W)
         res["depth"][ci] = o_d.reshape(H, W)

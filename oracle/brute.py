@@ -18,7 +18,9 @@ def composite(proj: dict, opacity, rgb, normal, width: int, height: int, opts_ve
     z_near, lowpass, sigma_cut, amin, amax, teps, bg0, bg1, bg2 = [float(x) for x in opts_vec]
     cut2 = sigma_cut * sigma_cut
     valid = np.nonzero(proj["valid"])[0]
-    zbits = np.asarray(proj["z"], np.float32).view(np.uint32)
+    # the depth order is taken on the FP32 depth of the exact projection (an FP64 projection carries
+    # it as "zf"; the FP32 projection's own depth is that value)
+    zbits = np.asarray(proj["zf"] if "zf" in proj else proj["z"], np.float32).view(np.uint32)
     order = sorted(valid.tolist(), key=lambda i: (int(zbits[i]), i))
     u = [float(x) for x in proj["u"]]
     v = [float(x) for x in proj["v"]]

@@ -177,6 +177,14 @@ void project_one_f32(int64_t n, int64_t i, const float* mean, const float* quat,
   out[0] = u; out[1] = v; out[2] = zc; out[3] = A; out[4] = Bc; out[5] = C; out[6] = rad; out[7] = o;
 }
 
+// Camera-space depth of step (4) of the exact FP32 sequence, from FP32 copies of the mean and
+// camera: the value whose bits order the splats (reading C-8: the depth order is defined on the
+// FP32 depth of the exact projection, the same order the FP32 path uses).
+float depth_f32(double px, double py, double pz, const double* cam) {
+  const float T6 = (float)cam[CAM_T + 6], T7 = (float)cam[CAM_T + 7], T8 = (float)cam[CAM_T + 8];
+  return ((T6 * (float)px + T7 * (float)py) + T8 * (float)pz) + (float)cam[CAM_t + 2];
+}
+
 // FP64 projection; if cov6 is non-null, Sigma is taken from it (xx,xy,xz,yy,yz,zz planar).
 void project_one_f64(int64_t n, int64_t i, const float* mean, const double* mean_d, const float* quat,
                      const double* quat_d, const float* scale, const double* scale_d,
@@ -236,7 +244,7 @@ void project_one_f64(int64_t n, int64_t i, const float* mean, const double* mean
   s.valid = true;
   s.x0 = (int)std::max(fx0, 0.0); s.x1 = (int)std::min(fx1, (double)(TX - 1));
   s.y0 = (int)std::max(fy0, 0.0); s.y1 = (int)std::min(fy1, (double)(TY - 1));
-  s.u = u; s.v = v; s.z = zc; s.zf = (float)zc;
+  s.u = u; s.v = v; s.z = zc; s.zf = depth_f32(px, py, pz, cam);
   s.a = a; s.b = b; s.c = c;
   s.A = c / det; s.B = -b / det; s.C = a / det; s.radius = rad;
 }
@@ -278,7 +286,8 @@ void orc_project_f64(int64_t n, const double* mean, const double* quat, const do
                      const double* cov6, const double* opac, const double* cam, int W, int H,
                      int tile, const float* opt, uint8_t* valid, double* u, double* v, double* z,
                      double* A, double* B, double* C, double* radius, int32_t* rect,
-                     uint32_t* count, double* cov2d /*[3][n]: a, b, c of Sigma_s*/) {
+                     uint32_t* count, double* cov2d /*[3][n]: a, b, c of Sigma_s*/,
+                     float* zf /*[n]: the FP32 depth that orders the splats*/) {
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     ScreenSplat s;
@@ -288,11 +297,13 @@ void orc_project_f64(int64_t n, const double* mean, const double* quat, const do
     if (s.valid) {
       u[i] = s.u; v[i] = s.v; z[i] = s.z; A[i] = s.A; B[i] = s.B; C[i] = s.C; radius[i] = s.radius;
       cov2d[i] = s.a; cov2d[n + i] = s.b; cov2d[2 * n + i] = s.c;
+      zf[i] = s.zf;
       rect[i] = s.x0; rect[n + i] = s.x1; rect[2 * n + i] = s.y0; rect[3 * n + i] = s.y1;
       count[i] = (uint32_t)((s.x1 - s.x0 + 1) * (s.y1 - s.y0 + 1));
     } else {
       u[i] = v[i] = z[i] = A[i] = B[i] = C[i] = radius[i] = 0.0;
       cov2d[i] = cov2d[n + i] = cov2d[2 * n + i] = 0.0;
+      zf[i] = 0.0f;
       rect[i] = rect[n + i] = rect[2 * n + i] = rect[3 * n + i] = 0;
       count[i] = 0;
     }
@@ -342,14 +353,19 @@ int64_t orc_bin(int64_t n, int n_cams, int ntiles, int TX, const uint8_t* valid,
 // cam_tile_base). pix: optional list of pixel indices (y*W+x) to evaluate (npix entries), else all.
 // Outputs are written at the pixel index (planar [3][H*W] for rgb and normal).
 // flags bits: 1 = a 3-sigma test, 2 = an alpha-cutoff test, 4 = the transmittance stop lies within
-// the rounding margin of its threshold. Returns the number of (pixel, list entry) visits.
+// the rounding margin of its threshold. alt (optional, 5 arrays of n: u, v, A, B, C of another
+// projection of the same splats, e.g. the FP64 one beside the exact FP32 one) widens every margin
+// by the difference between the two projections' quadratic forms, so that a pixel where the two
+// projections could take a decision differently is flagged. Returns the number of
+// (pixel, list entry) visits.
 int64_t orc_composite(int64_t n, const double* u, const double* v, const double* A,
                       const double* B, const double* C, const double* zdepth, const double* opac,
                       const double* rgb, const double* nrm, int64_t m, const uint64_t* keys,
                       const uint32_t* vals, uint64_t cam_tile_base, int W, int H, int tile,
                       const float* opt, const int64_t* pix, int64_t npix, double* out_rgb,
                       double* out_nrm, double* out_depth, double* out_alpha, double* out_T,
-                      int32_t* out_ncontrib, uint8_t* out_flags, int64_t* out_blends) {
+                      int32_t* out_ncontrib, uint8_t* out_flags, int64_t* out_blends,
+                      const double* alt) {
   const int TX = (W + tile - 1) / tile, TY = (H + tile - 1) / tile;
   const int64_t ntiles = (int64_t)TX * TY;
   std::vector<int64_t> start(ntiles, 0), end(ntiles, 0);
@@ -382,7 +398,13 @@ int64_t orc_composite(int64_t n, const double* u, const double* v, const double*
       const double dx = pxc - u[g], dy = pyc - v[g];
       const double qa = A[g] * dx * dx, qb = 2.0 * B[g] * dx * dy, qc = C[g] * dy * dy;
       const double q = qa + qb + qc;
-      const double dq = eps * (std::fabs(qa) + std::fabs(qb) + std::fabs(qc));
+      double dq = eps * (std::fabs(qa) + std::fabs(qb) + std::fabs(qc));
+      if (alt) {
+        const double dx2 = pxc - alt[g], dy2 = pyc - alt[n + g];
+        const double q2 = alt[2 * n + g] * dx2 * dx2 + 2.0 * alt[3 * n + g] * dx2 * dy2 +
+                          alt[4 * n + g] * dy2 * dy2;
+        dq += std::fabs(q - q2);
+      }
       if (std::fabs(q - cut2) <= dq) flag |= 1;
       if (!(q <= cut2)) continue;
       const double e = std::exp(-0.5 * q);
@@ -600,7 +622,8 @@ void orc_pull_back(int64_t n, const double* mean, const double* quat, const doub
 // grad_nrm [C][3][H][W], grad_depth [C][H][W] and, if not NULL, grad_alpha [C][H][W] (double; the
 // alpha output is 1 - the final transmittance, the covered fraction of the pixel). Outputs: grad[PG_COUNT][n] (planar, see
 // layout above) accumulated over cameras, sabs[PG_COUNT][n] the sum over pixels of the absolute
-// per-pixel contribution, and sig: a 64-bit signature of the discrete decisions (which splats each
+// per-pixel terms (the blend-weight part and the alpha part pulled back apart, the alpha part from
+// the absolute terms of dL/dalpha: the size of what an evaluation in lower precision rounds), and sig: a 64-bit signature of the discrete decisions (which splats each
 // pixel blends and where it stops), used to detect when a finite-difference step changes them.
 // cov6 optional (then the quat and scale gradients are left zero). only_gauss: -1 fills sabs for
 // every Gaussian, i >= 0 only for Gaussian i, -2 for none.
@@ -676,6 +699,8 @@ void orc_backward(int64_t n, const double* mean, const double* quat, const doubl
       gch[6] = grad_depth[(int64_t)cam_i * HW + pid];
       const double g_cover = grad_alpha ? grad_alpha[(int64_t)cam_i * HW + pid] : 0.0;
       double behind[7] = {T * bg[0], T * bg[1], T * bg[2], 0, 0, 0, 0};
+      // the same sums over absolute values, for the size of the terms that cancel in dL/dalpha
+      double behind_abs[7] = {T * std::fabs(bg[0]), T * std::fabs(bg[1]), T * std::fabs(bg[2]), 0, 0, 0, 0};
       for (int64_t h = (int64_t)hits.size() - 1; h >= 0; --h) {
         const Hit& hit = hits[h];
         const uint32_t g = hit.g;
@@ -683,13 +708,16 @@ void orc_backward(int64_t n, const double* mean, const double* quat, const doubl
         double f[7] = {rgb[g], rgb[n + g], rgb[2 * n + g], nrm[g], nrm[n + g], nrm[2 * n + g], s.z};
         double px_sg[SG_COUNT] = {0};
         const double wgt = hit.T * hit.alpha;
-        double dL_dalpha = 0.0;
+        double dL_dalpha = 0.0, dL_dalpha_terms = 0.0;
         for (int ch = 0; ch < 7; ++ch) {
           dL_dalpha += gch[ch] * (hit.T * f[ch] - behind[ch] / (1.0 - hit.alpha));
+          dL_dalpha_terms += std::fabs(gch[ch]) * (hit.T * std::fabs(f[ch]) + behind_abs[ch] / (1.0 - hit.alpha));
           behind[ch] += wgt * f[ch];
+          behind_abs[ch] += wgt * std::fabs(f[ch]);
         }
         // alpha output 1 - prod_j (1 - alpha_j): its derivative in alpha_h is T_final / (1 - alpha_h)
         dL_dalpha += g_cover * T / (1.0 - hit.alpha);
+        dL_dalpha_terms += std::fabs(g_cover) * T / (1.0 - hit.alpha);
         for (int ch = 0; ch < 3; ++ch) {
           px_sg[SG_R + ch] = gch[ch] * wgt;
           px_sg[SG_NX + ch] = gch[3 + ch] * wgt;
@@ -706,9 +734,24 @@ void orc_backward(int64_t n, const double* mean, const double* quat, const doubl
         }
         for (int k = 0; k < SG_COUNT; ++k) sgrad[(size_t)k * n + g] += px_sg[k];
         if (only_gauss == -1 || (int64_t)g == only_gauss) {
-          double pg[PG_COUNT] = {0};
-          pull_back(geo[g], cam, px_sg, pg, opt[OPT_LOWPASS]);
-          for (int k = 0; k < PG_COUNT; ++k) sabs[(size_t)k * n + g] += std::fabs(pg[k]);
+          // size of this pixel's terms: the blend-weight part as it is, and the alpha part with
+          // dL/dalpha replaced by the sum of the absolute values of its terms (front colour
+          // against the part behind, which cancel where the splat hardly changes the pixel)
+          double sg_w[SG_COUNT] = {0}, sg_a[SG_COUNT] = {0};
+          for (int k = SG_Z; k < SG_COUNT; ++k) sg_w[k] = px_sg[k];
+          if (!hit.clamped) {
+            const double dq = dL_dalpha_terms * (-0.5 * hit.alpha);
+            sg_a[SG_O] = dL_dalpha_terms * hit.e;
+            sg_a[SG_A] = dq * hit.dx * hit.dx;
+            sg_a[SG_B] = dq * 2.0 * hit.dx * hit.dy;
+            sg_a[SG_C] = dq * hit.dy * hit.dy;
+            sg_a[SG_U] = dq * (-2.0 * (s.A * hit.dx + s.B * hit.dy));
+            sg_a[SG_V] = dq * (-2.0 * (s.B * hit.dx + s.C * hit.dy));
+          }
+          double pw[PG_COUNT] = {0}, pa[PG_COUNT] = {0};
+          pull_back(geo[g], cam, sg_w, pw, opt[OPT_LOWPASS]);
+          pull_back(geo[g], cam, sg_a, pa, opt[OPT_LOWPASS]);
+          for (int k = 0; k < PG_COUNT; ++k) sabs[(size_t)k * n + g] += std::fabs(pw[k]) + std::fabs(pa[k]);
         }
       }
     }

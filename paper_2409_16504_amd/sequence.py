@@ -28,6 +28,43 @@ from . import Renderer, default_options  # noqa: E402
 from .estimator import SparseEstimator, Voxels, adaptive_grid, psnr  # noqa: E402
 
 
+SEQUENCE_SEED = 1005
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "estimator_surface.pt")
+
+
+def make_sequence(n_frames: int, points: int, seed: int = SEQUENCE_SEED):
+    """The deforming surface and its frames: radii scaled by 1 + 0.2 sin(2 pi t / 30 + phase), points
+    sampled area-uniformly plus N(0, 0.002^2) position noise, value-noise colour. Returns the
+    surface and a list of dicts with xyz (3, n) and rgb (3, n) float32 arrays and the radius scale."""
+    rng = np.random.default_rng(seed)
+    surf = ProceduralSurface(rng, margin_scale=1.2)
+    frames = []
+    for t in range(n_frames):
+        scale = 1.0 + 0.2 * np.sin(2.0 * math.pi * t / 30 + surf.phase)
+        p = surf.sample(points, rng, radius_scale=scale)
+        p = p + rng.normal(0.0, 0.002, size=p.shape)
+        rgb = surf.color(p)
+        frames.append(dict(xyz=np.ascontiguousarray(p, np.float32), rgb=np.ascontiguousarray(rgb, np.float32),
+                           scale=scale))
+    return surf, frames
+
+
+def sequence_cameras(width: int, height: int) -> list:
+    """The two views of every frame: eye at radius 3, 0.3 above the centre, 90 degrees apart."""
+    return [look_at_camera([3.0 * math.sin(a), 0.3, 3.0 * math.cos(a)], width=width, height=height)
+            for a in (0.0, math.pi / 2)]
+
+
+def load_estimator(R: Renderer, weights: str | None = WEIGHTS) -> SparseEstimator:
+    """The estimator with the shipped (or given) trained weights."""
+    est = SparseEstimator(R, seed=0)
+    if weights:
+        ck = torch.load(weights, weights_only=True)
+        for p_, v in zip(est.params, ck["params"]):
+            p_.copy_(v.to(p_.device))
+    return est
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--frames", type=int, default=30)
@@ -35,35 +72,20 @@ def main(argv=None):
     ap.add_argument("--points", type=int, default=1_000_000)
     ap.add_argument("--width", type=int, default=1440)
     ap.add_argument("--height", type=int, default=1600)
-    ap.add_argument("--weights", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
-                                                      "estimator_surface.pt"))
+    ap.add_argument("--weights", default=WEIGHTS)
     ap.add_argument("--kappa", type=float, default=1.0)
     ap.add_argument("--psnr-frames", type=int, default=3)
     args = ap.parse_args(argv)
 
     R = Renderer(0)
     dev = torch.device("cuda", 0)
-    rng = np.random.default_rng(1005)
-    surf = ProceduralSurface(rng, margin_scale=1.2)
-    frames = []
     t0 = time.time()
-    for t in range(args.frames + args.warmup):
-        scale = 1.0 + 0.2 * np.sin(2.0 * math.pi * t / 30 + surf.phase)
-        p = surf.sample(args.points, rng, radius_scale=scale)
-        clean = p.copy()
-        p = p + rng.normal(0.0, 0.002, size=p.shape)
-        rgb = surf.color(p)
-        frames.append(dict(xyz=torch.from_numpy(np.ascontiguousarray(p, np.float32)).to(dev),
-                           rgb=torch.from_numpy(np.ascontiguousarray(rgb, np.float32)).to(dev),
-                           scale=scale, clean=clean))
+    surf, raw = make_sequence(args.frames + args.warmup, args.points)
+    frames = [dict(xyz=torch.from_numpy(f["xyz"]).to(dev), rgb=torch.from_numpy(f["rgb"]).to(dev),
+                   scale=f["scale"]) for f in raw]
     print(f"[sequence] {len(frames)} frames ready in {time.time() - t0:.1f}s", flush=True)
-    cams = [look_at_camera([3.0 * math.sin(a), 0.3, 3.0 * math.cos(a)], width=args.width, height=args.height)
-            for a in (0.0, math.pi / 2)]
-    est = SparseEstimator(R, seed=0)
-    if args.weights:
-        ck = torch.load(args.weights, weights_only=True)
-        for p_, v in zip(est.params, ck["params"]):
-            p_.copy_(v.to(dev))
+    cams = sequence_cameras(args.width, args.height)
+    est = load_estimator(R, args.weights)
     opts = default_options()
     grid = adaptive_grid(R, frames[0]["xyz"], frames[0]["rgb"]).grid   # the density is the sequence's
     vox = Voxels(R)

@@ -188,27 +188,17 @@ def test_opaque_front_layer_occludes(R):
 @pytest.mark.parametrize("n,W,H,seed", [(1_000_000, 1920, 1080, 1006), (800_000, 1920, 1080, 1002)])
 def test_full_size_surface_frame(R, n, W, H, seed):
     """Full-size frames (1M surfel Gaussians at 1080p, the benchmark frame; 800k at 1080p): the
-    complete key lists bit-exact, images on 20,000 sampled pixels (the oracle composites those
-    pixels one by one)."""
+    complete key lists bit-exact, and every pixel of every image against the oracle's full frame."""
     g = surface_gaussians(n, seed)
     cams = [look_at_camera([0, 0, 3], width=W, height=H)]
     imgs, bins, _ = gpu_render(R, g, cams)
-    rng = np.random.default_rng(3)
-    cover = np.flatnonzero(imgs["alpha"][0].reshape(-1) > 0)
-    pix = np.concatenate([rng.choice(cover, 15000, replace=False), rng.choice(W * H, 5000, replace=False)])
-    ref = oracle.render(g, cams, mode="ref", pixels=pix)
+    ref = oracle.render(g, cams, mode="ref")
     TX, TY = (W + 15) // 16, (H + 15) // 16
     check_bins(bins, ref, TX * TY)
-    flat = lambda a: a.reshape(a.shape[0], -1)[..., pix] if a.ndim == 3 else a.reshape(a.shape[0], 3, -1)[..., pix]  # noqa: E731
-    sub = {k: flat(imgs[k]) for k in ("rgb", "normal", "depth", "alpha")}
-    rsub = {k: flat(ref[k]) for k in ("rgb", "normal", "depth", "alpha")}
-    rsub["flags"] = flat(ref["flags"])
-    err = image_errors(sub, rsub)
-    assert err["rgb"] <= 1e-4 and err["normal"] <= 1e-4 and err["alpha"] <= 1e-4, err
-    assert err["depth"] <= 1e-4 * 5.0, err
-    unf = rsub["flags"] == 0
-    assert np.array_equal(flat(bins["n_contrib"])[unf], flat(ref["n_contrib"])[unf])
-    assert err["flagged"] < 0.01 * pix.size
+    err = check_images(imgs, bins, ref, 5.0)
+    print(f"full frame {n} at {W}x{H}: {err}", flush=True)
+    assert err["flagged"] < 1e-3 * W * H
+    assert (ref["n_contrib"][0] > 0).sum() > 0.1 * W * H
 
 
 @pytest.mark.parametrize("n", [32 * 4096, 32 * 4096 + 1, 64 * 4096 + 4095])

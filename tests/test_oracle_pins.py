@@ -186,6 +186,32 @@ def test_fp32_projection_tracks_fp64():
     assert differ.sum() <= 2
 
 
+def test_fp64_projection_orders_by_the_exact_fp32_depth():
+    """Reading C-8: the depth order is defined on the FP32 depth of the exact projection, in the
+    FP64 render too (the FP64 depth rounded to FP32 can differ from it by an ulp and would swap
+    splats of nearly equal depth)."""
+    rng = np.random.default_rng(14)
+    g = random_gaussians(2000, rng)
+    cam = look_at_camera([0.3, -0.2, 3], width=128, height=128)
+    p32, p64 = oracle.project_f32(g, cam), oracle.project_f64(g, cam)
+    both = (p32["valid"] == 1) & (p64["valid"] == 1)
+    assert both.sum() > 1500
+    assert np.array_equal(p64["zf"][both].view(np.uint32), np.asarray(p32["z"], np.float32)[both].view(np.uint32))
+    # and the rounded FP64 depth is not always that value (otherwise the pin would be empty)
+    rounded = np.asarray(p64["z"], np.float32)
+    assert (rounded[both] != p64["zf"][both]).any()
+
+
+def test_margins_against_the_other_projection_only_add_flags():
+    g, cam = _c1_scene()
+    plain = oracle.render(g, [cam], mode="ref")
+    wide = oracle.render(g, [cam], mode="ref", margin_vs="f64")
+    for k in ("rgb", "normal", "depth", "alpha", "n_contrib"):
+        assert np.array_equal(plain[k], wide[k]), k
+    assert np.all(wide["flags"][plain["flags"] != 0] != 0)
+    assert (wide["flags"] != 0).sum() >= (plain["flags"] != 0).sum()
+
+
 def test_near_plane_and_nonfinite_culled():
     cam = look_at_camera([0, 0, 3], width=64, height=64)
     g = gauss([[0, 0, 2.9], [0, 0, 2.85], [0, 0, 0], [0, 0, 0], [0, 0, 0]], opac=[0.8, 0.8, 0.8, 0.8, 0.001])
