@@ -6,12 +6,13 @@
  *   - array arguments are DEVICE pointers on the context's device, FP32, planar
  *     ("component-major": component k of item i lives at ptr[k * n + i]);
  *   - the caller owns every input and output buffer; the library owns the context, the render
- *     state and the workspace they hold (device memory allocated with hipMalloc, grown on demand
- *     and released by the matching destroy call);
+ *     state and the workspace they hold (device memory from hipMalloc or from the allocator
+ *     installed with pcs_context_set_allocator, grown on demand and released by the matching
+ *     destroy call);
  *   - work is enqueued on `stream` (a hipStream_t; NULL = the null stream) in stream order; the
  *     host synchronises only where a size must be known: pcs_render_forward reads back the
- *     instance count and depth range, pcs_knn_pca the cloud's bounding box, pcs_voxelize the
- *     voxel count;
+ *     instance count and depth range (not in capacity mode, PCS_FLAG_CAPACITY_MODE), pcs_knn_pca
+ *     the cloud's bounding box, pcs_voxelize the voxel count;
  *   - a context or state may be used by one host thread at a time;
  *   - the return value is a status code; pcs_last_error() gives a thread-local message.
  *
@@ -42,6 +43,16 @@ extern "C" {
 
 /* ---- render flags ---------------------------------------------------------------------- */
 #define PCS_FLAG_SAVE_STATE 1u /* keep projection, sorted lists and tile ranges for backward */
+/* Capacity mode: the render enqueues everything without waiting on the device. The tile-instance
+ * buffers of the state keep a fixed capacity: 1.25 x the instance total of an earlier frame of the
+ * same state (the previous one, once its count has reached the host; the state's first
+ * capacity-mode frame waits for its own count, like a plain render, to size it). A frame with more
+ * instances than the capacity is not composited (every tile is left empty: background only) and
+ * pcs_state_status reports PCS_ERR_CAPACITY with the count it needs; the next capacity-mode render
+ * of the state is sized for it. With the same inputs and a capacity that holds, the launch sequence
+ * is the same on every call and allocates nothing, so it can be captured in a HIP graph and
+ * replayed (the graph replays the captured frame's sizes; check pcs_state_status after a replay). */
+#define PCS_FLAG_CAPACITY_MODE 2u
 
 /* Pinhole camera (Section 3.1, Eq. 3-4). x_c = T p + t with T row-major; camera axes x right,
  * y down, z forward; pixel (i, j) has its centre at (i + 0.5, j + 0.5); u = fx x/z + cx,
@@ -116,6 +127,20 @@ const char* pcs_last_error(void);
 int pcs_context_create(int device, pcs_context** out);
 void pcs_context_destroy(pcs_context* ctx);
 
+/* Device memory of the workspace. By default the library takes its workspace (the context's,
+ * states' and voxel objects' buffers, grown on demand and kept until they must grow or their owner
+ * is destroyed) with hipMalloc and returns it with hipFree. With an allocator installed, every
+ * buffer allocated from then on comes from alloc(bytes, user) (NULL: PCS_ERR_OOM, nothing leaked)
+ * and goes back through release(ptr, user), e.g. a framework's caching allocator. Buffers keep the
+ * allocator that made them, so the allocator may be changed at any time; both callbacks NULL
+ * restores hipMalloc. The callbacks run on the calling host thread, inside the library call that
+ * needs the memory (a render, a voxelisation, ...) or inside pcs_*_destroy; a buffer is released
+ * only after the work that used it has been enqueued on the call's stream (destroy synchronises
+ * the device first). Memory tied to one stream by the allocator must only be used on that stream. */
+typedef void* (*pcs_alloc_fn)(size_t bytes, void* user);
+typedef void (*pcs_free_fn)(void* ptr, void* user);
+int pcs_context_set_allocator(pcs_context* ctx, pcs_alloc_fn alloc, pcs_free_fn release, void* user);
+
 /* Per-stage timing with HIP events recorded on the caller's stream around every kernel stage.
  * pcs_context_timing(ctx, 1) resets the accumulators and enables timing; pcs_context_timings
  * copies up to `cap` accumulated millisecond totals (stage order: project, scan, binning, sort,
@@ -166,6 +191,23 @@ int pcs_render_backward(pcs_context* ctx, const pcs_state* state, const pcs_imag
  * pcs_render_backward. */
 int pcs_render_backward_noalloc(pcs_context* ctx, const pcs_state* state, const pcs_images* grad_out,
                                 const pcs_grads* grads, void* stream);
+
+/* Status of the frame last rendered into `state`: synchronises `stream` and returns PCS_OK, or
+ * PCS_ERR_CAPACITY (capacity mode: the frame had more tile instances than the state's capacity;
+ * *required, if given, receives its count), or PCS_ERR_HIP (a wait of the instance ordering ran out
+ * its bound, which only a broken launch does; the frame was not composited). A failed frame's
+ * images hold the background only, and its backward adds nothing. */
+int pcs_state_status(pcs_state* state, int64_t* required, void* stream);
+
+/* Instance capacity the state's capacity-mode renders use (0 before the first one). */
+int pcs_state_capacity(const pcs_state* state, int64_t* capacity);
+
+/* Bound, in polling rounds, of the waits in the instance ordering's chained scans (0: the default,
+ * 2^22 rounds). The waits end as soon as the earlier partitions of the launch have published, which
+ * always happens in a correct launch; the bound only keeps a broken launch from hanging. A tiny
+ * bound makes waits run out on purpose (diagnostics and tests of the error path): the frame then
+ * reports PCS_ERR_HIP through pcs_state_status and pcs_state_bins, and every kernel still ends. */
+int pcs_context_set_wait_limit(pcs_context* ctx, uint32_t rounds);
 
 /* Parity export of a saved state (device pointers owned by the state):
  *   keys[m]:  ((cam * tiles_per_cam + ty * TX + tx) << 32) | bits(fp32 camera-space depth)

@@ -14,15 +14,18 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_build", "l
 c_f, c_i32, c_i64, c_u32, c_vp = ctypes.c_float, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p
 
 PCS_OK, PCS_ERR_INVALID_ARG, PCS_ERR_HIP, PCS_ERR_OOM, PCS_ERR_CAPACITY, PCS_ERR_UNSUPPORTED = range(6)
+FLAG_SAVE_STATE, FLAG_CAPACITY_MODE = 1, 2
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "HIP_ERROR", 3: "OUT_OF_MEMORY", 4: "CAPACITY", 5: "UNSUPPORTED"}
 STAGES = ("project", "scan", "binning", "sort", "ranges", "composite", "backward_composite",
           "backward_project", "knn_pca", "voxelize", "conv", "conv_backward", "head", "head_backward",
           "shade")
 
-EXPORTED = ("pcs_last_error", "pcs_context_create", "pcs_context_destroy", "pcs_context_timing",
+EXPORTED = ("pcs_last_error", "pcs_context_create", "pcs_context_destroy", "pcs_context_set_allocator",
+            "pcs_context_timing",
             "pcs_context_timing_stages", "pcs_shade",
             "pcs_context_timings", "pcs_state_create", "pcs_state_destroy", "pcs_options_default",
             "pcs_render_forward", "pcs_render_backward", "pcs_render_backward_noalloc", "pcs_state_bins",
+            "pcs_state_status", "pcs_state_capacity", "pcs_context_set_wait_limit",
             "pcs_knn_pca", "pcs_voxels_create", "pcs_voxels_destroy", "pcs_voxelize", "pcs_voxels_get",
             "pcs_subm_conv_forward", "pcs_subm_conv_backward", "pcs_estimator_head_forward",
             "pcs_estimator_head_backward")
@@ -57,6 +60,11 @@ class Grads(ctypes.Structure):
                 ("rgb", c_vp), ("normal", c_vp)]
 
 
+# allocator callbacks: alloc(bytes, user) -> device pointer or NULL; release(ptr, user)
+ALLOC_FN = ctypes.CFUNCTYPE(c_vp, ctypes.c_size_t, c_vp)
+FREE_FN = ctypes.CFUNCTYPE(None, c_vp, c_vp)
+
+
 class PcsError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"pcsplat {STATUS_NAMES.get(code, code)}: {msg}")
@@ -84,6 +92,7 @@ def load():
     L.pcs_context_destroy.argtypes = [c_vp]
     L.pcs_context_destroy.restype = None
     L.pcs_context_timing.argtypes = [c_vp, ctypes.c_int]
+    L.pcs_context_set_allocator.argtypes = [c_vp, ALLOC_FN, FREE_FN, c_vp]
     L.pcs_context_timing_stages.argtypes = [c_vp, ctypes.c_uint32]
     L.pcs_context_timings.argtypes = [c_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_i64),
                                       ctypes.c_int, c_vp]
@@ -99,12 +108,16 @@ def load():
     L.pcs_state_bins.argtypes = [c_vp, ctypes.POINTER(c_vp), ctypes.POINTER(c_vp), ctypes.POINTER(c_i64),
                                  ctypes.POINTER(c_vp), ctypes.POINTER(c_i64), ctypes.POINTER(c_vp),
                                  ctypes.POINTER(c_vp)]
+    L.pcs_state_status.argtypes = [c_vp, ctypes.POINTER(c_i64), c_vp]
+    L.pcs_state_capacity.argtypes = [c_vp, ctypes.POINTER(c_i64)]
+    L.pcs_context_set_wait_limit.argtypes = [c_vp, ctypes.c_uint32]
     L.pcs_knn_pca.argtypes = [c_vp, c_vp, c_i64, c_i32, c_f, c_f, c_vp, c_vp, c_vp, c_vp, c_vp]
     L.pcs_shade.argtypes = [c_vp, ctypes.POINTER(Images), ctypes.POINTER(Camera), c_i32,
                             ctypes.POINTER(Light), ctypes.POINTER(c_f * 3), c_vp, c_vp]
-    for name in ("pcs_context_create", "pcs_context_timing", "pcs_context_timing_stages", "pcs_shade",
+    for name in ("pcs_context_create", "pcs_context_set_allocator", "pcs_context_timing", "pcs_context_timing_stages", "pcs_shade",
                  "pcs_context_timings", "pcs_state_create",
                  "pcs_render_forward", "pcs_render_backward", "pcs_render_backward_noalloc",
+                 "pcs_state_status", "pcs_state_capacity", "pcs_context_set_wait_limit",
                  "pcs_state_bins", "pcs_knn_pca", "pcs_voxels_create", "pcs_voxels_destroy", "pcs_voxelize", "pcs_voxels_get",
             "pcs_subm_conv_forward", "pcs_subm_conv_backward", "pcs_estimator_head_forward",
             "pcs_estimator_head_backward"):

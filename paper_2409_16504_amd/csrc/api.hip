@@ -43,17 +43,30 @@ int fail(int code, const std::string& msg) {
     if (rc_ != PCS_OK) return rc_; \
   } while (0)
 
+// Where device buffers come from: the context's allocator callbacks, or hipMalloc / hipFree.
+struct Allocator {
+  pcs_alloc_fn alloc = nullptr;
+  pcs_free_fn release = nullptr;
+  void* user = nullptr;
+};
+
+// A device buffer remembers the allocator that made it and returns its memory there.
 struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
+  Allocator from;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (from.release) from.release(p, from.user);
+      else (void)hipFree(p);
+    }
     p = nullptr;
     cap = 0;
+    from = Allocator{};
   }
   template <typename T> T* as() const { return reinterpret_cast<T*>(p); }
 };
@@ -61,13 +74,23 @@ struct DevBuf {
 void swap_buf(DevBuf& a, DevBuf& b) {
   std::swap(a.p, b.p);
   std::swap(a.cap, b.cap);
+  std::swap(a.from, b.from);
 }
 
 // Grow-only device buffer; 25% headroom so slowly growing sizes do not reallocate every call.
-int ensure(DevBuf& b, size_t bytes, const char* what) {
+int ensure_with(const Allocator& al, DevBuf& b, size_t bytes, const char* what) {
   if (bytes <= b.cap && b.p) return PCS_OK;
   b.release();
   const size_t want = std::max<size_t>(256, bytes + bytes / 4);
+  if (al.alloc) {
+    b.p = al.alloc(want, al.user);
+    if (!b.p)
+      return fail(PCS_ERR_OOM, std::string("the allocator callback returned no memory for ") +
+                                   std::to_string(want) + " bytes of " + what);
+    b.from = al;
+    b.cap = want;
+    return PCS_OK;
+  }
   hipError_t e = hipMalloc(&b.p, want);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -130,11 +153,10 @@ struct pcs_context {
   DevBuf dkeys, dkeys_alt, dvals, dvals_alt, dsort_scratch;   // depth sort of the splats
   DevBuf knn_scratch, conv_tmp, wt_tmp, shade_cams, tile_hist;
   uint32_t* host_small = nullptr;   // pinned 4 KiB: readback of the small device words
-  // pinned, coherent host word that the depth-key kernel sets to seq << 32 | instance total
-  unsigned long long* host_word = nullptr;
-  unsigned long long* host_word_dev = nullptr;   // its device address
-  uint32_t seq = 0;                              // frame sequence number (never 0 once used)
+  uint32_t seq = 0;                 // frame sequence number (never 0 once used)
+  uint32_t wait_limit = 0;          // look-back wait bound of the ordering kernels (0: default)
   float* noalloc_sgrad = nullptr;   // device address of `scratch` on this context's device
+  Allocator alloc;                  // where new workspace comes from (default: hipMalloc)
   pcs_state* internal = nullptr;    // state used when the caller passes none
   bool timing = false;
   uint32_t stage_mask = ~0u;        // stages whose launches are timed
@@ -151,12 +173,24 @@ struct pcs_context {
 struct pcs_state {
   pcs_context* ctx = nullptr;
   DevBuf rec, keys, vals, ranges, order, t_final, n_contrib, canon, dcams;   // keys: u32 tile ids
+  DevBuf words;                     // the frame's error word (device)
+  // pinned, coherent host words the kernels set to seq << 32 | value: [0] instance total (from the
+  // projection's counts), [1] depth bits, [2] the frame's error word (set once ordering is done)
+  unsigned long long* host = nullptr;
+  unsigned long long* host_dev = nullptr;   // their device address
+  uint32_t seq = 0;                 // sequence number of the last frame rendered into the state
   pcs_gaussians g{};
   std::vector<pcs_camera> cams;
   pcs_options opt{};
   int W = 0, H = 0, C = 0;
   int64_t n = 0, m = 0, n_tiles = 0;
+  bool m_known = false;             // m holds the frame's instance total (else read from host[0])
+  int64_t capacity = 0;             // instance capacity of capacity-mode frames (0: not sized yet)
+  bool capacity_frame = false;      // the last frame ran in capacity mode
   bool valid = false;
+  ~pcs_state() {
+    if (host) (void)hipHostFree(host);
+  }
 };
 
 struct pcs_voxels {
@@ -169,6 +203,11 @@ struct pcs_voxels {
 };
 
 namespace {
+
+// Workspace of a context (or of a state or voxels object on it) from the context's allocator.
+int ensure(pcs_context* ctx, DevBuf& b, size_t bytes, const char* what) {
+  return ensure_with(ctx->alloc, b, bytes, what);
+}
 
 // Records HIP events around a stage when timing is on. A stage of one kernel can instead hand the
 // pair to its launch (around = false), which stamps the kernel's own start and end into them.
@@ -235,12 +274,12 @@ int check_options(const pcs_options& o) {
 // total, word 1: depth bits). After the first millisecond the stream is queried every 100
 // microseconds (a query is not free: it is kept off the common path), so a failed launch or a
 // stream that drained without the stores is an error instead of a hang.
-int wait_frame_words(pcs_context* ctx, hipStream_t s, uint64_t* total, int* depth_bits) {
-  volatile unsigned long long* w = ctx->host_word;
+int wait_frame_words(pcs_state* st, hipStream_t s, uint64_t* total, int* depth_bits) {
+  volatile unsigned long long* w = st->host;
   using clock = std::chrono::steady_clock;
   auto next_query = clock::now() + std::chrono::milliseconds(1);
   auto ready = [&](unsigned long long a, unsigned long long b) {
-    return (uint32_t)(a >> 32) == ctx->seq && (uint32_t)(b >> 32) == ctx->seq;
+    return (uint32_t)(a >> 32) == st->seq && (uint32_t)(b >> 32) == st->seq;
   };
   for (uint64_t it = 1;; ++it) {
     unsigned long long a = w[0], b = w[1];
@@ -274,6 +313,54 @@ int check_gaussians(const pcs_gaussians* g) {
   return PCS_OK;
 }
 
+
+// A state's pinned host words (allocated once, on the state's first render).
+int state_host_words(pcs_state* st) {
+  if (st->host) return PCS_OK;
+  void* hw = nullptr;
+  void* hw_dev = nullptr;
+  if (hipHostMalloc(&hw, 64, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(PCS_ERR_OOM, "pinned host allocation of the state's words failed");
+  }
+  if (hipHostGetDevicePointer(&hw_dev, hw, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipHostFree(hw);
+    return fail(PCS_ERR_HIP, "no device address for the state's pinned words");
+  }
+  st->host = reinterpret_cast<unsigned long long*>(hw);
+  st->host_dev = reinterpret_cast<unsigned long long*>(hw_dev);
+  for (int i = 0; i < 8; ++i) st->host[i] = 0ull;
+  return PCS_OK;
+}
+
+// Status of the frame last rendered into the state, once the stream has reached its end: the
+// error word the ordering reported (host[2]) and, for a capacity-mode frame, its instance total.
+int frame_status(pcs_state* st, int64_t* required) {
+  if (required) *required = 0;
+  if (!st->host) return PCS_OK;
+  volatile unsigned long long* w = st->host;
+  const unsigned long long e = w[2], t = w[0];
+  if ((uint32_t)(e >> 32) != st->seq || (uint32_t)(t >> 32) != st->seq)
+    return fail(PCS_ERR_HIP, "the frame's status words were not delivered (stream not finished?)");
+  const uint32_t err = (uint32_t)e;
+  const int64_t total = (int64_t)(uint32_t)t;
+  if (!st->m_known && !(err & kErrSpin) && total <= st->capacity) {
+    st->m = total;
+    st->m_known = true;
+  }
+  if (err & kErrSpin)
+    return fail(PCS_ERR_HIP, "a look-back wait of the instance ordering ran out (broken launch); "
+                             "the frame was not composited");
+  if (err & kErrCapacity) {
+    if (required) *required = total;
+    return fail(PCS_ERR_CAPACITY, "the frame has " + std::to_string(total) +
+                                      " tile instances, more than the state's capacity of " +
+                                      std::to_string(st->capacity) + "; the next capacity-mode "
+                                      "render of this state is sized for it");
+  }
+  return PCS_OK;
+}
 
 int check_backward(pcs_context* ctx, const pcs_state* st, const pcs_images* grad_out,
                    const pcs_grads* grads) {
@@ -346,19 +433,6 @@ int pcs_context_create(int device, pcs_context** out) {
     return fail(PCS_ERR_OOM, "pinned host allocation failed");
   }
   ctx->host_small = reinterpret_cast<uint32_t*>(hp);
-  void* hw = nullptr;
-  void* hw_dev = nullptr;
-  if (hipHostMalloc(&hw, 64, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
-    pcs_context_destroy(ctx);
-    return fail(PCS_ERR_OOM, "pinned host allocation failed");
-  }
-  ctx->host_word = reinterpret_cast<unsigned long long*>(hw);
-  ctx->host_word[0] = ctx->host_word[1] = 0ull;
-  if (hipHostGetDevicePointer(&hw_dev, hw, 0) != hipSuccess) {
-    pcs_context_destroy(ctx);
-    return fail(PCS_ERR_HIP, "no device address for the pinned host word");
-  }
-  ctx->host_word_dev = reinterpret_cast<unsigned long long*>(hw_dev);
   // device address of the allocation-free backward's scratch on this device (taken once)
   if (noalloc_scratch(device, &ctx->noalloc_sgrad) != PCS_OK) {
     const std::string msg = g_err;
@@ -381,8 +455,15 @@ void pcs_context_destroy(pcs_context* ctx) {
   }
   delete ctx->internal;
   if (ctx->host_small) (void)hipHostFree(ctx->host_small);
-  if (ctx->host_word) (void)hipHostFree(ctx->host_word);
   delete ctx;
+}
+
+int pcs_context_set_allocator(pcs_context* ctx, pcs_alloc_fn alloc, pcs_free_fn release, void* user) {
+  if (!ctx) return fail(PCS_ERR_INVALID_ARG, "context is NULL");
+  if ((alloc == nullptr) != (release == nullptr))
+    return fail(PCS_ERR_INVALID_ARG, "give both allocator callbacks or neither");
+  ctx->alloc = Allocator{alloc, release, user};
+  return PCS_OK;
 }
 
 int pcs_context_timing_stages(pcs_context* ctx, uint32_t stage_mask) {
@@ -458,6 +539,7 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   PCS_HIP(hipSetDevice(ctx->device));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 
+  const bool capacity_mode = (opt->flags & PCS_FLAG_CAPACITY_MODE) != 0;
   pcs_state* st = state;
   if (!st) {
     if (!ctx->internal) {
@@ -467,38 +549,65 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
     st = ctx->internal;
   }
   st->valid = false;
+  PCS_TRY(state_host_words(st));
+  // Capacity mode: the tile buffers keep a fixed capacity, sized from an earlier frame's instance
+  // total (x 1.25), and the host does not wait for this frame's total. The previous frame's total,
+  // if its word has arrived, grows the capacity before anything is enqueued; the state's first
+  // capacity-mode frame is sized like a plain one (it waits once).
+  int64_t capacity = 0;
+  if (capacity_mode && st->capacity > 0) {
+    volatile unsigned long long* w = st->host;
+    const unsigned long long prev = w[0];
+    int64_t need = st->capacity;
+    if ((uint32_t)(prev >> 32) == st->seq && st->seq != 0) need = (int64_t)(uint32_t)prev;
+    if (need > st->capacity) st->capacity = std::min<int64_t>(need + need / 4, (int64_t(1) << 30) - 1);
+    capacity = st->capacity;
+  }
   // cameras reach the device as kernel arguments of the frame's first launch (no copy to wait on)
   std::vector<DevCamera> dc(n_cams);
   for (int c = 0; c < n_cams; ++c) dc[c] = to_dev(cams[c]);
-  PCS_TRY(ensure(st->dcams, sizeof(DevCamera) * n_cams, "cameras"));
+  PCS_TRY(ensure(ctx, st->dcams, sizeof(DevCamera) * n_cams, "cameras"));
+  PCS_TRY(ensure(ctx, st->words, 64, "frame words"));
+  uint32_t* d_err = st->words.as<uint32_t>();
   const DevOptions dopt = to_dev(*opt);
 
   const int64_t cn1 = std::max<int64_t>(cn, 1);
-  PCS_TRY(ensure(st->rec, cn1 * kRecFloat4 * sizeof(float4), "splat records"));
-  PCS_TRY(ensure(ctx->zbits, cn1 * sizeof(uint32_t), "depth bits"));
-  PCS_TRY(ensure(ctx->rect, cn1 * sizeof(uint2), "tile rectangles"));
-  PCS_TRY(ensure(ctx->scan_scratch, scan_scratch_bytes(cn), "scan scratch"));
-  PCS_TRY(ensure(ctx->small, kSmallWords * 4, "small"));
-  PCS_TRY(ensure(st->ranges, 2 * total_tiles * sizeof(uint32_t), "tile ranges"));
-  PCS_TRY(ensure(st->order, total_tiles * sizeof(uint32_t), "tile order"));
+  PCS_TRY(ensure(ctx, st->rec, cn1 * kRecFloat4 * sizeof(float4), "splat records"));
+  PCS_TRY(ensure(ctx, ctx->zbits, cn1 * sizeof(uint32_t), "depth bits"));
+  PCS_TRY(ensure(ctx, ctx->rect, cn1 * sizeof(uint2), "tile rectangles"));
+  PCS_TRY(ensure(ctx, ctx->scan_scratch, scan_scratch_bytes(cn), "scan scratch"));
+  PCS_TRY(ensure(ctx, ctx->small, kSmallWords * 4, "small"));
+  PCS_TRY(ensure(ctx, st->ranges, 2 * total_tiles * sizeof(uint32_t), "tile ranges"));
+  PCS_TRY(ensure(ctx, st->order, total_tiles * sizeof(uint32_t), "tile order"));
   const int64_t HWC = (int64_t)W * H * n_cams;
-  PCS_TRY(ensure(st->t_final, HWC * sizeof(float), "final transmittance"));
-  PCS_TRY(ensure(st->n_contrib, HWC * sizeof(int32_t), "last contributor"));
+  // the final transmittance and last contributor are kept only for a caller's state (backward,
+  // parity export); a render without one does not write them
+  if (state) {
+    PCS_TRY(ensure(ctx, st->t_final, HWC * sizeof(float), "final transmittance"));
+    PCS_TRY(ensure(ctx, st->n_contrib, HWC * sizeof(int32_t), "last contributor"));
+  }
 
   uint64_t* d_total = ctx->small.as<uint64_t>();
   uint32_t* d_zrange = ctx->small.as<uint32_t>() + 2;
   auto* d_counts = reinterpret_cast<unsigned long long*>(ctx->small.as<uint32_t>() + kCountWord);
   uint32_t* d_depth = ctx->small.as<uint32_t>() + kDepthWord;   // passes, depth bits, min depth bits
-  PCS_TRY(ensure(ctx->dkeys, cn1 * sizeof(uint32_t), "depth keys"));
-  PCS_TRY(ensure(ctx->dkeys_alt, cn1 * sizeof(uint32_t), "depth keys (alternate)"));
-  PCS_TRY(ensure(ctx->dvals, cn1 * sizeof(uint32_t), "depth order"));
-  PCS_TRY(ensure(ctx->dvals_alt, cn1 * sizeof(uint32_t), "depth order (alternate)"));
-  PCS_TRY(ensure(ctx->dsort_scratch, sort_scratch_bytes(cn), "depth sort scratch"));
+  PCS_TRY(ensure(ctx, ctx->dkeys, cn1 * sizeof(uint32_t), "depth keys"));
+  PCS_TRY(ensure(ctx, ctx->dkeys_alt, cn1 * sizeof(uint32_t), "depth keys (alternate)"));
+  PCS_TRY(ensure(ctx, ctx->dvals, cn1 * sizeof(uint32_t), "depth order"));
+  PCS_TRY(ensure(ctx, ctx->dvals_alt, cn1 * sizeof(uint32_t), "depth order (alternate)"));
+  PCS_TRY(ensure(ctx, ctx->dsort_scratch, sort_scratch_bytes(cn), "depth sort scratch"));
   // digit histograms counted by the kernels that write the keys: the tile sort's, then the depth
   // sort's
-  PCS_TRY(ensure(ctx->tile_hist, 2 * kTileHistWords * sizeof(uint32_t), "digit histograms"));
+  PCS_TRY(ensure(ctx, ctx->tile_hist, 2 * kTileHistWords * sizeof(uint32_t), "digit histograms"));
+  if (capacity > 0) {
+    PCS_TRY(ensure(ctx, st->keys, capacity * sizeof(uint32_t), "keys"));
+    PCS_TRY(ensure(ctx, st->vals, capacity * sizeof(uint32_t), "values"));
+    PCS_TRY(ensure(ctx, ctx->keys_alt, capacity * sizeof(uint32_t), "keys (alternate)"));
+    PCS_TRY(ensure(ctx, ctx->vals_alt, capacity * sizeof(uint32_t), "values (alternate)"));
+    PCS_TRY(ensure(ctx, ctx->sort_scratch, sort_scratch_bytes(capacity), "sort scratch"));
+  }
   uint32_t* depth_hist = ctx->tile_hist.as<uint32_t>() + kTileHistWords;
-  PCS_HIP(launch_init_small(ctx->small.as<uint32_t>(), dc.data(), n_cams, st->dcams.as<DevCamera>(), s));
+  PCS_HIP(launch_init_small(ctx->small.as<uint32_t>(), dc.data(), n_cams, st->dcams.as<DevCamera>(), s, d_err));
   {
     // the projection also clears what the depth sort and the scan need zeroed
     ClearSpans clear;
@@ -517,43 +626,52 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   // word, which the host polls); the (camera, depth) order needs nothing from the host (the depth
   // range is read from the projection's slots on the device, and sort passes beyond the bits that
   // range needs return at once), so it is all queued at once and the host sizes the tile buffers
-  // while the GPU sorts by depth.
+  // while the GPU sorts by depth. A capacity-mode frame queues every depth pass and never waits.
   ctx->seq = ctx->seq + 1 == 0 ? 1 : ctx->seq + 1;
+  st->seq = ctx->seq;
   if (cn > 0) {
     StageTimer tm(ctx, ST_SORT, s);
     bool unused = false;
-    PCS_HIP(launch_depth_keys_hist(cn, ctx->zbits.as<uint32_t>(), d_counts, ctx->host_word_dev, ctx->seq,
+    PCS_HIP(launch_depth_keys_hist(cn, ctx->zbits.as<uint32_t>(), d_counts, st->host_dev, st->seq,
                                    d_zrange, d_depth, ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(),
                                    depth_hist, s));
     // the first pass now (it returns at once if the depths need none), the others once the host
-    // knows how many the depth range needs
+    // knows how many the depth range needs (all of them in capacity mode)
     PCS_HIP(launch_sort(ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(), ctx->dkeys_alt.as<uint32_t>(),
                         ctx->dvals_alt.as<uint32_t>(), cn, 32, ctx->dsort_scratch.p, s, &unused, d_depth,
-                        true, true, depth_hist, 0, 1));
+                        true, true, depth_hist, 0, capacity > 0 ? -1 : 1, nullptr, 0, d_err,
+                        ctx->wait_limit));
   }
   uint64_t m64 = 0;
-  if (cn > 0) {
+  if (cn > 0 && capacity == 0) {
     int depth_bits = 0;
-    PCS_TRY(wait_frame_words(ctx, s, &m64, &depth_bits));
+    PCS_TRY(wait_frame_words(st, s, &m64, &depth_bits));
     const int depth_passes = (depth_bits + 7) / 8;
     if (depth_passes > 1) {
       StageTimer tm(ctx, ST_SORT, s);
       bool unused = false;
       PCS_HIP(launch_sort(ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(), ctx->dkeys_alt.as<uint32_t>(),
                           ctx->dvals_alt.as<uint32_t>(), cn, 32, ctx->dsort_scratch.p, s, &unused, d_depth,
-                          true, true, depth_hist, 1, depth_passes));
+                          true, true, depth_hist, 1, depth_passes, nullptr, 0, d_err, ctx->wait_limit));
+    }
+    if (m64 >= (uint64_t(1) << 30))
+      return fail(PCS_ERR_UNSUPPORTED, "instance count " + std::to_string(m64) + " is not below 2^30");
+    if (capacity_mode) {       // the state's first capacity-mode frame sizes the capacity
+      st->capacity = std::max<int64_t>(1024, std::min<int64_t>((int64_t)m64 + (int64_t)m64 / 4,
+                                                               (int64_t(1) << 30) - 1));
+      capacity = st->capacity;
     }
   }
-  if (m64 >= (uint64_t(1) << 30))
-    return fail(PCS_ERR_UNSUPPORTED, "instance count " + std::to_string(m64) + " is not below 2^30");
-  const int64_t m = (int64_t)m64;
+  // the tile buffers: the instance total, or the fixed capacity (then the count stays on the device)
+  const int64_t m = cn == 0 ? 0 : (capacity > 0 ? capacity : (int64_t)m64);
+  const uint64_t* m_dev = capacity > 0 ? d_total : nullptr;
   const int tile_bits = bit_length((uint64_t)(total_tiles - 1));
 
-  PCS_TRY(ensure(st->keys, std::max<int64_t>(m, 1) * sizeof(uint32_t), "keys"));
-  PCS_TRY(ensure(st->vals, std::max<int64_t>(m, 1) * sizeof(uint32_t), "values"));
-  PCS_TRY(ensure(ctx->keys_alt, std::max<int64_t>(m, 1) * sizeof(uint32_t), "keys (alternate)"));
-  PCS_TRY(ensure(ctx->vals_alt, std::max<int64_t>(m, 1) * sizeof(uint32_t), "values (alternate)"));
-  PCS_TRY(ensure(ctx->sort_scratch, sort_scratch_bytes(m), "sort scratch"));
+  PCS_TRY(ensure(ctx, st->keys, std::max<int64_t>(m, 1) * sizeof(uint32_t), "keys"));
+  PCS_TRY(ensure(ctx, st->vals, std::max<int64_t>(m, 1) * sizeof(uint32_t), "values"));
+  PCS_TRY(ensure(ctx, ctx->keys_alt, std::max<int64_t>(m, 1) * sizeof(uint32_t), "keys (alternate)"));
+  PCS_TRY(ensure(ctx, ctx->vals_alt, std::max<int64_t>(m, 1) * sizeof(uint32_t), "values (alternate)"));
+  PCS_TRY(ensure(ctx, ctx->sort_scratch, sort_scratch_bytes(m), "sort scratch"));
   if (m > 0) {
     {
       StageTimer tm(ctx, ST_BINNING, s);
@@ -568,7 +686,8 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
                                   ctx->dvals_alt.as<uint32_t>(), d_depth, ctx->rect.as<uint2>(), narrow_rect,
                                   ctx->scan_scratch.p, d_total, st->keys.as<uint32_t>(),
                                   st->vals.as<uint32_t>(), tile_bits, ctx->tile_hist.as<uint32_t>(),
-                                  clear, s));
+                                  clear, s, d_err, ctx->wait_limit,
+                                  capacity > 0 ? (uint64_t)capacity : ~uint64_t(0)));
     }
     bool in_alt = false;
     {
@@ -577,7 +696,7 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
       PCS_HIP(launch_sort(st->keys.as<uint32_t>(), st->vals.as<uint32_t>(), ctx->keys_alt.as<uint32_t>(),
                           ctx->vals_alt.as<uint32_t>(), m, tile_bits, ctx->sort_scratch.p, s, &in_alt,
                           nullptr, true, false, ctx->tile_hist.as<uint32_t>(), 0, -1,
-                          st->ranges.as<uint32_t>(), total_tiles));
+                          st->ranges.as<uint32_t>(), total_tiles, d_err, ctx->wait_limit, m_dev));
     }
     if (in_alt) {
       swap_buf(st->keys, ctx->keys_alt);
@@ -588,15 +707,18 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   {
     StageTimer tm(ctx, ST_RANGES, s);
     // runs found by the tile sort unless it had no pass to run (one instance or one tile)
-    if (m <= 1 || tile_bits == 0)
-      PCS_HIP(launch_ranges(st->keys.as<uint32_t>(), m, total_tiles, st->ranges.as<uint32_t>(), s));
-    PCS_HIP(launch_tile_order(st->ranges.as<uint32_t>(), total_tiles, st->order.as<uint32_t>(), s));
+    if ((capacity == 0 && m <= 1) || tile_bits == 0)
+      PCS_HIP(launch_ranges(st->keys.as<uint32_t>(), m, total_tiles, st->ranges.as<uint32_t>(), s, m_dev, d_err));
+    // the ordering is done: the frame's error word goes to the host
+    PCS_HIP(launch_tile_order(st->ranges.as<uint32_t>(), total_tiles, st->order.as<uint32_t>(), s, d_err,
+                              st->host_dev + 2, st->seq));
   }
   {
     StageTimer tm(ctx, ST_COMPOSITE, s, false);   // the kernel's own start and end
     PCS_HIP(launch_composite(n, n_cams, W, H, st->rec.as<float4>(), st->vals.as<uint32_t>(),
-                             st->ranges.as<uint32_t>(), st->order.as<uint32_t>(), dopt, *out, st->t_final.as<float>(),
-                             st->n_contrib.as<int32_t>(), s, tm.start(), tm.stop()));
+                             st->ranges.as<uint32_t>(), st->order.as<uint32_t>(), dopt, *out,
+                             state ? st->t_final.as<float>() : nullptr,
+                             state ? st->n_contrib.as<int32_t>() : nullptr, s, tm.start(), tm.stop()));
   }
   st->g = *g;
   st->cams.assign(cams, cams + n_cams);
@@ -605,7 +727,9 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   st->H = H;
   st->C = n_cams;
   st->n = n;
-  st->m = m;
+  st->m = capacity > 0 ? 0 : m;
+  st->m_known = capacity == 0;
+  st->capacity_frame = capacity > 0;
   st->n_tiles = total_tiles;
   st->valid = true;
   return PCS_OK;
@@ -617,7 +741,7 @@ int pcs_render_backward(pcs_context* ctx, const pcs_state* st, const pcs_images*
   PCS_HIP(hipSetDevice(ctx->device));
   const int64_t cn = st->n * st->C;
   if (cn == 0) return PCS_OK;
-  PCS_TRY(ensure(ctx->sgrad, (size_t)cn * kScreenStride * sizeof(float), "screen-space gradients"));
+  PCS_TRY(ensure(ctx, ctx->sgrad, (size_t)cn * kScreenStride * sizeof(float), "screen-space gradients"));
   return backward_launch(ctx, st, grad_out, grads, ctx->sgrad.as<float>(), true,
                          reinterpret_cast<hipStream_t>(stream));
 }
@@ -643,8 +767,9 @@ int pcs_state_bins(const pcs_state* st_c, const uint64_t** keys, const uint32_t*
   if (!st_c->valid) return fail(PCS_ERR_INVALID_ARG, "state holds no completed forward render");
   pcs_state* st = const_cast<pcs_state*>(st_c);
   PCS_HIP(hipSetDevice(st->ctx->device));
-  PCS_TRY(ensure(st->canon, std::max<int64_t>(st->m, 1) * sizeof(uint64_t), "canonical keys"));
   PCS_HIP(hipDeviceSynchronize());
+  if (st->n * st->C > 0) PCS_TRY(frame_status(st, nullptr));   // a failed frame has no lists
+  PCS_TRY(ensure(st->ctx, st->canon, std::max<int64_t>(st->m, 1) * sizeof(uint64_t), "canonical keys"));
   PCS_HIP(launch_canonical_keys(st->keys.as<uint32_t>(), st->vals.as<uint32_t>(), st->m, st->n,
                                 st->n_tiles / std::max(st->C, 1), st->rec.as<float4>(),
                                 st->canon.as<uint64_t>(), nullptr));
@@ -656,6 +781,28 @@ int pcs_state_bins(const pcs_state* st_c, const uint64_t** keys, const uint32_t*
   if (n_tiles) *n_tiles = st->n_tiles;
   if (n_contrib) *n_contrib = st->n_contrib.as<int32_t>();
   if (t_final) *t_final = st->t_final.as<float>();
+  return PCS_OK;
+}
+
+int pcs_state_status(pcs_state* st, int64_t* required, void* stream) {
+  if (required) *required = 0;
+  if (!st) return fail(PCS_ERR_INVALID_ARG, "state is NULL");
+  if (!st->valid) return fail(PCS_ERR_INVALID_ARG, "state holds no completed forward render");
+  PCS_HIP(hipSetDevice(st->ctx->device));
+  PCS_HIP(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
+  if (st->n * st->C == 0) return PCS_OK;
+  return frame_status(st, required);
+}
+
+int pcs_state_capacity(const pcs_state* st, int64_t* capacity) {
+  if (!st || !capacity) return fail(PCS_ERR_INVALID_ARG, "NULL argument");
+  *capacity = st->capacity;
+  return PCS_OK;
+}
+
+int pcs_context_set_wait_limit(pcs_context* ctx, uint32_t rounds) {
+  if (!ctx) return fail(PCS_ERR_INVALID_ARG, "context is NULL");
+  ctx->wait_limit = rounds;
   return PCS_OK;
 }
 
@@ -674,7 +821,7 @@ int pcs_knn_pca(pcs_context* ctx, const float* xyz, int64_t n, int32_t k, float 
   if (n == 0) return PCS_OK;
   PCS_HIP(hipSetDevice(ctx->device));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  PCS_TRY(ensure(ctx->knn_scratch, knn_scratch_bytes(n), "kNN scratch"));
+  PCS_TRY(ensure(ctx, ctx->knn_scratch, knn_scratch_bytes(n), "kNN scratch"));
   StageTimer tm(ctx, ST_KNN, s);
   PCS_HIP(launch_knn_pca(xyz, n, k, kappa, floor_ratio, quat, scale, normal, nn_dist, ctx->knn_scratch.p,
                          ctx->knn_scratch.cap, ctx->host_small + 192, s));
@@ -709,7 +856,7 @@ int pcs_shade(pcs_context* ctx, const pcs_images* in, const pcs_camera* cams, in
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   std::vector<DevCamera> dc(n_cams);
   for (int c = 0; c < n_cams; ++c) dc[c] = to_dev(cams[c]);
-  PCS_TRY(ensure(ctx->shade_cams, sizeof(DevCamera) * n_cams, "cameras"));
+  PCS_TRY(ensure(ctx, ctx->shade_cams, sizeof(DevCamera) * n_cams, "cameras"));
   PCS_HIP(hipMemcpyAsync(ctx->shade_cams.p, dc.data(), sizeof(DevCamera) * n_cams, hipMemcpyHostToDevice, s));
   StageTimer tm(ctx, ST_SHADE, s);
   PCS_HIP(launch_shade(W, H, n_cams, ctx->shade_cams.as<DevCamera>(), in->rgb, in->normal, in->alpha, L,
@@ -737,22 +884,25 @@ int pcs_voxelize(pcs_context* ctx, const float* xyz, const float* rgb, int64_t n
   PCS_HIP(hipSetDevice(ctx->device));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   vox->valid = false;
-  PCS_TRY(ensure(vox->keys, n * sizeof(uint64_t), "voxel keys"));
-  PCS_TRY(ensure(vox->order, n * sizeof(uint32_t), "voxel point order"));
-  PCS_TRY(ensure(ctx->keys_alt, n * sizeof(uint64_t), "keys (alternate)"));
-  PCS_TRY(ensure(ctx->vals_alt, n * sizeof(uint32_t), "values (alternate)"));
-  PCS_TRY(ensure(ctx->sort_scratch, sort_scratch_bytes(n), "sort scratch"));
-  PCS_TRY(ensure(vox->flag, n * sizeof(uint32_t), "voxel flags"));
-  PCS_TRY(ensure(vox->excl, n * sizeof(uint32_t) + 64, "voxel numbering"));
-  PCS_TRY(ensure(ctx->scan_scratch, scan_scratch_bytes(n), "scan scratch"));
-  PCS_TRY(ensure(ctx->small, kSmallWords * 4, "small"));
-  PCS_TRY(ensure(vox->point_voxel, n * sizeof(int32_t), "point to voxel map"));
-  PCS_TRY(ensure(vox->centroid, 64, "centroid"));
+  PCS_TRY(ensure(ctx, vox->keys, n * sizeof(uint64_t), "voxel keys"));
+  PCS_TRY(ensure(ctx, vox->order, n * sizeof(uint32_t), "voxel point order"));
+  PCS_TRY(ensure(ctx, ctx->keys_alt, n * sizeof(uint64_t), "keys (alternate)"));
+  PCS_TRY(ensure(ctx, ctx->vals_alt, n * sizeof(uint32_t), "values (alternate)"));
+  PCS_TRY(ensure(ctx, ctx->sort_scratch, sort_scratch_bytes(n), "sort scratch"));
+  PCS_TRY(ensure(ctx, vox->flag, n * sizeof(uint32_t), "voxel flags"));
+  PCS_TRY(ensure(ctx, vox->excl, n * sizeof(uint32_t) + 64, "voxel numbering"));
+  PCS_TRY(ensure(ctx, ctx->scan_scratch, scan_scratch_bytes(n), "scan scratch"));
+  PCS_TRY(ensure(ctx, ctx->small, kSmallWords * 4, "small"));
+  PCS_TRY(ensure(ctx, vox->point_voxel, n * sizeof(int32_t), "point to voxel map"));
+  PCS_TRY(ensure(ctx, vox->centroid, 64, "centroid"));
   StageTimer tm(ctx, ST_VOXELIZE, s);
+  uint32_t* d_err = ctx->small.as<uint32_t>() + kVoxErrWord;
+  PCS_HIP(launch_fill_u32(d_err, 0u, 1, s));
   PCS_HIP(launch_vox_keys(xyz, n, grid, vox->keys.as<uint64_t>(), vox->order.as<uint32_t>(), s));
   bool in_alt = false;
   PCS_HIP(launch_sort(vox->keys.as<uint64_t>(), vox->order.as<uint32_t>(), ctx->keys_alt.as<uint64_t>(),
-                      ctx->vals_alt.as<uint32_t>(), n, 30, ctx->sort_scratch.p, s, &in_alt));
+                      ctx->vals_alt.as<uint32_t>(), n, 30, ctx->sort_scratch.p, s, &in_alt, nullptr, false,
+                      false, nullptr, 0, -1, nullptr, 0, d_err, ctx->wait_limit));
   if (in_alt) {
     swap_buf(vox->keys, ctx->keys_alt);
     swap_buf(vox->order, ctx->vals_alt);
@@ -760,19 +910,22 @@ int pcs_voxelize(pcs_context* ctx, const float* xyz, const float* rgb, int64_t n
   PCS_HIP(launch_vox_flags(vox->keys.as<uint64_t>(), n, vox->flag.as<uint32_t>(), s));
   uint64_t* d_total = ctx->small.as<uint64_t>();
   PCS_HIP(launch_scan(vox->flag.as<uint32_t>(), nullptr, nullptr, nullptr, vox->excl.as<uint32_t>(), n, d_total,
-                      ctx->scan_scratch.p, s));
+                      ctx->scan_scratch.p, s, false, d_err, ctx->wait_limit));
   PCS_HIP(hipMemcpyAsync(ctx->host_small, d_total, 8, hipMemcpyDeviceToHost, s));
+  PCS_HIP(hipMemcpyAsync(ctx->host_small + 2, d_err, 4, hipMemcpyDeviceToHost, s));
   PCS_HIP(hipStreamSynchronize(s));
+  if (ctx->host_small[2] != 0u)
+    return fail(PCS_ERR_HIP, "a look-back wait of the voxel sort or numbering ran out (broken launch)");
   uint64_t V;
   std::memcpy(&V, ctx->host_small, 8);
   int log2cap = 6;
   while ((int64_t(1) << log2cap) < (int64_t)(2 * V)) ++log2cap;
-  PCS_TRY(ensure(vox->start, V * sizeof(uint32_t) + 64, "voxel starts"));
-  PCS_TRY(ensure(vox->coords, 3 * V * sizeof(int32_t), "voxel coordinates"));
-  PCS_TRY(ensure(vox->feat, V * 32 * sizeof(uint16_t), "voxel features"));
-  PCS_TRY(ensure(vox->hkeys, (size_t(1) << log2cap) * sizeof(uint32_t), "voxel hash keys"));
-  PCS_TRY(ensure(vox->hvals, (size_t(1) << log2cap) * sizeof(int32_t), "voxel hash values"));
-  PCS_TRY(ensure(vox->nbr, 27 * V * sizeof(int32_t), "kernel map"));
+  PCS_TRY(ensure(ctx, vox->start, V * sizeof(uint32_t) + 64, "voxel starts"));
+  PCS_TRY(ensure(ctx, vox->coords, 3 * V * sizeof(int32_t), "voxel coordinates"));
+  PCS_TRY(ensure(ctx, vox->feat, V * 32 * sizeof(uint16_t), "voxel features"));
+  PCS_TRY(ensure(ctx, vox->hkeys, (size_t(1) << log2cap) * sizeof(uint32_t), "voxel hash keys"));
+  PCS_TRY(ensure(ctx, vox->hvals, (size_t(1) << log2cap) * sizeof(int32_t), "voxel hash values"));
+  PCS_TRY(ensure(ctx, vox->nbr, 27 * V * sizeof(int32_t), "kernel map"));
   PCS_HIP(launch_vox_build(vox->keys.as<uint64_t>(), vox->order.as<uint32_t>(), vox->flag.as<uint32_t>(),
                            vox->excl.as<uint32_t>(), n, (int64_t)V, xyz, rgb, grid, vox->start.as<uint32_t>(),
                            vox->coords.as<int32_t>(), vox->feat.as<uint16_t>(),
@@ -821,14 +974,14 @@ int pcs_subm_conv_backward(pcs_context* ctx, const pcs_voxels* vox, const uint16
   StageTimer tm(ctx, ST_CONV_BWD, s);
   const uint16_t* g = dy;
   if (y) {
-    PCS_TRY(ensure(ctx->conv_tmp, (size_t)vox->V * cout * sizeof(uint16_t), "masked output gradient"));
+    PCS_TRY(ensure(ctx, ctx->conv_tmp, (size_t)vox->V * cout * sizeof(uint16_t), "masked output gradient"));
     PCS_HIP(launch_relu_mask(y, dy, vox->V * cout, ctx->conv_tmp.as<uint16_t>(), s));
     g = ctx->conv_tmp.as<uint16_t>();
   }
   if (dbias) PCS_HIP(launch_bias_grad(g, vox->V, cout, dbias, s));
   if (dw) PCS_HIP(launch_subm_conv_dw(x, cin, g, cout, vox->nbr.as<int32_t>(), vox->V, dw, s));
   if (dx) {
-    PCS_TRY(ensure(ctx->wt_tmp, (size_t)27 * cin * cout * sizeof(uint16_t), "transposed weights"));
+    PCS_TRY(ensure(ctx, ctx->wt_tmp, (size_t)27 * cin * cout * sizeof(uint16_t), "transposed weights"));
     PCS_HIP(launch_weight_flip_t(w, cin, cout, ctx->wt_tmp.as<uint16_t>(), s));
     PCS_HIP(launch_subm_conv(g, cout, ctx->wt_tmp.as<uint16_t>(), nullptr, cin, vox->nbr.as<int32_t>(),
                              vox->V, 0, dx, s));

@@ -122,6 +122,12 @@ __device__ __forceinline__ void wave_sum16_rows(const float (&v)[16], float (&ou
   }
 }
 
+// Bits of a frame's error word (device, one per render state): a look-back that waited too long
+// (a broken launch), and more tile instances than a fixed capacity holds. Kernels that consume the
+// failed stage's output return at once.
+constexpr uint32_t kErrSpin = 1u;
+constexpr uint32_t kErrCapacity = 2u;
+
 // Zeroing folded into a kernel that runs anyway: every thread of the grid clears the words
 // i = its global index, + the grid size, ... of each span (a span of count 0 is skipped).
 struct ClearSpans {
@@ -154,6 +160,7 @@ constexpr int kZSlots = 64;
 // launch_init_small.
 constexpr int kCountWord = 2 + 2 * kZSlots;
 constexpr int kDepthWord = kCountWord + 2 * kZSlots;
+constexpr int kVoxErrWord = kDepthWord + 3;   // error word of a voxelisation
 constexpr int kSmallWords = kDepthWord + 4;
 // Cameras travel to the device as kernel arguments, kArgCams per launch: the frame's first launch
 // resets the small words and writes the first batch into dst.
@@ -161,8 +168,9 @@ constexpr int kArgCams = 8;
 struct CamBatch {
   DevCamera c[kArgCams];
 };
+// err (may be null): the frame's error word, cleared with the small words.
 hipError_t launch_init_small(uint32_t* small, const DevCamera* cams, int n_cams, DevCamera* dst,
-                             hipStream_t s);
+                             hipStream_t s, uint32_t* err = nullptr);
 hipError_t launch_project(int64_t n, int n_cams, const DevCamera* cams, const DevOptions& opt,
                           const pcs_gaussians& g, float4* rec, uint32_t* zbits, uint2* rect,
                           bool narrow_rect, uint32_t* zrange, unsigned long long* count_slots,
@@ -171,9 +179,12 @@ hipError_t launch_project(int64_t n, int n_cams, const DevCamera* cams, const De
 // Exclusive scan of n u32 values in[gather[j]] (no gather: in[j]); writes out[n] and *total (u64).
 // gather is gather1 when sel is set and *sel is odd, else gather0. Scratch from scan_scratch_bytes.
 size_t scan_scratch_bytes(int64_t n);
+// err (may be null): set to kErrSpin if a look-back wait runs out its bound (spin_limit rounds,
+// 0 = the default).
 hipError_t launch_scan(const uint32_t* in, const uint32_t* gather0, const uint32_t* gather1,
                        const uint32_t* sel, uint32_t* out, int64_t n, uint64_t* total, void* scratch,
-                       hipStream_t s, bool scratch_cleared = false);
+                       hipStream_t s, bool scratch_cleared = false, uint32_t* err = nullptr,
+                       uint32_t spin_limit = 0);
 // Words of scan scratch that must be zero before a scan of n values.
 int64_t scan_clear_words(int64_t n);
 
@@ -203,12 +214,17 @@ constexpr int64_t kTileHistWords = (int64_t)kTileHistCopies * kTileHistPasses * 
 // for the tile sort (launch_sort with ext_hist). scan_scratch must be cleared (scan_clear_words);
 // *total receives the instance count. rect holds the rectangles in their narrow form when
 // narrow_rect is set (store_rect).
+// err: the frame's error word (binning returns at once if it is set; a look-back that waits
+// more than spin_limit rounds, 0 = the default bound, sets kErrSpin and goes on). capacity: keys
+// and values are written only below it (more instances set kErrCapacity; *total still receives
+// the full count).
 hipError_t launch_scan_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_cam,
                                const uint32_t* order0, const uint32_t* order1,
                                const uint32_t* passes, const uint2* rect, bool narrow_rect,
                                void* scan_scratch, uint64_t* total, uint32_t* keys, uint32_t* vals,
                                int tile_bits,
-                               uint32_t* hist, const ClearSpans& clear, hipStream_t s);
+                               uint32_t* hist, const ClearSpans& clear, hipStream_t s, uint32_t* err,
+                               uint32_t spin_limit, uint64_t capacity);
 
 // Stable LSD radix sort of (key, value) pairs over key bits [0, bits), K = uint32_t or uint64_t;
 // keys must have no bit set at or above `bits` (the ranking skips those bits).
@@ -222,12 +238,16 @@ size_t sort_scratch_bytes(int64_t m);
 // ranges (32-bit keys below n_tiles, zeroed beforehand): the last pass also records every key's
 // run as ranges[key] = ~start, ranges[n_tiles + key] = end (launch_tile_order turns the starts
 // back into plain ones).
+// err (may be null): the passes return at once if it is set, and a look-back that waits more than
+// spin_limit rounds (0 = the default bound) sets kErrSpin. m_dev (may be null): the element count
+// is read on the device (at most m, which then sizes the launch).
 template <typename K>
 hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int bits, void* scratch,
                        hipStream_t s, bool* result_in_alt, const uint32_t* live_passes = nullptr,
                        bool scratch_cleared = false, bool hist_ready = false,
                        const uint32_t* ext_hist = nullptr, int pass_begin = 0, int pass_end = -1,
-                       uint32_t* ranges = nullptr, int64_t n_tiles = 0);
+                       uint32_t* ranges = nullptr, int64_t n_tiles = 0, uint32_t* err = nullptr,
+                       uint32_t spin_limit = 0, const uint64_t* m_dev = nullptr);
 // Words at the start of sort scratch that must be zero before a sort of m pairs (cleared by the
 // sort itself unless the caller has cleared them and says so).
 int64_t sort_clear_words(int64_t m);
@@ -235,11 +255,16 @@ int64_t sort_clear_words(int64_t m);
 // ranges must be zero (cleared by the caller, e.g. folded into binning); starts are written
 // complemented, like the sort's (launch_tile_order turns them back).
 hipError_t launch_ranges(const uint32_t* keys, int64_t m, int64_t n_tiles, uint32_t* ranges,
-                         hipStream_t s);
+                         hipStream_t s, const uint64_t* m_dev = nullptr, const uint32_t* err = nullptr);
 
 // Permutation of the tiles for compositing: longest lists first, empty tiles last. Reads the
-// complemented starts and leaves plain ones.
-hipError_t launch_tile_order(uint32_t* ranges, int64_t n_tiles, uint32_t* order, hipStream_t s);
+// complemented starts and leaves plain ones. report (pinned host memory, may be null) receives
+// seq << 32 | the frame's error word; if that word is set, every tile's run is left empty instead
+// (the order is then the identity), so that compositing and its adjoint read nothing the failed
+// stage produced.
+hipError_t launch_tile_order(uint32_t* ranges, int64_t n_tiles, uint32_t* order, hipStream_t s,
+                             const uint32_t* err = nullptr, unsigned long long* report = nullptr,
+                             uint32_t seq = 0);
 
 hipError_t launch_canonical_keys(const uint32_t* keys, const uint32_t* vals, int64_t m, int64_t n,
                                  int64_t tiles_per_cam, const float4* rec, uint64_t* out,

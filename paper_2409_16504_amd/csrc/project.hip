@@ -124,11 +124,12 @@ __global__ __launch_bounds__(256) void k_project(
 
 // Resets the small words (when small is set) and copies n of the batch's cameras to dst.
 __global__ __launch_bounds__(256) void k_init_small(uint32_t* __restrict__ small, CamBatch cams, int n,
-                                                    DevCamera* __restrict__ dst) {
+                                                    DevCamera* __restrict__ dst, uint32_t* __restrict__ err) {
   const int i = threadIdx.x;
   constexpr int kWords = (int)(sizeof(DevCamera) / 4);
   if (i < n * kWords)
     reinterpret_cast<uint32_t*>(dst)[i] = reinterpret_cast<const uint32_t*>(cams.c)[i];
+  if (err && i == 0) *err = 0u;                               // the frame's error word
   if (!small) return;
   if (i < 2) small[i] = 0u;                                   // instance total (u64)
   if (i < kZSlots) {
@@ -153,14 +154,14 @@ hipError_t launch_fill_f32(float* p, float value, int64_t n, hipStream_t s) {
 }
 
 hipError_t launch_init_small(uint32_t* small, const DevCamera* cams, int n_cams, DevCamera* dst,
-                             hipStream_t s) {
+                             hipStream_t s, uint32_t* err) {
   static_assert(kArgCams * sizeof(DevCamera) / 4 <= 256 && 2 * kZSlots <= 256, "one 256-thread block");
   for (int c0 = 0; c0 == 0 || c0 < n_cams; c0 += kArgCams) {
     CamBatch b{};
     const int nb = std::min(kArgCams, n_cams - c0);
     for (int k = 0; k < nb; ++k) b.c[k] = cams[c0 + k];
     hipLaunchKernelGGL(k_init_small, dim3(1), dim3(256), 0, s, c0 == 0 ? small : nullptr, b,
-                       std::max(nb, 0), dst + c0);
+                       std::max(nb, 0), dst + c0, c0 == 0 ? err : nullptr);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

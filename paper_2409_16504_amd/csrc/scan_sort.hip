@@ -56,6 +56,16 @@ __device__ __forceinline__ void atomic_store_u32(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The frame's error word (null: none kept): a kernel whose input a failed stage produced returns
+// at once.
+__device__ __forceinline__ bool frame_failed(const uint32_t* err) {
+  return err && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+}
+
+__device__ __forceinline__ void flag_error(uint32_t* err, uint32_t bits) {
+  if (err) atomicOr(err, bits);
+}
+
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
@@ -68,7 +78,8 @@ __global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* __restrict__ 
                                                    const uint32_t* __restrict__ sel,
                                                    uint32_t* __restrict__ out, int64_t n,
                                                    int64_t n_parts, uint64_t* __restrict__ status,
-                                                   uint64_t* __restrict__ total) {
+                                                   uint64_t* __restrict__ total,
+                                                   uint32_t* __restrict__ err, uint32_t spin_limit) {
   __shared__ uint64_t s_wave[kWaves];
   __shared__ uint64_t s_excl;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
@@ -118,8 +129,12 @@ __global__ __launch_bounds__(kThreads) void k_scan(const uint32_t* __restrict__ 
         const uint64_t zero = __ballot(flag == 0);
         const int first = pre ? __ffsll((unsigned long long)pre) - 1 : kWave;
         const uint64_t need = first < kWave ? (first == 63 ? ~0ull : ((2ull << first) - 1)) : ~0ull;
-        // a predecessor has not published yet; the bound only guards against a broken launch
-        if ((zero & need) && ++spins < kSpinLimit) continue;
+        // a predecessor has not published yet; a wait that runs out (a broken launch) marks the
+        // result as failed and goes on with what it has, so the kernel still ends
+        if (zero & need) {
+          if (++spins < spin_limit) continue;
+          if (lane == 0) flag_error(err, kErrSpin);
+        }
         excl += wave_sum_u64(lane <= first ? (v & kScanValue) : 0ull);
         if (first < kWave) break;
         p -= kWave;
@@ -171,7 +186,8 @@ __global__ __launch_bounds__(kThreads) void k_scan_bin(
     const uint32_t* __restrict__ order1, const uint32_t* __restrict__ passes,
     const uint2* __restrict__ rect, bool narrow_rect, int64_t n_parts, uint64_t* __restrict__ status,
     uint64_t* __restrict__ instances, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
-    int n_digits, uint32_t* __restrict__ hist, ClearSpans clear) {
+    int n_digits, uint32_t* __restrict__ hist, ClearSpans clear, uint32_t* __restrict__ err,
+    uint32_t spin_limit, uint64_t capacity) {
   __shared__ uint32_t s_off[kBinPart];          // block-relative offset of each position
   __shared__ uint32_t s_idx[kBinPart];          // its (camera, Gaussian) entry
   __shared__ uint2 s_rect[kBinPart];
@@ -180,6 +196,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_bin(
   __shared__ uint64_t s_excl;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   clear_spans(clear, (int64_t)blockIdx.x * kThreads + tid, (int64_t)gridDim.x * kThreads);
+  if (frame_failed(err)) return;          // the depth order is not valid: nothing to place
   for (int d = 0; d < kTileHistPasses; ++d) sh[d][tid] = 0u;
   const int64_t part = blockIdx.x;    // in-order dispatch: predecessors are running or done
   const int64_t base = part * kBinPart + (int64_t)tid * kBinItems;
@@ -232,8 +249,12 @@ __global__ __launch_bounds__(kThreads) void k_scan_bin(
         const uint64_t zero = __ballot(flag == 0);
         const int first = pre ? __ffsll((unsigned long long)pre) - 1 : kWave;
         const uint64_t need = first < kWave ? (first == 63 ? ~0ull : ((2ull << first) - 1)) : ~0ull;
-        // a predecessor has not published yet; the bound only guards against a broken launch
-        if ((zero & need) && ++spins < kSpinLimit) continue;
+        // a predecessor has not published yet; a wait that runs out (a broken launch) marks the
+        // frame as failed and goes on with what it has, so the kernel still ends
+        if (zero & need) {
+          if (++spins < spin_limit) continue;
+          if (lane == 0) flag_error(err, kErrSpin);
+        }
         excl += wave_sum_u64(lane <= first ? (v & kScanValue) : 0ull);
         if (first < kWave) break;
         p -= kWave;
@@ -267,6 +288,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_bin(
       const uint32_t i = s_idx[j[t]];
       const uint32_t cam = i / n;
       const uint32_t key = cam * tiles_per_cam + (y0 + dy) * (uint32_t)TX + x0 + dx;
+      if (out0 + p >= capacity) break;           // beyond a fixed capacity: counted, not written
       keys[out0 + p] = key;
       vals[out0 + p] = i - cam * n;
       for (int d = 0; d < n_digits; ++d) atomicAdd(&sh[d][(key >> (8 * d)) & 0xFF], 1u);
@@ -278,7 +300,10 @@ __global__ __launch_bounds__(kThreads) void k_scan_bin(
     const uint32_t v = sh[d][tid];
     if (v) atomicAdd(&h[d * kBins + tid], v);
   }
-  if (part == n_parts - 1 && tid == 0) *instances = out0 + block_total;
+  if (part == n_parts - 1 && tid == 0) {
+    *instances = out0 + block_total;
+    if (out0 + block_total > capacity) flag_error(err, kErrCapacity);
+  }
 }
 
 // ---- radix sort -----------------------------------------------------------------------------
@@ -448,16 +473,21 @@ __global__ __launch_bounds__(256) void k_depth_keys_hist(int64_t m, const uint32
 template <typename K, int THREADS, int ITEMS>
 __global__ __launch_bounds__(THREADS) void k_onesweep(
     const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
-    uint32_t* __restrict__ vout, uint32_t m, int shift, int digit_bits,
+    uint32_t* __restrict__ vout, uint32_t m_arg, int shift, int digit_bits,
     const uint32_t* __restrict__ hist_row,
     int copies, int64_t copy_stride, uint32_t* __restrict__ status,
     uint32_t* __restrict__ status_next, uint32_t* __restrict__ gstatus,
     uint32_t* __restrict__ gstatus_next, const uint32_t* __restrict__ live_passes, int pass,
-    uint32_t* __restrict__ ranges, uint32_t n_tiles) {
+    uint32_t* __restrict__ ranges, uint32_t n_tiles, uint32_t* __restrict__ err, uint32_t spin_limit,
+    const uint64_t* __restrict__ m_dev) {
   constexpr int W = THREADS / kWave;
   constexpr int PART = THREADS * ITEMS;
   constexpr int kItems = ITEMS;
   if (live_passes && pass >= (int)*live_passes) return;    // digit beyond the data's bits
+  if (frame_failed(err)) return;
+  // with the count on the device (a fixed-capacity launch), partitions past it have nothing to do
+  const uint32_t m = m_dev ? (uint32_t)min(*m_dev, (uint64_t)m_arg) : m_arg;
+  if (blockIdx.x * (uint32_t)PART >= m) return;
   __shared__ uint32_t s_hist[W][kBins];        // per-wave counts, then per-wave offsets
   __shared__ uint32_t s_local[kBins];          // block-local start of each digit run
   __shared__ uint32_t s_global[kBins];         // global start of the run minus its local start
@@ -604,8 +634,11 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
           acc += v[w] & kSortValue;
           if (flag == kSortPrefix) state = 1;
         }
-        if (state == 2 && ++spins < kSpinLimit) continue;
-        break;                               // a spin-out guards a broken launch only
+        if (state == 2) {
+          if (++spins < spin_limit) continue;
+          flag_error(err, kErrSpin);           // a broken launch: the frame is marked failed
+        }
+        break;
       }
       excl += acc;
       // the group's total is known as soon as its last partition has read the group (group 0 always
@@ -630,7 +663,8 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
             if (flag == kSortPrefix) state = 1;
           }
           if (state == 2) {
-            if (++spins < kSpinLimit) continue;
+            if (++spins < spin_limit) continue;
+            flag_error(err, kErrSpin);
             break;
           }
           excl += acc;
@@ -671,9 +705,12 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   }
 }
 
-__global__ void k_ranges(const uint32_t* __restrict__ keys, int64_t m, int64_t n_tiles,
-                         uint32_t* __restrict__ ranges) {
+__global__ void k_ranges(const uint32_t* __restrict__ keys, int64_t m_arg, int64_t n_tiles,
+                         uint32_t* __restrict__ ranges, const uint64_t* __restrict__ m_dev,
+                         const uint32_t* __restrict__ err) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (frame_failed(err)) return;
+  const int64_t m = m_dev ? (int64_t)min(*m_dev, (uint64_t)m_arg) : m_arg;
   if (i >= m) return;
   const uint32_t t = keys[i];
   if (t >= (uint64_t)n_tiles) return;
@@ -697,9 +734,25 @@ __device__ __forceinline__ int order_bucket(uint32_t len) {
 
 __global__ __launch_bounds__(kOrderThreads) void k_tile_order(uint32_t* __restrict__ ranges,
                                                               int64_t n_tiles,
-                                                              uint32_t* __restrict__ order) {
+                                                              uint32_t* __restrict__ order,
+                                                              const uint32_t* __restrict__ err,
+                                                              unsigned long long* __restrict__ report,
+                                                              uint32_t seq) {
   __shared__ uint32_t s_cnt[kOrderBuckets + 1];
   const int tid = threadIdx.x, lane = lane_id();
+  // the frame's ordering is complete here: its error word goes to the host (one system-scope
+  // store), and a failed frame has no valid runs to order
+  if (tid == 0 && report)
+    __hip_atomic_store(report, ((unsigned long long)seq << 32) | (err ? *err : 0u), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+  if (frame_failed(err)) {
+    for (int64_t t = tid; t < n_tiles; t += kOrderThreads) {
+      ranges[t] = 0u;
+      ranges[n_tiles + t] = 0u;
+      order[t] = (uint32_t)t;
+    }
+    return;
+  }
   const uint64_t lt = lanemask_lt();
   constexpr int kPer = 8;                          // tiles per thread per step, loads issued first
   constexpr int64_t kStep = (int64_t)kOrderThreads * kPer;
@@ -794,7 +847,7 @@ int64_t scan_clear_words(int64_t n) { return (n + kBinPart - 1) / kBinPart * 2; 
 
 hipError_t launch_scan(const uint32_t* in, const uint32_t* gather0, const uint32_t* gather1,
                        const uint32_t* sel, uint32_t* out, int64_t n, uint64_t* total, void* scratch,
-                       hipStream_t s, bool scratch_cleared) {
+                       hipStream_t s, bool scratch_cleared, uint32_t* err, uint32_t spin_limit) {
   const int64_t parts = (n + kPart - 1) / kPart;
   uint64_t* status = reinterpret_cast<uint64_t*>(scratch);
   hipError_t e = scratch_cleared ? hipSuccess
@@ -802,7 +855,7 @@ hipError_t launch_scan(const uint32_t* in, const uint32_t* gather0, const uint32
   if (e != hipSuccess) return e;
   if (n == 0) return launch_fill_u32(reinterpret_cast<uint32_t*>(total), 0u, 2, s);
   hipLaunchKernelGGL(k_scan, dim3((unsigned)parts), dim3(kThreads), 0, s, in, gather0, gather1, sel, out,
-                     n, parts, status, total);
+                     n, parts, status, total, err, spin_limit ? spin_limit : kSpinLimit);
   return hipGetLastError();
 }
 
@@ -823,7 +876,8 @@ hipError_t launch_scan_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_
                                const uint32_t* order0, const uint32_t* order1,
                                const uint32_t* passes, const uint2* rect, bool narrow_rect,
                                void* scan_scratch, uint64_t* total, uint32_t* keys, uint32_t* vals, int tile_bits,
-                               uint32_t* hist, const ClearSpans& clear, hipStream_t s) {
+                               uint32_t* hist, const ClearSpans& clear, hipStream_t s, uint32_t* err,
+                               uint32_t spin_limit, uint64_t capacity) {
   const int64_t cn = n * n_cams;
   if (cn == 0) return hipSuccess;
   if (tile_bits > 8 * kTileHistPasses) return hipErrorInvalidValue;
@@ -831,7 +885,7 @@ hipError_t launch_scan_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_
   hipLaunchKernelGGL(k_scan_bin, dim3((unsigned)parts), dim3(kThreads), 0, s, cn, (uint32_t)n, TX,
                      (uint32_t)tiles_per_cam, order0, order1, passes, rect, narrow_rect, parts,
                      reinterpret_cast<uint64_t*>(scan_scratch), total, keys, vals, (tile_bits + 7) / 8,
-                     hist, clear);
+                     hist, clear, err, spin_limit ? spin_limit : kSpinLimit, capacity);
   return hipGetLastError();
 }
 
@@ -862,7 +916,8 @@ template <typename K>
 hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int bits, void* scratch,
                        hipStream_t s, bool* result_in_alt, const uint32_t* live_passes,
                        bool scratch_cleared, bool hist_ready, const uint32_t* ext_hist,
-                       int pass_begin, int pass_end, uint32_t* ranges, int64_t n_tiles) {
+                       int pass_begin, int pass_end, uint32_t* ranges, int64_t n_tiles,
+                       uint32_t* err, uint32_t spin_limit, const uint64_t* m_dev) {
   *result_in_alt = false;
   if (m <= 1 || bits <= 0) return hipSuccess;
   // the chained scan's status words carry 30-bit counts
@@ -909,7 +964,7 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
     uint32_t* rng = p == n_passes - 1 ? ranges : nullptr;
     hipLaunchKernelGGL((k_onesweep<K, kSweepThreads, kSweepItems>), dim3((unsigned)sweep_parts), dim3(kSweepThreads), 0, s, ki, vi, ko, vo, (uint32_t)m,
                        8 * p, std::min(8, bits - 8 * p), rows + p * kBins, copies, copy_stride, st, st_next, gst, gst_next, live_passes, p,
-                       rng, (uint32_t)n_tiles);
+                       rng, (uint32_t)n_tiles, err, spin_limit ? spin_limit : kSpinLimit, m_dev);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     std::swap(ki, ko);
     std::swap(vi, vo);
@@ -919,21 +974,26 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
 }
 template hipError_t launch_sort<uint32_t>(uint32_t*, uint32_t*, uint32_t*, uint32_t*, int64_t, int,
                                           void*, hipStream_t, bool*, const uint32_t*, bool, bool,
-                                          const uint32_t*, int, int, uint32_t*, int64_t);
+                                          const uint32_t*, int, int, uint32_t*, int64_t, uint32_t*,
+                                          uint32_t, const uint64_t*);
 template hipError_t launch_sort<uint64_t>(uint64_t*, uint32_t*, uint64_t*, uint32_t*, int64_t, int,
                                           void*, hipStream_t, bool*, const uint32_t*, bool, bool,
-                                          const uint32_t*, int, int, uint32_t*, int64_t);
+                                          const uint32_t*, int, int, uint32_t*, int64_t, uint32_t*,
+                                          uint32_t, const uint64_t*);
 
 hipError_t launch_ranges(const uint32_t* keys, int64_t m, int64_t n_tiles, uint32_t* ranges,
-                         hipStream_t s) {
+                         hipStream_t s, const uint64_t* m_dev, const uint32_t* err) {
   if (m == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ranges, dim3(blocks_for(m, 256)), dim3(256), 0, s, keys, m, n_tiles, ranges);
+  hipLaunchKernelGGL(k_ranges, dim3(blocks_for(m, 256)), dim3(256), 0, s, keys, m, n_tiles, ranges,
+                     m_dev, err);
   return hipGetLastError();
 }
 
-hipError_t launch_tile_order(uint32_t* ranges, int64_t n_tiles, uint32_t* order, hipStream_t s) {
+hipError_t launch_tile_order(uint32_t* ranges, int64_t n_tiles, uint32_t* order, hipStream_t s,
+                             const uint32_t* err, unsigned long long* report, uint32_t seq) {
   if (n_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, s, ranges, n_tiles, order);
+  hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, s, ranges, n_tiles, order, err,
+                     report, seq);
   return hipGetLastError();
 }
 

@@ -82,16 +82,55 @@ class RenderState:
         self.keep = None          # tensors the state points at (inputs must stay alive)
         self.shape = None
 
+    def status(self) -> tuple[int, int]:
+        """(status code, required instances) of the last frame rendered into this state; waits for
+        the current stream. Codes: _lib.PCS_OK, PCS_ERR_CAPACITY (capacity mode: more instances
+        than the capacity), PCS_ERR_HIP (the instance ordering failed)."""
+        req = ctypes.c_int64()
+        with torch.cuda.device(self.renderer.device):
+            rc = _lib.load().pcs_state_status(self.handle, ctypes.byref(req), _stream())
+        return rc, int(req.value)
+
+    def check(self) -> None:
+        """Raise PcsError if the last frame rendered into this state failed."""
+        rc, _ = self.status()
+        check(rc)
+
+    @property
+    def capacity(self) -> int:
+        c = ctypes.c_int64()
+        check(_lib.load().pcs_state_capacity(self.handle, ctypes.byref(c)))
+        return int(c.value)
+
     def __del__(self):
         if getattr(self, "handle", None) and self.handle.value:
             _lib.load().pcs_state_destroy(self.handle)
             self.handle = ctypes.c_void_p()
 
 
-class Renderer:
-    """One libpcsplat context on a HIP device."""
+def _torch_allocator(device: int):
+    """Allocator callbacks that take the library's workspace from PyTorch's caching allocator (on
+    the stream current when the library asks; the library enqueues on that same stream)."""
 
-    def __init__(self, device: int | None = None):
+    def alloc(nbytes, _user):
+        try:
+            with torch.cuda.device(device):
+                return torch.cuda.caching_allocator_alloc(int(nbytes), device)
+        except Exception:           # out of memory: the library reports PCS_ERR_OOM
+            return None
+
+    def release(ptr, _user):
+        if ptr:
+            torch.cuda.caching_allocator_delete(ptr)
+
+    return _lib.ALLOC_FN(alloc), _lib.FREE_FN(release)
+
+
+class Renderer:
+    """One libpcsplat context on a HIP device. With ``torch_allocator`` (the default) the library's
+    workspace comes from PyTorch's caching allocator."""
+
+    def __init__(self, device: int | None = None, torch_allocator: bool = True):
         if not torch.cuda.is_available():
             raise RuntimeError("the splatting renderer needs a HIP GPU")
         self.device = torch.cuda.current_device() if device is None else int(device)
@@ -102,6 +141,10 @@ class Renderer:
         self._finalizing = sys.is_finalizing
         with torch.cuda.device(self.device):
             check(L.pcs_context_create(self.device, ctypes.byref(self.ctx)))
+        self._alloc_cbs = None
+        if torch_allocator:
+            self._alloc_cbs = _torch_allocator(self.device)     # kept alive with the context
+            check(L.pcs_context_set_allocator(self.ctx, *self._alloc_cbs, None))
 
     def close(self) -> None:
         """Release the context's device buffers now (also done when the renderer is collected)."""
@@ -119,9 +162,11 @@ class Renderer:
 
     # -- forward --------------------------------------------------------------------------
     def render(self, g: dict, cams: list, opts: Options | None = None, state: RenderState | None = None,
-               want=("rgb", "normal", "depth", "alpha"), out: dict | None = None) -> dict:
+               want=("rgb", "normal", "depth", "alpha"), out: dict | None = None,
+               capacity: bool = False) -> dict:
         """Render every camera (all share one width and height). Returns planar float32 images
-        rgb (C,3,H,W), normal (C,3,H,W), depth (C,H,W), alpha (C,H,W)."""
+        rgb (C,3,H,W), normal (C,3,H,W), depth (C,H,W), alpha (C,H,W). ``capacity``: capacity mode
+        (no wait on the device; check ``state.status()`` afterwards)."""
         dev = torch.device("cuda", self.device)
         check_gaussians(g, dev)
         cams_c = (Camera * len(cams))(*[camera_struct(c) for c in cams])
@@ -138,6 +183,9 @@ class Renderer:
         imgs = Images(_ptr(out["rgb"]), _ptr(out.get("normal")), _ptr(out.get("depth")), _ptr(out.get("alpha")))
         gs = gaussians_struct(g)
         o = opts if opts is not None else default_options()
+        if capacity:
+            o = Options.from_buffer_copy(o)
+            o.flags |= _lib.FLAG_CAPACITY_MODE
         with torch.cuda.device(self.device):
             check(_lib.load().pcs_render_forward(self.ctx, ctypes.byref(gs), cams_c, C, ctypes.byref(o),
                                                  ctypes.byref(imgs), state.handle if state else None,
@@ -233,6 +281,10 @@ class Renderer:
             check(_lib.load().pcs_shade(self.ctx, ctypes.byref(imgs), cams_c, C, ctypes.byref(lt), ctypes.byref(bgc),
                                         _ptr(out), _stream()))
         return out
+
+    def set_wait_limit(self, rounds: int) -> None:
+        """Bound of the ordering kernels' look-back waits (0: the default); see the C header."""
+        check(_lib.load().pcs_context_set_wait_limit(self.ctx, int(rounds)))
 
     # -- timing -------------------------------------------------------------------------------
     def timing(self, enable=True, stages=None):
