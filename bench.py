@@ -27,7 +27,18 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ms/frame @1M Gaussians 1080p; Gaussians/s; learned-vs-kNN-PCA PSNR gap"
 HBM_PEAK_GBS = 8000.0
-FP32_VALU_PEAK_TFLOPS = 78.6     # 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, no packed FP32
+FP32_PEAK_TFLOPS = 157.3         # MI355X FP32 vector peak (packed FP32: 256 CUs x 4 SIMD x 32 x 2 x 2.4 GHz)
+FP32_VALU_PEAK_TFLOPS = 78.6     # the same without packed FP32 (the build disables it)
+BF16_MFMA_PEAK_TFLOPS = 2500.0   # dense BF16 matrix cores
+# Compositing work as the method defines it: 25 FLOP per evaluated (pixel, list entry) pair (the
+# quadratic form, one exp, the 7-channel blend), E pairs counted by the oracle.
+COMPOSITE_FLOP_PER_VISIT = 25
+# Backward compositing per (pixel, list entry) walked back from the last contributor: the
+# quadratic form (9 FLOP); per blended splat about 45 more (transmittance recovered with a
+# reciprocal and a product, the blend weight, the 7-channel dot products with the pixel gradient,
+# dL/dalpha, the behind-sum update, 7 weight gradients, opacity, q, conic and position partials).
+COMPOSITE_BWD_VISIT_FLOP = 9
+COMPOSITE_BWD_BLEND_FLOP = 45
 
 # Algorithmic bytes per unit (stated in the design doc):
 PROJECT_READ_B = 68      # mean 12 + quat 16 + scale 12 + opacity 4 + rgb 12 + normal 12
@@ -59,6 +70,8 @@ def parse():
     ap.add_argument("--extras-only", action="store_true",
                     help="run only the secondary workloads (64 views forward + backward, estimator) "
                          "and print their JSON; for profiling them apart from the headline frame")
+    ap.add_argument("--estimator-only", action="store_true",
+                    help="run only the sparse estimator workload (for profiling its kernels)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for scaling HBM byte counters)")
     return ap.parse_args()
@@ -74,8 +87,9 @@ def main():
     import paper_2409_16504_amd as P
     from synthetic import look_at_camera, make_surface
 
-    if args.extras_only:
-        print(json.dumps({"extras": extra_workloads(P.Renderer(0))}), flush=True)
+    if args.extras_only or args.estimator_only:
+        print(json.dumps({"extras": extra_workloads(P.Renderer(0), estimator_only=args.estimator_only)}),
+              flush=True)
         return
     t0 = time.time()
     _, xyz, rgb = make_surface(args.n, args.seed, quantize=True)
@@ -123,6 +137,8 @@ def main():
     composite_ms = R.timings()["composite"][0] / args.steps
     ms_per_step = (t2 - t1) * 1e3 / args.steps
     print(f"[bench] {args.steps} frames: {ms_per_step:.3f} ms/frame", file=sys.stderr, flush=True)
+    R.timing(False)
+    modes = frame_modes(R, g, cams, opts, args.steps)
     # per-stage breakdown from a separate run of the same frames with events around every stage
     R.timing(True)
     for _ in range(args.steps):
@@ -142,7 +158,10 @@ def main():
     if not args.no_cpu_baseline:
         cpu, visits, blends = cpu_baseline(xyz, rgb, cams)
 
-    roof = roofline(dict(per_stage, composite=composite_ms), args.n, m, bins, visits, blends)
+    lds_peak = R.lds_bandwidth()
+    print(f"[bench] measured LDS read peak {lds_peak / 1e3:.1f} TB/s", file=sys.stderr, flush=True)
+    roof = roofline(dict(per_stage, composite=composite_ms), args.n, m, bins, visits, blends, lds_peak)
+    roof_bwd = backward_roofline(R, g, cams, opts, bins, blends)
     stage_roof = stage_rooflines(per_stage, args.n, m, bins, args.width, args.height)
     extras = None if args.no_extras else extra_workloads(R)
     gap = None if args.no_extras else psnr_gap(R)
@@ -158,12 +177,13 @@ def main():
                     n_gaussians=args.n, width=args.width, height=args.height, cameras=1),
         ms_per_frame=ms_per_step, instances=m, knn_pca_ms=knn_ms,
         stage_ms={k: round(v, 5) for k, v in per_stage.items()},
-        roofline=roof, stage_roofline=stage_roof, cpu_baseline=cpu, psnr_gap_db=None if gap is None else gap["gap_db"], extras=extras,
+        frame_modes=modes, roofline=roof, roofline_backward=roof_bwd, stage_roofline=stage_roof,
+        cpu_baseline=cpu, psnr_gap_db=None if gap is None else gap["gap_db"], extras=extras,
     )
     print(json.dumps(line), flush=True)
 
 
-def extra_workloads(R):
+def extra_workloads(R, estimator_only=False):
     """Secondary measurements (not the headline value): the 64-camera 1024^2 forward + backward of
     the 800k-point surface in one launch, and the sparse estimator on that cloud."""
     import torch
@@ -176,31 +196,33 @@ def extra_workloads(R):
     est = R.knn_pca(txyz, k=16, kappa=1.0, floor=0.1)
     g = dict(mean=txyz, quat=est["quat"], scale=est["scale"], opacity=torch.full((xyz.shape[1],), 0.9, device=dev),
              rgb=trgb, normal=est["normal"])
-    cams = orbit_cameras(64, np.random.default_rng(1003), width=1024, height=1024)
-    st = P.RenderState(R)
-    opts = P.default_options()
-    out = R.render(g, cams, opts, state=st)
-    gen = torch.Generator(device=dev).manual_seed(0)
-    go = dict(rgb=torch.randn(out["rgb"].shape, device=dev, generator=gen),
-              normal=torch.randn(out["normal"].shape, device=dev, generator=gen),
-              depth=torch.randn(out["depth"].shape, device=dev, generator=gen))
-    R.render_backward(st, go)
-    torch.cuda.synchronize()
+    many = None
     reps = 3
-    R.timing(True)
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        R.render(g, cams, opts, state=st, out=out)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(reps):
+    if not estimator_only:
+        cams = orbit_cameras(64, np.random.default_rng(1003), width=1024, height=1024)
+        st = P.RenderState(R)
+        opts = P.default_options()
+        out = R.render(g, cams, opts, state=st)
+        gen = torch.Generator(device=dev).manual_seed(0)
+        go = dict(rgb=torch.randn(out["rgb"].shape, device=dev, generator=gen),
+                  normal=torch.randn(out["normal"].shape, device=dev, generator=gen),
+                  depth=torch.randn(out["depth"].shape, device=dev, generator=gen))
         R.render_backward(st, go)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    stages = {k: round(v[0] / reps, 4) for k, v in R.timings().items() if v[1] > 0}
-    many = dict(workload="800k surfel Gaussians x 64 orbit cameras at 1024x1024, one launch",
-                forward_ms=(t1 - t0) * 1e3 / reps, backward_ms=(t2 - t1) * 1e3 / reps, stage_ms=stages)
-    del st, out, go
+        torch.cuda.synchronize()
+        R.timing(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            R.render(g, cams, opts, state=st, out=out)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            R.render_backward(st, go)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        stages = {k: round(v[0] / reps, 4) for k, v in R.timings().items() if v[1] > 0}
+        many = dict(workload="800k surfel Gaussians x 64 orbit cameras at 1024x1024, one launch",
+                    forward_ms=(t1 - t0) * 1e3 / reps, backward_ms=(t2 - t1) * 1e3 / reps, stage_ms=stages)
+        del st, out, go
     # sparse estimator (BF16 MFMA) on the same cloud: voxelise + 8 convolutions + head
     E = SparseEstimator(R, seed=0)
     vox = adaptive_grid(R, txyz, trgb)
@@ -213,14 +235,105 @@ def extra_workloads(R):
     torch.cuda.synchronize()
     t4 = time.perf_counter()
     est_stages = {k: round(v[0] / reps, 4) for k, v in R.timings().items() if v[1] > 0}
-    conv_flop = 2 * 27 * sum(ci * co for ci, co in [(32, 32), (32, 32), (32, 64), (64, 64), (64, 64), (64, 64),
-                                                  (64, 32), (32, 32)]) * vox.V
+    from paper_2409_16504_amd.estimator import IN_CHANNELS, LAYERS
+    # the method's own work: 2 FLOP per multiply-add over the present (voxel, neighbour) pairs (the
+    # voxel itself included) and the used channels (6 inputs in the first layer); the kernels also
+    # multiply absent neighbours' zero rows and the first layer's padding, counted apart
+    pairs = int((vox.arrays()["nbr"] >= 0).sum().item())
+    used = sum((IN_CHANNELS if i == 0 else ci) * co for i, (ci, co) in enumerate(LAYERS))
+    conv_flop = 2 * pairs * used
+    dense_flop = 2 * 27 * vox.V * sum(ci * co for ci, co in LAYERS)
     conv_ms = est_stages.get("conv", float("nan"))
+    ok = conv_ms == conv_ms
     estimator = dict(workload=f"sparse estimator on {xyz.shape[1]} points ({vox.V} voxels, grid {vox.grid}^3, "
                               f"{vox.mean_neighbours():.1f} occupied neighbours per voxel)",
-                     ms_per_cloud=(t4 - t3) * 1e3 / reps, stage_ms=est_stages,
-                     conv_mfma_tflops=conv_flop / (conv_ms * 1e-3) / 1e12 if conv_ms == conv_ms else None)
-    return dict(many_cameras=many, estimator=estimator)
+                     ms_per_cloud=(t4 - t3) * 1e3 / reps, stage_ms=est_stages, neighbour_pairs=pairs,
+                     conv_flop=conv_flop,
+                     conv_tflops=conv_flop / (conv_ms * 1e-3) / 1e12 if ok else None,
+                     conv_frac_bf16=conv_flop / (conv_ms * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFLOPS if ok else None,
+                     conv_dense_equivalent_tflops=dense_flop / (conv_ms * 1e-3) / 1e12 if ok else None)
+    del E, vox
+    if estimator_only:
+        return dict(estimator=estimator)
+    # dynamic sequence (10 timed frames here; the full 30 run with python -m paper_2409_16504_amd.sequence)
+    from paper_2409_16504_amd import sequence
+    t5 = time.time()
+    import contextlib
+    with contextlib.redirect_stdout(sys.stderr):        # stdout carries the bench line alone
+        seq = sequence.main(["--frames", "10", "--warmup", "3", "--psnr-frames", "1"])
+    print(f"[bench] sequence in {time.time() - t5:.1f}s", file=sys.stderr, flush=True)
+    seq["workload"] = ("deforming procedural surface, 10 timed frames after 3 warm-up frames, ~1M points per "
+                       "frame, estimate + 2 views at 1440x1600; p99 over 10 frames is their maximum")
+    return dict(many_cameras=many, estimator=estimator, sequence=seq)
+
+
+def frame_modes(R, g, cams, opts, steps):
+    """The same frame in capacity mode (no host wait: frames queue back to back) and replayed from a
+    HIP graph captured in capacity mode; ms per frame by wall clock over `steps` frames."""
+    import torch
+    import paper_2409_16504_amd as P
+    st = P.RenderState(R)
+    out = R.render(g, cams, opts, state=st, capacity=True)      # sizes the capacity (waits once)
+    for _ in range(3):
+        R.render(g, cams, opts, state=st, out=out, capacity=True)
+    assert st.status() == (0, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        R.render(g, cams, opts, state=st, out=out, capacity=True)
+    torch.cuda.synchronize()
+    cap_ms = (time.perf_counter() - t0) * 1e3 / steps
+    assert st.status() == (0, 0)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        R.render(g, cams, opts, state=st, out=out, capacity=True)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        R.render(g, cams, opts, state=st, out=out, capacity=True)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - t0) * 1e3 / steps
+    assert st.status() == (0, 0)
+    print(f"[bench] capacity mode {cap_ms:.3f} ms/frame, graph replay {graph_ms:.3f} ms/frame",
+          file=sys.stderr, flush=True)
+    return dict(capacity_ms=cap_ms, graph_replay_ms=graph_ms, capacity=st.capacity,
+                note="same frame and outputs as the headline loop; capacity mode queues frames without "
+                     "a host wait, the graph replays the captured capacity-mode frame")
+
+
+def backward_roofline(R, g, cams, opts, bins, blends, reps=10):
+    """Roofline entry of the backward compositing kernel on the headline frame (upstream gradient
+    N(0,1) on rgb, normal, depth): FLOP = 9 per (pixel, list entry) up to each pixel's last
+    contributor (the sum of n_contrib) + 45 per blended splat (the oracle's blend count)."""
+    import torch
+    import paper_2409_16504_amd as P
+    st = P.RenderState(R)
+    out = R.render(g, cams, opts, state=st)
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    go = {k: torch.randn(out[k].shape, device="cuda", generator=gen) for k in ("rgb", "normal", "depth")}
+    R.render_backward(st, go)
+    torch.cuda.synchronize()
+    R.timing(True, stages=["backward_composite", "backward_project"])
+    for _ in range(reps):
+        R.render_backward(st, go)
+    t = R.timings()
+    ms = t["backward_composite"][0] / reps
+    walked = int(bins["n_contrib"].astype(np.int64).sum())
+    entry = dict(kernel="composite_backward", bound="alu", avg_ms=ms, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                 project_backward_ms=t["backward_project"][0] / reps, walked_pairs=walked)
+    if blends is not None:
+        flop = COMPOSITE_BWD_VISIT_FLOP * walked + COMPOSITE_BWD_BLEND_FLOP * blends
+        entry.update(flop=flop, achieved=flop / (ms * 1e-3) / 1e12,
+                     frac=flop / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS)
+    return entry
 
 
 def late_shading(R, out, cams, reps=20):
@@ -244,6 +357,25 @@ def late_shading(R, out, cams, reps=20):
 # this file is unchanged).
 STAGE_SOURCE = {"composite": "composite.hip", "project": "project.hip",
                 "binning": "scan_sort.hip", "sort": "scan_sort.hip", "ranges": "scan_sort.hip"}
+
+
+def measured_lds(stage="composite"):
+    """LDS bytes per launch of the stage's kernel (64 x SQ_INSTS_LDS_LOAD_BANDWIDTH +
+    64 x SQ_INSTS_LDS_STORE_BANDWIDTH) and its bank-conflict cycles from the committed rocprofv3
+    counter summary, or None when there is none or the kernel source has changed since."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"{stage}_1M_1080p_lds_counters.md")
+    src = os.path.join(ROOT, "paper_2409_16504_amd", "csrc", STAGE_SOURCE.get(stage, ""))
+    if not os.path.exists(path) or not os.path.isfile(src):
+        return None
+    text = open(path).read()
+    h = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
+    b = re.search(r"lds_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    c = re.search(r"bank_conflict_fraction:\s*([0-9.eE+-]+)", text)
+    if not h or not b or hashlib.sha256(open(src, "rb").read()).hexdigest() != h.group(1):
+        return None
+    return dict(bytes=float(b.group(1)), bank_conflict_fraction=float(c.group(1)) if c else None)
 
 
 def measured_traffic(stage):
@@ -331,7 +463,7 @@ def stage_rooflines(per_stage, n, m, bins, W, H):
     return out
 
 
-def roofline(per_stage, n, m, bins, visits, blends):
+def roofline(per_stage, n, m, bins, visits, blends, lds_peak=None):
     """Roofline entry of the frame's dominant kernel, from algorithmic work per launch. Every stage
     but compositing is a chain of short kernels (the sort alone runs about a dozen), so the longest
     single kernel is the compositing kernel; the other stages are in `stage_roofline`."""
@@ -342,13 +474,23 @@ def roofline(per_stage, n, m, bins, visits, blends):
         if visits is None:
             # the FLOP count needs the oracle's visit and blend counts, which only the CPU
             # baseline leg computes: no achieved figure without them
-            return dict(kernel=dom, bound="alu", achieved=None, peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
+            return dict(kernel=dom, bound="alu", achieved=None, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
                         frac=None, traffic=measured_traffic(dom), avg_ms=ms,
                         note="achieved needs the CPU baseline leg (run without --no-cpu-baseline)")
-        flop = COMPOSITE_VISIT_FLOP * visits + COMPOSITE_BLEND_FLOP * blends
+        flop = COMPOSITE_FLOP_PER_VISIT * visits
         ach = flop / (ms * 1e-3) / 1e12
-        return dict(kernel=dom, bound="alu", achieved=ach, peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=ach / FP32_VALU_PEAK_TFLOPS, traffic=measured_traffic(dom), avg_ms=ms)
+        # the finer count (9 FLOP per visit, 21 more per blend) against the peak without packed FP32
+        fine = COMPOSITE_VISIT_FLOP * visits + COMPOSITE_BLEND_FLOP * blends
+        fine_ach = fine / (ms * 1e-3) / 1e12
+        lds = measured_lds(dom)
+        if lds is not None:
+            gbs = lds["bytes"] / (ms * 1e-3) / 1e9
+            lds.update(gbs=gbs, peak_gbs=lds_peak, frac=gbs / lds_peak if lds_peak else None)
+        return dict(kernel=dom, bound="alu", achieved=ach, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=ach / FP32_PEAK_TFLOPS, traffic=measured_traffic(dom), avg_ms=ms,
+                    flop=flop, visits=visits, blends=blends, lds=lds,
+                    fine_model=dict(flop=fine, achieved=fine_ach, peak=FP32_VALU_PEAK_TFLOPS,
+                                    frac=fine_ach / FP32_VALU_PEAK_TFLOPS))
     if dom == "sort":
         # depth sort of the n splats (u32 keys) then tile sort of the m instances (u32 keys): per
         # pass a read and a write of key and value (the histograms are counted by the kernels that

@@ -51,7 +51,10 @@ extern "C" {
  * pcs_state_status reports PCS_ERR_CAPACITY with the count it needs; the next capacity-mode render
  * of the state is sized for it. With the same inputs and a capacity that holds, the launch sequence
  * is the same on every call and allocates nothing, so it can be captured in a HIP graph and
- * replayed (the graph replays the captured frame's sizes; check pcs_state_status after a replay). */
+ * replayed (the graph replays the captured frame's sizes; check pcs_state_status after a replay).
+ * A captured graph keeps the device addresses of the context's and the state's buffers: while it
+ * is in use, render nothing else into that state, and nothing on that context that needs more
+ * workspace (more Gaussians, cameras or pixels, or a capacity that has to grow). */
 #define PCS_FLAG_CAPACITY_MODE 2u
 
 /* Pinhole camera (Section 3.1, Eq. 3-4). x_c = T p + t with T row-major; camera axes x right,
@@ -209,6 +212,11 @@ int pcs_state_capacity(const pcs_state* state, int64_t* capacity);
  * reports PCS_ERR_HIP through pcs_state_status and pcs_state_bins, and every kernel still ends. */
 int pcs_context_set_wait_limit(pcs_context* ctx, uint32_t rounds);
 
+/* Measured LDS read bandwidth of the whole device in GB/s (a kernel of conflict-free 16-byte LDS
+ * reads on every CU, timed with HIP events; synchronises the stream): the peak that the benchmark
+ * holds the compositing kernel's LDS traffic against. */
+int pcs_measure_lds_bandwidth(pcs_context* ctx, double* gbs, void* stream);
+
 /* Parity export of a saved state (device pointers owned by the state):
  *   keys[m]:  ((cam * tiles_per_cam + ty * TX + tx) << 32) | bits(fp32 camera-space depth)
  *   vals[m]:  Gaussian index, sorted lexicographically by (key, value)
@@ -277,7 +285,7 @@ int pcs_voxels_get(const pcs_voxels* vox, const int32_t** coords, const int32_t*
  * y[v][o] = relu?(bias[o] + sum_k sum_c w[k][o][c] x[nbr_k(v)][c]), absent neighbours contribute
  * nothing. x[V][cin], y[V][cout], w[27][cout][cin] BF16; bias[cout] FP32 or NULL. Products on
  * BF16 matrix cores (MFMA) with FP32 accumulation; the output is rounded to BF16.
- * cin, cout in {32, 64} (UNSUPPORTED otherwise). */
+ * cin and cout in {32, 64, 128}, not both 128 (UNSUPPORTED otherwise). */
 int pcs_subm_conv_forward(pcs_context* ctx, const pcs_voxels* vox, const uint16_t* x, int32_t cin,
                           const uint16_t* w, const float* bias, int32_t cout, int32_t relu, uint16_t* y,
                           void* stream);
@@ -288,6 +296,59 @@ int pcs_subm_conv_forward(pcs_context* ctx, const pcs_voxels* vox, const uint16_
 int pcs_subm_conv_backward(pcs_context* ctx, const pcs_voxels* vox, const uint16_t* x, int32_t cin,
                            const uint16_t* w, int32_t cout, const uint16_t* y, const uint16_t* dy,
                            uint16_t* dx, float* dw, float* dbias, void* stream);
+
+/* ---- the paper's UNet-like estimator (Section 3.2, its network figure) ----------------------
+ * Encoder: 2x2x2 average pooling of the sparse grid, averaging only the occupied children;
+ * decoder: stride-2 transposed 2x2x2 convolution whose outputs are pruned to the encoder's
+ * occupancy at that level (so it has exactly the encoder's voxels there, for the skip connection);
+ * head: a shared MLP per point predicting offset, scale, rotation, opacity and normal.
+ *
+ * pcs_pool: the parent voxels of `child` on the grid of half the resolution (coordinates c >> 1,
+ * numbered in ascending linear key like a voxelisation; the child grid must be >= 2). `parent`
+ * then also holds the child -> parent map and the upsampling tables of pcs_up_conv_*. It must be
+ * another object than `child`; the child must stay unchanged while the parent is used.
+ * Synchronises the stream once (the parent count), like pcs_voxelize; *n_parents receives it. */
+int pcs_pool(pcs_context* ctx, const pcs_voxels* child, pcs_voxels* parent, int64_t* n_parents,
+             void* stream);
+
+/* Average pooling of features: parent_feat[p] = mean of child_feat over the occupied children of
+ * p (BF16 [V][channels], channels 32, 64 or 128; FP32 sums). The backward writes
+ * d_child[j] = d_parent[parent(j)] / (number of children of that parent) (overwritten). */
+int pcs_pool_features(pcs_context* ctx, const pcs_voxels* parent, const uint16_t* child_feat, int32_t channels,
+                      uint16_t* parent_feat, void* stream);
+int pcs_pool_features_backward(pcs_context* ctx, const pcs_voxels* parent, const uint16_t* d_parent,
+                               int32_t channels, uint16_t* d_child, void* stream);
+
+/* Transposed stride-2 convolution pruned to the encoder's occupancy: for every child voxel j of
+ * the pooled level `parent`, y[j] = relu?(bias + W[k(j)] x[parent(j)]), k(j) = 4 (cx & 1) +
+ * 2 (cy & 1) + (cz & 1) the child's position in its parent's 2x2x2 block. x[Vp][cin],
+ * y[Vc][cout], w[8][cout][cin] BF16 (cin, cout in {32, 64, 128}, not both 128), bias FP32 or NULL;
+ * BF16 MFMA with FP32 accumulation. The backward: dy masked by y > 0 if y is given; dx[Vp][cin]
+ * (BF16, overwritten) or NULL, dw[8][cout][cin] and dbias FP32 accumulated, or NULL. */
+int pcs_up_conv_forward(pcs_context* ctx, const pcs_voxels* parent, const uint16_t* x, int32_t cin,
+                        const uint16_t* w, const float* bias, int32_t cout, int32_t relu, uint16_t* y,
+                        void* stream);
+int pcs_up_conv_backward(pcs_context* ctx, const pcs_voxels* parent, const uint16_t* x, int32_t cin,
+                         const uint16_t* w, int32_t cout, const uint16_t* y, const uint16_t* dy,
+                         uint16_t* dx, float* dw, float* dbias, void* stream);
+
+/* The paper's head: per voxel raw = W2 relu(W1 f + b1) + b2 (f = feat[V][32] BF16; w1[32][32],
+ * b1[32], w2[14][32], b2[14] FP32); per point of the voxel (edge e = 2 / grid):
+ * mean = xyz + e tanh(raw[0:3]) (the offset delta stays within one voxel edge),
+ * scale = e exp(raw[3:6]), quat = normalise(raw[6:10] + (1,0,0,0)), opacity = sigmoid(raw[10]),
+ * normal = normalise(raw[11:14]), rgb = the point's colour (Section 3.1 keeps the original colour).
+ * The backward takes per-point gradients of mean, quat, scale, opacity and normal (any may be
+ * NULL = zero) and gives d_feat[V][32] (BF16, overwritten) and the weight gradients (FP32,
+ * accumulated). */
+int pcs_unet_head_forward(pcs_context* ctx, const pcs_voxels* vox, const uint16_t* feat, const float* w1,
+                          const float* b1, const float* w2, const float* b2, const float* xyz,
+                          const float* rgb, float* mean, float* quat, float* scale, float* opacity,
+                          float* out_rgb, float* normal, void* stream);
+int pcs_unet_head_backward(pcs_context* ctx, const pcs_voxels* vox, const uint16_t* feat, const float* w1,
+                           const float* b1, const float* w2, const float* b2, const float* d_mean,
+                           const float* d_quat, const float* d_scale, const float* d_opacity,
+                           const float* d_normal, uint16_t* d_feat, float* d_w1, float* d_b1, float* d_w2,
+                           float* d_b2, void* stream);
 
 /* Estimator head (Section 3.2's shared per-point head, with the outputs of configuration 4): per
  * voxel raw = wh f + bh (wh[11][32], bh[11] FP32; f = features[V][32] BF16); per point of the voxel:

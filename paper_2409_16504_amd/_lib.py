@@ -26,6 +26,8 @@ EXPORTED = ("pcs_last_error", "pcs_context_create", "pcs_context_destroy", "pcs_
             "pcs_context_timings", "pcs_state_create", "pcs_state_destroy", "pcs_options_default",
             "pcs_render_forward", "pcs_render_backward", "pcs_render_backward_noalloc", "pcs_state_bins",
             "pcs_state_status", "pcs_state_capacity", "pcs_context_set_wait_limit",
+            "pcs_measure_lds_bandwidth", "pcs_pool", "pcs_pool_features", "pcs_pool_features_backward",
+            "pcs_up_conv_forward", "pcs_up_conv_backward", "pcs_unet_head_forward", "pcs_unet_head_backward",
             "pcs_knn_pca", "pcs_voxels_create", "pcs_voxels_destroy", "pcs_voxelize", "pcs_voxels_get",
             "pcs_subm_conv_forward", "pcs_subm_conv_backward", "pcs_estimator_head_forward",
             "pcs_estimator_head_backward")
@@ -111,6 +113,14 @@ def load():
     L.pcs_state_status.argtypes = [c_vp, ctypes.POINTER(c_i64), c_vp]
     L.pcs_state_capacity.argtypes = [c_vp, ctypes.POINTER(c_i64)]
     L.pcs_context_set_wait_limit.argtypes = [c_vp, ctypes.c_uint32]
+    L.pcs_measure_lds_bandwidth.argtypes = [c_vp, ctypes.POINTER(ctypes.c_double), c_vp]
+    L.pcs_pool.argtypes = [c_vp, c_vp, c_vp, ctypes.POINTER(c_i64), c_vp]
+    L.pcs_pool_features.argtypes = [c_vp, c_vp, c_vp, c_i32, c_vp, c_vp]
+    L.pcs_pool_features_backward.argtypes = [c_vp, c_vp, c_vp, c_i32, c_vp, c_vp]
+    L.pcs_up_conv_forward.argtypes = [c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_i32, c_i32, c_vp, c_vp]
+    L.pcs_up_conv_backward.argtypes = [c_vp, c_vp, c_vp, c_i32, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]
+    L.pcs_unet_head_forward.argtypes = [c_vp] * 16
+    L.pcs_unet_head_backward.argtypes = [c_vp] * 18
     L.pcs_knn_pca.argtypes = [c_vp, c_vp, c_i64, c_i32, c_f, c_f, c_vp, c_vp, c_vp, c_vp, c_vp]
     L.pcs_shade.argtypes = [c_vp, ctypes.POINTER(Images), ctypes.POINTER(Camera), c_i32,
                             ctypes.POINTER(Light), ctypes.POINTER(c_f * 3), c_vp, c_vp]
@@ -118,6 +128,9 @@ def load():
                  "pcs_context_timings", "pcs_state_create",
                  "pcs_render_forward", "pcs_render_backward", "pcs_render_backward_noalloc",
                  "pcs_state_status", "pcs_state_capacity", "pcs_context_set_wait_limit",
+                 "pcs_measure_lds_bandwidth", "pcs_pool", "pcs_pool_features", "pcs_pool_features_backward",
+                 "pcs_up_conv_forward", "pcs_up_conv_backward", "pcs_unet_head_forward",
+                 "pcs_unet_head_backward",
                  "pcs_state_bins", "pcs_knn_pca", "pcs_voxels_create", "pcs_voxels_destroy", "pcs_voxelize", "pcs_voxels_get",
             "pcs_subm_conv_forward", "pcs_subm_conv_backward", "pcs_estimator_head_forward",
             "pcs_estimator_head_backward"):

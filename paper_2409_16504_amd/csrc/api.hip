@@ -151,7 +151,7 @@ struct pcs_context {
   int device = 0;
   DevBuf zbits, rect, keys_alt, vals_alt, scan_scratch, sort_scratch, sgrad, small;
   DevBuf dkeys, dkeys_alt, dvals, dvals_alt, dsort_scratch;   // depth sort of the splats
-  DevBuf knn_scratch, conv_tmp, wt_tmp, shade_cams, tile_hist;
+  DevBuf knn_scratch, conv_tmp, wt_tmp, shade_cams, tile_hist, probe;
   uint32_t* host_small = nullptr;   // pinned 4 KiB: readback of the small device words
   uint32_t seq = 0;                 // frame sequence number (never 0 once used)
   uint32_t wait_limit = 0;          // look-back wait bound of the ordering kernels (0: default)
@@ -199,6 +199,10 @@ struct pcs_voxels {
   int log2cap = 0;
   int grid = 1024;
   DevBuf keys, order, flag, excl, start, coords, feat, point_voxel, hkeys, hvals, nbr, centroid;
+  // a pooled (parent) voxel set: its "points" are the child voxels (point_voxel maps child ->
+  // parent), up_fwd[8][n] and up_bwd[8][V] are the transposed convolution's tables
+  DevBuf up_fwd, up_bwd, centres, mlp_raw;
+  bool pooled = false;
   bool valid = false;
 };
 
@@ -806,6 +810,34 @@ int pcs_context_set_wait_limit(pcs_context* ctx, uint32_t rounds) {
   return PCS_OK;
 }
 
+int pcs_measure_lds_bandwidth(pcs_context* ctx, double* gbs, void* stream) {
+  if (!ctx || !gbs) return fail(PCS_ERR_INVALID_ARG, "NULL argument");
+  PCS_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int cus = 0;
+  PCS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+  const int blocks = 8 * std::max(cus, 1), iters = 2000;
+  PCS_TRY(ensure(ctx, ctx->probe, (size_t)blocks * 256 * sizeof(float), "probe sink"));
+  hipEvent_t a = nullptr, b = nullptr;
+  PCS_HIP(hipEventCreate(&a));
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return fail(PCS_ERR_HIP, "hipEventCreate failed");
+  }
+  hipError_t e = launch_lds_probe(blocks, iters / 10, ctx->probe.as<float>(), s);   // warm-up
+  if (e == hipSuccess) e = hipEventRecord(a, s);
+  if (e == hipSuccess) e = launch_lds_probe(blocks, iters, ctx->probe.as<float>(), s);
+  if (e == hipSuccess) e = hipEventRecord(b, s);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  float ms = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (e != hipSuccess) return fail(PCS_ERR_HIP, std::string("LDS probe: ") + hipGetErrorString(e));
+  *gbs = (double)lds_probe_bytes(blocks, iters) / (ms * 1e-3) / 1e9;
+  return PCS_OK;
+}
+
 int pcs_knn_pca(pcs_context* ctx, const float* xyz, int64_t n, int32_t k, float kappa,
                 float floor_ratio, float* quat, float* scale, float* normal, float* nn_dist,
                 void* stream) {
@@ -875,6 +907,7 @@ void pcs_voxels_destroy(pcs_voxels* v) { delete v; }
 
 int pcs_voxelize(pcs_context* ctx, const float* xyz, const float* rgb, int64_t n, int32_t grid,
                  pcs_voxels* vox, int64_t* n_voxels, void* stream) {
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (!ctx || !vox || !n_voxels) return fail(PCS_ERR_INVALID_ARG, "NULL argument");
   if (grid < 2 || grid > 1024 || (grid & (grid - 1)) != 0)
     return fail(PCS_ERR_INVALID_ARG, "grid must be a power of two in [2, 1024]");
@@ -882,8 +915,8 @@ int pcs_voxelize(pcs_context* ctx, const float* xyz, const float* rgb, int64_t n
   if (n <= 0 || !xyz || !rgb) return fail(PCS_ERR_INVALID_ARG, "need at least one point");
   if (n >= (int64_t(1) << 30)) return fail(PCS_ERR_UNSUPPORTED, "n must be below 2^30");
   PCS_HIP(hipSetDevice(ctx->device));
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   vox->valid = false;
+  vox->pooled = false;
   PCS_TRY(ensure(ctx, vox->keys, n * sizeof(uint64_t), "voxel keys"));
   PCS_TRY(ensure(ctx, vox->order, n * sizeof(uint32_t), "voxel point order"));
   PCS_TRY(ensure(ctx, ctx->keys_alt, n * sizeof(uint64_t), "keys (alternate)"));
@@ -982,10 +1015,137 @@ int pcs_subm_conv_backward(pcs_context* ctx, const pcs_voxels* vox, const uint16
   if (dw) PCS_HIP(launch_subm_conv_dw(x, cin, g, cout, vox->nbr.as<int32_t>(), vox->V, dw, s));
   if (dx) {
     PCS_TRY(ensure(ctx, ctx->wt_tmp, (size_t)27 * cin * cout * sizeof(uint16_t), "transposed weights"));
-    PCS_HIP(launch_weight_flip_t(w, cin, cout, ctx->wt_tmp.as<uint16_t>(), s));
+    PCS_HIP(launch_weight_t(w, 27, cin, cout, true, ctx->wt_tmp.as<uint16_t>(), s));
     PCS_HIP(launch_subm_conv(g, cout, ctx->wt_tmp.as<uint16_t>(), nullptr, cin, vox->nbr.as<int32_t>(),
                              vox->V, 0, dx, s));
   }
+  return PCS_OK;
+}
+
+int pcs_pool(pcs_context* ctx, const pcs_voxels* child, pcs_voxels* parent, int64_t* n_parents,
+             void* stream) {
+  if (!ctx || !child || !parent || !n_parents) return fail(PCS_ERR_INVALID_ARG, "NULL argument");
+  if (!child->valid || child->ctx != ctx || parent->ctx != ctx)
+    return fail(PCS_ERR_INVALID_ARG, "child voxels empty or of another context");
+  if (child == parent) return fail(PCS_ERR_INVALID_ARG, "parent and child must be different objects");
+  if (child->grid < 2) return fail(PCS_ERR_INVALID_ARG, "a grid of one voxel has no coarser level");
+  PCS_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int64_t Vc = child->V;
+  // the child voxels' centres, voxelised on the grid of half the resolution, give the parents
+  PCS_TRY(ensure(ctx, parent->centres, 3 * Vc * sizeof(float), "child voxel centres"));
+  PCS_HIP(launch_voxel_centres(child->coords.as<int32_t>(), Vc, child->grid, parent->centres.as<float>(), s));
+  PCS_TRY(pcs_voxelize(ctx, parent->centres.as<float>(), parent->centres.as<float>(), Vc, child->grid / 2,
+                       parent, n_parents, stream));
+  PCS_TRY(ensure(ctx, parent->up_fwd, 8 * Vc * sizeof(int32_t), "upsampling table"));
+  PCS_TRY(ensure(ctx, parent->up_bwd, 8 * parent->V * sizeof(int32_t), "upsampling adjoint table"));
+  PCS_HIP(launch_up_tables(child->coords.as<int32_t>(), parent->point_voxel.as<int32_t>(), Vc, parent->V,
+                           parent->up_fwd.as<int32_t>(), parent->up_bwd.as<int32_t>(), s));
+  parent->pooled = true;
+  return PCS_OK;
+}
+
+int pcs_pool_features(pcs_context* ctx, const pcs_voxels* parent, const uint16_t* child_feat, int32_t channels,
+                      uint16_t* parent_feat, void* stream) {
+  if (!ctx || !parent || !child_feat || !parent_feat) return fail(PCS_ERR_INVALID_ARG, "NULL argument");
+  if (!parent->valid || !parent->pooled) return fail(PCS_ERR_INVALID_ARG, "voxels are not a pooled level");
+  if (channels != 32 && channels != 64 && channels != 128) return fail(PCS_ERR_UNSUPPORTED, "channels must be 32, 64 or 128");
+  PCS_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  StageTimer tm(ctx, ST_CONV, s);
+  PCS_HIP(launch_pool_features(parent->order.as<uint32_t>(), parent->start.as<uint32_t>(), parent->V, parent->n,
+                               child_feat, channels, parent_feat, s));
+  return PCS_OK;
+}
+
+int pcs_pool_features_backward(pcs_context* ctx, const pcs_voxels* parent, const uint16_t* d_parent,
+                               int32_t channels, uint16_t* d_child, void* stream) {
+  if (!ctx || !parent || !d_parent || !d_child) return fail(PCS_ERR_INVALID_ARG, "NULL argument");
+  if (!parent->valid || !parent->pooled) return fail(PCS_ERR_INVALID_ARG, "voxels are not a pooled level");
+  if (channels != 32 && channels != 64 && channels != 128) return fail(PCS_ERR_UNSUPPORTED, "channels must be 32, 64 or 128");
+  PCS_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  StageTimer tm(ctx, ST_CONV_BWD, s);
+  PCS_HIP(launch_pool_features_bwd(parent->point_voxel.as<int32_t>(), parent->start.as<uint32_t>(), parent->V,
+                                   parent->n, d_parent, channels, d_child, s));
+  return PCS_OK;
+}
+
+int pcs_up_conv_forward(pcs_context* ctx, const pcs_voxels* parent, const uint16_t* x, int32_t cin,
+                        const uint16_t* w, const float* bias, int32_t cout, int32_t relu, uint16_t* y,
+                        void* stream) {
+  if (!ctx || !parent || !x || !w || !y) return fail(PCS_ERR_INVALID_ARG, "NULL argument");
+  if (!parent->valid || !parent->pooled) return fail(PCS_ERR_INVALID_ARG, "voxels are not a pooled level");
+  if (!conv_shape_supported(cin, cout)) return fail(PCS_ERR_UNSUPPORTED, "unsupported channel counts");
+  PCS_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  StageTimer tm(ctx, ST_CONV, s);
+  // child j: y_j = W_{k(j)} x_{parent(j)}, the gather-GEMM over the 8-offset upsampling table
+  PCS_HIP(launch_subm_conv(x, cin, w, bias, cout, parent->up_fwd.as<int32_t>(), parent->n, relu ? 1 : 0, y, s, 8));
+  return PCS_OK;
+}
+
+int pcs_up_conv_backward(pcs_context* ctx, const pcs_voxels* parent, const uint16_t* x, int32_t cin,
+                         const uint16_t* w, int32_t cout, const uint16_t* y, const uint16_t* dy,
+                         uint16_t* dx, float* dw, float* dbias, void* stream) {
+  if (!ctx || !parent || !x || !w || !dy) return fail(PCS_ERR_INVALID_ARG, "NULL argument");
+  if (!parent->valid || !parent->pooled) return fail(PCS_ERR_INVALID_ARG, "voxels are not a pooled level");
+  if (!conv_shape_supported(cin, cout) || !conv_shape_supported(cout, cin))
+    return fail(PCS_ERR_UNSUPPORTED, "unsupported channel counts");
+  PCS_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  StageTimer tm(ctx, ST_CONV_BWD, s);
+  const int64_t Vc = parent->n;
+  const uint16_t* g = dy;
+  if (y) {
+    PCS_TRY(ensure(ctx, ctx->conv_tmp, (size_t)Vc * cout * sizeof(uint16_t), "masked output gradient"));
+    PCS_HIP(launch_relu_mask(y, dy, Vc * cout, ctx->conv_tmp.as<uint16_t>(), s));
+    g = ctx->conv_tmp.as<uint16_t>();
+  }
+  if (dbias) PCS_HIP(launch_bias_grad(g, Vc, cout, dbias, s));
+  if (dw) PCS_HIP(launch_subm_conv_dw(x, cin, g, cout, parent->up_fwd.as<int32_t>(), Vc, dw, s, 8));
+  if (dx) {
+    // parent p: dx_p = sum_k W_k^T dy_{child_k(p)} over the adjoint table
+    PCS_TRY(ensure(ctx, ctx->wt_tmp, (size_t)8 * cin * cout * sizeof(uint16_t), "transposed weights"));
+    PCS_HIP(launch_weight_t(w, 8, cin, cout, false, ctx->wt_tmp.as<uint16_t>(), s));
+    PCS_HIP(launch_subm_conv(g, cout, ctx->wt_tmp.as<uint16_t>(), nullptr, cin, parent->up_bwd.as<int32_t>(),
+                             parent->V, 0, dx, s, 8));
+  }
+  return PCS_OK;
+}
+
+int pcs_unet_head_forward(pcs_context* ctx, const pcs_voxels* vox, const uint16_t* feat, const float* w1,
+                          const float* b1, const float* w2, const float* b2, const float* xyz,
+                          const float* rgb, float* mean, float* quat, float* scale, float* opacity,
+                          float* out_rgb, float* normal, void* stream) {
+  if (!ctx || !vox || !vox->valid || !feat || !w1 || !b1 || !w2 || !b2 || !xyz || !rgb || !mean || !quat ||
+      !scale || !opacity || !out_rgb || !normal)
+    return fail(PCS_ERR_INVALID_ARG, "NULL argument or empty voxels");
+  PCS_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  StageTimer tm(ctx, ST_HEAD, s);
+  pcs_voxels* v = const_cast<pcs_voxels*>(vox);
+  PCS_TRY(ensure(ctx, v->mlp_raw, (size_t)std::max<int64_t>(vox->V, 1) * 14 * sizeof(float), "head outputs"));
+  PCS_HIP(launch_mlp_voxels(feat, vox->V, w1, b1, w2, b2, v->mlp_raw.as<float>(), s));
+  PCS_HIP(launch_mlp_points(v->mlp_raw.as<float>(), vox->point_voxel.as<int32_t>(), xyz, rgb, vox->n,
+                            2.0f / (float)vox->grid, mean, quat, scale, opacity, out_rgb, normal, s));
+  return PCS_OK;
+}
+
+int pcs_unet_head_backward(pcs_context* ctx, const pcs_voxels* vox, const uint16_t* feat, const float* w1,
+                           const float* b1, const float* w2, const float* b2, const float* d_mean,
+                           const float* d_quat, const float* d_scale, const float* d_opacity,
+                           const float* d_normal, uint16_t* d_feat, float* d_w1, float* d_b1, float* d_w2,
+                           float* d_b2, void* stream) {
+  if (!ctx || !vox || !vox->valid || !feat || !w1 || !b1 || !w2 || !b2 || !d_feat || !d_w1 || !d_b1 ||
+      !d_w2 || !d_b2)
+    return fail(PCS_ERR_INVALID_ARG, "NULL argument or empty voxels");
+  PCS_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  StageTimer tm(ctx, ST_HEAD_BWD, s);
+  PCS_HIP(launch_mlp_backward(feat, w1, b1, w2, b2, vox->order.as<uint32_t>(), vox->start.as<uint32_t>(), vox->V,
+                              vox->n, 2.0f / (float)vox->grid, d_mean, d_quat, d_scale, d_opacity, d_normal,
+                              d_feat, d_w1, d_b1, d_w2, d_b2, s));
   return PCS_OK;
 }
 

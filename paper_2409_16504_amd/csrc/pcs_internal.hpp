@@ -307,14 +307,37 @@ hipError_t launch_vox_build(const uint64_t* keys, const uint32_t* order, const u
                             uint16_t* feat, int32_t* point_voxel, uint32_t* hkeys, int32_t* hvals,
                             int log2cap, int32_t* nbr, hipStream_t s);
 bool conv_shape_supported(int cin, int cout);
+// y = relu?(bias + sum over n_off offsets of W_k x[nbr_k]): 27 offsets for the submanifold
+// convolution, 8 for the transposed stride-2 convolution (with its upsampling table).
 hipError_t launch_subm_conv(const uint16_t* x, int cin, const uint16_t* wt, const float* bias, int cout,
-                            const int32_t* nbr, int64_t V, int relu, uint16_t* y, hipStream_t s);
-hipError_t launch_weight_flip_t(const uint16_t* wt, int cin, int cout, uint16_t* out, hipStream_t s);
+                            const int32_t* nbr, int64_t V, int relu, uint16_t* y, hipStream_t s,
+                            int n_off = 27);
+// out[s][c][o] = wt[flip ? n_off - 1 - s : s][o][c]
+hipError_t launch_weight_t(const uint16_t* wt, int n_off, int cin, int cout, bool flip, uint16_t* out,
+                           hipStream_t s);
+hipError_t launch_voxel_centres(const int32_t* coords, int64_t V, int grid, float* xyz, hipStream_t s);
+hipError_t launch_up_tables(const int32_t* child_coords, const int32_t* parent_of, int64_t Vc, int64_t Vp,
+                            int32_t* fwd, int32_t* bwd, hipStream_t s);
+hipError_t launch_pool_features(const uint32_t* order, const uint32_t* start, int64_t Vp, int64_t Vc,
+                                const uint16_t* child, int C, uint16_t* parent, hipStream_t s);
+hipError_t launch_pool_features_bwd(const int32_t* parent_of, const uint32_t* start, int64_t Vp, int64_t Vc,
+                                    const uint16_t* dparent, int C, uint16_t* dchild, hipStream_t s);
+hipError_t launch_mlp_voxels(const uint16_t* feat, int64_t V, const float* w1, const float* b1,
+                             const float* w2, const float* b2, float* raw, hipStream_t s);
+hipError_t launch_mlp_points(const float* raw, const int32_t* point_voxel, const float* xyz, const float* rgb,
+                             int64_t n, float voxel, float* mean, float* quat, float* scale, float* opac,
+                             float* out_rgb, float* normal, hipStream_t s);
+hipError_t launch_mlp_backward(const uint16_t* feat, const float* w1, const float* b1, const float* w2,
+                               const float* b2, const uint32_t* order, const uint32_t* start, int64_t V,
+                               int64_t n, float voxel, const float* d_mean, const float* d_quat,
+                               const float* d_scale, const float* d_opac, const float* d_normal,
+                               uint16_t* d_feat, float* d_w1, float* d_b1, float* d_w2, float* d_b2,
+                               hipStream_t s);
 hipError_t launch_relu_mask(const uint16_t* y, const uint16_t* dy, int64_t count, uint16_t* out,
                             hipStream_t s);
 hipError_t launch_bias_grad(const uint16_t* dy, int64_t V, int cout, float* db, hipStream_t s);
 hipError_t launch_subm_conv_dw(const uint16_t* x, int cin, const uint16_t* dy, int cout,
-                               const int32_t* nbr, int64_t V, float* dw, hipStream_t s);
+                               const int32_t* nbr, int64_t V, float* dw, hipStream_t s, int n_off = 27);
 hipError_t launch_centroid(const float* xyz, int64_t n, double* sum, float* c, hipStream_t s);
 hipError_t launch_head_forward(const uint16_t* feat, const float* wh, const float* bh,
                                const int32_t* point_voxel, const float* xyz, const float* rgb,
@@ -330,5 +353,10 @@ hipError_t launch_head_backward(const uint16_t* feat, const float* wh, const flo
 hipError_t launch_shade(int W, int H, int n_cams, const DevCamera* cams, const float* rgb,
                         const float* nrm, const float* alpha, const DevLight& L, float* out,
                         hipStream_t s);
+
+// LDS read-bandwidth probe: `blocks` blocks each reading 16-byte LDS words; lds_probe_bytes gives
+// the bytes read. sink: blocks * 256 floats (never written in practice).
+hipError_t launch_lds_probe(int blocks, int iters, float* sink, hipStream_t s);
+int64_t lds_probe_bytes(int blocks, int iters);
 
 }  // namespace pcs

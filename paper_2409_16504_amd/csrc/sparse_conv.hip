@@ -157,13 +157,15 @@ __global__ void k_kernel_map(const int32_t* __restrict__ coords, int64_t V, int 
 }
 
 // ---- convolution ------------------------------------------------------------------------------
-// y[v][o] = relu?(bias[o] + sum_k sum_c W[k][o][c] x[nbr_k(v)][c]); wt is [27][COUT][CIN] BF16.
+// y[v][o] = relu?(bias[o] + sum_k sum_c W[k][o][c] x[nbr_k(v)][c]) over n_off offsets (27 for a
+// submanifold 3x3x3 convolution, 8 for a stride-2 transposed 2x2x2 one); wt is [n_off][COUT][CIN]
+// BF16 and nbr is [n_off][V].
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void k_subm_conv(const uint16_t* __restrict__ x,
                                                    const uint16_t* __restrict__ wt,
                                                    const float* __restrict__ bias,
                                                    const int32_t* __restrict__ nbr, int64_t V,
-                                                   int relu, uint16_t* __restrict__ y) {
+                                                   int relu, uint16_t* __restrict__ y, int n_off) {
   constexpr int KC = CIN / 32;       // K chunks of 32 channels
   constexpr int NB = COUT / 16;      // 16-column output blocks
   constexpr int LDW = CIN + 8;       // padded LDS row (avoids bank conflicts)
@@ -176,7 +178,7 @@ __global__ __launch_bounds__(256) void k_subm_conv(const uint16_t* __restrict__ 
   for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k = 0; k < 27; ++k) {
+  for (int k = 0; k < n_off; ++k) {
     __syncthreads();
     // stage W_k into LDS: COUT x CIN BF16, 16 bytes per thread per pass
     const uint4* wsrc = reinterpret_cast<const uint4*>(wt + (int64_t)k * COUT * CIN);
@@ -225,16 +227,87 @@ __global__ __launch_bounds__(256) void k_subm_conv(const uint16_t* __restrict__ 
     }
 }
 
-// wt_t[s][c][o] = wt[26 - s][o][c]: weights of the data-gradient convolution.
-__global__ void k_weight_flip_t(const uint16_t* __restrict__ wt, int cin, int cout,
-                                uint16_t* __restrict__ out) {
+// wt_t[s][c][o] = wt[flip ? n_off - 1 - s : s][o][c]: weights of a data-gradient convolution
+// (flipped for the symmetric submanifold map, not for the transposed convolution's own tables).
+__global__ void k_weight_t(const uint16_t* __restrict__ wt, int n_off, int cin, int cout, int flip,
+                           uint16_t* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t total = (int64_t)27 * cin * cout;
+  const int64_t total = (int64_t)n_off * cin * cout;
   if (i >= total) return;
   const int s = (int)(i / ((int64_t)cin * cout));
   const int rem = (int)(i % ((int64_t)cin * cout));
   const int c = rem / cout, o = rem % cout;
-  out[i] = wt[((int64_t)(26 - s) * cout + o) * cin + c];
+  out[i] = wt[((int64_t)(flip ? n_off - 1 - s : s) * cout + o) * cin + c];
+}
+
+// ---- pooling and upsampling tables (the encoder's 2x2x2 average pooling, the decoder's
+// transposed convolution pruned to the encoder's occupancy) --------------------------------------
+// World-space centre of every voxel of a G^3 grid over [-1,1]^3: voxelising the centres on the grid
+// of half the resolution gives the parent voxels (c >> 1, exactly: every step is exact in FP32).
+__global__ void k_voxel_centres(const int32_t* __restrict__ coords, int64_t V, int grid,
+                                float* __restrict__ xyz) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  const float h = 2.0f / (float)grid;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) xyz[a * V + v] = ((float)coords[a * V + v] + 0.5f) * h - 1.0f;
+}
+
+// Upsampling tables: child j (coordinates c) sits at offset k = 4 (cx & 1) + 2 (cy & 1) + (cz & 1)
+// of its parent p; fwd[k][j] = p at that offset and -1 at the other seven, bwd[k][p] = j (-1 where
+// the parent has no child at offset k; bwd is filled with -1 beforehand).
+__global__ void k_up_tables(const int32_t* __restrict__ child_coords, const int32_t* __restrict__ parent_of,
+                            int64_t Vc, int64_t Vp, int32_t* __restrict__ fwd, int32_t* __restrict__ bwd) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= Vc) return;
+  const int k = 4 * (child_coords[j] & 1) + 2 * (child_coords[Vc + j] & 1) + (child_coords[2 * Vc + j] & 1);
+  const int32_t p = parent_of[j];
+#pragma unroll
+  for (int o = 0; o < 8; ++o) fwd[(int64_t)o * Vc + j] = o == k ? p : -1;
+  bwd[(int64_t)k * Vp + p] = (int32_t)j;
+}
+
+// parent_feat[p] = mean of its children's features (BF16 in and out, FP32 sums); the children of p
+// are order[start[p] .. start[p + 1]) (the parent voxelisation's grouping).
+__global__ void k_pool_features(const uint32_t* __restrict__ order, const uint32_t* __restrict__ start,
+                                int64_t Vp, int64_t Vc, const uint16_t* __restrict__ child, int C,
+                                uint16_t* __restrict__ parent) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (parent, 8-channel group)
+  const int groups = C / 8;
+  if (i >= Vp * groups) return;
+  const int64_t p = i / groups;
+  const int g = (int)(i % groups);
+  const uint32_t b = start[p], e = p + 1 < Vp ? start[p + 1] : (uint32_t)Vc;
+  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (uint32_t q = b; q < e; ++q) {
+    const uint4 w = *reinterpret_cast<const uint4*>(child + (int64_t)order[q] * C + g * 8);
+    const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      acc[2 * t] += bf16_to_f32((uint16_t)(ws[t] & 0xFFFFu));
+      acc[2 * t + 1] += bf16_to_f32((uint16_t)(ws[t] >> 16));
+    }
+  }
+  const float inv = 1.0f / (float)(e - b);
+  uint4 o;
+  uint32_t* os = reinterpret_cast<uint32_t*>(&o);
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+    os[t] = f32_to_bf16(acc[2 * t] * inv) | ((uint32_t)f32_to_bf16(acc[2 * t + 1] * inv) << 16);
+  *reinterpret_cast<uint4*>(parent + p * C + g * 8) = o;
+}
+
+// Adjoint of the mean: d_child[j] = d_parent[p(j)] / (children of p(j)).
+__global__ void k_pool_features_bwd(const int32_t* __restrict__ parent_of, const uint32_t* __restrict__ start,
+                                    int64_t Vp, int64_t Vc, const uint16_t* __restrict__ dparent, int C,
+                                    uint16_t* __restrict__ dchild) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Vc * C) return;
+  const int64_t j = i / C;
+  const int c = (int)(i % C);
+  const int32_t p = parent_of[j];
+  const uint32_t b = start[p], e = p + 1 < Vp ? start[p + 1] : (uint32_t)Vc;
+  dchild[i] = f32_to_bf16(bf16_to_f32(dparent[(int64_t)p * C + c]) / (float)(e - b));
 }
 
 // dy_masked = dy * (y > 0) (ReLU derivative), BF16.
@@ -479,6 +552,249 @@ __global__ __launch_bounds__(256) void k_head_backward(
   if (threadIdx.x < kHeadOut && s_dbh[threadIdx.x] != 0.0f) unsafeAtomicAdd(&d_bh[threadIdx.x], s_dbh[threadIdx.x]);
 }
 
+// ---- the paper's head (Section 3.2): a shared two-layer MLP on the decoder's last features ------
+// raw = W2 relu(W1 f + b1) + b2 per voxel (32 -> 32 -> 14, FP32), then per point: offset
+// delta = voxel tanh(raw[0:3]) (within one voxel edge), scale = voxel exp(raw[3:6]),
+// q = normalise(raw[6:10] + (1,0,0,0)), opacity = sigmoid(raw[10]), normal = normalise(raw[11:14]).
+constexpr int kMlpIn = 32, kMlpHidden = 32, kMlpOut = 14;
+
+__device__ __forceinline__ void load_feat32(const uint16_t* __restrict__ f, float (&fv)[kMlpIn]) {
+  const uint4* src = reinterpret_cast<const uint4*>(f);
+#pragma unroll
+  for (int q = 0; q < kMlpIn / 8; ++q) {
+    const uint4 w = src[q];
+    const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      fv[8 * q + 2 * e] = bf16_to_f32((uint16_t)(ws[e] & 0xFFFF));
+      fv[8 * q + 2 * e + 1] = bf16_to_f32((uint16_t)(ws[e] >> 16));
+    }
+  }
+}
+
+__device__ __forceinline__ void mlp_forward(const float (&fv)[kMlpIn], const float* s_w1, const float* s_b1,
+                                            const float* s_w2, const float* s_b2, float (&h)[kMlpHidden],
+                                            float (&raw)[kMlpOut]) {
+#pragma unroll
+  for (int j = 0; j < kMlpHidden; ++j) {
+    float a = s_b1[j];
+#pragma unroll
+    for (int c = 0; c < kMlpIn; ++c) a = fmaf(s_w1[j * kMlpIn + c], fv[c], a);
+    h[j] = fmaxf(a, 0.0f);
+  }
+#pragma unroll
+  for (int o = 0; o < kMlpOut; ++o) {
+    float a = s_b2[o];
+#pragma unroll
+    for (int j = 0; j < kMlpHidden; ++j) a = fmaf(s_w2[o * kMlpHidden + j], h[j], a);
+    raw[o] = a;
+  }
+}
+
+// One thread per voxel: raw[V][14] (FP32).
+__global__ __launch_bounds__(256) void k_mlp_voxels(const uint16_t* __restrict__ feat, int64_t V,
+                                                    const float* __restrict__ w1, const float* __restrict__ b1,
+                                                    const float* __restrict__ w2, const float* __restrict__ b2,
+                                                    float* __restrict__ raw) {
+  __shared__ float s_w1[kMlpHidden * kMlpIn], s_b1[kMlpHidden], s_w2[kMlpOut * kMlpHidden], s_b2[kMlpOut];
+  for (int i = threadIdx.x; i < kMlpHidden * kMlpIn; i += blockDim.x) s_w1[i] = w1[i];
+  for (int i = threadIdx.x; i < kMlpOut * kMlpHidden; i += blockDim.x) s_w2[i] = w2[i];
+  if (threadIdx.x < kMlpHidden) s_b1[threadIdx.x] = b1[threadIdx.x];
+  if (threadIdx.x < kMlpOut) s_b2[threadIdx.x] = b2[threadIdx.x];
+  __syncthreads();
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  float fv[kMlpIn], h[kMlpHidden], r[kMlpOut];
+  load_feat32(feat + v * kMlpIn, fv);
+  mlp_forward(fv, s_w1, s_b1, s_w2, s_b2, h, r);
+#pragma unroll
+  for (int o = 0; o < kMlpOut; ++o) raw[v * kMlpOut + o] = r[o];
+}
+
+struct MlpAct {
+  float delta[3], th[3], scale[3], q[4], qn, opacity, n[3], nn;
+};
+
+__device__ __forceinline__ MlpAct mlp_activate(const float* r, float voxel) {
+  MlpAct a;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    a.th[k] = tanhf(r[k]);
+    a.delta[k] = voxel * a.th[k];
+    a.scale[k] = voxel * __expf(r[3 + k]);
+  }
+  const float q0 = r[6] + 1.0f, q1 = r[7], q2 = r[8], q3 = r[9];
+  a.qn = sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+  const float iq = a.qn > 0.0f ? 1.0f / a.qn : 0.0f;
+  a.q[0] = a.qn > 0.0f ? q0 * iq : 1.0f;
+  a.q[1] = q1 * iq; a.q[2] = q2 * iq; a.q[3] = q3 * iq;
+  a.opacity = 1.0f / (1.0f + __expf(-r[10]));
+  a.nn = sqrtf(r[11] * r[11] + r[12] * r[12] + r[13] * r[13]);
+  const float in = a.nn > 0.0f ? 1.0f / a.nn : 0.0f;
+  a.n[0] = r[11] * in; a.n[1] = r[12] * in; a.n[2] = r[13] * in;
+  return a;
+}
+
+// One thread per point: its voxel's activated outputs; mean = point + offset, colour = the point's.
+__global__ __launch_bounds__(256) void k_mlp_points(const float* __restrict__ raw, const int32_t* __restrict__ point_voxel,
+                                                    const float* __restrict__ xyz, const float* __restrict__ rgb,
+                                                    int64_t n, float voxel, float* __restrict__ mean,
+                                                    float* __restrict__ quat, float* __restrict__ scale,
+                                                    float* __restrict__ opac, float* __restrict__ out_rgb,
+                                                    float* __restrict__ normal) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t v = point_voxel[i];
+  float r[kMlpOut];
+#pragma unroll
+  for (int o = 0; o < kMlpOut; ++o) r[o] = raw[(int64_t)v * kMlpOut + o];
+  const MlpAct a = mlp_activate(r, voxel);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    mean[k * n + i] = xyz[k * n + i] + a.delta[k];
+    scale[k * n + i] = a.scale[k];
+    out_rgb[k * n + i] = rgb[k * n + i];
+    normal[k * n + i] = a.n[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) quat[k * n + i] = a.q[k];
+  opac[i] = a.opacity;
+}
+
+// Per voxel: the per-point gradients of (mean, quat, scale, opacity, normal) summed over its points
+// (contiguous in voxel order), through the activations to raw, then through the MLP (recomputed)
+// to the features. A block of kMlpBwdThreads voxels keeps each voxel's input, hidden activations
+// and the two layers' output gradients in LDS; the weight gradients are then the block's sums of
+// outer products, one weight element per thread at a time, added once per block.
+constexpr int kMlpBwdThreads = 128;
+constexpr int kMlpRow = 33;                      // padded LDS rows
+__global__ __launch_bounds__(kMlpBwdThreads) void k_mlp_backward(
+    const uint16_t* __restrict__ feat, const float* __restrict__ w1, const float* __restrict__ b1,
+    const float* __restrict__ w2, const float* __restrict__ b2, const uint32_t* __restrict__ order,
+    const uint32_t* __restrict__ start, int64_t V, int64_t n, float voxel, const float* __restrict__ d_mean,
+    const float* __restrict__ d_quat, const float* __restrict__ d_scale, const float* __restrict__ d_opac,
+    const float* __restrict__ d_normal, uint16_t* __restrict__ d_feat, float* __restrict__ d_w1,
+    float* __restrict__ d_b1, float* __restrict__ d_w2, float* __restrict__ d_b2) {
+  __shared__ float s_w1[kMlpHidden * kMlpIn], s_b1[kMlpHidden], s_w2[kMlpOut * kMlpHidden], s_b2[kMlpOut];
+  __shared__ float s_f[kMlpBwdThreads * kMlpRow], s_h[kMlpBwdThreads * kMlpRow];
+  __shared__ float s_gh[kMlpBwdThreads * kMlpRow], s_g[kMlpBwdThreads * 15];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kMlpHidden * kMlpIn; i += kMlpBwdThreads) s_w1[i] = w1[i];
+  for (int i = tid; i < kMlpOut * kMlpHidden; i += kMlpBwdThreads) s_w2[i] = w2[i];
+  if (tid < kMlpHidden) s_b1[tid] = b1[tid];
+  if (tid < kMlpOut) s_b2[tid] = b2[tid];
+  __syncthreads();
+  const int64_t v = (int64_t)blockIdx.x * kMlpBwdThreads + tid;
+  float* F = s_f + tid * kMlpRow;
+  float* Hh = s_h + tid * kMlpRow;
+  float* GH = s_gh + tid * kMlpRow;
+  float* G = s_g + tid * 15;
+  if (v < V) {
+    float fv[kMlpIn];
+    load_feat32(feat + v * kMlpIn, fv);
+    float r[kMlpOut];
+#pragma unroll
+    for (int o = 0; o < kMlpOut; ++o) r[o] = s_b2[o];
+#pragma unroll 4
+    for (int j = 0; j < kMlpHidden; ++j) {
+      float a = s_b1[j];
+#pragma unroll
+      for (int c = 0; c < kMlpIn; ++c) a = fmaf(s_w1[j * kMlpIn + c], fv[c], a);
+      a = fmaxf(a, 0.0f);
+      Hh[j] = a;
+#pragma unroll
+      for (int o = 0; o < kMlpOut; ++o) r[o] = fmaf(s_w2[o * kMlpHidden + j], a, r[o]);
+    }
+#pragma unroll
+    for (int c = 0; c < kMlpIn; ++c) F[c] = fv[c];
+    const MlpAct a = mlp_activate(r, voxel);
+    float gm[3] = {0.f, 0.f, 0.f}, gs[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f}, go = 0.f;
+    float gn[3] = {0.f, 0.f, 0.f};
+    const uint32_t b = start[v], e = v + 1 < V ? start[v + 1] : (uint32_t)n;
+    for (uint32_t j = b; j < e; ++j) {
+      const uint32_t i = order[j];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        if (d_mean) gm[k] += d_mean[k * n + i];
+        if (d_scale) gs[k] += d_scale[k * n + i];
+        if (d_normal) gn[k] += d_normal[k * n + i];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (d_quat) gq[k] += d_quat[k * n + i];
+      if (d_opac) go += d_opac[i];
+    }
+    float g[kMlpOut];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      g[k] = gm[k] * voxel * (1.0f - a.th[k] * a.th[k]);
+      g[3 + k] = gs[k] * a.scale[k];
+    }
+    const float dq = a.q[0] * gq[0] + a.q[1] * gq[1] + a.q[2] * gq[2] + a.q[3] * gq[3];
+    const float iq = a.qn > 0.0f ? 1.0f / a.qn : 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) g[6 + k] = (gq[k] - a.q[k] * dq) * iq;
+    g[10] = go * a.opacity * (1.0f - a.opacity);
+    const float dn = a.n[0] * gn[0] + a.n[1] * gn[1] + a.n[2] * gn[2];
+    const float in = a.nn > 0.0f ? 1.0f / a.nn : 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) g[11 + k] = (gn[k] - a.n[k] * dn) * in;
+#pragma unroll
+    for (int o = 0; o < kMlpOut; ++o) G[o] = g[o];
+    // through the second layer and the ReLU, then the first layer to the features
+    float df[kMlpIn];
+#pragma unroll
+    for (int c = 0; c < kMlpIn; ++c) df[c] = 0.0f;
+#pragma unroll 4
+    for (int j = 0; j < kMlpHidden; ++j) {
+      float t = 0.f;
+#pragma unroll
+      for (int o = 0; o < kMlpOut; ++o) t = fmaf(s_w2[o * kMlpHidden + j], g[o], t);
+      t = Hh[j] > 0.0f ? t : 0.0f;
+      GH[j] = t;
+#pragma unroll
+      for (int c = 0; c < kMlpIn; ++c) df[c] = fmaf(s_w1[j * kMlpIn + c], t, df[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < kMlpIn; c += 8) {
+      uint4 w;
+      w.x = f32_to_bf16(df[c]) | ((uint32_t)f32_to_bf16(df[c + 1]) << 16);
+      w.y = f32_to_bf16(df[c + 2]) | ((uint32_t)f32_to_bf16(df[c + 3]) << 16);
+      w.z = f32_to_bf16(df[c + 4]) | ((uint32_t)f32_to_bf16(df[c + 5]) << 16);
+      w.w = f32_to_bf16(df[c + 6]) | ((uint32_t)f32_to_bf16(df[c + 7]) << 16);
+      *reinterpret_cast<uint4*>(d_feat + v * kMlpIn + c) = w;
+    }
+  } else {
+    // rows of voxels past the end add nothing to the sums
+    for (int c = 0; c < kMlpRow; ++c) { F[c] = 0.f; Hh[c] = 0.f; GH[c] = 0.f; }
+    for (int o = 0; o < 15; ++o) G[o] = 0.f;
+  }
+  __syncthreads();
+  // weight gradients: dW2[o][j] = sum_v G[v][o] H[v][j], dW1[j][c] = sum_v GH[v][j] F[v][c], and the
+  // biases, each element summed over the block's voxels by one thread
+  constexpr int kW2 = kMlpOut * kMlpHidden, kW1 = kMlpHidden * kMlpIn;
+  for (int el = tid; el < kW2 + kW1 + kMlpOut + kMlpHidden; el += kMlpBwdThreads) {
+    float acc = 0.f;
+    if (el < kW2) {
+      const int o = el / kMlpHidden, j = el % kMlpHidden;
+      for (int u = 0; u < kMlpBwdThreads; ++u) acc = fmaf(s_g[u * 15 + o], s_h[u * kMlpRow + j], acc);
+      if (acc != 0.0f) unsafeAtomicAdd(&d_w2[el], acc);
+    } else if (el < kW2 + kW1) {
+      const int e2 = el - kW2, j = e2 / kMlpIn, c = e2 % kMlpIn;
+      for (int u = 0; u < kMlpBwdThreads; ++u) acc = fmaf(s_gh[u * kMlpRow + j], s_f[u * kMlpRow + c], acc);
+      if (acc != 0.0f) unsafeAtomicAdd(&d_w1[e2], acc);
+    } else if (el < kW2 + kW1 + kMlpOut) {
+      const int o = el - kW2 - kW1;
+      for (int u = 0; u < kMlpBwdThreads; ++u) acc += s_g[u * 15 + o];
+      if (acc != 0.0f) unsafeAtomicAdd(&d_b2[o], acc);
+    } else {
+      const int j = el - kW2 - kW1 - kMlpOut;
+      for (int u = 0; u < kMlpBwdThreads; ++u) acc += s_gh[u * kMlpRow + j];
+      if (acc != 0.0f) unsafeAtomicAdd(&d_b1[j], acc);
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_centroid(const float* __restrict__ xyz, int64_t n,
                                                   double* __restrict__ sum) {
   __shared__ double s[3][256];
@@ -530,25 +846,64 @@ hipError_t launch_vox_build(const uint64_t* keys, const uint32_t* order, const u
   return hipGetLastError();
 }
 
+// 128 channels enter the decoder's convolutions (skip connections concatenated) and leave their
+// data gradients; 128 -> 128 is not needed
 bool conv_shape_supported(int cin, int cout) {
-  return (cin == 32 || cin == 64) && (cout == 32 || cout == 64);
+  return (cin == 32 || cin == 64 || cin == 128) && (cout == 32 || cout == 64 || cout == 128) &&
+         !(cin == 128 && cout == 128);
 }
 
 hipError_t launch_subm_conv(const uint16_t* x, int cin, const uint16_t* wt, const float* bias, int cout,
-                            const int32_t* nbr, int64_t V, int relu, uint16_t* y, hipStream_t s) {
+                            const int32_t* nbr, int64_t V, int relu, uint16_t* y, hipStream_t s, int n_off) {
   if (V == 0) return hipSuccess;
   const dim3 grid(blocks_for(V, 256)), block(256);
-  if (cin == 32 && cout == 32) hipLaunchKernelGGL((k_subm_conv<32, 32>), grid, block, 0, s, x, wt, bias, nbr, V, relu, y);
-  else if (cin == 32 && cout == 64) hipLaunchKernelGGL((k_subm_conv<32, 64>), grid, block, 0, s, x, wt, bias, nbr, V, relu, y);
-  else if (cin == 64 && cout == 32) hipLaunchKernelGGL((k_subm_conv<64, 32>), grid, block, 0, s, x, wt, bias, nbr, V, relu, y);
-  else if (cin == 64 && cout == 64) hipLaunchKernelGGL((k_subm_conv<64, 64>), grid, block, 0, s, x, wt, bias, nbr, V, relu, y);
-  else return hipErrorInvalidValue;
+#define PCS_CONV(CI, CO)                                                                             \
+  if (cin == CI && cout == CO) {                                                                     \
+    hipLaunchKernelGGL((k_subm_conv<CI, CO>), grid, block, 0, s, x, wt, bias, nbr, V, relu, y, n_off); \
+    return hipGetLastError();                                                                        \
+  }
+  PCS_CONV(32, 32) PCS_CONV(32, 64) PCS_CONV(64, 32) PCS_CONV(64, 64) PCS_CONV(128, 32) PCS_CONV(128, 64)
+  PCS_CONV(32, 128) PCS_CONV(64, 128)
+#undef PCS_CONV
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_weight_t(const uint16_t* wt, int n_off, int cin, int cout, bool flip, uint16_t* out,
+                           hipStream_t s) {
+  const int64_t total = (int64_t)n_off * cin * cout;
+  hipLaunchKernelGGL(k_weight_t, dim3(blocks_for(total, 256)), dim3(256), 0, s, wt, n_off, cin, cout,
+                     flip ? 1 : 0, out);
   return hipGetLastError();
 }
 
-hipError_t launch_weight_flip_t(const uint16_t* wt, int cin, int cout, uint16_t* out, hipStream_t s) {
-  const int64_t total = (int64_t)27 * cin * cout;
-  hipLaunchKernelGGL(k_weight_flip_t, dim3(blocks_for(total, 256)), dim3(256), 0, s, wt, cin, cout, out);
+hipError_t launch_voxel_centres(const int32_t* coords, int64_t V, int grid, float* xyz, hipStream_t s) {
+  if (V == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_voxel_centres, dim3(blocks_for(V, 256)), dim3(256), 0, s, coords, V, grid, xyz);
+  return hipGetLastError();
+}
+
+hipError_t launch_up_tables(const int32_t* child_coords, const int32_t* parent_of, int64_t Vc, int64_t Vp,
+                            int32_t* fwd, int32_t* bwd, hipStream_t s) {
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(bwd), 0xFFFFFFFFu, 8 * Vp, s);
+  if (e != hipSuccess || Vc == 0) return e;
+  hipLaunchKernelGGL(k_up_tables, dim3(blocks_for(Vc, 256)), dim3(256), 0, s, child_coords, parent_of, Vc, Vp,
+                     fwd, bwd);
+  return hipGetLastError();
+}
+
+hipError_t launch_pool_features(const uint32_t* order, const uint32_t* start, int64_t Vp, int64_t Vc,
+                                const uint16_t* child, int C, uint16_t* parent, hipStream_t s) {
+  if (Vp == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pool_features, dim3(blocks_for(Vp * (C / 8), 256)), dim3(256), 0, s, order, start, Vp,
+                     Vc, child, C, parent);
+  return hipGetLastError();
+}
+
+hipError_t launch_pool_features_bwd(const int32_t* parent_of, const uint32_t* start, int64_t Vp, int64_t Vc,
+                                    const uint16_t* dparent, int C, uint16_t* dchild, hipStream_t s) {
+  if (Vc == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pool_features_bwd, dim3(blocks_for(Vc * C, 256)), dim3(256), 0, s, parent_of, start, Vp,
+                     Vc, dparent, C, dchild);
   return hipGetLastError();
 }
 
@@ -566,17 +921,50 @@ hipError_t launch_bias_grad(const uint16_t* dy, int64_t V, int cout, float* db, 
 }
 
 hipError_t launch_subm_conv_dw(const uint16_t* x, int cin, const uint16_t* dy, int cout,
-                               const int32_t* nbr, int64_t V, float* dw, hipStream_t s) {
+                               const int32_t* nbr, int64_t V, float* dw, hipStream_t s, int n_off) {
   if (V == 0) return hipSuccess;
   // ~32 voxel ranges per offset: enough blocks to fill the GPU, few atomics per weight
   const int64_t ranges = std::min<int64_t>(32, (V + 63) / 64);
   const int64_t chunk = ((V + ranges - 1) / ranges + 63) / 64 * 64;
-  const dim3 grid((unsigned)((V + chunk - 1) / chunk), 27), block(256);
-  if (cin == 32 && cout == 32) hipLaunchKernelGGL((k_subm_conv_dw<32, 32>), grid, block, 0, s, x, dy, nbr, V, chunk, dw);
-  else if (cin == 32 && cout == 64) hipLaunchKernelGGL((k_subm_conv_dw<32, 64>), grid, block, 0, s, x, dy, nbr, V, chunk, dw);
-  else if (cin == 64 && cout == 32) hipLaunchKernelGGL((k_subm_conv_dw<64, 32>), grid, block, 0, s, x, dy, nbr, V, chunk, dw);
-  else if (cin == 64 && cout == 64) hipLaunchKernelGGL((k_subm_conv_dw<64, 64>), grid, block, 0, s, x, dy, nbr, V, chunk, dw);
-  else return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((V + chunk - 1) / chunk), (unsigned)n_off), block(256);
+#define PCS_CONV_DW(CI, CO)                                                                    \
+  if (cin == CI && cout == CO) {                                                               \
+    hipLaunchKernelGGL((k_subm_conv_dw<CI, CO>), grid, block, 0, s, x, dy, nbr, V, chunk, dw); \
+    return hipGetLastError();                                                                  \
+  }
+  PCS_CONV_DW(32, 32) PCS_CONV_DW(32, 64) PCS_CONV_DW(64, 32) PCS_CONV_DW(64, 64) PCS_CONV_DW(128, 32)
+  PCS_CONV_DW(128, 64) PCS_CONV_DW(32, 128) PCS_CONV_DW(64, 128)
+#undef PCS_CONV_DW
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_mlp_voxels(const uint16_t* feat, int64_t V, const float* w1, const float* b1,
+                             const float* w2, const float* b2, float* raw, hipStream_t s) {
+  if (V == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mlp_voxels, dim3(blocks_for(V, 256)), dim3(256), 0, s, feat, V, w1, b1, w2, b2, raw);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_points(const float* raw, const int32_t* point_voxel, const float* xyz, const float* rgb,
+                             int64_t n, float voxel, float* mean, float* quat, float* scale, float* opac,
+                             float* out_rgb, float* normal, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mlp_points, dim3(blocks_for(n, 256)), dim3(256), 0, s, raw, point_voxel, xyz, rgb, n,
+                     voxel, mean, quat, scale, opac, out_rgb, normal);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_backward(const uint16_t* feat, const float* w1, const float* b1, const float* w2,
+                               const float* b2, const uint32_t* order, const uint32_t* start, int64_t V,
+                               int64_t n, float voxel, const float* d_mean, const float* d_quat,
+                               const float* d_scale, const float* d_opac, const float* d_normal,
+                               uint16_t* d_feat, float* d_w1, float* d_b1, float* d_w2, float* d_b2,
+                               hipStream_t s) {
+  if (V == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mlp_backward, dim3(blocks_for(V, kMlpBwdThreads)), dim3(kMlpBwdThreads), 0, s, feat, w1,
+                     b1, w2, b2, order,
+                     start, V, n, voxel, d_mean, d_quat, d_scale, d_opac, d_normal, d_feat, d_w1, d_b1, d_w2,
+                     d_b2);
   return hipGetLastError();
 }
 

@@ -248,3 +248,224 @@ def train_step(est: SparseEstimator, opt: Adam, clouds: list, view_fn, w_l1=0.8,
         loss_sum += float(loss.item())
     opt.step(total)
     return loss_sum / len(clouds)
+
+
+# ---- the paper's UNet-like estimator (Section 3.2) --------------------------------------------
+# (name, kind, cin, cout): encoder at levels 0-3, decoder back to level 0 with skip connections
+# (concatenated channels); every convolution is followed by ReLU. Head: MLP 32 -> 32 -> 14.
+UNET_LAYOUT = [
+    ("e0a", "subm", 32, 32), ("e0b", "subm", 32, 32),
+    ("e1", "subm", 32, 64), ("e2", "subm", 64, 64), ("e3", "subm", 64, 64),
+    ("u3", "up", 64, 64), ("d2", "subm", 128, 64),
+    ("u2", "up", 64, 64), ("d1", "subm", 128, 64),
+    ("u1", "up", 64, 32), ("d0", "subm", 64, 32),
+]
+UNET_HEAD_HIDDEN, UNET_HEAD_OUT = 32, 14
+
+
+def pool(R: Renderer, child: Voxels) -> Voxels:
+    """Parent voxels of ``child`` on the grid of half the resolution (Section 3.2's pooling),
+    holding the child -> parent map and the upsampling tables."""
+    parent = Voxels(R)
+    Vp = ctypes.c_int64()
+    check(_lib.load().pcs_pool(R.ctx, child.handle, parent.handle, ctypes.byref(Vp), _s()))
+    parent.V, parent.n, parent.grid = int(Vp.value), child.V, child.grid // 2
+    parent.child = child                      # the parent's tables refer to the child's numbering
+    return parent
+
+
+def pool_features(R: Renderer, parent: Voxels, x: torch.Tensor) -> torch.Tensor:
+    C = x.shape[1]
+    y = torch.empty((parent.V, C), device=x.device, dtype=torch.bfloat16)
+    check(_lib.load().pcs_pool_features(R.ctx, parent.handle, _p(x), C, _p(y), _s()))
+    return y
+
+
+def pool_features_backward(R: Renderer, parent: Voxels, dy: torch.Tensor) -> torch.Tensor:
+    C = dy.shape[1]
+    dx = torch.empty((parent.n, C), device=dy.device, dtype=torch.bfloat16)
+    check(_lib.load().pcs_pool_features_backward(R.ctx, parent.handle, _p(dy.contiguous()), C, _p(dx), _s()))
+    return dx
+
+
+def up_conv_forward(R: Renderer, parent: Voxels, x, w_bf16, bias, relu=True) -> torch.Tensor:
+    cin, cout = x.shape[1], w_bf16.shape[1]
+    y = torch.empty((parent.n, cout), device=x.device, dtype=torch.bfloat16)
+    check(_lib.load().pcs_up_conv_forward(R.ctx, parent.handle, _p(x), cin, _p(w_bf16), _p(bias), cout,
+                                          int(relu), _p(y), _s()))
+    return y
+
+
+def up_conv_backward(R: Renderer, parent: Voxels, x, w_bf16, y, dy, dw=None, db=None) -> torch.Tensor:
+    cin, cout = x.shape[1], w_bf16.shape[1]
+    dx = torch.empty((parent.V, cin), device=x.device, dtype=torch.bfloat16)
+    check(_lib.load().pcs_up_conv_backward(R.ctx, parent.handle, _p(x), cin, _p(w_bf16), cout, _p(y),
+                                           _p(dy.contiguous()), _p(dx), _p(dw), _p(db), _s()))
+    return dx
+
+
+def unet_head_forward(R: Renderer, vox: Voxels, f, w1, b1, w2, b2, xyz, rgb) -> dict:
+    n = xyz.shape[1]
+    dev = xyz.device
+    g = dict(mean=torch.empty((3, n), device=dev), quat=torch.empty((4, n), device=dev),
+             scale=torch.empty((3, n), device=dev), opacity=torch.empty((n,), device=dev),
+             rgb=torch.empty((3, n), device=dev), normal=torch.empty((3, n), device=dev))
+    check(_lib.load().pcs_unet_head_forward(R.ctx, vox.handle, _p(f), _p(w1), _p(b1), _p(w2), _p(b2), _p(xyz),
+                                            _p(rgb), _p(g["mean"]), _p(g["quat"]), _p(g["scale"]),
+                                            _p(g["opacity"]), _p(g["rgb"]), _p(g["normal"]), _s()))
+    return g
+
+
+def unet_head_backward(R: Renderer, vox: Voxels, f, w1, b1, w2, b2, grads: dict, dws: list) -> torch.Tensor:
+    df = torch.empty((vox.V, 32), device=f.device, dtype=torch.bfloat16)
+    c = {k: (grads[k].contiguous() if grads.get(k) is not None else None)
+         for k in ("mean", "quat", "scale", "opacity", "normal")}
+    check(_lib.load().pcs_unet_head_backward(R.ctx, vox.handle, _p(f), _p(w1), _p(b1), _p(w2), _p(b2),
+                                             _p(c["mean"]), _p(c["quat"]), _p(c["scale"]), _p(c["opacity"]),
+                                             _p(c["normal"]), _p(df), *(_p(t) for t in dws), _s()))
+    return df
+
+
+class UNetEstimator:
+    """The paper's estimator (Section 3.2): a sparse UNet over three 2x2x2 poolings with pruned
+    transposed convolutions and skip connections, and a shared MLP head predicting per point the
+    offset, scale, rotation, opacity and normal. FP32 master weights, BF16 copies for the MFMA
+    kernels; the head runs in FP32."""
+
+    def __init__(self, renderer: Renderer, seed: int = 0, opacity_init: float = 0.9):
+        self.R = renderer
+        dev = torch.device("cuda", renderer.device)
+        gen = torch.Generator(device="cpu").manual_seed(seed)
+        self.w, self.b = {}, {}
+        for name, kind, cin, cout in UNET_LAYOUT:
+            k = 27 if kind == "subm" else 8
+            fan_in = k * (IN_CHANNELS if name == "e0a" else cin)
+            w = torch.randn((k, cout, cin), generator=gen) * math.sqrt(2.0 / fan_in)
+            if name == "e0a":
+                w[:, :, IN_CHANNELS:] = 0.0
+            self.w[name] = w.to(dev)
+            self.b[name] = torch.zeros(cout, device=dev)
+        self.w1 = (torch.randn((UNET_HEAD_HIDDEN, 32), generator=gen) * math.sqrt(2.0 / 32)).to(dev)
+        self.b1 = torch.zeros(UNET_HEAD_HIDDEN, device=dev)
+        w2 = torch.randn((UNET_HEAD_OUT, UNET_HEAD_HIDDEN), generator=gen) * 1e-3
+        w2[11:14] = torch.randn((3, UNET_HEAD_HIDDEN), generator=gen) * 0.1    # varied initial normals
+        self.w2 = w2.to(dev)
+        self.b2 = torch.zeros(UNET_HEAD_OUT, device=dev)
+        self.b2[3:6] = math.log(2.3)            # initial scale ~2.3 voxel edges
+        self.b2[10] = math.log(opacity_init / (1.0 - opacity_init))
+        names = [n for n, *_ in UNET_LAYOUT]
+        self.params = [self.w[n] for n in names] + [self.b[n] for n in names] + [self.w1, self.b1, self.w2, self.b2]
+
+    @staticmethod
+    def levels(R: Renderer, vox: Voxels) -> list:
+        """Voxel sets of levels 0..3 of a voxelised cloud (level 0 is ``vox``)."""
+        lv = [vox]
+        for _ in range(3):
+            lv.append(pool(R, lv[-1]))
+        return lv
+
+    def forward(self, lv: list, save=False):
+        R = self.R
+        wb = {n: w.to(torch.bfloat16).contiguous() for n, w in self.w.items()}
+        x0 = lv[0].arrays()["features"]
+        a = {}
+
+        def conv(name, x, level):
+            a[name + ":in"] = x
+            a[name] = conv_forward(R, lv[level], x, wb[name], self.b[name], relu=True)
+            return a[name]
+
+        def up(name, x, level):          # from level + 1 to the children at `level`
+            a[name + ":in"] = x
+            a[name] = up_conv_forward(R, lv[level + 1], x, wb[name], self.b[name], relu=True)
+            return a[name]
+
+        s0 = conv("e0b", conv("e0a", x0, 0), 0)
+        s1 = conv("e1", pool_features(R, lv[1], s0), 1)
+        s2 = conv("e2", pool_features(R, lv[2], s1), 2)
+        b3 = conv("e3", pool_features(R, lv[3], s2), 3)
+        d2 = conv("d2", torch.cat([up("u3", b3, 2), s2], dim=1), 2)
+        d1 = conv("d1", torch.cat([up("u2", d2, 1), s1], dim=1), 1)
+        d0 = conv("d0", torch.cat([up("u1", d1, 0), s0], dim=1), 0)
+        g = unet_head_forward(R, lv[0], d0, self.w1, self.b1, self.w2, self.b2, lv[0].xyz, lv[0].rgb)
+        if save:
+            return g, dict(acts=a, wb=wb)
+        return g
+
+    def backward(self, lv: list, saved: dict, grads: dict):
+        """Weight gradients (FP32, order of ``params``) from per-point Gaussian gradients."""
+        R = self.R
+        a, wb = saved["acts"], saved["wb"]
+        dw = {n: torch.zeros_like(w) for n, w in self.w.items()}
+        db = {n: torch.zeros_like(b) for n, b in self.b.items()}
+        dh = [torch.zeros_like(t) for t in (self.w1, self.b1, self.w2, self.b2)]
+        g = unet_head_backward(R, lv[0], a["d0"], self.w1, self.b1, self.w2, self.b2, grads, dh)
+
+        def conv_b(name, level, dy, want_dx=True):
+            return conv_backward(R, lv[level], a[name + ":in"], wb[name], a[name], dy, want_dx=want_dx,
+                                 dw=dw[name], db=db[name])
+
+        def up_b(name, level, dy):
+            return up_conv_backward(R, lv[level + 1], a[name + ":in"], wb[name], a[name], dy, dw=dw[name],
+                                    db=db[name])
+
+        dc0 = conv_b("d0", 0, g)                                  # (V0, 64): [u1 | s0]
+        ds0 = dc0[:, 32:]
+        dd1 = up_b("u1", 0, dc0[:, :32])
+        dc1 = conv_b("d1", 1, dd1)                                # (V1, 128): [u2 | s1]
+        ds1 = dc1[:, 64:]
+        dd2 = up_b("u2", 1, dc1[:, :64])
+        dc2 = conv_b("d2", 2, dd2)                                # (V2, 128): [u3 | s2]
+        ds2 = dc2[:, 64:]
+        db3 = up_b("u3", 2, dc2[:, :64])
+        dp3 = conv_b("e3", 3, db3)
+        ds2 = ds2 + pool_features_backward(R, lv[3], dp3)
+        dp2 = conv_b("e2", 2, ds2)
+        ds1 = ds1 + pool_features_backward(R, lv[2], dp2)
+        dp1 = conv_b("e1", 1, ds1)
+        ds0 = ds0 + pool_features_backward(R, lv[1], dp1)
+        de0 = conv_b("e0b", 0, ds0)
+        conv_b("e0a", 0, de0, want_dx=False)
+        names = [n for n, *_ in UNET_LAYOUT]
+        return [dw[n] for n in names] + [db[n] for n in names] + dh
+
+
+def normal_loss(n_hat: torch.Tensor, n_gt: torch.Tensor, mask: torch.Tensor, w3: float = 0.1) -> torch.Tensor:
+    """Eq. 5's normal term over the pixels in ``mask``: |n x n_hat|_2 + w3 min(|n - n_hat|_2,
+    |n + n_hat|_2), both normal maps normalised per pixel ((C,3,H,W) maps, (C,H,W) mask)."""
+    eps = 1e-8
+    a = n_hat / (n_hat.norm(dim=1, keepdim=True) + eps)
+    b = n_gt / (n_gt.norm(dim=1, keepdim=True) + eps)
+    cross = torch.linalg.cross(a, b, dim=1).norm(dim=1)
+    sign = torch.minimum((a - b).norm(dim=1), (a + b).norm(dim=1))
+    per = cross + w3 * sign
+    m = mask.to(per.dtype)
+    return (per * m).sum() / m.sum().clamp_min(1.0)
+
+
+def train_step_unet(est: "UNetEstimator", opt: Adam, clouds: list, view_fn, w1=1.0, w2=10.0, w3=0.1) -> float:
+    """One optimisation step with Eq. 5: L = w1 |I - I_hat|_1 + w2 L_n, L_n the normal term of
+    ``normal_loss`` on the pixels covered in both the rendered and the ground-truth normal maps.
+    ``view_fn(cloud)`` returns (cameras, gt rgb (C,3,H,W), gt normal (C,3,H,W), gt alpha (C,H,W))."""
+    R = est.R
+    total = [torch.zeros_like(p) for p in est.params]
+    loss_sum = 0.0
+    for c in clouds:
+        cams, gt, gt_n, gt_a = view_fn(c)
+        g, saved = est.forward(c["levels"], save=True)
+        st = c.get("state")
+        if st is None:
+            st = c["state"] = RenderState(R)
+        out = R.render(g, cams, default_options(), state=st, want=("rgb", "normal", "alpha"))
+        img = out["rgb"].requires_grad_(True)
+        nrm = out["normal"].requires_grad_(True)
+        mask = (gt_a > 0.5) & (out["alpha"] > 0.5)
+        loss = w1 * (img - gt).abs().mean() + w2 * normal_loss(nrm, gt_n, mask, w3)
+        loss.backward()
+        gg = R.render_backward(st, dict(rgb=img.grad, normal=nrm.grad))
+        grads = est.backward(c["levels"], saved, gg)
+        for t, gr in zip(total, grads):
+            t.add_(gr, alpha=1.0 / len(clouds))
+        loss_sum += float(loss.item())
+    opt.step(total)
+    return loss_sum / len(clouds)

@@ -282,6 +282,13 @@ class Renderer:
                                         _ptr(out), _stream()))
         return out
 
+    def lds_bandwidth(self) -> float:
+        """Measured LDS read bandwidth of the device, GB/s."""
+        v = ctypes.c_double()
+        with torch.cuda.device(self.device):
+            check(_lib.load().pcs_measure_lds_bandwidth(self.ctx, ctypes.byref(v), _stream()))
+        return float(v.value)
+
     def set_wait_limit(self, rounds: int) -> None:
         """Bound of the ordering kernels' look-back waits (0: the default); see the C header."""
         check(_lib.load().pcs_context_set_wait_limit(self.ctx, int(rounds)))

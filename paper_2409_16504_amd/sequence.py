@@ -24,7 +24,7 @@ if ROOT not in sys.path:
 from synthetic import look_at_camera  # noqa: E402
 from synthetic.scenes import ProceduralSurface  # noqa: E402
 
-from . import Renderer, default_options  # noqa: E402
+from . import Renderer, RenderState, default_options  # noqa: E402
 from .estimator import SparseEstimator, Voxels, adaptive_grid, psnr  # noqa: E402
 
 
@@ -119,15 +119,53 @@ def main(argv=None):
         print(f"[sequence] {name}: {report[name]}", flush=True)
 
     # Pipelined: the estimate of frame t + 1 (its own context and stream) overlaps the render of
-    # frame t (another context and stream; both streams at the default priority). Throughput is
-    # the steady-state time per frame; the first frame's estimate is not overlapped.
-    R2 = Renderer(0)
+    # frame t (another context and stream; both streams at the default priority). The render runs
+    # in capacity mode, so the host never waits on it and can queue the next estimate at once.
+    # Throughput is the steady-state time per frame; the first frame's estimate is not overlapped.
+    # "graph": the render of both views is captured once in a HIP graph (capacity mode: it neither
+    # waits nor allocates) reading the Gaussians from fixed buffers; per frame they are copied in
+    # and the graph is replayed on the render stream.
     s_est, s_ren = torch.cuda.Stream(), torch.cuda.Stream()
-    out2 = R2.render(dict(mean=frames[0]["xyz"], quat=torch.zeros((4, args.points), device=dev),
-                          scale=torch.full((3, args.points), 0.002, device=dev),
-                          opacity=torch.full((args.points,), 0.9, device=dev), rgb=frames[0]["rgb"],
-                          normal=torch.zeros((3, args.points), device=dev)), cams, opts)
-    for name, fn in (("learned_bf16_pipelined", learned), ("knn_pca_pipelined", plain)):
+    static = {k: v.clone() for k, v in plain(frames[0]).items()}
+    # the eager capacity-mode renders and the captured one each have their own context and state:
+    # a captured graph keeps the addresses of its context's and state's buffers
+    R2, R3 = Renderer(0), Renderer(0)
+    st2, st3 = RenderState(R2), RenderState(R3)
+    out2, out3 = R2.render(static, cams, opts), R3.render(static, cams, opts)
+    # size both states' capacity over every frame of both estimates (an overflowing frame resizes
+    # the next render, so each frame is rendered until it fits)
+    for fn in (learned, plain):
+        for f in frames:
+            g = fn(f)
+            for k in static:
+                static[k].copy_(g[k])
+            for Rx, stx, outx in ((R2, st2, out2), (R3, st3, out3)):
+                for _ in range(3):
+                    Rx.render(static, cams, opts, state=stx, out=outx, capacity=True)
+                    if stx.status()[0] == 0:
+                        break
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    s_ren.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s_ren):
+        R3.render(static, cams, opts, state=st3, out=out3, capacity=True)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph, stream=s_ren):
+        R3.render(static, cams, opts, state=st3, out=out3, capacity=True)
+    torch.cuda.synchronize()
+
+    def render_capacity(g):
+        R2.render(g, cams, opts, state=st2, out=out2, capacity=True)
+
+    def render_graph(g):
+        for k in static:
+            static[k].copy_(g[k])
+        graph.replay()
+
+    for name, fn, render, stx in (("learned_bf16_pipelined", learned, render_capacity, st2),
+                                  ("knn_pca_pipelined", plain, render_capacity, st2),
+                                  ("learned_bf16_graph", learned, render_graph, st3),
+                                  ("knn_pca_graph", plain, render_graph, st3)):
         torch.cuda.synchronize()
         with torch.cuda.stream(s_est):
             g_cur = fn(frames[0])
@@ -146,14 +184,15 @@ def main(argv=None):
                     ev_next.record(s_est)
             with torch.cuda.stream(s_ren):
                 s_ren.wait_event(ev)
-                R2.render(g_cur, cams, opts, out=out2)
+                render(g_cur)
                 for t in g_cur.values():                # produced on s_est, last used on s_ren
                     t.record_stream(s_ren)
             g_cur, ev = g_next, ev_next
         torch.cuda.synchronize()
         n_timed = len(frames) - args.warmup
         ms = (time.perf_counter() - t1) * 1e3 / n_timed
-        report[name] = dict(ms_per_frame=ms, fps=1e3 / ms, frames=n_timed)
+        rc, _ = stx.status()                            # the last frame's status
+        report[name] = dict(ms_per_frame=ms, fps=1e3 / ms, frames=n_timed, last_frame_status=rc)
         print(f"[sequence] {name}: {report[name]}", flush=True)
 
     # PSNR on a few frames against the plain render of an 8x dense sample of the clean surface

@@ -177,13 +177,14 @@ class ProceduralSurface:
             a.append(4 * math.pi * r * r if kind == "sphere" else 4 * math.pi ** 2 * r * (r * self.minor_ratio))
         return np.asarray(a)
 
-    def sample(self, n: int, rng: np.random.Generator, radius_scale=None) -> np.ndarray:
-        """``n`` area-uniform points on the union, normalised into [-1,1]^3, shape (3, n) float64."""
+    def sample(self, n: int, rng: np.random.Generator, radius_scale=None, with_normals=False):
+        """``n`` area-uniform points on the union, normalised into [-1,1]^3, shape (3, n) float64;
+        with ``with_normals`` also their analytic outward unit normals (3, n) (same random draws)."""
         if radius_scale is None:
             radius_scale = np.ones(len(self.kinds))
         areas = self._areas(radius_scale)
         counts = rng.multinomial(n, areas / areas.sum())
-        pts = []
+        pts, nrms = [], []
         for i, (kind, m) in enumerate(zip(self.kinds, counts)):
             if m == 0:
                 continue
@@ -192,6 +193,7 @@ class ProceduralSurface:
                 d = rng.standard_normal(size=(3, m))
                 d /= np.linalg.norm(d, axis=0, keepdims=True)
                 local = r * d
+                local_n = d
             else:
                 rr = r * self.minor_ratio
                 theta = np.empty(0)
@@ -203,10 +205,16 @@ class ProceduralSurface:
                 phi = rng.uniform(0.0, 2.0 * math.pi, size=m)
                 ring = r + rr * np.cos(theta)
                 local = np.stack([ring * np.cos(phi), ring * np.sin(phi), rr * np.sin(theta)])
+                local_n = np.stack([np.cos(theta) * np.cos(phi), np.cos(theta) * np.sin(phi), np.sin(theta)])
             pts.append(self.center[i][:, None] + self.rot[i] @ local)
+            nrms.append(self.rot[i] @ local_n)
         p = np.concatenate(pts, axis=1)
-        p = np.ascontiguousarray(p[:, rng.permutation(p.shape[1])])
-        return (p - self.norm_center[:, None]) * self.norm_scale
+        perm = rng.permutation(p.shape[1])
+        p = np.ascontiguousarray(p[:, perm])
+        p = (p - self.norm_center[:, None]) * self.norm_scale
+        if with_normals:
+            return p, np.ascontiguousarray(np.concatenate(nrms, axis=1)[:, perm])
+        return p
 
     def color(self, p: np.ndarray) -> np.ndarray:
         """Value-noise RGB in [0,1] at positions p (3, n)."""
