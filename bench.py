@@ -165,8 +165,10 @@ def main():
     stage_roof = stage_rooflines(per_stage, args.n, m, bins, args.width, args.height)
     extras = None if args.no_extras else extra_workloads(R)
     gap = None if args.no_extras else psnr_gap(R)
+    unet = None if args.no_extras else unet_gap(R)
     if extras is not None:
         extras["psnr_gap"] = gap
+        extras["unet"] = unet
         extras["late_shading"] = late_shading(R, out, cams)
     line = dict(
         metric=METRIC, value=args.n / (ms_per_step * 1e-3), unit="Gaussians/s", n_gpus=1,
@@ -178,7 +180,7 @@ def main():
         ms_per_frame=ms_per_step, instances=m, knn_pca_ms=knn_ms,
         stage_ms={k: round(v, 5) for k, v in per_stage.items()},
         frame_modes=modes, roofline=roof, roofline_backward=roof_bwd, stage_roofline=stage_roof,
-        cpu_baseline=cpu, psnr_gap_db=None if gap is None else gap["gap_db"], extras=extras,
+        cpu_baseline=cpu, psnr_gap_db=(unet["gap_db"] if unet is not None else None if gap is None else gap["gap_db"]), extras=extras,
     )
     print(json.dumps(line), flush=True)
 
@@ -402,9 +404,10 @@ WEIGHTS = os.path.join(ROOT, "paper_2409_16504_amd", "weights", "estimator_surfa
 
 
 def psnr_gap(R):
-    """PSNR of the learned estimator (BF16, trained weights shipped with the package) against the
-    kNN-PCA plain path on held-out clouds; ground truth is the plain render of each cloud's 8x
-    denser unquantised sample (the evaluation of the training driver)."""
+    """PSNR of the plain sparse-convolution estimator (eight submanifold layers at one resolution,
+    BF16, trained weights shipped with the package) against the kNN-PCA plain path on held-out
+    clouds; ground truth is the plain render of each cloud's 8x denser unquantised sample (the
+    evaluation of the training driver)."""
     if not os.path.exists(WEIGHTS):
         return None
     import torch
@@ -436,6 +439,67 @@ def psnr_gap(R):
                          f"{rep['views']} orbit views at {rep['res']}x{rep['res']}; ground truth = plain render "
                          "of the 8x denser unquantised sample; kNN-PCA kappa chosen on the training clouds; "
                          "global-sigma baseline: isotropic sigma = factor x mean nearest-neighbour distance")
+
+
+UNET_WEIGHTS = os.path.join(ROOT, "paper_2409_16504_amd", "weights", "unet_surface.pt")
+
+
+def unet_gap(R):
+    """The paper's UNet-like estimator (BF16, trained with Eq. 5 and the density augmentation;
+    weights shipped with the package) against the kNN-PCA plain path and the global-sigma baseline
+    on held-out clouds: at full density and over the augmentation's range (lattices coarsened by a,
+    samples thinned to b); ground truth is the plain render of each cloud's 8x denser unquantised
+    sample (the evaluation of the training driver). Also the estimate's time per cloud against
+    kNN-PCA's on the same points."""
+    if not os.path.exists(UNET_WEIGHTS):
+        return None
+    import torch
+    from paper_2409_16504_amd import train_unet as TU
+    from paper_2409_16504_amd.estimator import UNetEstimator
+    from synthetic import orbit_cameras
+    ck = torch.load(UNET_WEIGHTS, weights_only=True)
+    est = UNetEstimator(R, seed=0)
+    with torch.no_grad():
+        for p, v in zip(est.params, ck["params"]):
+            p.copy_(v.to(p.device))
+    rep = ck["report"]
+    t0 = time.time()
+    held = [TU.make_cloud(R, 2000 + i, rep["points"]) for i in range(2)]
+    cams = orbit_cameras(rep["views"], np.random.default_rng(2024), width=rep["res"], height=rep["res"])
+    runs = {}
+    for a in (1.0, 0.5, 0.25):
+        runs[f"a={a}"] = TU.evaluate(R, est, held, cams, rep["kappa"], rep["sigma_factor"], True, a=a)
+    for b in (0.5, 0.25, 0.125):
+        runs[f"b={b}"] = TU.evaluate(R, est, held, cams, rep["kappa"], rep["sigma_factor"], False, b=b)
+    # time per cloud: voxelise + pool + network + head, against kNN-PCA of the same points
+    x = TU.sample_input(R, held[0], np.random.default_rng(0), True)
+    vox, grid = x["vox"], x["vox"].grid
+    with torch.no_grad():
+        for _ in range(2):
+            est.forward(UNetEstimator.levels(R, vox.build(x["xyz"], x["rgb"], grid)))
+            R.knn_pca(x["xyz"], k=16, kappa=rep["kappa"], floor=0.1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(10):
+            est.forward(UNetEstimator.levels(R, vox.build(x["xyz"], x["rgb"], grid)))
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(10):
+            R.knn_pca(x["xyz"], k=16, kappa=rep["kappa"], floor=0.1)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+    full = runs["a=1.0"]
+    print(f"[bench] UNet on held-out clouds in {time.time() - t0:.1f}s: {full}", file=sys.stderr, flush=True)
+    return dict(full, train_steps=rep["steps"], kappa=rep["kappa"], sigma_factor=rep["sigma_factor"],
+                gap_db_by_density={k: v["gap_db"] for k, v in runs.items()},
+                psnr_by_density={k: dict(learned=v["psnr_learned"], knn_pca=v["psnr_knn_pca"],
+                                         global_sigma=v["psnr_global_sigma"]) for k, v in runs.items()},
+                estimate_ms_per_cloud=(t2 - t1) * 1e3 / 10, knn_pca_ms_per_cloud=(t3 - t2) * 1e3 / 10,
+                points=int(x["xyz"].shape[1]),
+                workload=f"2 held-out procedural clouds ({rep['points']} points, seeds 2000-2001) x "
+                         f"{rep['views']} orbit views at {rep['res']}x{rep['res']}; a: integer lattice "
+                         "coordinates x -> round(a x)/a, b: fraction of points kept; ground truth = plain "
+                         "render of the 8x denser unquantised sample")
 
 
 def stage_rooflines(per_stage, n, m, bins, W, H):

@@ -278,7 +278,7 @@ __global__ __launch_bounds__(kSearchThreads) void k_knn_pca(const float4* __rest
   uint64_t thr = ~0ull;           // k-th best key so far
   // visit the points [b, e) of the cell-sorted array, kBatch loads in flight at a time; positions
   // past e re-read e - 1 and are visited as invalid (no branches: the visitors mask their effect)
-  constexpr int kBatch = 4;
+  constexpr int kBatch = 8;
   auto walk = [&](uint32_t b, uint32_t e, auto&& visit) {
     for (uint32_t j = b; j < e; j += kBatch) {
       float4 Q[kBatch];
