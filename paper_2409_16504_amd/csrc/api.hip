@@ -917,9 +917,9 @@ int pcs_voxelize(pcs_context* ctx, const float* xyz, const float* rgb, int64_t n
   PCS_HIP(hipSetDevice(ctx->device));
   vox->valid = false;
   vox->pooled = false;
-  PCS_TRY(ensure(ctx, vox->keys, n * sizeof(uint64_t), "voxel keys"));
+  PCS_TRY(ensure(ctx, vox->keys, n * sizeof(uint32_t), "voxel keys"));
   PCS_TRY(ensure(ctx, vox->order, n * sizeof(uint32_t), "voxel point order"));
-  PCS_TRY(ensure(ctx, ctx->keys_alt, n * sizeof(uint64_t), "keys (alternate)"));
+  PCS_TRY(ensure(ctx, ctx->keys_alt, n * sizeof(uint32_t), "keys (alternate)"));
   PCS_TRY(ensure(ctx, ctx->vals_alt, n * sizeof(uint32_t), "values (alternate)"));
   PCS_TRY(ensure(ctx, ctx->sort_scratch, sort_scratch_bytes(n), "sort scratch"));
   PCS_TRY(ensure(ctx, vox->flag, n * sizeof(uint32_t), "voxel flags"));
@@ -931,16 +931,16 @@ int pcs_voxelize(pcs_context* ctx, const float* xyz, const float* rgb, int64_t n
   StageTimer tm(ctx, ST_VOXELIZE, s);
   uint32_t* d_err = ctx->small.as<uint32_t>() + kVoxErrWord;
   PCS_HIP(launch_fill_u32(d_err, 0u, 1, s));
-  PCS_HIP(launch_vox_keys(xyz, n, grid, vox->keys.as<uint64_t>(), vox->order.as<uint32_t>(), s));
+  PCS_HIP(launch_vox_keys(xyz, n, grid, vox->keys.as<uint32_t>(), vox->order.as<uint32_t>(), s));
   bool in_alt = false;
-  PCS_HIP(launch_sort(vox->keys.as<uint64_t>(), vox->order.as<uint32_t>(), ctx->keys_alt.as<uint64_t>(),
-                      ctx->vals_alt.as<uint32_t>(), n, 30, ctx->sort_scratch.p, s, &in_alt, nullptr, false,
+  PCS_HIP(launch_sort(vox->keys.as<uint32_t>(), vox->order.as<uint32_t>(), ctx->keys_alt.as<uint32_t>(),
+                      ctx->vals_alt.as<uint32_t>(), n, 3 * grid_bits(grid), ctx->sort_scratch.p, s, &in_alt, nullptr, false,
                       false, nullptr, 0, -1, nullptr, 0, d_err, ctx->wait_limit));
   if (in_alt) {
     swap_buf(vox->keys, ctx->keys_alt);
     swap_buf(vox->order, ctx->vals_alt);
   }
-  PCS_HIP(launch_vox_flags(vox->keys.as<uint64_t>(), n, vox->flag.as<uint32_t>(), s));
+  PCS_HIP(launch_vox_flags(vox->keys.as<uint32_t>(), n, vox->flag.as<uint32_t>(), s));
   uint64_t* d_total = ctx->small.as<uint64_t>();
   PCS_HIP(launch_scan(vox->flag.as<uint32_t>(), nullptr, nullptr, nullptr, vox->excl.as<uint32_t>(), n, d_total,
                       ctx->scan_scratch.p, s, false, d_err, ctx->wait_limit));
@@ -959,7 +959,7 @@ int pcs_voxelize(pcs_context* ctx, const float* xyz, const float* rgb, int64_t n
   PCS_TRY(ensure(ctx, vox->hkeys, (size_t(1) << log2cap) * sizeof(uint32_t), "voxel hash keys"));
   PCS_TRY(ensure(ctx, vox->hvals, (size_t(1) << log2cap) * sizeof(int32_t), "voxel hash values"));
   PCS_TRY(ensure(ctx, vox->nbr, 27 * V * sizeof(int32_t), "kernel map"));
-  PCS_HIP(launch_vox_build(vox->keys.as<uint64_t>(), vox->order.as<uint32_t>(), vox->flag.as<uint32_t>(),
+  PCS_HIP(launch_vox_build(vox->keys.as<uint32_t>(), vox->order.as<uint32_t>(), vox->flag.as<uint32_t>(),
                            vox->excl.as<uint32_t>(), n, (int64_t)V, xyz, rgb, grid, vox->start.as<uint32_t>(),
                            vox->coords.as<int32_t>(), vox->feat.as<uint16_t>(),
                            vox->point_voxel.as<int32_t>(), vox->hkeys.as<uint32_t>(),

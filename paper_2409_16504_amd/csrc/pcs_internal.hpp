@@ -298,10 +298,12 @@ hipError_t launch_knn_pca(const float* xyz, int64_t n, int k, float kappa, float
 size_t knn_scratch_bytes(int64_t n);
 
 // ---- sparse estimator ---------------------------------------------------------------------------
-hipError_t launch_vox_keys(const float* xyz, int64_t n, int grid, uint64_t* keys, uint32_t* vals,
+// log2 of a power-of-two grid: the width of each coordinate field of a voxel key
+int grid_bits(int grid);
+hipError_t launch_vox_keys(const float* xyz, int64_t n, int grid, uint32_t* keys, uint32_t* vals,
                            hipStream_t s);
-hipError_t launch_vox_flags(const uint64_t* keys, int64_t n, uint32_t* flag, hipStream_t s);
-hipError_t launch_vox_build(const uint64_t* keys, const uint32_t* order, const uint32_t* flag,
+hipError_t launch_vox_flags(const uint32_t* keys, int64_t n, uint32_t* flag, hipStream_t s);
+hipError_t launch_vox_build(const uint32_t* keys, const uint32_t* order, const uint32_t* flag,
                             const uint32_t* excl, int64_t n, int64_t V, const float* xyz,
                             const float* rgb, int grid, uint32_t* start, int32_t* coords,
                             uint16_t* feat, int32_t* point_voxel, uint32_t* hkeys, int32_t* hvals,

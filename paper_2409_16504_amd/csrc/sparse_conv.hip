@@ -48,8 +48,10 @@ __device__ __forceinline__ uint32_t hash_slot(uint32_t key, int log2cap) {
 }
 
 // ---- voxelisation -----------------------------------------------------------------------------
-__global__ void k_vox_key(const float* __restrict__ xyz, int64_t n, int grid,
-                          uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+// Voxel key (x << 2b) | (y << b) | z with b = log2(grid): lexicographic (x, y, z) order in 3b bits,
+// so the sort runs ceil(3b / 8) passes.
+__global__ void k_vox_key(const float* __restrict__ xyz, int64_t n, int grid, int b,
+                          uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   uint32_t c[3];
@@ -58,11 +60,11 @@ __global__ void k_vox_key(const float* __restrict__ xyz, int64_t n, int grid,
     const float g = floorf((xyz[a * n + i] + 1.0f) * (0.5f * (float)grid));
     c[a] = (uint32_t)fminf(fmaxf(g, 0.0f), (float)(grid - 1));
   }
-  keys[i] = ((uint64_t)c[0] << 20) | ((uint64_t)c[1] << 10) | c[2];
+  keys[i] = (c[0] << (2 * b)) | (c[1] << b) | c[2];
   vals[i] = (uint32_t)i;
 }
 
-__global__ void k_vox_flag(const uint64_t* __restrict__ keys, int64_t n, uint32_t* __restrict__ flag) {
+__global__ void k_vox_flag(const uint32_t* __restrict__ keys, int64_t n, uint32_t* __restrict__ flag) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   flag[j] = (j == 0 || keys[j] != keys[j - 1]) ? 1u : 0u;
@@ -77,17 +79,17 @@ __global__ void k_vox_start(const uint32_t* __restrict__ flag, const uint32_t* _
 
 // One thread per voxel: coordinates, mean colour and residual (features, BF16, 32 channels:
 // rgb, residual, zero padding), point -> voxel map and hash insertion.
-__global__ void k_vox_reduce(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ order,
+__global__ void k_vox_reduce(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ order,
                              const uint32_t* __restrict__ start, int64_t V, int64_t n,
-                             const float* __restrict__ xyz, const float* __restrict__ rgb, int grid,
+                             const float* __restrict__ xyz, const float* __restrict__ rgb, int grid, int gb,
                              int32_t* __restrict__ coords, uint16_t* __restrict__ feat,
                              int32_t* __restrict__ point_voxel, uint32_t* __restrict__ hkeys,
                              int32_t* __restrict__ hvals, int log2cap) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= V) return;
   const uint32_t b = start[v], e = (v + 1 < V) ? start[v + 1] : (uint32_t)n;
-  const uint64_t key = keys[b];
-  const int cx = (int)(key >> 20) & 1023, cy = (int)(key >> 10) & 1023, cz = (int)key & 1023;
+  const uint32_t key = keys[b];
+  const int cx = (int)(key >> (2 * gb)), cy = (int)(key >> gb) & (grid - 1), cz = (int)key & (grid - 1);
   float s[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   for (uint32_t j = b; j < e; ++j) {
     const uint32_t i = order[j];
@@ -117,9 +119,10 @@ __global__ void k_vox_reduce(const uint64_t* __restrict__ keys, const uint32_t* 
     w.w = f[8 * q + 6] | ((uint32_t)f[8 * q + 7] << 16);
     dst[q] = w;
   }
-  // insert into the hash table (keys are unique; linear probing always finds a free slot because
-  // the table holds at most half its capacity)
-  const uint32_t k32 = (uint32_t)key;
+  // insert into the hash table under the 10-bit-field key the kernel map looks up (keys are
+  // unique; linear probing always finds a free slot because the table holds at most half its
+  // capacity)
+  const uint32_t k32 = ((uint32_t)cx << 20) | ((uint32_t)cy << 10) | (uint32_t)cz;
   const uint32_t mask = (1u << log2cap) - 1u;
   uint32_t slot = hash_slot(k32, log2cap);
   for (uint32_t probe = 0; probe <= mask; ++probe) {
@@ -132,35 +135,50 @@ __global__ void k_vox_reduce(const uint64_t* __restrict__ keys, const uint32_t* 
   }
 }
 
-__global__ void k_kernel_map(const int32_t* __restrict__ coords, int64_t V, int grid,
-                             const uint32_t* __restrict__ hkeys, const int32_t* __restrict__ hvals,
-                             int log2cap, int32_t* __restrict__ nbr) {
+// The 27 neighbours of every voxel by hash lookup. The first probe of all 27 keys is issued at
+// once (27 loads in flight per thread), and so are the value loads of the hits; only keys whose
+// first slot holds another key probe on (linear probing, the table at most half full).
+__global__ __launch_bounds__(256) void k_kernel_map(const int32_t* __restrict__ coords, int64_t V, int grid,
+                                                    const uint32_t* __restrict__ hkeys,
+                                                    const int32_t* __restrict__ hvals, int log2cap,
+                                                    int32_t* __restrict__ nbr) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= V) return;
   const int cx = coords[v], cy = coords[V + v], cz = coords[2 * V + v];
   const uint32_t mask = (1u << log2cap) - 1u;
+  uint32_t key[27], slot[27], hk[27];
+#pragma unroll
   for (int k = 0; k < 27; ++k) {
     const int x = cx + (k / 9) - 1, y = cy + ((k / 3) % 3) - 1, z = cz + (k % 3) - 1;
-    int32_t found = -1;
-    if (x >= 0 && x < grid && y >= 0 && y < grid && z >= 0 && z < grid) {
-      const uint32_t key = ((uint32_t)x << 20) | ((uint32_t)y << 10) | (uint32_t)z;
-      uint32_t slot = hash_slot(key, log2cap);
-      for (uint32_t probe = 0; probe <= mask; ++probe) {
-        const uint32_t hk = hkeys[slot];
-        if (hk == key) { found = hvals[slot]; break; }
-        if (hk == kEmptyKey) break;
-        slot = (slot + 1) & mask;
-      }
-    }
-    nbr[(int64_t)k * V + v] = found;
+    const bool in = x >= 0 && x < grid && y >= 0 && y < grid && z >= 0 && z < grid;
+    key[k] = in ? (((uint32_t)x << 20) | ((uint32_t)y << 10) | (uint32_t)z) : kEmptyKey;
+    slot[k] = in ? hash_slot(key[k], log2cap) : 0u;
   }
+#pragma unroll
+  for (int k = 0; k < 27; ++k) hk[k] = key[k] != kEmptyKey ? hkeys[slot[k]] : kEmptyKey;
+  // keys whose first slot holds another key probe on (rare)
+#pragma unroll
+  for (int k = 0; k < 27; ++k) {
+    if (key[k] == kEmptyKey) continue;
+    for (uint32_t probe = 1; hk[k] != key[k] && hk[k] != kEmptyKey && probe <= mask; ++probe) {
+      slot[k] = (slot[k] + 1) & mask;
+      hk[k] = hkeys[slot[k]];
+    }
+  }
+  int32_t found[27];
+#pragma unroll
+  for (int k = 0; k < 27; ++k) found[k] = (key[k] != kEmptyKey && hk[k] == key[k]) ? hvals[slot[k]] : -1;
+#pragma unroll
+  for (int k = 0; k < 27; ++k) nbr[(int64_t)k * V + v] = found[k];
 }
 
 // ---- convolution ------------------------------------------------------------------------------
+constexpr int kConvWaves = 4;                  // wavefronts per block
+constexpr int kConvTiles = 1;                  // 16-row MFMA tiles per wavefront
 // y[v][o] = relu?(bias[o] + sum_k sum_c W[k][o][c] x[nbr_k(v)][c]) over n_off offsets (27 for a
 // submanifold 3x3x3 convolution, 8 for a stride-2 transposed 2x2x2 one); wt is [n_off][COUT][CIN]
 // BF16 and nbr is [n_off][V].
-template <int CIN, int COUT>
+template <int CIN, int COUT, int MB>
 __global__ __launch_bounds__(256) void k_subm_conv(const uint16_t* __restrict__ x,
                                                    const uint16_t* __restrict__ wt,
                                                    const float* __restrict__ bias,
@@ -171,11 +189,11 @@ __global__ __launch_bounds__(256) void k_subm_conv(const uint16_t* __restrict__ 
   constexpr int LDW = CIN + 8;       // padded LDS row (avoids bank conflicts)
   __shared__ uint16_t s_w[COUT * LDW];
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-  const int64_t vbase = (int64_t)blockIdx.x * 256 + wave * 64;
+  const int64_t vbase = (int64_t)blockIdx.x * (kConvWaves * 16 * MB) + wave * (16 * MB);
   const int row = lane % 16, grp = lane / 16;
-  f32x4 acc[4][NB];
+  f32x4 acc[MB][NB];
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb)
+  for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
   for (int k = 0; k < n_off; ++k) {
@@ -194,7 +212,7 @@ __global__ __launch_bounds__(256) void k_subm_conv(const uint16_t* __restrict__ 
       for (int nb = 0; nb < NB; ++nb)
         bfr[kc][nb] = as_bf16x8(*reinterpret_cast<const uint4*>(&s_w[(nb * 16 + row) * LDW + kc * 32 + grp * 8]));
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb) {
+    for (int mb = 0; mb < MB; ++mb) {
       const int64_t v = vbase + mb * 16 + row;
       const int32_t j = v < V ? nbr[(int64_t)k * V + v] : -1;
 #pragma unroll
@@ -210,7 +228,7 @@ __global__ __launch_bounds__(256) void k_subm_conv(const uint16_t* __restrict__ 
   }
   // epilogue: lane holds rows 4*grp + r of column row of each 16x16 block
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb)
+  for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const int o = nb * 16 + row;
@@ -820,18 +838,25 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
 }  // namespace
 
 // ---- host launchers -----------------------------------------------------------------------------
-hipError_t launch_vox_keys(const float* xyz, int64_t n, int grid, uint64_t* keys, uint32_t* vals,
+int grid_bits(int grid) {
+  int b = 0;
+  while ((1 << b) < grid) ++b;
+  return b;
+}
+
+hipError_t launch_vox_keys(const float* xyz, int64_t n, int grid, uint32_t* keys, uint32_t* vals,
                            hipStream_t s) {
-  hipLaunchKernelGGL(k_vox_key, dim3(blocks_for(n, 256)), dim3(256), 0, s, xyz, n, grid, keys, vals);
+  hipLaunchKernelGGL(k_vox_key, dim3(blocks_for(n, 256)), dim3(256), 0, s, xyz, n, grid, grid_bits(grid), keys,
+                     vals);
   return hipGetLastError();
 }
 
-hipError_t launch_vox_flags(const uint64_t* keys, int64_t n, uint32_t* flag, hipStream_t s) {
+hipError_t launch_vox_flags(const uint32_t* keys, int64_t n, uint32_t* flag, hipStream_t s) {
   hipLaunchKernelGGL(k_vox_flag, dim3(blocks_for(n, 256)), dim3(256), 0, s, keys, n, flag);
   return hipGetLastError();
 }
 
-hipError_t launch_vox_build(const uint64_t* keys, const uint32_t* order, const uint32_t* flag,
+hipError_t launch_vox_build(const uint32_t* keys, const uint32_t* order, const uint32_t* flag,
                             const uint32_t* excl, int64_t n, int64_t V, const float* xyz,
                             const float* rgb, int grid, uint32_t* start, int32_t* coords,
                             uint16_t* feat, int32_t* point_voxel, uint32_t* hkeys, int32_t* hvals,
@@ -840,7 +865,7 @@ hipError_t launch_vox_build(const uint64_t* keys, const uint32_t* order, const u
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_vox_start, dim3(blocks_for(n, 256)), dim3(256), 0, s, flag, excl, n, start);
   hipLaunchKernelGGL(k_vox_reduce, dim3(blocks_for(V, 256)), dim3(256), 0, s, keys, order, start, V, n,
-                     xyz, rgb, grid, coords, feat, point_voxel, hkeys, hvals, log2cap);
+                     xyz, rgb, grid, grid_bits(grid), coords, feat, point_voxel, hkeys, hvals, log2cap);
   hipLaunchKernelGGL(k_kernel_map, dim3(blocks_for(V, 256)), dim3(256), 0, s, coords, V, grid, hkeys,
                      hvals, log2cap, nbr);
   return hipGetLastError();
@@ -856,11 +881,15 @@ bool conv_shape_supported(int cin, int cout) {
 hipError_t launch_subm_conv(const uint16_t* x, int cin, const uint16_t* wt, const float* bias, int cout,
                             const int32_t* nbr, int64_t V, int relu, uint16_t* y, hipStream_t s, int n_off) {
   if (V == 0) return hipSuccess;
-  const dim3 grid(blocks_for(V, 256)), block(256);
-#define PCS_CONV(CI, CO)                                                                             \
-  if (cin == CI && cout == CO) {                                                                     \
-    hipLaunchKernelGGL((k_subm_conv<CI, CO>), grid, block, 0, s, x, wt, bias, nbr, V, relu, y, n_off); \
-    return hipGetLastError();                                                                        \
+  // one 16-row MFMA tile per wavefront, four wavefronts per block: 64 voxels per block spread
+  // even a coarse UNet level over the chip (four row tiles per wavefront, which share the weight
+  // fragments, were slower at every level size measured, 26k to 333k voxels)
+  const dim3 grid(blocks_for(V, kConvWaves * 16 * kConvTiles)), block(kConvWaves * kWave);
+#define PCS_CONV(CI, CO)                                                                              \
+  if (cin == CI && cout == CO) {                                                                      \
+    hipLaunchKernelGGL((k_subm_conv<CI, CO, kConvTiles>), grid, block, 0, s, x, wt, bias, nbr, V, relu, y, \
+                       n_off);                                                                        \
+    return hipGetLastError();                                                                         \
   }
   PCS_CONV(32, 32) PCS_CONV(32, 64) PCS_CONV(64, 32) PCS_CONV(64, 64) PCS_CONV(128, 32) PCS_CONV(128, 64)
   PCS_CONV(32, 128) PCS_CONV(64, 128)

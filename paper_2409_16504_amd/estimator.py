@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import ctypes
 import math
+import sys
 
 import torch
 
@@ -45,7 +46,11 @@ class Voxels:
     def __init__(self, renderer: Renderer):
         self.renderer = renderer
         self.handle = ctypes.c_void_p()
-        check(_lib.load().pcs_voxels_create(renderer.ctx, ctypes.byref(self.handle)))
+        L = _lib.load()
+        check(L.pcs_voxels_create(renderer.ctx, ctypes.byref(self.handle)))
+        # held by the instance: module globals may already be cleared when __del__ runs
+        self._destroy = L.pcs_voxels_destroy
+        self._finalizing = sys.is_finalizing
         self.V = 0
         self.n = 0
 
@@ -79,8 +84,12 @@ class Voxels:
         return dict(coords=coords, nbr=nbr, point_voxel=pvox, features=feat)
 
     def __del__(self):
+        # at interpreter exit the HIP runtime may be shutting down; process exit frees the memory
+        finalizing = getattr(self, "_finalizing", None)
+        if finalizing is None or finalizing():
+            return
         if getattr(self, "handle", None) and self.handle.value:
-            _lib.load().pcs_voxels_destroy(self.handle)
+            self._destroy(self.handle)
             self.handle = ctypes.c_void_p()
 
 
@@ -356,6 +365,20 @@ class UNetEstimator:
         names = [n for n, *_ in UNET_LAYOUT]
         self.params = [self.w[n] for n in names] + [self.b[n] for n in names] + [self.w1, self.b1, self.w2, self.b2]
 
+    def _bf16_weights(self) -> dict:
+        """BF16 copies of the convolution weights, made again only for weights changed in place
+        since (tracked by each tensor's version counter, which optimiser steps advance)."""
+        cache = getattr(self, "_wb_cache", None)
+        if cache is None:
+            cache = self._wb_cache = {}
+        out = {}
+        for n, w in self.w.items():
+            hit = cache.get(n)
+            if hit is None or hit[0] is not w or hit[1] != w._version:
+                hit = cache[n] = (w, w._version, w.to(torch.bfloat16).contiguous())
+            out[n] = hit[2]
+        return out
+
     @staticmethod
     def levels(R: Renderer, vox: Voxels) -> list:
         """Voxel sets of levels 0..3 of a voxelised cloud (level 0 is ``vox``)."""
@@ -366,7 +389,7 @@ class UNetEstimator:
 
     def forward(self, lv: list, save=False):
         R = self.R
-        wb = {n: w.to(torch.bfloat16).contiguous() for n, w in self.w.items()}
+        wb = self._bf16_weights()
         x0 = lv[0].arrays()["features"]
         a = {}
 

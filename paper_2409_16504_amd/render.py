@@ -78,7 +78,11 @@ class RenderState:
     def __init__(self, renderer: "Renderer"):
         self.renderer = renderer
         self.handle = ctypes.c_void_p()
-        check(_lib.load().pcs_state_create(renderer.ctx, ctypes.byref(self.handle)))
+        L = _lib.load()
+        check(L.pcs_state_create(renderer.ctx, ctypes.byref(self.handle)))
+        # held by the instance: module globals may already be cleared when __del__ runs
+        self._destroy = L.pcs_state_destroy
+        self._finalizing = sys.is_finalizing
         self.keep = None          # tensors the state points at (inputs must stay alive)
         self.shape = None
 
@@ -103,8 +107,12 @@ class RenderState:
         return int(c.value)
 
     def __del__(self):
+        # at interpreter exit the HIP runtime may be shutting down; process exit frees the memory
+        finalizing = getattr(self, "_finalizing", None)
+        if finalizing is None or finalizing():
+            return
         if getattr(self, "handle", None) and self.handle.value:
-            _lib.load().pcs_state_destroy(self.handle)
+            self._destroy(self.handle)
             self.handle = ctypes.c_void_p()
 
 
