@@ -7,8 +7,9 @@ with ReLU and a per-voxel linear head. This module defines each step plainly:
 
 * ``voxelize``: voxel coordinate c = clamp(floor((p + 1) * G/2), 0, G-1) on a G^3 grid over
   [-1,1]^3 (G = 1024 is the 10-bit quantisation of Section 3.3); unique voxels in ascending linear
-  key (x << 20 | y << 10 | z); per voxel the mean colour and the mean residual
-  (p + 1) * G/2 - (c + 0.5) of its points (the coordinate residual of Section 3.2). The cloud's
+  key (x << 20 | y << 10 | z); per voxel the mean colour, the mean residual
+  (p + 1) * G/2 - (c + 0.5) (the coordinate residual of Section 3.2) and the mean absolute
+  position p of its points (Section 3.2 feeds coordinates, colour and residuals). The cloud's
   coordinates are FP32, so the voxel decision floor is taken on the FP32 sum p + 1 (times the
   power of two G/2, exact); the residual is FP64.
 * ``kernel_map``: for voxel i and offset k = 9 (dx + 1) + 3 (dy + 1) + (dz + 1) the index of the
@@ -48,8 +49,10 @@ def voxelize(xyz: np.ndarray, rgb: np.ndarray, grid: int = GRID) -> dict:
     col = np.stack([np.bincount(inv, weights=np.asarray(rgb, np.float64)[a], minlength=V) for a in range(3)], 1)
     res_p = (p + 1.0) * (grid / 2) - (c + 0.5)
     res = np.stack([np.bincount(inv, weights=res_p[:, a], minlength=V) for a in range(3)], 1)
+    pos = np.stack([np.bincount(inv, weights=p[:, a], minlength=V) for a in range(3)], 1)
     return dict(coords=coords, keys=ukeys, point_voxel=inv.astype(np.int64),
-                color=col / count[:, None], residual=res / count[:, None], count=count)
+                color=col / count[:, None], residual=res / count[:, None], position=pos / count[:, None],
+                count=count)
 
 
 def kernel_map(coords: np.ndarray, grid: int = GRID) -> np.ndarray:

@@ -77,8 +77,9 @@ __global__ void k_vox_start(const uint32_t* __restrict__ flag, const uint32_t* _
   if (flag[j]) start[excl[j]] = (uint32_t)j;
 }
 
-// One thread per voxel: coordinates, mean colour and residual (features, BF16, 32 channels:
-// rgb, residual, zero padding), point -> voxel map and hash insertion.
+// One thread per voxel: coordinates, mean colour, residual and position (features, BF16, 32
+// channels: rgb, residual, absolute position in [-1, 1]^3, zero padding), point -> voxel map and
+// hash insertion.
 __global__ void k_vox_reduce(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ order,
                              const uint32_t* __restrict__ start, int64_t V, int64_t n,
                              const float* __restrict__ xyz, const float* __restrict__ rgb, int grid, int gb,
@@ -90,7 +91,7 @@ __global__ void k_vox_reduce(const uint32_t* __restrict__ keys, const uint32_t* 
   const uint32_t b = start[v], e = (v + 1 < V) ? start[v + 1] : (uint32_t)n;
   const uint32_t key = keys[b];
   const int cx = (int)(key >> (2 * gb)), cy = (int)(key >> gb) & (grid - 1), cz = (int)key & (grid - 1);
-  float s[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float s[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   for (uint32_t j = b; j < e; ++j) {
     const uint32_t i = order[j];
     point_voxel[i] = (int32_t)v;
@@ -98,9 +99,13 @@ __global__ void k_vox_reduce(const uint32_t* __restrict__ keys, const uint32_t* 
     s[1] += rgb[n + i];
     s[2] += rgb[2 * n + i];
     const float half = 0.5f * (float)grid;
-    s[3] += (xyz[i] + 1.0f) * half - ((float)cx + 0.5f);
-    s[4] += (xyz[n + i] + 1.0f) * half - ((float)cy + 0.5f);
-    s[5] += (xyz[2 * n + i] + 1.0f) * half - ((float)cz + 0.5f);
+    const float px = xyz[i], py = xyz[n + i], pz = xyz[2 * n + i];
+    s[3] += (px + 1.0f) * half - ((float)cx + 0.5f);
+    s[4] += (py + 1.0f) * half - ((float)cy + 0.5f);
+    s[5] += (pz + 1.0f) * half - ((float)cz + 0.5f);
+    s[6] += px;
+    s[7] += py;
+    s[8] += pz;
   }
   const float inv = 1.0f / (float)(e - b);
   coords[v] = cx;
@@ -108,7 +113,7 @@ __global__ void k_vox_reduce(const uint32_t* __restrict__ keys, const uint32_t* 
   coords[2 * V + v] = cz;
   uint16_t f[32];
 #pragma unroll
-  for (int c = 0; c < 32; ++c) f[c] = c < 6 ? f32_to_bf16(s[c] * inv) : (uint16_t)0;
+  for (int c = 0; c < 32; ++c) f[c] = c < 9 ? f32_to_bf16(s[c] * inv) : (uint16_t)0;
   uint4* dst = reinterpret_cast<uint4*>(feat + v * 32);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {

@@ -21,6 +21,7 @@ from .render import Renderer, RenderState, default_options
 
 LAYERS = [(32, 32), (32, 32), (32, 64), (64, 64), (64, 64), (64, 64), (64, 32), (32, 32)]
 IN_CHANNELS = 6          # mean rgb + mean residual (the first layer's input is padded to 32)
+UNET_IN_CHANNELS = 9     # the UNet also reads the voxel's mean absolute position (channels 6-8)
 HEAD_OUT = 11
 
 
@@ -192,6 +193,7 @@ class SparseEstimator:
         for li in reversed(range(len(LAYERS))):
             dy = conv_backward(self.R, vox, acts[li], wb[li], acts[li + 1], dy, want_dx=li > 0,
                                dw=dws[li], db=dbs[li])
+        dws[0][:, :, IN_CHANNELS:] = 0.0      # this estimator reads colour and residual only
         return dws + dbs + [dwh, dbh]
 
 
@@ -348,10 +350,10 @@ class UNetEstimator:
         self.w, self.b = {}, {}
         for name, kind, cin, cout in UNET_LAYOUT:
             k = 27 if kind == "subm" else 8
-            fan_in = k * (IN_CHANNELS if name == "e0a" else cin)
+            fan_in = k * (UNET_IN_CHANNELS if name == "e0a" else cin)
             w = torch.randn((k, cout, cin), generator=gen) * math.sqrt(2.0 / fan_in)
             if name == "e0a":
-                w[:, :, IN_CHANNELS:] = 0.0
+                w[:, :, UNET_IN_CHANNELS:] = 0.0
             self.w[name] = w.to(dev)
             self.b[name] = torch.zeros(cout, device=dev)
         self.w1 = (torch.randn((UNET_HEAD_HIDDEN, 32), generator=gen) * math.sqrt(2.0 / 32)).to(dev)

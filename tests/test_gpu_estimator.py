@@ -51,12 +51,13 @@ def test_voxelize_and_kernel_map(cloud):
     nbr_ref = E.kernel_map(ref["coords"], GRID)
     assert np.array_equal(arr["nbr"].cpu().numpy(), nbr_ref)
     f = arr["features"].to(torch.float64).cpu().numpy()
-    want = np.concatenate([ref["color"], ref["residual"]], axis=1)
+    want = np.concatenate([ref["color"], ref["residual"], ref["position"]], axis=1)
     # BF16 rounding of the mean (2^-9 relative) plus, for the residual (p + 1) * G/2 - (c + 0.5),
-    # the FP32 rounding of p + 1 amplified by G/2 (at most 2^-23 * 512 = 6.1e-5 per point)
-    absolute = np.array([1e-6] * 3 + [1.5e-4] * 3)
-    assert np.all(np.abs(f[:, :6] - want) <= 2.0 ** -8 * np.abs(want) + absolute)
-    assert np.all(f[:, 6:] == 0)
+    # the FP32 rounding of p + 1 amplified by G/2 (at most 2^-23 * G/2 per point) and the FP32
+    # sums of at most a few points
+    absolute = np.array([1e-6] * 3 + [2.0 ** -23 * GRID / 2 * 8] * 3 + [1e-6] * 3)
+    assert np.all(np.abs(f[:, :9] - want) <= 2.0 ** -8 * np.abs(want) + absolute)
+    assert np.all(f[:, 9:] == 0)
     assert (nbr_ref >= 0).sum(axis=0).mean() > 3          # neighbours exist (surface connectivity)
 
 

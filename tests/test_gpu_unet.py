@@ -173,7 +173,7 @@ def test_network_forward_error_against_fp64(R, cloud):
         w = est.w[name].to(torch.bfloat16).to(torch.float64).cpu().numpy().transpose(0, 2, 1)
         weights[name] = (w, est.b[name].cpu().numpy().astype(np.float64))
     x0 = np.zeros((vox.V, 32))
-    x0[:, :6] = vox.arrays()["features"][:, :6].to(torch.float64).cpu().numpy()
+    x0[:, :9] = vox.arrays()["features"][:, :9].to(torch.float64).cpu().numpy()
     f = U.forward(x0, olv, weights)
     want = U.head(f, est.w1.cpu().numpy().T.astype(np.float64), est.b1.cpu().numpy(),
                   est.w2.cpu().numpy().T.astype(np.float64), est.b2.cpu().numpy(), p, rgb, ref["point_voxel"], GRID)
