@@ -459,9 +459,7 @@ def unet_gap(R):
     from synthetic import orbit_cameras
     ck = torch.load(UNET_WEIGHTS, weights_only=True)
     est = UNetEstimator(R, seed=0)
-    with torch.no_grad():
-        for p, v in zip(est.params, ck["params"]):
-            p.copy_(v.to(p.device))
+    est.load_params(ck["params"])
     rep = ck["report"]
     t0 = time.time()
     held = [TU.make_cloud(R, 2000 + i, rep["points"]) for i in range(2)]

@@ -332,21 +332,24 @@ int pcs_up_conv_backward(pcs_context* ctx, const pcs_voxels* parent, const uint1
                          const uint16_t* w, int32_t cout, const uint16_t* y, const uint16_t* dy,
                          uint16_t* dx, float* dw, float* dbias, void* stream);
 
-/* The paper's head: per voxel raw = W2 relu(W1 f + b1) + b2 (f = feat[V][32] BF16; w1[32][32],
- * b1[32], w2[14][32], b2[14] FP32); per point of the voxel (edge e = 2 / grid):
- * mean = xyz + e tanh(raw[0:3]) (the offset delta stays within one voxel edge),
+/* The paper's head (Section 3.2): a shared MLP per point. Point i in voxel v (edge e = 2 / grid,
+ * integer coordinates c_v) has the input x_i = [feat[v][0:32], (xyz_i + 1) grid / 2 - (c_v + 0.5)]
+ * (its voxel's decoder features, BF16, and its own residual inside the voxel in edges, FP32);
+ * raw_i = W2 relu(W1 x_i + b1) + b2 with w1[32][35], b1[32], w2[14][32], b2[14] (FP32, row-major
+ * [out][in]). Outputs: mean = xyz + e tanh(raw[0:3]) (the offset stays within one voxel edge),
  * scale = e exp(raw[3:6]), quat = normalise(raw[6:10] + (1,0,0,0)), opacity = sigmoid(raw[10]),
- * normal = normalise(raw[11:14]), rgb = the point's colour (Section 3.1 keeps the original colour).
- * The backward takes per-point gradients of mean, quat, scale, opacity and normal (any may be
- * NULL = zero) and gives d_feat[V][32] (BF16, overwritten) and the weight gradients (FP32,
- * accumulated). */
+ * normal = normalise(raw[11:14]), rgb = the point's colour (Section 3.1 keeps the original colour);
+ * all planar [3|4][n] or [n] FP32. xyz must be the points the voxels were built from. The backward
+ * takes per-point gradients of mean, quat, scale, opacity and normal (any may be NULL = zero) and
+ * gives d_feat[V][32] (BF16, overwritten) and the weight gradients (FP32, accumulated: zero them
+ * first). No gradient flows to xyz. */
 int pcs_unet_head_forward(pcs_context* ctx, const pcs_voxels* vox, const uint16_t* feat, const float* w1,
                           const float* b1, const float* w2, const float* b2, const float* xyz,
                           const float* rgb, float* mean, float* quat, float* scale, float* opacity,
                           float* out_rgb, float* normal, void* stream);
 int pcs_unet_head_backward(pcs_context* ctx, const pcs_voxels* vox, const uint16_t* feat, const float* w1,
-                           const float* b1, const float* w2, const float* b2, const float* d_mean,
-                           const float* d_quat, const float* d_scale, const float* d_opacity,
+                           const float* b1, const float* w2, const float* b2, const float* xyz,
+                           const float* d_mean, const float* d_quat, const float* d_scale, const float* d_opacity,
                            const float* d_normal, uint16_t* d_feat, float* d_w1, float* d_b1, float* d_w2,
                            float* d_b2, void* stream);
 

@@ -12,7 +12,9 @@ Section 3.2 (and its network figure) builds the estimator from:
   delta, the scale, the rotation, the opacity and the surface normal.
 
 Readings where the paper is silent (its figure's channel widths are not in the text): the
-channel plan and activations of ``LAYOUT`` and ``head``; skip connections concatenate channels
+channel plan and activations of ``LAYOUT`` and ``head``; the head's input per point is its
+voxel's decoder features and its own coordinate residual (several points can share a voxel, and
+the head is to give each its own parameters); skip connections concatenate channels
 (as the sparse-convolution UNets the paper builds on do). Everything is FP64 numpy; submanifold
 convolutions come from ``oracle.estimator.subm_conv``.
 """
@@ -71,22 +73,28 @@ def up_conv(x_parent: np.ndarray, W: np.ndarray, b, child_coords: np.ndarray, pa
 
 
 def head(f: np.ndarray, W1: np.ndarray, b1, W2: np.ndarray, b2, points: np.ndarray, rgb: np.ndarray,
-         point_voxel: np.ndarray, grid: int) -> dict:
-    """Per-point Gaussians from the level-0 features f (V, 32); W1 (32, 32), W2 (32, 14) map
-    inputs to outputs. Edge e = 2 / grid: mean = p + e tanh(raw[0:3]), scale = e exp(raw[3:6]),
-    q = normalise(raw[6:10] + (1,0,0,0)), opacity = sigmoid(raw[10]), normal = normalise(raw[11:14]),
-    colour = the point's own."""
-    h = np.maximum(np.asarray(f, np.float64) @ W1 + b1, 0.0)
+         point_voxel: np.ndarray, grid: int, coords: np.ndarray) -> dict:
+    """Per-point Gaussians from the level-0 decoder features f (V, 32) by a shared MLP (Section 3.2:
+    the last decoder layer holds the cloud's points and each one's parameters come from its own
+    features). Point i of voxel v = point_voxel[i] (integer coordinates coords[v], (V, 3)) has the
+    input x_i = [f[v], r_i] with r_i = (p_i + 1) grid / 2 - (coords[v] + 0.5), its residual inside
+    the voxel in edges (the per-point attribute that merging points into one voxel averages away).
+    raw_i = relu(x_i W1 + b1) W2 + b2 with W1 (35, 32), W2 (32, 14). Edge e = 2 / grid:
+    mean = p + e tanh(raw[0:3]), scale = e exp(raw[3:6]), q = normalise(raw[6:10] + (1,0,0,0)),
+    opacity = sigmoid(raw[10]), normal = normalise(raw[11:14]), colour = the point's own."""
+    P = np.asarray(points, np.float64)
+    pv = np.asarray(point_voxel)
+    r = (P.T + 1.0) * (grid / 2.0) - (np.asarray(coords, np.float64)[pv] + 0.5)
+    x = np.concatenate([np.asarray(f, np.float64)[pv], r], axis=1)
+    h = np.maximum(x @ W1 + b1, 0.0)
     raw = h @ W2 + b2
     e = 2.0 / grid
     q = raw[:, 6:10] + np.array([1.0, 0.0, 0.0, 0.0])
     q = q / np.linalg.norm(q, axis=1, keepdims=True)
     nrm = raw[:, 11:14] / np.linalg.norm(raw[:, 11:14], axis=1, keepdims=True)
-    pv = point_voxel
-    P = np.asarray(points, np.float64)
-    return dict(raw=raw, mean=P + e * np.tanh(raw[pv, 0:3]).T, scale=(e * np.exp(raw[pv, 3:6])).T,
-                quat=q[pv].T, opacity=1.0 / (1.0 + np.exp(-raw[pv, 10])), rgb=np.asarray(rgb, np.float64),
-                normal=nrm[pv].T)
+    return dict(input=x, raw=raw, mean=P + e * np.tanh(raw[:, 0:3]).T, scale=(e * np.exp(raw[:, 3:6])).T,
+                quat=q.T, opacity=1.0 / (1.0 + np.exp(-raw[:, 10])), rgb=np.asarray(rgb, np.float64),
+                normal=nrm.T)
 
 
 def levels(coords0: np.ndarray, grid: int, depth: int = 3) -> list:

@@ -120,7 +120,7 @@ def load():
     L.pcs_up_conv_forward.argtypes = [c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_i32, c_i32, c_vp, c_vp]
     L.pcs_up_conv_backward.argtypes = [c_vp, c_vp, c_vp, c_i32, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]
     L.pcs_unet_head_forward.argtypes = [c_vp] * 16
-    L.pcs_unet_head_backward.argtypes = [c_vp] * 18
+    L.pcs_unet_head_backward.argtypes = [c_vp] * 19
     L.pcs_knn_pca.argtypes = [c_vp, c_vp, c_i64, c_i32, c_f, c_f, c_vp, c_vp, c_vp, c_vp, c_vp]
     L.pcs_shade.argtypes = [c_vp, ctypes.POINTER(Images), ctypes.POINTER(Camera), c_i32,
                             ctypes.POINTER(Light), ctypes.POINTER(c_f * 3), c_vp, c_vp]

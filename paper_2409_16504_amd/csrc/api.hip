@@ -201,7 +201,7 @@ struct pcs_voxels {
   DevBuf keys, order, flag, excl, start, coords, feat, point_voxel, hkeys, hvals, nbr, centroid;
   // a pooled (parent) voxel set: its "points" are the child voxels (point_voxel maps child ->
   // parent), up_fwd[8][n] and up_bwd[8][V] are the transposed convolution's tables
-  DevBuf up_fwd, up_bwd, centres, mlp_raw;
+  DevBuf up_fwd, up_bwd, centres, head_gh;
   bool pooled = false;
   bool valid = false;
 };
@@ -1124,27 +1124,28 @@ int pcs_unet_head_forward(pcs_context* ctx, const pcs_voxels* vox, const uint16_
   PCS_HIP(hipSetDevice(ctx->device));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   StageTimer tm(ctx, ST_HEAD, s);
-  pcs_voxels* v = const_cast<pcs_voxels*>(vox);
-  PCS_TRY(ensure(ctx, v->mlp_raw, (size_t)std::max<int64_t>(vox->V, 1) * 14 * sizeof(float), "head outputs"));
-  PCS_HIP(launch_mlp_voxels(feat, vox->V, w1, b1, w2, b2, v->mlp_raw.as<float>(), s));
-  PCS_HIP(launch_mlp_points(v->mlp_raw.as<float>(), vox->point_voxel.as<int32_t>(), xyz, rgb, vox->n,
-                            2.0f / (float)vox->grid, mean, quat, scale, opacity, out_rgb, normal, s));
+  PCS_HIP(launch_mlp_points(feat, vox->coords.as<int32_t>(), vox->V, vox->point_voxel.as<int32_t>(), w1, b1, w2,
+                            b2, xyz, rgb, vox->n, vox->grid, mean, quat, scale, opacity, out_rgb, normal, s));
   return PCS_OK;
 }
 
 int pcs_unet_head_backward(pcs_context* ctx, const pcs_voxels* vox, const uint16_t* feat, const float* w1,
-                           const float* b1, const float* w2, const float* b2, const float* d_mean,
-                           const float* d_quat, const float* d_scale, const float* d_opacity,
+                           const float* b1, const float* w2, const float* b2, const float* xyz,
+                           const float* d_mean, const float* d_quat, const float* d_scale, const float* d_opacity,
                            const float* d_normal, uint16_t* d_feat, float* d_w1, float* d_b1, float* d_w2,
                            float* d_b2, void* stream) {
-  if (!ctx || !vox || !vox->valid || !feat || !w1 || !b1 || !w2 || !b2 || !d_feat || !d_w1 || !d_b1 ||
+  if (!ctx || !vox || !vox->valid || !feat || !w1 || !b1 || !w2 || !b2 || !xyz || !d_feat || !d_w1 || !d_b1 ||
       !d_w2 || !d_b2)
     return fail(PCS_ERR_INVALID_ARG, "NULL argument or empty voxels");
   PCS_HIP(hipSetDevice(ctx->device));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   StageTimer tm(ctx, ST_HEAD_BWD, s);
-  PCS_HIP(launch_mlp_backward(feat, w1, b1, w2, b2, vox->order.as<uint32_t>(), vox->start.as<uint32_t>(), vox->V,
-                              vox->n, 2.0f / (float)vox->grid, d_mean, d_quat, d_scale, d_opacity, d_normal,
+  pcs_voxels* v = const_cast<pcs_voxels*>(vox);
+  PCS_TRY(ensure(ctx, v->head_gh, (size_t)std::max<int64_t>(vox->n, 1) * 32 * sizeof(float),
+                 "head hidden-layer gradients"));
+  PCS_HIP(launch_mlp_backward(feat, vox->coords.as<int32_t>(), vox->V, vox->point_voxel.as<int32_t>(),
+                              vox->order.as<uint32_t>(), vox->start.as<uint32_t>(), w1, b1, w2, b2, xyz, vox->n,
+                              vox->grid, d_mean, d_quat, d_scale, d_opacity, d_normal, v->head_gh.as<float>(),
                               d_feat, d_w1, d_b1, d_w2, d_b2, s));
   return PCS_OK;
 }

@@ -324,17 +324,16 @@ hipError_t launch_pool_features(const uint32_t* order, const uint32_t* start, in
                                 const uint16_t* child, int C, uint16_t* parent, hipStream_t s);
 hipError_t launch_pool_features_bwd(const int32_t* parent_of, const uint32_t* start, int64_t Vp, int64_t Vc,
                                     const uint16_t* dparent, int C, uint16_t* dchild, hipStream_t s);
-hipError_t launch_mlp_voxels(const uint16_t* feat, int64_t V, const float* w1, const float* b1,
-                             const float* w2, const float* b2, float* raw, hipStream_t s);
-hipError_t launch_mlp_points(const float* raw, const int32_t* point_voxel, const float* xyz, const float* rgb,
-                             int64_t n, float voxel, float* mean, float* quat, float* scale, float* opac,
-                             float* out_rgb, float* normal, hipStream_t s);
-hipError_t launch_mlp_backward(const uint16_t* feat, const float* w1, const float* b1, const float* w2,
-                               const float* b2, const uint32_t* order, const uint32_t* start, int64_t V,
-                               int64_t n, float voxel, const float* d_mean, const float* d_quat,
-                               const float* d_scale, const float* d_opac, const float* d_normal,
-                               uint16_t* d_feat, float* d_w1, float* d_b1, float* d_w2, float* d_b2,
-                               hipStream_t s);
+hipError_t launch_mlp_points(const uint16_t* feat, const int32_t* coords, int64_t V, const int32_t* point_voxel,
+                             const float* w1, const float* b1, const float* w2, const float* b2,
+                             const float* xyz, const float* rgb, int64_t n, int grid, float* mean, float* quat,
+                             float* scale, float* opac, float* out_rgb, float* normal, hipStream_t s);
+hipError_t launch_mlp_backward(const uint16_t* feat, const int32_t* coords, int64_t V, const int32_t* point_voxel,
+                               const uint32_t* order, const uint32_t* start, const float* w1, const float* b1,
+                               const float* w2, const float* b2, const float* xyz, int64_t n, int grid,
+                               const float* d_mean, const float* d_quat, const float* d_scale,
+                               const float* d_opac, const float* d_normal, float* gh, uint16_t* d_feat,
+                               float* d_w1, float* d_b1, float* d_w2, float* d_b2, hipStream_t s);
 hipError_t launch_relu_mask(const uint16_t* y, const uint16_t* dy, int64_t count, uint16_t* out,
                             hipStream_t s);
 hipError_t launch_bias_grad(const uint16_t* dy, int64_t V, int cout, float* db, hipStream_t s);

@@ -579,59 +579,51 @@ __global__ __launch_bounds__(256) void k_head_backward(
 // raw = W2 relu(W1 f + b1) + b2 per voxel (32 -> 32 -> 14, FP32), then per point: offset
 // delta = voxel tanh(raw[0:3]) (within one voxel edge), scale = voxel exp(raw[3:6]),
 // q = normalise(raw[6:10] + (1,0,0,0)), opacity = sigmoid(raw[10]), normal = normalise(raw[11:14]).
-constexpr int kMlpIn = 32, kMlpHidden = 32, kMlpOut = 14;
+// ---- the UNet's head: a shared MLP per point --------------------------------------------------
+// Input of point i: the 32 decoder features of its voxel and its own coordinate residual (in voxel
+// edges, as the voxelisation computes it), 35 values; ReLU hidden layer of 32; 14 outputs
+// (offset 3, log-scale 3, rotation 4, opacity 1, normal 3), activated per point.
+constexpr int kMlpFeat = 32, kMlpIn = 35, kMlpHidden = 32, kMlpOut = 14;
 
-__device__ __forceinline__ void load_feat32(const uint16_t* __restrict__ f, float (&fv)[kMlpIn]) {
-  const uint4* src = reinterpret_cast<const uint4*>(f);
+__device__ __forceinline__ void load_feat32(const uint16_t* __restrict__ f, float* fv) {
+  const uint4* q4 = reinterpret_cast<const uint4*>(f);
 #pragma unroll
-  for (int q = 0; q < kMlpIn / 8; ++q) {
-    const uint4 w = src[q];
-    const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+  for (int q = 0; q < kMlpFeat / 8; ++q) {
+    const uint4 w = q4[q];
+    const uint32_t u[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      fv[8 * q + 2 * e] = bf16_to_f32((uint16_t)(ws[e] & 0xFFFF));
-      fv[8 * q + 2 * e + 1] = bf16_to_f32((uint16_t)(ws[e] >> 16));
+    for (int t = 0; t < 4; ++t) {
+      fv[8 * q + 2 * t] = __uint_as_float(u[t] << 16);
+      fv[8 * q + 2 * t + 1] = __uint_as_float(u[t] & 0xFFFF0000u);
     }
   }
 }
 
-__device__ __forceinline__ void mlp_forward(const float (&fv)[kMlpIn], const float* s_w1, const float* s_b1,
+// The MLP input of point i in voxel v.
+__device__ __forceinline__ void point_input(const uint16_t* __restrict__ feat, const int32_t* __restrict__ coords,
+                                            int64_t V, const float* __restrict__ xyz, int64_t n, int64_t i,
+                                            int32_t v, float half, float (&in)[kMlpIn]) {
+  load_feat32(feat + (int64_t)v * kMlpFeat, in);
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    in[kMlpFeat + k] = (xyz[k * n + i] + 1.0f) * half - ((float)coords[k * V + v] + 0.5f);
+}
+
+__device__ __forceinline__ void mlp_forward(const float (&in)[kMlpIn], const float* s_w1, const float* s_b1,
                                             const float* s_w2, const float* s_b2, float (&h)[kMlpHidden],
                                             float (&raw)[kMlpOut]) {
 #pragma unroll
+  for (int o = 0; o < kMlpOut; ++o) raw[o] = s_b2[o];
+#pragma unroll 4
   for (int j = 0; j < kMlpHidden; ++j) {
     float a = s_b1[j];
 #pragma unroll
-    for (int c = 0; c < kMlpIn; ++c) a = fmaf(s_w1[j * kMlpIn + c], fv[c], a);
-    h[j] = fmaxf(a, 0.0f);
+    for (int c = 0; c < kMlpIn; ++c) a = fmaf(s_w1[j * kMlpIn + c], in[c], a);
+    a = fmaxf(a, 0.0f);
+    h[j] = a;
+#pragma unroll
+    for (int o = 0; o < kMlpOut; ++o) raw[o] = fmaf(s_w2[o * kMlpHidden + j], a, raw[o]);
   }
-#pragma unroll
-  for (int o = 0; o < kMlpOut; ++o) {
-    float a = s_b2[o];
-#pragma unroll
-    for (int j = 0; j < kMlpHidden; ++j) a = fmaf(s_w2[o * kMlpHidden + j], h[j], a);
-    raw[o] = a;
-  }
-}
-
-// One thread per voxel: raw[V][14] (FP32).
-__global__ __launch_bounds__(256) void k_mlp_voxels(const uint16_t* __restrict__ feat, int64_t V,
-                                                    const float* __restrict__ w1, const float* __restrict__ b1,
-                                                    const float* __restrict__ w2, const float* __restrict__ b2,
-                                                    float* __restrict__ raw) {
-  __shared__ float s_w1[kMlpHidden * kMlpIn], s_b1[kMlpHidden], s_w2[kMlpOut * kMlpHidden], s_b2[kMlpOut];
-  for (int i = threadIdx.x; i < kMlpHidden * kMlpIn; i += blockDim.x) s_w1[i] = w1[i];
-  for (int i = threadIdx.x; i < kMlpOut * kMlpHidden; i += blockDim.x) s_w2[i] = w2[i];
-  if (threadIdx.x < kMlpHidden) s_b1[threadIdx.x] = b1[threadIdx.x];
-  if (threadIdx.x < kMlpOut) s_b2[threadIdx.x] = b2[threadIdx.x];
-  __syncthreads();
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= V) return;
-  float fv[kMlpIn], h[kMlpHidden], r[kMlpOut];
-  load_feat32(feat + v * kMlpIn, fv);
-  mlp_forward(fv, s_w1, s_b1, s_w2, s_b2, h, r);
-#pragma unroll
-  for (int o = 0; o < kMlpOut; ++o) raw[v * kMlpOut + o] = r[o];
 }
 
 struct MlpAct {
@@ -658,19 +650,77 @@ __device__ __forceinline__ MlpAct mlp_activate(const float* r, float voxel) {
   return a;
 }
 
-// One thread per point: its voxel's activated outputs; mean = point + offset, colour = the point's.
-__global__ __launch_bounds__(256) void k_mlp_points(const float* __restrict__ raw, const int32_t* __restrict__ point_voxel,
+// Gradient of the raw outputs from point i's upstream gradients through the activations.
+__device__ __forceinline__ void mlp_act_grad(const MlpAct& a, float voxel, int64_t i, int64_t n,
+                                             const float* __restrict__ d_mean, const float* __restrict__ d_quat,
+                                             const float* __restrict__ d_scale, const float* __restrict__ d_opac,
+                                             const float* __restrict__ d_normal, float (&g)[kMlpOut]) {
+  float gm[3] = {0.f, 0.f, 0.f}, gs[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f}, go = 0.f;
+  float gn[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (d_mean) gm[k] = d_mean[k * n + i];
+    if (d_scale) gs[k] = d_scale[k * n + i];
+    if (d_normal) gn[k] = d_normal[k * n + i];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (d_quat) gq[k] = d_quat[k * n + i];
+  if (d_opac) go = d_opac[i];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    g[k] = gm[k] * voxel * (1.0f - a.th[k] * a.th[k]);
+    g[3 + k] = gs[k] * a.scale[k];
+  }
+  const float dq = a.q[0] * gq[0] + a.q[1] * gq[1] + a.q[2] * gq[2] + a.q[3] * gq[3];
+  const float iq = a.qn > 0.0f ? 1.0f / a.qn : 0.0f;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) g[6 + k] = (gq[k] - a.q[k] * dq) * iq;
+  g[10] = go * a.opacity * (1.0f - a.opacity);
+  const float dn = a.n[0] * gn[0] + a.n[1] * gn[1] + a.n[2] * gn[2];
+  const float in = a.nn > 0.0f ? 1.0f / a.nn : 0.0f;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) g[11 + k] = (gn[k] - a.n[k] * dn) * in;
+}
+
+// The hidden layer's gradient (after the ReLU) from the raw outputs' gradient.
+__device__ __forceinline__ void mlp_hidden_grad(const float (&h)[kMlpHidden], const float (&g)[kMlpOut],
+                                                const float* s_w2, float (&gh)[kMlpHidden]) {
+#pragma unroll
+  for (int j = 0; j < kMlpHidden; ++j) {
+    float t = 0.f;
+#pragma unroll
+    for (int o = 0; o < kMlpOut; ++o) t = fmaf(s_w2[o * kMlpHidden + j], g[o], t);
+    gh[j] = h[j] > 0.0f ? t : 0.0f;
+  }
+}
+
+#define PCS_MLP_WEIGHTS_TO_LDS(NT)                                                                  \
+  __shared__ float s_w1[kMlpHidden * kMlpIn], s_b1[kMlpHidden], s_w2[kMlpOut * kMlpHidden], s_b2[kMlpOut]; \
+  for (int t_ = threadIdx.x; t_ < kMlpHidden * kMlpIn; t_ += (NT)) s_w1[t_] = w1[t_];              \
+  for (int t_ = threadIdx.x; t_ < kMlpOut * kMlpHidden; t_ += (NT)) s_w2[t_] = w2[t_];             \
+  if (threadIdx.x < kMlpHidden) s_b1[threadIdx.x] = b1[threadIdx.x];                               \
+  if (threadIdx.x < kMlpOut) s_b2[threadIdx.x] = b2[threadIdx.x];                                  \
+  __syncthreads();
+
+// One thread per point: the MLP on its input, activated; mean = point + offset, colour = the
+// point's own.
+__global__ __launch_bounds__(256) void k_mlp_points(const uint16_t* __restrict__ feat, const int32_t* __restrict__ coords,
+                                                    int64_t V, const int32_t* __restrict__ point_voxel,
+                                                    const float* __restrict__ w1, const float* __restrict__ b1,
+                                                    const float* __restrict__ w2, const float* __restrict__ b2,
                                                     const float* __restrict__ xyz, const float* __restrict__ rgb,
-                                                    int64_t n, float voxel, float* __restrict__ mean,
+                                                    int64_t n, int grid, float* __restrict__ mean,
                                                     float* __restrict__ quat, float* __restrict__ scale,
                                                     float* __restrict__ opac, float* __restrict__ out_rgb,
                                                     float* __restrict__ normal) {
+  PCS_MLP_WEIGHTS_TO_LDS(256)
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int32_t v = point_voxel[i];
-  float r[kMlpOut];
-#pragma unroll
-  for (int o = 0; o < kMlpOut; ++o) r[o] = raw[(int64_t)v * kMlpOut + o];
+  const float half = 0.5f * (float)grid, voxel = 2.0f / (float)grid;
+  float in[kMlpIn], h[kMlpHidden], r[kMlpOut];
+  point_input(feat, coords, V, xyz, n, i, point_voxel[i], half, in);
+  mlp_forward(in, s_w1, s_b1, s_w2, s_b2, h, r);
   const MlpAct a = mlp_activate(r, voxel);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -684,117 +734,56 @@ __global__ __launch_bounds__(256) void k_mlp_points(const float* __restrict__ ra
   opac[i] = a.opacity;
 }
 
-// Per voxel: the per-point gradients of (mean, quat, scale, opacity, normal) summed over its points
-// (contiguous in voxel order), through the activations to raw, then through the MLP (recomputed)
-// to the features. A block of kMlpBwdThreads voxels keeps each voxel's input, hidden activations
-// and the two layers' output gradients in LDS; the weight gradients are then the block's sums of
-// outer products, one weight element per thread at a time, added once per block.
+// Weight gradients of the head: one row per point, points taken in voxel order (row p is point
+// order[p]), kMlpBwdThreads rows per block. Each thread recomputes its point's input, hidden layer
+// and outputs, keeps the input, the hidden values and both layers' output gradients in LDS, and
+// stores the hidden-layer gradient to gh[p][32] for the feature gradients. The weight gradients are
+// the block's sums of outer products, one weight element per thread at a time, added once per block.
 constexpr int kMlpBwdThreads = 128;
-constexpr int kMlpRow = 33;                      // padded LDS rows
-__global__ __launch_bounds__(kMlpBwdThreads) void k_mlp_backward(
-    const uint16_t* __restrict__ feat, const float* __restrict__ w1, const float* __restrict__ b1,
-    const float* __restrict__ w2, const float* __restrict__ b2, const uint32_t* __restrict__ order,
-    const uint32_t* __restrict__ start, int64_t V, int64_t n, float voxel, const float* __restrict__ d_mean,
+constexpr int kMlpRowIn = 37, kMlpRow = 33;      // padded LDS rows
+__global__ __launch_bounds__(kMlpBwdThreads) void k_mlp_wgrad(
+    const uint16_t* __restrict__ feat, const int32_t* __restrict__ coords, int64_t V,
+    const int32_t* __restrict__ point_voxel, const uint32_t* __restrict__ order, const float* __restrict__ w1,
+    const float* __restrict__ b1, const float* __restrict__ w2, const float* __restrict__ b2,
+    const float* __restrict__ xyz, int64_t n, int grid, const float* __restrict__ d_mean,
     const float* __restrict__ d_quat, const float* __restrict__ d_scale, const float* __restrict__ d_opac,
-    const float* __restrict__ d_normal, uint16_t* __restrict__ d_feat, float* __restrict__ d_w1,
+    const float* __restrict__ d_normal, float* __restrict__ gh_out, float* __restrict__ d_w1,
     float* __restrict__ d_b1, float* __restrict__ d_w2, float* __restrict__ d_b2) {
-  __shared__ float s_w1[kMlpHidden * kMlpIn], s_b1[kMlpHidden], s_w2[kMlpOut * kMlpHidden], s_b2[kMlpOut];
-  __shared__ float s_f[kMlpBwdThreads * kMlpRow], s_h[kMlpBwdThreads * kMlpRow];
+  PCS_MLP_WEIGHTS_TO_LDS(kMlpBwdThreads)
+  __shared__ float s_f[kMlpBwdThreads * kMlpRowIn], s_h[kMlpBwdThreads * kMlpRow];
   __shared__ float s_gh[kMlpBwdThreads * kMlpRow], s_g[kMlpBwdThreads * 15];
   const int tid = threadIdx.x;
-  for (int i = tid; i < kMlpHidden * kMlpIn; i += kMlpBwdThreads) s_w1[i] = w1[i];
-  for (int i = tid; i < kMlpOut * kMlpHidden; i += kMlpBwdThreads) s_w2[i] = w2[i];
-  if (tid < kMlpHidden) s_b1[tid] = b1[tid];
-  if (tid < kMlpOut) s_b2[tid] = b2[tid];
-  __syncthreads();
-  const int64_t v = (int64_t)blockIdx.x * kMlpBwdThreads + tid;
-  float* F = s_f + tid * kMlpRow;
+  const int64_t p = (int64_t)blockIdx.x * kMlpBwdThreads + tid;
+  float* F = s_f + tid * kMlpRowIn;
   float* Hh = s_h + tid * kMlpRow;
   float* GH = s_gh + tid * kMlpRow;
   float* G = s_g + tid * 15;
-  if (v < V) {
-    float fv[kMlpIn];
-    load_feat32(feat + v * kMlpIn, fv);
-    float r[kMlpOut];
-#pragma unroll
-    for (int o = 0; o < kMlpOut; ++o) r[o] = s_b2[o];
-#pragma unroll 4
-    for (int j = 0; j < kMlpHidden; ++j) {
-      float a = s_b1[j];
-#pragma unroll
-      for (int c = 0; c < kMlpIn; ++c) a = fmaf(s_w1[j * kMlpIn + c], fv[c], a);
-      a = fmaxf(a, 0.0f);
-      Hh[j] = a;
-#pragma unroll
-      for (int o = 0; o < kMlpOut; ++o) r[o] = fmaf(s_w2[o * kMlpHidden + j], a, r[o]);
-    }
-#pragma unroll
-    for (int c = 0; c < kMlpIn; ++c) F[c] = fv[c];
+  if (p < n) {
+    const int64_t i = order[p];
+    const float half = 0.5f * (float)grid, voxel = 2.0f / (float)grid;
+    float in[kMlpIn], h[kMlpHidden], r[kMlpOut], g[kMlpOut], gh[kMlpHidden];
+    point_input(feat, coords, V, xyz, n, i, point_voxel[i], half, in);
+    mlp_forward(in, s_w1, s_b1, s_w2, s_b2, h, r);
     const MlpAct a = mlp_activate(r, voxel);
-    float gm[3] = {0.f, 0.f, 0.f}, gs[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f}, go = 0.f;
-    float gn[3] = {0.f, 0.f, 0.f};
-    const uint32_t b = start[v], e = v + 1 < V ? start[v + 1] : (uint32_t)n;
-    for (uint32_t j = b; j < e; ++j) {
-      const uint32_t i = order[j];
+    mlp_act_grad(a, voxel, i, n, d_mean, d_quat, d_scale, d_opac, d_normal, g);
+    mlp_hidden_grad(h, g, s_w2, gh);
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        if (d_mean) gm[k] += d_mean[k * n + i];
-        if (d_scale) gs[k] += d_scale[k * n + i];
-        if (d_normal) gn[k] += d_normal[k * n + i];
-      }
+    for (int c = 0; c < kMlpIn; ++c) F[c] = in[c];
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (d_quat) gq[k] += d_quat[k * n + i];
-      if (d_opac) go += d_opac[i];
-    }
-    float g[kMlpOut];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      g[k] = gm[k] * voxel * (1.0f - a.th[k] * a.th[k]);
-      g[3 + k] = gs[k] * a.scale[k];
-    }
-    const float dq = a.q[0] * gq[0] + a.q[1] * gq[1] + a.q[2] * gq[2] + a.q[3] * gq[3];
-    const float iq = a.qn > 0.0f ? 1.0f / a.qn : 0.0f;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) g[6 + k] = (gq[k] - a.q[k] * dq) * iq;
-    g[10] = go * a.opacity * (1.0f - a.opacity);
-    const float dn = a.n[0] * gn[0] + a.n[1] * gn[1] + a.n[2] * gn[2];
-    const float in = a.nn > 0.0f ? 1.0f / a.nn : 0.0f;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) g[11 + k] = (gn[k] - a.n[k] * dn) * in;
+    for (int j = 0; j < kMlpHidden; ++j) { Hh[j] = h[j]; GH[j] = gh[j]; }
 #pragma unroll
     for (int o = 0; o < kMlpOut; ++o) G[o] = g[o];
-    // through the second layer and the ReLU, then the first layer to the features
-    float df[kMlpIn];
+    float4* dst = reinterpret_cast<float4*>(gh_out + p * kMlpHidden);
 #pragma unroll
-    for (int c = 0; c < kMlpIn; ++c) df[c] = 0.0f;
-#pragma unroll 4
-    for (int j = 0; j < kMlpHidden; ++j) {
-      float t = 0.f;
-#pragma unroll
-      for (int o = 0; o < kMlpOut; ++o) t = fmaf(s_w2[o * kMlpHidden + j], g[o], t);
-      t = Hh[j] > 0.0f ? t : 0.0f;
-      GH[j] = t;
-#pragma unroll
-      for (int c = 0; c < kMlpIn; ++c) df[c] = fmaf(s_w1[j * kMlpIn + c], t, df[c]);
-    }
-#pragma unroll
-    for (int c = 0; c < kMlpIn; c += 8) {
-      uint4 w;
-      w.x = f32_to_bf16(df[c]) | ((uint32_t)f32_to_bf16(df[c + 1]) << 16);
-      w.y = f32_to_bf16(df[c + 2]) | ((uint32_t)f32_to_bf16(df[c + 3]) << 16);
-      w.z = f32_to_bf16(df[c + 4]) | ((uint32_t)f32_to_bf16(df[c + 5]) << 16);
-      w.w = f32_to_bf16(df[c + 6]) | ((uint32_t)f32_to_bf16(df[c + 7]) << 16);
-      *reinterpret_cast<uint4*>(d_feat + v * kMlpIn + c) = w;
-    }
+    for (int j = 0; j < kMlpHidden; j += 4) dst[j / 4] = make_float4(gh[j], gh[j + 1], gh[j + 2], gh[j + 3]);
   } else {
-    // rows of voxels past the end add nothing to the sums
-    for (int c = 0; c < kMlpRow; ++c) { F[c] = 0.f; Hh[c] = 0.f; GH[c] = 0.f; }
+    // rows past the last point add nothing to the sums
+    for (int c = 0; c < kMlpRowIn; ++c) F[c] = 0.f;
+    for (int c = 0; c < kMlpRow; ++c) { Hh[c] = 0.f; GH[c] = 0.f; }
     for (int o = 0; o < 15; ++o) G[o] = 0.f;
   }
   __syncthreads();
-  // weight gradients: dW2[o][j] = sum_v G[v][o] H[v][j], dW1[j][c] = sum_v GH[v][j] F[v][c], and the
-  // biases, each element summed over the block's voxels by one thread
+  // dW2[o][j] = sum G[o] H[j], dW1[j][c] = sum GH[j] F[c], and the biases
   constexpr int kW2 = kMlpOut * kMlpHidden, kW1 = kMlpHidden * kMlpIn;
   for (int el = tid; el < kW2 + kW1 + kMlpOut + kMlpHidden; el += kMlpBwdThreads) {
     float acc = 0.f;
@@ -804,7 +793,7 @@ __global__ __launch_bounds__(kMlpBwdThreads) void k_mlp_backward(
       if (acc != 0.0f) unsafeAtomicAdd(&d_w2[el], acc);
     } else if (el < kW2 + kW1) {
       const int e2 = el - kW2, j = e2 / kMlpIn, c = e2 % kMlpIn;
-      for (int u = 0; u < kMlpBwdThreads; ++u) acc = fmaf(s_gh[u * kMlpRow + j], s_f[u * kMlpRow + c], acc);
+      for (int u = 0; u < kMlpBwdThreads; ++u) acc = fmaf(s_gh[u * kMlpRow + j], s_f[u * kMlpRowIn + c], acc);
       if (acc != 0.0f) unsafeAtomicAdd(&d_w1[e2], acc);
     } else if (el < kW2 + kW1 + kMlpOut) {
       const int o = el - kW2 - kW1;
@@ -815,6 +804,47 @@ __global__ __launch_bounds__(kMlpBwdThreads) void k_mlp_backward(
       for (int u = 0; u < kMlpBwdThreads; ++u) acc += s_gh[u * kMlpRow + j];
       if (acc != 0.0f) unsafeAtomicAdd(&d_b1[j], acc);
     }
+  }
+}
+
+// Feature gradients of the head: one thread per voxel sums the hidden-layer gradients of its points
+// (rows start[v] .. start[v+1] of gh, voxel order) and maps the sum through the feature columns of
+// the first layer: d feat = W1[:, :32]^T sum_i gh_i (the residual columns give no feature gradient).
+__global__ __launch_bounds__(256) void k_mlp_dfeat(const float* __restrict__ gh, const uint32_t* __restrict__ start,
+                                                   int64_t V, int64_t n, const float* __restrict__ w1,
+                                                   uint16_t* __restrict__ d_feat) {
+  __shared__ float s_w1[kMlpHidden * kMlpIn];
+  for (int t = threadIdx.x; t < kMlpHidden * kMlpIn; t += 256) s_w1[t] = w1[t];
+  __syncthreads();
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  float sgh[kMlpHidden];
+#pragma unroll
+  for (int j = 0; j < kMlpHidden; ++j) sgh[j] = 0.0f;
+  const uint32_t b = start[v], e = v + 1 < V ? start[v + 1] : (uint32_t)n;
+  for (uint32_t p = b; p < e; ++p) {
+    const float4* row = reinterpret_cast<const float4*>(gh + (int64_t)p * kMlpHidden);
+#pragma unroll
+    for (int j = 0; j < kMlpHidden; j += 4) {
+      const float4 t = row[j / 4];
+      sgh[j] += t.x; sgh[j + 1] += t.y; sgh[j + 2] += t.z; sgh[j + 3] += t.w;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < kMlpFeat; c += 8) {
+    float df[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) df[t] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < kMlpHidden; ++j)
+#pragma unroll
+      for (int t = 0; t < 8; ++t) df[t] = fmaf(s_w1[j * kMlpIn + c + t], sgh[j], df[t]);
+    uint4 w;
+    w.x = f32_to_bf16(df[0]) | ((uint32_t)f32_to_bf16(df[1]) << 16);
+    w.y = f32_to_bf16(df[2]) | ((uint32_t)f32_to_bf16(df[3]) << 16);
+    w.z = f32_to_bf16(df[4]) | ((uint32_t)f32_to_bf16(df[5]) << 16);
+    w.w = f32_to_bf16(df[6]) | ((uint32_t)f32_to_bf16(df[7]) << 16);
+    *reinterpret_cast<uint4*>(d_feat + v * kMlpFeat + c) = w;
   }
 }
 
@@ -972,33 +1002,29 @@ hipError_t launch_subm_conv_dw(const uint16_t* x, int cin, const uint16_t* dy, i
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_mlp_voxels(const uint16_t* feat, int64_t V, const float* w1, const float* b1,
-                             const float* w2, const float* b2, float* raw, hipStream_t s) {
-  if (V == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mlp_voxels, dim3(blocks_for(V, 256)), dim3(256), 0, s, feat, V, w1, b1, w2, b2, raw);
-  return hipGetLastError();
-}
-
-hipError_t launch_mlp_points(const float* raw, const int32_t* point_voxel, const float* xyz, const float* rgb,
-                             int64_t n, float voxel, float* mean, float* quat, float* scale, float* opac,
-                             float* out_rgb, float* normal, hipStream_t s) {
+hipError_t launch_mlp_points(const uint16_t* feat, const int32_t* coords, int64_t V, const int32_t* point_voxel,
+                             const float* w1, const float* b1, const float* w2, const float* b2,
+                             const float* xyz, const float* rgb, int64_t n, int grid, float* mean, float* quat,
+                             float* scale, float* opac, float* out_rgb, float* normal, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mlp_points, dim3(blocks_for(n, 256)), dim3(256), 0, s, raw, point_voxel, xyz, rgb, n,
-                     voxel, mean, quat, scale, opac, out_rgb, normal);
+  hipLaunchKernelGGL(k_mlp_points, dim3(blocks_for(n, 256)), dim3(256), 0, s, feat, coords, V, point_voxel, w1,
+                     b1, w2, b2, xyz, rgb, n, grid, mean, quat, scale, opac, out_rgb, normal);
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_backward(const uint16_t* feat, const float* w1, const float* b1, const float* w2,
-                               const float* b2, const uint32_t* order, const uint32_t* start, int64_t V,
-                               int64_t n, float voxel, const float* d_mean, const float* d_quat,
-                               const float* d_scale, const float* d_opac, const float* d_normal,
-                               uint16_t* d_feat, float* d_w1, float* d_b1, float* d_w2, float* d_b2,
-                               hipStream_t s) {
-  if (V == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mlp_backward, dim3(blocks_for(V, kMlpBwdThreads)), dim3(kMlpBwdThreads), 0, s, feat, w1,
-                     b1, w2, b2, order,
-                     start, V, n, voxel, d_mean, d_quat, d_scale, d_opac, d_normal, d_feat, d_w1, d_b1, d_w2,
-                     d_b2);
+hipError_t launch_mlp_backward(const uint16_t* feat, const int32_t* coords, int64_t V, const int32_t* point_voxel,
+                               const uint32_t* order, const uint32_t* start, const float* w1, const float* b1,
+                               const float* w2, const float* b2, const float* xyz, int64_t n, int grid,
+                               const float* d_mean, const float* d_quat, const float* d_scale,
+                               const float* d_opac, const float* d_normal, float* gh, uint16_t* d_feat,
+                               float* d_w1, float* d_b1, float* d_w2, float* d_b2, hipStream_t s) {
+  if (V == 0 || n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mlp_wgrad, dim3(blocks_for(n, kMlpBwdThreads)), dim3(kMlpBwdThreads), 0, s, feat, coords,
+                     V, point_voxel, order, w1, b1, w2, b2, xyz, n, grid, d_mean, d_quat, d_scale, d_opac, d_normal,
+                     gh, d_w1, d_b1, d_w2, d_b2);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mlp_dfeat, dim3(blocks_for(V, 256)), dim3(256), 0, s, gh, start, V, n, w1, d_feat);
   return hipGetLastError();
 }
 

@@ -165,6 +165,12 @@ class SparseEstimator:
         self.bh[0:3] = math.log(2.3)            # initial scale ~2.3 voxels
         self.params = self.w + self.b + [self.wh, self.bh]
 
+    def load_params(self, params: list):
+        """Copy saved parameters (order of ``params``)."""
+        with torch.no_grad():
+            for p, v in zip(self.params, params):
+                p.copy_(v.to(p.device))
+
     def bf16_weights(self):
         return [w.to(torch.bfloat16).contiguous() for w in self.w]
 
@@ -272,6 +278,7 @@ UNET_LAYOUT = [
     ("u1", "up", 64, 32), ("d0", "subm", 64, 32),
 ]
 UNET_HEAD_HIDDEN, UNET_HEAD_OUT = 32, 14
+UNET_HEAD_IN = 35         # per point: its voxel's 32 decoder features and its own residual (3)
 
 
 def pool(R: Renderer, child: Voxels) -> Voxels:
@@ -327,11 +334,11 @@ def unet_head_forward(R: Renderer, vox: Voxels, f, w1, b1, w2, b2, xyz, rgb) -> 
     return g
 
 
-def unet_head_backward(R: Renderer, vox: Voxels, f, w1, b1, w2, b2, grads: dict, dws: list) -> torch.Tensor:
+def unet_head_backward(R: Renderer, vox: Voxels, f, w1, b1, w2, b2, xyz, grads: dict, dws: list) -> torch.Tensor:
     df = torch.empty((vox.V, 32), device=f.device, dtype=torch.bfloat16)
     c = {k: (grads[k].contiguous() if grads.get(k) is not None else None)
          for k in ("mean", "quat", "scale", "opacity", "normal")}
-    check(_lib.load().pcs_unet_head_backward(R.ctx, vox.handle, _p(f), _p(w1), _p(b1), _p(w2), _p(b2),
+    check(_lib.load().pcs_unet_head_backward(R.ctx, vox.handle, _p(f), _p(w1), _p(b1), _p(w2), _p(b2), _p(xyz),
                                              _p(c["mean"]), _p(c["quat"]), _p(c["scale"]), _p(c["opacity"]),
                                              _p(c["normal"]), _p(df), *(_p(t) for t in dws), _s()))
     return df
@@ -343,8 +350,11 @@ class UNetEstimator:
     offset, scale, rotation, opacity and normal. FP32 master weights, BF16 copies for the MFMA
     kernels; the head runs in FP32."""
 
-    def __init__(self, renderer: Renderer, seed: int = 0, opacity_init: float = 0.9):
+    def __init__(self, renderer: Renderer, seed: int = 0, opacity_init: float = 0.9, head_residual: bool = True):
+        """``head_residual`` False holds the head's weights on the point's residual at zero, so every
+        point of a voxel gets the same parameters."""
         self.R = renderer
+        self.head_residual = head_residual
         dev = torch.device("cuda", renderer.device)
         gen = torch.Generator(device="cpu").manual_seed(seed)
         self.w, self.b = {}, {}
@@ -356,7 +366,9 @@ class UNetEstimator:
                 w[:, :, UNET_IN_CHANNELS:] = 0.0
             self.w[name] = w.to(dev)
             self.b[name] = torch.zeros(cout, device=dev)
-        self.w1 = (torch.randn((UNET_HEAD_HIDDEN, 32), generator=gen) * math.sqrt(2.0 / 32)).to(dev)
+        self.w1 = (torch.randn((UNET_HEAD_HIDDEN, UNET_HEAD_IN), generator=gen) * math.sqrt(2.0 / UNET_HEAD_IN)).to(dev)
+        if not head_residual:
+            self.w1[:, 32:] = 0.0
         self.b1 = torch.zeros(UNET_HEAD_HIDDEN, device=dev)
         w2 = torch.randn((UNET_HEAD_OUT, UNET_HEAD_HIDDEN), generator=gen) * 1e-3
         w2[11:14] = torch.randn((3, UNET_HEAD_HIDDEN), generator=gen) * 0.1    # varied initial normals
@@ -366,6 +378,18 @@ class UNetEstimator:
         self.b2[10] = math.log(opacity_init / (1.0 - opacity_init))
         names = [n for n, *_ in UNET_LAYOUT]
         self.params = [self.w[n] for n in names] + [self.b[n] for n in names] + [self.w1, self.b1, self.w2, self.b2]
+
+    def load_params(self, params: list):
+        """Copy saved parameters (order of ``params``). A head saved with only the 32 feature
+        inputs gets zero weights on the residual inputs, which makes it the same per-voxel head."""
+        with torch.no_grad():
+            for p, v in zip(self.params, params):
+                v = v.to(p.device)
+                if p is self.w1 and v.shape[1] < p.shape[1]:
+                    p.zero_()
+                    p[:, :v.shape[1]] = v
+                else:
+                    p.copy_(v)
 
     def _bf16_weights(self) -> dict:
         """BF16 copies of the convolution weights, made again only for weights changed in place
@@ -424,7 +448,9 @@ class UNetEstimator:
         dw = {n: torch.zeros_like(w) for n, w in self.w.items()}
         db = {n: torch.zeros_like(b) for n, b in self.b.items()}
         dh = [torch.zeros_like(t) for t in (self.w1, self.b1, self.w2, self.b2)]
-        g = unet_head_backward(R, lv[0], a["d0"], self.w1, self.b1, self.w2, self.b2, grads, dh)
+        g = unet_head_backward(R, lv[0], a["d0"], self.w1, self.b1, self.w2, self.b2, lv[0].xyz, grads, dh)
+        if not self.head_residual:
+            dh[0][:, 32:] = 0.0
 
         def conv_b(name, level, dy, want_dx=True):
             return conv_backward(R, lv[level], a[name + ":in"], wb[name], a[name], dy, want_dx=want_dx,

@@ -138,6 +138,10 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--out", default=None)
     ap.add_argument("--curve", action="store_true", help="also the PSNR-versus-density curve")
+    ap.add_argument("--no-head-residual", action="store_true",
+                    help="hold the head's residual-input weights at zero (one set of parameters per voxel)")
+    ap.add_argument("--keep-frac", type=float, default=0.0,
+                    help="fraction of training inputs left at full density (the rest are downsampled)")
     args = ap.parse_args(argv)
 
     R = Renderer(0)
@@ -166,7 +170,7 @@ def main(argv=None):
     sigma_factor = max(sscores, key=sscores.get)
     print(f"[unet] kappa {scores} -> {kappa}; global sigma {sscores} -> {sigma_factor}", flush=True)
 
-    est = UNetEstimator(R, seed=0)
+    est = UNetEstimator(R, seed=0, head_residual=not args.no_head_residual)
     opt = Adam(est.params, lr=args.lr)
     eval_cams = orbit_cameras(args.views, np.random.default_rng(2024), width=args.res, height=args.res)
     before = evaluate(R, est, held, eval_cams, kappa, sigma_factor)
@@ -192,7 +196,9 @@ def main(argv=None):
         batch = []
         for c in train:
             quant = bool(rng.integers(2))
-            x = sample_input(R, c, rng, quant, a=rng.uniform(0.25, 1.0), b=rng.uniform(0.125, 1.0))
+            full = rng.uniform() < args.keep_frac
+            x = sample_input(R, c, rng, quant, a=1.0 if full else rng.uniform(0.25, 1.0),
+                             b=1.0 if full else rng.uniform(0.125, 1.0))
             x["dense"] = c["dense"]
             x["state"] = c.setdefault("state", RenderState(R))      # render buffers reused per cloud
             batch.append(x)
@@ -230,7 +236,9 @@ def main(argv=None):
                   kappa_scores=scores, sigma_factor=sigma_factor, sigma_scores=sscores, before=before, after=after,
                   curve=curve, loss_first=losses[0] if losses else None, loss_last=losses[-1] if losses else None,
                   inference_ms_per_cloud=infer_ms, loss="Eq. 5: 1 L1 + 10 (cross + 0.1 min(|n - n_hat|, |n + n_hat|))",
-                  augmentation="quantised: round(a x)/a, a~U[0.25,1]; unquantised: b N points, b~U[0.125,1]")
+                  head_residual=not args.no_head_residual, keep_frac=args.keep_frac,
+                  augmentation=f"quantised: round(a x)/a, a~U[0.25,1]; unquantised: b N points, b~U[0.125,1]; "
+                               f"a fraction {args.keep_frac} of inputs kept at full density")
     print(json.dumps(report), flush=True)
     if args.out:
         torch.save(dict(params=[p.detach().cpu() for p in est.params], report=report), args.out)

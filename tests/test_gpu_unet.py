@@ -4,8 +4,8 @@
 Bars: parent voxels, child -> parent maps and upsampling tables bit-exact; pooled features within
 BF16 rounding of the FP64 mean; transposed-convolution outputs within 2^-8 relative plus 1e-5 of
 the sum of absolute products (BF16 output rounding, FP32 accumulation), its gradients within 1e-4
-of the sum of absolute terms (as the submanifold convolution's); the FP32 head within 1e-4
-relative (BF16 features in, FP32 arithmetic). The whole network's BF16 error against the FP64
+of the sum of absolute terms (as the submanifold convolution's); the FP32 per-point head within
+1e-4 relative (BF16 features and FP32 residuals in, FP32 arithmetic). The whole network's BF16 error against the FP64
 chain is reported per output.
 """
 import numpy as np
@@ -120,30 +120,33 @@ def test_head_forward_and_adjoint(R, cloud):
     p, rgb, vox, lv, ref, olv = cloud
     rng = np.random.default_rng(5)
     f64, ft = bf16(np.abs(rng.normal(size=(vox.V, 32))))
-    W1 = (rng.normal(size=(32, 32)) * 0.3).astype(np.float32)
+    W1 = (rng.normal(size=(32, 35)) * 0.3).astype(np.float32)
     b1 = (rng.normal(size=32) * 0.1).astype(np.float32)
     W2 = (rng.normal(size=(14, 32)) * 0.3).astype(np.float32)
     b2 = (rng.normal(size=14) * 0.1).astype(np.float32)
     cu = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
     xyz, col = cu(p), cu(rgb)
     g = unet_head_forward(R, vox, ft.cuda(), cu(W1), cu(b1), cu(W2), cu(b2), xyz, col)
-    want = U.head(f64, W1.T.astype(np.float64), b1, W2.T.astype(np.float64), b2, p, rgb, ref["point_voxel"], GRID)
+    want = U.head(f64, W1.T.astype(np.float64), b1, W2.T.astype(np.float64), b2, p, rgb, ref["point_voxel"], GRID,
+                  ref["coords"])
     for k in ("mean", "quat", "scale", "opacity", "rgb", "normal"):
         got = g[k].cpu().numpy().astype(np.float64)
         assert np.allclose(got, want[k], rtol=1e-4, atol=1e-5), k
-    # adjoint against FP64 autograd of the same head
+    # adjoint against FP64 autograd of the same head (per point: its voxel's features and its residual)
     tf = torch.from_numpy(f64).requires_grad_(True)
     tw = [torch.from_numpy(a.astype(np.float64)).requires_grad_(True) for a in (W1, b1, W2, b2)]
-    h = torch.relu(tf @ tw[0].T + tw[1])
+    pv = torch.from_numpy(ref["point_voxel"])
+    res = torch.from_numpy((p.T.astype(np.float64) + 1.0) * (GRID / 2.0) - (ref["coords"][ref["point_voxel"]] + 0.5))
+    x = torch.cat([tf[pv], res], dim=1)
+    h = torch.relu(x @ tw[0].T + tw[1])
     raw = h @ tw[2].T + tw[3]
     e = 2.0 / GRID
-    pv = torch.from_numpy(ref["point_voxel"])
-    mean = torch.from_numpy(p.astype(np.float64)) + e * torch.tanh(raw[pv, 0:3]).T
-    scale = (e * torch.exp(raw[pv, 3:6])).T
+    mean = torch.from_numpy(p.astype(np.float64)) + e * torch.tanh(raw[:, 0:3]).T
+    scale = (e * torch.exp(raw[:, 3:6])).T
     q = raw[:, 6:10] + torch.tensor([1.0, 0, 0, 0], dtype=torch.float64)
-    q = (q / q.norm(dim=1, keepdim=True))[pv].T
-    opac = torch.sigmoid(raw[pv, 10])
-    nrm = (raw[:, 11:14] / raw[:, 11:14].norm(dim=1, keepdim=True))[pv].T
+    q = (q / q.norm(dim=1, keepdim=True)).T
+    opac = torch.sigmoid(raw[:, 10])
+    nrm = (raw[:, 11:14] / raw[:, 11:14].norm(dim=1, keepdim=True)).T
     up = {k: rng.normal(size=s) for k, s in dict(mean=(3, p.shape[1]), quat=(4, p.shape[1]),
                                                   scale=(3, p.shape[1]), opacity=(p.shape[1],),
                                                   normal=(3, p.shape[1])).items()}
@@ -151,7 +154,7 @@ def test_head_forward_and_adjoint(R, cloud):
                dict(mean=mean, quat=q, scale=scale, opacity=opac, normal=nrm).items())
     loss.backward()
     dws = [torch.zeros(a.shape, device="cuda") for a in (W1, b1, W2, b2)]
-    df = unet_head_backward(R, vox, ft.cuda(), cu(W1), cu(b1), cu(W2), cu(b2),
+    df = unet_head_backward(R, vox, ft.cuda(), cu(W1), cu(b1), cu(W2), cu(b2), xyz,
                             {k: cu(v.astype(np.float32)) for k, v in up.items()}, dws)
     dfg = df.to(torch.float64).cpu().numpy()
     ref_df = tf.grad.numpy()
@@ -176,7 +179,8 @@ def test_network_forward_error_against_fp64(R, cloud):
     x0[:, :9] = vox.arrays()["features"][:, :9].to(torch.float64).cpu().numpy()
     f = U.forward(x0, olv, weights)
     want = U.head(f, est.w1.cpu().numpy().T.astype(np.float64), est.b1.cpu().numpy(),
-                  est.w2.cpu().numpy().T.astype(np.float64), est.b2.cpu().numpy(), p, rgb, ref["point_voxel"], GRID)
+                  est.w2.cpu().numpy().T.astype(np.float64), est.b2.cpu().numpy(), p, rgb, ref["point_voxel"], GRID,
+                  ref["coords"])
     got = {k: v.cpu().numpy().astype(np.float64) for k, v in g.items()}
     errs = dict(mean=np.abs(got["mean"] - want["mean"]).max() / (2.0 / GRID),
                 scale_rel=np.abs(got["scale"] / want["scale"] - 1).max(),

@@ -66,25 +66,44 @@ def test_up_conv_equals_transposed_convolution_at_the_children():
 def test_head_closed_forms():
     rng = np.random.default_rng(3)
     V, n, grid = 50, 80, 64
+    coords = rng.integers(0, grid, size=(V, 3))
     f = rng.normal(size=(V, 32))
-    W1, b1 = rng.normal(size=(32, 32)) * 0.3, rng.normal(size=32) * 0.1
+    W1, b1 = rng.normal(size=(35, 32)) * 0.3, rng.normal(size=32) * 0.1
     W2, b2 = rng.normal(size=(32, 14)) * 0.3, rng.normal(size=14) * 0.1
     pv = rng.integers(0, V, size=n)
-    pts = rng.uniform(-1, 1, size=(3, n))
+    # each point inside its voxel: p = (c + u) 2 / grid - 1 with u in [0, 1)^3
+    u = rng.uniform(0, 1, size=(n, 3))
+    pts = ((coords[pv] + u) * (2.0 / grid) - 1.0).T
     rgb = rng.uniform(0, 1, size=(3, n))
-    h = U.head(f, W1, b1, W2, b2, pts, rgb, pv, grid)
-    raw = np.maximum(f @ W1 + b1, 0.0) @ W2 + b2
+    h = U.head(f, W1, b1, W2, b2, pts, rgb, pv, grid, coords)
+    # the input is the voxel's features and the point's residual, which lies in [-1/2, 1/2)^3
+    assert np.array_equal(h["input"][:, :32], f[pv])
+    assert np.allclose(h["input"][:, 32:], u - 0.5, atol=1e-12)
+    raw = np.array([np.maximum(np.r_[f[pv[i]], u[i] - 0.5] @ W1 + b1, 0.0) @ W2 + b2 for i in range(n)])
     e = 2.0 / grid
     assert np.allclose(h["raw"], raw)
     assert np.all(np.abs(h["mean"] - pts) < e)                       # the offset stays within a voxel edge
-    assert np.allclose(h["mean"] - pts, e * np.tanh(raw[pv, 0:3]).T)
-    assert np.allclose(np.log(h["scale"] / e), raw[pv, 3:6].T)
+    assert np.allclose(h["mean"] - pts, e * np.tanh(raw[:, 0:3]).T)
+    assert np.allclose(np.log(h["scale"] / e), raw[:, 3:6].T)
     assert np.allclose(np.linalg.norm(h["quat"], axis=0), 1.0) and np.allclose(np.linalg.norm(h["normal"], axis=0), 1.0)
-    assert np.allclose(h["opacity"], 1 / (1 + np.exp(-raw[pv, 10])))
+    assert np.allclose(h["opacity"], 1 / (1 + np.exp(-raw[:, 10])))
     assert np.array_equal(h["rgb"], rgb)
+    # two points of one voxel get different outputs through their residuals only; with zero
+    # residual weights they get the same (the head is then one per voxel)
+    same = np.flatnonzero(pv == pv[0])
+    if same.size < 2:
+        pv[1] = pv[0]
+        pts[:, 1] = ((coords[pv[0]] + u[1]) * (2.0 / grid) - 1.0)
+        same = np.array([0, 1])
+    W1z = W1.copy()
+    W1z[32:] = 0.0
+    hz = U.head(f, W1z, b1, W2, b2, pts, rgb, pv, grid, coords)
+    assert np.allclose(hz["raw"][same[0]], hz["raw"][same[1]])
+    h2 = U.head(f, W1, b1, W2, b2, pts, rgb, pv, grid, coords)
+    assert not np.allclose(h2["raw"][same[0]], h2["raw"][same[1]])
     # zero rotation outputs give the identity quaternion; a normal output is its own direction
     q = U.head(np.zeros((1, 32)), W1 * 0, np.zeros(32), W2 * 0, np.r_[np.zeros(11), 0, 0, 2.0], pts[:, :1],
-               rgb[:, :1], np.zeros(1, int), grid)
+               rgb[:, :1], np.zeros(1, int), grid, coords[pv[:1]])
     assert np.allclose(q["quat"][:, 0], [1, 0, 0, 0]) and np.allclose(q["normal"][:, 0], [0, 0, 1])
 
 
