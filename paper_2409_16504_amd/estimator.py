@@ -281,10 +281,11 @@ UNET_HEAD_HIDDEN, UNET_HEAD_OUT = 32, 14
 UNET_HEAD_IN = 35         # per point: its voxel's 32 decoder features and its own residual (3)
 
 
-def pool(R: Renderer, child: Voxels) -> Voxels:
+def pool(R: Renderer, child: Voxels, parent: Voxels | None = None) -> Voxels:
     """Parent voxels of ``child`` on the grid of half the resolution (Section 3.2's pooling),
-    holding the child -> parent map and the upsampling tables."""
-    parent = Voxels(R)
+    holding the child -> parent map and the upsampling tables. A given ``parent`` is rebuilt in
+    place (its device buffers are reused)."""
+    parent = parent if parent is not None else Voxels(R)
     Vp = ctypes.c_int64()
     check(_lib.load().pcs_pool(R.ctx, child.handle, parent.handle, ctypes.byref(Vp), _s()))
     parent.V, parent.n, parent.grid = int(Vp.value), child.V, child.grid // 2
@@ -350,9 +351,9 @@ class UNetEstimator:
     offset, scale, rotation, opacity and normal. FP32 master weights, BF16 copies for the MFMA
     kernels; the head runs in FP32."""
 
-    def __init__(self, renderer: Renderer, seed: int = 0, opacity_init: float = 0.9, head_residual: bool = True):
-        """``head_residual`` False holds the head's weights on the point's residual at zero, so every
-        point of a voxel gets the same parameters."""
+    def __init__(self, renderer: Renderer, seed: int = 0, opacity_init: float = 0.9, head_residual: bool = False):
+        """``head_residual`` False (the default) holds the head's weights on the point's residual at
+        zero, so every point of a voxel gets the same parameters; True trains them too."""
         self.R = renderer
         self.head_residual = head_residual
         dev = torch.device("cuda", renderer.device)
@@ -406,11 +407,12 @@ class UNetEstimator:
         return out
 
     @staticmethod
-    def levels(R: Renderer, vox: Voxels) -> list:
-        """Voxel sets of levels 0..3 of a voxelised cloud (level 0 is ``vox``)."""
+    def levels(R: Renderer, vox: Voxels, reuse: list | None = None) -> list:
+        """Voxel sets of levels 0..3 of a voxelised cloud (level 0 is ``vox``). ``reuse``, the
+        list of an earlier call, has its pooled levels rebuilt in place (no new device buffers)."""
         lv = [vox]
-        for _ in range(3):
-            lv.append(pool(R, lv[-1]))
+        for i in range(3):
+            lv.append(pool(R, lv[-1], reuse[i + 1] if reuse is not None else None))
         return lv
 
     def forward(self, lv: list, save=False):

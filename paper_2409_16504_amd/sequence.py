@@ -1,9 +1,9 @@
-"""Dynamic point-cloud sequence: per frame, estimate every point's ellipsoid (the learned sparse
-estimator in BF16, or the kNN-PCA plain path) and render two views, reporting p50/p99 latency
-per frame and PSNR against a dense ground-truth render (Section 4.3's video setting, at 30 frames
-of a deforming procedural surface).
+"""Dynamic point-cloud sequence: per frame, estimate every point's ellipsoid (the learned
+estimator in BF16: the paper's UNet by default, or the plain eight-layer network; or the kNN-PCA
+plain path) and render two views, reporting p50/p99 latency per frame and PSNR against a dense
+ground-truth render (Section 4.3's video setting, at 30 frames of a deforming procedural surface).
 
-    python -m paper_2409_16504_amd.sequence --weights gpurun_out/estimator.pt
+    python -m paper_2409_16504_amd.sequence [--estimator unet|plain] [--weights path.pt]
 """
 from __future__ import annotations
 
@@ -25,11 +25,12 @@ from synthetic import look_at_camera  # noqa: E402
 from synthetic.scenes import ProceduralSurface  # noqa: E402
 
 from . import Renderer, RenderState, default_options  # noqa: E402
-from .estimator import SparseEstimator, Voxels, adaptive_grid, psnr  # noqa: E402
+from .estimator import SparseEstimator, UNetEstimator, Voxels, adaptive_grid, psnr  # noqa: E402
 
 
 SEQUENCE_SEED = 1005
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "estimator_surface.pt")
+UNET_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "unet_surface.pt")
 
 
 def make_sequence(n_frames: int, points: int, seed: int = SEQUENCE_SEED):
@@ -55,13 +56,12 @@ def sequence_cameras(width: int, height: int) -> list:
             for a in (0.0, math.pi / 2)]
 
 
-def load_estimator(R: Renderer, weights: str | None = WEIGHTS) -> SparseEstimator:
-    """The estimator with the shipped (or given) trained weights."""
-    est = SparseEstimator(R, seed=0)
+def load_estimator(R: Renderer, weights: str | None = WEIGHTS, kind: str = "plain"):
+    """The estimator ("unet": the paper's UNet-like network; "plain": the eight-layer sparse
+    network) with the shipped (or given) trained weights."""
+    est = UNetEstimator(R, seed=0) if kind == "unet" else SparseEstimator(R, seed=0)
     if weights:
-        ck = torch.load(weights, weights_only=True)
-        for p_, v in zip(est.params, ck["params"]):
-            p_.copy_(v.to(p_.device))
+        est.load_params(torch.load(weights, weights_only=True)["params"])
     return est
 
 
@@ -72,7 +72,9 @@ def main(argv=None):
     ap.add_argument("--points", type=int, default=1_000_000)
     ap.add_argument("--width", type=int, default=1440)
     ap.add_argument("--height", type=int, default=1600)
-    ap.add_argument("--weights", default=WEIGHTS)
+    ap.add_argument("--estimator", choices=("unet", "plain"), default="unet",
+                    help="the learned estimator: the paper's UNet or the plain eight-layer network")
+    ap.add_argument("--weights", default=None, help="trained weights (default: the shipped ones)")
     ap.add_argument("--kappa", type=float, default=1.0)
     ap.add_argument("--psnr-frames", type=int, default=3)
     args = ap.parse_args(argv)
@@ -85,7 +87,9 @@ def main(argv=None):
                    scale=f["scale"]) for f in raw]
     print(f"[sequence] {len(frames)} frames ready in {time.time() - t0:.1f}s", flush=True)
     cams = sequence_cameras(args.width, args.height)
-    est = load_estimator(R, args.weights)
+    if args.weights is None:
+        args.weights = UNET_WEIGHTS if args.estimator == "unet" else WEIGHTS
+    est = load_estimator(R, args.weights, args.estimator)
     opts = default_options()
     grid = adaptive_grid(R, frames[0]["xyz"], frames[0]["rgb"]).grid   # the density is the sequence's
     vox = Voxels(R)
@@ -94,8 +98,13 @@ def main(argv=None):
                         opacity=torch.full((args.points,), 0.9, device=dev), rgb=frames[0]["rgb"],
                         normal=torch.zeros((3, args.points), device=dev)), cams, opts)
 
+    levels = []                         # the UNet's pooled voxel sets, rebuilt in place per frame
+
     def learned(f):
         vox.build(f["xyz"], f["rgb"], grid)
+        if args.estimator == "unet":
+            levels[:] = UNetEstimator.levels(R, vox, levels or None)
+            return est.forward(levels)
         return est.forward(vox)
 
     def plain(f):
@@ -210,6 +219,7 @@ def main(argv=None):
     for name in ps:
         report[name]["psnr_db"] = float(np.mean(ps[name]))
     report["config"] = dict(frames=args.frames, points=args.points, views=2, width=args.width, height=args.height,
+                            estimator=args.estimator,
                             weights=os.path.relpath(args.weights, ROOT) if args.weights else None)
     print(json.dumps(report), flush=True)
     return report

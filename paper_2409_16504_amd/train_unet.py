@@ -138,8 +138,9 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--out", default=None)
     ap.add_argument("--curve", action="store_true", help="also the PSNR-versus-density curve")
-    ap.add_argument("--no-head-residual", action="store_true",
-                    help="hold the head's residual-input weights at zero (one set of parameters per voxel)")
+    ap.add_argument("--head-residual", action="store_true",
+                    help="train the head's weights on each point's residual (default: held at zero, one set "
+                         "of parameters per voxel)")
     ap.add_argument("--keep-frac", type=float, default=0.0,
                     help="fraction of training inputs left at full density (the rest are downsampled)")
     args = ap.parse_args(argv)
@@ -170,7 +171,7 @@ def main(argv=None):
     sigma_factor = max(sscores, key=sscores.get)
     print(f"[unet] kappa {scores} -> {kappa}; global sigma {sscores} -> {sigma_factor}", flush=True)
 
-    est = UNetEstimator(R, seed=0, head_residual=not args.no_head_residual)
+    est = UNetEstimator(R, seed=0, head_residual=args.head_residual)
     opt = Adam(est.params, lr=args.lr)
     eval_cams = orbit_cameras(args.views, np.random.default_rng(2024), width=args.res, height=args.res)
     before = evaluate(R, est, held, eval_cams, kappa, sigma_factor)
@@ -236,7 +237,7 @@ def main(argv=None):
                   kappa_scores=scores, sigma_factor=sigma_factor, sigma_scores=sscores, before=before, after=after,
                   curve=curve, loss_first=losses[0] if losses else None, loss_last=losses[-1] if losses else None,
                   inference_ms_per_cloud=infer_ms, loss="Eq. 5: 1 L1 + 10 (cross + 0.1 min(|n - n_hat|, |n + n_hat|))",
-                  head_residual=not args.no_head_residual, keep_frac=args.keep_frac,
+                  head_residual=args.head_residual, keep_frac=args.keep_frac,
                   augmentation=f"quantised: round(a x)/a, a~U[0.25,1]; unquantised: b N points, b~U[0.125,1]; "
                                f"a fraction {args.keep_frac} of inputs kept at full density")
     print(json.dumps(report), flush=True)

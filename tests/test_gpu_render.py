@@ -158,6 +158,27 @@ def test_nonfinite_gaussians_never_reach_pixels(R):
     check_images(imgs, bins, ref, 4.0)
 
 
+def assert_stateless_identical(R, g, cams, imgs):
+    import paper_2409_16504_amd as P
+    out = R.render(to_torch(g), cams, P.default_options())
+    for k, v in out.items():
+        assert np.array_equal(v.cpu().numpy(), imgs[k]), k
+
+
+def test_render_without_state_is_identical(R):
+    g, cams = c1_scene()
+    imgs, _, _ = gpu_render(R, g, cams)
+    assert_stateless_identical(R, g, cams, imgs)
+    rng = np.random.default_rng(11)
+    g = random_gaussians(3000, rng, scale_range=(0.005, 0.08))
+    cams = orbit_cameras(3, rng, width=100, height=75)
+    imgs, _, _ = gpu_render(R, g, cams, opts=dict(t_eps=0.5))
+    import paper_2409_16504_amd as P
+    out = R.render(to_torch(g), cams, P.default_options(t_eps=0.5))
+    for k, v in out.items():
+        assert np.array_equal(v.cpu().numpy(), imgs[k]), k
+
+
 def test_permutation_invariance_and_determinism(R):
     g, cams = c1_scene()
     a, ba, _ = gpu_render(R, g, cams)
@@ -197,6 +218,9 @@ def test_full_size_surface_frame(R, n, W, H, seed):
     check_bins(bins, ref, TX * TY)
     err = check_images(imgs, bins, ref, 5.0)
     print(f"full frame {n} at {W}x{H}: {err}", flush=True)
+    # the same frame without a state (the final transmittance and last contributor are then not
+    # written): bit-identical images
+    assert_stateless_identical(R, g, cams, imgs)
     assert err["flagged"] < 1e-3 * W * H
     assert (ref["n_contrib"][0] > 0).sum() > 0.1 * W * H
 
