@@ -81,6 +81,21 @@ def test_other_k(R, k):
     compare(p, gpu, ref, gap, check_normals=k > 2)
 
 
+def test_clustered_cloud(R):
+    """Tight clusters of 1,500 points in a sparse background: a cluster query's 3x3x3 block holds
+    far more candidates than the histogram-bounded list keeps, so those queries insert every
+    candidate of the block (the other clouds here take the bounded-list path)."""
+    rng = np.random.default_rng(77)
+    centres = rng.uniform(-1, 1, (3, 20))
+    clusters = (centres[:, :, None] + rng.normal(0, 0.01, (3, 20, 1500))).reshape(3, -1)
+    p = np.concatenate([clusters, rng.uniform(-1, 1, (3, 4000))], axis=1).astype(np.float32)
+    nb, gap = kp.knn(p, 16)
+    ref = kp.knn_pca(p, 16, neighbours=nb)
+    gpu = gpu_knn(R, p)
+    ties = compare(p, gpu, ref, gap)
+    assert ties < 0.01 * p.shape[1]      # within a cluster the k-th and next distances often nearly tie
+
+
 def test_rejects_bad_arguments(R):
     import torch
     from paper_2409_16504_amd import PcsError
