@@ -158,6 +158,27 @@ def test_nonfinite_gaussians_never_reach_pixels(R):
     check_images(imgs, bins, ref, 4.0)
 
 
+@pytest.mark.parametrize("t_eps", [1e-4, 0.05])
+def test_long_faint_lists(R, t_eps):
+    """60k faint Gaussians over a 96x96 image: the inner tiles' lists hold 4,800-11,600 records
+    and many pixels never reach the stop, so the walks run to the end of long lists. Keys, images
+    and last contributors against the oracle at every pixel; with t_eps = 0.05 most pixels stop."""
+    rng = np.random.default_rng(2048)
+    g = random_gaussians(60000, rng, scale_range=(0.01, 0.06), opacity_range=(0.02, 0.3))
+    cams = [look_at_camera([0, 0, 3], width=96, height=96)]
+    imgs, bins, _ = gpu_render(R, g, cams, opts=dict(t_eps=t_eps))
+    lengths = bins["ranges"][1].astype(np.int64) - bins["ranges"][0]
+    assert (lengths >= 4096).sum() >= 16, np.sort(lengths)
+    ref = oracle.render(g, cams, mode="ref", opts=dict(t_eps=t_eps))
+    check_bins(bins, ref, 36)
+    err = check_images(imgs, bins, ref, 4.0)
+    assert err["flagged"] < 0.02 * 96 * 96, err
+    if t_eps > 0.01:
+        assert (ref["T"][0] < t_eps).mean() > 0.5
+    if t_eps < 0.01:
+        assert_stateless_identical(R, g, cams, imgs)
+
+
 def assert_stateless_identical(R, g, cams, imgs):
     import paper_2409_16504_amd as P
     out = R.render(to_torch(g), cams, P.default_options())
