@@ -331,62 +331,77 @@ __global__ __launch_bounds__(kWave) void k_composite_bwd(
     }
     if (bstart > 0) fetch(max(0, bstart - kWave), bstart);
     __syncthreads();                                  // one wavefront: orders the LDS writes
-    for (int k = __popcll(relmask) - 1; k >= 0; --k) {
-      float pg[kScreenGrads];
+    // groups of kGroup kept records, back to front: first every record's blend decision, alpha and
+    // 1 / (1 - alpha) (they do not depend on T), then the in-order steps, which select instead of
+    // branching (a record that did not blend at this pixel leaves T, gb and its partials at zero)
+    const int nrel = __popcll(relmask);
+    for (int k0 = nrel - 1; k0 >= 0; k0 -= kGroup) {
+      bool pass[kGroup];
+      float sqv[kGroup], dxv[kGroup], dyv[kGroup], av[kGroup], arawv[kGroup], invv[kGroup];
 #pragma unroll
-      for (int i = 0; i < kScreenGrads; ++i) pg[i] = 0.f;
-      bool contrib = false;
-      const float4 f2 = s_f2[k];
-      if (__float_as_int(f2.w) < nc) {           // list position (from 0) before the pixel's stop
+      for (int j = 0; j < kGroup; ++j) {
+        const int k = max(k0 - j, 0);                 // slots below 0 re-read slot 0, never pass
         const float4 f0 = s_f0[k];
         const float4 f1 = s_f1[k];
+        const float4 f2 = s_f2[k];
         float dx, dy;
         const float sq = blend_kq(f0, f1, pxf, pyf, dx, dy);
-        if (sq >= f1.z) {                        // the forward pass's blend decision
-          const float araw = __builtin_amdgcn_exp2f(sq + f1.y);
-          const float a = fminf(amax, araw);
-          contrib = true;
-          const float4 f3 = s_f3[k];
-          const float inv = __builtin_amdgcn_rcpf(1.0f - a);
-          T = T * inv;                           // transmittance in front of this splat
-          const float w = a * T;
-          const float gf = fmaf(g[0], f2.x, fmaf(g[1], f2.y, fmaf(g[2], f2.z, fmaf(g[3], f3.x,
-                           fmaf(g[4], f3.y, fmaf(g[5], f3.z, g[6] * f1.w))))));
-          const float dLda = fmaf(T, gf, -gb * inv);
-          gb = fmaf(w, gf, gb);
-          pg[7] = g[0] * w;
-          pg[8] = g[1] * w;
-          pg[9] = g[2] * w;
-          pg[10] = g[3] * w;
-          pg[11] = g[4] * w;
-          pg[12] = g[5] * w;
-          pg[6] = g[6] * w;
-          if (!(araw > opt.alpha_max)) {
-            pg[5] = dLda * __builtin_amdgcn_exp2f(sq);      // d alpha / d o = e^(-q/2)
-            const float dLdq = dLda * (-0.5f * a);
-            pg[2] = dLdq * dx * dx;
-            pg[3] = dLdq * 2.0f * dx * dy;
-            pg[4] = dLdq * dy * dy;
-            const float dLdq2 = dLdq * kM2OverK;
-            pg[0] = dLdq2 * fmaf(f0.z, dx, (0.5f * f0.w) * dy);
-            pg[1] = dLdq2 * fmaf(0.5f * f0.w, dx, f1.x * dy);
-          }
-        }
+        // the forward pass's blend decision, for list positions (from 0) before the pixel's stop
+        pass[j] = k0 - j >= 0 && __float_as_int(f2.w) < nc && sq >= f1.z;
+        const float araw = __builtin_amdgcn_exp2f(sq + f1.y);
+        const float a = fminf(amax, araw);
+        sqv[j] = sq; dxv[j] = dx; dyv[j] = dy; av[j] = a; arawv[j] = araw;
+        invv[j] = __builtin_amdgcn_rcpf(1.0f - a);
       }
-      if (__ballot(contrib) == 0ull) continue;   // wave-uniform
-      const int64_t dst = base_idx + s_g[k];
-      float v16[16], sv[4];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) v16[i] = i < kScreenGrads ? pg[i] : 0.0f;
-      wave_sum16_rows(v16, sv);
-      // sum i sits in lane 16 (i / 4) + 15, slot i % 4: bring it to lane i, then one atomic
-      // instruction adds all thirteen into the splat's 64-byte line
-      const int src = 16 * ((lane & 15) >> 2) + 15;
-      const float t0 = __shfl(sv[0], src, kWave), t1 = __shfl(sv[1], src, kWave);
-      const float t2 = __shfl(sv[2], src, kWave), t3 = __shfl(sv[3], src, kWave);
-      const int j = lane & 3;
-      const float val = j == 0 ? t0 : (j == 1 ? t1 : (j == 2 ? t2 : t3));
-      if (lane < kScreenGrads && val != 0.0f) unsafeAtomicAdd(&sgrad[dst * kScreenStride + lane], val);
+      for (int j = 0; j < kGroup; ++j) {
+        const bool contrib = pass[j];
+        if (__ballot(contrib) == 0ull) continue;      // wave-uniform
+        const int k = k0 - j;                         // >= 0 here: some lane passed
+        const float4 f1 = s_f1[k];
+        const float4 f2 = s_f2[k];
+        const float4 f3 = s_f3[k];
+        const float4 f0 = s_f0[k];
+        const float a = av[j], inv = invv[j], dx = dxv[j], dy = dyv[j];
+        T = contrib ? T * inv : T;                    // transmittance in front of this splat
+        const float w = contrib ? a * T : 0.0f;
+        const float gf = fmaf(g[0], f2.x, fmaf(g[1], f2.y, fmaf(g[2], f2.z, fmaf(g[3], f3.x,
+                         fmaf(g[4], f3.y, fmaf(g[5], f3.z, g[6] * f1.w))))));
+        const float dLda = contrib ? fmaf(T, gf, -gb * inv) : 0.0f;
+        gb = contrib ? fmaf(w, gf, gb) : gb;
+        float pg[kScreenGrads];
+        pg[7] = g[0] * w;
+        pg[8] = g[1] * w;
+        pg[9] = g[2] * w;
+        pg[10] = g[3] * w;
+        pg[11] = g[4] * w;
+        pg[12] = g[5] * w;
+        pg[6] = g[6] * w;
+        // alpha clamped at alpha_max: no gradient to opacity or the quadratic form
+        const bool free_a = contrib && !(arawv[j] > opt.alpha_max);
+        const float dLda_u = free_a ? dLda : 0.0f;
+        pg[5] = free_a ? dLda * __builtin_amdgcn_exp2f(sqv[j]) : 0.0f;   // d alpha / d o = e^(-q/2)
+        const float dLdq = dLda_u * (-0.5f * a);
+        pg[2] = dLdq * dx * dx;
+        pg[3] = dLdq * 2.0f * dx * dy;
+        pg[4] = dLdq * dy * dy;
+        const float dLdq2 = dLdq * kM2OverK;
+        pg[0] = dLdq2 * fmaf(f0.z, dx, (0.5f * f0.w) * dy);
+        pg[1] = dLdq2 * fmaf(0.5f * f0.w, dx, f1.x * dy);
+        const int64_t dst = base_idx + s_g[k];
+        float v16[16], sv[4];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v16[i] = i < kScreenGrads ? pg[i] : 0.0f;
+        wave_sum16_rows(v16, sv);
+        // sum i sits in lane 16 (i / 4) + 15, slot i % 4: bring it to lane i, then one atomic
+        // instruction adds all thirteen into the splat's 64-byte line
+        const int src = 16 * ((lane & 15) >> 2) + 15;
+        const float t0 = __shfl(sv[0], src, kWave), t1 = __shfl(sv[1], src, kWave);
+        const float t2 = __shfl(sv[2], src, kWave), t3 = __shfl(sv[3], src, kWave);
+        const int jj = lane & 3;
+        const float val = jj == 0 ? t0 : (jj == 1 ? t1 : (jj == 2 ? t2 : t3));
+        if (lane < kScreenGrads && val != 0.0f) unsafeAtomicAdd(&sgrad[dst * kScreenStride + lane], val);
+      }
     }
     __syncthreads();                                  // reads done before the next batch lands
   }
