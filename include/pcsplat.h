@@ -339,7 +339,8 @@ int pcs_up_conv_backward(pcs_context* ctx, const pcs_voxels* parent, const uint1
  * [out][in]). Outputs: mean = xyz + e tanh(raw[0:3]) (the offset stays within one voxel edge),
  * scale = e exp(raw[3:6]), quat = normalise(raw[6:10] + (1,0,0,0)), opacity = sigmoid(raw[10]),
  * normal = normalise(raw[11:14]), rgb = the point's colour (Section 3.1 keeps the original colour);
- * all planar [3|4][n] or [n] FP32. xyz must be the points the voxels were built from. The backward
+ * all planar [3|4][n] or [n] FP32. xyz must be the points the voxels were built from (a pooled level
+ * is refused with PCS_ERR_INVALID_ARG). The backward
  * takes per-point gradients of mean, quat, scale, opacity and normal (any may be NULL = zero) and
  * gives d_feat[V][32] (BF16, overwritten) and the weight gradients (FP32, accumulated: zero them
  * first). No gradient flows to xyz. */

@@ -1121,6 +1121,7 @@ int pcs_unet_head_forward(pcs_context* ctx, const pcs_voxels* vox, const uint16_
   if (!ctx || !vox || !vox->valid || !feat || !w1 || !b1 || !w2 || !b2 || !xyz || !rgb || !mean || !quat ||
       !scale || !opacity || !out_rgb || !normal)
     return fail(PCS_ERR_INVALID_ARG, "NULL argument or empty voxels");
+  if (vox->pooled) return fail(PCS_ERR_INVALID_ARG, "the head takes the voxels of the points, not a pooled level");
   PCS_HIP(hipSetDevice(ctx->device));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   StageTimer tm(ctx, ST_HEAD, s);
@@ -1137,6 +1138,7 @@ int pcs_unet_head_backward(pcs_context* ctx, const pcs_voxels* vox, const uint16
   if (!ctx || !vox || !vox->valid || !feat || !w1 || !b1 || !w2 || !b2 || !xyz || !d_feat || !d_w1 || !d_b1 ||
       !d_w2 || !d_b2)
     return fail(PCS_ERR_INVALID_ARG, "NULL argument or empty voxels");
+  if (vox->pooled) return fail(PCS_ERR_INVALID_ARG, "the head takes the voxels of the points, not a pooled level");
   PCS_HIP(hipSetDevice(ctx->device));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   StageTimer tm(ctx, ST_HEAD_BWD, s);

@@ -575,11 +575,7 @@ __global__ __launch_bounds__(256) void k_head_backward(
   if (threadIdx.x < kHeadOut && s_dbh[threadIdx.x] != 0.0f) unsafeAtomicAdd(&d_bh[threadIdx.x], s_dbh[threadIdx.x]);
 }
 
-// ---- the paper's head (Section 3.2): a shared two-layer MLP on the decoder's last features ------
-// raw = W2 relu(W1 f + b1) + b2 per voxel (32 -> 32 -> 14, FP32), then per point: offset
-// delta = voxel tanh(raw[0:3]) (within one voxel edge), scale = voxel exp(raw[3:6]),
-// q = normalise(raw[6:10] + (1,0,0,0)), opacity = sigmoid(raw[10]), normal = normalise(raw[11:14]).
-// ---- the UNet's head: a shared MLP per point --------------------------------------------------
+// ---- the UNet's head (Section 3.2): a shared MLP per point ------------------------------------
 // Input of point i: the 32 decoder features of its voxel and its own coordinate residual (in voxel
 // edges, as the voxelisation computes it), 35 values; ReLU hidden layer of 32; 14 outputs
 // (offset 3, log-scale 3, rotation 4, opacity 1, normal 3), activated per point.

@@ -162,6 +162,10 @@ def test_head_forward_and_adjoint(R, cloud):
     for got, t in zip(dws, tw):
         r = t.grad.numpy()
         assert np.allclose(got.cpu().numpy(), r, rtol=1e-3, atol=1e-4 * np.abs(r).max()), t.shape
+    # a pooled level is not the points' voxels: refused
+    from paper_2409_16504_amd import PcsError
+    with pytest.raises(PcsError):
+        unet_head_forward(R, lv[1], ft.cuda()[: lv[1].V], cu(W1), cu(b1), cu(W2), cu(b2), xyz, col)
 
 
 def test_network_forward_error_against_fp64(R, cloud):
