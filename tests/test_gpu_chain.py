@@ -254,3 +254,39 @@ def test_sequence_frame_estimator_and_render():
     u = 2.0 ** -9
     assert errs["scale_rel"].mean() <= 32 * u and errs["opacity"].mean() <= 32 * u
     assert errs["rgb"].mean() <= 32 * u and errs["angle_deg"].mean() <= 5.0
+
+
+def test_sequence_unet_frames_with_reused_levels():
+    """Two frames of the dynamic sequence through the shipped UNet estimator, the second with the
+    first frame's pooled voxel sets rebuilt in place (as the sequence driver does): its outputs
+    equal those of freshly pooled levels bit for bit, and the render of the estimate matches the
+    oracle (keys bit-exact, images within 1e-4 on unflagged pixels)."""
+    import paper_2409_16504_amd as P
+    from paper_2409_16504_amd import sequence as S
+    from paper_2409_16504_amd.estimator import UNetEstimator, Voxels, adaptive_grid
+    from helpers import image_errors
+    R = P.Renderer(0)
+    _, frames = S.make_sequence(2, 200_000)
+    cams = S.sequence_cameras(360, 400)
+    est = S.load_estimator(R, S.UNET_WEIGHTS, kind="unet")
+    xyz0, rgb0 = torch.from_numpy(frames[0]["xyz"]).cuda(), torch.from_numpy(frames[0]["rgb"]).cuda()
+    grid = adaptive_grid(R, xyz0, rgb0).grid
+    vox = Voxels(R).build(xyz0, rgb0, grid)
+    levels = UNetEstimator.levels(R, vox)
+    est.forward(levels)
+    xyz1, rgb1 = torch.from_numpy(frames[1]["xyz"]).cuda(), torch.from_numpy(frames[1]["rgb"]).cuda()
+    vox.build(xyz1, rgb1, grid)
+    reused = UNetEstimator.levels(R, vox, levels)
+    g = est.forward(reused)
+    fresh = Voxels(R).build(xyz1, rgb1, grid)
+    g_fresh = est.forward(UNetEstimator.levels(R, fresh))
+    for k in g:
+        assert torch.equal(g[k], g_fresh[k]), k
+    st = P.RenderState(R)
+    out = R.render(g, cams, P.default_options(), state=st)
+    bins = R.bins(st)
+    ref = oracle.render({k: v.cpu().numpy() for k, v in g.items()}, cams, mode="ref")
+    assert np.array_equal(bins["keys"], ref["keys"]) and np.array_equal(bins["vals"], ref["vals"])
+    err = image_errors({k: v.cpu().numpy() for k, v in out.items()}, ref)
+    print(f"UNet sequence frame render: {err}", flush=True)
+    assert err["rgb"] <= 1e-4 and err["normal"] <= 1e-4 and err["alpha"] <= 1e-4, err
