@@ -461,16 +461,19 @@ def unet_gap(R):
     est = UNetEstimator(R, seed=0)
     est.load_params(ck["params"])
     rep = ck["report"]
+    gn = rep.get("grid_neighbours", 6.0)        # the voxel-grid rule the weights were trained with
     t0 = time.time()
     held = [TU.make_cloud(R, 2000 + i, rep["points"]) for i in range(2)]
     cams = orbit_cameras(rep["views"], np.random.default_rng(2024), width=rep["res"], height=rep["res"])
     runs = {}
     for a in (1.0, 0.5, 0.25):
-        runs[f"a={a}"] = TU.evaluate(R, est, held, cams, rep["kappa"], rep["sigma_factor"], True, a=a)
+        runs[f"a={a}"] = TU.evaluate(R, est, held, cams, rep["kappa"], rep["sigma_factor"], True, a=a,
+                                     grid_neighbours=gn)
     for b in (0.5, 0.25, 0.125):
-        runs[f"b={b}"] = TU.evaluate(R, est, held, cams, rep["kappa"], rep["sigma_factor"], False, b=b)
+        runs[f"b={b}"] = TU.evaluate(R, est, held, cams, rep["kappa"], rep["sigma_factor"], False, b=b,
+                                     grid_neighbours=gn)
     # time per cloud: voxelise + pool + network + head, against kNN-PCA of the same points
-    x = TU.sample_input(R, held[0], np.random.default_rng(0), True)
+    x = TU.sample_input(R, held[0], np.random.default_rng(0), True, grid_neighbours=gn)
     vox, grid = x["vox"], x["vox"].grid
     with torch.no_grad():
         for _ in range(2):
@@ -489,6 +492,7 @@ def unet_gap(R):
     full = runs["a=1.0"]
     print(f"[bench] UNet on held-out clouds in {time.time() - t0:.1f}s: {full}", file=sys.stderr, flush=True)
     return dict(full, train_steps=rep["steps"], kappa=rep["kappa"], sigma_factor=rep["sigma_factor"],
+                grid_neighbours=gn,
                 gap_db_by_density={k: v["gap_db"] for k, v in runs.items()},
                 psnr_by_density={k: dict(learned=v["psnr_learned"], knn_pca=v["psnr_knn_pca"],
                                          global_sigma=v["psnr_global_sigma"]) for k, v in runs.items()},

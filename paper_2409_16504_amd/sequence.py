@@ -60,8 +60,11 @@ def load_estimator(R: Renderer, weights: str | None = WEIGHTS, kind: str = "plai
     """The estimator ("unet": the paper's UNet-like network; "plain": the eight-layer sparse
     network) with the shipped (or given) trained weights."""
     est = UNetEstimator(R, seed=0) if kind == "unet" else SparseEstimator(R, seed=0)
+    est.grid_neighbours = 6.0               # the voxel-grid rule (see estimator.adaptive_grid)
     if weights:
-        est.load_params(torch.load(weights, weights_only=True)["params"])
+        ck = torch.load(weights, weights_only=True)
+        est.load_params(ck["params"])
+        est.grid_neighbours = ck.get("report", {}).get("grid_neighbours", 6.0)
     return est
 
 
@@ -91,7 +94,8 @@ def main(argv=None):
         args.weights = UNET_WEIGHTS if args.estimator == "unet" else WEIGHTS
     est = load_estimator(R, args.weights, args.estimator)
     opts = default_options()
-    grid = adaptive_grid(R, frames[0]["xyz"], frames[0]["rgb"]).grid   # the density is the sequence's
+    # the density is the sequence's; the grid rule is the estimator's
+    grid = adaptive_grid(R, frames[0]["xyz"], frames[0]["rgb"], est.grid_neighbours).grid
     vox = Voxels(R)
     out = R.render(dict(mean=frames[0]["xyz"], quat=torch.zeros((4, args.points), device=dev),
                         scale=torch.full((3, args.points), 0.002, device=dev),

@@ -60,10 +60,11 @@ def make_cloud(R: Renderer, seed: int, n: int, dense_factor: int = 8) -> dict:
 
 
 def sample_input(R: Renderer, c: dict, rng: np.random.Generator, quantise: bool, a: float = 1.0,
-                 b: float = 1.0) -> dict:
+                 b: float = 1.0, grid_neighbours: float = 6.0) -> dict:
     """The network input of a cloud: quantised coordinates coarsened to round(a x) / a, or the
     unquantised sample thinned to a fraction b (points keep their colours); voxelised at the
-    density-adaptive grid with its pooled levels."""
+    density-adaptive grid (the finest whose voxels have on average at least ``grid_neighbours``
+    occupied neighbours) with its pooled levels."""
     if quantise:
         x = np.round(a * c["q"]) / a
         pts, rgb = (x + 0.5) / 512.0 - 1.0, c["rgb"]
@@ -74,7 +75,7 @@ def sample_input(R: Renderer, c: dict, rng: np.random.Generator, quantise: bool,
     dev = torch.device("cuda", R.device)
     xyz = torch.from_numpy(np.ascontiguousarray(pts, np.float32)).to(dev)
     col = torch.from_numpy(np.ascontiguousarray(rgb, np.float32)).to(dev)
-    vox = adaptive_grid(R, xyz, col)
+    vox = adaptive_grid(R, xyz, col, grid_neighbours)
     return dict(xyz=xyz, rgb=col, vox=vox, levels=UNetEstimator.levels(R, vox))
 
 
@@ -105,12 +106,13 @@ def normal_angle(n_hat: torch.Tensor, n_gt: torch.Tensor, mask: torch.Tensor) ->
     return float(torch.rad2deg(torch.acos(cos))[mask].mean().item())
 
 
-def evaluate(R, est, clouds, cams, kappa, sigma_factor, quantise=True, a=1.0, b=1.0, seed=0) -> dict:
+def evaluate(R, est, clouds, cams, kappa, sigma_factor, quantise=True, a=1.0, b=1.0, seed=0,
+             grid_neighbours=6.0) -> dict:
     rng = np.random.default_rng(seed)
     res = {k: [] for k in ("learned", "knn_pca", "global_sigma", "normal_learned", "normal_knn_pca")}
     with torch.no_grad():
         for c in clouds:
-            x = sample_input(R, c, rng, quantise, a, b)
+            x = sample_input(R, c, rng, quantise, a, b, grid_neighbours)
             gt = render_all(R, c["dense"], cams)
             mask = gt["alpha"] > 0.5
             dbar = float(R.knn_pca(x["xyz"], k=16, kappa=1.0, floor=0.1, nn_dist=True)["nn_dist"].mean().item())
@@ -141,6 +143,8 @@ def main(argv=None):
     ap.add_argument("--head-residual", action="store_true",
                     help="train the head's weights on each point's residual (default: held at zero, one set "
                          "of parameters per voxel)")
+    ap.add_argument("--grid-neighbours", type=float, default=6.0,
+                    help="voxel grid: the finest whose voxels have on average this many occupied neighbours")
     ap.add_argument("--keep-frac", type=float, default=0.0,
                     help="fraction of training inputs left at full density (the rest are downsampled)")
     args = ap.parse_args(argv)
@@ -174,7 +178,8 @@ def main(argv=None):
     est = UNetEstimator(R, seed=0, head_residual=args.head_residual)
     opt = Adam(est.params, lr=args.lr)
     eval_cams = orbit_cameras(args.views, np.random.default_rng(2024), width=args.res, height=args.res)
-    before = evaluate(R, est, held, eval_cams, kappa, sigma_factor)
+    gn = args.grid_neighbours
+    before = evaluate(R, est, held, eval_cams, kappa, sigma_factor, grid_neighbours=gn)
     print(f"[unet] before: {before}", flush=True)
     view_rng = np.random.default_rng(99)
 
@@ -199,7 +204,7 @@ def main(argv=None):
             quant = bool(rng.integers(2))
             full = rng.uniform() < args.keep_frac
             x = sample_input(R, c, rng, quant, a=1.0 if full else rng.uniform(0.25, 1.0),
-                             b=1.0 if full else rng.uniform(0.125, 1.0))
+                             b=1.0 if full else rng.uniform(0.125, 1.0), grid_neighbours=gn)
             x["dense"] = c["dense"]
             x["state"] = c.setdefault("state", RenderState(R))      # render buffers reused per cloud
             batch.append(x)
@@ -209,19 +214,20 @@ def main(argv=None):
             print(f"[unet] step {step} loss {loss:.5f} ({time.time() - t1:.1f}s)", flush=True)
     torch.cuda.synchronize()
     train_s = time.time() - t1
-    after = evaluate(R, est, held, eval_cams, kappa, sigma_factor)
+    after = evaluate(R, est, held, eval_cams, kappa, sigma_factor, grid_neighbours=gn)
     print(f"[unet] after: {after}", flush=True)
     curve = None
     if args.curve:
         curve = dict(quantised={}, subsampled={})
         for a in (1.0, 0.5, 0.25):
-            curve["quantised"][a] = evaluate(R, est, held, eval_cams, kappa, sigma_factor, True, a=a)
+            curve["quantised"][a] = evaluate(R, est, held, eval_cams, kappa, sigma_factor, True, a=a, grid_neighbours=gn)
             print(f"[unet] a={a}: {curve['quantised'][a]}", flush=True)
         for b in (1.0, 0.5, 0.25, 0.125):
-            curve["subsampled"][b] = evaluate(R, est, held, eval_cams, kappa, sigma_factor, False, b=b)
+            curve["subsampled"][b] = evaluate(R, est, held, eval_cams, kappa, sigma_factor, False, b=b,
+                                              grid_neighbours=gn)
             print(f"[unet] b={b}: {curve['subsampled'][b]}", flush=True)
     # inference time per cloud: voxelise (density-adaptive grid chosen once) + pool + network + head
-    x = sample_input(R, held[0], rng, True)
+    x = sample_input(R, held[0], rng, True, grid_neighbours=gn)
     vox, grid = x["vox"], x["vox"].grid
     for _ in range(2):
         est.forward(UNetEstimator.levels(R, vox.build(x["xyz"], x["rgb"], grid)))
@@ -237,7 +243,7 @@ def main(argv=None):
                   kappa_scores=scores, sigma_factor=sigma_factor, sigma_scores=sscores, before=before, after=after,
                   curve=curve, loss_first=losses[0] if losses else None, loss_last=losses[-1] if losses else None,
                   inference_ms_per_cloud=infer_ms, loss="Eq. 5: 1 L1 + 10 (cross + 0.1 min(|n - n_hat|, |n + n_hat|))",
-                  head_residual=args.head_residual, keep_frac=args.keep_frac,
+                  head_residual=args.head_residual, keep_frac=args.keep_frac, grid_neighbours=gn,
                   augmentation=f"quantised: round(a x)/a, a~U[0.25,1]; unquantised: b N points, b~U[0.125,1]; "
                                f"a fraction {args.keep_frac} of inputs kept at full density")
     print(json.dumps(report), flush=True)
