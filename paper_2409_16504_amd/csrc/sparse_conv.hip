@@ -201,14 +201,47 @@ __global__ __launch_bounds__(256) void k_subm_conv(const uint16_t* __restrict__ 
   for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k = 0; k < n_off; ++k) {
-    __syncthreads();
-    // stage W_k into LDS: COUT x CIN BF16, 16 bytes per thread per pass
+  // Software pipeline over the offsets: offset k + 1's weight slice (16 bytes per thread per pass,
+  // kWQ passes), neighbour indices and gathered input rows are loaded into registers while offset
+  // k's products run, so each offset waits on LDS only.
+  constexpr int kWQ = (COUT * CIN / 8 + 255) / 256;
+  uint4 wreg[kWQ];
+  uint4 arow[MB][KC];
+  auto load_offset = [&](int k) {
     const uint4* wsrc = reinterpret_cast<const uint4*>(wt + (int64_t)k * COUT * CIN);
-    for (int q = tid; q < COUT * CIN / 8; q += 256) {
-      const int o = (q * 8) / CIN, c = (q * 8) % CIN;
-      *reinterpret_cast<uint4*>(&s_w[o * LDW + c]) = wsrc[q];
+#pragma unroll
+    for (int i = 0; i < kWQ; ++i) {
+      const int q = tid + i * 256;
+      wreg[i] = q < COUT * CIN / 8 ? wsrc[q] : make_uint4(0u, 0u, 0u, 0u);
     }
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const int64_t v = vbase + mb * 16 + row;
+      const int32_t j = v < V ? nbr[(int64_t)k * V + v] : -1;
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc)
+        arow[mb][kc] = j >= 0 ? *reinterpret_cast<const uint4*>(x + (int64_t)j * CIN + kc * 32 + grp * 8)
+                              : make_uint4(0u, 0u, 0u, 0u);
+    }
+  };
+  if (n_off > 0) load_offset(0);
+  for (int k = 0; k < n_off; ++k) {
+    __syncthreads();                                   // the last offset's LDS reads are done
+    // stage W_k into LDS: COUT x CIN BF16
+#pragma unroll
+    for (int i = 0; i < kWQ; ++i) {
+      const int q = tid + i * 256;
+      if (q < COUT * CIN / 8) {
+        const int o = (q * 8) / CIN, c = (q * 8) % CIN;
+        *reinterpret_cast<uint4*>(&s_w[o * LDW + c]) = wreg[i];
+      }
+    }
+    uint4 acur[MB][KC];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) acur[mb][kc] = arow[mb][kc];
+    if (k + 1 < n_off) load_offset(k + 1);
     __syncthreads();
     bf16x8 bfr[KC][NB];
 #pragma unroll
@@ -217,19 +250,14 @@ __global__ __launch_bounds__(256) void k_subm_conv(const uint16_t* __restrict__ 
       for (int nb = 0; nb < NB; ++nb)
         bfr[kc][nb] = as_bf16x8(*reinterpret_cast<const uint4*>(&s_w[(nb * 16 + row) * LDW + kc * 32 + grp * 8]));
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-      const int64_t v = vbase + mb * 16 + row;
-      const int32_t j = v < V ? nbr[(int64_t)k * V + v] : -1;
+    for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
-        uint4 a = make_uint4(0u, 0u, 0u, 0u);
-        if (j >= 0) a = *reinterpret_cast<const uint4*>(x + (int64_t)j * CIN + kc * 32 + grp * 8);
-        const bf16x8 af = as_bf16x8(a);
+        const bf16x8 af = as_bf16x8(acur[mb][kc]);
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb)
           acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr[kc][nb], acc[mb][nb], 0, 0, 0);
       }
-    }
   }
   // epilogue: lane holds rows 4*grp + r of column row of each 16x16 block
 #pragma unroll
