@@ -277,7 +277,8 @@ int pcs_voxelize(pcs_context* ctx, const float* xyz, const float* rgb, int64_t n
                  pcs_voxels* vox, int64_t* n_voxels, void* stream);
 
 /* Device pointers owned by vox: coords[3][V] (int32), nbr[27][V] (int32), point_voxel[n] (int32),
- * features[V][32] (BF16). */
+ * features[V][32] (BF16; a pooled level computes none, its features pointer holds unspecified
+ * values: the parents' features come from pcs_pool_features). */
 int pcs_voxels_get(const pcs_voxels* vox, const int32_t** coords, const int32_t** nbr,
                    const int32_t** point_voxel, const uint16_t** features, int64_t* n_voxels);
 

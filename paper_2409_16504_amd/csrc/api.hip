@@ -905,8 +905,11 @@ int pcs_voxels_create(pcs_context* ctx, pcs_voxels** out) {
 
 void pcs_voxels_destroy(pcs_voxels* v) { delete v; }
 
-int pcs_voxelize(pcs_context* ctx, const float* xyz, const float* rgb, int64_t n, int32_t grid,
-                 pcs_voxels* vox, int64_t* n_voxels, void* stream) {
+namespace {
+// with_features false (a pooled level): coordinates, point -> voxel map, starts and kernel map only;
+// no features and no centroid
+int voxelize_impl(pcs_context* ctx, const float* xyz, const float* rgb, int64_t n, int32_t grid,
+                  pcs_voxels* vox, int64_t* n_voxels, void* stream, bool with_features) {
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (!ctx || !vox || !n_voxels) return fail(PCS_ERR_INVALID_ARG, "NULL argument");
   if (grid < 2 || grid > 1024 || (grid & (grid - 1)) != 0)
@@ -961,10 +964,10 @@ int pcs_voxelize(pcs_context* ctx, const float* xyz, const float* rgb, int64_t n
   PCS_TRY(ensure(ctx, vox->nbr, 27 * V * sizeof(int32_t), "kernel map"));
   PCS_HIP(launch_vox_build(vox->keys.as<uint32_t>(), vox->order.as<uint32_t>(), vox->flag.as<uint32_t>(),
                            vox->excl.as<uint32_t>(), n, (int64_t)V, xyz, rgb, grid, vox->start.as<uint32_t>(),
-                           vox->coords.as<int32_t>(), vox->feat.as<uint16_t>(),
+                           vox->coords.as<int32_t>(), with_features ? vox->feat.as<uint16_t>() : nullptr,
                            vox->point_voxel.as<int32_t>(), vox->hkeys.as<uint32_t>(),
                            vox->hvals.as<int32_t>(), log2cap, vox->nbr.as<int32_t>(), s));
-  PCS_HIP(launch_centroid(xyz, n, vox->centroid.as<double>(), vox->centroid.as<float>() + 8, s));
+  if (with_features) PCS_HIP(launch_centroid(xyz, n, vox->centroid.as<double>(), vox->centroid.as<float>() + 8, s));
   vox->n = n;
   vox->V = (int64_t)V;
   vox->log2cap = log2cap;
@@ -972,6 +975,12 @@ int pcs_voxelize(pcs_context* ctx, const float* xyz, const float* rgb, int64_t n
   vox->valid = true;
   *n_voxels = (int64_t)V;
   return PCS_OK;
+}
+}  // namespace
+
+int pcs_voxelize(pcs_context* ctx, const float* xyz, const float* rgb, int64_t n, int32_t grid,
+                 pcs_voxels* vox, int64_t* n_voxels, void* stream) {
+  return voxelize_impl(ctx, xyz, rgb, n, grid, vox, n_voxels, stream, true);
 }
 
 int pcs_voxels_get(const pcs_voxels* vox, const int32_t** coords, const int32_t** nbr,
@@ -1035,8 +1044,8 @@ int pcs_pool(pcs_context* ctx, const pcs_voxels* child, pcs_voxels* parent, int6
   // the child voxels' centres, voxelised on the grid of half the resolution, give the parents
   PCS_TRY(ensure(ctx, parent->centres, 3 * Vc * sizeof(float), "child voxel centres"));
   PCS_HIP(launch_voxel_centres(child->coords.as<int32_t>(), Vc, child->grid, parent->centres.as<float>(), s));
-  PCS_TRY(pcs_voxelize(ctx, parent->centres.as<float>(), parent->centres.as<float>(), Vc, child->grid / 2,
-                       parent, n_parents, stream));
+  PCS_TRY(voxelize_impl(ctx, parent->centres.as<float>(), parent->centres.as<float>(), Vc, child->grid / 2,
+                        parent, n_parents, stream, false));
   PCS_TRY(ensure(ctx, parent->up_fwd, 8 * Vc * sizeof(int32_t), "upsampling table"));
   PCS_TRY(ensure(ctx, parent->up_bwd, 8 * parent->V * sizeof(int32_t), "upsampling adjoint table"));
   PCS_HIP(launch_up_tables(child->coords.as<int32_t>(), parent->point_voxel.as<int32_t>(), Vc, parent->V,

@@ -91,38 +91,43 @@ __global__ void k_vox_reduce(const uint32_t* __restrict__ keys, const uint32_t* 
   const uint32_t b = start[v], e = (v + 1 < V) ? start[v + 1] : (uint32_t)n;
   const uint32_t key = keys[b];
   const int cx = (int)(key >> (2 * gb)), cy = (int)(key >> gb) & (grid - 1), cz = (int)key & (grid - 1);
-  float s[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  for (uint32_t j = b; j < e; ++j) {
-    const uint32_t i = order[j];
-    point_voxel[i] = (int32_t)v;
-    s[0] += rgb[i];
-    s[1] += rgb[n + i];
-    s[2] += rgb[2 * n + i];
-    const float half = 0.5f * (float)grid;
-    const float px = xyz[i], py = xyz[n + i], pz = xyz[2 * n + i];
-    s[3] += (px + 1.0f) * half - ((float)cx + 0.5f);
-    s[4] += (py + 1.0f) * half - ((float)cy + 0.5f);
-    s[5] += (pz + 1.0f) * half - ((float)cz + 0.5f);
-    s[6] += px;
-    s[7] += py;
-    s[8] += pz;
-  }
-  const float inv = 1.0f / (float)(e - b);
   coords[v] = cx;
   coords[V + v] = cy;
   coords[2 * V + v] = cz;
-  uint16_t f[32];
+  if (!feat) {
+    // a pooled level: the parents' features come from their children, not from these points
+    for (uint32_t j = b; j < e; ++j) point_voxel[order[j]] = (int32_t)v;
+  } else {
+    float s[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (uint32_t j = b; j < e; ++j) {
+      const uint32_t i = order[j];
+      point_voxel[i] = (int32_t)v;
+      s[0] += rgb[i];
+      s[1] += rgb[n + i];
+      s[2] += rgb[2 * n + i];
+      const float half = 0.5f * (float)grid;
+      const float px = xyz[i], py = xyz[n + i], pz = xyz[2 * n + i];
+      s[3] += (px + 1.0f) * half - ((float)cx + 0.5f);
+      s[4] += (py + 1.0f) * half - ((float)cy + 0.5f);
+      s[5] += (pz + 1.0f) * half - ((float)cz + 0.5f);
+      s[6] += px;
+      s[7] += py;
+      s[8] += pz;
+    }
+    const float inv = 1.0f / (float)(e - b);
+    uint16_t f[32];
 #pragma unroll
-  for (int c = 0; c < 32; ++c) f[c] = c < 9 ? f32_to_bf16(s[c] * inv) : (uint16_t)0;
-  uint4* dst = reinterpret_cast<uint4*>(feat + v * 32);
+    for (int c = 0; c < 32; ++c) f[c] = c < 9 ? f32_to_bf16(s[c] * inv) : (uint16_t)0;
+    uint4* dst = reinterpret_cast<uint4*>(feat + v * 32);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    uint4 w;
-    w.x = f[8 * q + 0] | ((uint32_t)f[8 * q + 1] << 16);
-    w.y = f[8 * q + 2] | ((uint32_t)f[8 * q + 3] << 16);
-    w.z = f[8 * q + 4] | ((uint32_t)f[8 * q + 5] << 16);
-    w.w = f[8 * q + 6] | ((uint32_t)f[8 * q + 7] << 16);
-    dst[q] = w;
+    for (int q = 0; q < 4; ++q) {
+      uint4 w;
+      w.x = f[8 * q + 0] | ((uint32_t)f[8 * q + 1] << 16);
+      w.y = f[8 * q + 2] | ((uint32_t)f[8 * q + 3] << 16);
+      w.z = f[8 * q + 4] | ((uint32_t)f[8 * q + 5] << 16);
+      w.w = f[8 * q + 6] | ((uint32_t)f[8 * q + 7] << 16);
+      dst[q] = w;
+    }
   }
   // insert into the hash table under the 10-bit-field key the kernel map looks up (keys are
   // unique; linear probing always finds a free slot because the table holds at most half its
