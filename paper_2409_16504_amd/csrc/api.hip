@@ -644,7 +644,7 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
     PCS_HIP(launch_sort(ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(), ctx->dkeys_alt.as<uint32_t>(),
                         ctx->dvals_alt.as<uint32_t>(), cn, 32, ctx->dsort_scratch.p, s, &unused, d_depth,
                         true, true, depth_hist, 0, capacity > 0 ? -1 : 1, nullptr, 0, d_err,
-                        ctx->wait_limit));
+                        ctx->wait_limit, nullptr, true));
   }
   uint64_t m64 = 0;
   if (cn > 0 && capacity == 0) {
@@ -656,7 +656,8 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
       bool unused = false;
       PCS_HIP(launch_sort(ctx->dkeys.as<uint32_t>(), ctx->dvals.as<uint32_t>(), ctx->dkeys_alt.as<uint32_t>(),
                           ctx->dvals_alt.as<uint32_t>(), cn, 32, ctx->dsort_scratch.p, s, &unused, d_depth,
-                          true, true, depth_hist, 1, depth_passes, nullptr, 0, d_err, ctx->wait_limit));
+                          true, true, depth_hist, 1, depth_passes, nullptr, 0, d_err, ctx->wait_limit,
+                          nullptr, true));
     }
     if (m64 >= (uint64_t(1) << 30))
       return fail(PCS_ERR_UNSUPPORTED, "instance count " + std::to_string(m64) + " is not below 2^30");

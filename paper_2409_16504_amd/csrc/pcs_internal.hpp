@@ -240,14 +240,16 @@ size_t sort_scratch_bytes(int64_t m);
 // back into plain ones).
 // err (may be null): the passes return at once if it is set, and a look-back that waits more than
 // spin_limit rounds (0 = the default bound) sets kErrSpin. m_dev (may be null): the element count
-// is read on the device (at most m, which then sizes the launch).
+// is read on the device (at most m, which then sizes the launch). wide (32-bit keys): scatter
+// partitions run as 1024 threads x 4 keys instead of 512 x 8 (same partitions, same result; faster
+// for the depth sort of a frame's splats, slower for the tile sort of its instances).
 template <typename K>
 hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int bits, void* scratch,
                        hipStream_t s, bool* result_in_alt, const uint32_t* live_passes = nullptr,
                        bool scratch_cleared = false, bool hist_ready = false,
                        const uint32_t* ext_hist = nullptr, int pass_begin = 0, int pass_end = -1,
                        uint32_t* ranges = nullptr, int64_t n_tiles = 0, uint32_t* err = nullptr,
-                       uint32_t spin_limit = 0, const uint64_t* m_dev = nullptr);
+                       uint32_t spin_limit = 0, const uint64_t* m_dev = nullptr, bool wide = false);
 // Words at the start of sort scratch that must be zero before a sort of m pairs (cleared by the
 // sort itself unless the caller has cleared them and says so).
 int64_t sort_clear_words(int64_t m);

@@ -890,8 +890,9 @@ hipError_t launch_scan_binning(int64_t n, int n_cams, int TX, int64_t tiles_per_
 }
 
 
-// Scatter partitions of 4096 keys: 32-bit keys 512 threads x 8, 64-bit keys 256 x 16. Scratch is
-// sized (and cleared) for kSortPartMin-key partitions.
+// Scatter partitions of 4096 keys: 32-bit keys 512 threads x 8 (1024 x 4 when the caller asks for
+// the wide shape), 64-bit keys 256 x 16. Scratch is sized (and cleared) for kSortPartMin-key
+// partitions.
 constexpr int kSortPartMin = 4096;
 template <typename K> struct SweepShape {
   static constexpr int threads = sizeof(K) == 4 ? 512 : 256;
@@ -917,7 +918,7 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
                        hipStream_t s, bool* result_in_alt, const uint32_t* live_passes,
                        bool scratch_cleared, bool hist_ready, const uint32_t* ext_hist,
                        int pass_begin, int pass_end, uint32_t* ranges, int64_t n_tiles,
-                       uint32_t* err, uint32_t spin_limit, const uint64_t* m_dev) {
+                       uint32_t* err, uint32_t spin_limit, const uint64_t* m_dev, bool wide) {
   *result_in_alt = false;
   if (m <= 1 || bits <= 0) return hipSuccess;
   // the chained scan's status words carry 30-bit counts
@@ -956,13 +957,24 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
     std::swap(vi, vo);
   }
   if (ranges && (sizeof(K) != 4 || n_tiles <= 0 || n_tiles > 0xFFFFFFFFll)) return hipErrorInvalidValue;
+  // the same 4096-key partitions as 1024 threads x 4 keys: twice the wavefronts per CU to hide
+  // each pass's load, look-back and scatter latency where the partitions are few (one per CU)
+  auto sweep = k_onesweep<K, kSweepThreads, kSweepItems>;
+  int sweep_threads = kSweepThreads;
+  if constexpr (sizeof(K) == 4) {
+    static_assert(1024 * 4 == SweepShape<uint32_t>::part, "the wide shape keeps the partition size");
+    if (wide) {
+      sweep = k_onesweep<K, 1024, 4>;
+      sweep_threads = 1024;
+    }
+  }
   for (int p = pass_begin; p < pass_end; ++p) {
     uint32_t* st = (p & 1) ? status1 : status0;
     uint32_t* st_next = (p & 1) ? status0 : status1;
     uint32_t* gst = (p & 1) ? gstatus1 : gstatus0;
     uint32_t* gst_next = (p & 1) ? gstatus0 : gstatus1;
     uint32_t* rng = p == n_passes - 1 ? ranges : nullptr;
-    hipLaunchKernelGGL((k_onesweep<K, kSweepThreads, kSweepItems>), dim3((unsigned)sweep_parts), dim3(kSweepThreads), 0, s, ki, vi, ko, vo, (uint32_t)m,
+    hipLaunchKernelGGL(sweep, dim3((unsigned)sweep_parts), dim3(sweep_threads), 0, s, ki, vi, ko, vo, (uint32_t)m,
                        8 * p, std::min(8, bits - 8 * p), rows + p * kBins, copies, copy_stride, st, st_next, gst, gst_next, live_passes, p,
                        rng, (uint32_t)n_tiles, err, spin_limit ? spin_limit : kSpinLimit, m_dev);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -975,11 +987,11 @@ hipError_t launch_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t m, int 
 template hipError_t launch_sort<uint32_t>(uint32_t*, uint32_t*, uint32_t*, uint32_t*, int64_t, int,
                                           void*, hipStream_t, bool*, const uint32_t*, bool, bool,
                                           const uint32_t*, int, int, uint32_t*, int64_t, uint32_t*,
-                                          uint32_t, const uint64_t*);
+                                          uint32_t, const uint64_t*, bool);
 template hipError_t launch_sort<uint64_t>(uint64_t*, uint32_t*, uint64_t*, uint32_t*, int64_t, int,
                                           void*, hipStream_t, bool*, const uint32_t*, bool, bool,
                                           const uint32_t*, int, int, uint32_t*, int64_t, uint32_t*,
-                                          uint32_t, const uint64_t*);
+                                          uint32_t, const uint64_t*, bool);
 
 hipError_t launch_ranges(const uint32_t* keys, int64_t m, int64_t n_tiles, uint32_t* ranges,
                          hipStream_t s, const uint64_t* m_dev, const uint32_t* err) {
