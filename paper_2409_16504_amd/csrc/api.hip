@@ -154,6 +154,7 @@ struct pcs_context {
   DevBuf knn_scratch, conv_tmp, wt_tmp, shade_cams, tile_hist, probe;
   uint32_t* host_small = nullptr;   // pinned 4 KiB: readback of the small device words
   uint32_t seq = 0;                 // frame sequence number (never 0 once used)
+  void* small_reset_for = nullptr;  // the small-word buffer whose projection slots are reset
   uint32_t wait_limit = 0;          // look-back wait bound of the ordering kernels (0: default)
   float* noalloc_sgrad = nullptr;   // device address of `scratch` on this context's device
   Allocator alloc;                  // where new workspace comes from (default: hipMalloc)
@@ -611,7 +612,19 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
     PCS_TRY(ensure(ctx, ctx->sort_scratch, sort_scratch_bytes(capacity), "sort scratch"));
   }
   uint32_t* depth_hist = ctx->tile_hist.as<uint32_t>() + kTileHistWords;
-  PCS_HIP(launch_init_small(ctx->small.as<uint32_t>(), dc.data(), n_cams, st->dcams.as<DevCamera>(), s, d_err));
+  // Cameras reach the projection as kernel arguments and it resets the frame's error word and
+  // instance total; the projection slots were reset by the previous frame's tile order. A set-up
+  // kernel runs first only for more cameras than one launch carries, for a frame without Gaussians
+  // (no projection runs) and where the slots are not known to be reset (a new buffer, or a frame
+  // that ended on the host before its tile order was queued: the mark stays cleared until then).
+  const bool arg_cams = n_cams <= kArgCams && cn > 0;
+  const bool slots_reset = ctx->small_reset_for == ctx->small.p;
+  ctx->small_reset_for = nullptr;
+  if (!arg_cams || !slots_reset)
+    PCS_HIP(launch_init_small(ctx->small.as<uint32_t>(), dc.data(), n_cams, st->dcams.as<DevCamera>(), s, d_err));
+  if (cn == 0) ctx->small_reset_for = ctx->small.p;      // no projection: the slots stay reset
+  CamBatch batch{};
+  for (int c = 0; arg_cams && c < n_cams; ++c) batch.c[c] = dc[c];
   {
     // the projection also clears what the depth sort and the scan need zeroed
     ClearSpans clear;
@@ -624,7 +637,7 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
     StageTimer tm(ctx, ST_PROJECT, s);
     PCS_HIP(launch_project(n, n_cams, st->dcams.as<DevCamera>(), dopt, *g, st->rec.as<float4>(),
                            ctx->zbits.as<uint32_t>(), ctx->rect.as<uint2>(), narrow_rect, d_zrange, d_counts,
-                           clear, s));
+                           clear, s, arg_cams ? &batch : nullptr, d_err, d_total));
   }
   // The instance total reaches the host from the first depth-sort kernel (a store into a pinned
   // word, which the host polls); the (camera, depth) order needs nothing from the host (the depth
@@ -715,8 +728,10 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
     if ((capacity == 0 && m <= 1) || tile_bits == 0)
       PCS_HIP(launch_ranges(st->keys.as<uint32_t>(), m, total_tiles, st->ranges.as<uint32_t>(), s, m_dev, d_err));
     // the ordering is done: the frame's error word goes to the host
+    // and the projection slots are reset for the next frame
     PCS_HIP(launch_tile_order(st->ranges.as<uint32_t>(), total_tiles, st->order.as<uint32_t>(), s, d_err,
-                              st->host_dev + 2, st->seq));
+                              st->host_dev + 2, st->seq, ctx->small.as<uint32_t>() + 2));
+    if (total_tiles > 0) ctx->small_reset_for = ctx->small.p;
   }
   {
     StageTimer tm(ctx, ST_COMPOSITE, s, false);   // the kernel's own start and end

@@ -156,25 +156,34 @@ hipError_t launch_fill_f32(float* p, float value, int64_t n, hipStream_t s);
 constexpr int kZSlots = 64;
 // small[0..1] a u64 total written by the scan, small[2..2+2 kZSlots) depth-bit range slots,
 // small[kCountWord..) kZSlots u64 partial instance counts, small[kDepthWord..+3) the depth sort's
-// pass count, depth bits and minimum depth bits (written on the device); slots reset by
-// launch_init_small.
+// pass count, depth bits and minimum depth bits (written on the device). The range slots and
+// counts (kSlotWords from word 2) are reset for the next frame by the frame's tile-order kernel,
+// after their only reader, or by launch_init_small.
 constexpr int kCountWord = 2 + 2 * kZSlots;
 constexpr int kDepthWord = kCountWord + 2 * kZSlots;
 constexpr int kVoxErrWord = kDepthWord + 3;   // error word of a voxelisation
 constexpr int kSmallWords = kDepthWord + 4;
-// Cameras travel to the device as kernel arguments, kArgCams per launch: the frame's first launch
-// resets the small words and writes the first batch into dst.
+constexpr int kSlotWords = kDepthWord - 2;
+// Cameras travel to the device as kernel arguments, kArgCams per launch.
 constexpr int kArgCams = 8;
 struct CamBatch {
   DevCamera c[kArgCams];
 };
-// err (may be null): the frame's error word, cleared with the small words.
+// Resets the frame's error word (err, may be null) and, when small is set, the instance total and
+// the projection slots; writes the batch of up to kArgCams cameras into dst. Needed only where the
+// frame cannot do this itself: more than kArgCams cameras, no Gaussians, or slots whose last
+// frame did not reach its tile order.
 hipError_t launch_init_small(uint32_t* small, const DevCamera* cams, int n_cams, DevCamera* dst,
                              hipStream_t s, uint32_t* err = nullptr);
-hipError_t launch_project(int64_t n, int n_cams, const DevCamera* cams, const DevOptions& opt,
+// zrange / count_slots: the projection slots (reset beforehand). arg_cams (may be null; else
+// n_cams <= kArgCams): the cameras as kernel arguments, which the projection reads instead of
+// cams and also writes to cams for the later kernels. err, total (may be null): the frame's error
+// word and the instance total, reset (nothing in the frame writes them before the projection ends).
+hipError_t launch_project(int64_t n, int n_cams, DevCamera* cams, const DevOptions& opt,
                           const pcs_gaussians& g, float4* rec, uint32_t* zbits, uint2* rect,
                           bool narrow_rect, uint32_t* zrange, unsigned long long* count_slots,
-                          const ClearSpans& clear, hipStream_t s);
+                          const ClearSpans& clear, hipStream_t s, const CamBatch* arg_cams = nullptr,
+                          uint32_t* err = nullptr, uint64_t* total = nullptr);
 
 // Exclusive scan of n u32 values in[gather[j]] (no gather: in[j]); writes out[n] and *total (u64).
 // gather is gather1 when sel is set and *sel is odd, else gather0. Scratch from scan_scratch_bytes.
@@ -264,9 +273,10 @@ hipError_t launch_ranges(const uint32_t* keys, int64_t m, int64_t n_tiles, uint3
 // seq << 32 | the frame's error word; if that word is set, every tile's run is left empty instead
 // (the order is then the identity), so that compositing and its adjoint read nothing the failed
 // stage produced.
+// slots (may be null): the projection slots (kSlotWords words), reset for the next frame.
 hipError_t launch_tile_order(uint32_t* ranges, int64_t n_tiles, uint32_t* order, hipStream_t s,
                              const uint32_t* err = nullptr, unsigned long long* report = nullptr,
-                             uint32_t seq = 0);
+                             uint32_t seq = 0, uint32_t* slots = nullptr);
 
 hipError_t launch_canonical_keys(const uint32_t* keys, const uint32_t* vals, int64_t m, int64_t n,
                                  int64_t tiles_per_cam, const float4* rec, uint64_t* out,

@@ -28,19 +28,39 @@ __global__ void k_fill_f32(float* __restrict__ p, float value, int64_t n) {
 
 __device__ __forceinline__ bool fin(float x) { return isfinite(x); }
 
+// Frame words written by block (0, 0) of the projection: the error word and the instance total
+// reset, and (ARG_CAMS) the cameras of the kernel arguments copied to cams_out for the later kernels.
+template <bool ARG_CAMS>
+__device__ __forceinline__ void frame_words(const CamBatch& arg_cams, DevCamera* __restrict__ cams_out,
+                                            uint32_t* __restrict__ err, uint64_t* __restrict__ total) {
+  if (blockIdx.x != 0 || blockIdx.y != 0) return;
+  const int t = threadIdx.x;
+  if (t == 0 && err) *err = 0u;
+  if (t == 0 && total) *total = 0u;
+  if constexpr (ARG_CAMS) {
+    constexpr int kWords = (int)(sizeof(DevCamera) / 4);
+    if (t < (int)gridDim.y * kWords)
+      reinterpret_cast<uint32_t*>(cams_out)[t] = reinterpret_cast<const uint32_t*>(arg_cams.c)[t];
+  }
+}
+
+// ARG_CAMS: the cameras come as kernel arguments (at most kArgCams), else from cams.
+template <bool ARG_CAMS>
 __global__ __launch_bounds__(256) void k_project(
-    int64_t n, const DevCamera* __restrict__ cams, DevOptions opt,
+    int64_t n, DevCamera* __restrict__ cams, DevOptions opt,
     const float* __restrict__ mean, const float* __restrict__ quat,
     const float* __restrict__ scale, const float* __restrict__ opac,
     const float* __restrict__ rgb, const float* __restrict__ nrm, float4* __restrict__ rec,
     uint32_t* __restrict__ zbits_out, uint2* __restrict__ rect, bool narrow_rect,
     uint32_t* __restrict__ zrange,
-    unsigned long long* __restrict__ count_slots, ClearSpans clear) {
+    unsigned long long* __restrict__ count_slots, ClearSpans clear, CamBatch arg_cams,
+    uint32_t* __restrict__ err, uint64_t* __restrict__ total) {
   clear_spans(clear, ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x,
               (int64_t)gridDim.x * gridDim.y * blockDim.x);
+  frame_words<ARG_CAMS>(arg_cams, cams, err, total);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int c = blockIdx.y;
-  const DevCamera& cam = cams[c];
+  const DevCamera& cam = ARG_CAMS ? arg_cams.c[c] : cams[c];
   const int64_t out = (int64_t)c * n + i;
   bool visible = false;
   uint32_t zbits = 0, my_count = 0;
@@ -95,7 +115,7 @@ __global__ __launch_bounds__(256) void k_project(
     }
   }
   // depth-bit range and instance total of the block: block reduction, then one atomic each into
-  // one of kZSlots slots (spreading the atomics; the host folds the slots)
+  // one of kZSlots slots (spreading the atomics; the depth-key pass folds the slots)
   __shared__ uint32_t s_lo[4], s_hi[4];
   __shared__ unsigned long long s_cnt[4];
   uint32_t lo = visible ? zbits : 0xFFFFFFFFu, hi = visible ? zbits : 0u;
@@ -168,15 +188,24 @@ hipError_t launch_init_small(uint32_t* small, const DevCamera* cams, int n_cams,
   return hipSuccess;
 }
 
-hipError_t launch_project(int64_t n, int n_cams, const DevCamera* cams, const DevOptions& opt,
+hipError_t launch_project(int64_t n, int n_cams, DevCamera* cams, const DevOptions& opt,
                           const pcs_gaussians& g, float4* rec, uint32_t* zbits, uint2* rect,
                           bool narrow_rect, uint32_t* zrange, unsigned long long* count_slots,
-                          const ClearSpans& clear, hipStream_t s) {
+                          const ClearSpans& clear, hipStream_t s, const CamBatch* arg_cams,
+                          uint32_t* err, uint64_t* total) {
   if (n <= 0 || n_cams <= 0) return hipSuccess;
+  if (arg_cams && n_cams > kArgCams) return hipErrorInvalidValue;
+  static_assert(kArgCams * sizeof(DevCamera) / 4 <= 256, "block (0, 0) copies the cameras");
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)n_cams);
-  hipLaunchKernelGGL(k_project, grid, dim3(256), 0, s, n, cams, opt, g.mean, g.quat, g.scale,
-                     g.opacity, g.rgb, g.normal, rec, zbits, rect, narrow_rect, zrange, count_slots,
-                     clear);
+  const CamBatch none{};
+  if (arg_cams)
+    hipLaunchKernelGGL(k_project<true>, grid, dim3(256), 0, s, n, cams, opt, g.mean, g.quat, g.scale,
+                       g.opacity, g.rgb, g.normal, rec, zbits, rect, narrow_rect, zrange, count_slots,
+                       clear, *arg_cams, err, total);
+  else
+    hipLaunchKernelGGL(k_project<false>, grid, dim3(256), 0, s, n, cams, opt, g.mean, g.quat, g.scale,
+                       g.opacity, g.rgb, g.normal, rec, zbits, rect, narrow_rect, zrange, count_slots,
+                       clear, none, err, total);
   return hipGetLastError();
 }
 

@@ -737,9 +737,11 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(uint32_t* __restri
                                                               uint32_t* __restrict__ order,
                                                               const uint32_t* __restrict__ err,
                                                               unsigned long long* __restrict__ report,
-                                                              uint32_t seq) {
+                                                              uint32_t seq, uint32_t* __restrict__ slots) {
   __shared__ uint32_t s_cnt[kOrderBuckets + 1];
   const int tid = threadIdx.x, lane = lane_id();
+  // the projection slots have been read (by the depth-key pass): reset for the next frame
+  if (slots && tid < kSlotWords) slots[tid] = tid < kZSlots ? 0xFFFFFFFFu : 0u;
   // the frame's ordering is complete here: its error word goes to the host (one system-scope
   // store), and a failed frame has no valid runs to order
   if (tid == 0 && report)
@@ -1002,10 +1004,12 @@ hipError_t launch_ranges(const uint32_t* keys, int64_t m, int64_t n_tiles, uint3
 }
 
 hipError_t launch_tile_order(uint32_t* ranges, int64_t n_tiles, uint32_t* order, hipStream_t s,
-                             const uint32_t* err, unsigned long long* report, uint32_t seq) {
+                             const uint32_t* err, unsigned long long* report, uint32_t seq,
+                             uint32_t* slots) {
   if (n_tiles == 0) return hipSuccess;
+  static_assert(kSlotWords <= kOrderThreads, "one thread per slot word");
   hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, s, ranges, n_tiles, order, err,
-                     report, seq);
+                     report, seq, slots);
   return hipGetLastError();
 }
 

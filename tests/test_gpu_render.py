@@ -144,6 +144,36 @@ def test_empty_and_culled_scenes(R):
     assert np.all(imgs["rgb"] == 0) and np.all(imgs["depth"] == 0)
 
 
+def test_consecutive_frames_on_one_context():
+    """Frames of different clouds, depth ranges and camera counts in a row on one context and one
+    state: each frame's projection slots (depth-bit range and instance counts) must start reset,
+    whether the previous frame reset them (its tile order), the set-up kernel did (more than eight
+    cameras, an empty cloud) or the context is new. Keys, values and ranges bit-exact, images to
+    the oracle's bar, for every frame."""
+    import paper_2409_16504_amd as P
+    R2 = P.Renderer(0)
+    st = P.RenderState(R2)
+    rng = np.random.default_rng(41)
+    ga, cams_a = c1_scene()
+    gb = random_gaussians(3000, rng, mean_range=0.6, scale_range=(0.005, 0.06))
+    cams_b = [look_at_camera([0.5, 0.3, 5.5], width=96, height=80)]      # a farther depth range
+    cams_c = orbit_cameras(12, rng, width=40, height=36)
+    g0 = {k: v[..., :0] for k, v in ga.items()}
+    o = P.default_options()
+    for g, cams, n_tiles, zmax in [(ga, cams_a, 64, 4.0), (gb, cams_b, 30, 7.0), (ga, cams_c, 12 * 9, 5.0),
+                                   (gb, cams_b, 30, 7.0), (g0, cams_a, 64, 4.0), (ga, cams_a, 64, 4.0),
+                                   (gb, cams_b, 30, 7.0)]:
+        out = R2.render(to_torch(g), cams, o, state=st)
+        imgs = {k: v.cpu().numpy() for k, v in out.items()}
+        bins = R2.bins(st)
+        ref = oracle.render(g, cams, mode="ref")
+        check_bins(bins, ref, n_tiles)
+        if bins["keys"].size:
+            check_images(imgs, bins, ref, zmax)
+    del st
+    R2.close()
+
+
 def test_nonfinite_gaussians_never_reach_pixels(R):
     g, cams = c1_scene()
     g = {k: v.copy() for k, v in g.items()}
