@@ -617,12 +617,17 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
   // kernel runs first only for more cameras than one launch carries, for a frame without Gaussians
   // (no projection runs) and where the slots are not known to be reset (a new buffer, or a frame
   // that ended on the host before its tile order was queued: the mark stays cleared until then).
+  // A frame captured into a HIP graph always starts with the set-up kernel, so that every replay
+  // resets the slots itself, and leaves the mark alone (captured launches do not run).
+  hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
+  PCS_HIP(hipStreamIsCapturing(s, &capture));
+  const bool capturing = capture != hipStreamCaptureStatusNone;
   const bool arg_cams = n_cams <= kArgCams && cn > 0;
-  const bool slots_reset = ctx->small_reset_for == ctx->small.p;
-  ctx->small_reset_for = nullptr;
+  const bool slots_reset = !capturing && ctx->small_reset_for == ctx->small.p;
+  if (!capturing) ctx->small_reset_for = nullptr;
   if (!arg_cams || !slots_reset)
     PCS_HIP(launch_init_small(ctx->small.as<uint32_t>(), dc.data(), n_cams, st->dcams.as<DevCamera>(), s, d_err));
-  if (cn == 0) ctx->small_reset_for = ctx->small.p;      // no projection: the slots stay reset
+  if (cn == 0 && !capturing) ctx->small_reset_for = ctx->small.p;   // no projection: the slots stay reset
   CamBatch batch{};
   for (int c = 0; arg_cams && c < n_cams; ++c) batch.c[c] = dc[c];
   {
@@ -731,7 +736,7 @@ int pcs_render_forward(pcs_context* ctx, const pcs_gaussians* g, const pcs_camer
     // and the projection slots are reset for the next frame
     PCS_HIP(launch_tile_order(st->ranges.as<uint32_t>(), total_tiles, st->order.as<uint32_t>(), s, d_err,
                               st->host_dev + 2, st->seq, ctx->small.as<uint32_t>() + 2));
-    if (total_tiles > 0) ctx->small_reset_for = ctx->small.p;
+    if (total_tiles > 0 && !capturing) ctx->small_reset_for = ctx->small.p;
   }
   {
     StageTimer tm(ctx, ST_COMPOSITE, s, false);   // the kernel's own start and end

@@ -125,7 +125,8 @@ def test_wait_bound_running_out_fails_the_frame(R, capacity):
 def test_graph_capture_replays_capacity_frame(R):
     """A capacity-mode frame captured in a HIP graph (through torch.cuda.CUDAGraph) and replayed
     gives the plain render's key lists and images bit for bit, on every replay, with eager work and
-    synchronisations between the replays."""
+    synchronisations between the replays, one of them an eager render of another state on the same
+    context (which must match its own reference too)."""
     import torch
     import paper_2409_16504_amd as P
     g = surface_gaussians(800_000, 1002)
@@ -142,11 +143,18 @@ def test_graph_capture_replays_capacity_frame(R):
         R.render(tg, cams, P.default_options(), state=st, out=out, capacity=True)
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
+    gs, cs = c1_scene()
+    tgs = to_torch(gs)
+    st_small, small_ref = _render(R, tgs, cs, False)
+    small_bins = R.bins(st_small)
     graph = torch.cuda.CUDAGraph()
     print("capturing a capacity-mode frame", flush=True)
     with torch.cuda.graph(graph):
         R.render(tg, cams, P.default_options(), state=st, out=out, capacity=True)
     for rep in range(3):
+        if rep == 1:                                  # an eager frame between replays
+            st_e, imgs_e = _render(R, tgs, cs, False)
+            _same(small_ref, small_bins, imgs_e, R.bins(st_e))
         for v in out.values():
             v.fill_(-1.0)                             # eager work between replays
         torch.cuda.synchronize()
