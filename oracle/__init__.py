@@ -96,15 +96,17 @@ def project_f32(g: dict, cam, opts=None, tile=16) -> dict:
     """Exact-FP32 projection of every Gaussian through one camera."""
     n = g["opacity"].shape[-1]
     W, H = _cam_wh(cam)
-    out = {k: np.zeros(n, np.float32) for k in ("u", "v", "z", "A", "B", "C", "radius")}
+    out = {k: np.zeros(n, np.float32) for k in ("u", "v", "z", "A", "B", "C")}
+    ext = np.zeros((2, n), np.float32)
     out["valid"] = np.zeros(n, np.uint8)
     out["rect"] = np.zeros((4, n), np.int32)
     out["count"] = np.zeros(n, np.uint32)
     arrs = [_f32(g, k) for k in ("mean", "quat", "scale", "opacity", "rgb", "normal")]
     lib().orc_project_f32(n, *[_p(a) for a in arrs], _p(camera_vector(cam)), W, H, tile,
                           _p(options_vector(opts)), _p(out["valid"]), _p(out["u"]), _p(out["v"]),
-                          _p(out["z"]), _p(out["A"]), _p(out["B"]), _p(out["C"]), _p(out["radius"]),
+                          _p(out["z"]), _p(out["A"]), _p(out["B"]), _p(out["C"]), _p(ext),
                           _p(out["rect"]), _p(out["count"]))
+    out["ex"], out["ey"] = ext[0], ext[1]
     return out
 
 
@@ -112,7 +114,8 @@ def project_f64(g: dict, cam, opts=None, tile=16, cov6=None) -> dict:
     """FP64 projection; parameters are read as float64 (``cov6`` overrides quat/scale)."""
     n = g["opacity"].shape[-1]
     W, H = _cam_wh(cam)
-    out = {k: np.zeros(n, np.float64) for k in ("u", "v", "z", "A", "B", "C", "radius")}
+    out = {k: np.zeros(n, np.float64) for k in ("u", "v", "z", "A", "B", "C")}
+    ext = np.zeros((2, n), np.float64)
     out["valid"] = np.zeros(n, np.uint8)
     out["rect"] = np.zeros((4, n), np.int32)
     out["count"] = np.zeros(n, np.uint32)
@@ -123,8 +126,9 @@ def project_f64(g: dict, cam, opts=None, tile=16, cov6=None) -> dict:
     lib().orc_project_f64(n, _p(d["mean"]), _p(d["quat"]), _p(d["scale"]), _p(c6), _p(d["opacity"]),
                           _p(camera_vector(cam, np.float64)), W, H, tile, _p(options_vector(opts)),
                           _p(out["valid"]), _p(out["u"]), _p(out["v"]), _p(out["z"]), _p(out["A"]),
-                          _p(out["B"]), _p(out["C"]), _p(out["radius"]), _p(out["rect"]),
+                          _p(out["B"]), _p(out["C"]), _p(ext), _p(out["rect"]),
                           _p(out["count"]), _p(out["cov2d"]), _p(out["zf"]))
+    out["ex"], out["ey"] = ext[0], ext[1]
     return out
 
 

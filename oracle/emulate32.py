@@ -22,12 +22,14 @@ The sequence, step by step:
   (8) P = M Sigma with P_rk = (M_r0 S_0k + M_r1 S_1k) + M_r2 S_2k; a = ((P_00 M_00 + P_01 M_01)
       + P_02 M_02) + lowpass, b = (P_00 M_10 + P_01 M_11) + P_02 M_12, c likewise from row 1 plus
       lowpass.
-  (9) det = a c - b b; A = c / det, B = -(b / det), C = a / det; mid = 0.5 (a + c);
-      lambda = mid + sqrt(max(mid mid - det, 0)); r = ceil(sigma_cut sqrt(lambda)).
- (10) tile range floor((u - r) / 16) .. floor((u + r) / 16) clamped to the frame, likewise in y.
+  (9) det = a c - b b; A = c / det, B = -(b / det), C = a / det; half extents of the
+      sigma_cut ellipse's axis-aligned box e_x = (sigma_cut sqrt(a)) 1.001 + 0.01 and
+      e_y = (sigma_cut sqrt(c)) 1.001 + 0.01.
+ (10) tile range floor((u - e_x) / 16) .. floor((u + e_x) / 16) clamped to the frame, likewise in
+      y with e_y.
 Culled (valid = 0): any non-finite input field, opacity below alpha_min (alpha <= o never reaches
 the cut-off), z <= z_near or a non-finite camera-space point, det <= 0, a non-finite u, v, conic or
-radius, and a rectangle that misses the frame.
+extents, and a rectangle that misses the frame.
 """
 from __future__ import annotations
 
@@ -41,7 +43,7 @@ def _f(x):
 
 
 def project(g: dict, cam: dict, opts: dict | None = None, tile: int = 16) -> dict:
-    """Outputs as ``oracle.project_f32``: valid, u, v, z, A, B, C, radius, rect[4] (x0, x1, y0,
+    """Outputs as ``oracle.project_f32``: valid, u, v, z, A, B, C, ex, ey, rect[4] (x0, x1, y0,
     y1 inclusive), count."""
     from . import DEFAULT_OPTIONS
     o = dict(DEFAULT_OPTIONS)
@@ -117,24 +119,23 @@ def project(g: dict, cam: dict, opts: dict | None = None, tile: int = 16) -> dic
         a = ((P0[0] * M0[0] + P0[1] * M0[1]) + P0[2] * M0[2]) + lowpass
         b = (P0[0] * M1[0] + P0[1] * M1[1]) + P0[2] * M1[2]
         cc = ((P1[0] * M1[0] + P1[1] * M1[1]) + P1[2] * M1[2]) + lowpass
-        # (9) conic and 3-sigma extent
+        # (9) conic and the padded half extents of the sigma_cut ellipse's box
         det = a * cc - b * b
         ok &= det > F(0)
         A = cc / det
         B = -(b / det)
         C = a / det
-        mid = F(0.5) * (a + cc)
-        lam = mid + np.sqrt(np.maximum(mid * mid - det, F(0)))
-        rad = np.ceil(cut * np.sqrt(lam))
-        for arr in (u, vv, A, B, C, rad):
+        ex = (cut * np.sqrt(a)) * F(1.001) + F(0.01)
+        ey = (cut * np.sqrt(cc)) * F(1.001) + F(0.01)
+        for arr in (u, vv, A, B, C, ex, ey):
             ok &= np.isfinite(arr)
-        # (10) tile rectangle of the square [u - r, u + r] x [v - r, v + r]
+        # (10) tile rectangle of the box [u - e_x, u + e_x] x [v - e_y, v + e_y]
         ts = F(tile)
-        x0, x1 = np.floor((u - rad) / ts), np.floor((u + rad) / ts)
-        y0, y1 = np.floor((vv - rad) / ts), np.floor((vv + rad) / ts)
+        x0, x1 = np.floor((u - ex) / ts), np.floor((u + ex) / ts)
+        y0, y1 = np.floor((vv - ey) / ts), np.floor((vv + ey) / ts)
         ok &= ~((x1 < 0) | (y1 < 0) | (x0 > TX - 1) | (y0 > TY - 1))
     out = dict(valid=ok.astype(np.uint8))
-    for name, arr in (("u", u), ("v", vv), ("z", xc[2]), ("A", A), ("B", B), ("C", C), ("radius", rad)):
+    for name, arr in (("u", u), ("v", vv), ("z", xc[2]), ("A", A), ("B", B), ("C", C), ("ex", ex), ("ey", ey)):
         out[name] = np.where(ok, arr, F(0)).astype(F)
     with np.errstate(invalid="ignore"):
         rect = np.stack([np.maximum(x0, 0), np.minimum(x1, TX - 1), np.maximum(y0, 0), np.minimum(y1, TY - 1)])

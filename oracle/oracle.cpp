@@ -77,7 +77,7 @@ struct ScreenSplat {
   double u, v, z;        // pixel centre of the mean and camera-space depth
   double a, b, c;        // screen covariance Sigma_s = [[a,b],[b,c]] including the low-pass
   double A, B, C;        // conic = inverse of Sigma_s
-  double radius;         // ceil(sigma_cut * sqrt(lambda_max))
+  double ex, ey;         // padded half extents of the sigma_cut ellipse's axis-aligned box
   int x0, x1, y0, y1;    // inclusive tile rectangle
   float zf;              // FP32 depth whose bits order the splats
 };
@@ -88,7 +88,7 @@ struct ScreenSplat {
 // ---------------------------------------------------------------------------------------------
 void project_one_f32(int64_t n, int64_t i, const float* mean, const float* quat, const float* scale,
                      const float* opac, const float* rgb, const float* nrm, const float* cam,
-                     int W, int H, int tile, const float* opt, ScreenSplat& s, float out[8]) {
+                     int W, int H, int tile, const float* opt, ScreenSplat& s, float out[9]) {
   s.valid = false;
   const float px = mean[i], py = mean[n + i], pz = mean[2 * n + i];
   float qw = quat[i], qx = quat[n + i], qy = quat[2 * n + i], qz = quat[3 * n + i];
@@ -154,27 +154,30 @@ void project_one_f32(int64_t n, int64_t i, const float* mean, const float* quat,
   float a = ((P[0] * M[0] + P[1] * M[1]) + P[2] * M[2]) + lp;
   float b = (P[0] * M[3] + P[1] * M[4]) + P[2] * M[5];
   float c = ((P[3] * M[3] + P[4] * M[4]) + P[5] * M[5]) + lp;
-  // (9) conic and extent.
+  // (9) conic, and the half extents of the axis-aligned box of the sigma_cut ellipse: the
+  // ellipse x^T Sigma_s^-1 x <= sigma_cut^2 reaches sigma_cut sqrt(a) in x and sigma_cut sqrt(c)
+  // in y; the extents are widened by 0.1 % and 0.01 px so that no pixel whose rounded quadratic
+  // form passes the cut lies outside them.
   float det = a * c - b * b;
   if (!(det > 0.0f)) return;
   float A = c / det, Bc = -(b / det), C = a / det;
-  float mid = 0.5f * (a + c);
-  float disc = mid * mid - det;
-  float lam = mid + std::sqrt(std::max(disc, 0.0f));
-  float rad = std::ceil(opt[OPT_SIGMA_CUT] * std::sqrt(lam));
-  if (!fin(u) || !fin(v) || !fin(A) || !fin(Bc) || !fin(C) || !fin(rad)) return;
-  // (10) tile rectangle of the square [u-r, u+r] x [v-r, v+r].
+  const float cut = opt[OPT_SIGMA_CUT];
+  float ex = (cut * std::sqrt(a)) * 1.001f + 0.01f;
+  float ey = (cut * std::sqrt(c)) * 1.001f + 0.01f;
+  if (!fin(u) || !fin(v) || !fin(A) || !fin(Bc) || !fin(C) || !fin(ex) || !fin(ey)) return;
+  // (10) tile rectangle of the box [u-ex, u+ex] x [v-ey, v+ey].
   const float ts = (float)tile;
-  float fx0 = std::floor((u - rad) / ts), fx1 = std::floor((u + rad) / ts);
-  float fy0 = std::floor((v - rad) / ts), fy1 = std::floor((v + rad) / ts);
+  float fx0 = std::floor((u - ex) / ts), fx1 = std::floor((u + ex) / ts);
+  float fy0 = std::floor((v - ey) / ts), fy1 = std::floor((v + ey) / ts);
   const int TX = (W + tile - 1) / tile, TY = (H + tile - 1) / tile;
   if (fx1 < 0.0f || fy1 < 0.0f || fx0 > (float)(TX - 1) || fy0 > (float)(TY - 1)) return;
   s.valid = true;
   s.x0 = (int)std::max(fx0, 0.0f); s.x1 = (int)std::min(fx1, (float)(TX - 1));
   s.y0 = (int)std::max(fy0, 0.0f); s.y1 = (int)std::min(fy1, (float)(TY - 1));
   s.u = u; s.v = v; s.z = zc; s.zf = zc;
-  s.a = a; s.b = b; s.c = c; s.A = A; s.B = Bc; s.C = C; s.radius = rad;
-  out[0] = u; out[1] = v; out[2] = zc; out[3] = A; out[4] = Bc; out[5] = C; out[6] = rad; out[7] = o;
+  s.a = a; s.b = b; s.c = c; s.A = A; s.B = Bc; s.C = C; s.ex = ex; s.ey = ey;
+  out[0] = u; out[1] = v; out[2] = zc; out[3] = A; out[4] = Bc; out[5] = C; out[6] = ex; out[7] = ey;
+  out[8] = o;
 }
 
 // Camera-space depth of step (4) of the exact FP32 sequence, from FP32 copies of the mean and
@@ -234,19 +237,20 @@ void project_one_f64(int64_t n, int64_t i, const float* mean, const double* mean
   double a = Ss[0] + lp, b = 0.5 * (Ss[1] + Ss[2]), c = Ss[3] + lp;
   double det = a * c - b * b;
   if (!(det > 0.0)) return;
-  double lam = 0.5 * (a + c) + std::sqrt(std::max(0.25 * (a + c) * (a + c) - det, 0.0));
-  double rad = std::ceil((double)opt[OPT_SIGMA_CUT] * std::sqrt(lam));
-  if (!fin(u) || !fin(v) || !fin(rad)) return;
+  // half extents of the sigma_cut ellipse's axis-aligned box, widened as in the FP32 sequence
+  const double cut = opt[OPT_SIGMA_CUT];
+  double ex = cut * std::sqrt(a) * 1.001 + 0.01, ey = cut * std::sqrt(c) * 1.001 + 0.01;
+  if (!fin(u) || !fin(v) || !fin(ex) || !fin(ey)) return;
   const int TX = (W + tile - 1) / tile, TY = (H + tile - 1) / tile;
-  double fx0 = std::floor((u - rad) / tile), fx1 = std::floor((u + rad) / tile);
-  double fy0 = std::floor((v - rad) / tile), fy1 = std::floor((v + rad) / tile);
+  double fx0 = std::floor((u - ex) / tile), fx1 = std::floor((u + ex) / tile);
+  double fy0 = std::floor((v - ey) / tile), fy1 = std::floor((v + ey) / tile);
   if (fx1 < 0 || fy1 < 0 || fx0 > TX - 1 || fy0 > TY - 1) return;
   s.valid = true;
   s.x0 = (int)std::max(fx0, 0.0); s.x1 = (int)std::min(fx1, (double)(TX - 1));
   s.y0 = (int)std::max(fy0, 0.0); s.y1 = (int)std::min(fy1, (double)(TY - 1));
   s.u = u; s.v = v; s.z = zc; s.zf = depth_f32(px, py, pz, cam);
   s.a = a; s.b = b; s.c = c;
-  s.A = c / det; s.B = -b / det; s.C = a / det; s.radius = rad;
+  s.A = c / det; s.B = -b / det; s.C = a / det; s.ex = ex; s.ey = ey;
 }
 
 inline uint32_t f32_bits(float f) { uint32_t u; std::memcpy(&u, &f, 4); return u; }
@@ -256,25 +260,25 @@ inline uint32_t f32_bits(float f) { uint32_t u; std::memcpy(&u, &f, 4); return u
 extern "C" {
 
 // Projection of n Gaussians through one camera as the exact FP32 sequence.
-// Outputs (n each): valid, u, v, z, A, B, C, radius, rect[4][n] (x0,x1,y0,y1), count.
+// Outputs (n each): valid, u, v, z, A, B, C, ext[2][n] (ex, ey), rect[4][n] (x0,x1,y0,y1), count.
 void orc_project_f32(int64_t n, const float* mean, const float* quat, const float* scale,
                      const float* opac, const float* rgb, const float* nrm, const float* cam,
                      int W, int H, int tile, const float* opt, uint8_t* valid, float* u, float* v,
-                     float* z, float* A, float* B, float* C, float* radius, int32_t* rect,
+                     float* z, float* A, float* B, float* C, float* ext, int32_t* rect,
                      uint32_t* count) {
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     ScreenSplat s;
-    float o8[8];
-    project_one_f32(n, i, mean, quat, scale, opac, rgb, nrm, cam, W, H, tile, opt, s, o8);
+    float o9[9];
+    project_one_f32(n, i, mean, quat, scale, opac, rgb, nrm, cam, W, H, tile, opt, s, o9);
     valid[i] = s.valid ? 1 : 0;
     if (s.valid) {
-      u[i] = o8[0]; v[i] = o8[1]; z[i] = o8[2]; A[i] = o8[3]; B[i] = o8[4]; C[i] = o8[5];
-      radius[i] = o8[6];
+      u[i] = o9[0]; v[i] = o9[1]; z[i] = o9[2]; A[i] = o9[3]; B[i] = o9[4]; C[i] = o9[5];
+      ext[i] = o9[6]; ext[n + i] = o9[7];
       rect[i] = s.x0; rect[n + i] = s.x1; rect[2 * n + i] = s.y0; rect[3 * n + i] = s.y1;
       count[i] = (uint32_t)((s.x1 - s.x0 + 1) * (s.y1 - s.y0 + 1));
     } else {
-      u[i] = v[i] = z[i] = A[i] = B[i] = C[i] = radius[i] = 0.0f;
+      u[i] = v[i] = z[i] = A[i] = B[i] = C[i] = ext[i] = ext[n + i] = 0.0f;
       rect[i] = rect[n + i] = rect[2 * n + i] = rect[3 * n + i] = 0;
       count[i] = 0;
     }
@@ -285,7 +289,7 @@ void orc_project_f32(int64_t n, const float* mean, const float* quat, const floa
 void orc_project_f64(int64_t n, const double* mean, const double* quat, const double* scale,
                      const double* cov6, const double* opac, const double* cam, int W, int H,
                      int tile, const float* opt, uint8_t* valid, double* u, double* v, double* z,
-                     double* A, double* B, double* C, double* radius, int32_t* rect,
+                     double* A, double* B, double* C, double* ext, int32_t* rect,
                      uint32_t* count, double* cov2d /*[3][n]: a, b, c of Sigma_s*/,
                      float* zf /*[n]: the FP32 depth that orders the splats*/) {
 #pragma omp parallel for schedule(static)
@@ -295,13 +299,14 @@ void orc_project_f64(int64_t n, const double* mean, const double* quat, const do
                     W, H, tile, opt, s);
     valid[i] = s.valid ? 1 : 0;
     if (s.valid) {
-      u[i] = s.u; v[i] = s.v; z[i] = s.z; A[i] = s.A; B[i] = s.B; C[i] = s.C; radius[i] = s.radius;
+      u[i] = s.u; v[i] = s.v; z[i] = s.z; A[i] = s.A; B[i] = s.B; C[i] = s.C;
+      ext[i] = s.ex; ext[n + i] = s.ey;
       cov2d[i] = s.a; cov2d[n + i] = s.b; cov2d[2 * n + i] = s.c;
       zf[i] = s.zf;
       rect[i] = s.x0; rect[n + i] = s.x1; rect[2 * n + i] = s.y0; rect[3 * n + i] = s.y1;
       count[i] = (uint32_t)((s.x1 - s.x0 + 1) * (s.y1 - s.y0 + 1));
     } else {
-      u[i] = v[i] = z[i] = A[i] = B[i] = C[i] = radius[i] = 0.0;
+      u[i] = v[i] = z[i] = A[i] = B[i] = C[i] = ext[i] = ext[n + i] = 0.0;
       cov2d[i] = cov2d[n + i] = cov2d[2 * n + i] = 0.0;
       zf[i] = 0.0f;
       rect[i] = rect[n + i] = rect[2 * n + i] = rect[3 * n + i] = 0;

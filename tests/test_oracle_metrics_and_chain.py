@@ -122,7 +122,7 @@ def _same_bits(a, b):
 def _check_projection(g, cam, opts=None):
     a = oracle.project_f32(g, cam, opts)
     b = emulate32.project(g, cam, opts)
-    for k in ("valid", "u", "v", "z", "A", "B", "C", "radius", "rect", "count"):
+    for k in ("valid", "u", "v", "z", "A", "B", "C", "ex", "ey", "rect", "count"):
         assert _same_bits(a[k], b[k]), (k, int(np.sum(a[k] != b[k])))
     return int(a["valid"].sum())
 

@@ -153,20 +153,29 @@ def test_rotated_anisotropic_on_axis():
         assert math.isclose(cc, k * Syy + LP, rel_tol=1e-9)
 
 
-def test_conic_is_inverse_and_radius_is_three_sigma():
+def test_conic_is_inverse_and_extents_bound_the_three_sigma_ellipse():
+    """The binning box is the axis-aligned box of the 3-sigma ellipse x^T Sigma_s^-1 x <= 9: points
+    of the ellipse's boundary, built from the eigen-decomposition of Sigma_s (x = 3 V L^1/2
+    (cos t, sin t)), reach 3 sqrt(a) in x and 3 sqrt(c) in y and never pass the padded extents."""
     rng = np.random.default_rng(3)
     g = random_gaussians(200, rng)
     cam = look_at_camera([0, 0, 3], width=128, height=128)
     p = oracle.project_f64(g, cam)
     idx = np.nonzero(p["valid"])[0]
     assert idx.size > 150
+    t = np.linspace(0.0, 2.0 * np.pi, 4001)
+    circle = np.stack([np.cos(t), np.sin(t)])
     for i in idx:
         a, b, c = p["cov2d"][:, i]
         Ss = np.array([[a, b], [b, c]])
         Cn = np.array([[p["A"][i], p["B"][i]], [p["B"][i], p["C"][i]]])
         assert np.allclose(Cn @ Ss, np.eye(2), atol=1e-12)
-        lam = np.linalg.eigvalsh(Ss)[-1]
-        assert p["radius"][i] == math.ceil(3.0 * math.sqrt(lam))
+        lam, V = np.linalg.eigh(Ss)
+        pts = 3.0 * (V * np.sqrt(lam)) @ circle                # the boundary q = 9
+        reach = np.abs(pts).max(axis=1)
+        assert np.all(reach <= np.array([p["ex"][i], p["ey"][i]]))
+        assert np.allclose(reach, [3.0 * math.sqrt(a), 3.0 * math.sqrt(c)], rtol=1e-6)
+        assert p["ex"][i] == 3.0 * math.sqrt(a) * 1.001 + 0.01 and p["ey"][i] == 3.0 * math.sqrt(c) * 1.001 + 0.01
 
 
 def test_fp32_projection_tracks_fp64():
@@ -181,8 +190,10 @@ def test_fp32_projection_tracks_fp64():
     for k in ("A", "B", "C"):
         scale = np.maximum(np.abs(p64["A"][both]), np.abs(p64["C"][both]))
         assert np.max(np.abs(p32[k][both] - p64[k][both]) / scale) < 1e-4
-    # radius and rectangle differ only where ceil() sits on the edge of an integer
-    differ = both & (p32["radius"] != p64["radius"])
+    # extents agree to FP32 rounding; rectangles differ only where a box edge sits on a tile edge
+    for k in ("ex", "ey"):
+        assert np.max(np.abs(p32[k][both] - p64[k][both]) / p64[k][both]) < 1e-5
+    differ = both & np.any(p32["rect"] != p64["rect"], axis=0)
     assert differ.sum() <= 2
 
 
@@ -242,7 +253,8 @@ def test_single_splat_head_on(mode):
     assert math.isclose(img["rgb"][0, 1, c, c], o * 0.6, rel_tol=1e-6)
     assert math.isclose(img["alpha"][0, c, c], o, rel_tol=1e-6)
     p = oracle.project_f64(g, cam)
-    assert p["radius"][0] == math.ceil(3 * math.sqrt(s2))
+    assert math.isclose(p["ex"][0], 3 * math.sqrt(s2) * 1.001 + 0.01, rel_tol=1e-6)   # FP32 inputs
+    assert math.isclose(p["ey"][0], 3 * math.sqrt(s2) * 1.001 + 0.01, rel_tol=1e-6)
     for d in range(0, 10):
         a = o * math.exp(-d * d / (2 * s2))
         if d * d > 9 * s2 or a < 1 / 255:
@@ -331,10 +343,11 @@ def test_binning_matches_bruteforce_tile_test_and_python_sorted():
     for ci, p in enumerate(projs):
         zb = p["z"].view(np.uint32)
         for i in np.nonzero(p["valid"])[0]:
-            u, v, r = float(p["u"][i]), float(p["v"][i]), float(p["radius"][i])
+            u, v = float(p["u"][i]), float(p["v"][i])
+            ex, ey = float(p["ex"][i]), float(p["ey"][i])
             for ty in range(TY):
                 for tx in range(TX):
-                    if 16 * tx <= u + r and 16 * (tx + 1) > u - r and 16 * ty <= v + r and 16 * (ty + 1) > v - r:
+                    if 16 * tx <= u + ex and 16 * (tx + 1) > u - ex and 16 * ty <= v + ey and 16 * (ty + 1) > v - ey:
                         pairs.append((((ci * TX * TY + ty * TX + tx) << 32) | int(zb[i]), int(i)))
     pairs = sorted(pairs)
     assert len(pairs) == keys.size
