@@ -80,16 +80,18 @@ __global__ __launch_bounds__(256) void k_project(
     ok = ok && (zc > opt.z_near) && fin(G.xc) && fin(G.yc) && fin(zc);
     ok = ok && (G.det > 0.0f);
     const float A = G.c / G.det, B = -(G.b / G.det), C = G.a / G.det;
-    const float mid = 0.5f * (G.a + G.c);
-    const float disc = mid * mid - G.det;
-    const float lam = mid + sqrtf(fmaxf(disc, 0.0f));
-    const float rad = ceilf(opt.sigma_cut * sqrtf(lam));
-    ok = ok && fin(u) && fin(v) && fin(A) && fin(B) && fin(C) && fin(rad);
-    // tile rectangle of the square [u - r, u + r] x [v - r, v + r]
+    // half extents of the axis-aligned box of the sigma_cut ellipse (it reaches sigma_cut sqrt(a)
+    // in x and sigma_cut sqrt(c) in y), widened so that pixels outside the box fail the
+    // sigma_cut test by a wide margin whatever the rounding of the quadratic form; the box bins
+    // the splat and culls it in compositing
+    const float ex = (opt.sigma_cut * sqrtf(G.a)) * 1.001f + 0.01f;
+    const float ey = (opt.sigma_cut * sqrtf(G.c)) * 1.001f + 0.01f;
+    ok = ok && fin(u) && fin(v) && fin(A) && fin(B) && fin(C) && fin(ex) && fin(ey);
+    // tile rectangle of the box [u - ex, u + ex] x [v - ey, v + ey]
     const int TX = (cam.W + kTile - 1) / kTile, TY = (cam.H + kTile - 1) / kTile;
     const float ts = (float)kTile;
-    const float fx0 = floorf((u - rad) / ts), fx1 = floorf((u + rad) / ts);
-    const float fy0 = floorf((v - rad) / ts), fy1 = floorf((v + rad) / ts);
+    const float fx0 = floorf((u - ex) / ts), fx1 = floorf((u + ex) / ts);
+    const float fy0 = floorf((v - ey) / ts), fy1 = floorf((v + ey) / ts);
     ok = ok && !(fx1 < 0.0f || fy1 < 0.0f || fx0 > (float)(TX - 1) || fy0 > (float)(TY - 1));
     if (ok) {
       const int x0 = (int)fmaxf(fx0, 0.0f), x1 = (int)fminf(fx1, (float)(TX - 1));
@@ -102,10 +104,6 @@ __global__ __launch_bounds__(256) void k_project(
                  (uint32_t)(y1 + 1));
       float4* r = rec + out * kRecFloat4;
       r[0] = make_float4(u, v, o, zc);
-      // half extents of the sigma_cut ellipse's bounding box, padded so that pixels outside it
-      // fail the sigma_cut test by a wide margin whatever the rounding of the quadratic form
-      const float ex = fmaf(opt.sigma_cut * sqrtf(G.a), 1.001f, 0.01f);
-      const float ey = fmaf(opt.sigma_cut * sqrtf(G.c), 1.001f, 0.01f);
       r[1] = make_float4(A, B, C, ex);
       r[2] = make_float4(cr, cg, cb, ey);
       r[3] = make_float4(nx, ny, nz, 0.0f);
