@@ -357,25 +357,40 @@ def late_shading(R, out, cams, reps=20):
 
 # Kernel source each stage's dominant kernel is built from (a counter summary applies only while
 # this file is unchanged).
-STAGE_SOURCE = {"composite": "composite.hip", "project": "project.hip",
-                "binning": "scan_sort.hip", "sort": "scan_sort.hip", "ranges": "scan_sort.hip"}
+# Sources a stage's counters depend on: its kernel's, and the projection's where the tile lists
+# it walks come from the projection's binning rule.
+STAGE_SOURCES = {"composite": ("project.hip", "composite.hip"), "project": ("project.hip",),
+                 "binning": ("project.hip", "scan_sort.hip"), "sort": ("project.hip", "scan_sort.hip"),
+                 "ranges": ("project.hip", "scan_sort.hip")}
+
+
+def sources_sha256(stage):
+    """sha256 of the stage's sources (STAGE_SOURCES, concatenated in that order), or None."""
+    import hashlib
+    paths = [os.path.join(ROOT, "paper_2409_16504_amd", "csrc", f) for f in STAGE_SOURCES.get(stage, ())]
+    if not paths or not all(os.path.isfile(q) for q in paths):
+        return None
+    h = hashlib.sha256()
+    for q in paths:
+        with open(q, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_lds(stage="composite"):
     """LDS bytes per launch of the stage's kernel (64 x SQ_INSTS_LDS_LOAD_BANDWIDTH +
     64 x SQ_INSTS_LDS_STORE_BANDWIDTH) and its bank-conflict cycles from the committed rocprofv3
-    counter summary, or None when there is none or the kernel source has changed since."""
-    import hashlib
+    counter summary, or None when there is none or the stage's sources have changed since."""
     import re
     path = os.path.join(ROOT, "profiles", f"{stage}_1M_1080p_lds_counters.md")
-    src = os.path.join(ROOT, "paper_2409_16504_amd", "csrc", STAGE_SOURCE.get(stage, ""))
-    if not os.path.exists(path) or not os.path.isfile(src):
+    sha = sources_sha256(stage)
+    if not os.path.exists(path) or sha is None:
         return None
     text = open(path).read()
     h = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
     b = re.search(r"lds_bytes_per_launch:\s*([0-9.eE+]+)", text)
     c = re.search(r"bank_conflict_fraction:\s*([0-9.eE+-]+)", text)
-    if not h or not b or hashlib.sha256(open(src, "rb").read()).hexdigest() != h.group(1):
+    if not h or not b or sha != h.group(1):
         return None
     return dict(bytes=float(b.group(1)), bank_conflict_fraction=float(c.group(1)) if c else None)
 
@@ -383,19 +398,16 @@ def measured_lds(stage="composite"):
 def measured_traffic(stage):
     """HBM bytes per launch of the stage's kernel from the committed rocprofv3 counter summary
     (FETCH_SIZE + WRITE_SIZE scaled by a plain copy kernel's counters), or None when there is no
-    summary or the kernel source has changed since it was taken."""
-    import hashlib
+    summary or the stage's sources have changed since it was taken."""
     import re
     path = os.path.join(ROOT, "profiles", f"{stage}_1M_1080p_hbm_traffic.md")
-    src = os.path.join(ROOT, "paper_2409_16504_amd", "csrc", STAGE_SOURCE.get(stage, ""))
-    if not os.path.exists(path) or not os.path.isfile(src):
+    sha = sources_sha256(stage)
+    if not os.path.exists(path) or sha is None:
         return None
     text = open(path).read()
     h = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
     b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not h or not b:
-        return None
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != h.group(1):
+    if not h or not b or sha != h.group(1):
         return None
     return float(b.group(1))
 

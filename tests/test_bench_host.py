@@ -30,30 +30,32 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_measured_traffic_follows_the_source_hash(bench, tmp_path, monkeypatch):
+    """The composite's counters are reported only while the projection (whose binning rule makes
+    the tile lists) and the compositing source both hash to what they were taken on."""
     text = open(os.path.join(ROOT, "profiles", "composite_1M_1080p_hbm_traffic.md")).read()
     stored = float(re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text).group(1))
     taken_on = re.search(r"source_sha256:\s*([0-9a-f]{64})", text).group(1)
-    src = os.path.join(ROOT, "paper_2409_16504_amd", "csrc", "composite.hip")
-    same = hashlib.sha256(open(src, "rb").read()).hexdigest() == taken_on
-    assert bench.measured_traffic("composite") == (stored if same else None)
+    csrc_root = os.path.join(ROOT, "paper_2409_16504_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("project.hip", "composite.hip"):
+        h.update(open(os.path.join(csrc_root, f), "rb").read())
+    assert bench.sources_sha256("composite") == h.hexdigest()
+    assert bench.measured_traffic("composite") == (stored if h.hexdigest() == taken_on else None)
     assert bench.measured_traffic("no_such_stage") is None
-    # the summary against the source it was taken on is reported
-    (tmp_path / "ok" / "profiles").mkdir(parents=True)
-    (tmp_path / "ok" / "profiles" / "composite_1M_1080p_hbm_traffic.md").write_text(
-        text.replace(taken_on, hashlib.sha256(b"// this source\n").hexdigest()))
-    (tmp_path / "ok" / "paper_2409_16504_amd" / "csrc").mkdir(parents=True)
-    (tmp_path / "ok" / "paper_2409_16504_amd" / "csrc" / "composite.hip").write_bytes(b"// this source\n")
-    monkeypatch.setattr(bench, "ROOT", str(tmp_path / "ok"))
-    assert bench.measured_traffic("composite") == stored
-    monkeypatch.undo()
-    # the same summary against a changed source is not reported
-    (tmp_path / "profiles").mkdir()
-    (tmp_path / "profiles" / "composite_1M_1080p_hbm_traffic.md").write_text(text)
-    csrc = tmp_path / "paper_2409_16504_amd" / "csrc"
-    csrc.mkdir(parents=True)
-    (csrc / "composite.hip").write_text("// another source\n")
-    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.measured_traffic("composite") is None
+    sources = {"project.hip": b"// projection\n", "composite.hip": b"// compositing\n"}
+    want = hashlib.sha256(sources["project.hip"] + sources["composite.hip"]).hexdigest()
+    # the summary against the sources it was taken on is reported; a change to either is not
+    for changed in (None, "project.hip", "composite.hip"):
+        root = tmp_path / str(changed)
+        (root / "profiles").mkdir(parents=True)
+        (root / "profiles" / "composite_1M_1080p_hbm_traffic.md").write_text(text.replace(taken_on, want))
+        csrc = root / "paper_2409_16504_amd" / "csrc"
+        csrc.mkdir(parents=True)
+        for f, body in sources.items():
+            (csrc / f).write_bytes(body if f != changed else b"// another source\n")
+        monkeypatch.setattr(bench, "ROOT", str(root))
+        assert bench.measured_traffic("composite") == (stored if changed is None else None), changed
+        monkeypatch.undo()
 
 
 def _bins(n_tiles, tile_ids, depth_bits_values, vals):
