@@ -217,7 +217,10 @@ int pcs_context_set_wait_limit(pcs_context* ctx, uint32_t rounds);
  * holds the compositing kernel's LDS traffic against. */
 int pcs_measure_lds_bandwidth(pcs_context* ctx, double* gbs, void* stream);
 
-/* Parity export of a saved state (device pointers owned by the state):
+/* Parity export of a saved state (device pointers owned by the state). A splat is listed in every
+ * 16x16 tile that meets the axis-aligned box of its sigma_cut ellipse (Section 3.1): half extents
+ * (sigma_cut sqrt(a)) 1.001 + 0.01 and (sigma_cut sqrt(c)) 1.001 + 0.01 pixels for the screen
+ * covariance [[a, b], [b, c]], evaluated in FP32.
  *   keys[m]:  ((cam * tiles_per_cam + ty * TX + tx) << 32) | bits(fp32 camera-space depth)
  *   vals[m]:  Gaussian index, sorted lexicographically by (key, value)
  *   ranges[2][n_tiles]: start and end of every tile's run (empty tiles: 0, 0)
