@@ -378,6 +378,35 @@ def test_tiled_composite_equals_bruteforce(seed, mode):
     assert (img["n_contrib"][0] > 0).sum() > 300
 
 
+@pytest.mark.parametrize("mode", ["ref", "f64"])
+def test_tiled_composite_equals_bruteforce_on_thin_tilted_ellipses(mode):
+    """Surfel-like splats (one long, one short and one near-zero axis, random orientations) give
+    long thin screen ellipses at every angle, where the axis-aligned box of the 3-sigma ellipse is
+    far smaller than the square of half width 3 sqrt(lambda_max): the tiled render must still equal
+    the tile-free brute force exactly, so the box holds every pixel the 3-sigma test accepts."""
+    rng = np.random.default_rng(77)
+    n = 48
+    g = random_gaussians(n, rng, mean_range=0.35, opacity_range=(0.3, 0.99))
+    g["scale"] = np.ascontiguousarray(np.stack([rng.uniform(0.08, 0.3, n), rng.uniform(0.002, 0.02, n),
+                                                np.full(n, 5e-4)]).astype(np.float32))
+    W, H = 61, 47
+    cam = look_at_camera([0.4, -0.3, 1.6], width=W, height=H)
+    img = oracle.render(g, [cam], mode=mode)
+    proj = img["proj"][0]
+    ref = brute.composite(proj, g["opacity"].astype(np.float64), g["rgb"].astype(np.float64),
+                          g["normal"].astype(np.float64), W, H, oracle.options_vector())
+    for k in ("rgb", "normal", "depth", "T"):
+        assert np.array_equal(img[k][0], ref[k]), k
+    assert (img["n_contrib"][0] > 0).sum() > 300
+    # the regime where the box matters: its area is well below the square's
+    v = proj["valid"] == 1
+    A, B, C = (np.asarray(proj[k], np.float64)[v] for k in ("A", "B", "C"))
+    lam_max = 1.0 / np.linalg.eigvalsh(np.stack([np.stack([A, B], -1), np.stack([B, C], -1)], -2))[:, 0]
+    square = (2 * np.ceil(3 * np.sqrt(lam_max))) ** 2
+    box = 4 * np.asarray(proj["ex"], np.float64)[v] * np.asarray(proj["ey"], np.float64)[v]
+    assert v.sum() > 40 and np.mean(box / square) < 0.6
+
+
 # --------------------------------------------------------------------------------------------
 # Invariants
 # --------------------------------------------------------------------------------------------
