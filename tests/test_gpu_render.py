@@ -251,10 +251,14 @@ def test_opaque_front_layer_occludes(R):
                 opacity=np.ones(3, np.float32), rgb=np.full((3, 3), 0.5, np.float32),
                 normal=np.tile(np.array([[0.0], [0], [1]], np.float32), (1, 3)))
     both = {k: np.concatenate([wall[k], g[k]], axis=-1) for k in g}
-    a, _, _ = gpu_render(R, both, cams)
+    a, bins, _ = gpu_render(R, both, cams)
     b, _, _ = gpu_render(R, wall, cams)
     for k in a:
         assert np.array_equal(a[k], b[k]), k
+    # and the occluded frame against the oracle (key lists bit-exact, images to the parity bar)
+    ref = oracle.render(both, cams, mode="ref")
+    check_bins(bins, ref, 64)
+    check_images(a, bins, ref, 4.0)
 
 
 @pytest.mark.parametrize("n,W,H,seed", [(1_000_000, 1920, 1080, 1006), (800_000, 1920, 1080, 1002)])
