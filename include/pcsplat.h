@@ -294,6 +294,15 @@ int pcs_subm_conv_forward(pcs_context* ctx, const pcs_voxels* vox, const uint16_
                           const uint16_t* w, const float* bias, int32_t cout, int32_t relu, uint16_t* y,
                           void* stream);
 
+/* pcs_subm_conv_forward of the channel concatenation [x1 | x2] (the UNet's skip connections,
+ * Section 3.2), read where the two parts lie: x1[V][c1], x2[V][c2] BF16, w[27][cout][c1 + c2].
+ * Equal halves c1 = c2, a multiple of 32, with c1 + c2 and cout as for pcs_subm_conv_forward
+ * (UNSUPPORTED otherwise). Same arithmetic, bit for bit, as pcs_subm_conv_forward on the
+ * concatenated rows. */
+int pcs_subm_conv_forward_cat(pcs_context* ctx, const pcs_voxels* vox, const uint16_t* x1, int32_t c1,
+                              const uint16_t* x2, int32_t c2, const uint16_t* w, const float* bias,
+                              int32_t cout, int32_t relu, uint16_t* y, void* stream);
+
 /* Adjoint of pcs_subm_conv_forward. If y (the forward output) is given, dy is first multiplied by
  * the ReLU derivative (y > 0). dx[V][cin] (BF16, overwritten) or NULL; dw[27][cout][cin] and
  * dbias[cout] FP32, ACCUMULATED (+=), or NULL. */

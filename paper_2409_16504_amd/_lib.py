@@ -29,7 +29,7 @@ EXPORTED = ("pcs_last_error", "pcs_context_create", "pcs_context_destroy", "pcs_
             "pcs_measure_lds_bandwidth", "pcs_pool", "pcs_pool_features", "pcs_pool_features_backward",
             "pcs_up_conv_forward", "pcs_up_conv_backward", "pcs_unet_head_forward", "pcs_unet_head_backward",
             "pcs_knn_pca", "pcs_voxels_create", "pcs_voxels_destroy", "pcs_voxelize", "pcs_voxels_get",
-            "pcs_subm_conv_forward", "pcs_subm_conv_backward", "pcs_estimator_head_forward",
+            "pcs_subm_conv_forward", "pcs_subm_conv_forward_cat", "pcs_subm_conv_backward", "pcs_estimator_head_forward",
             "pcs_estimator_head_backward")
 
 
@@ -132,7 +132,7 @@ def load():
                  "pcs_up_conv_forward", "pcs_up_conv_backward", "pcs_unet_head_forward",
                  "pcs_unet_head_backward",
                  "pcs_state_bins", "pcs_knn_pca", "pcs_voxels_create", "pcs_voxels_destroy", "pcs_voxelize", "pcs_voxels_get",
-            "pcs_subm_conv_forward", "pcs_subm_conv_backward", "pcs_estimator_head_forward",
+            "pcs_subm_conv_forward", "pcs_subm_conv_forward_cat", "pcs_subm_conv_backward", "pcs_estimator_head_forward",
             "pcs_estimator_head_backward"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L

@@ -1027,6 +1027,20 @@ int pcs_subm_conv_forward(pcs_context* ctx, const pcs_voxels* vox, const uint16_
   return PCS_OK;
 }
 
+int pcs_subm_conv_forward_cat(pcs_context* ctx, const pcs_voxels* vox, const uint16_t* x1, int32_t c1,
+                              const uint16_t* x2, int32_t c2, const uint16_t* w, const float* bias,
+                              int32_t cout, int32_t relu, uint16_t* y, void* stream) {
+  if (!ctx || !vox || !vox->valid || !x1 || !x2 || !w || !y) return fail(PCS_ERR_INVALID_ARG, "NULL argument or empty voxels");
+  if (c1 != c2 || c1 % 32 != 0 || c1 <= 0 || !conv_shape_supported(c1 + c2, cout))
+    return fail(PCS_ERR_UNSUPPORTED, "the halves must be equal multiples of 32, with c1 + c2 and cout supported");
+  PCS_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  StageTimer tm(ctx, ST_CONV, s);
+  PCS_HIP(launch_subm_conv(x1, c1 + c2, w, bias, cout, vox->nbr.as<int32_t>(), vox->V, relu ? 1 : 0, y, s,
+                           27, x2, c1));
+  return PCS_OK;
+}
+
 int pcs_subm_conv_backward(pcs_context* ctx, const pcs_voxels* vox, const uint16_t* x, int32_t cin,
                            const uint16_t* w, int32_t cout, const uint16_t* y, const uint16_t* dy,
                            uint16_t* dx, float* dw, float* dbias, void* stream) {

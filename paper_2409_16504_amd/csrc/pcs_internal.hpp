@@ -322,10 +322,12 @@ hipError_t launch_vox_build(const uint32_t* keys, const uint32_t* order, const u
                             int log2cap, int32_t* nbr, hipStream_t s);
 bool conv_shape_supported(int cin, int cout);
 // y = relu?(bias + sum over n_off offsets of W_k x[nbr_k]): 27 offsets for the submanifold
-// convolution, 8 for the transposed stride-2 convolution (with its upsampling table).
+// convolution, 8 for the transposed stride-2 convolution (with its upsampling table). x2 (may be
+// null): the input is [x | x2] along the channels in equal halves, x[V][c1] and x2[V][c1] with
+// c1 = cin / 2 a multiple of 32 (hipErrorInvalidValue otherwise).
 hipError_t launch_subm_conv(const uint16_t* x, int cin, const uint16_t* wt, const float* bias, int cout,
                             const int32_t* nbr, int64_t V, int relu, uint16_t* y, hipStream_t s,
-                            int n_off = 27);
+                            int n_off = 27, const uint16_t* x2 = nullptr, int c1 = 0);
 // out[s][c][o] = wt[flip ? n_off - 1 - s : s][o][c]
 hipError_t launch_weight_t(const uint16_t* wt, int n_off, int cin, int cout, bool flip, uint16_t* out,
                            hipStream_t s);

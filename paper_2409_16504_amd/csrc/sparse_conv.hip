@@ -187,13 +187,15 @@ constexpr int kConvWaves = 4;                  // wavefronts per block
 constexpr int kConvTiles = 1;                  // 16-row MFMA tiles per wavefront
 // y[v][o] = relu?(bias[o] + sum_k sum_c W[k][o][c] x[nbr_k(v)][c]) over n_off offsets (27 for a
 // submanifold 3x3x3 convolution, 8 for a stride-2 transposed 2x2x2 one); wt is [n_off][COUT][CIN]
-// BF16 and nbr is [n_off][V].
-template <int CIN, int COUT, int MB>
+// BF16 and nbr is [n_off][V]. HALVES: the input rows are the concatenation of x ([V][CIN / 2]) and
+// x2 ([V][CIN / 2]) along the channels, read where they lie.
+template <int CIN, int COUT, int MB, bool HALVES>
 __global__ __launch_bounds__(256) void k_subm_conv(const uint16_t* __restrict__ x,
                                                    const uint16_t* __restrict__ wt,
                                                    const float* __restrict__ bias,
                                                    const int32_t* __restrict__ nbr, int64_t V,
-                                                   int relu, uint16_t* __restrict__ y, int n_off) {
+                                                   int relu, uint16_t* __restrict__ y, int n_off,
+                                                   const uint16_t* __restrict__ x2) {
   constexpr int KC = CIN / 32;       // K chunks of 32 channels
   constexpr int NB = COUT / 16;      // 16-column output blocks
   constexpr int LDW = CIN + 8;       // padded LDS row (avoids bank conflicts)
@@ -212,6 +214,8 @@ __global__ __launch_bounds__(256) void k_subm_conv(const uint16_t* __restrict__ 
   constexpr int kWQ = (COUT * CIN / 8 + 255) / 256;
   uint4 wreg[kWQ];
   uint4 arow[MB][KC];
+  static_assert(!HALVES || KC % 2 == 0, "the halves are whole 32-channel chunks");
+  constexpr int LDX = HALVES ? CIN / 2 : CIN;       // row stride of x (and of x2)
   auto load_offset = [&](int k) {
     const uint4* wsrc = reinterpret_cast<const uint4*>(wt + (int64_t)k * COUT * CIN);
 #pragma unroll
@@ -224,9 +228,11 @@ __global__ __launch_bounds__(256) void k_subm_conv(const uint16_t* __restrict__ 
       const int64_t v = vbase + mb * 16 + row;
       const int32_t j = v < V ? nbr[(int64_t)k * V + v] : -1;
 #pragma unroll
-      for (int kc = 0; kc < KC; ++kc)
-        arow[mb][kc] = j >= 0 ? *reinterpret_cast<const uint4*>(x + (int64_t)j * CIN + kc * 32 + grp * 8)
-                              : make_uint4(0u, 0u, 0u, 0u);
+      for (int kc = 0; kc < KC; ++kc) {
+        const bool second = HALVES && kc >= KC / 2;
+        const uint16_t* piece = (second ? x2 : x) + (int64_t)j * LDX + (second ? kc - KC / 2 : kc) * 32 + grp * 8;
+        arow[mb][kc] = j >= 0 ? *reinterpret_cast<const uint4*>(piece) : make_uint4(0u, 0u, 0u, 0u);
+      }
     }
   };
   if (n_off > 0) load_offset(0);
@@ -943,20 +949,30 @@ bool conv_shape_supported(int cin, int cout) {
 }
 
 hipError_t launch_subm_conv(const uint16_t* x, int cin, const uint16_t* wt, const float* bias, int cout,
-                            const int32_t* nbr, int64_t V, int relu, uint16_t* y, hipStream_t s, int n_off) {
+                            const int32_t* nbr, int64_t V, int relu, uint16_t* y, hipStream_t s, int n_off,
+                            const uint16_t* x2, int c1) {
   if (V == 0) return hipSuccess;
+  if (x2 && (c1 * 2 != cin || c1 % 32 != 0)) return hipErrorInvalidValue;
   // one 16-row MFMA tile per wavefront, four wavefronts per block: 64 voxels per block spread
   // even a coarse UNet level over the chip (four row tiles per wavefront, which share the weight
   // fragments, were slower at every level size measured, 26k to 333k voxels)
   const dim3 grid(blocks_for(V, kConvWaves * 16 * kConvTiles)), block(kConvWaves * kWave);
 #define PCS_CONV(CI, CO)                                                                              \
-  if (cin == CI && cout == CO) {                                                                      \
-    hipLaunchKernelGGL((k_subm_conv<CI, CO, kConvTiles>), grid, block, 0, s, x, wt, bias, nbr, V, relu, y, \
-                       n_off);                                                                        \
+  if (cin == CI && cout == CO && !x2) {                                                               \
+    hipLaunchKernelGGL((k_subm_conv<CI, CO, kConvTiles, false>), grid, block, 0, s, x, wt, bias, nbr, V, \
+                       relu, y, n_off, nullptr);                                                      \
+    return hipGetLastError();                                                                         \
+  }
+#define PCS_CONV_CAT(CI, CO)                                                                          \
+  if (cin == CI && cout == CO && x2) {                                                                \
+    hipLaunchKernelGGL((k_subm_conv<CI, CO, kConvTiles, true>), grid, block, 0, s, x, wt, bias, nbr, V,  \
+                       relu, y, n_off, x2);                                                           \
     return hipGetLastError();                                                                         \
   }
   PCS_CONV(32, 32) PCS_CONV(32, 64) PCS_CONV(64, 32) PCS_CONV(64, 64) PCS_CONV(128, 32) PCS_CONV(128, 64)
   PCS_CONV(32, 128) PCS_CONV(64, 128)
+  PCS_CONV_CAT(64, 32) PCS_CONV_CAT(64, 64) PCS_CONV_CAT(64, 128) PCS_CONV_CAT(128, 32) PCS_CONV_CAT(128, 64)
+#undef PCS_CONV_CAT
 #undef PCS_CONV
   return hipErrorInvalidValue;
 }

@@ -115,6 +115,16 @@ def conv_forward(R: Renderer, vox: Voxels, x: torch.Tensor, w_bf16: torch.Tensor
     return y
 
 
+def conv_forward_cat(R: Renderer, vox: Voxels, x1: torch.Tensor, x2: torch.Tensor, w_bf16: torch.Tensor,
+                     bias, relu: bool) -> torch.Tensor:
+    """conv_forward of the channel concatenation [x1 | x2], which the kernel reads in place."""
+    c1, c2, cout = x1.shape[1], x2.shape[1], w_bf16.shape[1]
+    y = torch.empty((vox.V, cout), device=x1.device, dtype=torch.bfloat16)
+    check(_lib.load().pcs_subm_conv_forward_cat(R.ctx, vox.handle, _p(x1), c1, _p(x2), c2, _p(w_bf16),
+                                                _p(bias), cout, int(relu), _p(y), _s()))
+    return y
+
+
 def conv_backward(R: Renderer, vox: Voxels, x, w_bf16, y, dy, want_dx=True, dw=None, db=None):
     cin, cout = x.shape[1], w_bf16.shape[1]
     dx = torch.empty((vox.V, cin), device=x.device, dtype=torch.bfloat16) if want_dx else None
@@ -431,13 +441,21 @@ class UNetEstimator:
             a[name] = up_conv_forward(R, lv[level + 1], x, wb[name], self.b[name], relu=True)
             return a[name]
 
+        def conv_skip(name, x, skip, level):
+            # the skip concatenation: training keeps the concatenated input for the weight gradient;
+            # inference lets the convolution read the two parts where they lie
+            if save:
+                return conv(name, torch.cat([x, skip], dim=1), level)
+            a[name] = conv_forward_cat(R, lv[level], x, skip, wb[name], self.b[name], relu=True)
+            return a[name]
+
         s0 = conv("e0b", conv("e0a", x0, 0), 0)
         s1 = conv("e1", pool_features(R, lv[1], s0), 1)
         s2 = conv("e2", pool_features(R, lv[2], s1), 2)
         b3 = conv("e3", pool_features(R, lv[3], s2), 3)
-        d2 = conv("d2", torch.cat([up("u3", b3, 2), s2], dim=1), 2)
-        d1 = conv("d1", torch.cat([up("u2", d2, 1), s1], dim=1), 1)
-        d0 = conv("d0", torch.cat([up("u1", d1, 0), s0], dim=1), 0)
+        d2 = conv_skip("d2", up("u3", b3, 2), s2, 2)
+        d1 = conv_skip("d1", up("u2", d2, 1), s1, 1)
+        d0 = conv_skip("d0", up("u1", d1, 0), s0, 0)
         g = unet_head_forward(R, lv[0], d0, self.w1, self.b1, self.w2, self.b2, lv[0].xyz, lv[0].rgb)
         if save:
             return g, dict(acts=a, wb=wb)

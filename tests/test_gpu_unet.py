@@ -70,6 +70,30 @@ def test_pool_features_and_adjoint(R, cloud):
         assert np.all(np.abs(dx - want) <= 2.0 ** -8 * np.abs(want) + 1e-12), C
 
 
+@pytest.mark.parametrize("level,half,cout", [(0, 32, 32), (1, 64, 64), (2, 64, 64), (0, 64, 32)])
+def test_skip_concatenation_is_read_in_place(R, cloud, level, half, cout):
+    """The decoder's convolution over the skip concatenation [up | skip], read from the two arrays
+    where they lie, equals the convolution over the concatenated rows bit for bit; unequal halves
+    are refused."""
+    from paper_2409_16504_amd import _lib
+    from paper_2409_16504_amd.estimator import conv_forward, conv_forward_cat
+    _, _, vox, lv, _, _ = cloud
+    rng = np.random.default_rng(30 + level)
+    V = lv[level].V
+    _, x1 = bf16(rng.normal(size=(V, half)))
+    _, x2 = bf16(rng.normal(size=(V, half)))
+    _, wt = bf16(rng.normal(size=(27, cout, 2 * half)) * np.sqrt(2.0 / (27 * 2 * half)))
+    bt = torch.from_numpy(rng.normal(size=cout).astype(np.float32) * 0.1).cuda()
+    x1, x2, wt = x1.cuda(), x2.cuda(), wt.cuda()
+    for relu in (False, True):
+        want = conv_forward(R, lv[level], torch.cat([x1, x2], dim=1), wt, bt, relu)
+        got = conv_forward_cat(R, lv[level], x1, x2, wt, bt, relu)
+        torch.cuda.synchronize()
+        assert torch.equal(got.view(torch.int16), want.view(torch.int16)), relu
+    with pytest.raises(_lib.PcsError):
+        conv_forward_cat(R, lv[level], x1, x2[:, :half // 2].contiguous(), wt, bt, True)
+
+
 @pytest.mark.parametrize("level,cin,cout", [(0, 64, 32), (1, 64, 64), (2, 128, 64)])
 def test_up_conv_forward_and_adjoint(R, cloud, level, cin, cout):
     """Children at `level` from their parents at level + 1."""
